@@ -1,0 +1,807 @@
+/*
+ * bkry_oracle.c -- plain, slow, FP64 CPU oracle for the block Krylov hot path.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the
+ * benchmark's CPU-baseline leg may load this library.  It shares no code,
+ * header, table or helper with the GPU library: it is written directly from
+ * the thesis (Dreier, "Hardware-Oriented Krylov Methods for High-Performance
+ * Computing", arXiv 2104.02494), in plain loops, without blocking, fusion or
+ * reordering, so that it can be checked against the text by eye.
+ *
+ * Conventions: block vectors are n x s row-major ("row-interleaved"), element
+ * (i,j) at X[i*ld + j]; CSR is 0-based with int32 indices; every s x s
+ * element of a *-subalgebra is a dense row-major s x s array.  Build with
+ * -O2 -ffp-contract=off so that no multiply-add is fused.
+ *
+ * Status codes: 0 ok, 1 not converged, -1 invalid argument, -2 breakdown
+ * (a Cholesky pivot <= 0), -3 non-finite value.
+ */
+#include <float.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+enum { OR_PARALLEL = 0, OR_GLOBAL = 1, OR_BLOCK = 2, OR_HYBRID = 3 };
+enum { OR_OK = 0, OR_NOT_CONVERGED = 1, OR_E_INVALID = -1, OR_E_BREAKDOWN = -2, OR_E_NONFINITE = -3 };
+
+typedef int64_t i64;
+
+/* ------------------------------------------------------------------------ */
+/* Subalgebra bookkeeping (Definitions "elementary *-subalgebras" and        */
+/* "Relevant *-subalgebras", Ch. 3).  "hybrid" is the block-parallel         */
+/* subalgebra with q contiguous column groups of width g = s/q.              */
+/* ------------------------------------------------------------------------ */
+static int group_width(int s, int kind, int q) {
+  switch (kind) {
+    case OR_BLOCK: return s;
+    case OR_HYBRID: return (q > 0 && s % q == 0) ? s / q : -1;
+    case OR_PARALLEL: return 1;
+    case OR_GLOBAL: return 1;
+    default: return -1;
+  }
+}
+
+static int valid_subalg(int s, int kind, int q) {
+  if (s < 1) return 0;
+  return group_width(s, kind, q) > 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* BOP: Y = A X for CSR A (Ch. 3, Performance Analysis, kernel BOP).          */
+/* Each entry is summed in CSR order.                                        */
+/* ------------------------------------------------------------------------ */
+void or_spmm(i64 n, const int32_t* rowptr, const int32_t* colind, const double* val, int s,
+             const double* X, double* Y) {
+  for (i64 i = 0; i < n; ++i) {
+    for (int j = 0; j < s; ++j) {
+      double acc = 0.0;
+      for (i64 k = rowptr[i]; k < rowptr[i + 1]; ++k) acc += val[k] * X[(i64)colind[k] * s + j];
+      Y[i * s + j] = acc;
+    }
+  }
+}
+
+/* R = B - A X */
+void or_residual(i64 n, const int32_t* rowptr, const int32_t* colind, const double* val, int s,
+                 const double* B, const double* X, double* R) {
+  or_spmm(n, rowptr, colind, val, s, X, R);
+  for (i64 t = 0; t < n * s; ++t) R[t] = B[t] - R[t];
+}
+
+/* Full Gram matrix G = X^T Y (s x s), rows summed in ascending order. */
+void or_gram(i64 n, int s, const double* X, i64 ldx, const double* Y, i64 ldy, double* G) {
+  for (int a = 0; a < s; ++a)
+    for (int b = 0; b < s; ++b) {
+      double acc = 0.0;
+      for (i64 i = 0; i < n; ++i) acc += X[i * ldx + a] * Y[i * ldy + b];
+      G[a * s + b] = acc;
+    }
+}
+
+/* Projection of a full Gram matrix onto the subalgebra, which turns X^T Y into
+ * the block inner product of that subalgebra:
+ *   block:    X^T Y;
+ *   hybrid:   only the q diagonal g x g blocks are kept;
+ *   parallel: only the diagonal is kept;
+ *   global:   (tr(X^T Y) / s) * I.  The printed definition has no 1/s; the
+ *             normality axiom tr<X,Y> = <X,Y>_F requires it. */
+void or_project(int s, int kind, int q, double* G) {
+  int g = group_width(s, kind, q);
+  if (kind == OR_GLOBAL) {
+    double tr = 0.0;
+    for (int a = 0; a < s; ++a) tr += G[a * s + a];
+    tr /= (double)s;
+    for (int a = 0; a < s; ++a)
+      for (int b = 0; b < s; ++b) G[a * s + b] = (a == b) ? tr : 0.0;
+    return;
+  }
+  for (int a = 0; a < s; ++a)
+    for (int b = 0; b < s; ++b)
+      if (a / g != b / g) G[a * s + b] = 0.0;
+}
+
+/* BDOT: the block inner product <X, Y>_S (Ch. 3, kernel BDOT). */
+int or_bdot(i64 n, int s, int kind, int q, const double* X, const double* Y, double* G) {
+  if (!valid_subalg(s, kind, q)) return OR_E_INVALID;
+  or_gram(n, s, X, s, Y, s, G);
+  or_project(s, kind, q, G);
+  return OR_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Householder thin QR (Golub & Van Loan, "house" + backward accumulation),  */
+/* the method the thesis uses for the normaliser (Ch. 3, normaliser remark).  */
+/* X is m x c (row stride ldx), m >= c.  Outputs Q (m x c, stride ldq) with   */
+/* Q^T Q = I and R (c x c, upper triangular) with diag(R) >= 0.  A zero       */
+/* sub-column gives the identity reflector, so rank-deficient X still yields */
+/* an orthonormal Q (the completion is whatever the reflectors produce).     */
+/* ------------------------------------------------------------------------ */
+int or_householder_qr(i64 m, int c, const double* X, i64 ldx, double* Q, i64 ldq, double* R) {
+  if (m < c || c < 1) return OR_E_INVALID;
+  double* A = (double*)malloc(sizeof(double) * (size_t)(m * c));
+  double* beta = (double*)malloc(sizeof(double) * (size_t)c);
+  if (!A || !beta) { free(A); free(beta); return OR_E_INVALID; }
+  for (i64 i = 0; i < m; ++i)
+    for (int j = 0; j < c; ++j) A[i * c + j] = X[i * ldx + j];
+
+  for (int j = 0; j < c; ++j) {
+    double x1 = A[(i64)j * c + j];
+    double sig = 0.0;
+    for (i64 i = j + 1; i < m; ++i) sig += A[i * c + j] * A[i * c + j];
+    if (sig == 0.0) {
+      beta[j] = 0.0; /* identity reflector; R_jj = x1 */
+      continue;
+    }
+    double mu = sqrt(x1 * x1 + sig);
+    double v1 = (x1 <= 0.0) ? (x1 - mu) : (-sig / (x1 + mu));
+    beta[j] = 2.0 * v1 * v1 / (sig + v1 * v1);
+    for (i64 i = j + 1; i < m; ++i) A[i * c + j] /= v1; /* v = [1; x(2:)/v1] */
+    A[(i64)j * c + j] = mu;
+    /* apply H_j = I - beta v v^T to the trailing columns */
+    for (int cc = j + 1; cc < c; ++cc) {
+      double w = A[(i64)j * c + cc];
+      for (i64 i = j + 1; i < m; ++i) w += A[i * c + j] * A[i * c + cc];
+      A[(i64)j * c + cc] -= beta[j] * w;
+      for (i64 i = j + 1; i < m; ++i) A[i * c + cc] -= beta[j] * A[i * c + j] * w;
+    }
+  }
+  for (int a = 0; a < c; ++a)
+    for (int b = 0; b < c; ++b) R[a * c + b] = (b >= a) ? A[(i64)a * c + b] : 0.0;
+
+  /* Q = H_0 H_1 ... H_{c-1} [I_c; 0], accumulated from the last reflector. */
+  for (i64 i = 0; i < m; ++i)
+    for (int j = 0; j < c; ++j) Q[i * ldq + j] = (i == j) ? 1.0 : 0.0;
+  for (int j = c - 1; j >= 0; --j) {
+    if (beta[j] == 0.0) continue;
+    for (int cc = j; cc < c; ++cc) {
+      double w = Q[(i64)j * ldq + cc];
+      for (i64 i = j + 1; i < m; ++i) w += A[i * c + j] * Q[i * ldq + cc];
+      Q[(i64)j * ldq + cc] -= beta[j] * w;
+      for (i64 i = j + 1; i < m; ++i) Q[i * ldq + cc] -= beta[j] * A[i * c + j] * w;
+    }
+  }
+  /* canonical signs: diag(R) >= 0 */
+  for (int j = 0; j < c; ++j) {
+    if (R[j * c + j] < 0.0) {
+      for (int b = j; b < c; ++b) R[j * c + b] = -R[j * c + b];
+      for (i64 i = 0; i < m; ++i) Q[i * ldq + j] = -Q[i * ldq + j];
+    }
+  }
+  free(A);
+  free(beta);
+  return OR_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Normaliser Norm_S(X): X = Y N with <Y,Y>_S = I and N in S (Definition     */
+/* "normalizer", Ch. 3), computed by Householder QR for every X including    */
+/* rank-deficient ones.                                                      */
+/*   block:    N = R of the QR of X;                                         */
+/*   hybrid:   one QR per column group, N block diagonal;                    */
+/*   parallel: N_jj = |x_j|, y_j = x_j / N_jj, and y_j = e_1 for x_j = 0;    */
+/*   global:   N = c I with c = |X|_F / sqrt(s), Y = X / c; for X = 0 the     */
+/*             columns of Y are e_1, ..., e_s.                               */
+/* Y may alias X.                                                            */
+/* ------------------------------------------------------------------------ */
+int or_normalize(i64 n, int s, int kind, int q, const double* X, double* Y, double* N) {
+  int g = group_width(s, kind, q);
+  if (g < 1 || n < g || (kind == OR_GLOBAL && n < s)) return OR_E_INVALID;
+  for (int t = 0; t < s * s; ++t) N[t] = 0.0;
+  if (kind == OR_PARALLEL) {
+    for (int j = 0; j < s; ++j) {
+      double ss = 0.0;
+      for (i64 i = 0; i < n; ++i) ss += X[i * s + j] * X[i * s + j];
+      double nrm = sqrt(ss);
+      N[j * s + j] = nrm;
+      for (i64 i = 0; i < n; ++i) Y[i * s + j] = (nrm > 0.0) ? X[i * s + j] / nrm : (i == 0 ? 1.0 : 0.0);
+    }
+    return OR_OK;
+  }
+  if (kind == OR_GLOBAL) {
+    double ss = 0.0;
+    for (i64 t = 0; t < n * s; ++t) ss += X[t] * X[t];
+    double c = sqrt(ss) / sqrt((double)s);
+    for (int j = 0; j < s; ++j) N[j * s + j] = c;
+    for (i64 i = 0; i < n; ++i)
+      for (int j = 0; j < s; ++j) Y[i * s + j] = (c > 0.0) ? X[i * s + j] / c : (i == j ? 1.0 : 0.0);
+    return OR_OK;
+  }
+  double* Qg = (double*)malloc(sizeof(double) * (size_t)(n * g));
+  double* Rg = (double*)malloc(sizeof(double) * (size_t)(g * g));
+  if (!Qg || !Rg) { free(Qg); free(Rg); return OR_E_INVALID; }
+  for (int grp = 0; grp < s / g; ++grp) {
+    int st = or_householder_qr(n, g, X + grp * g, s, Qg, g, Rg);
+    if (st != OR_OK) { free(Qg); free(Rg); return st; }
+    for (i64 i = 0; i < n; ++i)
+      for (int j = 0; j < g; ++j) Y[i * s + grp * g + j] = Qg[i * g + j];
+    for (int a = 0; a < g; ++a)
+      for (int b = 0; b < g; ++b) N[(grp * g + a) * s + grp * g + b] = Rg[a * g + b];
+  }
+  free(Qg);
+  free(Rg);
+  return OR_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Solve A X = B inside the subalgebra, A symmetric positive definite in S   */
+/* (alpha and rho of the block CG are SPD by block positive definiteness,    */
+/* Definition "BSA/BPD", Ch. 3).  One Cholesky factorisation per S-block;    */
+/* no pivoting.  A non-positive or non-finite pivot is a breakdown.  Only    */
+/* the S-blocks of B are used; X is returned in S.                           */
+/* ------------------------------------------------------------------------ */
+int or_chol_solve(int s, int kind, int q, const double* A, const double* B, double* X) {
+  int g = group_width(s, kind, q);
+  if (g < 1) return OR_E_INVALID;
+  double L[64 * 64];
+  if (g > 64) return OR_E_INVALID;
+  for (int t = 0; t < s * s; ++t) X[t] = 0.0;
+  for (int grp = 0; grp < s / g; ++grp) {
+    int o = grp * g;
+    for (int j = 0; j < g; ++j) {
+      for (int i = j; i < g; ++i) {
+        double sum = A[(o + i) * s + o + j];
+        for (int k = 0; k < j; ++k) sum -= L[i * g + k] * L[j * g + k];
+        if (i == j) {
+          if (!(sum > 0.0) || !isfinite(sum)) return OR_E_BREAKDOWN;
+          L[j * g + j] = sqrt(sum);
+        } else {
+          L[i * g + j] = sum / L[j * g + j];
+        }
+      }
+    }
+    for (int col = 0; col < g; ++col) {
+      double y[64];
+      for (int i = 0; i < g; ++i) { /* L y = b */
+        double sum = B[(o + i) * s + o + col];
+        for (int k = 0; k < i; ++k) sum -= L[i * g + k] * y[k];
+        y[i] = sum / L[i * g + i];
+      }
+      for (int i = g - 1; i >= 0; --i) { /* L^T x = y */
+        double sum = y[i];
+        for (int k = i + 1; k < g; ++k) sum -= L[k * g + i] * X[(o + k) * s + o + col];
+        X[(o + i) * s + o + col] = sum / L[i * g + i];
+      }
+    }
+  }
+  return OR_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Eigenvalues of a symmetric s x s matrix by the cyclic Jacobi method       */
+/* (Golub & Van Loan, cyclic-by-row with the symmetric 2x2 Schur step).      */
+/* ------------------------------------------------------------------------ */
+int or_sym_eigenvalues(int s, const double* Ain, double* ev) {
+  if (s < 1 || s > 64) return OR_E_INVALID;
+  double A[64 * 64];
+  for (int t = 0; t < s * s; ++t) A[t] = Ain[t];
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0, tot = 0.0;
+    for (int i = 0; i < s; ++i)
+      for (int j = 0; j < s; ++j) {
+        tot += A[i * s + j] * A[i * s + j];
+        if (i != j) off += A[i * s + j] * A[i * s + j];
+      }
+    if (off <= 1e-30 * tot || off == 0.0) break;
+    for (int p = 0; p < s - 1; ++p)
+      for (int qq = p + 1; qq < s; ++qq) {
+        double apq = A[p * s + qq];
+        if (apq == 0.0) continue;
+        double tau = (A[qq * s + qq] - A[p * s + p]) / (2.0 * apq);
+        double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+        double c = 1.0 / sqrt(1.0 + t * t), sn = t * c;
+        for (int k = 0; k < s; ++k) { /* A <- A J (columns p, q) */
+          double akp = A[k * s + p], akq = A[k * s + qq];
+          A[k * s + p] = c * akp - sn * akq;
+          A[k * s + qq] = sn * akp + c * akq;
+        }
+        for (int k = 0; k < s; ++k) { /* A <- J^T A (rows p, q) */
+          double apk = A[p * s + k], aqk = A[qq * s + k];
+          A[p * s + k] = c * apk - sn * aqk;
+          A[qq * s + k] = sn * apk + c * aqk;
+        }
+      }
+  }
+  for (int i = 0; i < s; ++i) ev[i] = A[i * s + i];
+  return OR_OK;
+}
+
+/* Diagonally scaled condition number kappa_D(alpha) = kappa(D^-1/2 alpha D^-1/2),
+ * D = diag(alpha) (Definition "Diagonally scaled condition number", Ch. 4).
+ * Infinity if a diagonal entry or the smallest eigenvalue is not positive. */
+double or_kappa_D(int s, const double* alpha) {
+  double S[64 * 64] = {0.0}, ev[64] = {0.0};
+  if (s < 1 || s > 64) return INFINITY;
+  for (int i = 0; i < s; ++i)
+    if (!(alpha[i * s + i] > 0.0)) return INFINITY;
+  for (int i = 0; i < s; ++i)
+    for (int j = 0; j < s; ++j) S[i * s + j] = alpha[i * s + j] / sqrt(alpha[i * s + i] * alpha[j * s + j]);
+  or_sym_eigenvalues(s, S, ev);
+  double lo = ev[0], hi = ev[0];
+  for (int i = 1; i < s; ++i) {
+    if (ev[i] < lo) lo = ev[i];
+    if (ev[i] > hi) hi = ev[i];
+  }
+  if (!(lo > 0.0)) return INFINITY;
+  return hi / lo;
+}
+
+/* Re-orthonormalisation test of the adaptive block CG.  The printed test
+ * "eta * kappa_D > sqrt(eps)" fires for every eta >= 1e-8; the reading used
+ * here, which is consistent with the iteration/re-orthonormalisation counts
+ * the thesis reports for both precisions and with "no re-orthonormalization
+ * in the parallel case", is: fire iff eta * kappa_D * sqrt(eps) > 1, with
+ * eta = 0 never and eta = infinity always firing. */
+int or_reortho_fires(double eta, double kappaD, double eps) {
+  if (eta <= 0.0) return 0;
+  if (isinf(eta)) return 1;
+  return eta * kappaD * sqrt(eps) > 1.0;
+}
+
+/* small dense helpers (row-major s x s) */
+static void mm(int s, const double* A, const double* B, double* C) { /* C = A B */
+  for (int i = 0; i < s; ++i)
+    for (int j = 0; j < s; ++j) {
+      double acc = 0.0;
+      for (int k = 0; k < s; ++k) acc += A[i * s + k] * B[k * s + j];
+      C[i * s + j] = acc;
+    }
+}
+static void mtm(int s, const double* A, const double* B, double* C) { /* C = A^T B */
+  for (int i = 0; i < s; ++i)
+    for (int j = 0; j < s; ++j) {
+      double acc = 0.0;
+      for (int k = 0; k < s; ++k) acc += A[k * s + i] * B[k * s + j];
+      C[i * s + j] = acc;
+    }
+}
+static void eye(int s, double* A) {
+  for (int i = 0; i < s; ++i)
+    for (int j = 0; j < s; ++j) A[i * s + j] = (i == j) ? 1.0 : 0.0;
+}
+/* Y += X c  (X, Y n x s; c s x s) */
+static void block_axpy(i64 n, int s, const double* X, const double* c, double* Y) {
+  for (i64 i = 0; i < n; ++i)
+    for (int j = 0; j < s; ++j) {
+      double acc = 0.0;
+      for (int k = 0; k < s; ++k) acc += X[i * s + k] * c[k * s + j];
+      Y[i * s + j] += acc;
+    }
+}
+/* Y -= X c */
+static void block_axmy(i64 n, int s, const double* X, const double* c, double* Y) {
+  for (i64 i = 0; i < n; ++i)
+    for (int j = 0; j < s; ++j) {
+      double acc = 0.0;
+      for (int k = 0; k < s; ++k) acc += X[i * s + k] * c[k * s + j];
+      Y[i * s + j] -= acc;
+    }
+}
+static void column_norms(i64 n, int s, const double* X, double* out) {
+  for (int j = 0; j < s; ++j) {
+    double acc = 0.0;
+    for (i64 i = 0; i < n; ++i) acc += X[i * s + j] * X[i * s + j];
+    out[j] = sqrt(acc);
+  }
+}
+/* max_i num_i / den_i over columns with den_i > 0 (a column whose initial
+ * residual is zero counts as converged) */
+static double max_rel(int s, const double* num, const double* den, double* rel) {
+  double m = 0.0;
+  for (int i = 0; i < s; ++i) {
+    double r = (den[i] > 0.0) ? num[i] / den[i] : 0.0;
+    if (rel) rel[i] = r;
+    if (r > m || isnan(r)) m = isnan(r) ? NAN : r;
+  }
+  return m;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Block CG with adaptive residual re-orthonormalisation (Algorithm          */
+/* "BCG Method with Adaptive Residual Re-Orthonormalization", Ch. 4), with   */
+/* the identity preconditioner, so Z = R-bar and rho = <R-bar, R-bar>_S.     */
+/*                                                                          */
+/*   R0 = B - A X0                                                           */
+/*   (R-bar, sigma) = Norm_S(R0) if eta > 0, else (R0, I)                    */
+/*   P = R-bar, rho = <P, R-bar>_S                                           */
+/*   repeat: Q = A P; alpha = <P,Q>_S; lambda = alpha^-1 rho;                */
+/*           X += P lambda sigma; R~ = R-bar - Q lambda;                     */
+/*           if the test fires: (R-bar, gamma) = Norm_S(R~), sigma = gamma sigma */
+/*           else R-bar = R~, gamma = I;                                     */
+/*           stop if max_i |(R-bar sigma)_i| / |R0_i| <= tol;                */
+/*           rho' = <R-bar, R-bar>_S; beta = rho^-1 gamma^T rho';            */
+/*           P = R-bar + P beta; rho = rho'.                                 */
+/*                                                                          */
+/* The stopping norm is the maximum column 2-norm (the thesis' choice),      */
+/* taken relative to the initial residual column.  After a normalisation the */
+/* column norms are those of sigma (exact for block, hybrid and parallel);   */
+/* for global they are computed from R-bar sigma.  If every initial column   */
+/* is zero the solve returns immediately.                                    */
+/*                                                                          */
+/* info[0] = iterations, info[1] = normalisations (the initial one included),*/
+/* info[2] = converged.  relres[s] = final recursive relative column norms.  */
+/* hist (optional, cap entries) = max relative column norm per iteration.    */
+/* Pk/Rk (optional, cap_blocks n x s blocks) record P^k and the true residual */
+/* R^k = R-bar^k sigma^k for k = 0, 1, ... (for invariant checks).           */
+/* ------------------------------------------------------------------------ */
+int or_bcg(i64 n, const int32_t* rowptr, const int32_t* colind, const double* val, int s, int kind, int q,
+           const double* B, double* X, double tol, int maxit, double eta, double eps, int32_t* info,
+           double* relres, double* hist, int hist_cap, double* Pk, double* Rk, int cap_blocks) {
+  if (!valid_subalg(s, kind, q) || s > 64 || n < group_width(s, kind, q)) return OR_E_INVALID;
+  size_t blk = (size_t)(n * s);
+  double* R = (double*)calloc(blk, sizeof(double));
+  double* P = (double*)calloc(blk, sizeof(double));
+  double* Qb = (double*)calloc(blk, sizeof(double));
+  double* T = (double*)calloc(blk, sizeof(double));
+  if (!R || !P || !Qb || !T) { free(R); free(P); free(Qb); free(T); return OR_E_INVALID; }
+  size_t ss = (size_t)s * s;
+  double sigma[64 * 64], alpha[64 * 64], rho[64 * 64], rho_new[64 * 64], lambda[64 * 64], tmp[64 * 64];
+  double gamma[64 * 64], beta[64 * 64], r0n[64], cn[64], rel[64];
+  int st = OR_OK, iters = 0, nro = 0, conv = 0;
+
+  or_residual(n, rowptr, colind, val, s, B, X, R);
+  column_norms(n, s, R, r0n);
+  for (int i = 0; i < s; ++i) rel[i] = (r0n[i] > 0.0) ? 1.0 : 0.0;
+  {
+    int allzero = 1;
+    for (int i = 0; i < s; ++i) allzero &= (r0n[i] == 0.0);
+    if (allzero) {
+      conv = 1;
+      for (int i = 0; i < s; ++i) rel[i] = 0.0;
+      goto done;
+    }
+  }
+  if (eta > 0.0) {
+    st = or_normalize(n, s, kind, q, R, R, sigma);
+    if (st != OR_OK) goto done;
+    nro++;
+  } else {
+    eye(s, sigma);
+  }
+  memcpy(P, R, blk * sizeof(double));
+  or_bdot(n, s, kind, q, P, R, rho);
+
+  for (int k = 0; k < maxit; ++k) {
+    if (Pk && k < cap_blocks) memcpy(Pk + (size_t)k * blk, P, blk * sizeof(double));
+    if (Rk && k < cap_blocks) {
+      memset(T, 0, blk * sizeof(double));
+      block_axpy(n, s, R, sigma, T);
+      memcpy(Rk + (size_t)k * blk, T, blk * sizeof(double));
+    }
+    or_spmm(n, rowptr, colind, val, s, P, Qb);        /* Q = A P */
+    or_bdot(n, s, kind, q, P, Qb, alpha);             /* alpha = <P, Q>_S */
+    for (size_t t = 0; t < ss; ++t)
+      if (!isfinite(alpha[t])) { st = OR_E_NONFINITE; goto done; }
+    st = or_chol_solve(s, kind, q, alpha, rho, lambda); /* lambda = alpha^-1 rho */
+    if (st != OR_OK) goto done;
+    mm(s, lambda, sigma, tmp);                        /* X += P (lambda sigma) */
+    block_axpy(n, s, P, tmp, X);
+    block_axmy(n, s, Qb, lambda, R);                  /* R~ = R-bar - Q lambda */
+    iters = k + 1;
+    int fire = or_reortho_fires(eta, or_kappa_D(s, alpha), eps);
+    if (fire) {
+      st = or_normalize(n, s, kind, q, R, R, gamma);  /* (R-bar, gamma) = Norm_S(R~) */
+      if (st != OR_OK) goto done;
+      nro++;
+      mm(s, gamma, sigma, tmp);                       /* sigma = gamma sigma */
+      memcpy(sigma, tmp, ss * sizeof(double));
+      if (kind != OR_GLOBAL) {
+        for (int i = 0; i < s; ++i) {
+          double acc = 0.0;
+          for (int a = 0; a < s; ++a) acc += sigma[a * s + i] * sigma[a * s + i];
+          cn[i] = sqrt(acc);
+        }
+      } else {
+        memset(T, 0, blk * sizeof(double));
+        block_axpy(n, s, R, sigma, T);
+        column_norms(n, s, T, cn);
+      }
+    } else {
+      eye(s, gamma);
+      memset(T, 0, blk * sizeof(double));
+      block_axpy(n, s, R, sigma, T);
+      column_norms(n, s, T, cn);
+    }
+    double m = max_rel(s, cn, r0n, rel);
+    if (hist && k < hist_cap) hist[k] = m;
+    if (isnan(m)) { st = OR_E_NONFINITE; goto done; }
+    if (m <= tol) { conv = 1; break; }
+    or_bdot(n, s, kind, q, R, R, rho_new);            /* rho' = <R-bar, R-bar>_S */
+    mtm(s, gamma, rho_new, tmp);                      /* beta = rho^-1 gamma^T rho' */
+    st = or_chol_solve(s, kind, q, rho, tmp, beta);
+    if (st != OR_OK) goto done;
+    memcpy(T, R, blk * sizeof(double));               /* P = R-bar + P beta */
+    block_axpy(n, s, P, beta, T);
+    memcpy(P, T, blk * sizeof(double));
+    memcpy(rho, rho_new, ss * sizeof(double));
+  }
+done:
+  if (info) { info[0] = iters; info[1] = nro; info[2] = conv; }
+  if (relres) for (int i = 0; i < s; ++i) relres[i] = rel[i];
+  free(R); free(P); free(Qb); free(T);
+  if (st != OR_OK) return st;
+  return conv ? OR_OK : OR_NOT_CONVERGED;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Block Arnoldi step with modified Gram-Schmidt (Algorithm "Block Arnoldi    */
+/* Method", Ch. 5).  Given S-orthonormal V_0..V_k (each n x s, consecutive), */
+/* computes W = A V_k, h_jk = <V_j, W>_S and W -= V_j h_jk for j = 0..k in   */
+/* turn, then (V_{k+1}, gamma) = Norm_S(W).  The printed step stores         */
+/* eta = -<V_j, W> and adds V_j eta while the normaliser returns a positive  */
+/* sub-diagonal; the Hessenberg matrix is kept consistent here by storing    */
+/* +<V_j, W> and subtracting (as in Gram-Schmidt).  h has k+2 entries.        */
+/* ------------------------------------------------------------------------ */
+static int arnoldi_step(i64 n, const int32_t* rowptr, const int32_t* colind, const double* val, int s,
+                        int kind, int q, double* V, int k, double* h /* (k+2) s x s */) {
+  size_t blk = (size_t)(n * s), ss = (size_t)s * s;
+  double* W = V + (size_t)(k + 1) * blk;
+  or_spmm(n, rowptr, colind, val, s, V + (size_t)k * blk, W);
+  for (int j = 0; j <= k; ++j) {
+    or_bdot(n, s, kind, q, V + (size_t)j * blk, W, h + (size_t)j * ss);
+    block_axmy(n, s, V + (size_t)j * blk, h + (size_t)j * ss, W);
+  }
+  return or_normalize(n, s, kind, q, W, W, h + (size_t)(k + 1) * ss);
+}
+
+/* Block Arnoldi with m steps from V0 = Norm_S(R) (for the Arnoldi relation
+ * checks).  V gets m+1 blocks; H ((m+1) x m S-elements, entry (j,k) at
+ * H[(j*m + k) * s*s]) the block Hessenberg matrix with A V~ = V H. */
+int or_block_arnoldi(i64 n, const int32_t* rowptr, const int32_t* colind, const double* val, int s, int kind,
+                     int q, const double* R, int m, double* V, double* H, double* sigma0) {
+  if (!valid_subalg(s, kind, q) || s > 64) return OR_E_INVALID;
+  size_t ss = (size_t)s * s;
+  int st = or_normalize(n, s, kind, q, R, V, sigma0);
+  if (st != OR_OK) return st;
+  double* h = (double*)malloc(sizeof(double) * (size_t)(m + 1) * ss);
+  memset(H, 0, sizeof(double) * (size_t)(m + 1) * m * ss);
+  for (int k = 0; k < m; ++k) {
+    st = arnoldi_step(n, rowptr, colind, val, s, kind, q, V, k, h);
+    if (st != OR_OK) break;
+    for (int j = 0; j <= k + 1; ++j) memcpy(H + ((size_t)j * m + k) * ss, h + (size_t)j * ss, ss * sizeof(double));
+  }
+  free(h);
+  return st;
+}
+
+/* Full QR of the 2g x g matrix [top; bot] (each g x g, row stride s, taken
+ * from the S-block at offset o): [top; bot] = Om [rho; 0] with Om (2g x 2g)
+ * orthogonal, the generalised Givens rotation of the block GMRes method.
+ * Om is returned explicitly (row-major 2g x 2g); rho replaces top and zero
+ * replaces bot. */
+static void block_givens(int s, int g, int o, double* top, double* bot, double* Om) {
+  int m2 = 2 * g;
+  double M[128 * 64];
+  double Qf[128 * 128];
+  double beta[64];
+  for (int i = 0; i < g; ++i)
+    for (int j = 0; j < g; ++j) {
+      M[i * g + j] = top[(o + i) * s + o + j];
+      M[(g + i) * g + j] = bot[(o + i) * s + o + j];
+    }
+  for (int j = 0; j < g; ++j) {
+    double x1 = M[j * g + j], sig = 0.0;
+    for (int i = j + 1; i < m2; ++i) sig += M[i * g + j] * M[i * g + j];
+    if (sig == 0.0) { beta[j] = 0.0; continue; }
+    double mu = sqrt(x1 * x1 + sig);
+    double v1 = (x1 <= 0.0) ? (x1 - mu) : (-sig / (x1 + mu));
+    beta[j] = 2.0 * v1 * v1 / (sig + v1 * v1);
+    for (int i = j + 1; i < m2; ++i) M[i * g + j] /= v1;
+    M[j * g + j] = mu;
+    for (int c = j + 1; c < g; ++c) {
+      double w = M[j * g + c];
+      for (int i = j + 1; i < m2; ++i) w += M[i * g + j] * M[i * g + c];
+      M[j * g + c] -= beta[j] * w;
+      for (int i = j + 1; i < m2; ++i) M[i * g + c] -= beta[j] * M[i * g + j] * w;
+    }
+  }
+  /* full Q = H_0 ... H_{g-1} (2g x 2g) */
+  for (int i = 0; i < m2; ++i)
+    for (int j = 0; j < m2; ++j) Qf[i * m2 + j] = (i == j) ? 1.0 : 0.0;
+  for (int j = g - 1; j >= 0; --j) {
+    if (beta[j] == 0.0) continue;
+    for (int c = 0; c < m2; ++c) {
+      double w = Qf[j * m2 + c];
+      for (int i = j + 1; i < m2; ++i) w += M[i * g + j] * Qf[i * m2 + c];
+      Qf[j * m2 + c] -= beta[j] * w;
+      for (int i = j + 1; i < m2; ++i) Qf[i * m2 + c] -= beta[j] * M[i * g + j] * w;
+    }
+  }
+  for (int i = 0; i < g; ++i)
+    for (int j = 0; j < g; ++j) {
+      top[(o + i) * s + o + j] = (j >= i) ? M[i * g + j] : 0.0;
+      bot[(o + i) * s + o + j] = 0.0;
+    }
+  memcpy(Om, Qf, sizeof(double) * (size_t)m2 * m2);
+}
+
+/* [x; y] <- Om^T [x; y] per S-block, for s x s S-elements x, y. */
+static void apply_givens_T(int s, int g, const double* Om /* per group 2g x 2g */, double* x, double* y) {
+  int m2 = 2 * g;
+  double col[128], out[128];
+  for (int grp = 0; grp < s / g; ++grp) {
+    const double* O = Om + (size_t)grp * m2 * m2;
+    int o = grp * g;
+    for (int c = 0; c < g; ++c) {
+      for (int i = 0; i < g; ++i) {
+        col[i] = x[(o + i) * s + o + c];
+        col[g + i] = y[(o + i) * s + o + c];
+      }
+      for (int i = 0; i < m2; ++i) {
+        double acc = 0.0;
+        for (int k = 0; k < m2; ++k) acc += O[k * m2 + i] * col[k];
+        out[i] = acc;
+      }
+      for (int i = 0; i < g; ++i) {
+        x[(o + i) * s + o + c] = out[i];
+        y[(o + i) * s + o + c] = out[g + i];
+      }
+    }
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Restarted block GMRes (Algorithm "Block GMRes Method", Ch. 5) with MGS    */
+/* block Arnoldi, the generalised Givens rotations applied on the fly to the */
+/* Hessenberg column and to sigma, block back-substitution and restart.      */
+/*                                                                          */
+/* Readings: the Hessenberg entries are +<V_j, W>_S (see arnoldi_step); the  */
+/* back-substitution runs over the steps actually taken in the cycle; the    */
+/* step count limit maxit counts Arnoldi steps over all cycles; the stopping */
+/* test is max_i |sigma^{k+1} e_i| / |R0_i| <= tol for block, hybrid and     */
+/* parallel (these are the residual column norms) and, for global, the       */
+/* Frobenius form |sigma^{k+1}|_F / |R0|_F <= tol.  A zero pivot in the back */
+/* substitution gives a zero component.                                      */
+/*                                                                          */
+/* info[0] = Arnoldi steps, info[1] = cycles, info[2] = converged.           */
+/* relres[s] = true relative column residuals at exit; hist = per step       */
+/* residual measure.                                                         */
+/* ------------------------------------------------------------------------ */
+int or_bgmres(i64 n, const int32_t* rowptr, const int32_t* colind, const double* val, int s, int kind, int q,
+              const double* B, double* X, double tol, int maxit, int restart, int32_t* info, double* relres,
+              double* hist, int hist_cap) {
+  int g = group_width(s, kind, q);
+  if (g < 1 || s > 64 || restart < 1 || n < s) return OR_E_INVALID;
+  int m = restart, ngrp = s / g;
+  size_t blk = (size_t)(n * s), ss = (size_t)s * s;
+  double* V = (double*)malloc(sizeof(double) * (size_t)(m + 1) * blk);
+  double* R = (double*)malloc(sizeof(double) * blk);
+  double* H = (double*)malloc(sizeof(double) * (size_t)(m + 1) * m * ss);
+  double* sig = (double*)malloc(sizeof(double) * (size_t)(m + 1) * ss);
+  double* Om = (double*)malloc(sizeof(double) * (size_t)m * ngrp * 4 * g * g);
+  double* zeta = (double*)malloc(sizeof(double) * (size_t)m * ss);
+  double* h = (double*)malloc(sizeof(double) * (size_t)(m + 1) * ss);
+  if (!V || !R || !H || !sig || !Om || !zeta || !h) {
+    free(V); free(R); free(H); free(sig); free(Om); free(zeta); free(h);
+    return OR_E_INVALID;
+  }
+  double r0n[64], cn[64], rel[64], tmp[64 * 64], r0F = 0.0;
+  int st = OR_OK, total = 0, cycles = 0, conv = 0;
+
+  or_residual(n, rowptr, colind, val, s, B, X, R);
+  column_norms(n, s, R, r0n);
+  for (int i = 0; i < s; ++i) r0F += r0n[i] * r0n[i];
+  r0F = sqrt(r0F);
+  if (r0F == 0.0) { conv = 1; goto finish; }
+
+  while (1) {
+    cycles++;
+    or_residual(n, rowptr, colind, val, s, B, X, R);
+    memset(sig, 0, sizeof(double) * (size_t)(m + 1) * ss);
+    memset(H, 0, sizeof(double) * (size_t)(m + 1) * m * ss);
+    st = or_normalize(n, s, kind, q, R, V, sig); /* V^0 sigma^0 = Norm_S(R0) */
+    if (st != OR_OK) goto finish;
+    int kend = 0;
+    for (int k = 0; k < m; ++k) {
+      st = arnoldi_step(n, rowptr, colind, val, s, kind, q, V, k, h);
+      if (st != OR_OK) goto finish;
+      for (int j = 0; j <= k; ++j) memcpy(H + ((size_t)j * m + k) * ss, h + (size_t)j * ss, ss * sizeof(double));
+      double* gam = h + (size_t)(k + 1) * ss;
+      for (int j = 0; j < k; ++j) /* apply the previous rotations to column k */
+        apply_givens_T(s, g, Om + (size_t)j * ngrp * 4 * g * g, H + ((size_t)j * m + k) * ss,
+                       H + ((size_t)(j + 1) * m + k) * ss);
+      for (int grp = 0; grp < ngrp; ++grp) /* Q_k [eta_kk; 0] = [eta_kk; gamma] */
+        block_givens(s, g, grp * g, H + ((size_t)k * m + k) * ss, gam,
+                     Om + ((size_t)k * ngrp + grp) * 4 * g * g);
+      apply_givens_T(s, g, Om + (size_t)k * ngrp * 4 * g * g, sig + (size_t)k * ss, sig + (size_t)(k + 1) * ss);
+      total++;
+      kend = k + 1;
+      const double* sk = sig + (size_t)(k + 1) * ss;
+      double meas;
+      if (kind == OR_GLOBAL) {
+        double f = 0.0;
+        for (size_t t = 0; t < ss; ++t) f += sk[t] * sk[t];
+        meas = sqrt(f) / r0F;
+      } else {
+        for (int i = 0; i < s; ++i) {
+          double acc = 0.0;
+          for (int a = 0; a < s; ++a) acc += sk[a * s + i] * sk[a * s + i];
+          cn[i] = sqrt(acc);
+        }
+        meas = max_rel(s, cn, r0n, NULL);
+      }
+      if (hist && total - 1 < hist_cap) hist[total - 1] = meas;
+      if (isnan(meas)) { st = OR_E_NONFINITE; goto finish; }
+      if (meas <= tol) { conv = 1; break; }
+      if (total >= maxit) break;
+    }
+    /* back-substitution: zeta_l = eta_ll^-1 (sigma_l - sum_{j>l} eta_lj zeta_j) */
+    for (int l = kend - 1; l >= 0; --l) {
+      memcpy(tmp, sig + (size_t)l * ss, ss * sizeof(double));
+      for (int j = l + 1; j < kend; ++j) {
+        const double* hl = H + ((size_t)l * m + j) * ss;
+        const double* zj = zeta + (size_t)j * ss;
+        for (int a = 0; a < s; ++a)
+          for (int b = 0; b < s; ++b) {
+            double acc = 0.0;
+            for (int c = 0; c < s; ++c) acc += hl[a * s + c] * zj[c * s + b];
+            tmp[a * s + b] -= acc;
+          }
+      }
+      const double* T = H + ((size_t)l * m + l) * ss; /* upper triangular per S-block */
+      double* z = zeta + (size_t)l * ss;
+      memset(z, 0, ss * sizeof(double));
+      for (int grp = 0; grp < ngrp; ++grp) {
+        int o = grp * g;
+        for (int b = 0; b < g; ++b)
+          for (int a = g - 1; a >= 0; --a) {
+            double acc = tmp[(o + a) * s + o + b];
+            for (int c = a + 1; c < g; ++c) acc -= T[(o + a) * s + o + c] * z[(o + c) * s + o + b];
+            double piv = T[(o + a) * s + o + a];
+            z[(o + a) * s + o + b] = (piv != 0.0) ? acc / piv : 0.0;
+          }
+      }
+    }
+    for (int j = 0; j < kend; ++j) block_axpy(n, s, V + (size_t)j * blk, zeta + (size_t)j * ss, X);
+    if (conv || total >= maxit) break;
+  }
+finish:
+  or_residual(n, rowptr, colind, val, s, B, X, R);
+  column_norms(n, s, R, cn);
+  max_rel(s, cn, r0n, rel);
+  if (relres) for (int i = 0; i < s; ++i) relres[i] = rel[i];
+  if (info) { info[0] = total; info[1] = cycles; info[2] = conv; }
+  free(V); free(R); free(H); free(sig); free(Om); free(zeta); free(h);
+  if (st != OR_OK) return st;
+  return conv ? OR_OK : OR_NOT_CONVERGED;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Sampled dense-dense product on the pattern of A:                          */
+/*   out[k] = alpha * sum_c L[i][c] * X[colind[k]][c]  for k in row i.       */
+/* With alpha = -1, L = Lambda (adjoint solution) and X the forward solution */
+/* this is dL/dval = -(Lambda X^T) restricted to the pattern of A.           */
+/* ------------------------------------------------------------------------ */
+void or_sddmm(i64 n, const int32_t* rowptr, const int32_t* colind, int s, double alpha, const double* L,
+              const double* X, double* out) {
+  for (i64 i = 0; i < n; ++i)
+    for (i64 k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+      double acc = 0.0;
+      for (int c = 0; c < s; ++c) acc += L[i * s + c] * X[(i64)colind[k] * s + c];
+      out[k] = alpha * acc;
+    }
+}
+
+/* Transpose of a square CSR matrix by a stable counting sort over the
+ * entries in storage order: rows of A^T list their columns ascending.
+ * permT[t] = index in A of entry t of A^T. */
+void or_csr_transpose(i64 n, const int32_t* rowptr, const int32_t* colind, const double* val, int32_t* rowptrT,
+                      int32_t* colindT, double* valT, int32_t* permT) {
+  i64 nnz = rowptr[n];
+  for (i64 j = 0; j <= n; ++j) rowptrT[j] = 0;
+  for (i64 k = 0; k < nnz; ++k) rowptrT[colind[k] + 1]++;
+  for (i64 j = 0; j < n; ++j) rowptrT[j + 1] += rowptrT[j];
+  int32_t* cur = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n + 1));
+  for (i64 j = 0; j <= n; ++j) cur[j] = rowptrT[j];
+  for (i64 i = 0; i < n; ++i)
+    for (i64 k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+      int32_t t = cur[colind[k]]++;
+      colindT[t] = (int32_t)i;
+      valT[t] = val[k];
+      permT[t] = (int32_t)k;
+    }
+  free(cur);
+}
+
+double or_eps_f64(void) { return DBL_EPSILON; }
+double or_eps_f32(void) { return (double)FLT_EPSILON; }

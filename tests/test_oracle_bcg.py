@@ -1,0 +1,205 @@
+"""Pins for the oracle's block CG (Algorithm "BCG Method with Adaptive
+Residual Re-Orthonormalization", Ch. 4).
+
+The block CG iterate X^k is the energy minimiser over X0 + K_k^S (Theorem
+"minimizing-orthogonality", Ch. 4), so it is compared with a brute-force
+minimiser over an explicitly assembled block Krylov space; s = 1 and the
+parallel subalgebra reduce to textbook scalar CG, global to scalar CG on the
+Kronecker system (Definition "elementary *-subalgebras"); plus finite
+termination, orthogonality invariants, the subalgebra-lattice ordering
+(Lemma "Embeddings of *-subalgebras"), the eigenvector one-step case and the
+Chebyshev bound (Ch. 2 / Ch. 4 convergence results).
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from krylov_ref import (energy_fro, galerkin_minimiser, laplace2d_eigpair, laplace2d_extremes,
+                        textbook_cg)
+
+SUBALGS = [("block", 1), ("hybrid", 2), ("parallel", 1), ("global", 1)]
+
+
+def small_problem(n_grid=6, s=4, seed=0):
+    A = W.laplace_2d(n_grid)
+    B = W.uniform_block(A.n, s, seed)
+    return A, A.to_dense(), B
+
+
+@pytest.mark.parametrize("kind,q", SUBALGS)
+@pytest.mark.parametrize("eta", [0.0, np.inf])
+def test_bcg_iterates_are_energy_minimisers(orc, kind, q, eta):
+    A, D, B = small_problem()
+    X0 = W.gaussian_block(A.n, 4, 9) * 0.1
+    for k in (1, 2, 3, 4):
+        r = orc.bcg(A, B, X0, kind=kind, q=q, tol=0.0, maxit=k, eta=eta)
+        assert r["iters"] == k
+        Xr = galerkin_minimiser(D, B, X0, k, kind, q)
+        err = np.linalg.norm(r["X"] - Xr) / np.linalg.norm(Xr)
+        assert err < 1e-10, (k, err)
+
+
+def test_bcg_s1_is_textbook_cg(orc):
+    A, D, B = small_problem(s=1)
+    for k in range(1, 9):
+        r = orc.bcg(A, B, kind="block", tol=0.0, maxit=k)
+        x = textbook_cg(D, B[:, 0], np.zeros(A.n), k)
+        assert np.allclose(r["X"][:, 0], x, rtol=0, atol=1e-12 * np.abs(x).max())
+
+
+def test_bcg_parallel_is_independent_cgs(orc):
+    A, D, B = small_problem(s=5)
+    for k in (1, 3, 7, 12):
+        r = orc.bcg(A, B, kind="parallel", tol=0.0, maxit=k)
+        for j in range(5):
+            x = textbook_cg(D, B[:, j], np.zeros(A.n), k)
+            assert np.allclose(r["X"][:, j], x, rtol=0, atol=1e-11 * np.abs(x).max())
+
+
+def test_bcg_global_is_cg_on_kronecker_system(orc):
+    A, D, B = small_problem(s=3)
+    Dk = np.kron(np.eye(3), D)
+    for k in (1, 2, 5, 9):
+        r = orc.bcg(A, B, kind="global", tol=0.0, maxit=k)
+        x = textbook_cg(Dk, B.reshape(-1, order="F"), np.zeros(3 * A.n), k)
+        assert np.allclose(r["X"].reshape(-1, order="F"), x, rtol=0, atol=1e-11 * np.abs(x).max())
+
+
+def test_bcg_hybrid_is_independent_block_solves(orc):
+    A, D, B = small_problem(s=8)
+    for k in (1, 3, 6):
+        r = orc.bcg(A, B, kind="hybrid", q=2, tol=0.0, maxit=k)
+        for grp in range(2):
+            sub = orc.bcg(A, B[:, 4 * grp:4 * grp + 4], kind="block", tol=0.0, maxit=k)
+            assert np.allclose(r["X"][:, 4 * grp:4 * grp + 4], sub["X"], rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("s", [1, 2, 4])
+@pytest.mark.parametrize("kind,q", SUBALGS)
+def test_bcg_matches_dense_solution(orc, kind, q, s):
+    if kind == "hybrid" and s % 2:
+        pytest.skip("q must divide s")
+    grid = small_problem(n_grid=7, s=s, seed=s)
+    A2 = W.random_spd_csr(60, 0.1, seed=s, shift=1.0)
+    rnd = (A2, A2.to_dense(), W.uniform_block(60, s, s))
+    for (A, D, B), eta in [(grid, np.inf), (rnd, 1e4), (rnd, 0.0)]:
+        r = orc.bcg(A, B, kind=kind, q=q, tol=1e-12, maxit=500, eta=eta)
+        assert r["status"] == orc.OK and r["converged"]
+        Xs = np.linalg.solve(D, B)
+        assert np.linalg.norm(r["X"] - Xs) / np.linalg.norm(Xs) < 1e-10
+        R = B - D @ r["X"]
+        assert np.all(np.linalg.norm(R, axis=0) / np.linalg.norm(B, axis=0) < 1e-11)
+
+
+def test_bcg_exhausted_krylov_space_breaks_down_without_reortho(orc):
+    """The 7x7 grid Laplacian has repeated eigenvalues, so the block Krylov
+    space is exhausted before ceil(n/s) steps and the residual turns rank
+    deficient; with eta = 0 (and here also eta = 1e4, whose kappa_D test does
+    not fire in time) the Cholesky of rho fails, while eta = inf converges."""
+    A, D, B = small_problem(n_grid=7, s=4, seed=4)
+    assert orc.bcg(A, B, kind="block", tol=1e-12, maxit=500, eta=0.0)["status"] == orc.E_BREAKDOWN
+    r = orc.bcg(A, B, kind="block", tol=1e-12, maxit=500, eta=np.inf)
+    assert r["converged"] and r["iters"] <= 13
+
+
+@pytest.mark.parametrize("kind,q,g", [("block", 1, 4), ("hybrid", 2, 2), ("parallel", 1, 1)])
+def test_bcg_finite_termination(orc, kind, q, g):
+    """X* lies in X0 + K_nu with block grade nu <= ceil(n/g) (Lemma on the block grade, Ch. 3)."""
+    A = W.random_spd_csr(24, 0.2, seed=4, shift=2.0)
+    B = W.gaussian_block(24, 4, 1)
+    r = orc.bcg(A, B, kind=kind, q=q, tol=1e-8, maxit=200, eta=np.inf)
+    assert r["converged"] and r["iters"] <= int(np.ceil(24 / g))
+
+
+@pytest.mark.parametrize("kind,q", SUBALGS)
+def test_bcg_orthogonality_invariants(orc, kind, q):
+    """<R^k, P^j>_S = 0 for j < k and <P^i, A P^j>_S = 0 for i != j."""
+    A, D, B = small_problem(n_grid=8, s=4)
+    r = orc.bcg(A, B, kind=kind, q=q, tol=0.0, maxit=5, eta=1e4, record_blocks=6)
+    Pk, Rk = r["Pk"], r["Rk"]
+    for k in range(len(Rk)):
+        for j in range(k):
+            G = orc.bdot(Rk[k], Pk[j], kind, q)
+            assert np.abs(G).max() < 1e-11 * np.linalg.norm(Rk[k]) * np.linalg.norm(Pk[j])
+    for i in range(len(Pk)):
+        for j in range(len(Pk)):
+            if i != j:
+                G = orc.bdot(Pk[i], D @ Pk[j], kind, q)
+                scale = np.linalg.norm(Pk[i]) * np.linalg.norm(D @ Pk[j])
+                assert np.abs(G).max() < 1e-11 * scale
+
+
+def test_bcg_lattice_ordering(orc):
+    """Energy errors at equal k are ordered S_P >= S_BP^2 >= S_BP^4 >= S_B."""
+    A, D, B = small_problem(n_grid=8, s=8, seed=3)
+    Xs = np.linalg.solve(D, B)
+    for k in (1, 2, 3, 4):
+        errs = []
+        for kind, q in [("parallel", 1), ("hybrid", 4), ("hybrid", 2), ("block", 1)]:
+            r = orc.bcg(A, B, kind=kind, q=q, tol=0.0, maxit=k)
+            errs.append(energy_fro(D, r["X"] - Xs))
+        assert all(errs[i + 1] <= errs[i] * (1 + 1e-10) for i in range(3)), errs
+
+
+@pytest.mark.parametrize("kind", ["block", "parallel"])
+def test_bcg_eigenvector_rhs_one_step(orc, kind):
+    N = 8
+    pairs = [laplace2d_eigpair(N, i, j) for (i, j) in [(1, 1), (1, 2), (2, 3), (4, 1)]]
+    B = np.stack([u for _, u in pairs], axis=1)
+    A = W.laplace_2d(N)
+    r = orc.bcg(A, B, kind=kind, tol=1e-12, maxit=10)
+    assert r["converged"] and r["iters"] == 1
+    Xs = B / np.array([lam for lam, _ in pairs])[None, :]
+    assert np.allclose(r["X"], Xs, atol=1e-13)
+
+
+@pytest.mark.parametrize("kind,q", SUBALGS)
+def test_bcg_chebyshev_bound(orc, kind, q):
+    N = 10
+    A = W.laplace_2d(N)
+    D = A.to_dense()
+    B = W.uniform_block(A.n, 4, 2)
+    lo, hi = laplace2d_extremes(N)
+    kap = hi / lo
+    mu = (np.sqrt(kap) - 1) / (np.sqrt(kap) + 1)
+    Xs = np.linalg.solve(D, B)
+    e0 = energy_fro(D, Xs)
+    for k in (1, 5, 10, 20):
+        r = orc.bcg(A, B, kind=kind, q=q, tol=0.0, maxit=k)
+        assert energy_fro(D, r["X"] - Xs) <= 2 * mu ** k * e0 * (1 + 1e-12)
+
+
+def test_bcg_breakdown_and_edge_cases(orc):
+    A, D, B = small_problem()
+    negA = W.Csr(A.n, A.rowptr, A.colind, -A.val)
+    assert orc.bcg(negA, B, kind="block", eta=0.0)["status"] == orc.E_BREAKDOWN
+    Bz = B.copy()
+    Bz[:, 1] = 0.0
+    assert orc.bcg(A, Bz, kind="block", eta=0.0, tol=1e-12)["status"] == orc.E_BREAKDOWN
+    r = orc.bcg(A, Bz, kind="block", eta=np.inf, tol=1e-12, maxit=200)
+    assert r["converged"] and np.abs(r["X"][:, 1]).max() < 1e-12
+    assert np.allclose(r["X"], np.linalg.solve(D, Bz), atol=1e-10)
+    r = orc.bcg(A, np.zeros_like(B), kind="block")
+    assert r["converged"] and r["iters"] == 0 and np.all(r["X"] == 0)
+    r = orc.bcg(A, B, kind="block", maxit=1, tol=1e-10)
+    assert r["status"] == orc.NOT_CONVERGED and r["iters"] == 1
+    assert orc.bcg(A, B, kind="hybrid", q=3)["status"] == orc.E_INVALID
+
+
+def test_bcg_reortho_counts(orc):
+    A, D, B = small_problem(n_grid=10, s=4)
+    r = orc.bcg(A, B, kind="block", tol=1e-10, maxit=500, eta=np.inf)
+    assert r["reorth"] == r["iters"] + 1       # the initial residual and every iteration
+    r0 = orc.bcg(A, B, kind="block", tol=1e-10, maxit=500, eta=0.0)
+    assert r0["reorth"] == 0
+    rp = orc.bcg(A, B, kind="parallel", tol=1e-10, maxit=500, eta=1e4)
+    assert rp["reorth"] == 1                  # kappa_D = 1 in the parallel case
+
+
+def test_bcg_recursive_residual_tracks_true_residual(orc):
+    A, D, B = small_problem(n_grid=12, s=4)
+    for eta in (0.0, 1e4, np.inf):
+        r = orc.bcg(A, B, kind="block", tol=1e-10, maxit=500, eta=eta)
+        true = np.linalg.norm(B - D @ r["X"], axis=0) / np.linalg.norm(B, axis=0)
+        assert np.allclose(true, r["relres"], rtol=1e-3, atol=1e-13)
+        assert r["relres"].max() <= 1e-10
