@@ -1,0 +1,168 @@
+/*
+ * bkry.h -- C ABI of the MI355X block Krylov library (libbkry.so).
+ *
+ * Solves A X = B for a sparse n x n matrix A in CSR form and p right-hand
+ * sides (the block system of Ch. 3, "A General Block Krylov Framework", of
+ * N.-A. Dreier, "Hardware-Oriented Krylov Methods for High-Performance
+ * Computing", arXiv 2104.02494), over a chosen *-subalgebra S of R^{p x p}.
+ *
+ * Conventions shared by every entry point:
+ *  - Pointers are DEVICE pointers (memory of the handle's device) unless a
+ *    comment marks them [host].  The caller owns every buffer it passes; the
+ *    library owns only its internal workspace, which lives as long as the
+ *    handle.
+ *  - Block vectors are n x p, row-major ("row-interleaved": element (i,j) at
+ *    i*p + j), FP64 unless the name says _f32; 16-byte aligned base pointers.
+ *  - CSR is 0-based with int32 row pointers and column indices, columns
+ *    sorted or not, nnz < 2^31.  Kernels never read outside [0, nnz) or
+ *    outside the n rows of a block even for malformed index data; a column
+ *    index outside [0, n) makes the call fail with BKRY_E_INVALID (reported
+ *    by the solvers, and by bkry_last_error after a bkry_synchronize for the
+ *    asynchronous kernels).
+ *  - 1 <= p <= 32.  Every call is ordered on the handle's stream.  bkry_spmm,
+ *    bkry_bdot, bkry_tsqr and bkry_sddmm are asynchronous; the solvers and
+ *    bkry_csr_transpose return when their result is complete.
+ *  - Every function returns a status code; no C++ exception crosses the ABI.
+ *    The last failure's message is available from bkry_last_error.
+ *  - Results are deterministic: reductions run in a fixed order, with no
+ *    floating-point atomics, so repeated calls give identical bits.
+ */
+#ifndef BKRY_H
+#define BKRY_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define BKRY_OK 0
+#define BKRY_NOT_CONVERGED 1 /* iteration cap reached; X holds the last iterate, info is valid */
+#define BKRY_E_INVALID (-1)  /* bad size, null pointer, p % q != 0, p > 32, bad CSR index */
+#define BKRY_E_BREAKDOWN (-2) /* a Cholesky pivot of alpha or rho was not positive (A not SPD,
+                                 or a rank-deficient residual without re-orthonormalisation) */
+#define BKRY_E_NONFINITE (-3) /* a non-finite value appeared in the block coefficients */
+#define BKRY_E_HIP (-4)       /* HIP runtime error */
+#define BKRY_E_ALLOC (-5)     /* device memory allocation failed */
+
+/* *-subalgebras (Definitions "elementary *-subalgebras" and "Relevant
+ * *-subalgebras", Ch. 3):
+ *   BKRY_PARALLEL  diagonal matrices, <X,Y> = diag(X^T Y)  (columns independent);
+ *   BKRY_GLOBAL    multiples of I, <X,Y> = tr(X^T Y)/p * I;
+ *   BKRY_BLOCK     all p x p matrices, <X,Y> = X^T Y;
+ *   BKRY_HYBRID    block-parallel with q contiguous column groups of width p/q,
+ *                  <X,Y> = blockdiag(X_1^T Y_1, ..., X_q^T Y_q).            */
+#define BKRY_PARALLEL 0
+#define BKRY_GLOBAL 1
+#define BKRY_BLOCK 2
+#define BKRY_HYBRID 3
+
+/* arithmetic of a CG solve */
+#define BKRY_F64 0    /* everything in FP64 */
+#define BKRY_F32_IR 1 /* FP32 inner block CG (SpMM, BDOT, BAXPY, TSQR tiles in FP32,
+                         p x p algebra and TSQR R-combine in FP64) inside FP64
+                         iterative refinement on the true residual */
+
+typedef struct bkry_handle_s* bkry_handle;
+
+typedef struct {
+  int32_t kind; /* BKRY_PARALLEL / GLOBAL / BLOCK / HYBRID */
+  int32_t q;    /* number of column groups for BKRY_HYBRID (p % q == 0); ignored otherwise */
+} bkry_subalg;
+
+typedef struct {
+  int64_t n;
+  int64_t nnz;
+  const int32_t* rowptr; /* [n+1] */
+  const int32_t* colind; /* [nnz] */
+  const double* val;     /* [nnz] */
+} bkry_csr;
+
+typedef struct {
+  /* inputs (0 / NULL select the default) */
+  double inner_tol;     /* BKRY_F32_IR: relative tolerance of each inner solve (default 1e-5) */
+  int32_t max_outer;    /* BKRY_F32_IR: cap on refinement steps (default 30) */
+  int32_t hist_cap;     /* capacity of hist */
+  double* hist;         /* [host] per iteration: max_i relative residual of column i */
+  double* relres;       /* [host] p entries: final relative column residuals (recursive) */
+  double* true_relres;  /* [host] p entries: final |B_i - A X_i| / |R0_i|, recomputed in FP64 */
+  /* outputs */
+  int32_t iters;        /* block iterations (CG) or Arnoldi steps (GMRes), inner total for IR */
+  int32_t reorth;       /* normalisations of the residual (CG) */
+  int32_t outer_iters;  /* refinement steps (IR) or restart cycles (GMRes) */
+  int32_t converged;    /* 1 if every column met the tolerance */
+  int32_t hist_len;     /* entries written to hist */
+  int32_t pad_;
+  double seconds;       /* wall time of the solve */
+} bkry_info;
+
+/* Create a handle on HIP device `device` that orders all work on `stream`
+ * (a hipStream_t; NULL = the null stream).  The handle is not thread-safe. */
+int bkry_create(bkry_handle* h, int device, void* stream);
+int bkry_destroy(bkry_handle h);
+int bkry_set_stream(bkry_handle h, void* stream);
+/* Wait for the handle's stream and report a pending asynchronous error. */
+int bkry_synchronize(bkry_handle h);
+/* Message of the last failing call on this handle (valid until the next call). */
+const char* bkry_last_error(bkry_handle h);
+
+/* BOP (Ch. 3, Performance Analysis): Y = A X for n x p blocks.  Each output
+ * entry is summed over the row's non-zeros in storage order. */
+int bkry_spmm(bkry_handle h, const bkry_csr* A, int32_t p, const double* X, double* Y);
+/* FP32 BOP with FP32 accumulation (the inner kernel of BKRY_F32_IR). */
+int bkry_spmm_f32(bkry_handle h, int64_t n, int64_t nnz, const int32_t* rowptr, const int32_t* colind,
+                  const float* val, int32_t p, const float* X, float* Y);
+
+/* BDOT (Ch. 3, block inner product): G = <X, Y>_S, a p x p row-major device
+ * array; entries outside the subalgebra's pattern are zero. */
+int bkry_bdot(bkry_handle h, int64_t n, int32_t p, bkry_subalg S, const double* X, const double* Y, double* G);
+/* FP32 BDOT with FP32 accumulation inside each workgroup; G in FP64. */
+int bkry_bdot_f32(bkry_handle h, int64_t n, int32_t p, bkry_subalg S, const float* X, const float* Y, double* G);
+
+/* Normaliser / S-QR decomposition (Definition "normalizer", Ch. 3; TSQR,
+ * Ch. 7): X = Q R with <Q,Q>_S = I and R in S upper triangular per S-block,
+ * diag(R) >= 0; Q overwrites X, R (p x p) goes to device memory.  Block and
+ * hybrid use a Householder tall-skinny QR (tile QRs, then a tree of R
+ * combines); parallel normalises columns and global scales by
+ * |X|_F / sqrt(p).  Rank-deficient X is allowed: Q is still S-orthonormal.
+ * Requires n >= p (block/global) or n >= p/q (hybrid). */
+int bkry_tsqr(bkry_handle h, int64_t n, int32_t p, bkry_subalg S, double* X_inout_Q, double* R);
+
+/* Block CG with adaptive residual re-orthonormalisation (Algorithm "BCG
+ * Method with Adaptive Residual Re-Orthonormalization", Ch. 4) for SPD A,
+ * without preconditioner.  X holds X0 on entry and the solution on exit.
+ * Stops when max_i |R_i| / |R0_i| <= tol (recursive residual) or after maxit
+ * iterations.  The residual is re-normalised in iteration k when
+ * eta * kappa_D(alpha_k) * sqrt(eps) > 1 (eps of the working precision);
+ * eta = 0 never, eta = INFINITY always.  prec = BKRY_F64 or BKRY_F32_IR.
+ * info [host] may be NULL. */
+int bkry_cg_solve(bkry_handle h, const bkry_csr* A, int32_t p, bkry_subalg S, const double* B, double* X,
+                  double tol, int32_t maxit, double eta, int32_t prec, bkry_info* info);
+
+/* Restarted block GMRes (Algorithm "Block GMRes Method", Ch. 5): block
+ * Arnoldi with classical Gram-Schmidt applied twice (Algorithm "classical
+ * Gram-Schmidt", Ch. 9) and TSQR normalisation of each new block, generalised
+ * Givens rotations on the block Hessenberg matrix, restart length `restart`.
+ * maxit counts Arnoldi steps over all cycles.  Stops when every column's
+ * relative residual is <= tol (Frobenius form for BKRY_GLOBAL).  Requires
+ * n >= p. */
+int bkry_gmres_solve(bkry_handle h, const bkry_csr* A, int32_t p, bkry_subalg S, const double* B, double* X,
+                     double tol, int32_t maxit, int32_t restart, bkry_info* info);
+
+/* Sampled product on the pattern of A: out_val[k] = alpha * sum_c L[i][c] X[j][c]
+ * for the k-th stored entry (i, j).  With L the adjoint solution and
+ * alpha = -1 this is the gradient of a loss with respect to the values of A. */
+int bkry_sddmm(bkry_handle h, const bkry_csr* pattern, int32_t p, double alpha, const double* L, const double* X,
+               double* out_val);
+
+/* Transpose of a square CSR matrix (counting sort; rows of A^T list their
+ * columns in ascending order).  rowptrT [n+1], colindT/valT/permT [nnz];
+ * permT[t] is the position in A of entry t of A^T.  Synchronous. */
+int bkry_csr_transpose(bkry_handle h, const bkry_csr* A, int32_t* rowptrT, int32_t* colindT, double* valT,
+                       int32_t* permT);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BKRY_H */

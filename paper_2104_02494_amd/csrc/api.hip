@@ -1,0 +1,443 @@
+// api.hip -- the C ABI of libbkry.so (declared in include/bkry.h).
+//
+// The handle owns a growable device workspace, a pinned host staging area
+// and the stream; every entry point validates its arguments on the host
+// (sizes, pointers, subalgebra), sets the device, and then only enqueues
+// kernels.  No C++ exception crosses the ABI.
+#include <float.h>
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <chrono>
+#include <new>
+#include <string>
+
+#include "bkry.h"
+#include "solvers.hpp"
+
+using namespace bkry;
+
+struct bkry_handle_s {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  char* ws = nullptr;
+  size_t ws_cap = 0;
+  int32_t* hflags = nullptr;  // pinned host, kHostFlagsInts
+  int32_t* dflags = nullptr;  // device: [0] bad CSR index seen by an asynchronous kernel
+  std::string err;
+};
+
+namespace {
+
+int fail(bkry_handle h, int code, const std::string& msg) {
+  if (h) h->err = msg;
+  return code;
+}
+
+int hip_fail(bkry_handle h, hipError_t e, const char* where) {
+  return fail(h, BKRY_E_HIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define API_HIP(x, where)                           \
+  do {                                              \
+    hipError_t e_ = (x);                            \
+    if (e_ != hipSuccess) return hip_fail(h, e_, where); \
+  } while (0)
+
+int ensure_ws(bkry_handle h, size_t bytes) {
+  if (bytes <= h->ws_cap) return BKRY_OK;
+  hipError_t e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "workspace sync");
+  if (h->ws) (void)hipFree(h->ws);
+  h->ws = nullptr;
+  h->ws_cap = 0;
+  size_t want = bytes + bytes / 8;
+  e = hipMalloc(reinterpret_cast<void**>(&h->ws), want);
+  if (e != hipSuccess) {
+    h->ws = nullptr;
+    (void)hipGetLastError();
+    return fail(h, BKRY_E_ALLOC, "workspace allocation of " + std::to_string(want) + " bytes failed");
+  }
+  h->ws_cap = want;
+  return BKRY_OK;
+}
+
+int begin(bkry_handle h) {
+  if (!h) return BKRY_E_INVALID;
+  h->err.clear();
+  hipError_t e = hipSetDevice(h->device);
+  if (e != hipSuccess) return hip_fail(h, e, "hipSetDevice");
+  return BKRY_OK;
+}
+
+// Validates p and the subalgebra; fills sub.
+int check_sub(bkry_handle h, int32_t p, bkry_subalg S, Sub& sub) {
+  if (p < 1 || p > kMaxS) return fail(h, BKRY_E_INVALID, "p must be in [1, 32]");
+  sub.s = p;
+  sub.kind = S.kind;
+  switch (S.kind) {
+    case BKRY_BLOCK: sub.g = p; break;
+    case BKRY_PARALLEL:
+    case BKRY_GLOBAL: sub.g = 1; break;
+    case BKRY_HYBRID:
+      if (S.q < 1 || p % S.q != 0) return fail(h, BKRY_E_INVALID, "hybrid subalgebra needs q >= 1 dividing p");
+      sub.g = p / S.q;
+      break;
+    default: return fail(h, BKRY_E_INVALID, "unknown subalgebra kind");
+  }
+  return BKRY_OK;
+}
+
+int check_csr(bkry_handle h, const bkry_csr* A, bool need_val) {
+  if (!A) return fail(h, BKRY_E_INVALID, "null CSR descriptor");
+  if (A->n < 1) return fail(h, BKRY_E_INVALID, "n must be >= 1");
+  if (A->nnz < 0 || A->nnz >= (int64_t)1 << 31) return fail(h, BKRY_E_INVALID, "nnz must be in [0, 2^31)");
+  if (A->n >= (int64_t)1 << 31) return fail(h, BKRY_E_INVALID, "n must be < 2^31");
+  if (!A->rowptr) return fail(h, BKRY_E_INVALID, "null rowptr");
+  if (A->nnz > 0 && (!A->colind || (need_val && !A->val))) return fail(h, BKRY_E_INVALID, "null colind/val");
+  return BKRY_OK;
+}
+
+bool misaligned(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) != 0; }
+
+int check_blocks(bkry_handle h, std::initializer_list<const void*> ptrs) {
+  for (const void* p : ptrs) {
+    if (!p) return fail(h, BKRY_E_INVALID, "null block pointer");
+    if (misaligned(p)) return fail(h, BKRY_E_INVALID, "block pointers must be 16-byte aligned");
+  }
+  return BKRY_OK;
+}
+
+CsrView view(const bkry_csr* A) { return CsrView{A->n, A->nnz, A->rowptr, A->colind, A->val}; }
+
+int status_of(int st, bkry_handle h) {
+  if (st == -2) return fail(h, BKRY_E_BREAKDOWN, "breakdown: a Cholesky pivot of alpha or rho was not positive");
+  if (st == -3) return fail(h, BKRY_E_NONFINITE, "non-finite value in the block coefficients");
+  return BKRY_OK;
+}
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+template <typename T>
+int bdot_impl(bkry_handle h, int64_t n, int32_t p, bkry_subalg S, const T* X, const T* Y, double* G) {
+  int rc = begin(h);
+  Sub sub;
+  if (!rc) rc = check_sub(h, p, S, sub);
+  if (!rc && n < 1) rc = fail(h, BKRY_E_INVALID, "n must be >= 1");
+  if (!rc) rc = check_blocks(h, {X, Y});
+  if (!rc && !G) rc = fail(h, BKRY_E_INVALID, "null G");
+  if (rc) return rc;
+  const int nblk = stream_grid(n, p, sizeof(T));
+  Carver c;
+  c.take<T>((size_t)nblk * p * p);
+  c.take<double>((size_t)p * p);
+  rc = ensure_ws(h, c.off);
+  if (rc) return rc;
+  Carver w{h->ws};
+  T* part = w.take<T>((size_t)nblk * p * p);
+  double* Gf = w.take<double>((size_t)p * p);
+  API_HIP(launch_gram<T>(n, p, X, Y, part, nblk, nullptr, h->stream), "bdot");
+  API_HIP(launch_reduce_partials<T>(p, part, nblk, Gf, nullptr, h->stream), "bdot");
+  API_HIP(launch_project(Gf, G, sub, h->stream), "bdot");
+  return BKRY_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int bkry_create(bkry_handle* out, int device, void* stream) {
+  if (!out) return BKRY_E_INVALID;
+  *out = nullptr;
+  bkry_handle h = new (std::nothrow) bkry_handle_s();
+  if (!h) return BKRY_E_ALLOC;
+  h->device = device;
+  h->stream = static_cast<hipStream_t>(stream);
+  hipError_t e = hipSetDevice(device);
+  if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&h->hflags), kHostFlagsInts * sizeof(int32_t));
+  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&h->dflags), 64 * sizeof(int32_t));
+  if (e == hipSuccess) e = hipMemsetAsync(h->dflags, 0, 64 * sizeof(int32_t), h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) {
+    if (h->hflags) (void)hipHostFree(h->hflags);
+    if (h->dflags) (void)hipFree(h->dflags);
+    delete h;
+    return BKRY_E_HIP;
+  }
+  *out = h;
+  return BKRY_OK;
+}
+
+int bkry_destroy(bkry_handle h) {
+  if (!h) return BKRY_E_INVALID;
+  (void)hipSetDevice(h->device);
+  (void)hipStreamSynchronize(h->stream);
+  if (h->ws) (void)hipFree(h->ws);
+  if (h->dflags) (void)hipFree(h->dflags);
+  if (h->hflags) (void)hipHostFree(h->hflags);
+  delete h;
+  return BKRY_OK;
+}
+
+int bkry_set_stream(bkry_handle h, void* stream) {
+  int rc = begin(h);
+  if (rc) return rc;
+  h->stream = static_cast<hipStream_t>(stream);
+  return BKRY_OK;
+}
+
+const char* bkry_last_error(bkry_handle h) { return h ? h->err.c_str() : "null handle"; }
+
+int bkry_synchronize(bkry_handle h) {
+  int rc = begin(h);
+  if (rc) return rc;
+  API_HIP(hipMemcpyAsync(h->hflags, h->dflags, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream), "sync");
+  API_HIP(hipStreamSynchronize(h->stream), "sync");
+  if (h->hflags[0]) {
+    API_HIP(hipMemsetAsync(h->dflags, 0, sizeof(int32_t), h->stream), "sync");
+    API_HIP(hipStreamSynchronize(h->stream), "sync");
+    return fail(h, BKRY_E_INVALID, "a CSR column index was outside [0, n)");
+  }
+  return BKRY_OK;
+}
+
+int bkry_spmm(bkry_handle h, const bkry_csr* A, int32_t p, const double* X, double* Y) {
+  int rc = begin(h);
+  if (!rc) rc = check_csr(h, A, true);
+  if (!rc && (p < 1 || p > kMaxS)) rc = fail(h, BKRY_E_INVALID, "p must be in [1, 32]");
+  if (!rc) rc = check_blocks(h, {X, Y});
+  if (rc) return rc;
+  const int nblk = stream_grid(A->n, p, sizeof(double));
+  API_HIP(launch_spmm<double>(view(A), p, X, Y, nullptr, 0, nullptr, nblk, h->dflags, nullptr, h->stream), "spmm");
+  return BKRY_OK;
+}
+
+int bkry_spmm_f32(bkry_handle h, int64_t n, int64_t nnz, const int32_t* rowptr, const int32_t* colind,
+                  const float* val, int32_t p, const float* X, float* Y) {
+  bkry_csr A{n, nnz, rowptr, colind, nullptr};
+  int rc = begin(h);
+  if (!rc) rc = check_csr(h, &A, false);
+  if (!rc && nnz > 0 && !val) rc = fail(h, BKRY_E_INVALID, "null val");
+  if (!rc && (p < 1 || p > kMaxS)) rc = fail(h, BKRY_E_INVALID, "p must be in [1, 32]");
+  if (!rc) rc = check_blocks(h, {X, Y});
+  if (rc) return rc;
+  CsrView v{n, nnz, rowptr, colind, val};
+  const int nblk = stream_grid(n, p, sizeof(float));
+  API_HIP(launch_spmm<float>(v, p, X, Y, nullptr, 0, nullptr, nblk, h->dflags, nullptr, h->stream), "spmm_f32");
+  return BKRY_OK;
+}
+
+int bkry_bdot(bkry_handle h, int64_t n, int32_t p, bkry_subalg S, const double* X, const double* Y, double* G) {
+  return bdot_impl<double>(h, n, p, S, X, Y, G);
+}
+
+int bkry_bdot_f32(bkry_handle h, int64_t n, int32_t p, bkry_subalg S, const float* X, const float* Y, double* G) {
+  return bdot_impl<float>(h, n, p, S, X, Y, G);
+}
+
+int bkry_tsqr(bkry_handle h, int64_t n, int32_t p, bkry_subalg S, double* X, double* R) {
+  int rc = begin(h);
+  Sub sub;
+  if (!rc) rc = check_sub(h, p, S, sub);
+  if (!rc && (n < sub.g || (S.kind == BKRY_GLOBAL && n < p)))
+    rc = fail(h, BKRY_E_INVALID, "the normaliser needs n >= p (block, global) or n >= p/q (hybrid)");
+  if (!rc) rc = check_blocks(h, {X});
+  if (!rc && !R) rc = fail(h, BKRY_E_INVALID, "null R");
+  if (rc) return rc;
+  rc = ensure_ws(h, tsqr_workspace_bytes(n, sub));
+  if (rc) return rc;
+  API_HIP(tsqr_run<double>(n, sub, X, R, h->ws, nullptr, nullptr, h->stream), "tsqr");
+  return BKRY_OK;
+}
+
+int bkry_cg_solve(bkry_handle h, const bkry_csr* A, int32_t p, bkry_subalg S, const double* B, double* X,
+                  double tol, int32_t maxit, double eta, int32_t prec, bkry_info* info) {
+  int rc = begin(h);
+  Sub sub;
+  if (!rc) rc = check_csr(h, A, true);
+  if (!rc) rc = check_sub(h, p, S, sub);
+  if (!rc) rc = check_blocks(h, {B, X});
+  if (!rc && !(tol >= 0.0)) rc = fail(h, BKRY_E_INVALID, "tol must be >= 0");
+  if (!rc && maxit < 0) rc = fail(h, BKRY_E_INVALID, "maxit must be >= 0");
+  if (!rc && !(eta >= 0.0)) rc = fail(h, BKRY_E_INVALID, "eta must be >= 0");
+  if (!rc && prec != BKRY_F64 && prec != BKRY_F32_IR) rc = fail(h, BKRY_E_INVALID, "unknown precision");
+  if (!rc && eta > 0.0 && (A->n < sub.g || (S.kind == BKRY_GLOBAL && A->n < p)))
+    rc = fail(h, BKRY_E_INVALID, "re-orthonormalisation needs n >= p (block, global) or n >= p/q (hybrid)");
+  if (rc) return rc;
+  const double t0 = now_s();
+  const int64_t n = A->n;
+  const int hist_cap = (info && info->hist && info->hist_cap > 0) ? info->hist_cap : 0;
+  double relres[kMaxS], trel[kMaxS];
+  int status = 0, iters = 0, nre = 0, outer = 0, conv = 0, bad = 0, hist_len = 0;
+  if (prec == BKRY_F64) {
+    Carver c;
+    carve_cg<double>(c, n, sub, hist_cap);
+    c.take<double>(kMaxS);
+    c.take<double>(kMaxS);
+    c.take<int32_t>(4);
+    rc = ensure_ws(h, c.off);
+    if (rc) return rc;
+    Carver w{h->ws};
+    CgBufs<double> cb = carve_cg<double>(w, n, sub, hist_cap);
+    double* trr = w.take<double>(kMaxS);
+    double* tsc = w.take<double>(kMaxS);
+    int32_t* tfl = w.take<int32_t>(4);
+    CgResult r;
+    hipError_t e = cg_run<double>(view(A), sub, B, X, tol, maxit, eta, DBL_EPSILON, hist_cap, cb, h->stream,
+                                  h->hflags, r);
+    if (e != hipSuccess) return hip_fail(h, e, "cg_solve");
+    status = r.status;
+    iters = r.iters;
+    nre = r.nreorth;
+    conv = r.converged;
+    bad = r.bad_index;
+    hist_len = iters < hist_cap ? iters : hist_cap;
+    API_HIP(hipMemcpyAsync(relres, cb.ctl->relres, sizeof(double) * p, hipMemcpyDeviceToHost, h->stream), "cg");
+    if (hist_len > 0)
+      API_HIP(hipMemcpyAsync(info->hist, cb.hist, sizeof(double) * hist_len, hipMemcpyDeviceToHost, h->stream), "cg");
+    API_HIP(true_relres(view(A), p, B, X, cb.Q, cb.partial, cb.Ga, cb.ctl->r0n, trr, tfl, tsc, h->stream), "cg");
+    API_HIP(hipMemcpyAsync(trel, trr, sizeof(double) * p, hipMemcpyDeviceToHost, h->stream), "cg");
+    API_HIP(hipStreamSynchronize(h->stream), "cg");
+  } else {
+    Carver c;
+    carve_ir(c, n, A->nnz, sub);
+    c.take<double>(kMaxS);
+    c.take<double>(kMaxS);
+    c.take<int32_t>(4);
+    rc = ensure_ws(h, c.off);
+    if (rc) return rc;
+    Carver w{h->ws};
+    IrBufs ib = carve_ir(w, n, A->nnz, sub);
+    double* trr = w.take<double>(kMaxS);
+    double* tsc = w.take<double>(kMaxS);
+    int32_t* tfl = w.take<int32_t>(4);
+    const double itol = (info && info->inner_tol > 0.0) ? info->inner_tol : 1e-5;
+    const int mo = (info && info->max_outer > 0) ? info->max_outer : 30;
+    IrResult r;
+    hipError_t e = ir_run(view(A), sub, B, X, tol, maxit, eta, itol, mo, info ? info->hist : nullptr, hist_cap, ib,
+                          h->stream, h->hflags, relres, r);
+    if (e != hipSuccess) return hip_fail(h, e, "cg_solve (FP32 refinement)");
+    status = r.status;
+    iters = r.inner_iters;
+    nre = r.nreorth;
+    outer = r.outer;
+    conv = r.converged;
+    bad = r.bad_index;
+    hist_len = r.hist_len;
+    API_HIP(true_relres(view(A), p, B, X, ib.R64, ib.partial, ib.G, ib.r0n, trr, tfl, tsc, h->stream), "ir");
+    API_HIP(hipMemcpyAsync(trel, trr, sizeof(double) * p, hipMemcpyDeviceToHost, h->stream), "ir");
+    API_HIP(hipStreamSynchronize(h->stream), "ir");
+  }
+  if (info) {
+    info->iters = iters;
+    info->reorth = nre;
+    info->outer_iters = outer;
+    info->converged = conv;
+    info->hist_len = hist_len;
+    info->seconds = now_s() - t0;
+    if (info->relres) memcpy(info->relres, relres, sizeof(double) * p);
+    if (info->true_relres) memcpy(info->true_relres, trel, sizeof(double) * p);
+  }
+  if (bad) return fail(h, BKRY_E_INVALID, "a CSR column index was outside [0, n)");
+  rc = status_of(status, h);
+  if (rc) return rc;
+  return conv ? BKRY_OK : BKRY_NOT_CONVERGED;
+}
+
+int bkry_gmres_solve(bkry_handle h, const bkry_csr* A, int32_t p, bkry_subalg S, const double* B, double* X,
+                     double tol, int32_t maxit, int32_t restart, bkry_info* info) {
+  int rc = begin(h);
+  Sub sub;
+  if (!rc) rc = check_csr(h, A, true);
+  if (!rc) rc = check_sub(h, p, S, sub);
+  if (!rc) rc = check_blocks(h, {B, X});
+  if (!rc && !(tol >= 0.0)) rc = fail(h, BKRY_E_INVALID, "tol must be >= 0");
+  if (!rc && maxit < 0) rc = fail(h, BKRY_E_INVALID, "maxit must be >= 0");
+  if (!rc && (restart < 1 || restart > 200)) rc = fail(h, BKRY_E_INVALID, "restart must be in [1, 200]");
+  if (!rc && A->n < p) rc = fail(h, BKRY_E_INVALID, "block GMRes needs n >= p");
+  if (rc) return rc;
+  const double t0 = now_s();
+  const int64_t n = A->n;
+  const int hist_cap = (info && info->hist && info->hist_cap > 0) ? info->hist_cap : 0;
+  Carver c;
+  carve_gm(c, n, sub, restart, hist_cap);
+  c.take<double>(kMaxS);
+  c.take<double>(kMaxS);
+  rc = ensure_ws(h, c.off);
+  if (rc) return rc;
+  Carver w{h->ws};
+  GmBufs gb = carve_gm(w, n, sub, restart, hist_cap);
+  double* trr = w.take<double>(kMaxS);
+  double* tsc = w.take<double>(kMaxS);
+  GmResult r;
+  if (maxit > 0) {
+    hipError_t e = gm_run(view(A), sub, B, X, tol, maxit, restart, hist_cap, gb, h->stream, h->hflags, r);
+    if (e != hipSuccess) return hip_fail(h, e, "gmres_solve");
+  } else {
+    // no step allowed: only the initial residual norms
+    const int nblk = stream_grid(n, p, sizeof(double));
+    API_HIP(launch_spmm<double>(view(A), p, X, gb.V, B, 2, gb.partial, nblk, nullptr, nullptr, h->stream), "gmres");
+    API_HIP(launch_reduce_partials<double>(p, gb.partial, nblk, gb.Gb, nullptr, h->stream), "gmres");
+    API_HIP(launch_gm_cycle_init(gb.ctl, gb.sig, gb.Gb, gb.Gb, 1, h->stream), "gmres");
+    API_HIP(hipMemcpyAsync(h->hflags, gb.ctl, 16 * sizeof(int32_t), hipMemcpyDeviceToHost, h->stream), "gmres");
+    API_HIP(hipStreamSynchronize(h->stream), "gmres");
+    r.converged = reinterpret_cast<GmCtl*>(h->hflags)->converged;
+  }
+  double trel[kMaxS];
+  API_HIP(true_relres(view(A), p, B, X, gb.V, gb.partial, gb.Gb, gb.ctl->r0n, trr, gb.flag, tsc, h->stream), "gmres");
+  API_HIP(hipMemcpyAsync(trel, trr, sizeof(double) * p, hipMemcpyDeviceToHost, h->stream), "gmres");
+  const int hist_len = r.steps < hist_cap ? r.steps : hist_cap;
+  if (hist_len > 0)
+    API_HIP(hipMemcpyAsync(info->hist, gb.hist, sizeof(double) * hist_len, hipMemcpyDeviceToHost, h->stream), "gmres");
+  API_HIP(hipStreamSynchronize(h->stream), "gmres");
+  if (info) {
+    info->iters = r.steps;
+    info->reorth = 0;
+    info->outer_iters = r.cycles;
+    info->converged = r.converged;
+    info->hist_len = hist_len;
+    info->seconds = now_s() - t0;
+    if (info->relres) memcpy(info->relres, trel, sizeof(double) * p);
+    if (info->true_relres) memcpy(info->true_relres, trel, sizeof(double) * p);
+  }
+  if (r.bad_index) return fail(h, BKRY_E_INVALID, "a CSR column index was outside [0, n)");
+  rc = status_of(r.status, h);
+  if (rc) return rc;
+  return r.converged ? BKRY_OK : BKRY_NOT_CONVERGED;
+}
+
+int bkry_sddmm(bkry_handle h, const bkry_csr* pattern, int32_t p, double alpha, const double* L, const double* X,
+               double* out_val) {
+  int rc = begin(h);
+  if (!rc) rc = check_csr(h, pattern, false);
+  if (!rc && (p < 1 || p > kMaxS)) rc = fail(h, BKRY_E_INVALID, "p must be in [1, 32]");
+  if (!rc) rc = check_blocks(h, {L, X});
+  if (!rc && pattern->nnz > 0 && !out_val) rc = fail(h, BKRY_E_INVALID, "null out_val");
+  if (rc) return rc;
+  if (pattern->nnz == 0) return BKRY_OK;
+  API_HIP(launch_sddmm<double>(view(pattern), p, alpha, L, X, out_val, h->dflags, h->stream), "sddmm");
+  return BKRY_OK;
+}
+
+int bkry_csr_transpose(bkry_handle h, const bkry_csr* A, int32_t* rowptrT, int32_t* colindT, double* valT,
+                       int32_t* permT) {
+  int rc = begin(h);
+  if (!rc) rc = check_csr(h, A, true);
+  if (!rc && (!rowptrT || (A->nnz > 0 && (!colindT || !valT || !permT))))
+    rc = fail(h, BKRY_E_INVALID, "null output pointer");
+  if (rc) return rc;
+  rc = ensure_ws(h, csr_transpose_ws_bytes(A->n));
+  if (rc) return rc;
+  API_HIP(csr_transpose_run(A->n, A->nnz, A->rowptr, A->colind, A->val, rowptrT, colindT, valT, permT, h->ws,
+                            h->stream),
+          "csr_transpose");
+  API_HIP(hipMemcpyAsync(h->hflags, h->ws, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream), "csr_transpose");
+  API_HIP(hipStreamSynchronize(h->stream), "csr_transpose");
+  if (h->hflags[0]) return fail(h, BKRY_E_INVALID, "a CSR column index was outside [0, n)");
+  return BKRY_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,96 @@
+// common.hpp -- device helpers shared by the block Krylov kernels (gfx950).
+//
+// Lane layout used by every n x s block kernel ("row-interleaved" blocks):
+// a wavefront of 64 lanes is split into RPW row slots of LPR = S / VEC lanes;
+// lane (r, c) owns columns [c*VEC, c*VEC + VEC) of one row and moves them with
+// one VEC-wide load (16 bytes for FP64 VEC = 2 and FP32 VEC = 4), so the LPR
+// lanes of a row read or write the row's S*sizeof(T) bytes contiguously.  The
+// full row, when a lane needs it (Gram updates, block products), is gathered
+// from the row's other lanes with wavefront shuffles.  S is a power of two
+// <= 32; a runtime s <= S gives the active columns (VEC = 1 when s != S).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace bkry {
+
+constexpr int kWave = 64;
+
+template <typename T, int N>
+struct alignas(sizeof(T) * N) vec_t {
+  T v[N];
+};
+
+template <typename T, int N>
+__device__ __forceinline__ vec_t<T, N> load_vec(const T* p) {
+  return *reinterpret_cast<const vec_t<T, N>*>(p);
+}
+
+template <typename T, int N>
+__device__ __forceinline__ void store_vec(T* p, const vec_t<T, N>& x) {
+  *reinterpret_cast<vec_t<T, N>*>(p) = x;
+}
+
+template <typename T, int N>
+__device__ __forceinline__ vec_t<T, N> zero_vec() {
+  vec_t<T, N> z;
+#pragma unroll
+  for (int i = 0; i < N; ++i) z.v[i] = T(0);
+  return z;
+}
+
+// Compile-time layout of a block kernel for element type T and width S.
+template <typename T, int S_, int VEC_>
+struct Layout {
+  static constexpr int S = S_;
+  static constexpr int VEC = VEC_;
+  static constexpr int LPR = S / VEC;          // lanes per row
+  static constexpr int RPW = kWave / LPR;      // rows per wavefront
+  static_assert(S % VEC == 0 && LPR <= kWave, "bad layout");
+};
+
+// Sum over all 64 lanes; every lane receives the total.  Fixed butterfly
+// order, so the result is the same on every call.
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) v += __shfl_xor(v, d);
+  return v;
+}
+
+// Sum over the lanes that share the low log2(LPR) lane bits (the row slots
+// of one column chunk): after this, every lane holds the sum over all row
+// slots of its chunk.
+template <typename T, int LPR>
+__device__ __forceinline__ T rowslot_sum(T v) {
+#pragma unroll
+  for (int d = LPR; d < kWave; d <<= 1) v += __shfl_xor(v, d);
+  return v;
+}
+
+// Sum over the LPR lanes of one row (the column chunks of a row).
+template <typename T, int LPR>
+__device__ __forceinline__ T rowgroup_sum(T v) {
+#pragma unroll
+  for (int d = 1; d < LPR; d <<= 1) v += __shfl_xor(v, d);
+  return v;
+}
+
+// Contiguous row range of block `blk` out of `nblk`, rounded to `step` rows,
+// with the block index remapped so that consecutive row ranges stay on one
+// XCD (workgroups are dealt round-robin over the 8 XCDs; each XCD has its
+// own L2, which then sees neighbouring rows of the gathered operand).
+// The remap is a bijection of [0, nblk) only when nblk is a multiple of 8;
+// otherwise blocks keep their own index.
+__device__ __forceinline__ void block_rows(int64_t n, int blk, int nblk, int step, int64_t& r0, int64_t& r1) {
+  int logical = (nblk % 8 == 0) ? (blk % 8) * (nblk / 8) + blk / 8 : blk;
+  int64_t per = (n + nblk - 1) / nblk;
+  per = (per + step - 1) / step * step;
+  r0 = (int64_t)logical * per;
+  r1 = r0 + per;
+  if (r1 > n) r1 = n;
+  if (r0 > n) r0 = n;
+}
+
+}  // namespace bkry

@@ -1,0 +1,180 @@
+// internal.hpp -- host-side interfaces between the translation units of
+// libbkry.so (kernel launchers, device control blocks, workspace).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+namespace bkry {
+
+constexpr int kMaxS = 32;
+constexpr int kBlock = 256;  // threads per workgroup of the streaming kernels
+
+enum Kind { PARALLEL = 0, GLOBAL = 1, BLOCK = 2, HYBRID = 3 };
+
+// Subalgebra in the library's terms: group width g (block: s, hybrid: s/q,
+// parallel and global: 1) plus the kind (global differs from parallel only in
+// the projection and the normaliser).
+struct Sub {
+  int kind;
+  int s;
+  int g;
+};
+
+struct CsrView {
+  int64_t n, nnz;
+  const int32_t* rowptr;
+  const int32_t* colind;
+  const void* val;  // double or float, by the launcher's T
+};
+
+// Device control block of a block CG solve.  The integer header is read back
+// by the host to steer the loop; everything else stays on the device.
+struct CgCtl {
+  int32_t done;       // 1: the solve has ended (converged, cap, breakdown)
+  int32_t status;     // 0, or -2 breakdown, -3 non-finite
+  int32_t converged;
+  int32_t fire;       // re-orthonormalise in this iteration
+  int32_t x_pending;  // the X update of this iteration is still due
+  int32_t iters;
+  int32_t nreorth;
+  int32_t maxit;
+  int32_t s, kind, g, hist_cap;
+  int32_t bad_index;  // a CSR column index was out of range
+  int32_t pad_[3];
+  double tol, eta, sqrt_eps, pad2_;
+  double r0n[kMaxS];
+  double relres[kMaxS];
+  double alpha[kMaxS * kMaxS];
+  double rho[kMaxS * kMaxS];
+  double lam[kMaxS * kMaxS];
+  double lamsig[kMaxS * kMaxS];
+  double sigma[kMaxS * kMaxS];
+  double gamma[kMaxS * kMaxS];
+  double beta[kMaxS * kMaxS];
+  float lam_f[kMaxS * kMaxS];
+  float lamsig_f[kMaxS * kMaxS];
+  float beta_f[kMaxS * kMaxS];
+};
+constexpr int kCtlHeaderInts = 16;
+
+// Device control block of a block GMRes solve (per-cycle arrays live in
+// separate workspace buffers: H, sig, Om, zeta).
+struct GmCtl {
+  int32_t done;       // cycle finished (converged or step cap)
+  int32_t status;
+  int32_t converged;
+  int32_t kend;       // steps taken in the current cycle
+  int32_t total;      // Arnoldi steps over all cycles
+  int32_t maxit;
+  int32_t s, kind, g, m, hist_cap, bad_index;
+  int32_t pad_[4];
+  double tol, r0F, pad2_[2];
+  double r0n[kMaxS];
+};
+
+// ---------------------------------------------------------------- grids ----
+// Number of workgroups of the streaming block kernels for n rows of width s
+// (a multiple of 8 so that the XCD-contiguous row mapping is a bijection).
+int stream_grid(int64_t n, int s, int elem_bytes);
+
+// ------------------------------------------------------- block kernels ----
+// SpMM modes: 0 Y = A X; 1 also Gram partials of X^T Y (X the own rows);
+// 2 Y = B - A X and Gram partials of Y^T Y.
+template <typename T>
+hipError_t launch_spmm(const CsrView& A, int s, const T* X, T* Y, const T* B, int mode, T* partial,
+                       int nblk, int32_t* bad, const int32_t* done, hipStream_t st);
+
+// Gram partials of X^T Y (full s x s per workgroup).
+// (The optional `fire` gate: run only if *fire != 0.)
+template <typename T>
+hipError_t launch_gram(int64_t n, int s, const T* X, const T* Y, T* partial, int nblk, const int32_t* done,
+                       hipStream_t st, const int32_t* fire = nullptr);
+
+// Batched Gram partials: X_j = X + j*n*s for j < nx; partial[(j*nblk + blk)*s*s].
+template <typename T>
+hipError_t launch_gram_batched(int64_t n, int s, const T* X, int nx, const T* Y, T* partial, int nblk,
+                               const int32_t* done, hipStream_t st, const int32_t* fire = nullptr);
+// G_j = sum over blk of partial[(j*nblk + blk)*s*s] for j < batch.
+template <typename T>
+hipError_t launch_reduce_batched(int s, const T* partial, int nblk, int batch, double* G, const int32_t* gate,
+                                 hipStream_t st, const int32_t* fire = nullptr);
+
+// G = sum of nblk partials (s x s each), accumulated in FP64 in a fixed order.
+template <typename T>
+hipError_t launch_reduce_partials(int s, const T* partial, int nblk, double* G, const int32_t* gate,
+                                  hipStream_t st, const int32_t* fire = nullptr);
+
+// CG residual update R~ = R - Q lambda (in place in R) + Gram partials of R~.
+template <typename T>
+hipError_t launch_cg_update(int64_t n, int s, T* R, const T* Q, const CgCtl* ctl, T* partial, int nblk,
+                            hipStream_t st);
+
+// CG direction update X += P (lambda sigma); if not done: P = R + P beta.
+template <typename T>
+hipError_t launch_cg_pupdate(int64_t n, int s, T* X, T* P, const T* R, const CgCtl* ctl, hipStream_t st);
+
+// Y = X C (+ Y if accumulate) for a list of blocks: Y op= sum_j X_j C_j,
+// X_j = X + j*n*s, C_j s x s FP64 at C + j*s*s; sign = +1 or -1.
+template <typename T>
+hipError_t launch_block_combine(int64_t n, int s, const T* X, int nx, const double* C, double sign, T* Y,
+                                const int32_t* done, hipStream_t st);
+
+// Column scaling used by the parallel / global normalisers: Y[i][j] = X[i][j] / d[j]
+// where d[j] > 0, else e_(zero_row(j)) with zero_row = 0 (parallel) or j (global).
+template <typename T>
+hipError_t launch_colscale(int64_t n, int s, const T* X, T* Y, const double* d, int global_kind,
+                           const int32_t* gate_done, const int32_t* gate_fire, hipStream_t st);
+
+hipError_t launch_cast_scale_f32(int64_t n, int s, const double* R, const double* scale, float* out,
+                                 hipStream_t st);
+hipError_t launch_accum_scaled(int64_t n, int s, const float* D, const double* scale, double* X,
+                               hipStream_t st);
+hipError_t launch_cast_f32(int64_t count, const double* in, float* out, hipStream_t st);
+
+template <typename T>
+hipError_t launch_sddmm(const CsrView& A, int s, double alpha, const T* L, const T* X, T* out, int32_t* bad,
+                        hipStream_t st);
+
+// ----------------------------------------------------- small algebra ----
+// Single-workgroup kernels on the p x p coefficients (FP64).
+hipError_t launch_project(const double* G, double* out, Sub sub, hipStream_t st);
+hipError_t launch_cg_init(CgCtl* ctl, const double* G_R0, const double* G_rho, hipStream_t st);
+hipError_t launch_cg_alpha(CgCtl* ctl, const double* G, hipStream_t st);
+hipError_t launch_cg_rho(CgCtl* ctl, const double* G, double* hist, hipStream_t st);
+hipError_t launch_cg_reortho_fin(CgCtl* ctl, const double* G, hipStream_t st);
+// Normaliser coefficients for parallel / global: from the Gram G of X, write
+// the column divisors d and N (p x p) to `out_N` (gated like the CG kernels).
+hipError_t launch_norm_diag(const double* G, Sub sub, double* d, double* out_N, const int32_t* gate_done,
+                            const int32_t* gate_fire, hipStream_t st);
+
+// GMRes small kernels
+hipError_t launch_gm_step(GmCtl* ctl, int k, double* H, double* sig, double* Om, const double* H1, const double* H2,
+                          const double* gamma, double* hist, hipStream_t st);
+hipError_t launch_project_batched(const double* G, double* out, Sub sub, int batch, const int32_t* gate,
+                                  hipStream_t st);
+hipError_t launch_ir_check(int s, const double* G, double* r0n, double* scale, double* relres, int32_t* flag,
+                           double tol, int first, hipStream_t st);
+hipError_t launch_gm_backsub(GmCtl* ctl, const double* H, const double* sig, double* zeta, hipStream_t st);
+hipError_t launch_gm_cycle_init(GmCtl* ctl, double* sig, const double* sigma0, const double* G_R,
+                                int first_cycle, hipStream_t st);
+
+// ---------------------------------------------------------------- TSQR ----
+// Workspace (bytes) needed by tsqr_run for n rows, width s, subalgebra sub.
+size_t tsqr_workspace_bytes(int64_t n, Sub sub);
+// Normalise X (n x s, row stride s, element T) in place; N (s x s FP64,
+// device) receives the normaliser.  gate_done / gate_fire (may be null): run
+// only if *gate_done == 0 and *gate_fire != 0.
+template <typename T>
+hipError_t tsqr_run(int64_t n, Sub sub, T* X, double* N, void* ws, const int32_t* gate_done,
+                    const int32_t* gate_fire, hipStream_t st);
+
+// -------------------------------------------------------- transpose ----
+hipError_t csr_transpose_run(int64_t n, int64_t nnz, const int32_t* rowptr, const int32_t* colind,
+                             const double* val, int32_t* rowptrT, int32_t* colindT, double* valT,
+                             int32_t* permT, void* ws, hipStream_t st);
+size_t csr_transpose_ws_bytes(int64_t n);
+
+}  // namespace bkry

@@ -1,0 +1,761 @@
+// kernels_small.hip -- the p x p coefficient algebra, on the device, FP64.
+//
+// One workgroup of 256 threads works on matrices in LDS (p <= 32).  Keeping
+// this on the device lets a whole block CG iteration (or GMRes step) be
+// enqueued without a host round trip; the host reads back only a few flags.
+//
+//   cg_init / cg_alpha / cg_rho / cg_reortho_fin   the coefficient steps of
+//       the adaptive block CG (Algorithm "BCG Method with Adaptive Residual
+//       Re-Orthonormalization", Ch. 4): alpha, lambda = alpha^-1 rho,
+//       lambda sigma, the kappa_D test, the column-norm stopping test,
+//       beta = rho^-1 gamma^T rho', sigma = gamma sigma;
+//   norm_diag    normaliser of the parallel / global subalgebras;
+//   gm_*         block GMRes: generalised Givens rotations of the block
+//       Hessenberg column, the sigma update, the residual test and the block
+//       back-substitution (Algorithm "Block GMRes Method", Ch. 5);
+//   ir_check     stopping test and column scales of iterative refinement.
+//
+// Cholesky solves run on the projected (S-structured) matrices; since the
+// entries outside the subalgebra's blocks are exact zeros, the factorisation
+// of the whole p x p matrix equals one factorisation per S-block.
+#include <math.h>
+
+#include "common.hpp"
+#include "internal.hpp"
+
+namespace bkry {
+
+constexpr int kSB = 256;        // threads of the small-algebra workgroups
+constexpr int kSS = kMaxS * kMaxS;
+
+__device__ __forceinline__ int tid() { return threadIdx.x; }
+
+__device__ void sm_copy(double* dst, const double* src, int count) {
+  for (int t = tid(); t < count; t += kSB) dst[t] = src[t];
+}
+
+__device__ void sm_eye(double* M, int s) {
+  for (int t = tid(); t < s * s; t += kSB) M[t] = (t / s == t % s) ? 1.0 : 0.0;
+}
+
+// Projection onto the subalgebra (zero outside the g x g diagonal blocks;
+// global: tr/s * I).
+__device__ void sm_project(double* M, const Sub& sub, double* scratch1) {
+  const int s = sub.s;
+  __syncthreads();
+  if (sub.kind == GLOBAL) {
+    if (tid() == 0) {
+      double tr = 0.0;
+      for (int a = 0; a < s; ++a) tr += M[a * s + a];
+      scratch1[0] = tr / (double)s;
+    }
+    __syncthreads();
+    const double v = scratch1[0];
+    for (int t = tid(); t < s * s; t += kSB) M[t] = (t / s == t % s) ? v : 0.0;
+  } else {
+    for (int t = tid(); t < s * s; t += kSB)
+      if ((t / s) / sub.g != (t % s) / sub.g) M[t] = 0.0;
+  }
+  __syncthreads();
+}
+
+// C = A B (transA: C = A^T B); C must not alias A or B.
+__device__ void sm_mm(double* C, const double* A, const double* B, int s, bool transA) {
+  __syncthreads();
+  for (int t = tid(); t < s * s; t += kSB) {
+    const int i = t / s, j = t % s;
+    double acc = 0.0;
+    for (int k = 0; k < s; ++k) acc += (transA ? A[k * s + i] : A[i * s + k]) * B[k * s + j];
+    C[t] = acc;
+  }
+  __syncthreads();
+}
+
+// In-place Cholesky A = L L^T (lower triangle); false on a non-positive or
+// non-finite pivot.
+__device__ bool sm_cholesky(double* A, int s, int* flag) {
+  for (int j = 0; j < s; ++j) {
+    __syncthreads();
+    if (tid() == 0) {
+      const double d = A[j * s + j];
+      const bool ok = (d > 0.0) && isfinite(d);
+      flag[0] = ok ? 1 : 0;
+      if (ok) A[j * s + j] = sqrt(d);
+    }
+    __syncthreads();
+    if (!flag[0]) return false;
+    const double ljj = A[j * s + j];
+    for (int i = j + 1 + tid(); i < s; i += kSB) A[i * s + j] /= ljj;
+    __syncthreads();
+    const int m = s - j - 1;
+    for (int e = tid(); e < m * m; e += kSB) {
+      const int i = j + 1 + e / m, k = j + 1 + e % m;
+      if (k <= i) A[i * s + k] -= A[i * s + j] * A[k * s + j];
+    }
+  }
+  __syncthreads();
+  return true;
+}
+
+// X = L^-T L^-1 B, one thread per column of B.
+__device__ void sm_chol_solve(const double* L, const double* B, double* X, int s) {
+  __syncthreads();
+  const int col = tid();
+  if (col < s) {
+    for (int i = 0; i < s; ++i) {
+      double sum = B[i * s + col];
+      for (int k = 0; k < i; ++k) sum -= L[i * s + k] * X[k * s + col];
+      X[i * s + col] = sum / L[i * s + i];
+    }
+    for (int i = s - 1; i >= 0; --i) {
+      double sum = X[i * s + col];
+      for (int k = i + 1; k < s; ++k) sum -= L[k * s + i] * X[k * s + col];
+      X[i * s + col] = sum / L[i * s + i];
+    }
+  }
+  __syncthreads();
+}
+
+// kappa_D(A) = kappa(D^-1/2 A D^-1/2) (Definition "Diagonally scaled condition
+// number", Ch. 4) from the eigenvalues of the scaled matrix by the parallel
+// (round-robin) cyclic Jacobi method.  Infinity if a diagonal entry or the
+// smallest eigenvalue is not positive.
+__device__ double sm_kappaD(const double* A, int s, double* M, double* T, double* rc, double* rs, int* partner,
+                            int* first, double* red) {
+  const int sp = s + (s & 1);
+  __syncthreads();
+  if (tid() == 0) {
+    int bad = 0;
+    for (int i = 0; i < s; ++i) bad |= !(A[i * s + i] > 0.0);
+    red[0] = bad;
+  }
+  __syncthreads();
+  if (red[0] != 0.0) return INFINITY;
+  for (int e = tid(); e < sp * sp; e += kSB) {
+    const int i = e / sp, j = e % sp;
+    M[e] = (i < s && j < s) ? A[i * s + j] / sqrt(A[i * s + i] * A[j * s + j]) : 0.0;
+  }
+  __syncthreads();
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    if (tid() == 0) {
+      double off = 0.0, tot = 0.0;
+      for (int e = 0; e < sp * sp; ++e) {
+        const double v = M[e] * M[e];
+        tot += v;
+        if (e / sp != e % sp) off += v;
+      }
+      red[1] = (off == 0.0 || off <= 1e-30 * tot) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    if (red[1] != 0.0) break;
+    for (int round = 0; round < sp - 1; ++round) {
+      if (tid() < sp / 2) {
+        const int pa = tid(), pb = sp - 1 - tid();
+        int p = pa == 0 ? 0 : 1 + (pa - 1 + round) % (sp - 1);
+        int q = pb == 0 ? 0 : 1 + (pb - 1 + round) % (sp - 1);
+        if (p > q) {
+          int tmp = p;
+          p = q;
+          q = tmp;
+        }
+        double c = 1.0, sn = 0.0;
+        const double apq = M[p * sp + q];
+        if (q < s && apq != 0.0) {
+          const double tau = (M[q * sp + q] - M[p * sp + p]) / (2.0 * apq);
+          const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+          c = 1.0 / sqrt(1.0 + t * t);
+          sn = t * c;
+        }
+        rc[p] = c;
+        rs[p] = sn;
+        partner[p] = q;
+        first[p] = 1;
+        rc[q] = c;
+        rs[q] = sn;
+        partner[q] = p;
+        first[q] = 0;
+      }
+      __syncthreads();
+      for (int e = tid(); e < sp * sp; e += kSB) {  // T = M J
+        const int i = e / sp, j = e % sp, jp = partner[j];
+        const double c = rc[j], sn = rs[j];
+        T[e] = first[j] ? c * M[i * sp + j] - sn * M[i * sp + jp] : sn * M[i * sp + jp] + c * M[i * sp + j];
+      }
+      __syncthreads();
+      for (int e = tid(); e < sp * sp; e += kSB) {  // M = J^T T
+        const int i = e / sp, j = e % sp, ip = partner[i];
+        const double c = rc[i], sn = rs[i];
+        M[e] = first[i] ? c * T[i * sp + j] - sn * T[ip * sp + j] : sn * T[ip * sp + j] + c * T[i * sp + j];
+      }
+      __syncthreads();
+    }
+  }
+  __syncthreads();
+  if (tid() == 0) {
+    double lo = M[0], hi = M[0];
+    for (int i = 1; i < s; ++i) {
+      lo = fmin(lo, M[i * sp + i]);
+      hi = fmax(hi, M[i * sp + i]);
+    }
+    red[2] = (lo > 0.0) ? hi / lo : INFINITY;
+  }
+  __syncthreads();
+  return red[2];
+}
+
+// Re-orthonormalisation test: fire iff eta * kappa_D * sqrt(eps) > 1
+// (eta = 0 never, eta = infinity always); kappa_D equals 1 for the diagonal
+// subalgebras.
+__device__ bool reortho_test(const CgCtl* c, const double* alpha, double* M, double* T, double* rc, double* rs,
+                             int* partner, int* first, double* red) {
+  if (!(c->eta > 0.0)) return false;
+  if (isinf(c->eta)) return true;
+  double kd = 1.0;
+  if (c->g > 1) kd = sm_kappaD(alpha, c->s, M, T, rc, rs, partner, first, red);
+  return c->eta * kd * c->sqrt_eps > 1.0;
+}
+
+__device__ void store_coeff(double* d64, float* d32, const double* src, int s) {
+  for (int t = tid(); t < s * s; t += kSB) {
+    d64[t] = src[t];
+    d32[t] = (float)src[t];
+  }
+}
+
+__device__ bool all_finite(const double* M, int count, double* red) {
+  __syncthreads();
+  if (tid() == 0) {
+    int ok = 1;
+    for (int t = 0; t < count; ++t) ok &= isfinite(M[t]) ? 1 : 0;
+    red[0] = ok;
+  }
+  __syncthreads();
+  return red[0] != 0.0;
+}
+
+// ------------------------------------------------------------ projection --
+__global__ __launch_bounds__(kSB) void project_kernel(const double* G, double* out, Sub sub, const int32_t* gate) {
+  __shared__ double M[kSS];
+  __shared__ double red[4];
+  if (gate && *gate) return;
+  const int ss = sub.s * sub.s;
+  sm_copy(M, G + (int64_t)blockIdx.x * ss, ss);
+  sm_project(M, sub, red);
+  sm_copy(out + (int64_t)blockIdx.x * ss, M, ss);
+}
+
+hipError_t launch_project_batched(const double* G, double* out, Sub sub, int batch, const int32_t* gate,
+                                  hipStream_t st) {
+  if (batch <= 0) return hipSuccess;
+  hipLaunchKernelGGL(project_kernel, dim3(batch), dim3(kSB), 0, st, G, out, sub, gate);
+  return hipGetLastError();
+}
+
+hipError_t launch_project(const double* G, double* out, Sub sub, hipStream_t st) {
+  return launch_project_batched(G, out, sub, 1, nullptr, st);
+}
+
+// --------------------------------------------------------------- CG steps --
+// G_R0 (non-null): Gram of R0 = B - A X0 -> initial column norms, sigma = I
+// when no normalisation follows.  G_rho (non-null): Gram of the (normalised)
+// residual -> rho = <R, R>_S.
+__global__ __launch_bounds__(kSB) void cg_init_kernel(CgCtl* c, const double* G_R0, const double* G_rho) {
+  __shared__ double M[kSS];
+  __shared__ double red[4];
+  const int s = c->s;
+  const Sub sub{c->kind, s, c->g};
+  if (G_R0) {
+    if (tid() == 0) {
+      int allzero = 1;
+      for (int i = 0; i < s; ++i) {
+        const double nr = sqrt(G_R0[i * s + i]);
+        c->r0n[i] = nr;
+        c->relres[i] = nr > 0.0 ? 1.0 : 0.0;
+        allzero &= (nr == 0.0);
+      }
+      c->iters = 0;
+      c->status = 0;
+      c->fire = 0;
+      c->x_pending = 0;
+      c->converged = allzero;
+      c->done = allzero;
+      c->nreorth = (c->eta > 0.0 && !allzero) ? 1 : 0;
+      c->bad_index = 0;
+    }
+    if (!(c->eta > 0.0)) sm_eye(c->sigma, s);
+    for (int t = tid(); t < s * s; t += kSB) c->gamma[t] = (t / s == t % s) ? 1.0 : 0.0;
+  }
+  if (G_rho) {
+    __syncthreads();
+    if (c->done) return;
+    sm_copy(M, G_rho, s * s);
+    sm_project(M, sub, red);
+    if (!all_finite(M, s * s, red)) {
+      if (tid() == 0) {
+        c->status = -3;
+        c->done = 1;
+      }
+      return;
+    }
+    sm_copy(c->rho, M, s * s);
+  }
+}
+
+hipError_t launch_cg_init(CgCtl* ctl, const double* G_R0, const double* G_rho, hipStream_t st) {
+  hipLaunchKernelGGL(cg_init_kernel, dim3(1), dim3(kSB), 0, st, ctl, G_R0, G_rho);
+  return hipGetLastError();
+}
+
+// alpha = <P, Q>_S; lambda = alpha^-1 rho; lambda sigma; the kappa_D test.
+__global__ __launch_bounds__(kSB) void cg_alpha_kernel(CgCtl* c, const double* G) {
+  __shared__ double Al[kSS], L[kSS], Rh[kSS], Lm[kSS], W[kSS], T[kSS];
+  __shared__ double rc[kMaxS], rs[kMaxS], red[4];
+  __shared__ int partner[kMaxS], first[kMaxS], flag[1];
+  if (c->done) {
+    if (tid() == 0) c->x_pending = 0;
+    return;
+  }
+  const int s = c->s;
+  const Sub sub{c->kind, s, c->g};
+  sm_copy(Al, G, s * s);
+  sm_project(Al, sub, red);
+  bool ok = all_finite(Al, s * s, red);
+  if (!ok) {
+    if (tid() == 0) {
+      c->status = -3;
+      c->done = 1;
+      c->x_pending = 0;
+    }
+    return;
+  }
+  sm_copy(L, Al, s * s);
+  sm_copy(Rh, c->rho, s * s);
+  __syncthreads();
+  if (!sm_cholesky(L, s, flag)) {
+    if (tid() == 0) {
+      c->status = -2;
+      c->done = 1;
+      c->x_pending = 0;
+    }
+    return;
+  }
+  sm_chol_solve(L, Rh, Lm, s);          // lambda = alpha^-1 rho
+  sm_copy(W, c->sigma, s * s);
+  sm_mm(T, Lm, W, s, false);            // lambda sigma
+  store_coeff(c->lam, c->lam_f, Lm, s);
+  store_coeff(c->lamsig, c->lamsig_f, T, s);
+  sm_copy(c->alpha, Al, s * s);
+  const bool fire = reortho_test(c, Al, W, T, rc, rs, partner, first, red);
+  __syncthreads();
+  if (tid() == 0) {
+    c->fire = fire ? 1 : 0;
+    c->x_pending = 1;
+  }
+}
+
+hipError_t launch_cg_alpha(CgCtl* ctl, const double* G, hipStream_t st) {
+  hipLaunchKernelGGL(cg_alpha_kernel, dim3(1), dim3(kSB), 0, st, ctl, G);
+  return hipGetLastError();
+}
+
+// G = R~^T R~ (full).  Column norms of the true residual R~ sigma, stopping
+// test, and (no normalisation this iteration) rho' = <R~, R~>_S and
+// beta = rho^-1 rho'.
+__global__ __launch_bounds__(kSB) void cg_rho_kernel(CgCtl* c, const double* G, double* hist) {
+  __shared__ double Gm[kSS], Sg[kSS], T1[kSS], L[kSS], Bt[kSS];
+  __shared__ double red[4];
+  __shared__ int flag[2];
+  if (c->done) return;
+  const int s = c->s;
+  const Sub sub{c->kind, s, c->g};
+  sm_copy(Gm, G, s * s);
+  sm_copy(Sg, c->sigma, s * s);
+  sm_mm(T1, Gm, Sg, s, false);  // G sigma
+  if (tid() == 0) {
+    double m = 0.0;
+    bool nan = false;
+    for (int i = 0; i < s; ++i) {
+      double acc = 0.0;
+      for (int a = 0; a < s; ++a) acc += Sg[a * s + i] * T1[a * s + i];
+      const double cn = sqrt(fmax(acc, 0.0));
+      const double rel = c->r0n[i] > 0.0 ? cn / c->r0n[i] : 0.0;
+      if (!isfinite(acc)) nan = true;
+      c->relres[i] = rel;
+      m = fmax(m, rel);
+    }
+    const int it = c->iters;
+    if (hist && it < c->hist_cap) hist[it] = nan ? NAN : m;
+    c->iters = it + 1;
+    if (c->fire) c->nreorth += 1;
+    int state = 0;  // 0 continue, 1 ended
+    if (nan) {
+      c->status = -3;
+      state = 1;
+    } else if (m <= c->tol) {
+      c->converged = 1;
+      state = 1;
+    } else if (it + 1 >= c->maxit) {
+      state = 1;
+    }
+    c->done = state;
+    flag[0] = state;
+  }
+  __syncthreads();
+  if (flag[0] || c->fire) return;
+  // rho' = <R~, R~>_S, beta = rho^-1 rho' (gamma = I)
+  sm_project(Gm, sub, red);
+  sm_copy(L, c->rho, s * s);
+  __syncthreads();
+  if (!sm_cholesky(L, s, flag + 1)) {
+    if (tid() == 0) {
+      c->status = -2;
+      c->done = 1;
+    }
+    return;
+  }
+  sm_chol_solve(L, Gm, Bt, s);
+  store_coeff(c->beta, c->beta_f, Bt, s);
+  sm_copy(c->rho, Gm, s * s);
+}
+
+hipError_t launch_cg_rho(CgCtl* ctl, const double* G, double* hist, hipStream_t st) {
+  hipLaunchKernelGGL(cg_rho_kernel, dim3(1), dim3(kSB), 0, st, ctl, G, hist);
+  return hipGetLastError();
+}
+
+// After the residual was normalised, R~ = R-bar gamma: sigma = gamma sigma,
+// rho' = <R-bar, R-bar>_S (G is the Gram of R-bar), beta = rho^-1 gamma^T rho'.
+__global__ __launch_bounds__(kSB) void cg_reortho_fin_kernel(CgCtl* c, const double* G) {
+  __shared__ double Gm[kSS], Ga[kSS], Sg[kSS], T1[kSS], L[kSS], Bt[kSS];
+  __shared__ double red[4];
+  __shared__ int flag[1];
+  if (c->done || !c->fire) return;
+  const int s = c->s;
+  const Sub sub{c->kind, s, c->g};
+  sm_copy(Ga, c->gamma, s * s);
+  sm_copy(Sg, c->sigma, s * s);
+  sm_mm(T1, Ga, Sg, s, false);
+  sm_copy(c->sigma, T1, s * s);
+  sm_copy(Gm, G, s * s);
+  sm_project(Gm, sub, red);
+  sm_mm(T1, Ga, Gm, s, true);  // gamma^T rho'
+  sm_copy(L, c->rho, s * s);
+  __syncthreads();
+  if (!sm_cholesky(L, s, flag)) {
+    if (tid() == 0) {
+      c->status = -2;
+      c->done = 1;
+    }
+    return;
+  }
+  sm_chol_solve(L, T1, Bt, s);
+  store_coeff(c->beta, c->beta_f, Bt, s);
+  sm_copy(c->rho, Gm, s * s);
+}
+
+hipError_t launch_cg_reortho_fin(CgCtl* ctl, const double* G, hipStream_t st) {
+  hipLaunchKernelGGL(cg_reortho_fin_kernel, dim3(1), dim3(kSB), 0, st, ctl, G);
+  return hipGetLastError();
+}
+
+// Normaliser of the parallel (N = diag(|x_j|)) and global (N = |X|_F/sqrt(p) I)
+// subalgebras from the Gram matrix G of X.
+__global__ __launch_bounds__(kSB) void norm_diag_kernel(const double* G, Sub sub, double* d, double* N,
+                                                         const int32_t* gd, const int32_t* gf) {
+  if (gd && *gd) return;
+  if (gf && !*gf) return;
+  const int s = sub.s;
+  __shared__ double cg[1];
+  if (tid() == 0) {
+    double ss = 0.0;
+    for (int j = 0; j < s; ++j) ss += G[j * s + j];
+    cg[0] = sqrt(ss) / sqrt((double)s);
+  }
+  __syncthreads();
+  for (int t = tid(); t < s * s; t += kSB) {
+    const int i = t / s, j = t % s;
+    const double dj = sub.kind == GLOBAL ? cg[0] : sqrt(G[j * s + j]);
+    if (i == 0) d[j] = dj;
+    N[t] = (i == j) ? dj : 0.0;
+  }
+}
+
+hipError_t launch_norm_diag(const double* G, Sub sub, double* d, double* out_N, const int32_t* gate_done,
+                            const int32_t* gate_fire, hipStream_t st) {
+  hipLaunchKernelGGL(norm_diag_kernel, dim3(1), dim3(kSB), 0, st, G, sub, d, out_N, gate_done, gate_fire);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ GMRes --
+// Full QR of the rows x cols matrix M (row stride cols, rows <= 64) by
+// Householder reflections: R in the upper triangle of M, the full rows x rows
+// orthogonal Q (row stride rows) with M_in = Q [R; 0].
+__device__ void sm_house_full(double* M, int rows, int cols, double* Q, double* beta) {
+  for (int j = 0; j < cols; ++j) {
+    __syncthreads();
+    if (tid() == 0) {
+      const double x1 = M[j * cols + j];
+      double sig = 0.0;
+      for (int i = j + 1; i < rows; ++i) sig += M[i * cols + j] * M[i * cols + j];
+      if (sig == 0.0) {
+        beta[j] = 0.0;
+      } else {
+        const double mu = sqrt(x1 * x1 + sig);
+        const double v1 = (x1 <= 0.0) ? (x1 - mu) : (-sig / (x1 + mu));
+        beta[j] = 2.0 * v1 * v1 / (sig + v1 * v1);
+        for (int i = j + 1; i < rows; ++i) M[i * cols + j] /= v1;
+        M[j * cols + j] = mu;
+      }
+    }
+    __syncthreads();
+    const double b = beta[j];
+    if (b != 0.0) {
+      for (int cc = j + 1 + tid(); cc < cols; cc += kSB) {
+        double w = M[j * cols + cc];
+        for (int i = j + 1; i < rows; ++i) w += M[i * cols + j] * M[i * cols + cc];
+        M[j * cols + cc] -= b * w;
+        for (int i = j + 1; i < rows; ++i) M[i * cols + cc] -= b * M[i * cols + j] * w;
+      }
+    }
+  }
+  __syncthreads();
+  for (int t = tid(); t < rows * rows; t += kSB) Q[t] = (t / rows == t % rows) ? 1.0 : 0.0;
+  for (int j = cols - 1; j >= 0; --j) {
+    __syncthreads();
+    const double b = beta[j];
+    if (b == 0.0) continue;
+    for (int cc = tid(); cc < rows; cc += kSB) {
+      double w = Q[j * rows + cc];
+      for (int i = j + 1; i < rows; ++i) w += M[i * cols + j] * Q[i * rows + cc];
+      Q[j * rows + cc] -= b * w;
+      for (int i = j + 1; i < rows; ++i) Q[i * rows + cc] -= b * M[i * cols + j] * w;
+    }
+  }
+  __syncthreads();
+}
+
+// [x; y] <- Om^T [x; y] for S-elements x, y (s x s, row stride s), Om the
+// per-group 2g x 2g factors stored consecutively.
+__device__ void sm_apply_givens_T(const double* Om, double* x, double* y, int s, int g, double* tmp) {
+  const int ngrp = s / g, m2 = 2 * g;
+  __syncthreads();
+  for (int e = tid(); e < ngrp * m2 * g; e += kSB) {
+    const int grp = e / (m2 * g), rem = e % (m2 * g), i = rem / g, cc = rem % g;
+    const double* O = Om + (int64_t)grp * m2 * m2;
+    const int o = grp * g;
+    double acc = 0.0;
+    for (int k = 0; k < m2; ++k) {
+      const double col = k < g ? x[(o + k) * s + o + cc] : y[(o + k - g) * s + o + cc];
+      acc += O[k * m2 + i] * col;
+    }
+    tmp[e] = acc;
+  }
+  __syncthreads();
+  for (int e = tid(); e < ngrp * m2 * g; e += kSB) {
+    const int grp = e / (m2 * g), rem = e % (m2 * g), i = rem / g, cc = rem % g;
+    const int o = grp * g;
+    if (i < g)
+      x[(o + i) * s + o + cc] = tmp[e];
+    else
+      y[(o + i - g) * s + o + cc] = tmp[e];
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(kSB) void gm_cycle_init_kernel(GmCtl* c, double* sig, const double* sigma0,
+                                                             const double* G_R, int first) {
+  const int s = c->s, m = c->m, ss = s * s;
+  if (first && tid() == 0) {
+    double f = 0.0;
+    for (int i = 0; i < s; ++i) {
+      c->r0n[i] = sqrt(G_R[i * s + i]);
+      f += G_R[i * s + i];
+    }
+    c->r0F = sqrt(f);
+    c->total = 0;
+    c->status = 0;
+    c->converged = (f == 0.0);
+    c->bad_index = 0;
+  }
+  __syncthreads();
+  for (int t = tid(); t < (m + 1) * ss; t += kSB) sig[t] = t < ss ? sigma0[t] : 0.0;
+  if (tid() == 0) {
+    c->kend = 0;
+    c->done = c->converged;
+  }
+}
+
+hipError_t launch_gm_cycle_init(GmCtl* ctl, double* sig, const double* sigma0, const double* G_R, int first,
+                                hipStream_t st) {
+  hipLaunchKernelGGL(gm_cycle_init_kernel, dim3(1), dim3(kSB), 0, st, ctl, sig, sigma0, G_R, first);
+  return hipGetLastError();
+}
+
+// Step k of a cycle: the new Hessenberg column h_jk = H1_j + H2_j (the two
+// Gram-Schmidt passes) for j <= k and gamma = h_{k+1,k}.
+__global__ __launch_bounds__(kSB) void gm_step_kernel(GmCtl* c, int k, double* H, double* sig, double* Om,
+                                                       const double* H1, const double* H2, const double* gamma,
+                                                       double* hist) {
+  __shared__ double Qf[4 * kMaxS * kMaxS], tmp[2 * kMaxS * kMaxS], gm[kSS];
+  __shared__ double beta[kMaxS];
+  double* M = tmp;  // the Householder input is not live while rotations use tmp
+  if (c->done) return;
+  const int s = c->s, g = c->g, m = c->m, ss = s * s, ngrp = s / g, m2 = 2 * g;
+  for (int t = tid(); t < (k + 1) * ss; t += kSB) {
+    const int j = t / ss, e = t % ss;
+    H[((int64_t)j * m + k) * ss + e] = H1[t] + H2[t];
+  }
+  sm_copy(gm, gamma, ss);
+  __syncthreads();
+  for (int j = 0; j < k; ++j)
+    sm_apply_givens_T(Om + (int64_t)j * ngrp * m2 * m2, H + ((int64_t)j * m + k) * ss,
+                      H + ((int64_t)(j + 1) * m + k) * ss, s, g, tmp);
+  double* hkk = H + ((int64_t)k * m + k) * ss;
+  double* Omk = Om + (int64_t)k * ngrp * m2 * m2;
+  if (g == 1) {
+    // 2 x 1 Householder per column
+    for (int grp = tid(); grp < ngrp; grp += kSB) {
+      const double x1 = hkk[grp * s + grp], x2 = gm[grp * s + grp];
+      const double sg = x2 * x2;
+      double* O = Omk + grp * 4;
+      if (sg == 0.0) {
+        O[0] = 1.0; O[1] = 0.0; O[2] = 0.0; O[3] = 1.0;
+      } else {
+        const double mu = sqrt(x1 * x1 + sg);
+        const double v1 = (x1 <= 0.0) ? (x1 - mu) : (-sg / (x1 + mu));
+        const double b = 2.0 * v1 * v1 / (sg + v1 * v1);
+        const double v2 = x2 / v1;
+        O[0] = 1.0 - b; O[1] = -b * v2; O[2] = -b * v2; O[3] = 1.0 - b * v2 * v2;
+        hkk[grp * s + grp] = mu;
+      }
+    }
+  } else {
+    for (int grp = 0; grp < ngrp; ++grp) {
+      const int o = grp * g;
+      __syncthreads();
+      for (int t = tid(); t < m2 * g; t += kSB) {
+        const int i = t / g, cc = t % g;
+        M[t] = i < g ? hkk[(o + i) * s + o + cc] : gm[(o + i - g) * s + o + cc];
+      }
+      sm_house_full(M, m2, g, Qf, beta);
+      for (int t = tid(); t < m2 * m2; t += kSB) Omk[grp * m2 * m2 + t] = Qf[t];
+      for (int t = tid(); t < g * g; t += kSB) {
+        const int i = t / g, cc = t % g;
+        hkk[(o + i) * s + o + cc] = cc >= i ? M[i * g + cc] : 0.0;
+      }
+    }
+  }
+  __syncthreads();
+  sm_apply_givens_T(Omk, sig + (int64_t)k * ss, sig + (int64_t)(k + 1) * ss, s, g, tmp);
+  if (tid() == 0) {
+    const double* sk = sig + (int64_t)(k + 1) * ss;
+    double meas = 0.0;
+    bool nan = false;
+    if (c->kind == GLOBAL) {
+      double f = 0.0;
+      for (int t = 0; t < ss; ++t) f += sk[t] * sk[t];
+      meas = sqrt(f) / c->r0F;
+      nan = !isfinite(f);
+    } else {
+      for (int i = 0; i < s; ++i) {
+        double acc = 0.0;
+        for (int a = 0; a < s; ++a) acc += sk[a * s + i] * sk[a * s + i];
+        nan |= !isfinite(acc);
+        const double rel = c->r0n[i] > 0.0 ? sqrt(acc) / c->r0n[i] : 0.0;
+        meas = fmax(meas, rel);
+      }
+    }
+    const int tot = c->total;
+    if (hist && tot < c->hist_cap) hist[tot] = nan ? NAN : meas;
+    c->total = tot + 1;
+    c->kend = k + 1;
+    if (nan) {
+      c->status = -3;
+      c->done = 1;
+    } else if (meas <= c->tol) {
+      c->converged = 1;
+      c->done = 1;
+    } else if (tot + 1 >= c->maxit) {
+      c->done = 1;
+    }
+  }
+}
+
+hipError_t launch_gm_step(GmCtl* ctl, int k, double* H, double* sig, double* Om, const double* H1, const double* H2,
+                          const double* gamma, double* hist, hipStream_t st) {
+  hipLaunchKernelGGL(gm_step_kernel, dim3(1), dim3(kSB), 0, st, ctl, k, H, sig, Om, H1, H2, gamma, hist);
+  return hipGetLastError();
+}
+
+// zeta_l = R_ll^-1 (sigma_l - sum_{j>l} H_lj zeta_j), l = kend-1 .. 0; a zero
+// pivot gives a zero component.
+__global__ __launch_bounds__(kSB) void gm_backsub_kernel(GmCtl* c, const double* H, const double* sig,
+                                                          double* zeta) {
+  __shared__ double tmp[kSS];
+  const int s = c->s, g = c->g, m = c->m, ss = s * s, kend = c->kend;
+  for (int l = kend - 1; l >= 0; --l) {
+    __syncthreads();
+    for (int t = tid(); t < ss; t += kSB) {
+      const int a = t / s, b = t % s;
+      double acc = sig[(int64_t)l * ss + t];
+      for (int j = l + 1; j < kend; ++j) {
+        const double* hl = H + ((int64_t)l * m + j) * ss;
+        const double* zj = zeta + (int64_t)j * ss;
+        double d = 0.0;
+        for (int cc = 0; cc < s; ++cc) d += hl[a * s + cc] * zj[cc * s + b];
+        acc -= d;
+      }
+      tmp[t] = acc;
+    }
+    __syncthreads();
+    const double* T = H + ((int64_t)l * m + l) * ss;
+    double* z = zeta + (int64_t)l * ss;
+    for (int t = tid(); t < ss; t += kSB) z[t] = 0.0;
+    __syncthreads();
+    for (int e = tid(); e < s; e += kSB) {  // thread per (group, column): e = o + b
+      const int grp = e / g, b = e % g, o = grp * g;
+      for (int a = g - 1; a >= 0; --a) {
+        double acc = tmp[(o + a) * s + o + b];
+        for (int cc = a + 1; cc < g; ++cc) acc -= T[(o + a) * s + o + cc] * z[(o + cc) * s + o + b];
+        const double piv = T[(o + a) * s + o + a];
+        z[(o + a) * s + o + b] = piv != 0.0 ? acc / piv : 0.0;
+      }
+    }
+  }
+}
+
+hipError_t launch_gm_backsub(GmCtl* ctl, const double* H, const double* sig, double* zeta, hipStream_t st) {
+  hipLaunchKernelGGL(gm_backsub_kernel, dim3(1), dim3(kSB), 0, st, ctl, H, sig, zeta);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------- iterative refinement --
+// From the Gram G of the FP64 residual: column norms -> scale, relative
+// residuals (r0n is set on the first call), flag[0] = converged,
+// flag[1] = non-finite.
+__global__ __launch_bounds__(kSB) void ir_check_kernel(int s, const double* G, double* r0n, double* scale,
+                                                        double* relres, int32_t* flag, double tol, int first) {
+  if (tid() != 0) return;
+  double m = 0.0;
+  int nan = 0;
+  for (int i = 0; i < s; ++i) {
+    const double g = G[i * s + i];
+    nan |= !isfinite(g);
+    const double cn = sqrt(fmax(g, 0.0));
+    if (first) r0n[i] = cn;
+    scale[i] = cn;
+    const double rel = r0n[i] > 0.0 ? cn / r0n[i] : 0.0;
+    relres[i] = rel;
+    m = fmax(m, rel);
+  }
+  flag[0] = (m <= tol) ? 1 : 0;
+  flag[1] = nan;
+}
+
+hipError_t launch_ir_check(int s, const double* G, double* r0n, double* scale, double* relres, int32_t* flag,
+                           double tol, int first, hipStream_t st) {
+  hipLaunchKernelGGL(ir_check_kernel, dim3(1), dim3(kSB), 0, st, s, G, r0n, scale, relres, flag, tol, first);
+  return hipGetLastError();
+}
+
+}  // namespace bkry

@@ -1,0 +1,283 @@
+// solvers.hip -- host drivers of the block solvers.  Every arithmetic step
+// runs in the kernels; the host enqueues them on one stream and reads back
+// only the few integers of a control block (once per batch of iterations for
+// CG, once per cycle for GMRes, once per refinement step for IR).
+#include <float.h>
+#include <math.h>
+#include <stddef.h>
+#include <string.h>
+
+#include "solvers.hpp"
+
+namespace bkry {
+
+#define BK_TRY(x)                       \
+  do {                                  \
+    hipError_t e_ = (x);                \
+    if (e_ != hipSuccess) return e_;    \
+  } while (0)
+
+// ---------------------------------------------------------------- block CG --
+template <typename T>
+CgBufs<T> carve_cg(Carver& c, int64_t n, Sub sub, int hist_cap) {
+  const int s = sub.s;
+  CgBufs<T> b;
+  b.P = c.take<T>((size_t)n * s);
+  b.Q = c.take<T>((size_t)n * s);
+  b.R = c.take<T>((size_t)n * s);
+  b.partial = c.take<T>((size_t)stream_grid(n, s, sizeof(T)) * s * s);
+  b.Ga = c.take<double>((size_t)s * s);
+  b.Gr = c.take<double>((size_t)s * s);
+  b.Gq = c.take<double>((size_t)s * s);
+  b.hist = c.take<double>((size_t)(hist_cap > 0 ? hist_cap : 1));
+  b.ctl = c.take<CgCtl>(1);
+  b.tsqr_ws = c.take<char>(tsqr_workspace_bytes(n, sub));
+  return b;
+}
+
+template <typename T>
+hipError_t cg_run(const CsrView& A, Sub sub, const T* B, T* X, double tol, int maxit, double eta, double eps,
+                  int hist_cap, const CgBufs<T>& b, hipStream_t st, int32_t* hflags, CgResult& res) {
+  const int64_t n = A.n;
+  const int s = sub.s;
+  const int nblk = stream_grid(n, s, sizeof(T));
+  CgCtl* c = b.ctl;
+  int32_t* done = &c->done;
+
+  // control header, staged through pinned memory
+  CgCtl* h = reinterpret_cast<CgCtl*>(hflags + 64);
+  static_assert(offsetof(CgCtl, r0n) <= 256 * sizeof(int32_t) - 64 * sizeof(int32_t), "header too large");
+  memset(h, 0, offsetof(CgCtl, r0n));
+  h->maxit = maxit;
+  h->s = s;
+  h->kind = sub.kind;
+  h->g = sub.g;
+  h->hist_cap = hist_cap;
+  h->tol = tol;
+  h->eta = eta;
+  h->sqrt_eps = sqrt(eps);
+  BK_TRY(hipMemcpyAsync(c, h, offsetof(CgCtl, r0n), hipMemcpyHostToDevice, st));
+
+  // R0 = B - A X0 with its Gram matrix; initial normalisation; P = R; rho.
+  BK_TRY(launch_spmm<T>(A, s, X, b.R, B, 2, b.partial, nblk, &c->bad_index, nullptr, st));
+  BK_TRY(launch_reduce_partials<T>(s, b.partial, nblk, b.Ga, nullptr, st));
+  BK_TRY(launch_cg_init(c, b.Ga, nullptr, st));
+  if (eta > 0.0) BK_TRY(tsqr_run<T>(n, sub, b.R, c->sigma, b.tsqr_ws, done, nullptr, st));
+  BK_TRY(launch_gram<T>(n, s, b.R, b.R, b.partial, nblk, done, st));
+  BK_TRY(launch_reduce_partials<T>(s, b.partial, nblk, b.Gr, done, st));
+  BK_TRY(launch_cg_init(c, nullptr, b.Gr, st));
+  BK_TRY(hipMemcpyAsync(b.P, b.R, sizeof(T) * (size_t)n * s, hipMemcpyDeviceToDevice, st));
+
+  // Whether the residual can be re-normalised: never for eta = 0; for the
+  // diagonal subalgebras kappa_D = 1, so the test is decided in advance.
+  bool may_fire = eta > 0.0;
+  if (may_fire && sub.g == 1 && !isinf(eta)) may_fire = eta * sqrt(eps) > 1.0;
+
+  int launched = 0, batch = 4;
+  while (maxit > 0) {
+    for (int it = 0; it < batch; ++it) {
+      BK_TRY(launch_spmm<T>(A, s, b.P, b.Q, nullptr, 1, b.partial, nblk, &c->bad_index, done, st));
+      BK_TRY(launch_reduce_partials<T>(s, b.partial, nblk, b.Ga, done, st));
+      BK_TRY(launch_cg_alpha(c, b.Ga, st));
+      BK_TRY(launch_cg_update<T>(n, s, b.R, b.Q, c, b.partial, nblk, st));
+      BK_TRY(launch_reduce_partials<T>(s, b.partial, nblk, b.Gr, done, st));
+      BK_TRY(launch_cg_rho(c, b.Gr, b.hist, st));
+      if (may_fire) {
+        BK_TRY(tsqr_run<T>(n, sub, b.R, c->gamma, b.tsqr_ws, done, &c->fire, st));
+        BK_TRY(launch_gram<T>(n, s, b.R, b.R, b.partial, nblk, done, st, &c->fire));
+        BK_TRY(launch_reduce_partials<T>(s, b.partial, nblk, b.Gq, done, st, &c->fire));
+        BK_TRY(launch_cg_reortho_fin(c, b.Gq, st));
+      }
+      BK_TRY(launch_cg_pupdate<T>(n, s, X, b.P, b.R, c, st));
+    }
+    launched += batch;
+    BK_TRY(hipMemcpyAsync(hflags, c, kCtlHeaderInts * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    BK_TRY(hipStreamSynchronize(st));
+    if (hflags[0] || launched >= maxit) break;
+    if (batch < 16) batch *= 2;
+  }
+  if (maxit <= 0) {
+    BK_TRY(hipMemcpyAsync(hflags, c, kCtlHeaderInts * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    BK_TRY(hipStreamSynchronize(st));
+  }
+  const CgCtl* hc = reinterpret_cast<const CgCtl*>(hflags);
+  res.status = hc->status;
+  res.iters = hc->iters;
+  res.nreorth = hc->nreorth;
+  res.converged = hc->converged;
+  res.bad_index = hc->bad_index;
+  return hipSuccess;
+}
+
+template CgBufs<double> carve_cg<double>(Carver&, int64_t, Sub, int);
+template CgBufs<float> carve_cg<float>(Carver&, int64_t, Sub, int);
+template hipError_t cg_run<double>(const CsrView&, Sub, const double*, double*, double, int, double, double, int,
+                                   const CgBufs<double>&, hipStream_t, int32_t*, CgResult&);
+template hipError_t cg_run<float>(const CsrView&, Sub, const float*, float*, double, int, double, double, int,
+                                  const CgBufs<float>&, hipStream_t, int32_t*, CgResult&);
+
+// ------------------------------------------------------ true residuals --
+hipError_t true_relres(const CsrView& A, int s, const double* B, const double* X, double* R, double* partial,
+                       double* G, const double* r0n, double* relres, int32_t* flag, double* scale_scratch,
+                       hipStream_t st) {
+  const int nblk = stream_grid(A.n, s, sizeof(double));
+  BK_TRY(launch_spmm<double>(A, s, X, R, B, 2, partial, nblk, nullptr, nullptr, st));
+  BK_TRY(launch_reduce_partials<double>(s, partial, nblk, G, nullptr, st));
+  return launch_ir_check(s, G, const_cast<double*>(r0n), scale_scratch, relres, flag, 0.0, 0, st);
+}
+
+// ------------------------------------------------ iterative refinement --
+IrBufs carve_ir(Carver& c, int64_t n, int64_t nnz, Sub sub) {
+  const int s = sub.s;
+  IrBufs b;
+  b.A32 = c.take<float>((size_t)(nnz > 0 ? nnz : 1));
+  b.R32 = c.take<float>((size_t)n * s);
+  b.X32 = c.take<float>((size_t)n * s);
+  b.R64 = c.take<double>((size_t)n * s);
+  b.partial = c.take<double>((size_t)stream_grid(n, s, sizeof(double)) * s * s);
+  b.G = c.take<double>((size_t)s * s);
+  b.r0n = c.take<double>(kMaxS);
+  b.scale = c.take<double>(kMaxS);
+  b.relres = c.take<double>(kMaxS);
+  b.flag = c.take<int32_t>(4);
+  b.cg = carve_cg<float>(c, n, sub, 0);
+  return b;
+}
+
+// Mixed precision: the FP64 residual R = B - A X is scaled column-wise to unit
+// norm, rounded to FP32, and an FP32 block CG solves A D = R/|R| to the inner
+// tolerance; X += D |R| in FP64; repeat until the FP64 residual meets tol.
+hipError_t ir_run(const CsrView& A, Sub sub, const double* B, double* X, double tol, int maxit, double eta,
+                  double inner_tol, int max_outer, double* hist_host, int hist_cap, const IrBufs& b, hipStream_t st,
+                  int32_t* hflags, double* relres_host, IrResult& res) {
+  const int64_t n = A.n;
+  const int s = sub.s;
+  const int nblk = stream_grid(n, s, sizeof(double));
+  BK_TRY(launch_cast_f32(A.nnz, static_cast<const double*>(A.val), b.A32, st));
+  CsrView A32 = A;
+  A32.val = b.A32;
+  int32_t* dflag = b.flag;
+  BK_TRY(hipMemsetAsync(dflag, 0, 4 * sizeof(int32_t), st));
+  for (int outer = 0;; ++outer) {
+    BK_TRY(launch_spmm<double>(A, s, X, b.R64, B, 2, b.partial, nblk, dflag + 2, nullptr, st));
+    BK_TRY(launch_reduce_partials<double>(s, b.partial, nblk, b.G, nullptr, st));
+    BK_TRY(launch_ir_check(s, b.G, b.r0n, b.scale, b.relres, dflag, tol, outer == 0, st));
+    BK_TRY(hipMemcpyAsync(hflags, dflag, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    BK_TRY(hipMemcpyAsync(relres_host, b.relres, s * sizeof(double), hipMemcpyDeviceToHost, st));
+    BK_TRY(hipStreamSynchronize(st));
+    double m = 0.0;
+    for (int i = 0; i < s; ++i) m = fmax(m, relres_host[i]);
+    if (outer > 0 && res.hist_len < hist_cap && hist_host) hist_host[res.hist_len++] = m;
+    res.outer = outer;
+    res.bad_index = hflags[2];
+    if (hflags[2]) return hipSuccess;
+    if (hflags[1]) {
+      res.status = -3;
+      return hipSuccess;
+    }
+    if (hflags[0]) {
+      res.converged = 1;
+      return hipSuccess;
+    }
+    if (outer >= max_outer) return hipSuccess;
+    BK_TRY(launch_cast_scale_f32(n, s, b.R64, b.scale, b.R32, st));
+    BK_TRY(hipMemsetAsync(b.X32, 0, sizeof(float) * (size_t)n * s, st));
+    CgResult r;
+    BK_TRY(cg_run<float>(A32, sub, b.R32, b.X32, inner_tol, maxit, eta, (double)FLT_EPSILON, 0, b.cg, st, hflags, r));
+    res.inner_iters += r.iters;
+    res.nreorth += r.nreorth;
+    if (r.bad_index) {
+      res.bad_index = 1;
+      return hipSuccess;
+    }
+    if (r.status != 0 && r.iters <= 1) {
+      res.status = r.status;
+      return hipSuccess;
+    }
+    BK_TRY(launch_accum_scaled(n, s, b.X32, b.scale, X, st));
+  }
+}
+
+// ------------------------------------------------------------ block GMRes --
+GmBufs carve_gm(Carver& c, int64_t n, Sub sub, int m, int hist_cap) {
+  const int s = sub.s, ss = s * s;
+  const int nblk = stream_grid(n, s, sizeof(double));
+  GmBufs b;
+  b.V = c.take<double>((size_t)(m + 1) * n * s);
+  b.partial = c.take<double>((size_t)(m + 1) * nblk * ss);
+  b.Gb = c.take<double>((size_t)(m + 1) * ss);
+  b.H1 = c.take<double>((size_t)(m + 1) * ss);
+  b.H2 = c.take<double>((size_t)(m + 1) * ss);
+  b.H = c.take<double>((size_t)(m + 1) * m * ss);
+  b.sig = c.take<double>((size_t)(m + 1) * ss);
+  b.Om = c.take<double>((size_t)m * 4 * ss);
+  b.zeta = c.take<double>((size_t)m * ss);
+  b.sigma0 = c.take<double>((size_t)ss);
+  b.gam = c.take<double>((size_t)ss);
+  b.hist = c.take<double>((size_t)(hist_cap > 0 ? hist_cap : 1));
+  b.relres = c.take<double>(kMaxS);
+  b.flag = c.take<int32_t>(4);
+  b.ctl = c.take<GmCtl>(1);
+  b.tsqr_ws = c.take<char>(tsqr_workspace_bytes(n, sub));
+  return b;
+}
+
+hipError_t gm_run(const CsrView& A, Sub sub, const double* B, double* X, double tol, int maxit, int m,
+                  int hist_cap, const GmBufs& b, hipStream_t st, int32_t* hflags, GmResult& res) {
+  const int64_t n = A.n;
+  const int s = sub.s;
+  const size_t blk = (size_t)n * s;
+  const int nblk = stream_grid(n, s, sizeof(double));
+  GmCtl* c = b.ctl;
+  int32_t* done = &c->done;
+  GmCtl* h = reinterpret_cast<GmCtl*>(hflags + 64);
+  memset(h, 0, sizeof(GmCtl));
+  h->maxit = maxit;
+  h->s = s;
+  h->kind = sub.kind;
+  h->g = sub.g;
+  h->m = m;
+  h->hist_cap = hist_cap;
+  h->tol = tol;
+  BK_TRY(hipMemcpyAsync(c, h, sizeof(GmCtl), hipMemcpyHostToDevice, st));
+  for (int cycle = 0;; ++cycle) {
+    // R = B - A X into V_0, its Gram; V_0 sigma_0 = Norm_S(R)
+    BK_TRY(launch_spmm<double>(A, s, X, b.V, B, 2, b.partial, nblk, &c->bad_index, nullptr, st));
+    BK_TRY(launch_reduce_partials<double>(s, b.partial, nblk, b.Gb, nullptr, st));
+    BK_TRY(tsqr_run<double>(n, sub, b.V, b.sigma0, b.tsqr_ws, nullptr, nullptr, st));
+    BK_TRY(launch_gm_cycle_init(c, b.sig, b.sigma0, b.Gb, cycle == 0, st));
+    for (int k = 0; k < m; ++k) {
+      double* Vk = b.V + (size_t)k * blk;
+      double* W = b.V + (size_t)(k + 1) * blk;
+      BK_TRY(launch_spmm<double>(A, s, Vk, W, nullptr, 0, nullptr, nblk, &c->bad_index, done, st));
+      // classical Gram-Schmidt, twice: H_j = <V_j, W>_S, W -= sum_j V_j H_j
+      double* Hp[2] = {b.H1, b.H2};
+      for (int pass = 0; pass < 2; ++pass) {
+        BK_TRY(launch_gram_batched<double>(n, s, b.V, k + 1, W, b.partial, nblk, done, st));
+        BK_TRY(launch_reduce_batched<double>(s, b.partial, nblk, k + 1, b.Gb, done, st));
+        BK_TRY(launch_project_batched(b.Gb, Hp[pass], sub, k + 1, done, st));
+        BK_TRY(launch_block_combine<double>(n, s, b.V, k + 1, Hp[pass], -1.0, W, done, st));
+      }
+      BK_TRY(tsqr_run<double>(n, sub, W, b.gam, b.tsqr_ws, done, nullptr, st));
+      BK_TRY(launch_gm_step(c, k, b.H, b.sig, b.Om, b.H1, b.H2, b.gam, b.hist, st));
+    }
+    BK_TRY(hipMemcpyAsync(hflags, c, 16 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    BK_TRY(hipStreamSynchronize(st));
+    const GmCtl* hc = reinterpret_cast<const GmCtl*>(hflags);
+    const int kend = hc->kend;
+    res.status = hc->status;
+    res.converged = hc->converged;
+    res.steps = hc->total;
+    res.cycles = cycle + (kend > 0 ? 1 : 0);
+    res.bad_index = hc->bad_index;
+    if (res.bad_index || res.status) return hipSuccess;
+    if (kend > 0) {
+      BK_TRY(launch_gm_backsub(c, b.H, b.sig, b.zeta, st));
+      BK_TRY(launch_block_combine<double>(n, s, b.V, kend, b.zeta, 1.0, X, nullptr, st));
+    }
+    if (res.converged || res.steps >= maxit || kend == 0) break;
+  }
+  return hipSuccess;
+}
+
+}  // namespace bkry

@@ -1,0 +1,85 @@
+// solvers.hpp -- workspace layout and drivers of the block solvers.
+#pragma once
+
+#include <stddef.h>
+
+#include "internal.hpp"
+
+namespace bkry {
+
+// Carves 256-byte aligned buffers out of one workspace; with base == nullptr
+// it only counts the bytes.
+struct Carver {
+  char* base = nullptr;
+  size_t off = 0;
+  template <typename T>
+  T* take(size_t count) {
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += (count * sizeof(T) + 255) / 256 * 256;
+    return p;
+  }
+};
+
+// Pinned host staging area shared by the drivers: [0, 64) ints for read-backs,
+// [64, 128) ints (256 bytes) for uploads.
+constexpr int kHostFlagsInts = 256;
+
+template <typename T>
+struct CgBufs {
+  T *P = nullptr, *Q = nullptr, *R = nullptr, *partial = nullptr;
+  double *Ga = nullptr, *Gr = nullptr, *Gq = nullptr, *hist = nullptr;
+  CgCtl* ctl = nullptr;
+  void* tsqr_ws = nullptr;
+};
+
+template <typename T>
+CgBufs<T> carve_cg(Carver& c, int64_t n, Sub sub, int hist_cap);
+
+struct CgResult {
+  int status = 0;  // 0, -2 breakdown, -3 non-finite
+  int iters = 0, nreorth = 0, converged = 0, bad_index = 0;
+};
+
+// Block CG in element type T (FP64 or FP32 streaming kernels; p x p algebra in
+// FP64).  X holds X0 on entry.  eps is the machine epsilon of T.
+template <typename T>
+hipError_t cg_run(const CsrView& A, Sub sub, const T* B, T* X, double tol, int maxit, double eta, double eps,
+                  int hist_cap, const CgBufs<T>& b, hipStream_t st, int32_t* hflags, CgResult& res);
+
+struct IrBufs {
+  float *A32 = nullptr, *R32 = nullptr, *X32 = nullptr;
+  double *R64 = nullptr, *partial = nullptr, *G = nullptr, *r0n = nullptr, *scale = nullptr, *relres = nullptr;
+  int32_t* flag = nullptr;
+  CgBufs<float> cg;
+};
+IrBufs carve_ir(Carver& c, int64_t n, int64_t nnz, Sub sub);
+
+struct IrResult {
+  int status = 0, converged = 0, outer = 0, inner_iters = 0, nreorth = 0, bad_index = 0, hist_len = 0;
+};
+hipError_t ir_run(const CsrView& A, Sub sub, const double* B, double* X, double tol, int maxit, double eta,
+                  double inner_tol, int max_outer, double* hist_host, int hist_cap, const IrBufs& b, hipStream_t st,
+                  int32_t* hflags, double* relres_host, IrResult& res);
+
+struct GmBufs {
+  double *V = nullptr, *partial = nullptr, *Gb = nullptr, *H1 = nullptr, *H2 = nullptr, *H = nullptr, *sig = nullptr;
+  double *Om = nullptr, *zeta = nullptr, *sigma0 = nullptr, *gam = nullptr, *hist = nullptr, *relres = nullptr;
+  int32_t* flag = nullptr;
+  GmCtl* ctl = nullptr;
+  void* tsqr_ws = nullptr;
+};
+GmBufs carve_gm(Carver& c, int64_t n, Sub sub, int m, int hist_cap);
+
+struct GmResult {
+  int status = 0, converged = 0, steps = 0, cycles = 0, bad_index = 0;
+};
+hipError_t gm_run(const CsrView& A, Sub sub, const double* B, double* X, double tol, int maxit, int m,
+                  int hist_cap, const GmBufs& b, hipStream_t st, int32_t* hflags, GmResult& res);
+
+// True relative column residuals |B_i - A X_i| / r0n_i (FP64) into relres
+// (device); uses R (n x s) and partial as scratch.
+hipError_t true_relres(const CsrView& A, int s, const double* B, const double* X, double* R, double* partial,
+                       double* G, const double* r0n, double* relres, int32_t* flag, double* scale_scratch,
+                       hipStream_t st);
+
+}  // namespace bkry
