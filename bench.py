@@ -1,0 +1,328 @@
+#!/usr/bin/env python3
+"""Benchmark of the block Krylov hot path on one MI355X.
+
+Workload (the headline): 3D 7-point Laplacian on a 128^3 grid (n = 2,097,152,
+nnz = 14,581,760), p = 8 right-hand sides uniform in [-1, 1] (seed 1002),
+block CG over the block subalgebra with adaptive re-orthonormalisation
+(eta = 1e4), X0 = 0, relative residual tolerance 1e-10 per column.
+
+One step = one complete solve to 1e-10 (time-to-tolerance).  The reported
+value is block-CG iterations per second over the K timed solves; the solve
+time is ms_per_step.  Inputs are resident in HBM before timing starts.
+
+roofline: the dominant kernel is the SpMM fused with the alpha Gram partials;
+its average duration comes from HIP events the library records around every
+launch on the solve's stream during the timed region (bkry_profile).
+Algorithmic bytes per launch = rowptr + colind + values + X read + Y write.
+
+cpu_baseline: the oracle (plain C, one thread) on a bounded sample of the
+same solve (a fixed number of block iterations), as iterations per second.
+
+extras: the other hot-path rows measured on their own workloads (hybrid
+subalgebra, BDOT, block GMRes(30) cycle with TSQR, standalone TSQR
+4,194,304 x 32, FP32-inner iterative refinement, adjoint solve).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+PEAK_FP64_TFLOPS = 78.6
+METRIC = "block-CG iters/s + SpMM/BDOT HBM GB/s (p=8, 128³ Laplacian); time-to-1e-10"
+PMC_FILE = os.path.join(ROOT, "profiles", "spmm_laplace3d_128_s8_pmc.txt")
+KERNEL_SRC = os.path.join(ROOT, "paper_2104_02494_amd", "csrc", "kernels_block.hip")
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def kernel_hash():
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def pmc_traffic():
+    """HBM bytes per launch of the fused SpMM from the committed rocprofv3
+    counter summary, or None if absent or taken on a different kernel source."""
+    if not os.path.exists(PMC_FILE):
+        return None
+    vals = {}
+    for line in open(PMC_FILE):
+        if "=" in line and not line.startswith("#"):
+            k, v = line.split("=", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256_16") != kernel_hash():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def spmm_bytes(A, s, elem=8):
+    return (A.n + 1) * 4 + A.nnz * 4 + A.nnz * elem + 2 * A.n * s * elem
+
+
+def cpu_baseline(A, B, iters_a=1, iters_b=4):
+    """Oracle block CG on the same workload; the per-iteration time is the
+    difference of two bounded runs, so set-up is excluded."""
+    import oracle
+    t0 = time.perf_counter()
+    oracle.bcg(A, B, kind="block", tol=0.0, maxit=iters_a, eta=1e4)
+    t1 = time.perf_counter()
+    oracle.bcg(A, B, kind="block", tol=0.0, maxit=iters_b, eta=1e4)
+    t2 = time.perf_counter()
+    per_it = ((t2 - t1) - (t1 - t0)) / (iters_b - iters_a)
+    return dict(value=1.0 / per_it, unit="block-iter/s", cores=1, kind="oracle",
+                sample=f"128^3 Laplacian, p=8, block subalgebra, eta=1e4: {iters_b} vs {iters_a} block iterations "
+                       f"(difference), single-threaded C oracle; {t2 - t0:.1f} s of CPU work",
+                seconds_per_iter=per_it)
+
+
+def run(args):
+    import numpy as np
+    import torch
+
+    import paper_2104_02494_amd as P
+    import workloads as W
+
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda", 0)
+    h = P.Handle(0)
+    log("building 128^3 Laplacian workload")
+    A, B, _ = W.build_workload("laplace3d_128_s8")
+    s = B.shape[1]
+    Ad = P.CsrMatrix.from_numpy(A.n, A.rowptr, A.colind, A.val, device=dev)
+    Bd = torch.as_tensor(B).to(dev)
+    opts = dict(kind="block", q=1, tol=1e-10, maxit=args.maxit, eta=1e4)
+
+    for w in range(args.warmup):
+        X, info = P.bkry_cg_solve(h, Ad, Bd, **opts)
+        log(f"warmup {w}: iters {info['iters']} reorth {info['reorth']} {info['seconds']*1e3:.1f} ms")
+    P.bkry_profile(h, True)
+    for k in range(4):
+        P.bkry_profile_read(h, k, reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    iters = 0
+    infos = []
+    for k in range(args.steps):
+        X, info = P.bkry_cg_solve(h, Ad, Bd, **opts)
+        iters += info["iters"]
+        infos.append(info)
+        log(f"step {k}: iters {info['iters']} reorth {info['reorth']} {info['seconds']*1e3:.1f} ms "
+            f"true relres {max(info['true_relres']):.2e}")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = {k: P.bkry_profile_read(h, k) for k in range(4)}
+    P.bkry_profile(h, False)
+    elapsed = t1 - t0
+    value = iters / elapsed
+    ms_per_step = elapsed / args.steps * 1e3
+
+    spmm_ms, spmm_n = prof[P.PROF_CG_SPMM]
+    upd_ms, upd_n = prof[P.PROF_CG_UPDATE]
+    pup_ms, pup_n = prof[P.PROF_CG_PUPDATE]
+    blk = A.n * s * 8
+    sp_bytes = spmm_bytes(A, s)
+    sp_avg = spmm_ms / max(spmm_n, 1) * 1e-3
+    achieved = sp_bytes / sp_avg / 1e9
+    upd_gbs = 3 * blk / (upd_ms / max(upd_n, 1) * 1e-3) / 1e9
+    pup_gbs = 5 * blk / (pup_ms / max(pup_n, 1) * 1e-3) / 1e9
+    iter_bytes = sp_bytes + 8 * blk          # + residual pass (3 blocks) + direction pass (5 blocks)
+    traffic = pmc_traffic()
+    result = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "block-iter/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "laplace3d_128_s8: 3D 7-point Laplacian 128^3 (n=2097152, nnz=14581760), "
+                               "p=8 uniform[-1,1] seed 1002, block CG, block subalgebra, eta=1e4, tol=1e-10, X0=0",
+                   "global_batch": s, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": round(achieved / PEAK_HBM_GBS, 4),
+                     "traffic": traffic,
+                     "kernel": "spmm_kernel<double,8,2,1> (SpMM fused with alpha Gram partials)",
+                     "algorithmic_bytes_per_launch": sp_bytes,
+                     "avg_launch_us": round(sp_avg * 1e6, 2), "launches_timed": spmm_n},
+        "time_to_tol_s": round(ms_per_step / 1e3, 4),
+        "iters_per_solve": infos[-1]["iters"],
+        "reorth_per_solve": infos[-1]["reorth"],
+        "true_relres_max": max(infos[-1]["true_relres"]),
+        "cg_iteration_GBps_algorithmic": round(iter_bytes * value / 1e9, 1),
+        "kernels_GBps": {"spmm_alpha_gram": round(achieved, 1), "residual_update_gram": round(upd_gbs, 1),
+                         "direction_update": round(pup_gbs, 1)},
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        cb = cpu_baseline(A, B)
+        result["cpu_baseline"] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in cb.items()
+                                  if k != "seconds_per_iter"}
+    if args.extras:
+        result["extras"] = extras(P, W, h, dev, A, Ad, Bd, args)
+    h.close()
+    print(json.dumps(result), flush=True)
+
+
+def timed(fn, reps):
+    import torch
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    out = None
+    for _ in range(reps):
+        out = fn()
+    ev1.record()
+    torch.cuda.synchronize()
+    return ev0.elapsed_time(ev1) / reps, out
+
+
+def extras(P, W, h, dev, A, Ad, Bd, args):
+    import numpy as np
+    import torch
+
+    ex = {}
+    s = Bd.shape[1]
+    # hybrid subalgebra, q = 2 groups of 4
+    X, info = P.bkry_cg_solve(h, Ad, Bd, kind="hybrid", q=2, tol=1e-10, maxit=args.maxit, eta=1e4)
+    ex["cg_hybrid_q2"] = dict(iters=info["iters"], reorth=info["reorth"], seconds=round(info["seconds"], 4),
+                              iters_per_s=round(info["iters"] / info["seconds"], 1),
+                              true_relres_max=max(info["true_relres"]))
+    log("hybrid", ex["cg_hybrid_q2"])
+    # BDOT alone (block subalgebra), 2 blocks read
+    Y = torch.randn_like(Bd)
+    ms, _ = timed(lambda: P.bkry_bdot(h, Bd, Y, "block"), 20)
+    ex["bdot_block_GBps"] = round(2 * A.n * s * 8 / (ms * 1e-3) / 1e9, 1)
+    ex["bdot_block_us"] = round(ms * 1e3, 2)
+    # SpMM alone (mode 0)
+    ms, _ = timed(lambda: P.bkry_spmm(h, Ad, Bd, Y), 20)
+    ex["spmm_plain_GBps"] = round(spmm_bytes(A, s) / (ms * 1e-3) / 1e9, 1)
+    del Y
+    # standalone TSQR 4,194,304 x 32
+    try:
+        Xt = torch.as_tensor(W.tsqr_input()).to(dev)
+        Xw = torch.empty_like(Xt)
+
+        def tsqr_once():
+            Xw.copy_(Xt)
+            return P.bkry_tsqr(h, Xw, "block")
+        ms_copy, _ = timed(lambda: Xw.copy_(Xt), 5)
+        ms, R = timed(tsqr_once, 5)
+        ms -= ms_copy
+        m, c = Xt.shape
+        ex["tsqr_4194304x32"] = dict(ms=round(ms, 3), GBps_algorithmic=round(2 * m * c * 8 / (ms * 1e-3) / 1e9, 1),
+                                     TFLOPs_algorithmic=round(4 * m * c * c / (ms * 1e-3) / 1e12, 2),
+                                     orth_err=float((Xw.T @ Xw - torch.eye(c, device=dev, dtype=Xw.dtype))
+                                                    .abs().max()))
+        del Xt, Xw
+        log("tsqr", ex["tsqr_4194304x32"])
+    except Exception as e:  # report, do not hide
+        ex["tsqr_4194304x32"] = dict(error=str(e))
+    # block GMRes(30): one cycle on the convection-diffusion workload
+    try:
+        Ac, Bc, _ = W.build_workload("convdiff2d_1024_s8")
+        Acd = P.CsrMatrix.from_numpy(Ac.n, Ac.rowptr, Ac.colind, Ac.val, device=dev)
+        Bcd = torch.as_tensor(Bc).to(dev)
+        P.bkry_gmres_solve(h, Acd, Bcd, kind="block", tol=0.0, maxit=30, restart=30)
+        Xg, gi = P.bkry_gmres_solve(h, Acd, Bcd, kind="block", tol=0.0, maxit=30, restart=30)
+        Xg, gt = P.bkry_gmres_solve(h, Acd, Bcd, kind="block", tol=1e-10, maxit=6000, restart=30)
+        ex["gmres30_convdiff1024"] = dict(cycle_ms=round(gi["seconds"] * 1e3, 2), solve_s=round(gt["seconds"], 3),
+                                          steps=gt["iters"], cycles=gt["outer_iters"], converged=gt["converged"],
+                                          true_relres_max=max(gt["true_relres"]))
+        log("gmres", ex["gmres30_convdiff1024"])
+        del Acd, Bcd, Xg
+    except Exception as e:
+        ex["gmres30_convdiff1024"] = dict(error=str(e))
+    # FP32-inner iterative refinement vs FP64 on the 27-point variable-coefficient workload
+    try:
+        A3, B3, _ = W.build_workload("diffusion27_96_s16")
+        A3d = P.CsrMatrix.from_numpy(A3.n, A3.rowptr, A3.colind, A3.val, device=dev)
+        B3d = torch.as_tensor(B3).to(dev)
+        X64, i64 = P.bkry_cg_solve(h, A3d, B3d, kind="block", tol=1e-10, maxit=20000, eta=1e4)
+        X32, i32 = P.bkry_cg_solve(h, A3d, B3d, kind="block", tol=1e-10, maxit=20000, eta=1.0, prec=P.F32_IR)
+        err = float(torch.linalg.norm(X32 - X64) / torch.linalg.norm(X64))
+        ex["ir_diffusion27_96_s16"] = dict(fp64_s=round(i64["seconds"], 3), fp64_iters=i64["iters"],
+                                           ir_s=round(i32["seconds"], 3), ir_inner_iters=i32["iters"],
+                                           ir_outer=i32["outer_iters"], ir_converged=i32["converged"],
+                                           ir_true_relres_max=max(i32["true_relres"]),
+                                           rel_err_vs_fp64=err)
+        log("ir", ex["ir_diffusion27_96_s16"])
+        del A3d, B3d, X64, X32
+    except Exception as e:
+        ex["ir_diffusion27_96_s16"] = dict(error=str(e))
+    # differentiable solve: forward + adjoint on the 64^3 variable-coefficient workload
+    try:
+        A5, B5, e5 = W.build_workload("diffusion7var_64_s32")
+        A5d = P.CsrMatrix.from_numpy(A5.n, A5.rowptr, A5.colind, A5.val, device=dev)
+        vals = A5d.val.clone().requires_grad_(True)
+        B5d = torch.as_tensor(B5).to(dev).requires_grad_(True)
+        T5 = torch.as_tensor(e5["target"]).to(dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        X5 = P.block_solve(vals, B5d, A5d, h, tol=1e-10, eta=1e4)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        loss = 0.5 * ((X5 - T5) ** 2).sum()
+        loss.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        ex["adjoint_diffusion7var_64_s32"] = dict(forward_s=round(t1 - t0, 4), backward_s=round(t2 - t1, 4))
+        log("adjoint", ex["adjoint_diffusion7var_64_s32"])
+    except Exception as e:
+        ex["adjoint_diffusion7var_64_s32"] = dict(error=str(e))
+    return ex
+
+
+def copy_probe():
+    """A plain device copy of known size, for scaling the HBM byte counters."""
+    import torch
+    n = 1 << 27  # 1 GiB of float64
+    x = torch.ones(n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": n * 8, "copy_probe_bytes_written": n * 8}))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--maxit", type=int, default=5000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--extras", dest="extras", action="store_true", default=True)
+    ap.add_argument("--no-extras", dest="extras", action="store_false")
+    ap.add_argument("--copy-probe", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build runs the whole hot path on a single MI355X "
+              "(no multi-GPU path); run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+    if args.copy_probe:
+        copy_probe()
+        return
+    run(args)
+
+
+if __name__ == "__main__":
+    main()

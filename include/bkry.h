@@ -107,6 +107,16 @@ int bkry_synchronize(bkry_handle h);
 /* Message of the last failing call on this handle (valid until the next call). */
 const char* bkry_last_error(bkry_handle h);
 
+/* Kernel timing (measurement support, not part of the method): when enabled,
+ * the block CG driver brackets each launch of its streaming kernels with HIP
+ * events on the handle's stream and accumulates the elapsed times.  Kernel
+ * ids: 0 SpMM fused with the alpha Gram, 1 residual update fused with the
+ * Gram of R~, 2 direction update (X and P), 3 whole re-normalisation (TSQR,
+ * Gram, coefficients).  bkry_profile_read returns the total milliseconds and
+ * the number of timed launches of one kernel id, optionally resetting them. */
+int bkry_profile(bkry_handle h, int enable);
+int bkry_profile_read(bkry_handle h, int32_t kernel, double* total_ms, int64_t* launches, int32_t reset);
+
 /* BOP (Ch. 3, Performance Analysis): Y = A X for n x p blocks.  Each output
  * entry is summed over the row's non-zeros in storage order. */
 int bkry_spmm(bkry_handle h, const bkry_csr* A, int32_t p, const double* X, double* Y);

@@ -55,7 +55,8 @@ class bkry_info(ctypes.Structure):
                 ("seconds", ctypes.c_double)]
 
 
-EXPORTS = ["bkry_create", "bkry_destroy", "bkry_set_stream", "bkry_synchronize", "bkry_last_error", "bkry_spmm",
+EXPORTS = ["bkry_create", "bkry_destroy", "bkry_set_stream", "bkry_synchronize", "bkry_last_error",
+           "bkry_profile", "bkry_profile_read", "bkry_spmm",
            "bkry_spmm_f32", "bkry_bdot", "bkry_bdot_f32", "bkry_tsqr", "bkry_cg_solve", "bkry_gmres_solve",
            "bkry_sddmm", "bkry_csr_transpose"]
 
@@ -78,6 +79,8 @@ def lib():
             "bkry_destroy": [H],
             "bkry_set_stream": [H, vp],
             "bkry_synchronize": [H],
+            "bkry_profile": [H, ctypes.c_int],
+            "bkry_profile_read": [H, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64), i32],
             "bkry_spmm": [H, csr_p, i32, vp, vp],
             "bkry_spmm_f32": [H, i64, i64, vp, vp, vp, i32, vp, vp],
             "bkry_bdot": [H, i64, i32, bkry_subalg, vp, vp, vp],
@@ -288,6 +291,22 @@ def bkry_csr_transpose(h: Handle, A: CsrMatrix):
 
 def bkry_synchronize(h: Handle):
     h._check(lib().bkry_synchronize(h.h))
+
+
+PROF_CG_SPMM, PROF_CG_UPDATE, PROF_CG_PUPDATE, PROF_CG_NORMALISE = 0, 1, 2, 3
+
+
+def bkry_profile(h: Handle, enable: bool = True):
+    """Enable/disable event timing of the CG driver's streaming kernels."""
+    h._check(lib().bkry_profile(h.h, int(bool(enable))))
+
+
+def bkry_profile_read(h: Handle, kernel: int, reset: bool = False):
+    """(total milliseconds, number of timed launches) of one kernel id."""
+    ms = ctypes.c_double()
+    cnt = ctypes.c_int64()
+    h._check(lib().bkry_profile_read(h.h, int(kernel), ctypes.byref(ms), ctypes.byref(cnt), int(reset)))
+    return ms.value, cnt.value
 
 
 from .autograd import BlockSolve, block_solve  # noqa: E402,F401

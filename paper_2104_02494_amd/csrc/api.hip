@@ -25,6 +25,7 @@ struct bkry_handle_s {
   size_t ws_cap = 0;
   int32_t* hflags = nullptr;  // pinned host, kHostFlagsInts
   int32_t* dflags = nullptr;  // device: [0] bad CSR index seen by an asynchronous kernel
+  Prof* prof = nullptr;       // kernel timing, when enabled
   std::string err;
 };
 
@@ -178,6 +179,10 @@ int bkry_destroy(bkry_handle h) {
   if (h->ws) (void)hipFree(h->ws);
   if (h->dflags) (void)hipFree(h->dflags);
   if (h->hflags) (void)hipHostFree(h->hflags);
+  if (h->prof) {
+    prof_destroy(h->prof);
+    delete h->prof;
+  }
   delete h;
   return BKRY_OK;
 }
@@ -200,6 +205,36 @@ int bkry_synchronize(bkry_handle h) {
     API_HIP(hipMemsetAsync(h->dflags, 0, sizeof(int32_t), h->stream), "sync");
     API_HIP(hipStreamSynchronize(h->stream), "sync");
     return fail(h, BKRY_E_INVALID, "a CSR column index was outside [0, n)");
+  }
+  return BKRY_OK;
+}
+
+int bkry_profile(bkry_handle h, int enable) {
+  int rc = begin(h);
+  if (rc) return rc;
+  if (enable && !h->prof) {
+    h->prof = new (std::nothrow) Prof();
+    if (!h->prof) return fail(h, BKRY_E_ALLOC, "profile state");
+    API_HIP(prof_init(h->prof), "profile");
+  } else if (!enable && h->prof) {
+    API_HIP(hipStreamSynchronize(h->stream), "profile");
+    prof_destroy(h->prof);
+    delete h->prof;
+    h->prof = nullptr;
+  }
+  return BKRY_OK;
+}
+
+int bkry_profile_read(bkry_handle h, int32_t kernel, double* total_ms, int64_t* launches, int32_t reset) {
+  int rc = begin(h);
+  if (rc) return rc;
+  if (!h->prof) return fail(h, BKRY_E_INVALID, "kernel timing is not enabled");
+  if (kernel < 0 || kernel >= PROF_N) return fail(h, BKRY_E_INVALID, "unknown kernel id");
+  if (total_ms) *total_ms = h->prof->ms[kernel];
+  if (launches) *launches = h->prof->cnt[kernel];
+  if (reset) {
+    h->prof->ms[kernel] = 0.0;
+    h->prof->cnt[kernel] = 0;
   }
   return BKRY_OK;
 }
@@ -287,7 +322,7 @@ int bkry_cg_solve(bkry_handle h, const bkry_csr* A, int32_t p, bkry_subalg S, co
     int32_t* tfl = w.take<int32_t>(4);
     CgResult r;
     hipError_t e = cg_run<double>(view(A), sub, B, X, tol, maxit, eta, DBL_EPSILON, hist_cap, cb, h->stream,
-                                  h->hflags, r);
+                                  h->hflags, r, h->prof);
     if (e != hipSuccess) return hip_fail(h, e, "cg_solve");
     status = r.status;
     iters = r.iters;
@@ -318,7 +353,7 @@ int bkry_cg_solve(bkry_handle h, const bkry_csr* A, int32_t p, bkry_subalg S, co
     const int mo = (info && info->max_outer > 0) ? info->max_outer : 30;
     IrResult r;
     hipError_t e = ir_run(view(A), sub, B, X, tol, maxit, eta, itol, mo, info ? info->hist : nullptr, hist_cap, ib,
-                          h->stream, h->hflags, relres, r);
+                          h->stream, h->hflags, relres, r, h->prof);
     if (e != hipSuccess) return hip_fail(h, e, "cg_solve (FP32 refinement)");
     status = r.status;
     iters = r.inner_iters;

@@ -17,6 +17,55 @@ namespace bkry {
     if (e_ != hipSuccess) return e_;    \
   } while (0)
 
+// ------------------------------------------------------------ kernel timing --
+hipError_t prof_init(Prof* p) {
+  for (int k = 0; k < PROF_N; ++k) {
+    p->used[k] = 0;
+    p->ms[k] = 0.0;
+    p->cnt[k] = 0;
+    for (int e = 0; e < 2; ++e)
+      for (int i = 0; i < kProfSlots; ++i) BK_TRY(hipEventCreate(&p->ev[k][e][i]));
+  }
+  return hipSuccess;
+}
+
+void prof_destroy(Prof* p) {
+  for (int k = 0; k < PROF_N; ++k)
+    for (int e = 0; e < 2; ++e)
+      for (int i = 0; i < kProfSlots; ++i) (void)hipEventDestroy(p->ev[k][e][i]);
+}
+
+hipError_t prof_flush(Prof* p) {
+  if (!p) return hipSuccess;
+  for (int k = 0; k < PROF_N; ++k) {
+    for (int i = 0; i < p->used[k]; ++i) {
+      float ms = 0.0f;
+      BK_TRY(hipEventElapsedTime(&ms, p->ev[k][0][i], p->ev[k][1][i]));
+      p->ms[k] += ms;
+      p->cnt[k] += 1;
+    }
+    p->used[k] = 0;
+  }
+  return hipSuccess;
+}
+
+namespace {
+struct ProfScope {
+  Prof* p;
+  int k;
+  hipStream_t st;
+  ProfScope(Prof* p_, int k_, hipStream_t st_) : p(p_), k(k_), st(st_) {
+    if (p && p->used[k] < kProfSlots) (void)hipEventRecord(p->ev[k][0][p->used[k]], st);
+  }
+  ~ProfScope() {
+    if (p && p->used[k] < kProfSlots) {
+      (void)hipEventRecord(p->ev[k][1][p->used[k]], st);
+      p->used[k] += 1;
+    }
+  }
+};
+}  // namespace
+
 // ---------------------------------------------------------------- block CG --
 template <typename T>
 CgBufs<T> carve_cg(Carver& c, int64_t n, Sub sub, int hist_cap) {
@@ -37,7 +86,7 @@ CgBufs<T> carve_cg(Carver& c, int64_t n, Sub sub, int hist_cap) {
 
 template <typename T>
 hipError_t cg_run(const CsrView& A, Sub sub, const T* B, T* X, double tol, int maxit, double eta, double eps,
-                  int hist_cap, const CgBufs<T>& b, hipStream_t st, int32_t* hflags, CgResult& res) {
+                  int hist_cap, const CgBufs<T>& b, hipStream_t st, int32_t* hflags, CgResult& res, Prof* prof) {
   const int64_t n = A.n;
   const int s = sub.s;
   const int nblk = stream_grid(n, s, sizeof(T));
@@ -76,23 +125,34 @@ hipError_t cg_run(const CsrView& A, Sub sub, const T* B, T* X, double tol, int m
   int launched = 0, batch = 4;
   while (maxit > 0) {
     for (int it = 0; it < batch; ++it) {
-      BK_TRY(launch_spmm<T>(A, s, b.P, b.Q, nullptr, 1, b.partial, nblk, &c->bad_index, done, st));
+      {
+        ProfScope ps(prof, PROF_CG_SPMM, st);
+        BK_TRY(launch_spmm<T>(A, s, b.P, b.Q, nullptr, 1, b.partial, nblk, &c->bad_index, done, st));
+      }
       BK_TRY(launch_reduce_partials<T>(s, b.partial, nblk, b.Ga, done, st));
       BK_TRY(launch_cg_alpha(c, b.Ga, st));
-      BK_TRY(launch_cg_update<T>(n, s, b.R, b.Q, c, b.partial, nblk, st));
+      {
+        ProfScope ps(prof, PROF_CG_UPDATE, st);
+        BK_TRY(launch_cg_update<T>(n, s, b.R, b.Q, c, b.partial, nblk, st));
+      }
       BK_TRY(launch_reduce_partials<T>(s, b.partial, nblk, b.Gr, done, st));
       BK_TRY(launch_cg_rho(c, b.Gr, b.hist, st));
       if (may_fire) {
+        ProfScope ps(prof, PROF_CG_NORMALISE, st);
         BK_TRY(tsqr_run<T>(n, sub, b.R, c->gamma, b.tsqr_ws, done, &c->fire, st));
         BK_TRY(launch_gram<T>(n, s, b.R, b.R, b.partial, nblk, done, st, &c->fire));
         BK_TRY(launch_reduce_partials<T>(s, b.partial, nblk, b.Gq, done, st, &c->fire));
         BK_TRY(launch_cg_reortho_fin(c, b.Gq, st));
       }
-      BK_TRY(launch_cg_pupdate<T>(n, s, X, b.P, b.R, c, st));
+      {
+        ProfScope ps(prof, PROF_CG_PUPDATE, st);
+        BK_TRY(launch_cg_pupdate<T>(n, s, X, b.P, b.R, c, st));
+      }
     }
     launched += batch;
     BK_TRY(hipMemcpyAsync(hflags, c, kCtlHeaderInts * sizeof(int32_t), hipMemcpyDeviceToHost, st));
     BK_TRY(hipStreamSynchronize(st));
+    BK_TRY(prof_flush(prof));
     if (hflags[0] || launched >= maxit) break;
     if (batch < 16) batch *= 2;
   }
@@ -112,9 +172,9 @@ hipError_t cg_run(const CsrView& A, Sub sub, const T* B, T* X, double tol, int m
 template CgBufs<double> carve_cg<double>(Carver&, int64_t, Sub, int);
 template CgBufs<float> carve_cg<float>(Carver&, int64_t, Sub, int);
 template hipError_t cg_run<double>(const CsrView&, Sub, const double*, double*, double, int, double, double, int,
-                                   const CgBufs<double>&, hipStream_t, int32_t*, CgResult&);
+                                   const CgBufs<double>&, hipStream_t, int32_t*, CgResult&, Prof*);
 template hipError_t cg_run<float>(const CsrView&, Sub, const float*, float*, double, int, double, double, int,
-                                  const CgBufs<float>&, hipStream_t, int32_t*, CgResult&);
+                                  const CgBufs<float>&, hipStream_t, int32_t*, CgResult&, Prof*);
 
 // ------------------------------------------------------ true residuals --
 hipError_t true_relres(const CsrView& A, int s, const double* B, const double* X, double* R, double* partial,
@@ -149,7 +209,7 @@ IrBufs carve_ir(Carver& c, int64_t n, int64_t nnz, Sub sub) {
 // tolerance; X += D |R| in FP64; repeat until the FP64 residual meets tol.
 hipError_t ir_run(const CsrView& A, Sub sub, const double* B, double* X, double tol, int maxit, double eta,
                   double inner_tol, int max_outer, double* hist_host, int hist_cap, const IrBufs& b, hipStream_t st,
-                  int32_t* hflags, double* relres_host, IrResult& res) {
+                  int32_t* hflags, double* relres_host, IrResult& res, Prof* prof) {
   const int64_t n = A.n;
   const int s = sub.s;
   const int nblk = stream_grid(n, s, sizeof(double));
@@ -183,7 +243,8 @@ hipError_t ir_run(const CsrView& A, Sub sub, const double* B, double* X, double 
     BK_TRY(launch_cast_scale_f32(n, s, b.R64, b.scale, b.R32, st));
     BK_TRY(hipMemsetAsync(b.X32, 0, sizeof(float) * (size_t)n * s, st));
     CgResult r;
-    BK_TRY(cg_run<float>(A32, sub, b.R32, b.X32, inner_tol, maxit, eta, (double)FLT_EPSILON, 0, b.cg, st, hflags, r));
+    BK_TRY(cg_run<float>(A32, sub, b.R32, b.X32, inner_tol, maxit, eta, (double)FLT_EPSILON, 0, b.cg, st, hflags, r,
+                         prof));
     res.inner_iters += r.iters;
     res.nreorth += r.nreorth;
     if (r.bad_index) {

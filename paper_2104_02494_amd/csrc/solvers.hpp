@@ -20,6 +20,21 @@ struct Carver {
   }
 };
 
+// Optional timing of the solver's streaming kernels with HIP events recorded
+// on the solver's stream around each launch (kernel ids below).
+enum ProfKernel { PROF_CG_SPMM = 0, PROF_CG_UPDATE = 1, PROF_CG_PUPDATE = 2, PROF_CG_NORMALISE = 3, PROF_N = 4 };
+constexpr int kProfSlots = 64;
+struct Prof {
+  hipEvent_t ev[PROF_N][2][kProfSlots];
+  int used[PROF_N];
+  double ms[PROF_N];
+  long long cnt[PROF_N];
+};
+hipError_t prof_init(Prof* p);
+void prof_destroy(Prof* p);
+// Accumulates the recorded pairs (the stream must have been synchronised).
+hipError_t prof_flush(Prof* p);
+
 // Pinned host staging area shared by the drivers: [0, 64) ints for read-backs,
 // [64, 128) ints (256 bytes) for uploads.
 constexpr int kHostFlagsInts = 256;
@@ -44,7 +59,8 @@ struct CgResult {
 // FP64).  X holds X0 on entry.  eps is the machine epsilon of T.
 template <typename T>
 hipError_t cg_run(const CsrView& A, Sub sub, const T* B, T* X, double tol, int maxit, double eta, double eps,
-                  int hist_cap, const CgBufs<T>& b, hipStream_t st, int32_t* hflags, CgResult& res);
+                  int hist_cap, const CgBufs<T>& b, hipStream_t st, int32_t* hflags, CgResult& res,
+                  Prof* prof = nullptr);
 
 struct IrBufs {
   float *A32 = nullptr, *R32 = nullptr, *X32 = nullptr;
@@ -59,7 +75,7 @@ struct IrResult {
 };
 hipError_t ir_run(const CsrView& A, Sub sub, const double* B, double* X, double tol, int maxit, double eta,
                   double inner_tol, int max_outer, double* hist_host, int hist_cap, const IrBufs& b, hipStream_t st,
-                  int32_t* hflags, double* relres_host, IrResult& res);
+                  int32_t* hflags, double* relres_host, IrResult& res, Prof* prof = nullptr);
 
 struct GmBufs {
   double *V = nullptr, *partial = nullptr, *Gb = nullptr, *H1 = nullptr, *H2 = nullptr, *H = nullptr, *sig = nullptr;
