@@ -25,6 +25,7 @@ struct bkry_handle_s {
   size_t ws_cap = 0;
   int32_t* hflags = nullptr;  // pinned host, kHostFlagsInts
   int32_t* dflags = nullptr;  // device: [0] bad CSR index seen by an asynchronous kernel
+  uint32_t* cnt = nullptr;    // device: zeroed grid-reduction counters (left zero by every kernel)
   Prof* prof = nullptr;       // kernel timing, when enabled
   std::string err;
 };
@@ -134,14 +135,15 @@ int bdot_impl(bkry_handle h, int64_t n, int32_t p, bkry_subalg S, const T* X, co
   const int nblk = stream_grid(n, p, sizeof(T));
   Carver c;
   c.take<T>((size_t)nblk * p * p);
+  c.take<double>(red_gpart_count(nblk, p));
   c.take<double>((size_t)p * p);
   rc = ensure_ws(h, c.off);
   if (rc) return rc;
   Carver w{h->ws};
   T* part = w.take<T>((size_t)nblk * p * p);
+  double* gpart = w.take<double>(red_gpart_count(nblk, p));
   double* Gf = w.take<double>((size_t)p * p);
-  API_HIP(launch_gram<T>(n, p, X, Y, part, nblk, nullptr, h->stream), "bdot");
-  API_HIP(launch_reduce_partials<T>(p, part, nblk, Gf, nullptr, h->stream), "bdot");
+  API_HIP(launch_gram<T>(n, p, X, 1, Y, part, nblk, Red{Gf, gpart, h->cnt}, nullptr, h->stream), "bdot");
   API_HIP(launch_project(Gf, G, sub, h->stream), "bdot");
   return BKRY_OK;
 }
@@ -161,10 +163,13 @@ int bkry_create(bkry_handle* out, int device, void* stream) {
   if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&h->hflags), kHostFlagsInts * sizeof(int32_t));
   if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&h->dflags), 64 * sizeof(int32_t));
   if (e == hipSuccess) e = hipMemsetAsync(h->dflags, 0, 64 * sizeof(int32_t), h->stream);
+  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&h->cnt), kCounterInts * sizeof(uint32_t));
+  if (e == hipSuccess) e = hipMemsetAsync(h->cnt, 0, kCounterInts * sizeof(uint32_t), h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) {
     if (h->hflags) (void)hipHostFree(h->hflags);
     if (h->dflags) (void)hipFree(h->dflags);
+    if (h->cnt) (void)hipFree(h->cnt);
     delete h;
     return BKRY_E_HIP;
   }
@@ -178,6 +183,7 @@ int bkry_destroy(bkry_handle h) {
   (void)hipStreamSynchronize(h->stream);
   if (h->ws) (void)hipFree(h->ws);
   if (h->dflags) (void)hipFree(h->dflags);
+  if (h->cnt) (void)hipFree(h->cnt);
   if (h->hflags) (void)hipHostFree(h->hflags);
   if (h->prof) {
     prof_destroy(h->prof);
@@ -246,7 +252,8 @@ int bkry_spmm(bkry_handle h, const bkry_csr* A, int32_t p, const double* X, doub
   if (!rc) rc = check_blocks(h, {X, Y});
   if (rc) return rc;
   const int nblk = stream_grid(A->n, p, sizeof(double));
-  API_HIP(launch_spmm<double>(view(A), p, X, Y, nullptr, 0, nullptr, nblk, h->dflags, nullptr, h->stream), "spmm");
+  API_HIP(launch_spmm<double>(view(A), p, X, Y, nullptr, 0, nullptr, nblk, Red{}, h->dflags, nullptr, h->stream),
+          "spmm");
   return BKRY_OK;
 }
 
@@ -261,7 +268,8 @@ int bkry_spmm_f32(bkry_handle h, int64_t n, int64_t nnz, const int32_t* rowptr, 
   if (rc) return rc;
   CsrView v{n, nnz, rowptr, colind, val};
   const int nblk = stream_grid(n, p, sizeof(float));
-  API_HIP(launch_spmm<float>(v, p, X, Y, nullptr, 0, nullptr, nblk, h->dflags, nullptr, h->stream), "spmm_f32");
+  API_HIP(launch_spmm<float>(v, p, X, Y, nullptr, 0, nullptr, nblk, Red{}, h->dflags, nullptr, h->stream),
+          "spmm_f32");
   return BKRY_OK;
 }
 
@@ -284,7 +292,7 @@ int bkry_tsqr(bkry_handle h, int64_t n, int32_t p, bkry_subalg S, double* X, dou
   if (rc) return rc;
   rc = ensure_ws(h, tsqr_workspace_bytes(n, sub));
   if (rc) return rc;
-  API_HIP(tsqr_run<double>(n, sub, X, R, h->ws, nullptr, nullptr, h->stream), "tsqr");
+  API_HIP(tsqr_run<double>(n, sub, X, R, h->ws, h->cnt, nullptr, nullptr, h->stream), "tsqr");
   return BKRY_OK;
 }
 
@@ -309,14 +317,14 @@ int bkry_cg_solve(bkry_handle h, const bkry_csr* A, int32_t p, bkry_subalg S, co
   int status = 0, iters = 0, nre = 0, outer = 0, conv = 0, bad = 0, hist_len = 0;
   if (prec == BKRY_F64) {
     Carver c;
-    carve_cg<double>(c, n, sub, hist_cap);
+    carve_cg<double>(c, n, sub, hist_cap, h->cnt);
     c.take<double>(kMaxS);
     c.take<double>(kMaxS);
     c.take<int32_t>(4);
     rc = ensure_ws(h, c.off);
     if (rc) return rc;
     Carver w{h->ws};
-    CgBufs<double> cb = carve_cg<double>(w, n, sub, hist_cap);
+    CgBufs<double> cb = carve_cg<double>(w, n, sub, hist_cap, h->cnt);
     double* trr = w.take<double>(kMaxS);
     double* tsc = w.take<double>(kMaxS);
     int32_t* tfl = w.take<int32_t>(4);
@@ -333,19 +341,21 @@ int bkry_cg_solve(bkry_handle h, const bkry_csr* A, int32_t p, bkry_subalg S, co
     API_HIP(hipMemcpyAsync(relres, cb.ctl->relres, sizeof(double) * p, hipMemcpyDeviceToHost, h->stream), "cg");
     if (hist_len > 0)
       API_HIP(hipMemcpyAsync(info->hist, cb.hist, sizeof(double) * hist_len, hipMemcpyDeviceToHost, h->stream), "cg");
-    API_HIP(true_relres(view(A), p, B, X, cb.Q, cb.partial, cb.Ga, cb.ctl->r0n, trr, tfl, tsc, h->stream), "cg");
+    API_HIP(true_relres(view(A), p, B, X, cb.Q, cb.partial, cb.gpart, h->cnt, cb.Ga, cb.ctl->r0n, trr, tfl, tsc,
+                        h->stream),
+            "cg");
     API_HIP(hipMemcpyAsync(trel, trr, sizeof(double) * p, hipMemcpyDeviceToHost, h->stream), "cg");
     API_HIP(hipStreamSynchronize(h->stream), "cg");
   } else {
     Carver c;
-    carve_ir(c, n, A->nnz, sub);
+    carve_ir(c, n, A->nnz, sub, h->cnt);
     c.take<double>(kMaxS);
     c.take<double>(kMaxS);
     c.take<int32_t>(4);
     rc = ensure_ws(h, c.off);
     if (rc) return rc;
     Carver w{h->ws};
-    IrBufs ib = carve_ir(w, n, A->nnz, sub);
+    IrBufs ib = carve_ir(w, n, A->nnz, sub, h->cnt);
     double* trr = w.take<double>(kMaxS);
     double* tsc = w.take<double>(kMaxS);
     int32_t* tfl = w.take<int32_t>(4);
@@ -362,7 +372,9 @@ int bkry_cg_solve(bkry_handle h, const bkry_csr* A, int32_t p, bkry_subalg S, co
     conv = r.converged;
     bad = r.bad_index;
     hist_len = r.hist_len;
-    API_HIP(true_relres(view(A), p, B, X, ib.R64, ib.partial, ib.G, ib.r0n, trr, tfl, tsc, h->stream), "ir");
+    API_HIP(true_relres(view(A), p, B, X, ib.R64, ib.partial, ib.gpart, h->cnt, ib.G, ib.r0n, trr, tfl, tsc,
+                        h->stream),
+            "ir");
     API_HIP(hipMemcpyAsync(trel, trr, sizeof(double) * p, hipMemcpyDeviceToHost, h->stream), "ir");
     API_HIP(hipStreamSynchronize(h->stream), "ir");
   }
@@ -398,13 +410,13 @@ int bkry_gmres_solve(bkry_handle h, const bkry_csr* A, int32_t p, bkry_subalg S,
   const int64_t n = A->n;
   const int hist_cap = (info && info->hist && info->hist_cap > 0) ? info->hist_cap : 0;
   Carver c;
-  carve_gm(c, n, sub, restart, hist_cap);
+  carve_gm(c, n, sub, restart, hist_cap, h->cnt);
   c.take<double>(kMaxS);
   c.take<double>(kMaxS);
   rc = ensure_ws(h, c.off);
   if (rc) return rc;
   Carver w{h->ws};
-  GmBufs gb = carve_gm(w, n, sub, restart, hist_cap);
+  GmBufs gb = carve_gm(w, n, sub, restart, hist_cap, h->cnt);
   double* trr = w.take<double>(kMaxS);
   double* tsc = w.take<double>(kMaxS);
   GmResult r;
@@ -414,15 +426,18 @@ int bkry_gmres_solve(bkry_handle h, const bkry_csr* A, int32_t p, bkry_subalg S,
   } else {
     // no step allowed: only the initial residual norms
     const int nblk = stream_grid(n, p, sizeof(double));
-    API_HIP(launch_spmm<double>(view(A), p, X, gb.V, B, 2, gb.partial, nblk, nullptr, nullptr, h->stream), "gmres");
-    API_HIP(launch_reduce_partials<double>(p, gb.partial, nblk, gb.Gb, nullptr, h->stream), "gmres");
+    API_HIP(launch_spmm<double>(view(A), p, X, gb.V, B, 2, gb.partial, nblk, Red{gb.Gb, gb.gpart, h->cnt}, nullptr,
+                                nullptr, h->stream),
+            "gmres");
     API_HIP(launch_gm_cycle_init(gb.ctl, gb.sig, gb.Gb, gb.Gb, 1, h->stream), "gmres");
     API_HIP(hipMemcpyAsync(h->hflags, gb.ctl, 16 * sizeof(int32_t), hipMemcpyDeviceToHost, h->stream), "gmres");
     API_HIP(hipStreamSynchronize(h->stream), "gmres");
     r.converged = reinterpret_cast<GmCtl*>(h->hflags)->converged;
   }
   double trel[kMaxS];
-  API_HIP(true_relres(view(A), p, B, X, gb.V, gb.partial, gb.Gb, gb.ctl->r0n, trr, gb.flag, tsc, h->stream), "gmres");
+  API_HIP(true_relres(view(A), p, B, X, gb.V, gb.partial, gb.gpart, h->cnt, gb.Gb, gb.ctl->r0n, trr, gb.flag, tsc,
+                      h->stream),
+          "gmres");
   API_HIP(hipMemcpyAsync(trel, trr, sizeof(double) * p, hipMemcpyDeviceToHost, h->stream), "gmres");
   const int hist_len = r.steps < hist_cap ? r.steps : hist_cap;
   if (hist_len > 0)

@@ -23,6 +23,19 @@ struct Sub {
   int g;
 };
 
+// Target of the Gram reductions: the producer writes one s x s partial per
+// workgroup; the reduction kernel (<= 16 workgroups per batch slice) writes
+// slice sums to gpart and the final FP64 Gram to G.  cnt holds one zeroed
+// counter per batch slice (left zero).
+struct Red {
+  double* G;
+  double* gpart;
+  uint32_t* cnt;
+};
+constexpr int kCntStride = 64;    // counters reserved per batch slice
+constexpr int kMaxBatch = 256;    // batch slices of one launch
+inline size_t red_gpart_count(int nblk, int s) { return (size_t)16 * s * s; }
+
 struct CsrView {
   int64_t n, nnz;
   const int32_t* rowptr;
@@ -43,7 +56,11 @@ struct CgCtl {
   int32_t maxit;
   int32_t s, kind, g, hist_cap;
   int32_t bad_index;  // a CSR column index was out of range
-  int32_t pad_[3];
+  int32_t gate;       // streaming kernels skip while set (done or suspended)
+  int32_t suspended;  // the iteration waits for a re-normalisation launched by the host
+  int32_t dynamic;    // the re-orthonormalisation test is decided per iteration
+  int32_t kd_jacobi;  // iterations whose kappa_D needed the Jacobi eigenvalues
+  int32_t pad_[7];
   double tol, eta, sqrt_eps, pad2_;
   double r0n[kMaxS];
   double relres[kMaxS];
@@ -58,7 +75,7 @@ struct CgCtl {
   float lamsig_f[kMaxS * kMaxS];
   float beta_f[kMaxS * kMaxS];
 };
-constexpr int kCtlHeaderInts = 16;
+constexpr int kCtlHeaderInts = 24;
 
 // Device control block of a block GMRes solve (per-cycle arrays live in
 // separate workspace buffers: H, sig, Om, zeta).
@@ -81,35 +98,22 @@ struct GmCtl {
 int stream_grid(int64_t n, int s, int elem_bytes);
 
 // ------------------------------------------------------- block kernels ----
-// SpMM modes: 0 Y = A X; 1 also Gram partials of X^T Y (X the own rows);
-// 2 Y = B - A X and Gram partials of Y^T Y.
+// SpMM modes: 0 Y = A X; 1 also the Gram X^T Y (X the own rows) into red.G;
+// 2 Y = B - A X and the Gram Y^T Y into red.G.  partial: nblk*s*s of T.
 template <typename T>
 hipError_t launch_spmm(const CsrView& A, int s, const T* X, T* Y, const T* B, int mode, T* partial,
-                       int nblk, int32_t* bad, const int32_t* done, hipStream_t st);
+                       int nblk, Red red, int32_t* bad, const int32_t* gate, hipStream_t st);
 
-// Gram partials of X^T Y (full s x s per workgroup).
-// (The optional `fire` gate: run only if *fire != 0.)
+// Gram X_j^T Y for X_j = X + j*n*s, j < nx, into red.G + j*s*s (batched:
+// partial, gpart and counters are per slice).  Optional second gate `fire`:
+// run only if *fire != 0.
 template <typename T>
-hipError_t launch_gram(int64_t n, int s, const T* X, const T* Y, T* partial, int nblk, const int32_t* done,
-                       hipStream_t st, const int32_t* fire = nullptr);
+hipError_t launch_gram(int64_t n, int s, const T* X, int nx, const T* Y, T* partial, int nblk, Red red,
+                       const int32_t* gate, hipStream_t st, const int32_t* fire = nullptr);
 
-// Batched Gram partials: X_j = X + j*n*s for j < nx; partial[(j*nblk + blk)*s*s].
+// CG residual update R~ = R - Q lambda (in place in R) and the Gram of R~ into red.G.
 template <typename T>
-hipError_t launch_gram_batched(int64_t n, int s, const T* X, int nx, const T* Y, T* partial, int nblk,
-                               const int32_t* done, hipStream_t st, const int32_t* fire = nullptr);
-// G_j = sum over blk of partial[(j*nblk + blk)*s*s] for j < batch.
-template <typename T>
-hipError_t launch_reduce_batched(int s, const T* partial, int nblk, int batch, double* G, const int32_t* gate,
-                                 hipStream_t st, const int32_t* fire = nullptr);
-
-// G = sum of nblk partials (s x s each), accumulated in FP64 in a fixed order.
-template <typename T>
-hipError_t launch_reduce_partials(int s, const T* partial, int nblk, double* G, const int32_t* gate,
-                                  hipStream_t st, const int32_t* fire = nullptr);
-
-// CG residual update R~ = R - Q lambda (in place in R) + Gram partials of R~.
-template <typename T>
-hipError_t launch_cg_update(int64_t n, int s, T* R, const T* Q, const CgCtl* ctl, T* partial, int nblk,
+hipError_t launch_cg_update(int64_t n, int s, T* R, const T* Q, const CgCtl* ctl, T* partial, int nblk, Red red,
                             hipStream_t st);
 
 // CG direction update X += P (lambda sigma); if not done: P = R + P beta.
@@ -168,7 +172,7 @@ size_t tsqr_workspace_bytes(int64_t n, Sub sub);
 // device) receives the normaliser.  gate_done / gate_fire (may be null): run
 // only if *gate_done == 0 and *gate_fire != 0.
 template <typename T>
-hipError_t tsqr_run(int64_t n, Sub sub, T* X, double* N, void* ws, const int32_t* gate_done,
+hipError_t tsqr_run(int64_t n, Sub sub, T* X, double* N, void* ws, uint32_t* cnt, const int32_t* gate_done,
                     const int32_t* gate_fire, hipStream_t st);
 
 // -------------------------------------------------------- transpose ----

@@ -3,9 +3,7 @@
 //   spmm          BOP, Y = A X (Ch. 3, kernel BOP), optionally fused with the
 //                 Gram partials of <X, Y> (the alpha BDOT of block CG) or with
 //                 the residual R = B - A X and its Gram partials;
-//   gram          BDOT partials X^T Y, one s x s partial per workgroup, batched
-//                 over several X blocks (block Gram-Schmidt);
-//   reduce        fixed-order sum of the partials in FP64;
+//   gram          BDOT X^T Y, batched over several X blocks (block Gram-Schmidt);
 //   cg_update     R~ = R - Q lambda fused with the Gram partials of R~
 //                 (BAXPY + BDOT fusion of the two-reduction BCG, Ch. 8);
 //   cg_pupdate    X += P (lambda sigma) and P = R + P beta in one pass;
@@ -14,10 +12,15 @@
 //   casts / column scalings for the normalisers and iterative refinement.
 //
 // All kernels are bandwidth-bound (arithmetic intensity <= s/4 flop/byte in
-// FP64, below the MI355X ridge of ~10).  Each lane streams 16-byte vectors;
-// per-lane register accumulation, then a fixed butterfly over the row slots
-// of a wavefront, then a fixed-order sum over the wavefronts of a workgroup.
-// No floating-point atomics anywhere.
+// FP64, below the MI355X ridge of ~10).  Each lane streams 16-byte vectors.
+// Gram matrices: per-lane register accumulation, a fixed butterfly over the
+// row slots of a wavefront, a fixed-order sum over the wavefronts of a
+// workgroup, one s x s partial per workgroup; then a small reduction kernel
+// (at most 16 workgroups per Gram) sums contiguous slices of the partials and
+// its last workgroup to finish adds the slice sums in slice order.  Which
+// workgroup arrives last does not change the order of any sum, so results
+// are deterministic.  The producers themselves need no grid-wide fences.
+// Only integer counters use atomics; no floating-point atomics anywhere.
 #include <type_traits>
 
 #include "common.hpp"
@@ -109,9 +112,10 @@ __device__ __forceinline__ void row_times(T (&out)[VEC], const vec_t<T, VEC>& mi
   }
 }
 
-// Reduce per-lane Gram accumulators of a workgroup into one s x s partial.
+// Reduce per-lane Gram accumulators of a workgroup into its s x s partial
+// (partial + ((blockIdx.y * gridDim.x + blockIdx.x) * s * s)).
 template <typename T, int S, int VEC>
-__device__ __forceinline__ void gram_store(T (&acc)[VEC][S], int s, T* partial_blk, T* sh /* [NW][S*S] */) {
+__device__ __forceinline__ void gram_store(T (&acc)[VEC][S], int s, T* partial, T* sh /* [NW][S*S] */) {
   constexpr int LPR = S / VEC;
   constexpr int NW = kBlock / kWave;
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
@@ -127,13 +131,75 @@ __device__ __forceinline__ void gram_store(T (&acc)[VEC][S], int s, T* partial_b
       for (int b = 0; b < S; ++b) sh[wave * S * S + (c * VEC + a) * S + b] = acc[a][b];
   }
   __syncthreads();
+  T* pblk = partial + ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * s * s;
   for (int t = threadIdx.x; t < s * s; t += kBlock) {
     int a = t / s, b = t % s;
     T sum = T(0);
 #pragma unroll
     for (int w = 0; w < NW; ++w) sum += sh[w * S * S + a * S + b];
-    partial_blk[t] = sum;
+    pblk[t] = sum;
   }
+}
+
+// ------------------------------------------------------------ reduction --
+// grid (ns, batch): workgroup (sl, y) sums partials [b0, b1) of slice y in
+// block order into red.gpart[y][sl]; the last workgroup of slice y to finish
+// adds the ns slice sums in order into red.G[y].  Only ns <= 16 workgroups
+// take part, so the device-scope fences of the hand-off are cheap.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void reduce_kernel(int ss, const T* __restrict__ partial, int nblk, Red red,
+                                                         const int32_t* gate, const int32_t* fire) {
+  __shared__ double sh[kBlock];
+  __shared__ int last;
+  if ((gate && *gate) || (fire && !*fire)) return;
+  const int ns = gridDim.x, sl = blockIdx.x, y = blockIdx.y;
+  const T* P = partial + (int64_t)y * nblk * ss;
+  const int b0 = (int)((int64_t)nblk * sl / ns), b1 = (int)((int64_t)nblk * (sl + 1) / ns);
+  double* slices = red.gpart + (int64_t)y * ns * ss;
+  const int EB = ss < kBlock ? ss : kBlock;  // entries per pass
+  const int SUB = kBlock / EB;                // sub-slices per entry
+  const int t = threadIdx.x, te = t % EB, sub = t / EB;
+  for (int base = 0; base < ss; base += EB) {
+    const int e = base + te;
+    double acc = 0.0;
+    if (sub < SUB && e < ss)
+      for (int b = b0 + sub; b < b1; b += SUB) acc += (double)P[(int64_t)b * ss + e];
+    sh[t] = acc;
+    __syncthreads();
+    if (t < EB && e < ss) {
+      double v = 0.0;
+      for (int k = 0; k < SUB; ++k) v += sh[k * EB + t];
+      slices[(int64_t)sl * ss + e] = v;
+    }
+    __syncthreads();
+  }
+  uint32_t* cnt = red.cnt + (int64_t)y * kCntStride;
+  __threadfence();
+  __syncthreads();
+  if (t == 0) last = (atomicAdd(cnt, 1u) == (uint32_t)(ns - 1));
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  double* G = red.G + (int64_t)y * ss;
+  for (int e = t; e < ss; e += kBlock) {
+    double v = 0.0;
+    for (int k = 0; k < ns; ++k) v += slices[(int64_t)k * ss + e];
+    G[e] = v;
+  }
+  if (t == 0) *cnt = 0;
+}
+
+static hipError_t launch_reduce(int s, const void* partial, bool f32, int nblk, int batch, Red red,
+                                const int32_t* gate, const int32_t* fire, hipStream_t st) {
+  const int ns = nblk < 16 ? nblk : 16;
+  dim3 grid(ns, batch);
+  if (f32)
+    hipLaunchKernelGGL(reduce_kernel<float>, grid, dim3(kBlock), 0, st, s * s, static_cast<const float*>(partial),
+                       nblk, red, gate, fire);
+  else
+    hipLaunchKernelGGL(reduce_kernel<double>, grid, dim3(kBlock), 0, st, s * s,
+                       static_cast<const double*>(partial), nblk, red, gate, fire);
+  return hipGetLastError();
 }
 
 // ------------------------------------------------------------------ SpMM --
@@ -212,13 +278,13 @@ __global__ __launch_bounds__(kBlock) void spmm_kernel(int64_t n, int64_t nnz, co
     }
   }
   if (badidx && bad) *bad = 1;
-  if constexpr (MODE != 0) gram_store<T, S, VEC>(gacc, s, partial + (int64_t)blockIdx.x * s * s, sh);
+  if constexpr (MODE != 0) gram_store<T, S, VEC>(gacc, s, partial, sh);
 }
 
 template <typename T>
 hipError_t launch_spmm(const CsrView& A, int s, const T* X, T* Y, const T* B, int mode, T* partial, int nblk,
-                       int32_t* bad, const int32_t* done, hipStream_t st) {
-  return dispatch_s<T>(s, [&](auto S_, auto V_) -> hipError_t {
+                       Red red, int32_t* bad, const int32_t* done, hipStream_t st) {
+  hipError_t e = dispatch_s<T>(s, [&](auto S_, auto V_) -> hipError_t {
     constexpr int S = decltype(S_)::value, V = decltype(V_)::value;
     const T* val = static_cast<const T*>(A.val);
     if (mode == 0)
@@ -232,6 +298,8 @@ hipError_t launch_spmm(const CsrView& A, int s, const T* X, T* Y, const T* B, in
                          A.colind, val, s, X, Y, B, partial, bad, done);
     return hipGetLastError();
   });
+  if (e != hipSuccess || mode == 0) return e;
+  return launch_reduce(s, partial, sizeof(T) == 4, nblk, 1, red, done, nullptr, st);
 }
 
 // ------------------------------------------------------------------ Gram --
@@ -264,63 +332,21 @@ __global__ __launch_bounds__(kBlock) void gram_kernel(int64_t n, int s, const T*
     vec_t<T, VEC> y = rv ? load_vec<T, VEC>(Y + row * s + col0) : zero_vec<T, VEC>();
     gram_row<T, S, VEC>(gacc, x, y, lane);
   }
-  gram_store<T, S, VEC>(gacc, s, partial + ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * s * s, sh);
+  gram_store<T, S, VEC>(gacc, s, partial, sh);
 }
 
 template <typename T>
-hipError_t launch_gram_batched(int64_t n, int s, const T* X, int nx, const T* Y, T* partial, int nblk,
-                               const int32_t* done, hipStream_t st, const int32_t* fire) {
+hipError_t launch_gram(int64_t n, int s, const T* X, int nx, const T* Y, T* partial, int nblk, Red red,
+                       const int32_t* done, hipStream_t st, const int32_t* fire) {
   if (nx <= 0) return hipSuccess;
-  return dispatch_s<T>(s, [&](auto S_, auto V_) -> hipError_t {
+  if (nx > kMaxBatch) return hipErrorInvalidValue;
+  hipError_t e = dispatch_s<T>(s, [&](auto S_, auto V_) -> hipError_t {
     constexpr int S = decltype(S_)::value, V = decltype(V_)::value;
-    hipLaunchKernelGGL((gram_kernel<T, S, V>), dim3(nblk, nx), dim3(kBlock), 0, st, n, s, X, Y, partial, done,
-                       fire);
+    hipLaunchKernelGGL((gram_kernel<T, S, V>), dim3(nblk, nx), dim3(kBlock), 0, st, n, s, X, Y, partial, done, fire);
     return hipGetLastError();
   });
-}
-
-template <typename T>
-hipError_t launch_gram(int64_t n, int s, const T* X, const T* Y, T* partial, int nblk, const int32_t* done,
-                       hipStream_t st, const int32_t* fire) {
-  return launch_gram_batched<T>(n, s, X, 1, Y, partial, nblk, done, st, fire);
-}
-
-// -------------------------------------------------------- reduce partials --
-// grid.x covers the s*s entries in chunks of 64, grid.y the batch; the 4
-// wavefronts each sum every 4th partial, then the 4 sums are added in order.
-template <typename T>
-__global__ __launch_bounds__(kBlock) void reduce_kernel(int s, const T* __restrict__ partial, int nblk,
-                                                         double* __restrict__ G, const int32_t* gate,
-                                                         const int32_t* fire) {
-  __shared__ double sh[kBlock];
-  if ((gate && *gate) || (fire && !*fire)) return;
-  const int ss = s * s;
-  const int e = blockIdx.x * 64 + (threadIdx.x & 63);
-  const int slice = threadIdx.x / 64;
-  const T* P = partial + (int64_t)blockIdx.y * nblk * ss;
-  double acc = 0.0;
-  if (e < ss)
-    for (int b = slice; b < nblk; b += 4) acc += (double)P[(int64_t)b * ss + e];
-  sh[threadIdx.x] = acc;
-  __syncthreads();
-  if (threadIdx.x < 64 && e < ss)
-    G[(int64_t)blockIdx.y * ss + e] = ((sh[threadIdx.x] + sh[threadIdx.x + 64]) + sh[threadIdx.x + 128]) +
-                                      sh[threadIdx.x + 192];
-}
-
-template <typename T>
-hipError_t launch_reduce_batched(int s, const T* partial, int nblk, int batch, double* G, const int32_t* gate,
-                                 hipStream_t st, const int32_t* fire) {
-  if (batch <= 0) return hipSuccess;
-  dim3 grid((s * s + 63) / 64, batch);
-  hipLaunchKernelGGL(reduce_kernel<T>, grid, dim3(kBlock), 0, st, s, partial, nblk, G, gate, fire);
-  return hipGetLastError();
-}
-
-template <typename T>
-hipError_t launch_reduce_partials(int s, const T* partial, int nblk, double* G, const int32_t* gate,
-                                  hipStream_t st, const int32_t* fire) {
-  return launch_reduce_batched<T>(s, partial, nblk, 1, G, gate, st, fire);
+  if (e != hipSuccess) return e;
+  return launch_reduce(s, partial, sizeof(T) == 4, nblk, nx, red, done, fire, st);
 }
 
 // ---------------------------------------------------------- CG updates --
@@ -354,7 +380,7 @@ __global__ __launch_bounds__(kBlock) void cg_update_kernel(int64_t n, int s, T* 
   constexpr int RPB = NW * L::RPW;
   __shared__ T lam[S * S];
   __shared__ T sh[NW * S * S];
-  if (ctl->done) return;
+  if (ctl->gate) return;
   load_coeff<T, S>(lam, ctl_mat<T>(ctl, 0), s);
   __syncthreads();
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
@@ -381,17 +407,19 @@ __global__ __launch_bounds__(kBlock) void cg_update_kernel(int64_t n, int s, T* 
     if (rv) store_vec<T, VEC>(R + row * s + col0, out);
     gram_row<T, S, VEC>(gacc, out, out, lane);
   }
-  gram_store<T, S, VEC>(gacc, s, partial + (int64_t)blockIdx.x * s * s, sh);
+  gram_store<T, S, VEC>(gacc, s, partial, sh);
 }
 
 template <typename T>
-hipError_t launch_cg_update(int64_t n, int s, T* R, const T* Q, const CgCtl* ctl, T* partial, int nblk,
+hipError_t launch_cg_update(int64_t n, int s, T* R, const T* Q, const CgCtl* ctl, T* partial, int nblk, Red red,
                             hipStream_t st) {
-  return dispatch_s<T>(s, [&](auto S_, auto V_) -> hipError_t {
+  hipError_t e = dispatch_s<T>(s, [&](auto S_, auto V_) -> hipError_t {
     constexpr int S = decltype(S_)::value, V = decltype(V_)::value;
     hipLaunchKernelGGL((cg_update_kernel<T, S, V>), dim3(nblk), dim3(kBlock), 0, st, n, s, R, Q, ctl, partial);
     return hipGetLastError();
   });
+  if (e != hipSuccess) return e;
+  return launch_reduce(s, partial, sizeof(T) == 4, nblk, 1, red, &ctl->gate, nullptr, st);
 }
 
 // X += P (lambda sigma); unless the solve has ended: P = R + P beta.
@@ -404,7 +432,7 @@ __global__ __launch_bounds__(kBlock) void cg_pupdate_kernel(int64_t n, int s, T*
   constexpr int RPB = NW * L::RPW;
   __shared__ T ls[S * S];
   __shared__ T bt[S * S];
-  if (!ctl->x_pending) return;
+  if (!ctl->x_pending || ctl->suspended) return;
   const bool pdir = !ctl->done;
   load_coeff<T, S>(ls, ctl_mat<T>(ctl, 1), s);
   load_coeff<T, S>(bt, ctl_mat<T>(ctl, 2), s);
@@ -638,17 +666,11 @@ hipError_t launch_cast_f32(int64_t count, const double* in, float* out, hipStrea
 
 // ------------------------------------------------------ instantiations --
 #define BKRY_INST(T)                                                                                              \
-  template hipError_t launch_spmm<T>(const CsrView&, int, const T*, T*, const T*, int, T*, int, int32_t*,          \
+  template hipError_t launch_spmm<T>(const CsrView&, int, const T*, T*, const T*, int, T*, int, Red, int32_t*,     \
                                      const int32_t*, hipStream_t);                                                 \
-  template hipError_t launch_gram<T>(int64_t, int, const T*, const T*, T*, int, const int32_t*, hipStream_t,       \
-                                     const int32_t*);                                                              \
-  template hipError_t launch_gram_batched<T>(int64_t, int, const T*, int, const T*, T*, int, const int32_t*,       \
-                                             hipStream_t, const int32_t*);                                         \
-  template hipError_t launch_reduce_partials<T>(int, const T*, int, double*, const int32_t*, hipStream_t,          \
-                                                const int32_t*);                                                   \
-  template hipError_t launch_reduce_batched<T>(int, const T*, int, int, double*, const int32_t*, hipStream_t,      \
-                                               const int32_t*);                                                    \
-  template hipError_t launch_cg_update<T>(int64_t, int, T*, const T*, const CgCtl*, T*, int, hipStream_t);         \
+  template hipError_t launch_gram<T>(int64_t, int, const T*, int, const T*, T*, int, Red, const int32_t*,          \
+                                     hipStream_t, const int32_t*);                                                 \
+  template hipError_t launch_cg_update<T>(int64_t, int, T*, const T*, const CgCtl*, T*, int, Red, hipStream_t);    \
   template hipError_t launch_cg_pupdate<T>(int64_t, int, T*, T*, const T*, const CgCtl*, hipStream_t);             \
   template hipError_t launch_block_combine<T>(int64_t, int, const T*, int, const double*, double, T*,               \
                                               const int32_t*, hipStream_t);                                        \

@@ -1,8 +1,9 @@
 // kernels_small.hip -- the p x p coefficient algebra, on the device, FP64.
 //
-// One workgroup of 256 threads works on matrices in LDS (p <= 32).  Keeping
-// this on the device lets a whole block CG iteration (or GMRes step) be
-// enqueued without a host round trip; the host reads back only a few flags.
+// One workgroup of one wavefront (64 threads) works on matrices in LDS
+// (p <= 32); with a single wavefront the workgroup barriers are nearly free.
+// Keeping this on the device lets a whole block CG iteration (or GMRes step)
+// be enqueued without a host round trip; the host reads back only a few flags.
 //
 //   cg_init / cg_alpha / cg_rho / cg_reortho_fin   the coefficient steps of
 //       the adaptive block CG (Algorithm "BCG Method with Adaptive Residual
@@ -25,10 +26,24 @@
 
 namespace bkry {
 
-constexpr int kSB = 256;        // threads of the small-algebra workgroups
+constexpr int kSB = 64;         // threads of the small-algebra workgroups (one wavefront)
 constexpr int kSS = kMaxS * kMaxS;
 
 __device__ __forceinline__ int tid() { return threadIdx.x; }
+
+// Reductions over the workgroup's single wavefront (every lane receives the
+// result; fixed butterfly order).
+__device__ __forceinline__ double wsum(double v) {
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) v += __shfl_xor(v, d);
+  return v;
+}
+__device__ __forceinline__ double wmax(double v) {
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) v = fmax(v, __shfl_xor(v, d));
+  return v;
+}
+__device__ __forceinline__ bool wany(bool b) { return __any(b ? 1 : 0) != 0; }
 
 __device__ void sm_copy(double* dst, const double* src, int count) {
   for (int t = tid(); t < count; t += kSB) dst[t] = src[t];
@@ -44,13 +59,10 @@ __device__ void sm_project(double* M, const Sub& sub, double* scratch1) {
   const int s = sub.s;
   __syncthreads();
   if (sub.kind == GLOBAL) {
-    if (tid() == 0) {
-      double tr = 0.0;
-      for (int a = 0; a < s; ++a) tr += M[a * s + a];
-      scratch1[0] = tr / (double)s;
-    }
+    double d = 0.0;
+    for (int a = tid(); a < s; a += kSB) d += M[a * s + a];
+    const double v = wsum(d) / (double)s;
     __syncthreads();
-    const double v = scratch1[0];
     for (int t = tid(); t < s * s; t += kSB) M[t] = (t / s == t % s) ? v : 0.0;
   } else {
     for (int t = tid(); t < s * s; t += kSB)
@@ -203,15 +215,40 @@ __device__ double sm_kappaD(const double* A, int s, double* M, double* T, double
   return red[2];
 }
 
-// Re-orthonormalisation test: fire iff eta * kappa_D * sqrt(eps) > 1
+// Re-orthonormalisation test: fire iff eta * kappa_D(alpha) * sqrt(eps) > 1
 // (eta = 0 never, eta = infinity always); kappa_D equals 1 for the diagonal
-// subalgebras.
-__device__ bool reortho_test(const CgCtl* c, const double* alpha, double* M, double* T, double* rc, double* rs,
-                             int* partner, int* first, double* red) {
+// subalgebras.  L is the Cholesky factor of alpha.  Before the eigenvalues,
+// an exact upper bound is tried: with M = D^-1/2 alpha D^-1/2 = L_M L_M^T,
+// kappa_D = |M|_2 |M^-1|_2 <= |M|_F |L_M^-1|_F^2; when even the bound does not
+// fire, the test does not fire (same decision as with kappa_D itself).
+__device__ bool reortho_test(CgCtl* c, const double* alpha, const double* L, double* M, double* T, double* rc,
+                             double* rs, int* partner, int* first, double* red) {
   if (!(c->eta > 0.0)) return false;
   if (isinf(c->eta)) return true;
-  double kd = 1.0;
-  if (c->g > 1) kd = sm_kappaD(alpha, c->s, M, T, rc, rs, partner, first, red);
+  const int s = c->s;
+  if (c->eta * c->sqrt_eps > 1.0) return true;  // kappa_D >= 1
+  if (c->g <= 1) return false;                  // kappa_D = 1
+  __syncthreads();
+  const int col = tid();
+  if (col < s) {  // column col of L^-1
+    for (int i = 0; i < s; ++i) {
+      double sum = (i == col) ? 1.0 : 0.0;
+      for (int k = 0; k < i; ++k) sum -= L[i * s + k] * T[k * s + col];
+      T[i * s + col] = sum / L[i * s + i];
+    }
+  }
+  __syncthreads();
+  double fm = 0.0, li = 0.0;
+  for (int e = tid(); e < s * s; e += kSB) {
+    const int i = e / s, j = e % s;
+    const double a = alpha[e];
+    fm += a * a / (alpha[i * s + i] * alpha[j * s + j]);
+    li += T[e] * T[e] * alpha[j * s + j];
+  }
+  const double bound = sqrt(wsum(fm)) * wsum(li);
+  if (isfinite(bound) && bound * (1.0 + 1e-12) * c->eta * c->sqrt_eps <= 1.0) return false;
+  const double kd = sm_kappaD(alpha, s, M, T, rc, rs, partner, first, red);
+  if (tid() == 0) c->kd_jacobi += 1;
   return c->eta * kd * c->sqrt_eps > 1.0;
 }
 
@@ -223,14 +260,11 @@ __device__ void store_coeff(double* d64, float* d32, const double* src, int s) {
 }
 
 __device__ bool all_finite(const double* M, int count, double* red) {
+  (void)red;
   __syncthreads();
-  if (tid() == 0) {
-    int ok = 1;
-    for (int t = 0; t < count; ++t) ok &= isfinite(M[t]) ? 1 : 0;
-    red[0] = ok;
-  }
-  __syncthreads();
-  return red[0] != 0.0;
+  bool bad = false;
+  for (int t = tid(); t < count; t += kSB) bad |= !isfinite(M[t]);
+  return !wany(bad);
 }
 
 // ------------------------------------------------------------ projection --
@@ -279,6 +313,9 @@ __global__ __launch_bounds__(kSB) void cg_init_kernel(CgCtl* c, const double* G_
       c->x_pending = 0;
       c->converged = allzero;
       c->done = allzero;
+      c->gate = allzero;
+      c->suspended = 0;
+      c->kd_jacobi = 0;
       c->nreorth = (c->eta > 0.0 && !allzero) ? 1 : 0;
       c->bad_index = 0;
     }
@@ -294,6 +331,7 @@ __global__ __launch_bounds__(kSB) void cg_init_kernel(CgCtl* c, const double* G_
       if (tid() == 0) {
         c->status = -3;
         c->done = 1;
+        c->gate = 1;
       }
       return;
     }
@@ -315,6 +353,7 @@ __global__ __launch_bounds__(kSB) void cg_alpha_kernel(CgCtl* c, const double* G
     if (tid() == 0) c->x_pending = 0;
     return;
   }
+  if (c->gate) return;  // suspended: this iteration waits for its re-normalisation
   const int s = c->s;
   const Sub sub{c->kind, s, c->g};
   sm_copy(Al, G, s * s);
@@ -324,6 +363,7 @@ __global__ __launch_bounds__(kSB) void cg_alpha_kernel(CgCtl* c, const double* G
     if (tid() == 0) {
       c->status = -3;
       c->done = 1;
+      c->gate = 1;
       c->x_pending = 0;
     }
     return;
@@ -335,6 +375,7 @@ __global__ __launch_bounds__(kSB) void cg_alpha_kernel(CgCtl* c, const double* G
     if (tid() == 0) {
       c->status = -2;
       c->done = 1;
+      c->gate = 1;
       c->x_pending = 0;
     }
     return;
@@ -345,7 +386,7 @@ __global__ __launch_bounds__(kSB) void cg_alpha_kernel(CgCtl* c, const double* G
   store_coeff(c->lam, c->lam_f, Lm, s);
   store_coeff(c->lamsig, c->lamsig_f, T, s);
   sm_copy(c->alpha, Al, s * s);
-  const bool fire = reortho_test(c, Al, W, T, rc, rs, partner, first, red);
+  const bool fire = reortho_test(c, Al, L, W, T, rc, rs, partner, first, red);
   __syncthreads();
   if (tid() == 0) {
     c->fire = fire ? 1 : 0;
@@ -365,24 +406,27 @@ __global__ __launch_bounds__(kSB) void cg_rho_kernel(CgCtl* c, const double* G, 
   __shared__ double Gm[kSS], Sg[kSS], T1[kSS], L[kSS], Bt[kSS];
   __shared__ double red[4];
   __shared__ int flag[2];
-  if (c->done) return;
+  if (c->gate) return;
   const int s = c->s;
   const Sub sub{c->kind, s, c->g};
   sm_copy(Gm, G, s * s);
   sm_copy(Sg, c->sigma, s * s);
   sm_mm(T1, Gm, Sg, s, false);  // G sigma
+  // column norms of R~ sigma: sqrt(diag(sigma^T G sigma)), one lane per column
+  double rel = 0.0;
+  bool nanl = false;
+  for (int i = tid(); i < s; i += kSB) {
+    double acc = 0.0;
+    for (int a = 0; a < s; ++a) acc += Sg[a * s + i] * T1[a * s + i];
+    const double cn = sqrt(fmax(acc, 0.0));
+    const double r = c->r0n[i] > 0.0 ? cn / c->r0n[i] : 0.0;
+    nanl |= !isfinite(acc);
+    c->relres[i] = r;
+    rel = fmax(rel, r);
+  }
+  const double m = wmax(rel);
+  const bool nan = wany(nanl);
   if (tid() == 0) {
-    double m = 0.0;
-    bool nan = false;
-    for (int i = 0; i < s; ++i) {
-      double acc = 0.0;
-      for (int a = 0; a < s; ++a) acc += Sg[a * s + i] * T1[a * s + i];
-      const double cn = sqrt(fmax(acc, 0.0));
-      const double rel = c->r0n[i] > 0.0 ? cn / c->r0n[i] : 0.0;
-      if (!isfinite(acc)) nan = true;
-      c->relres[i] = rel;
-      m = fmax(m, rel);
-    }
     const int it = c->iters;
     if (hist && it < c->hist_cap) hist[it] = nan ? NAN : m;
     c->iters = it + 1;
@@ -398,6 +442,10 @@ __global__ __launch_bounds__(kSB) void cg_rho_kernel(CgCtl* c, const double* G, 
       state = 1;
     }
     c->done = state;
+    // a dynamically decided re-normalisation suspends the iteration; the host
+    // launches it at its next read-back
+    c->suspended = (!state && c->fire && c->dynamic) ? 1 : 0;
+    c->gate = state | c->suspended;
     flag[0] = state;
   }
   __syncthreads();
@@ -410,6 +458,7 @@ __global__ __launch_bounds__(kSB) void cg_rho_kernel(CgCtl* c, const double* G, 
     if (tid() == 0) {
       c->status = -2;
       c->done = 1;
+      c->gate = 1;
     }
     return;
   }
@@ -445,12 +494,19 @@ __global__ __launch_bounds__(kSB) void cg_reortho_fin_kernel(CgCtl* c, const dou
     if (tid() == 0) {
       c->status = -2;
       c->done = 1;
+      c->gate = 1;
+      c->suspended = 0;  // the X update of this iteration still runs
     }
     return;
   }
   sm_chol_solve(L, T1, Bt, s);
   store_coeff(c->beta, c->beta_f, Bt, s);
   sm_copy(c->rho, Gm, s * s);
+  __syncthreads();
+  if (tid() == 0) {
+    c->suspended = 0;
+    c->gate = c->done;
+  }
 }
 
 hipError_t launch_cg_reortho_fin(CgCtl* ctl, const double* G, hipStream_t st) {

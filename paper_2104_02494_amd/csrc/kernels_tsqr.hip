@@ -325,7 +325,7 @@ template <typename T>
 size_t norms_ws(int64_t n, const Sub& sub) {
   const int nblk = stream_grid(n, sub.s, sizeof(T));
   return align256(sizeof(T) * (size_t)nblk * sub.s * sub.s) + align256(sizeof(double) * sub.s * sub.s) +
-         align256(sizeof(double) * sub.s);
+         align256(sizeof(double) * sub.s) + align256(sizeof(double) * red_gpart_count(nblk, sub.s));
 }
 
 }  // namespace
@@ -337,19 +337,22 @@ size_t tsqr_workspace_bytes(int64_t n, Sub sub) {
 }
 
 template <typename T>
-hipError_t tsqr_run(int64_t n, Sub sub, T* X, double* N, void* ws, const int32_t* gd, const int32_t* gf,
-                    hipStream_t st) {
+hipError_t tsqr_run(int64_t n, Sub sub, T* X, double* N, void* ws, uint32_t* cnt, const int32_t* gd,
+                    const int32_t* gf, hipStream_t st) {
   char* w = static_cast<char*>(ws);
   const int s = sub.s;
   if (uses_norms(sub)) {
     const int nblk = stream_grid(n, s, sizeof(T));
     T* part = reinterpret_cast<T*>(w);
-    double* G = reinterpret_cast<double*>(w + align256(sizeof(T) * (size_t)nblk * s * s));
-    double* d = G + align256(sizeof(double) * s * s) / sizeof(double);
+    w += align256(sizeof(T) * (size_t)nblk * s * s);
+    double* G = reinterpret_cast<double*>(w);
+    w += align256(sizeof(double) * s * s);
+    double* d = reinterpret_cast<double*>(w);
+    w += align256(sizeof(double) * s);
+    double* gpart = reinterpret_cast<double*>(w);
     Sub ns = sub;
     if (ns.kind == HYBRID) ns.kind = PARALLEL;
-    hipError_t e = launch_gram<T>(n, s, X, X, part, nblk, gd, st, gf);
-    if (e == hipSuccess) e = launch_reduce_partials<T>(s, part, nblk, G, gd, st, gf);
+    hipError_t e = launch_gram<T>(n, s, X, 1, X, part, nblk, Red{G, gpart, cnt}, gd, st, gf);
     if (e == hipSuccess) e = launch_norm_diag(G, ns, d, N, gd, gf, st);
     if (e == hipSuccess) e = launch_colscale<T>(n, s, X, X, d, ns.kind == GLOBAL, gd, gf, st);
     return e;
@@ -377,9 +380,9 @@ hipError_t tsqr_run(int64_t n, Sub sub, T* X, double* N, void* ws, const int32_t
   });
 }
 
-template hipError_t tsqr_run<double>(int64_t, Sub, double*, double*, void*, const int32_t*, const int32_t*,
-                                     hipStream_t);
-template hipError_t tsqr_run<float>(int64_t, Sub, float*, double*, void*, const int32_t*, const int32_t*,
-                                    hipStream_t);
+template hipError_t tsqr_run<double>(int64_t, Sub, double*, double*, void*, uint32_t*, const int32_t*,
+                                     const int32_t*, hipStream_t);
+template hipError_t tsqr_run<float>(int64_t, Sub, float*, double*, void*, uint32_t*, const int32_t*,
+                                    const int32_t*, hipStream_t);
 
 }  // namespace bkry

@@ -68,20 +68,35 @@ struct ProfScope {
 
 // ---------------------------------------------------------------- block CG --
 template <typename T>
-CgBufs<T> carve_cg(Carver& c, int64_t n, Sub sub, int hist_cap) {
+CgBufs<T> carve_cg(Carver& c, int64_t n, Sub sub, int hist_cap, uint32_t* cnt) {
   const int s = sub.s;
+  const int nblk = stream_grid(n, s, sizeof(T));
   CgBufs<T> b;
   b.P = c.take<T>((size_t)n * s);
   b.Q = c.take<T>((size_t)n * s);
   b.R = c.take<T>((size_t)n * s);
-  b.partial = c.take<T>((size_t)stream_grid(n, s, sizeof(T)) * s * s);
+  b.partial = c.take<T>((size_t)nblk * s * s);
+  b.gpart = c.take<double>(red_gpart_count(nblk, s));
   b.Ga = c.take<double>((size_t)s * s);
   b.Gr = c.take<double>((size_t)s * s);
   b.Gq = c.take<double>((size_t)s * s);
   b.hist = c.take<double>((size_t)(hist_cap > 0 ? hist_cap : 1));
   b.ctl = c.take<CgCtl>(1);
   b.tsqr_ws = c.take<char>(tsqr_workspace_bytes(n, sub));
+  b.cnt = cnt;
   return b;
+}
+
+// Re-normalisation of the residual (R-bar, gamma) = Norm_S(R~), then
+// sigma = gamma sigma, rho' and beta (cg_reortho_fin); runs only while the
+// solve is live and the re-orthonormalisation test fired.
+template <typename T>
+static hipError_t cg_normalise(int64_t n, Sub sub, const CgBufs<T>& b, int nblk, hipStream_t st, Prof* prof) {
+  CgCtl* c = b.ctl;
+  ProfScope ps(prof, PROF_CG_NORMALISE, st);
+  BK_TRY(tsqr_run<T>(n, sub, b.R, c->gamma, b.tsqr_ws, b.cnt, &c->done, &c->fire, st));
+  BK_TRY(launch_gram<T>(n, sub.s, b.R, 1, b.R, b.partial, nblk, Red{b.Gq, b.gpart, b.cnt}, &c->done, st, &c->fire));
+  return launch_cg_reortho_fin(c, b.Gq, st);
 }
 
 template <typename T>
@@ -92,85 +107,91 @@ hipError_t cg_run(const CsrView& A, Sub sub, const T* B, T* X, double tol, int m
   const int nblk = stream_grid(n, s, sizeof(T));
   CgCtl* c = b.ctl;
   int32_t* done = &c->done;
+  int32_t* gate = &c->gate;
+  const Red ra{b.Ga, b.gpart, b.cnt}, rr{b.Gr, b.gpart, b.cnt};
+
+  // The test eta kappa_D sqrt(eps) > 1 never fires for eta = 0 and always
+  // fires for eta = inf or eta sqrt(eps) > 1 (kappa_D >= 1); for the diagonal
+  // subalgebras kappa_D = 1.  Only the remaining cases are decided per
+  // iteration on the device.
+  const bool always = eta > 0.0 && (isinf(eta) || eta * sqrt(eps) > 1.0);
+  const bool dynamic = eta > 0.0 && !always && sub.g > 1;
 
   // control header, staged through pinned memory
   CgCtl* h = reinterpret_cast<CgCtl*>(hflags + 64);
-  static_assert(offsetof(CgCtl, r0n) <= 256 * sizeof(int32_t) - 64 * sizeof(int32_t), "header too large");
+  static_assert(offsetof(CgCtl, r0n) <= (kHostFlagsInts - 64) * sizeof(int32_t), "header too large");
   memset(h, 0, offsetof(CgCtl, r0n));
   h->maxit = maxit;
   h->s = s;
   h->kind = sub.kind;
   h->g = sub.g;
   h->hist_cap = hist_cap;
+  h->dynamic = dynamic ? 1 : 0;
   h->tol = tol;
   h->eta = eta;
   h->sqrt_eps = sqrt(eps);
   BK_TRY(hipMemcpyAsync(c, h, offsetof(CgCtl, r0n), hipMemcpyHostToDevice, st));
 
   // R0 = B - A X0 with its Gram matrix; initial normalisation; P = R; rho.
-  BK_TRY(launch_spmm<T>(A, s, X, b.R, B, 2, b.partial, nblk, &c->bad_index, nullptr, st));
-  BK_TRY(launch_reduce_partials<T>(s, b.partial, nblk, b.Ga, nullptr, st));
+  BK_TRY(launch_spmm<T>(A, s, X, b.R, B, 2, b.partial, nblk, ra, &c->bad_index, nullptr, st));
   BK_TRY(launch_cg_init(c, b.Ga, nullptr, st));
-  if (eta > 0.0) BK_TRY(tsqr_run<T>(n, sub, b.R, c->sigma, b.tsqr_ws, done, nullptr, st));
-  BK_TRY(launch_gram<T>(n, s, b.R, b.R, b.partial, nblk, done, st));
-  BK_TRY(launch_reduce_partials<T>(s, b.partial, nblk, b.Gr, done, st));
+  if (eta > 0.0) BK_TRY(tsqr_run<T>(n, sub, b.R, c->sigma, b.tsqr_ws, b.cnt, done, nullptr, st));
+  BK_TRY(launch_gram<T>(n, s, b.R, 1, b.R, b.partial, nblk, rr, done, st));
   BK_TRY(launch_cg_init(c, nullptr, b.Gr, st));
   BK_TRY(hipMemcpyAsync(b.P, b.R, sizeof(T) * (size_t)n * s, hipMemcpyDeviceToDevice, st));
 
-  // Whether the residual can be re-normalised: never for eta = 0; for the
-  // diagonal subalgebras kappa_D = 1, so the test is decided in advance.
-  bool may_fire = eta > 0.0;
-  if (may_fire && sub.g == 1 && !isinf(eta)) may_fire = eta * sqrt(eps) > 1.0;
-
-  int launched = 0, batch = 4;
+  const CgCtl* hc = reinterpret_cast<const CgCtl*>(hflags);
+  int batch = 4, last_iters = -1;
   while (maxit > 0) {
     for (int it = 0; it < batch; ++it) {
       {
         ProfScope ps(prof, PROF_CG_SPMM, st);
-        BK_TRY(launch_spmm<T>(A, s, b.P, b.Q, nullptr, 1, b.partial, nblk, &c->bad_index, done, st));
+        BK_TRY(launch_spmm<T>(A, s, b.P, b.Q, nullptr, 1, b.partial, nblk, ra, &c->bad_index, gate, st));
       }
-      BK_TRY(launch_reduce_partials<T>(s, b.partial, nblk, b.Ga, done, st));
       BK_TRY(launch_cg_alpha(c, b.Ga, st));
       {
         ProfScope ps(prof, PROF_CG_UPDATE, st);
-        BK_TRY(launch_cg_update<T>(n, s, b.R, b.Q, c, b.partial, nblk, st));
+        BK_TRY(launch_cg_update<T>(n, s, b.R, b.Q, c, b.partial, nblk, rr, st));
       }
-      BK_TRY(launch_reduce_partials<T>(s, b.partial, nblk, b.Gr, done, st));
       BK_TRY(launch_cg_rho(c, b.Gr, b.hist, st));
-      if (may_fire) {
-        ProfScope ps(prof, PROF_CG_NORMALISE, st);
-        BK_TRY(tsqr_run<T>(n, sub, b.R, c->gamma, b.tsqr_ws, done, &c->fire, st));
-        BK_TRY(launch_gram<T>(n, s, b.R, b.R, b.partial, nblk, done, st, &c->fire));
-        BK_TRY(launch_reduce_partials<T>(s, b.partial, nblk, b.Gq, done, st, &c->fire));
-        BK_TRY(launch_cg_reortho_fin(c, b.Gq, st));
-      }
+      if (always) BK_TRY(cg_normalise<T>(n, sub, b, nblk, st, prof));
       {
         ProfScope ps(prof, PROF_CG_PUPDATE, st);
         BK_TRY(launch_cg_pupdate<T>(n, s, X, b.P, b.R, c, st));
       }
     }
-    launched += batch;
     BK_TRY(hipMemcpyAsync(hflags, c, kCtlHeaderInts * sizeof(int32_t), hipMemcpyDeviceToHost, st));
     BK_TRY(hipStreamSynchronize(st));
     BK_TRY(prof_flush(prof));
-    if (hflags[0] || launched >= maxit) break;
-    if (batch < 16) batch *= 2;
+    if (hc->done) break;
+    if (hc->suspended) {
+      // the iteration waits for its re-normalisation: run it, finish the
+      // iteration's direction update, continue with short batches
+      BK_TRY(cg_normalise<T>(n, sub, b, nblk, st, prof));
+      {
+        ProfScope ps(prof, PROF_CG_PUPDATE, st);
+        BK_TRY(launch_cg_pupdate<T>(n, s, X, b.P, b.R, c, st));
+      }
+      batch = 2;
+    } else {
+      if (hc->iters == last_iters) break;  // no progress (cannot happen while live)
+      if (batch < 32) batch *= 2;
+    }
+    last_iters = hc->iters;
   }
-  if (maxit <= 0) {
-    BK_TRY(hipMemcpyAsync(hflags, c, kCtlHeaderInts * sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    BK_TRY(hipStreamSynchronize(st));
-  }
-  const CgCtl* hc = reinterpret_cast<const CgCtl*>(hflags);
+  BK_TRY(hipMemcpyAsync(hflags, c, kCtlHeaderInts * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  BK_TRY(hipStreamSynchronize(st));
   res.status = hc->status;
   res.iters = hc->iters;
   res.nreorth = hc->nreorth;
   res.converged = hc->converged;
   res.bad_index = hc->bad_index;
+  res.kd_jacobi = hc->kd_jacobi;
   return hipSuccess;
 }
 
-template CgBufs<double> carve_cg<double>(Carver&, int64_t, Sub, int);
-template CgBufs<float> carve_cg<float>(Carver&, int64_t, Sub, int);
+template CgBufs<double> carve_cg<double>(Carver&, int64_t, Sub, int, uint32_t*);
+template CgBufs<float> carve_cg<float>(Carver&, int64_t, Sub, int, uint32_t*);
 template hipError_t cg_run<double>(const CsrView&, Sub, const double*, double*, double, int, double, double, int,
                                    const CgBufs<double>&, hipStream_t, int32_t*, CgResult&, Prof*);
 template hipError_t cg_run<float>(const CsrView&, Sub, const float*, float*, double, int, double, double, int,
@@ -178,29 +199,31 @@ template hipError_t cg_run<float>(const CsrView&, Sub, const float*, float*, dou
 
 // ------------------------------------------------------ true residuals --
 hipError_t true_relres(const CsrView& A, int s, const double* B, const double* X, double* R, double* partial,
-                       double* G, const double* r0n, double* relres, int32_t* flag, double* scale_scratch,
-                       hipStream_t st) {
+                       double* gpart, uint32_t* cnt, double* G, const double* r0n, double* relres, int32_t* flag,
+                       double* scale_scratch, hipStream_t st) {
   const int nblk = stream_grid(A.n, s, sizeof(double));
-  BK_TRY(launch_spmm<double>(A, s, X, R, B, 2, partial, nblk, nullptr, nullptr, st));
-  BK_TRY(launch_reduce_partials<double>(s, partial, nblk, G, nullptr, st));
+  BK_TRY(launch_spmm<double>(A, s, X, R, B, 2, partial, nblk, Red{G, gpart, cnt}, nullptr, nullptr, st));
   return launch_ir_check(s, G, const_cast<double*>(r0n), scale_scratch, relres, flag, 0.0, 0, st);
 }
 
 // ------------------------------------------------ iterative refinement --
-IrBufs carve_ir(Carver& c, int64_t n, int64_t nnz, Sub sub) {
+IrBufs carve_ir(Carver& c, int64_t n, int64_t nnz, Sub sub, uint32_t* cnt) {
   const int s = sub.s;
+  const int nblk = stream_grid(n, s, sizeof(double));
   IrBufs b;
   b.A32 = c.take<float>((size_t)(nnz > 0 ? nnz : 1));
   b.R32 = c.take<float>((size_t)n * s);
   b.X32 = c.take<float>((size_t)n * s);
   b.R64 = c.take<double>((size_t)n * s);
-  b.partial = c.take<double>((size_t)stream_grid(n, s, sizeof(double)) * s * s);
+  b.partial = c.take<double>((size_t)nblk * s * s);
+  b.gpart = c.take<double>(red_gpart_count(nblk, s));
   b.G = c.take<double>((size_t)s * s);
   b.r0n = c.take<double>(kMaxS);
   b.scale = c.take<double>(kMaxS);
   b.relres = c.take<double>(kMaxS);
   b.flag = c.take<int32_t>(4);
-  b.cg = carve_cg<float>(c, n, sub, 0);
+  b.cnt = cnt;
+  b.cg = carve_cg<float>(c, n, sub, 0, cnt);
   return b;
 }
 
@@ -219,8 +242,8 @@ hipError_t ir_run(const CsrView& A, Sub sub, const double* B, double* X, double 
   int32_t* dflag = b.flag;
   BK_TRY(hipMemsetAsync(dflag, 0, 4 * sizeof(int32_t), st));
   for (int outer = 0;; ++outer) {
-    BK_TRY(launch_spmm<double>(A, s, X, b.R64, B, 2, b.partial, nblk, dflag + 2, nullptr, st));
-    BK_TRY(launch_reduce_partials<double>(s, b.partial, nblk, b.G, nullptr, st));
+    BK_TRY(launch_spmm<double>(A, s, X, b.R64, B, 2, b.partial, nblk, Red{b.G, b.gpart, b.cnt}, dflag + 2, nullptr,
+                               st));
     BK_TRY(launch_ir_check(s, b.G, b.r0n, b.scale, b.relres, dflag, tol, outer == 0, st));
     BK_TRY(hipMemcpyAsync(hflags, dflag, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
     BK_TRY(hipMemcpyAsync(relres_host, b.relres, s * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -260,12 +283,13 @@ hipError_t ir_run(const CsrView& A, Sub sub, const double* B, double* X, double 
 }
 
 // ------------------------------------------------------------ block GMRes --
-GmBufs carve_gm(Carver& c, int64_t n, Sub sub, int m, int hist_cap) {
+GmBufs carve_gm(Carver& c, int64_t n, Sub sub, int m, int hist_cap, uint32_t* cnt) {
   const int s = sub.s, ss = s * s;
   const int nblk = stream_grid(n, s, sizeof(double));
   GmBufs b;
   b.V = c.take<double>((size_t)(m + 1) * n * s);
   b.partial = c.take<double>((size_t)(m + 1) * nblk * ss);
+  b.gpart = c.take<double>((size_t)(m + 1) * red_gpart_count(nblk, s));
   b.Gb = c.take<double>((size_t)(m + 1) * ss);
   b.H1 = c.take<double>((size_t)(m + 1) * ss);
   b.H2 = c.take<double>((size_t)(m + 1) * ss);
@@ -280,6 +304,7 @@ GmBufs carve_gm(Carver& c, int64_t n, Sub sub, int m, int hist_cap) {
   b.flag = c.take<int32_t>(4);
   b.ctl = c.take<GmCtl>(1);
   b.tsqr_ws = c.take<char>(tsqr_workspace_bytes(n, sub));
+  b.cnt = cnt;
   return b;
 }
 
@@ -289,6 +314,7 @@ hipError_t gm_run(const CsrView& A, Sub sub, const double* B, double* X, double 
   const int s = sub.s;
   const size_t blk = (size_t)n * s;
   const int nblk = stream_grid(n, s, sizeof(double));
+  const Red red{b.Gb, b.gpart, b.cnt};
   GmCtl* c = b.ctl;
   int32_t* done = &c->done;
   GmCtl* h = reinterpret_cast<GmCtl*>(hflags + 64);
@@ -303,23 +329,21 @@ hipError_t gm_run(const CsrView& A, Sub sub, const double* B, double* X, double 
   BK_TRY(hipMemcpyAsync(c, h, sizeof(GmCtl), hipMemcpyHostToDevice, st));
   for (int cycle = 0;; ++cycle) {
     // R = B - A X into V_0, its Gram; V_0 sigma_0 = Norm_S(R)
-    BK_TRY(launch_spmm<double>(A, s, X, b.V, B, 2, b.partial, nblk, &c->bad_index, nullptr, st));
-    BK_TRY(launch_reduce_partials<double>(s, b.partial, nblk, b.Gb, nullptr, st));
-    BK_TRY(tsqr_run<double>(n, sub, b.V, b.sigma0, b.tsqr_ws, nullptr, nullptr, st));
+    BK_TRY(launch_spmm<double>(A, s, X, b.V, B, 2, b.partial, nblk, red, &c->bad_index, nullptr, st));
+    BK_TRY(tsqr_run<double>(n, sub, b.V, b.sigma0, b.tsqr_ws, b.cnt, nullptr, nullptr, st));
     BK_TRY(launch_gm_cycle_init(c, b.sig, b.sigma0, b.Gb, cycle == 0, st));
     for (int k = 0; k < m; ++k) {
       double* Vk = b.V + (size_t)k * blk;
       double* W = b.V + (size_t)(k + 1) * blk;
-      BK_TRY(launch_spmm<double>(A, s, Vk, W, nullptr, 0, nullptr, nblk, &c->bad_index, done, st));
+      BK_TRY(launch_spmm<double>(A, s, Vk, W, nullptr, 0, nullptr, nblk, red, &c->bad_index, done, st));
       // classical Gram-Schmidt, twice: H_j = <V_j, W>_S, W -= sum_j V_j H_j
       double* Hp[2] = {b.H1, b.H2};
       for (int pass = 0; pass < 2; ++pass) {
-        BK_TRY(launch_gram_batched<double>(n, s, b.V, k + 1, W, b.partial, nblk, done, st));
-        BK_TRY(launch_reduce_batched<double>(s, b.partial, nblk, k + 1, b.Gb, done, st));
+        BK_TRY(launch_gram<double>(n, s, b.V, k + 1, W, b.partial, nblk, red, done, st));
         BK_TRY(launch_project_batched(b.Gb, Hp[pass], sub, k + 1, done, st));
         BK_TRY(launch_block_combine<double>(n, s, b.V, k + 1, Hp[pass], -1.0, W, done, st));
       }
-      BK_TRY(tsqr_run<double>(n, sub, W, b.gam, b.tsqr_ws, done, nullptr, st));
+      BK_TRY(tsqr_run<double>(n, sub, W, b.gam, b.tsqr_ws, b.cnt, done, nullptr, st));
       BK_TRY(launch_gm_step(c, k, b.H, b.sig, b.Om, b.H1, b.H2, b.gam, b.hist, st));
     }
     BK_TRY(hipMemcpyAsync(hflags, c, 16 * sizeof(int32_t), hipMemcpyDeviceToHost, st));

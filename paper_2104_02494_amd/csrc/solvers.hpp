@@ -35,24 +35,28 @@ void prof_destroy(Prof* p);
 // Accumulates the recorded pairs (the stream must have been synchronised).
 hipError_t prof_flush(Prof* p);
 
-// Pinned host staging area shared by the drivers: [0, 64) ints for read-backs,
-// [64, 128) ints (256 bytes) for uploads.
+// Pinned host staging area shared by the drivers: ints [0, 64) receive
+// read-backs, ints [64, 256) stage uploads.
 constexpr int kHostFlagsInts = 256;
+
+// Zeroed reduction counters owned by the handle (kMaxBatch slices).
+constexpr size_t kCounterInts = (size_t)kMaxBatch * kCntStride;
 
 template <typename T>
 struct CgBufs {
   T *P = nullptr, *Q = nullptr, *R = nullptr, *partial = nullptr;
-  double *Ga = nullptr, *Gr = nullptr, *Gq = nullptr, *hist = nullptr;
+  double *Ga = nullptr, *Gr = nullptr, *Gq = nullptr, *gpart = nullptr, *hist = nullptr;
   CgCtl* ctl = nullptr;
   void* tsqr_ws = nullptr;
+  uint32_t* cnt = nullptr;
 };
 
 template <typename T>
-CgBufs<T> carve_cg(Carver& c, int64_t n, Sub sub, int hist_cap);
+CgBufs<T> carve_cg(Carver& c, int64_t n, Sub sub, int hist_cap, uint32_t* cnt);
 
 struct CgResult {
   int status = 0;  // 0, -2 breakdown, -3 non-finite
-  int iters = 0, nreorth = 0, converged = 0, bad_index = 0;
+  int iters = 0, nreorth = 0, converged = 0, bad_index = 0, kd_jacobi = 0;
 };
 
 // Block CG in element type T (FP64 or FP32 streaming kernels; p x p algebra in
@@ -64,11 +68,13 @@ hipError_t cg_run(const CsrView& A, Sub sub, const T* B, T* X, double tol, int m
 
 struct IrBufs {
   float *A32 = nullptr, *R32 = nullptr, *X32 = nullptr;
-  double *R64 = nullptr, *partial = nullptr, *G = nullptr, *r0n = nullptr, *scale = nullptr, *relres = nullptr;
+  double *R64 = nullptr, *partial = nullptr, *gpart = nullptr, *G = nullptr, *r0n = nullptr, *scale = nullptr;
+  double* relres = nullptr;
   int32_t* flag = nullptr;
+  uint32_t* cnt = nullptr;
   CgBufs<float> cg;
 };
-IrBufs carve_ir(Carver& c, int64_t n, int64_t nnz, Sub sub);
+IrBufs carve_ir(Carver& c, int64_t n, int64_t nnz, Sub sub, uint32_t* cnt);
 
 struct IrResult {
   int status = 0, converged = 0, outer = 0, inner_iters = 0, nreorth = 0, bad_index = 0, hist_len = 0;
@@ -78,13 +84,15 @@ hipError_t ir_run(const CsrView& A, Sub sub, const double* B, double* X, double 
                   int32_t* hflags, double* relres_host, IrResult& res, Prof* prof = nullptr);
 
 struct GmBufs {
-  double *V = nullptr, *partial = nullptr, *Gb = nullptr, *H1 = nullptr, *H2 = nullptr, *H = nullptr, *sig = nullptr;
-  double *Om = nullptr, *zeta = nullptr, *sigma0 = nullptr, *gam = nullptr, *hist = nullptr, *relres = nullptr;
+  double *V = nullptr, *partial = nullptr, *gpart = nullptr, *Gb = nullptr, *H1 = nullptr, *H2 = nullptr;
+  double *H = nullptr, *sig = nullptr, *Om = nullptr, *zeta = nullptr, *sigma0 = nullptr, *gam = nullptr;
+  double *hist = nullptr, *relres = nullptr;
   int32_t* flag = nullptr;
   GmCtl* ctl = nullptr;
   void* tsqr_ws = nullptr;
+  uint32_t* cnt = nullptr;
 };
-GmBufs carve_gm(Carver& c, int64_t n, Sub sub, int m, int hist_cap);
+GmBufs carve_gm(Carver& c, int64_t n, Sub sub, int m, int hist_cap, uint32_t* cnt);
 
 struct GmResult {
   int status = 0, converged = 0, steps = 0, cycles = 0, bad_index = 0;
@@ -93,9 +101,9 @@ hipError_t gm_run(const CsrView& A, Sub sub, const double* B, double* X, double 
                   int hist_cap, const GmBufs& b, hipStream_t st, int32_t* hflags, GmResult& res);
 
 // True relative column residuals |B_i - A X_i| / r0n_i (FP64) into relres
-// (device); uses R (n x s) and partial as scratch.
+// (device); R (n x s), partial, gpart, G and scale_scratch are scratch.
 hipError_t true_relres(const CsrView& A, int s, const double* B, const double* X, double* R, double* partial,
-                       double* G, const double* r0n, double* relres, int32_t* flag, double* scale_scratch,
-                       hipStream_t st);
+                       double* gpart, uint32_t* cnt, double* G, const double* r0n, double* relres, int32_t* flag,
+                       double* scale_scratch, hipStream_t st);
 
 }  // namespace bkry
