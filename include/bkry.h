@@ -110,9 +110,10 @@ const char* bkry_last_error(bkry_handle h);
 /* Kernel timing (measurement support, not part of the method): when enabled,
  * the block CG driver brackets each launch of its streaming kernels with HIP
  * events on the handle's stream and accumulates the elapsed times.  Kernel
- * ids: 0 SpMM fused with the alpha Gram, 1 residual update fused with the
- * Gram of R~, 2 direction update (X and P), 3 whole re-normalisation (TSQR,
- * Gram, coefficients).  bkry_profile_read returns the total milliseconds and
+ * ids: 0 SpMM fused with the alpha Gram partials, 1 residual update fused
+ * with the Gram partials of R~ (for 0 and 1 the Gram reductions and
+ * coefficient steps that follow are not included), 2 direction update
+ * (X and P), 3 whole re-normalisation (TSQR, Gram, coefficients).  bkry_profile_read returns the total milliseconds and
  * the number of timed launches of one kernel id, optionally resetting them. */
 int bkry_profile(bkry_handle h, int enable);
 int bkry_profile_read(bkry_handle h, int32_t kernel, double* total_ms, int64_t* launches, int32_t reset);

@@ -21,7 +21,7 @@ from dataclasses import dataclass
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libbkry.so")
+LIB_PATH = os.environ.get("BKRY_LIB") or os.path.join(_HERE, "libbkry.so")
 
 OK, NOT_CONVERGED, E_INVALID, E_BREAKDOWN, E_NONFINITE, E_HIP, E_ALLOC = 0, 1, -1, -2, -3, -4, -5
 PARALLEL, GLOBAL, BLOCK, HYBRID = 0, 1, 2, 3

@@ -24,9 +24,9 @@ struct Sub {
 };
 
 // Target of the Gram reductions: the producer writes one s x s partial per
-// workgroup; the reduction kernel (<= 16 workgroups per batch slice) writes
-// slice sums to gpart and the final FP64 Gram to G.  cnt holds one zeroed
-// counter per batch slice (left zero).
+// workgroup; the reduction kernel (<= kMaxSlices workgroups per batch slice)
+// writes slice sums to gpart and the final FP64 Gram to G.  cnt holds one
+// zeroed counter per batch slice (left zero).
 struct Red {
   double* G;
   double* gpart;
@@ -34,7 +34,11 @@ struct Red {
 };
 constexpr int kCntStride = 64;    // counters reserved per batch slice
 constexpr int kMaxBatch = 256;    // batch slices of one launch
-inline size_t red_gpart_count(int nblk, int s) { return (size_t)16 * s * s; }
+constexpr int kMaxSlices = 64;    // reduction workgroups per batch slice
+inline size_t red_gpart_count(int nblk, int s) {
+  (void)nblk;
+  return (size_t)kMaxSlices * s * s;
+}
 
 struct CsrView {
   int64_t n, nnz;
@@ -92,6 +96,23 @@ struct GmCtl {
   double r0n[kMaxS];
 };
 
+// Work that the last workgroup of a Gram reduction does once G is complete:
+// nothing, or the coefficient step of block CG that consumes this Gram
+// (EPI_CG_ALPHA after the SpMM, EPI_CG_RHO after the residual update), so
+// that no separate launch is needed.  The CG epilogues gate themselves on
+// the control block (the reduction's gate / fire arguments are then unused).
+enum EpiKind { EPI_NONE = 0, EPI_CG_ALPHA = 1, EPI_CG_RHO = 2 };
+struct Epi {
+  int kind = EPI_NONE;
+  CgCtl* ctl = nullptr;
+  double* hist = nullptr;  // EPI_CG_RHO: per-iteration residual history (device)
+};
+
+// Reduce `batch` slices of nblk partials (T = double or float) into red.G;
+// run only if *gate == 0 and *fire != 0 (null: no condition).
+hipError_t launch_reduce(int s, const void* partial, bool f32, int nblk, int batch, Red red, const int32_t* gate,
+                         const int32_t* fire, Epi epi, hipStream_t st);
+
 // ---------------------------------------------------------------- grids ----
 // Number of workgroups of the streaming block kernels for n rows of width s
 // (a multiple of 8 so that the XCD-contiguous row mapping is a bijection).
@@ -100,9 +121,12 @@ int stream_grid(int64_t n, int s, int elem_bytes);
 // ------------------------------------------------------- block kernels ----
 // SpMM modes: 0 Y = A X; 1 also the Gram X^T Y (X the own rows) into red.G;
 // 2 Y = B - A X and the Gram Y^T Y into red.G.  partial: nblk*s*s of T.
+// ev_after (optional): recorded on st right after the streaming kernel,
+// before its reduction (kernel timing).
 template <typename T>
 hipError_t launch_spmm(const CsrView& A, int s, const T* X, T* Y, const T* B, int mode, T* partial,
-                       int nblk, Red red, int32_t* bad, const int32_t* gate, hipStream_t st);
+                       int nblk, Red red, int32_t* bad, const int32_t* gate, hipStream_t st, Epi epi = Epi{},
+                       hipEvent_t ev_after = nullptr);
 
 // Gram X_j^T Y for X_j = X + j*n*s, j < nx, into red.G + j*s*s (batched:
 // partial, gpart and counters are per slice).  Optional second gate `fire`:
@@ -114,7 +138,7 @@ hipError_t launch_gram(int64_t n, int s, const T* X, int nx, const T* Y, T* part
 // CG residual update R~ = R - Q lambda (in place in R) and the Gram of R~ into red.G.
 template <typename T>
 hipError_t launch_cg_update(int64_t n, int s, T* R, const T* Q, const CgCtl* ctl, T* partial, int nblk, Red red,
-                            hipStream_t st);
+                            hipStream_t st, Epi epi = Epi{}, hipEvent_t ev_after = nullptr);
 
 // CG direction update X += P (lambda sigma); if not done: P = R + P beta.
 template <typename T>
@@ -146,8 +170,6 @@ hipError_t launch_sddmm(const CsrView& A, int s, double alpha, const T* L, const
 // Single-workgroup kernels on the p x p coefficients (FP64).
 hipError_t launch_project(const double* G, double* out, Sub sub, hipStream_t st);
 hipError_t launch_cg_init(CgCtl* ctl, const double* G_R0, const double* G_rho, hipStream_t st);
-hipError_t launch_cg_alpha(CgCtl* ctl, const double* G, hipStream_t st);
-hipError_t launch_cg_rho(CgCtl* ctl, const double* G, double* hist, hipStream_t st);
 hipError_t launch_cg_reortho_fin(CgCtl* ctl, const double* G, hipStream_t st);
 // Normaliser coefficients for parallel / global: from the Gram G of X, write
 // the column divisors d and N (p x p) to `out_N` (gated like the CG kernels).

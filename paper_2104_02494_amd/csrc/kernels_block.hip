@@ -31,18 +31,44 @@ namespace bkry {
 template <int V>
 using IC = std::integral_constant<int, V>;
 
-// Calls f(IC<S>, IC<VEC>) for the block width s: powers of two use 16-byte
-// vectors, other widths run one element per lane in the next power of two.
+// Tuning constants (bytes per lane for width 8, workgroup cap for widths <= 8,
+// non-zeros per SpMM load batch).
+#ifndef BKRY_LANE_BYTES8
+#define BKRY_LANE_BYTES8 16
+#endif
+#ifndef BKRY_CAP8
+#define BKRY_CAP8 1024
+#endif
+#ifndef BKRY_SPMM_LDS
+#define BKRY_SPMM_LDS 0
+#endif
+#ifndef BKRY_NT
+#define BKRY_NT 0
+#endif
+#ifndef BKRY_GANG
+#define BKRY_GANG 1
+#endif
+#ifndef BKRY_NTL
+#define BKRY_NTL 0
+#endif
+#ifndef BKRY_UNROLL
+#define BKRY_UNROLL 8
+#endif
+
+// Calls f(IC<S>, IC<VEC>) for the block width s.  Powers of two move 16 or
+// 32 bytes per lane (32 bytes up to s = 8, where the per-lane Gram
+// accumulators still fit in registers, so that a wavefront keeps more rows
+// in flight); other widths run one element per lane in the next power of two.
 template <typename T, typename F>
 hipError_t dispatch_s(int s, F&& f) {
-  constexpr int vm = 16 / (int)sizeof(T);
+  constexpr int v16 = 16 / (int)sizeof(T), v32 = 32 / (int)sizeof(T);
   switch (s) {
     case 1: return f(IC<1>{}, IC<1>{});
-    case 2: return f(IC<2>{}, IC<(2 < vm ? 2 : vm)>{});
-    case 4: return f(IC<4>{}, IC<(4 < vm ? 4 : vm)>{});
-    case 8: return f(IC<8>{}, IC<vm>{});
-    case 16: return f(IC<16>{}, IC<vm>{});
-    case 32: return f(IC<32>{}, IC<vm>{});
+    case 2: return f(IC<2>{}, IC<2>{});
+    case 4: return f(IC<4>{}, IC<4>{});
+    case 8: return f(IC<8>{}, IC<(BKRY_LANE_BYTES8 == 32 ? (8 < v32 ? 8 : v32) : v16)>{});
+    case 16: return f(IC<16>{}, IC<v16>{});
+    case 32: return f(IC<32>{}, IC<v16>{});
     default: break;
   }
   if (s == 3) return f(IC<4>{}, IC<1>{});
@@ -52,20 +78,45 @@ hipError_t dispatch_s(int s, F&& f) {
   return hipErrorInvalidValue;
 }
 
+// Store of a streaming output; with BKRY_NT the store carries the non-temporal
+// hint (the data is not re-read soon by this kernel).
+template <typename T, int N>
+__device__ __forceinline__ void store_out(T* p, const vec_t<T, N>& x) {
+#if BKRY_NT
+#pragma unroll
+  for (int i = 0; i < N; ++i) __builtin_nontemporal_store(x.v[i], p + i);
+#else
+  store_vec<T, N>(p, x);
+#endif
+}
+
 static int next_pow2(int s) {
   int S = 1;
   while (S < s) S <<= 1;
   return S;
 }
 
+// VEC chosen by dispatch_s for width s and element size (host mirror).
+static int vec_for(int s, int elem_bytes) {
+  const int v16 = 16 / elem_bytes, v32 = 32 / elem_bytes;
+  switch (s) {
+    case 1: return 1;
+    case 2: return 2;
+    case 4: return 4;
+    case 8: return BKRY_LANE_BYTES8 == 32 ? (8 < v32 ? 8 : v32) : v16;
+    case 16:
+    case 32: return v16;
+    default: return 1;
+  }
+}
+
 int stream_grid(int64_t n, int s, int elem_bytes) {
   int S = next_pow2(s);
-  int vm = 16 / elem_bytes;
-  int VEC = (S == s) ? (S < vm ? S : vm) : 1;
+  int VEC = vec_for(s, elem_bytes);
   int LPR = S / VEC;
   int RPB = (kBlock / kWave) * (kWave / LPR);
   int64_t need = (n + RPB - 1) / RPB;
-  int cap = (S <= 16) ? 1024 : 512;
+  int cap = (S <= 8) ? BKRY_CAP8 : (S <= 16 ? 1024 : 512);
   int64_t g = need < cap ? need : cap;
   g = (g + 7) / 8 * 8;
   return (int)(g < 8 ? 8 : g);
@@ -142,66 +193,6 @@ __device__ __forceinline__ void gram_store(T (&acc)[VEC][S], int s, T* partial, 
 }
 
 // ------------------------------------------------------------ reduction --
-// grid (ns, batch): workgroup (sl, y) sums partials [b0, b1) of slice y in
-// block order into red.gpart[y][sl]; the last workgroup of slice y to finish
-// adds the ns slice sums in order into red.G[y].  Only ns <= 16 workgroups
-// take part, so the device-scope fences of the hand-off are cheap.
-template <typename T>
-__global__ __launch_bounds__(kBlock) void reduce_kernel(int ss, const T* __restrict__ partial, int nblk, Red red,
-                                                         const int32_t* gate, const int32_t* fire) {
-  __shared__ double sh[kBlock];
-  __shared__ int last;
-  if ((gate && *gate) || (fire && !*fire)) return;
-  const int ns = gridDim.x, sl = blockIdx.x, y = blockIdx.y;
-  const T* P = partial + (int64_t)y * nblk * ss;
-  const int b0 = (int)((int64_t)nblk * sl / ns), b1 = (int)((int64_t)nblk * (sl + 1) / ns);
-  double* slices = red.gpart + (int64_t)y * ns * ss;
-  const int EB = ss < kBlock ? ss : kBlock;  // entries per pass
-  const int SUB = kBlock / EB;                // sub-slices per entry
-  const int t = threadIdx.x, te = t % EB, sub = t / EB;
-  for (int base = 0; base < ss; base += EB) {
-    const int e = base + te;
-    double acc = 0.0;
-    if (sub < SUB && e < ss)
-      for (int b = b0 + sub; b < b1; b += SUB) acc += (double)P[(int64_t)b * ss + e];
-    sh[t] = acc;
-    __syncthreads();
-    if (t < EB && e < ss) {
-      double v = 0.0;
-      for (int k = 0; k < SUB; ++k) v += sh[k * EB + t];
-      slices[(int64_t)sl * ss + e] = v;
-    }
-    __syncthreads();
-  }
-  uint32_t* cnt = red.cnt + (int64_t)y * kCntStride;
-  __threadfence();
-  __syncthreads();
-  if (t == 0) last = (atomicAdd(cnt, 1u) == (uint32_t)(ns - 1));
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
-  double* G = red.G + (int64_t)y * ss;
-  for (int e = t; e < ss; e += kBlock) {
-    double v = 0.0;
-    for (int k = 0; k < ns; ++k) v += slices[(int64_t)k * ss + e];
-    G[e] = v;
-  }
-  if (t == 0) *cnt = 0;
-}
-
-static hipError_t launch_reduce(int s, const void* partial, bool f32, int nblk, int batch, Red red,
-                                const int32_t* gate, const int32_t* fire, hipStream_t st) {
-  const int ns = nblk < 16 ? nblk : 16;
-  dim3 grid(ns, batch);
-  if (f32)
-    hipLaunchKernelGGL(reduce_kernel<float>, grid, dim3(kBlock), 0, st, s * s, static_cast<const float*>(partial),
-                       nblk, red, gate, fire);
-  else
-    hipLaunchKernelGGL(reduce_kernel<double>, grid, dim3(kBlock), 0, st, s * s,
-                       static_cast<const double*>(partial), nblk, red, gate, fire);
-  return hipGetLastError();
-}
-
 // ------------------------------------------------------------------ SpMM --
 // MODE 0: Y = A X.  MODE 1: Y = A X and Gram partials of X_own^T Y.
 // MODE 2: Y = B - A X and Gram partials of Y^T Y.
@@ -215,7 +206,7 @@ __global__ __launch_bounds__(kBlock) void spmm_kernel(int64_t n, int64_t nnz, co
   using L = Layout<T, S, VEC>;
   constexpr int NW = kBlock / kWave;
   constexpr int RPB = NW * L::RPW;
-  constexpr int U = 8;
+  constexpr int U = BKRY_UNROLL;
   constexpr int GA = MODE ? VEC : 1;
   constexpr int GB = MODE ? S : 1;
   __shared__ T sh[MODE ? NW * S * S : 1];
@@ -233,10 +224,80 @@ __global__ __launch_bounds__(kBlock) void spmm_kernel(int64_t n, int64_t nnz, co
     for (int b = 0; b < GB; ++b) gacc[a][b] = T(0);
   bool badidx = false;
 
+#if BKRY_SPMM_LDS
+  // CSR segment of the wavefront's rows, staged through LDS with coalesced loads
+  constexpr int CH = 256;
+  __shared__ int32_t s_ci[NW][CH];
+  __shared__ T s_v[NW][CH];
+#endif
   for (int64_t base = r0; base < r1; base += RPB) {
     const int64_t row = base + wave * L::RPW + r;
     const bool rv = row < r1 && active;
     vec_t<T, VEC> acc = zero_vec<T, VEC>();
+#if BKRY_SPMM_LDS
+    {
+      const int64_t wrow0 = base + wave * L::RPW;
+      const int nrows = (int)((r1 - wrow0) < L::RPW ? (r1 - wrow0) : L::RPW);  // rows of this wavefront (may be <= 0)
+      int64_t rp = 0;
+      if (nrows > 0 && lane <= nrows) {
+        rp = rowptr[wrow0 + lane];
+        rp = rp < 0 ? 0 : (rp > nnz ? nnz : rp);
+      }
+      const int64_t kb = __shfl(rp, 0);
+      const int64_t ke = __shfl(rp, nrows > 0 ? nrows : 0);
+      int64_t my0 = __shfl(rp, r < nrows ? r : 0), my1 = __shfl(rp, r < nrows ? r + 1 : 0);
+      if (my1 < my0) my1 = my0;
+      const int64_t seg = ke > kb ? ke - kb : 0;
+      for (int64_t off = 0; off < seg; off += CH) {
+        const int cnt = (int)((seg - off) < CH ? (seg - off) : CH);
+        for (int t = lane; t < cnt; t += kWave) {
+          s_ci[wave][t] = colind[kb + off + t];
+          s_v[wave][t] = val[kb + off + t];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        int64_t a = my0 - kb, e = my1 - kb;
+        if (a < off) a = off;
+        if (e > off + cnt) e = off + cnt;
+        if (rv) {
+          for (int64_t k = a; k < e; k += U) {
+            int jj[U];
+            T aa[U];
+            bool okk[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+              okk[u] = (k + u) < e;
+              jj[u] = okk[u] ? s_ci[wave][k + u - off] : 0;
+              aa[u] = okk[u] ? s_v[wave][k + u - off] : T(0);
+            }
+            vec_t<T, VEC> xx[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+              const bool okj = (uint32_t)jj[u] < (uint64_t)n;
+              badidx |= okk[u] && !okj;
+              xx[u] = (okk[u] && okj) ? load_vec<T, VEC>(X + (int64_t)jj[u] * s + col0) : zero_vec<T, VEC>();
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+              for (int w = 0; w < VEC; ++w) acc.v[w] += aa[u] * xx[u].v[w];
+          }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      }
+      if (rv) {
+        if (MODE == 2) {
+          vec_t<T, VEC> b = load_vec<T, VEC>(B + row * s + col0);
+#pragma unroll
+          for (int w = 0; w < VEC; ++w) acc.v[w] = b.v[w] - acc.v[w];
+        }
+        store_out<T, VEC>(Y + row * s + col0, acc);
+      }
+    }
+#else
     if (rv) {
       int64_t k0 = rowptr[row], k1 = rowptr[row + 1];
       if (k0 < 0) k0 = 0;
@@ -268,8 +329,9 @@ __global__ __launch_bounds__(kBlock) void spmm_kernel(int64_t n, int64_t nnz, co
 #pragma unroll
         for (int w = 0; w < VEC; ++w) acc.v[w] = b.v[w] - acc.v[w];
       }
-      store_vec<T, VEC>(Y + row * s + col0, acc);
+      store_out<T, VEC>(Y + row * s + col0, acc);
     }
+#endif
     if constexpr (MODE == 1) {
       vec_t<T, VEC> own = rv ? load_vec<T, VEC>(X + row * s + col0) : zero_vec<T, VEC>();
       gram_row<T, S, VEC>(gacc, own, acc, lane);
@@ -281,25 +343,209 @@ __global__ __launch_bounds__(kBlock) void spmm_kernel(int64_t n, int64_t nnz, co
   if constexpr (MODE != 0) gram_store<T, S, VEC>(gacc, s, partial, sh);
 }
 
+// Software-pipelined variant: the row pointers of tile i+2 and the first
+// U non-zeros of tile i+1 are loaded while the X rows of tile i are gathered,
+// so one memory round trip per tile is exposed instead of three.
+template <typename T, int S, int VEC, int MODE>
+__global__ __launch_bounds__(kBlock) void spmm_pf_kernel(int64_t n, int64_t nnz, const int32_t* __restrict__ rowptr,
+                                                          const int32_t* __restrict__ colind,
+                                                          const T* __restrict__ val, int s, const T* __restrict__ X,
+                                                          T* __restrict__ Y, const T* __restrict__ B,
+                                                          T* __restrict__ partial, int32_t* bad,
+                                                          const int32_t* done) {
+  using L = Layout<T, S, VEC>;
+  constexpr int NW = kBlock / kWave;
+  constexpr int RPB = NW * L::RPW;
+  constexpr int U = BKRY_UNROLL;
+  constexpr int GA = MODE ? VEC : 1;
+  constexpr int GB = MODE ? S : 1;
+  __shared__ T sh[MODE ? NW * S * S : 1];
+  if (done && *done) return;
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  const int r = lane / L::LPR, c = lane % L::LPR;
+  const int col0 = c * VEC;
+  const bool active = col0 < s;
+  int64_t r0, r1;
+  int64_t step;
+  gang_rows(n, blockIdx.x, gridDim.x, RPB, BKRY_GANG, r0, r1, step);
+  T gacc[GA][GB];
+#pragma unroll
+  for (int a = 0; a < GA; ++a)
+#pragma unroll
+    for (int b = 0; b < GB; ++b) gacc[a][b] = T(0);
+  bool badidx = false;
+  const int64_t roff = wave * L::RPW + r;
+
+  // row extent [k0, k1) clamped to [0, nnz]; empty for rows outside the slice
+  auto ld_rp = [&](int64_t rw, int64_t& k0, int64_t& k1) {
+    k0 = 0;
+    k1 = 0;
+    if (rw < r1 && active) {
+      k0 = rowptr[rw];
+      k1 = rowptr[rw + 1];
+      k0 = k0 < 0 ? 0 : k0;
+      k1 = k1 > nnz ? nnz : k1;
+    }
+  };
+  // first U entries of [k0, k1): returns how many are present
+  auto ld_chunk = [&](int64_t k0, int64_t k1, int (&jj)[U], T (&aa)[U]) -> int {
+    const int64_t m = k1 - k0;
+    const int cnt = m <= 0 ? 0 : (m < U ? (int)m : U);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+#if BKRY_NTL
+      jj[u] = u < cnt ? __builtin_nontemporal_load(colind + k0 + u) : 0;
+      aa[u] = u < cnt ? __builtin_nontemporal_load(val + k0 + u) : T(0);
+#else
+      jj[u] = u < cnt ? colind[k0 + u] : 0;
+      aa[u] = u < cnt ? val[k0 + u] : T(0);
+#endif
+    }
+    return cnt;
+  };
+
+  int64_t k0c, k1c, k0n, k1n;
+  ld_rp(r0 + roff, k0c, k1c);
+  ld_rp(r0 + roff + step, k0n, k1n);
+  int cj[U];
+  T ca[U];
+  int cc = ld_chunk(k0c, k1c, cj, ca);
+  for (int64_t base = r0; base < r1; base += step) {
+    const int64_t row = base + roff;
+    const bool rv = row < r1 && active;
+    int64_t k0nn, k1nn;
+    ld_rp(row + 2 * step, k0nn, k1nn);
+    int nj[U];
+    T na[U];
+    const int nc = ld_chunk(k0n, k1n, nj, na);
+    vec_t<T, VEC> xx[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const bool okj = (uint32_t)cj[u] < (uint64_t)n;
+      badidx |= (u < cc) && !okj;
+      xx[u] = (u < cc && okj) ? load_vec<T, VEC>(X + (int64_t)cj[u] * s + col0) : zero_vec<T, VEC>();
+    }
+    vec_t<T, VEC> own = zero_vec<T, VEC>();
+    if (MODE == 1 && rv) own = load_vec<T, VEC>(X + row * s + col0);
+    if (MODE == 2 && rv) own = load_vec<T, VEC>(B + row * s + col0);
+    vec_t<T, VEC> acc = zero_vec<T, VEC>();
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int w = 0; w < VEC; ++w) acc.v[w] += ca[u] * xx[u].v[w];
+    // rows longer than U: remaining entries without pipelining
+    for (int64_t k = k0c + U; k < k1c; k += U) {
+      int jj[U];
+      T aa[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const bool ok = (k + u) < k1c;
+        jj[u] = ok ? colind[k + u] : 0;
+        aa[u] = ok ? val[k + u] : T(0);
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const bool ok = (k + u) < k1c;
+        const bool okj = (uint32_t)jj[u] < (uint64_t)n;
+        badidx |= ok && !okj;
+        xx[u] = (ok && okj) ? load_vec<T, VEC>(X + (int64_t)jj[u] * s + col0) : zero_vec<T, VEC>();
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int w = 0; w < VEC; ++w) acc.v[w] += aa[u] * xx[u].v[w];
+    }
+    if (MODE == 2) {
+#pragma unroll
+      for (int w = 0; w < VEC; ++w) acc.v[w] = own.v[w] - acc.v[w];
+    }
+    if (rv) store_out<T, VEC>(Y + row * s + col0, acc);
+    if constexpr (MODE == 1) {
+      gram_row<T, S, VEC>(gacc, own, acc, lane);
+    } else if constexpr (MODE == 2) {
+      gram_row<T, S, VEC>(gacc, acc, acc, lane);
+    }
+    k0c = k0n;
+    k1c = k1n;
+    k0n = k0nn;
+    k1n = k1nn;
+    cc = nc;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      cj[u] = nj[u];
+      ca[u] = na[u];
+    }
+  }
+  if (badidx && bad) *bad = 1;
+  if constexpr (MODE != 0) gram_store<T, S, VEC>(gacc, s, partial, sh);
+}
+
+#ifndef BKRY_FIT_GRID
+#define BKRY_FIT_GRID 1
+#endif
+#ifndef BKRY_SPMM_PF
+#define BKRY_SPMM_PF 1
+#endif
+#if BKRY_SPMM_PF
+#define BKRY_SPMM_KERNEL spmm_pf_kernel
+#else
+#define BKRY_SPMM_KERNEL spmm_kernel
+#endif
+
+// Workgroups of kernel K that the device holds at once (cached per kernel).
+template <auto K>
+static int resident_blocks() {
+  static int cached = 0;
+  if (cached == 0) {
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, K, kBlock, 0) != hipSuccess || per <= 0 || cus <= 0) {
+      (void)hipGetLastError();
+      return 1 << 30;
+    }
+    cached = per * cus;
+  }
+  return cached;
+}
+
+// Launch width of a streaming kernel: the requested width, capped so that
+// every workgroup is resident (a workgroup owns a contiguous row range, so a
+// second round of workgroups would only lengthen the tail), a multiple of 8.
+template <auto K>
+static int fit_grid(int nblk) {
+  const int cap = resident_blocks<K>() / 8 * 8;
+  return (cap >= 8 && nblk > cap) ? cap : nblk;
+}
+
 template <typename T>
 hipError_t launch_spmm(const CsrView& A, int s, const T* X, T* Y, const T* B, int mode, T* partial, int nblk,
-                       Red red, int32_t* bad, const int32_t* done, hipStream_t st) {
+                       Red red, int32_t* bad, const int32_t* done, hipStream_t st, Epi epi, hipEvent_t ev_after) {
   hipError_t e = dispatch_s<T>(s, [&](auto S_, auto V_) -> hipError_t {
     constexpr int S = decltype(S_)::value, V = decltype(V_)::value;
     const T* val = static_cast<const T*>(A.val);
+#if BKRY_FIT_GRID
     if (mode == 0)
-      hipLaunchKernelGGL((spmm_kernel<T, S, V, 0>), dim3(nblk), dim3(kBlock), 0, st, A.n, A.nnz, A.rowptr,
+      nblk = fit_grid<BKRY_SPMM_KERNEL<T, S, V, 0>>(nblk);
+    else if (mode == 1)
+      nblk = fit_grid<BKRY_SPMM_KERNEL<T, S, V, 1>>(nblk);
+    else
+      nblk = fit_grid<BKRY_SPMM_KERNEL<T, S, V, 2>>(nblk);
+#endif
+    if (mode == 0)
+      hipLaunchKernelGGL((BKRY_SPMM_KERNEL<T, S, V, 0>), dim3(nblk), dim3(kBlock), 0, st, A.n, A.nnz, A.rowptr,
                          A.colind, val, s, X, Y, B, partial, bad, done);
     else if (mode == 1)
-      hipLaunchKernelGGL((spmm_kernel<T, S, V, 1>), dim3(nblk), dim3(kBlock), 0, st, A.n, A.nnz, A.rowptr,
+      hipLaunchKernelGGL((BKRY_SPMM_KERNEL<T, S, V, 1>), dim3(nblk), dim3(kBlock), 0, st, A.n, A.nnz, A.rowptr,
                          A.colind, val, s, X, Y, B, partial, bad, done);
     else
-      hipLaunchKernelGGL((spmm_kernel<T, S, V, 2>), dim3(nblk), dim3(kBlock), 0, st, A.n, A.nnz, A.rowptr,
+      hipLaunchKernelGGL((BKRY_SPMM_KERNEL<T, S, V, 2>), dim3(nblk), dim3(kBlock), 0, st, A.n, A.nnz, A.rowptr,
                          A.colind, val, s, X, Y, B, partial, bad, done);
     return hipGetLastError();
   });
+  if (e == hipSuccess && ev_after) e = hipEventRecord(ev_after, st);
   if (e != hipSuccess || mode == 0) return e;
-  return launch_reduce(s, partial, sizeof(T) == 4, nblk, 1, red, done, nullptr, st);
+  return launch_reduce(s, partial, sizeof(T) == 4, nblk, 1, red, done, nullptr, epi, st);
 }
 
 // ------------------------------------------------------------------ Gram --
@@ -346,7 +592,7 @@ hipError_t launch_gram(int64_t n, int s, const T* X, int nx, const T* Y, T* part
     return hipGetLastError();
   });
   if (e != hipSuccess) return e;
-  return launch_reduce(s, partial, sizeof(T) == 4, nblk, nx, red, done, fire, st);
+  return launch_reduce(s, partial, sizeof(T) == 4, nblk, nx, red, done, fire, Epi{}, st);
 }
 
 // ---------------------------------------------------------- CG updates --
@@ -404,7 +650,7 @@ __global__ __launch_bounds__(kBlock) void cg_update_kernel(int64_t n, int s, T* 
     vec_t<T, VEC> out;
 #pragma unroll
     for (int w = 0; w < VEC; ++w) out.v[w] = rr.v[w] - ql[w];
-    if (rv) store_vec<T, VEC>(R + row * s + col0, out);
+    if (rv) store_out<T, VEC>(R + row * s + col0, out);
     gram_row<T, S, VEC>(gacc, out, out, lane);
   }
   gram_store<T, S, VEC>(gacc, s, partial, sh);
@@ -412,14 +658,15 @@ __global__ __launch_bounds__(kBlock) void cg_update_kernel(int64_t n, int s, T* 
 
 template <typename T>
 hipError_t launch_cg_update(int64_t n, int s, T* R, const T* Q, const CgCtl* ctl, T* partial, int nblk, Red red,
-                            hipStream_t st) {
+                            hipStream_t st, Epi epi, hipEvent_t ev_after) {
   hipError_t e = dispatch_s<T>(s, [&](auto S_, auto V_) -> hipError_t {
     constexpr int S = decltype(S_)::value, V = decltype(V_)::value;
     hipLaunchKernelGGL((cg_update_kernel<T, S, V>), dim3(nblk), dim3(kBlock), 0, st, n, s, R, Q, ctl, partial);
     return hipGetLastError();
   });
+  if (e == hipSuccess && ev_after) e = hipEventRecord(ev_after, st);
   if (e != hipSuccess) return e;
-  return launch_reduce(s, partial, sizeof(T) == 4, nblk, 1, red, &ctl->gate, nullptr, st);
+  return launch_reduce(s, partial, sizeof(T) == 4, nblk, 1, red, &ctl->gate, nullptr, epi, st);
 }
 
 // X += P (lambda sigma); unless the solve has ended: P = R + P beta.
@@ -452,14 +699,14 @@ __global__ __launch_bounds__(kBlock) void cg_pupdate_kernel(int64_t n, int s, T*
     row_times<T, S, VEC>(dx, p, ls, col0, lane);
 #pragma unroll
     for (int w = 0; w < VEC; ++w) x.v[w] += dx[w];
-    if (rv) store_vec<T, VEC>(X + row * s + col0, x);
+    if (rv) store_out<T, VEC>(X + row * s + col0, x);
     if (pdir) {
       vec_t<T, VEC> rr = rv ? load_vec<T, VEC>(R + row * s + col0) : zero_vec<T, VEC>();
       T pb[VEC];
       row_times<T, S, VEC>(pb, p, bt, col0, lane);
 #pragma unroll
       for (int w = 0; w < VEC; ++w) rr.v[w] += pb[w];
-      if (rv) store_vec<T, VEC>(P + row * s + col0, rr);
+      if (rv) store_out<T, VEC>(P + row * s + col0, rr);
     }
   }
 }
@@ -667,10 +914,11 @@ hipError_t launch_cast_f32(int64_t count, const double* in, float* out, hipStrea
 // ------------------------------------------------------ instantiations --
 #define BKRY_INST(T)                                                                                              \
   template hipError_t launch_spmm<T>(const CsrView&, int, const T*, T*, const T*, int, T*, int, Red, int32_t*,     \
-                                     const int32_t*, hipStream_t);                                                 \
+                                     const int32_t*, hipStream_t, Epi, hipEvent_t);                                \
   template hipError_t launch_gram<T>(int64_t, int, const T*, int, const T*, T*, int, Red, const int32_t*,          \
                                      hipStream_t, const int32_t*);                                                 \
-  template hipError_t launch_cg_update<T>(int64_t, int, T*, const T*, const CgCtl*, T*, int, Red, hipStream_t);    \
+  template hipError_t launch_cg_update<T>(int64_t, int, T*, const T*, const CgCtl*, T*, int, Red, hipStream_t,    \
+                                          Epi, hipEvent_t);                                                        \
   template hipError_t launch_cg_pupdate<T>(int64_t, int, T*, T*, const T*, const CgCtl*, hipStream_t);             \
   template hipError_t launch_block_combine<T>(int64_t, int, const T*, int, const double*, double, T*,               \
                                               const int32_t*, hipStream_t);                                        \

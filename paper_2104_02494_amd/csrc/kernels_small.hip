@@ -345,15 +345,11 @@ hipError_t launch_cg_init(CgCtl* ctl, const double* G_R0, const double* G_rho, h
 }
 
 // alpha = <P, Q>_S; lambda = alpha^-1 rho; lambda sigma; the kappa_D test.
-__global__ __launch_bounds__(kSB) void cg_alpha_kernel(CgCtl* c, const double* G) {
+// Runs only while the solve is live and not suspended (the caller checks).
+__device__ void cg_alpha_body(CgCtl* c, const double* G) {
   __shared__ double Al[kSS], L[kSS], Rh[kSS], Lm[kSS], W[kSS], T[kSS];
   __shared__ double rc[kMaxS], rs[kMaxS], red[4];
   __shared__ int partner[kMaxS], first[kMaxS], flag[1];
-  if (c->done) {
-    if (tid() == 0) c->x_pending = 0;
-    return;
-  }
-  if (c->gate) return;  // suspended: this iteration waits for its re-normalisation
   const int s = c->s;
   const Sub sub{c->kind, s, c->g};
   sm_copy(Al, G, s * s);
@@ -394,19 +390,14 @@ __global__ __launch_bounds__(kSB) void cg_alpha_kernel(CgCtl* c, const double* G
   }
 }
 
-hipError_t launch_cg_alpha(CgCtl* ctl, const double* G, hipStream_t st) {
-  hipLaunchKernelGGL(cg_alpha_kernel, dim3(1), dim3(kSB), 0, st, ctl, G);
-  return hipGetLastError();
-}
-
 // G = R~^T R~ (full).  Column norms of the true residual R~ sigma, stopping
 // test, and (no normalisation this iteration) rho' = <R~, R~>_S and
-// beta = rho^-1 rho'.
-__global__ __launch_bounds__(kSB) void cg_rho_kernel(CgCtl* c, const double* G, double* hist) {
+// beta = rho^-1 rho'.  Runs only while the iteration is live (the caller
+// checks the gate).
+__device__ void cg_rho_body(CgCtl* c, const double* G, double* hist) {
   __shared__ double Gm[kSS], Sg[kSS], T1[kSS], L[kSS], Bt[kSS];
   __shared__ double red[4];
   __shared__ int flag[2];
-  if (c->gate) return;
   const int s = c->s;
   const Sub sub{c->kind, s, c->g};
   sm_copy(Gm, G, s * s);
@@ -467,9 +458,100 @@ __global__ __launch_bounds__(kSB) void cg_rho_kernel(CgCtl* c, const double* G, 
   sm_copy(c->rho, Gm, s * s);
 }
 
-hipError_t launch_cg_rho(CgCtl* ctl, const double* G, double* hist, hipStream_t st) {
-  hipLaunchKernelGGL(cg_rho_kernel, dim3(1), dim3(kSB), 0, st, ctl, G, hist);
+// --------------------------------------------------- Gram reduction --
+// grid (ns, batch), one wavefront per workgroup: workgroup (sl, y) sums the
+// partials [b0, b1) of batch slice y in block order into red.gpart[y][sl];
+// the last workgroup of slice y to finish adds the ns slice sums in slice
+// order into red.G[y] and then runs the epilogue EPI on it.  Which workgroup
+// finishes last does not change the order of any sum, so the result is
+// deterministic.  Only the <= kMaxSlices workgroups of a slice take part in
+// the hand-off, so its device-scope fences are cheap.
+template <typename T>
+__device__ __forceinline__ double sum_strided(const T* __restrict__ p, int64_t stride, int count) {
+  double acc = 0.0;
+  int b = 0;
+  for (; b + 8 <= count; b += 8) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = (double)p[(int64_t)(b + u) * stride];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc += v[u];
+  }
+  for (; b < count; ++b) acc += (double)p[(int64_t)b * stride];
+  return acc;
+}
+
+template <typename T, int EPI>
+__global__ __launch_bounds__(kSB) void reduce_kernel(int ss, const T* __restrict__ partial, int nblk, Red red,
+                                                      const int32_t* gate, const int32_t* fire, CgCtl* c,
+                                                      double* hist) {
+  __shared__ int last;
+  if constexpr (EPI == EPI_CG_ALPHA) {
+    if (c->done) {  // ended: the X update of this iteration is dropped
+      if (blockIdx.x == 0 && tid() == 0) c->x_pending = 0;
+      return;
+    }
+    if (c->gate) return;  // suspended: the iteration waits for its re-normalisation
+  } else if constexpr (EPI == EPI_CG_RHO) {
+    if (c->gate) return;
+  } else {
+    if ((gate && *gate) || (fire && !*fire)) return;
+  }
+  const int ns = gridDim.x, sl = blockIdx.x, y = blockIdx.y;
+  const T* P = partial + (int64_t)y * nblk * ss;
+  const int b0 = (int)((int64_t)nblk * sl / ns), b1 = (int)((int64_t)nblk * (sl + 1) / ns);
+  double* slices = red.gpart + (int64_t)y * ns * ss;
+  for (int e = tid(); e < ss; e += kSB) slices[(int64_t)sl * ss + e] = sum_strided<T>(P + (int64_t)b0 * ss + e, ss, b1 - b0);
+  uint32_t* cnt = red.cnt + (int64_t)y * kCntStride;
+  __threadfence();
+  __syncthreads();
+  if (tid() == 0) last = (atomicAdd(cnt, 1u) == (uint32_t)(ns - 1));
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  double* G = red.G + (int64_t)y * ss;
+  for (int e = tid(); e < ss; e += kSB) G[e] = sum_strided<double>(slices + e, ss, ns);
+  if (tid() == 0) *cnt = 0;
+  if constexpr (EPI == EPI_CG_ALPHA) {
+    __syncthreads();
+    cg_alpha_body(c, G);
+  } else if constexpr (EPI == EPI_CG_RHO) {
+    __syncthreads();
+    cg_rho_body(c, G, hist);
+  }
+}
+
+// About 16 partials per reduction workgroup, at most kMaxSlices workgroups.
+static int reduce_slices(int nblk) {
+  int ns = nblk / 16;
+  if (ns < 1) ns = 1;
+  if (ns > kMaxSlices) ns = kMaxSlices;
+  return ns;
+}
+
+template <typename T>
+static hipError_t launch_reduce_t(int s, const T* partial, int nblk, int batch, Red red, const int32_t* gate,
+                                  const int32_t* fire, Epi epi, hipStream_t st) {
+  dim3 grid(reduce_slices(nblk), batch);
+  if (epi.kind == EPI_CG_ALPHA) {
+    if (batch != 1 || !epi.ctl) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((reduce_kernel<T, EPI_CG_ALPHA>), grid, dim3(kSB), 0, st, s * s, partial, nblk, red, gate,
+                       fire, epi.ctl, epi.hist);
+  } else if (epi.kind == EPI_CG_RHO) {
+    if (batch != 1 || !epi.ctl) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((reduce_kernel<T, EPI_CG_RHO>), grid, dim3(kSB), 0, st, s * s, partial, nblk, red, gate,
+                       fire, epi.ctl, epi.hist);
+  } else {
+    hipLaunchKernelGGL((reduce_kernel<T, EPI_NONE>), grid, dim3(kSB), 0, st, s * s, partial, nblk, red, gate, fire,
+                       epi.ctl, epi.hist);
+  }
   return hipGetLastError();
+}
+
+hipError_t launch_reduce(int s, const void* partial, bool f32, int nblk, int batch, Red red, const int32_t* gate,
+                         const int32_t* fire, Epi epi, hipStream_t st) {
+  if (f32) return launch_reduce_t<float>(s, static_cast<const float*>(partial), nblk, batch, red, gate, fire, epi, st);
+  return launch_reduce_t<double>(s, static_cast<const double*>(partial), nblk, batch, red, gate, fire, epi, st);
 }
 
 // After the residual was normalised, R~ = R-bar gamma: sigma = gamma sigma,

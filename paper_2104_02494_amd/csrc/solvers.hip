@@ -50,16 +50,25 @@ hipError_t prof_flush(Prof* p) {
 }
 
 namespace {
+// Records the start event on construction and the end event on destruction,
+// unless the timed launcher records the end event itself (end()).
 struct ProfScope {
   Prof* p;
   int k;
   hipStream_t st;
+  bool handed = false;
   ProfScope(Prof* p_, int k_, hipStream_t st_) : p(p_), k(k_), st(st_) {
     if (p && p->used[k] < kProfSlots) (void)hipEventRecord(p->ev[k][0][p->used[k]], st);
   }
+  // End event for a launcher to record after its streaming kernel (or null).
+  hipEvent_t end() {
+    if (!(p && p->used[k] < kProfSlots)) return nullptr;
+    handed = true;
+    return p->ev[k][1][p->used[k]];
+  }
   ~ProfScope() {
     if (p && p->used[k] < kProfSlots) {
-      (void)hipEventRecord(p->ev[k][1][p->used[k]], st);
+      if (!handed) (void)hipEventRecord(p->ev[k][1][p->used[k]], st);
       p->used[k] += 1;
     }
   }
@@ -145,15 +154,18 @@ hipError_t cg_run(const CsrView& A, Sub sub, const T* B, T* X, double tol, int m
   while (maxit > 0) {
     for (int it = 0; it < batch; ++it) {
       {
+        // Q = A P and alpha = <P, Q>_S; the reduction's last workgroup
+        // computes lambda, lambda sigma and the re-orthonormalisation test
         ProfScope ps(prof, PROF_CG_SPMM, st);
-        BK_TRY(launch_spmm<T>(A, s, b.P, b.Q, nullptr, 1, b.partial, nblk, ra, &c->bad_index, gate, st));
+        BK_TRY(launch_spmm<T>(A, s, b.P, b.Q, nullptr, 1, b.partial, nblk, ra, &c->bad_index, gate, st,
+                              Epi{EPI_CG_ALPHA, c, nullptr}, ps.end()));
       }
-      BK_TRY(launch_cg_alpha(c, b.Ga, st));
       {
+        // R~ = R - Q lambda and its Gram; then the stopping test, rho' and beta
         ProfScope ps(prof, PROF_CG_UPDATE, st);
-        BK_TRY(launch_cg_update<T>(n, s, b.R, b.Q, c, b.partial, nblk, rr, st));
+        BK_TRY(launch_cg_update<T>(n, s, b.R, b.Q, c, b.partial, nblk, rr, st, Epi{EPI_CG_RHO, c, b.hist},
+                                   ps.end()));
       }
-      BK_TRY(launch_cg_rho(c, b.Gr, b.hist, st));
       if (always) BK_TRY(cg_normalise<T>(n, sub, b, nblk, st, prof));
       {
         ProfScope ps(prof, PROF_CG_PUPDATE, st);
