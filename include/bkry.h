@@ -118,6 +118,21 @@ const char* bkry_last_error(bkry_handle h);
 int bkry_profile(bkry_handle h, int enable);
 int bkry_profile_read(bkry_handle h, int32_t kernel, double* total_ms, int64_t* launches, int32_t reset);
 
+/* Matrix format that the SpMM streams (measurement and testing support; the
+ * arithmetic is the same): BKRY_FMT_AUTO (default) lets the solvers stream a
+ * padded row-major copy of A (ELL: every row padded to the longest row,
+ * rounded up to a multiple of 2, 4 or 8 entries by p), built in the handle's
+ * workspace at the start of each solve, when that copy costs at most 25 %
+ * more bytes per product than CSR, and streams CSR otherwise and in
+ * bkry_spmm; BKRY_FMT_CSR always streams CSR; BKRY_FMT_ELL always streams
+ * the ELL copy (bkry_spmm and bkry_spmm_f32 then build it on every call and
+ * return when it is built).  Entries are summed in storage order either way,
+ * so results are bit-identical across formats. */
+#define BKRY_FMT_AUTO 0
+#define BKRY_FMT_CSR 1
+#define BKRY_FMT_ELL 2
+int bkry_set_spmm_format(bkry_handle h, int32_t format);
+
 /* BOP (Ch. 3, Performance Analysis): Y = A X for n x p blocks.  Each output
  * entry is summed over the row's non-zeros in storage order. */
 int bkry_spmm(bkry_handle h, const bkry_csr* A, int32_t p, const double* X, double* Y);

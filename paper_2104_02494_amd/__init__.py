@@ -56,7 +56,7 @@ class bkry_info(ctypes.Structure):
 
 
 EXPORTS = ["bkry_create", "bkry_destroy", "bkry_set_stream", "bkry_synchronize", "bkry_last_error",
-           "bkry_profile", "bkry_profile_read", "bkry_spmm",
+           "bkry_profile", "bkry_profile_read", "bkry_set_spmm_format", "bkry_spmm",
            "bkry_spmm_f32", "bkry_bdot", "bkry_bdot_f32", "bkry_tsqr", "bkry_cg_solve", "bkry_gmres_solve",
            "bkry_sddmm", "bkry_csr_transpose"]
 
@@ -81,6 +81,7 @@ def lib():
             "bkry_synchronize": [H],
             "bkry_profile": [H, ctypes.c_int],
             "bkry_profile_read": [H, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64), i32],
+            "bkry_set_spmm_format": [H, i32],
             "bkry_spmm": [H, csr_p, i32, vp, vp],
             "bkry_spmm_f32": [H, i64, i64, vp, vp, vp, i32, vp, vp],
             "bkry_bdot": [H, i64, i32, bkry_subalg, vp, vp, vp],
@@ -294,6 +295,16 @@ def bkry_synchronize(h: Handle):
 
 
 PROF_CG_SPMM, PROF_CG_UPDATE, PROF_CG_PUPDATE, PROF_CG_NORMALISE = 0, 1, 2, 3
+
+
+FMT_AUTO, FMT_CSR, FMT_ELL = 0, 1, 2
+_FMTS = {"auto": FMT_AUTO, "csr": FMT_CSR, "ell": FMT_ELL}
+
+
+def bkry_set_spmm_format(h: Handle, fmt):
+    """Matrix format streamed by the SpMM: "auto", "csr" or "ell" (or 0/1/2)."""
+    f = _FMTS[fmt] if isinstance(fmt, str) else int(fmt)
+    h._check(lib().bkry_set_spmm_format(h.h, f))
 
 
 def bkry_profile(h: Handle, enable: bool = True):

@@ -24,9 +24,11 @@ struct bkry_handle_s {
   char* ws = nullptr;
   size_t ws_cap = 0;
   int32_t* hflags = nullptr;  // pinned host, kHostFlagsInts
-  int32_t* dflags = nullptr;  // device: [0] bad CSR index seen by an asynchronous kernel
+  int32_t* dflags = nullptr;  // device: [0] bad CSR index seen by an asynchronous kernel,
+                              // [1] longest CSR row, [2] bad index seen while building an ELL copy
   uint32_t* cnt = nullptr;    // device: zeroed grid-reduction counters (left zero by every kernel)
   Prof* prof = nullptr;       // kernel timing, when enabled
+  int32_t spmm_format = BKRY_FMT_AUTO;
   std::string err;
 };
 
@@ -46,6 +48,8 @@ int hip_fail(bkry_handle h, hipError_t e, const char* where) {
     hipError_t e_ = (x);                            \
     if (e_ != hipSuccess) return hip_fail(h, e_, where); \
   } while (0)
+
+CsrView view(const bkry_csr* A) { return CsrView{A->n, A->nnz, A->rowptr, A->colind, A->val}; }
 
 int ensure_ws(bkry_handle h, size_t bytes) {
   if (bytes <= h->ws_cap) return BKRY_OK;
@@ -101,6 +105,45 @@ int check_csr(bkry_handle h, const bkry_csr* A, bool need_val) {
   return BKRY_OK;
 }
 
+// Row width of the ELL copy of A that this call streams (0: stream CSR).
+// AUTO picks ELL for the solvers when the padded copy costs at most 25 %
+// more bytes per SpMM than CSR; bkry_spmm uses ELL only when it is forced.
+int ell_width_for(bkry_handle h, const bkry_csr* A, int p, int elem_bytes, bool solver, int& W) {
+  W = 0;
+  if (h->spmm_format == BKRY_FMT_CSR || (h->spmm_format == BKRY_FMT_AUTO && !solver)) return BKRY_OK;
+  API_HIP(launch_ell_width(view(A), h->dflags + 1, h->stream), "ell width");
+  API_HIP(hipMemcpyAsync(h->hflags, h->dflags + 1, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream), "ell width");
+  API_HIP(hipStreamSynchronize(h->stream), "ell width");
+  const int64_t wmax = h->hflags[0] > 1 ? h->hflags[0] : 1;
+  const int64_t C = ell_chunk(p, elem_bytes);
+  const int64_t Wc = (wmax + C - 1) / C * C;
+  if (h->spmm_format == BKRY_FMT_AUTO) {
+    const double n = (double)A->n, eb = elem_bytes;
+    const double csr = 4.0 * (n + 1) + (double)A->nnz * (4.0 + eb) + 2.0 * n * p * eb;
+    const double ell = n * (double)Wc * (4.0 + eb) + 2.0 * n * p * eb;
+    if (ell > 1.25 * csr) return BKRY_OK;
+  }
+  if (Wc > (1 << 20)) return fail(h, BKRY_E_INVALID, "ELL row width too large");
+  W = (int)Wc;
+  return BKRY_OK;
+}
+
+// Fill the ELL copy (width W) of A with values val and attach it to v;
+// synchronous, so that a bad column index is reported here.
+template <typename Tin, typename T>
+int ell_build(bkry_handle h, const bkry_csr* A, const Tin* val, int W, int32_t* ecol, T* eval, CsrView& v) {
+  if (W <= 0) return BKRY_OK;
+  API_HIP(hipMemsetAsync(h->dflags + 2, 0, sizeof(int32_t), h->stream), "ell fill");
+  API_HIP((launch_ell_fill<Tin, T>(view(A), val, W, ecol, eval, h->dflags + 2, h->stream)), "ell fill");
+  API_HIP(hipMemcpyAsync(h->hflags, h->dflags + 2, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream), "ell fill");
+  API_HIP(hipStreamSynchronize(h->stream), "ell fill");
+  if (h->hflags[0]) return fail(h, BKRY_E_INVALID, "a CSR column index was outside [0, n)");
+  v.ell_w = W;
+  v.ell_col = ecol;
+  v.ell_val = eval;
+  return BKRY_OK;
+}
+
 bool misaligned(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) != 0; }
 
 int check_blocks(bkry_handle h, std::initializer_list<const void*> ptrs) {
@@ -111,7 +154,6 @@ int check_blocks(bkry_handle h, std::initializer_list<const void*> ptrs) {
   return BKRY_OK;
 }
 
-CsrView view(const bkry_csr* A) { return CsrView{A->n, A->nnz, A->rowptr, A->colind, A->val}; }
 
 int status_of(int st, bkry_handle h) {
   if (st == -2) return fail(h, BKRY_E_BREAKDOWN, "breakdown: a Cholesky pivot of alpha or rho was not positive");
@@ -245,15 +287,39 @@ int bkry_profile_read(bkry_handle h, int32_t kernel, double* total_ms, int64_t* 
   return BKRY_OK;
 }
 
+int bkry_set_spmm_format(bkry_handle h, int32_t format) {
+  int rc = begin(h);
+  if (rc) return rc;
+  if (format != BKRY_FMT_AUTO && format != BKRY_FMT_CSR && format != BKRY_FMT_ELL)
+    return fail(h, BKRY_E_INVALID, "unknown SpMM format");
+  h->spmm_format = format;
+  return BKRY_OK;
+}
+
 int bkry_spmm(bkry_handle h, const bkry_csr* A, int32_t p, const double* X, double* Y) {
   int rc = begin(h);
   if (!rc) rc = check_csr(h, A, true);
   if (!rc && (p < 1 || p > kMaxS)) rc = fail(h, BKRY_E_INVALID, "p must be in [1, 32]");
   if (!rc) rc = check_blocks(h, {X, Y});
   if (rc) return rc;
+  int W = 0;
+  rc = ell_width_for(h, A, p, sizeof(double), false, W);
+  if (rc) return rc;
+  CsrView v = view(A);
+  if (W > 0) {
+    Carver c;
+    c.take<int32_t>((size_t)A->n * W);
+    c.take<double>((size_t)A->n * W);
+    rc = ensure_ws(h, c.off);
+    if (rc) return rc;
+    Carver w{h->ws};
+    int32_t* ecol = w.take<int32_t>((size_t)A->n * W);
+    double* eval = w.take<double>((size_t)A->n * W);
+    rc = ell_build<double, double>(h, A, A->val, W, ecol, eval, v);
+    if (rc) return rc;
+  }
   const int nblk = stream_grid(A->n, p, sizeof(double));
-  API_HIP(launch_spmm<double>(view(A), p, X, Y, nullptr, 0, nullptr, nblk, Red{}, h->dflags, nullptr, h->stream),
-          "spmm");
+  API_HIP(launch_spmm<double>(v, p, X, Y, nullptr, 0, nullptr, nblk, Red{}, h->dflags, nullptr, h->stream), "spmm");
   return BKRY_OK;
 }
 
@@ -267,6 +333,21 @@ int bkry_spmm_f32(bkry_handle h, int64_t n, int64_t nnz, const int32_t* rowptr, 
   if (!rc) rc = check_blocks(h, {X, Y});
   if (rc) return rc;
   CsrView v{n, nnz, rowptr, colind, val};
+  int W = 0;
+  rc = ell_width_for(h, &A, p, sizeof(float), false, W);
+  if (rc) return rc;
+  if (W > 0) {
+    Carver c;
+    c.take<int32_t>((size_t)n * W);
+    c.take<float>((size_t)n * W);
+    rc = ensure_ws(h, c.off);
+    if (rc) return rc;
+    Carver w{h->ws};
+    int32_t* ecol = w.take<int32_t>((size_t)n * W);
+    float* eval = w.take<float>((size_t)n * W);
+    rc = ell_build<float, float>(h, &A, val, W, ecol, eval, v);
+    if (rc) return rc;
+  }
   const int nblk = stream_grid(n, p, sizeof(float));
   API_HIP(launch_spmm<float>(v, p, X, Y, nullptr, 0, nullptr, nblk, Red{}, h->dflags, nullptr, h->stream),
           "spmm_f32");
@@ -315,12 +396,18 @@ int bkry_cg_solve(bkry_handle h, const bkry_csr* A, int32_t p, bkry_subalg S, co
   const int hist_cap = (info && info->hist && info->hist_cap > 0) ? info->hist_cap : 0;
   double relres[kMaxS], trel[kMaxS];
   int status = 0, iters = 0, nre = 0, outer = 0, conv = 0, bad = 0, hist_len = 0;
+  int W = 0;
+  rc = ell_width_for(h, A, p, prec == BKRY_F64 ? sizeof(double) : sizeof(float), true, W);
+  if (rc) return rc;
+  const size_t ne = (size_t)n * W;
   if (prec == BKRY_F64) {
     Carver c;
     carve_cg<double>(c, n, sub, hist_cap, h->cnt);
     c.take<double>(kMaxS);
     c.take<double>(kMaxS);
     c.take<int32_t>(4);
+    c.take<int32_t>(ne);
+    c.take<double>(ne);
     rc = ensure_ws(h, c.off);
     if (rc) return rc;
     Carver w{h->ws};
@@ -328,9 +415,14 @@ int bkry_cg_solve(bkry_handle h, const bkry_csr* A, int32_t p, bkry_subalg S, co
     double* trr = w.take<double>(kMaxS);
     double* tsc = w.take<double>(kMaxS);
     int32_t* tfl = w.take<int32_t>(4);
+    int32_t* ecol = w.take<int32_t>(ne);
+    double* eval = w.take<double>(ne);
+    CsrView v = view(A);
+    rc = ell_build<double, double>(h, A, A->val, W, ecol, eval, v);
+    if (rc) return rc;
     CgResult r;
-    hipError_t e = cg_run<double>(view(A), sub, B, X, tol, maxit, eta, DBL_EPSILON, hist_cap, cb, h->stream,
-                                  h->hflags, r, h->prof);
+    hipError_t e = cg_run<double>(v, sub, B, X, tol, maxit, eta, DBL_EPSILON, hist_cap, cb, h->stream, h->hflags, r,
+                                  h->prof);
     if (e != hipSuccess) return hip_fail(h, e, "cg_solve");
     status = r.status;
     iters = r.iters;
@@ -341,8 +433,7 @@ int bkry_cg_solve(bkry_handle h, const bkry_csr* A, int32_t p, bkry_subalg S, co
     API_HIP(hipMemcpyAsync(relres, cb.ctl->relres, sizeof(double) * p, hipMemcpyDeviceToHost, h->stream), "cg");
     if (hist_len > 0)
       API_HIP(hipMemcpyAsync(info->hist, cb.hist, sizeof(double) * hist_len, hipMemcpyDeviceToHost, h->stream), "cg");
-    API_HIP(true_relres(view(A), p, B, X, cb.Q, cb.partial, cb.gpart, h->cnt, cb.Ga, cb.ctl->r0n, trr, tfl, tsc,
-                        h->stream),
+    API_HIP(true_relres(v, p, B, X, cb.Q, cb.partial, cb.gpart, h->cnt, cb.Ga, cb.ctl->r0n, trr, tfl, tsc, h->stream),
             "cg");
     API_HIP(hipMemcpyAsync(trel, trr, sizeof(double) * p, hipMemcpyDeviceToHost, h->stream), "cg");
     API_HIP(hipStreamSynchronize(h->stream), "cg");
@@ -352,6 +443,8 @@ int bkry_cg_solve(bkry_handle h, const bkry_csr* A, int32_t p, bkry_subalg S, co
     c.take<double>(kMaxS);
     c.take<double>(kMaxS);
     c.take<int32_t>(4);
+    c.take<int32_t>(ne);
+    c.take<float>(ne);
     rc = ensure_ws(h, c.off);
     if (rc) return rc;
     Carver w{h->ws};
@@ -359,6 +452,14 @@ int bkry_cg_solve(bkry_handle h, const bkry_csr* A, int32_t p, bkry_subalg S, co
     double* trr = w.take<double>(kMaxS);
     double* tsc = w.take<double>(kMaxS);
     int32_t* tfl = w.take<int32_t>(4);
+    int32_t* ecol = w.take<int32_t>(ne);
+    float* eval = w.take<float>(ne);
+    CsrView v32 = view(A);
+    rc = ell_build<double, float>(h, A, A->val, W, ecol, eval, v32);
+    if (rc) return rc;
+    ib.ell_w = v32.ell_w;
+    ib.ell_col = v32.ell_col;
+    ib.ell_val = static_cast<const float*>(v32.ell_val);
     const double itol = (info && info->inner_tol > 0.0) ? info->inner_tol : 1e-5;
     const int mo = (info && info->max_outer > 0) ? info->max_outer : 30;
     IrResult r;
@@ -409,24 +510,35 @@ int bkry_gmres_solve(bkry_handle h, const bkry_csr* A, int32_t p, bkry_subalg S,
   const double t0 = now_s();
   const int64_t n = A->n;
   const int hist_cap = (info && info->hist && info->hist_cap > 0) ? info->hist_cap : 0;
+  int W = 0;
+  rc = ell_width_for(h, A, p, sizeof(double), true, W);
+  if (rc) return rc;
+  const size_t ne = (size_t)n * W;
   Carver c;
   carve_gm(c, n, sub, restart, hist_cap, h->cnt);
   c.take<double>(kMaxS);
   c.take<double>(kMaxS);
+  c.take<int32_t>(ne);
+  c.take<double>(ne);
   rc = ensure_ws(h, c.off);
   if (rc) return rc;
   Carver w{h->ws};
   GmBufs gb = carve_gm(w, n, sub, restart, hist_cap, h->cnt);
   double* trr = w.take<double>(kMaxS);
   double* tsc = w.take<double>(kMaxS);
+  int32_t* ecol = w.take<int32_t>(ne);
+  double* eval = w.take<double>(ne);
+  CsrView v = view(A);
+  rc = ell_build<double, double>(h, A, A->val, W, ecol, eval, v);
+  if (rc) return rc;
   GmResult r;
   if (maxit > 0) {
-    hipError_t e = gm_run(view(A), sub, B, X, tol, maxit, restart, hist_cap, gb, h->stream, h->hflags, r);
+    hipError_t e = gm_run(v, sub, B, X, tol, maxit, restart, hist_cap, gb, h->stream, h->hflags, r);
     if (e != hipSuccess) return hip_fail(h, e, "gmres_solve");
   } else {
     // no step allowed: only the initial residual norms
     const int nblk = stream_grid(n, p, sizeof(double));
-    API_HIP(launch_spmm<double>(view(A), p, X, gb.V, B, 2, gb.partial, nblk, Red{gb.Gb, gb.gpart, h->cnt}, nullptr,
+    API_HIP(launch_spmm<double>(v, p, X, gb.V, B, 2, gb.partial, nblk, Red{gb.Gb, gb.gpart, h->cnt}, nullptr,
                                 nullptr, h->stream),
             "gmres");
     API_HIP(launch_gm_cycle_init(gb.ctl, gb.sig, gb.Gb, gb.Gb, 1, h->stream), "gmres");
@@ -435,7 +547,7 @@ int bkry_gmres_solve(bkry_handle h, const bkry_csr* A, int32_t p, bkry_subalg S,
     r.converged = reinterpret_cast<GmCtl*>(h->hflags)->converged;
   }
   double trel[kMaxS];
-  API_HIP(true_relres(view(A), p, B, X, gb.V, gb.partial, gb.gpart, h->cnt, gb.Gb, gb.ctl->r0n, trr, gb.flag, tsc,
+  API_HIP(true_relres(v, p, B, X, gb.V, gb.partial, gb.gpart, h->cnt, gb.Gb, gb.ctl->r0n, trr, gb.flag, tsc,
                       h->stream),
           "gmres");
   API_HIP(hipMemcpyAsync(trel, trr, sizeof(double) * p, hipMemcpyDeviceToHost, h->stream), "gmres");

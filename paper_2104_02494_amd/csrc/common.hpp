@@ -13,6 +13,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace bkry {
 
 constexpr int kWave = 64;
@@ -77,6 +79,51 @@ __device__ __forceinline__ T rowgroup_sum(T v) {
   return v;
 }
 
+// f(integral_constant<int, I>) for I = 0 .. N-1, unrolled at compile time.
+template <int I, int N, typename F>
+__device__ __forceinline__ void static_for_impl(F& f) {
+  if constexpr (I < N) {
+    f(std::integral_constant<int, I>{});
+    static_for_impl<I + 1, N>(f);
+  }
+}
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  static_for_impl<0, N>(f);
+}
+
+// Entries of the padded (ELL) matrix copy that each lane of an LPR-lane row
+// group loads per chunk; a chunk holds LPR * E consecutive entries of a row.
+constexpr int ell_entries_per_lane(int LPR) { return LPR <= 4 ? 2 : 1; }
+
+// Value held by lane K (0 <= K < LPR) of the caller's LPR-lane row group.
+// LPR <= 4 uses a DPP quad permutation (no LDS traffic); wider groups use a
+// cross-lane permute.  Every lane of the wavefront must execute it.
+template <int LPR, int K>
+__device__ __forceinline__ int group_bcast(int v) {
+  static_assert(K >= 0 && K < LPR, "lane out of group");
+  if constexpr (LPR == 1) {
+    return v;
+  } else if constexpr (LPR == 2) {
+    return __builtin_amdgcn_update_dpp(0, v, K | (K << 2) | ((2 + K) << 4) | ((2 + K) << 6), 0xF, 0xF, false);
+  } else if constexpr (LPR == 4) {
+    return __builtin_amdgcn_update_dpp(0, v, K * 0x55, 0xF, 0xF, false);
+  } else {
+    return __shfl(v, (int)(threadIdx.x & (kWave - 1) & ~(LPR - 1)) + K);
+  }
+}
+template <int LPR, int K>
+__device__ __forceinline__ float group_bcast(float v) {
+  return __int_as_float(group_bcast<LPR, K>(__float_as_int(v)));
+}
+template <int LPR, int K>
+__device__ __forceinline__ double group_bcast(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = group_bcast<LPR, K>((int)(b & 0xffffffffLL));
+  const int hi = group_bcast<LPR, K>((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 // Contiguous row range of block `blk` out of `nblk`, rounded to `step` rows,
 // with the block index remapped so that consecutive row ranges stay on one
 // XCD (workgroups are dealt round-robin over the 8 XCDs; each XCD has its
@@ -91,32 +138,6 @@ __device__ __forceinline__ void block_rows(int64_t n, int blk, int nblk, int ste
   r1 = r0 + per;
   if (r1 > n) r1 = n;
   if (r0 > n) r0 = n;
-}
-
-// Row range of a workgroup that belongs to a gang of G workgroups on one XCD
-// (launch width a multiple of 8 * G): the gang owns one contiguous range and
-// its members take turns on consecutive tiles of `step0` rows, so the gang
-// sweeps its range as one front.  The workgroup starts at r0 (its first tile)
-// and advances by `step` = G * step0; r1 bounds the gang's range.
-__device__ __forceinline__ void gang_rows(int64_t n, int blk, int nblk, int step0, int G, int64_t& r0, int64_t& r1,
-                                          int64_t& step) {
-  if (G == 0) G = nblk / 8;  // one gang per XCD
-  if (G <= 1 || nblk % (8 * G) != 0) {
-    block_rows(n, blk, nblk, step0, r0, r1);
-    step = step0;
-    return;
-  }
-  const int per_xcd = nblk / 8, xcd = blk % 8, local = blk / 8;
-  const int nstreams = nblk / G;
-  const int stream = xcd * (per_xcd / G) + local / G, sub = local % G;
-  int64_t per = (n + nstreams - 1) / nstreams;
-  per = (per + step0 - 1) / step0 * step0;
-  int64_t g0 = (int64_t)stream * per;
-  r1 = g0 + per;
-  if (r1 > n) r1 = n;
-  r0 = g0 + (int64_t)sub * step0;
-  if (r0 > r1) r0 = r1;
-  step = (int64_t)G * step0;
 }
 
 }  // namespace bkry

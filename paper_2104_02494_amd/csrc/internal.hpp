@@ -40,11 +40,16 @@ inline size_t red_gpart_count(int nblk, int s) {
   return (size_t)kMaxSlices * s * s;
 }
 
+// A sparse matrix as the kernels see it: CSR, plus optionally a padded
+// row-major copy (ELL, row width ell_w > 0) that the SpMM then reads instead.
 struct CsrView {
   int64_t n, nnz;
   const int32_t* rowptr;
   const int32_t* colind;
-  const void* val;  // double or float, by the launcher's T
+  const void* val;                  // double or float, by the launcher's T
+  int ell_w = 0;                    // 0: no ELL copy
+  const int32_t* ell_col = nullptr; // [n * ell_w], padding -1
+  const void* ell_val = nullptr;    // [n * ell_w], element type of val
 };
 
 // Device control block of a block CG solve.  The integer header is read back
@@ -186,6 +191,19 @@ hipError_t launch_ir_check(int s, const double* G, double* r0n, double* scale, d
 hipError_t launch_gm_backsub(GmCtl* ctl, const double* H, const double* sig, double* zeta, hipStream_t st);
 hipError_t launch_gm_cycle_init(GmCtl* ctl, double* sig, const double* sigma0, const double* G_R,
                                 int first_cycle, hipStream_t st);
+
+// ------------------------------------------------------------ ELL copy ----
+// Lanes per row of the streaming kernels for width s (element size in bytes).
+int spmm_lanes_per_row(int s, int elem_bytes);
+// ELL row widths are multiples of this chunk for width s.
+int ell_chunk(int s, int elem_bytes);
+// *wmax = longest row of A (enqueued on st; the caller reads it back).
+hipError_t launch_ell_width(const CsrView& A, int32_t* wmax, hipStream_t st);
+// Fill the ELL copy (row width W >= longest row) from A's CSR arrays with
+// values `val` converted to T; bad column indices set *bad = 1.
+template <typename Tin, typename T>
+hipError_t launch_ell_fill(const CsrView& A, const Tin* val, int W, int32_t* ecol, T* eval, int32_t* bad,
+                           hipStream_t st);
 
 // ---------------------------------------------------------------- TSQR ----
 // Workspace (bytes) needed by tsqr_run for n rows, width s, subalgebra sub.

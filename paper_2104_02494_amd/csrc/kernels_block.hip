@@ -31,42 +31,20 @@ namespace bkry {
 template <int V>
 using IC = std::integral_constant<int, V>;
 
-// Tuning constants (bytes per lane for width 8, workgroup cap for widths <= 8,
-// non-zeros per SpMM load batch).
-#ifndef BKRY_LANE_BYTES8
-#define BKRY_LANE_BYTES8 16
-#endif
-#ifndef BKRY_CAP8
-#define BKRY_CAP8 1024
-#endif
-#ifndef BKRY_SPMM_LDS
-#define BKRY_SPMM_LDS 0
-#endif
-#ifndef BKRY_NT
-#define BKRY_NT 0
-#endif
-#ifndef BKRY_GANG
-#define BKRY_GANG 1
-#endif
-#ifndef BKRY_NTL
-#define BKRY_NTL 0
-#endif
-#ifndef BKRY_UNROLL
-#define BKRY_UNROLL 8
-#endif
+// Non-zeros per SpMM load batch of the CSR kernel.
+constexpr int kUnroll = 8;
 
-// Calls f(IC<S>, IC<VEC>) for the block width s.  Powers of two move 16 or
-// 32 bytes per lane (32 bytes up to s = 8, where the per-lane Gram
-// accumulators still fit in registers, so that a wavefront keeps more rows
-// in flight); other widths run one element per lane in the next power of two.
+// Calls f(IC<S>, IC<VEC>) for the block width s.  Widths 1, 2 and 4 give a
+// lane a whole row; 8, 16 and 32 move 16 bytes per lane; other widths run one
+// element per lane in the next power of two.
 template <typename T, typename F>
 hipError_t dispatch_s(int s, F&& f) {
-  constexpr int v16 = 16 / (int)sizeof(T), v32 = 32 / (int)sizeof(T);
+  constexpr int v16 = 16 / (int)sizeof(T);
   switch (s) {
     case 1: return f(IC<1>{}, IC<1>{});
     case 2: return f(IC<2>{}, IC<2>{});
     case 4: return f(IC<4>{}, IC<4>{});
-    case 8: return f(IC<8>{}, IC<(BKRY_LANE_BYTES8 == 32 ? (8 < v32 ? 8 : v32) : v16)>{});
+    case 8: return f(IC<8>{}, IC<v16>{});
     case 16: return f(IC<16>{}, IC<v16>{});
     case 32: return f(IC<32>{}, IC<v16>{});
     default: break;
@@ -78,16 +56,10 @@ hipError_t dispatch_s(int s, F&& f) {
   return hipErrorInvalidValue;
 }
 
-// Store of a streaming output; with BKRY_NT the store carries the non-temporal
-// hint (the data is not re-read soon by this kernel).
+// Store of a streaming output.
 template <typename T, int N>
 __device__ __forceinline__ void store_out(T* p, const vec_t<T, N>& x) {
-#if BKRY_NT
-#pragma unroll
-  for (int i = 0; i < N; ++i) __builtin_nontemporal_store(x.v[i], p + i);
-#else
   store_vec<T, N>(p, x);
-#endif
 }
 
 static int next_pow2(int s) {
@@ -98,17 +70,19 @@ static int next_pow2(int s) {
 
 // VEC chosen by dispatch_s for width s and element size (host mirror).
 static int vec_for(int s, int elem_bytes) {
-  const int v16 = 16 / elem_bytes, v32 = 32 / elem_bytes;
+  const int v16 = 16 / elem_bytes;
   switch (s) {
     case 1: return 1;
     case 2: return 2;
     case 4: return 4;
-    case 8: return BKRY_LANE_BYTES8 == 32 ? (8 < v32 ? 8 : v32) : v16;
+    case 8: return v16;
     case 16:
     case 32: return v16;
     default: return 1;
   }
 }
+
+int spmm_lanes_per_row(int s, int elem_bytes) { return next_pow2(s) / vec_for(s, elem_bytes); }
 
 int stream_grid(int64_t n, int s, int elem_bytes) {
   int S = next_pow2(s);
@@ -116,7 +90,7 @@ int stream_grid(int64_t n, int s, int elem_bytes) {
   int LPR = S / VEC;
   int RPB = (kBlock / kWave) * (kWave / LPR);
   int64_t need = (n + RPB - 1) / RPB;
-  int cap = (S <= 8) ? BKRY_CAP8 : (S <= 16 ? 1024 : 512);
+  int cap = (S <= 16) ? 1024 : 512;
   int64_t g = need < cap ? need : cap;
   g = (g + 7) / 8 * 8;
   return (int)(g < 8 ? 8 : g);
@@ -192,21 +166,26 @@ __device__ __forceinline__ void gram_store(T (&acc)[VEC][S], int s, T* partial, 
   }
 }
 
-// ------------------------------------------------------------ reduction --
 // ------------------------------------------------------------------ SpMM --
 // MODE 0: Y = A X.  MODE 1: Y = A X and Gram partials of X_own^T Y.
-// MODE 2: Y = B - A X and Gram partials of Y^T Y.
+// MODE 2: Y = B - A X and Gram partials of Y^T Y.  Every product term is an
+// explicit fused multiply-add in storage order, so the CSR and ELL kernels
+// round identically.
+//
+// CSR kernel, software-pipelined: the row pointers of tile i+2 and the first
+// kUnroll non-zeros of tile i+1 are loaded while the X rows of tile i are
+// gathered, so one memory round trip per tile is exposed instead of three.
 template <typename T, int S, int VEC, int MODE>
-__global__ __launch_bounds__(kBlock) void spmm_kernel(int64_t n, int64_t nnz, const int32_t* __restrict__ rowptr,
-                                                       const int32_t* __restrict__ colind,
-                                                       const T* __restrict__ val, int s, const T* __restrict__ X,
-                                                       T* __restrict__ Y, const T* __restrict__ B,
-                                                       T* __restrict__ partial, int32_t* bad,
-                                                       const int32_t* done) {
+__global__ __launch_bounds__(kBlock) void spmm_csr_kernel(int64_t n, int64_t nnz, const int32_t* __restrict__ rowptr,
+                                                          const int32_t* __restrict__ colind,
+                                                          const T* __restrict__ val, int s, const T* __restrict__ X,
+                                                          T* __restrict__ Y, const T* __restrict__ B,
+                                                          T* __restrict__ partial, int32_t* bad,
+                                                          const int32_t* done) {
   using L = Layout<T, S, VEC>;
   constexpr int NW = kBlock / kWave;
   constexpr int RPB = NW * L::RPW;
-  constexpr int U = BKRY_UNROLL;
+  constexpr int U = kUnroll;
   constexpr int GA = MODE ? VEC : 1;
   constexpr int GB = MODE ? S : 1;
   __shared__ T sh[MODE ? NW * S * S : 1];
@@ -217,157 +196,7 @@ __global__ __launch_bounds__(kBlock) void spmm_kernel(int64_t n, int64_t nnz, co
   const bool active = col0 < s;
   int64_t r0, r1;
   block_rows(n, blockIdx.x, gridDim.x, RPB, r0, r1);
-  T gacc[GA][GB];
-#pragma unroll
-  for (int a = 0; a < GA; ++a)
-#pragma unroll
-    for (int b = 0; b < GB; ++b) gacc[a][b] = T(0);
-  bool badidx = false;
-
-#if BKRY_SPMM_LDS
-  // CSR segment of the wavefront's rows, staged through LDS with coalesced loads
-  constexpr int CH = 256;
-  __shared__ int32_t s_ci[NW][CH];
-  __shared__ T s_v[NW][CH];
-#endif
-  for (int64_t base = r0; base < r1; base += RPB) {
-    const int64_t row = base + wave * L::RPW + r;
-    const bool rv = row < r1 && active;
-    vec_t<T, VEC> acc = zero_vec<T, VEC>();
-#if BKRY_SPMM_LDS
-    {
-      const int64_t wrow0 = base + wave * L::RPW;
-      const int nrows = (int)((r1 - wrow0) < L::RPW ? (r1 - wrow0) : L::RPW);  // rows of this wavefront (may be <= 0)
-      int64_t rp = 0;
-      if (nrows > 0 && lane <= nrows) {
-        rp = rowptr[wrow0 + lane];
-        rp = rp < 0 ? 0 : (rp > nnz ? nnz : rp);
-      }
-      const int64_t kb = __shfl(rp, 0);
-      const int64_t ke = __shfl(rp, nrows > 0 ? nrows : 0);
-      int64_t my0 = __shfl(rp, r < nrows ? r : 0), my1 = __shfl(rp, r < nrows ? r + 1 : 0);
-      if (my1 < my0) my1 = my0;
-      const int64_t seg = ke > kb ? ke - kb : 0;
-      for (int64_t off = 0; off < seg; off += CH) {
-        const int cnt = (int)((seg - off) < CH ? (seg - off) : CH);
-        for (int t = lane; t < cnt; t += kWave) {
-          s_ci[wave][t] = colind[kb + off + t];
-          s_v[wave][t] = val[kb + off + t];
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        int64_t a = my0 - kb, e = my1 - kb;
-        if (a < off) a = off;
-        if (e > off + cnt) e = off + cnt;
-        if (rv) {
-          for (int64_t k = a; k < e; k += U) {
-            int jj[U];
-            T aa[U];
-            bool okk[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-              okk[u] = (k + u) < e;
-              jj[u] = okk[u] ? s_ci[wave][k + u - off] : 0;
-              aa[u] = okk[u] ? s_v[wave][k + u - off] : T(0);
-            }
-            vec_t<T, VEC> xx[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-              const bool okj = (uint32_t)jj[u] < (uint64_t)n;
-              badidx |= okk[u] && !okj;
-              xx[u] = (okk[u] && okj) ? load_vec<T, VEC>(X + (int64_t)jj[u] * s + col0) : zero_vec<T, VEC>();
-            }
-#pragma unroll
-            for (int u = 0; u < U; ++u)
-#pragma unroll
-              for (int w = 0; w < VEC; ++w) acc.v[w] += aa[u] * xx[u].v[w];
-          }
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      }
-      if (rv) {
-        if (MODE == 2) {
-          vec_t<T, VEC> b = load_vec<T, VEC>(B + row * s + col0);
-#pragma unroll
-          for (int w = 0; w < VEC; ++w) acc.v[w] = b.v[w] - acc.v[w];
-        }
-        store_out<T, VEC>(Y + row * s + col0, acc);
-      }
-    }
-#else
-    if (rv) {
-      int64_t k0 = rowptr[row], k1 = rowptr[row + 1];
-      if (k0 < 0) k0 = 0;
-      if (k1 > nnz) k1 = nnz;
-      for (int64_t k = k0; k < k1; k += U) {
-        int jj[U];
-        T aa[U];
-        bool okk[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-          okk[u] = (k + u) < k1;
-          jj[u] = okk[u] ? colind[k + u] : 0;
-          aa[u] = okk[u] ? val[k + u] : T(0);
-        }
-        vec_t<T, VEC> xx[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const bool okj = (uint32_t)jj[u] < (uint64_t)n;
-          badidx |= okk[u] && !okj;
-          xx[u] = (okk[u] && okj) ? load_vec<T, VEC>(X + (int64_t)jj[u] * s + col0) : zero_vec<T, VEC>();
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-#pragma unroll
-          for (int w = 0; w < VEC; ++w) acc.v[w] += aa[u] * xx[u].v[w];
-      }
-      if (MODE == 2) {
-        vec_t<T, VEC> b = load_vec<T, VEC>(B + row * s + col0);
-#pragma unroll
-        for (int w = 0; w < VEC; ++w) acc.v[w] = b.v[w] - acc.v[w];
-      }
-      store_out<T, VEC>(Y + row * s + col0, acc);
-    }
-#endif
-    if constexpr (MODE == 1) {
-      vec_t<T, VEC> own = rv ? load_vec<T, VEC>(X + row * s + col0) : zero_vec<T, VEC>();
-      gram_row<T, S, VEC>(gacc, own, acc, lane);
-    } else if constexpr (MODE == 2) {
-      gram_row<T, S, VEC>(gacc, acc, acc, lane);
-    }
-  }
-  if (badidx && bad) *bad = 1;
-  if constexpr (MODE != 0) gram_store<T, S, VEC>(gacc, s, partial, sh);
-}
-
-// Software-pipelined variant: the row pointers of tile i+2 and the first
-// U non-zeros of tile i+1 are loaded while the X rows of tile i are gathered,
-// so one memory round trip per tile is exposed instead of three.
-template <typename T, int S, int VEC, int MODE>
-__global__ __launch_bounds__(kBlock) void spmm_pf_kernel(int64_t n, int64_t nnz, const int32_t* __restrict__ rowptr,
-                                                          const int32_t* __restrict__ colind,
-                                                          const T* __restrict__ val, int s, const T* __restrict__ X,
-                                                          T* __restrict__ Y, const T* __restrict__ B,
-                                                          T* __restrict__ partial, int32_t* bad,
-                                                          const int32_t* done) {
-  using L = Layout<T, S, VEC>;
-  constexpr int NW = kBlock / kWave;
-  constexpr int RPB = NW * L::RPW;
-  constexpr int U = BKRY_UNROLL;
-  constexpr int GA = MODE ? VEC : 1;
-  constexpr int GB = MODE ? S : 1;
-  __shared__ T sh[MODE ? NW * S * S : 1];
-  if (done && *done) return;
-  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-  const int r = lane / L::LPR, c = lane % L::LPR;
-  const int col0 = c * VEC;
-  const bool active = col0 < s;
-  int64_t r0, r1;
-  int64_t step;
-  gang_rows(n, blockIdx.x, gridDim.x, RPB, BKRY_GANG, r0, r1, step);
+  const int64_t step = RPB;
   T gacc[GA][GB];
 #pragma unroll
   for (int a = 0; a < GA; ++a)
@@ -393,13 +222,8 @@ __global__ __launch_bounds__(kBlock) void spmm_pf_kernel(int64_t n, int64_t nnz,
     const int cnt = m <= 0 ? 0 : (m < U ? (int)m : U);
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-#if BKRY_NTL
-      jj[u] = u < cnt ? __builtin_nontemporal_load(colind + k0 + u) : 0;
-      aa[u] = u < cnt ? __builtin_nontemporal_load(val + k0 + u) : T(0);
-#else
       jj[u] = u < cnt ? colind[k0 + u] : 0;
       aa[u] = u < cnt ? val[k0 + u] : T(0);
-#endif
     }
     return cnt;
   };
@@ -432,7 +256,7 @@ __global__ __launch_bounds__(kBlock) void spmm_pf_kernel(int64_t n, int64_t nnz,
 #pragma unroll
     for (int u = 0; u < U; ++u)
 #pragma unroll
-      for (int w = 0; w < VEC; ++w) acc.v[w] += ca[u] * xx[u].v[w];
+      for (int w = 0; w < VEC; ++w) acc.v[w] = fma(ca[u], xx[u].v[w], acc.v[w]);
     // rows longer than U: remaining entries without pipelining
     for (int64_t k = k0c + U; k < k1c; k += U) {
       int jj[U];
@@ -453,7 +277,7 @@ __global__ __launch_bounds__(kBlock) void spmm_pf_kernel(int64_t n, int64_t nnz,
 #pragma unroll
       for (int u = 0; u < U; ++u)
 #pragma unroll
-        for (int w = 0; w < VEC; ++w) acc.v[w] += aa[u] * xx[u].v[w];
+        for (int w = 0; w < VEC; ++w) acc.v[w] = fma(aa[u], xx[u].v[w], acc.v[w]);
     }
     if (MODE == 2) {
 #pragma unroll
@@ -480,17 +304,114 @@ __global__ __launch_bounds__(kBlock) void spmm_pf_kernel(int64_t n, int64_t nnz,
   if constexpr (MODE != 0) gram_store<T, S, VEC>(gacc, s, partial, sh);
 }
 
-#ifndef BKRY_FIT_GRID
-#define BKRY_FIT_GRID 1
-#endif
-#ifndef BKRY_SPMM_PF
-#define BKRY_SPMM_PF 1
-#endif
-#if BKRY_SPMM_PF
-#define BKRY_SPMM_KERNEL spmm_pf_kernel
-#else
-#define BKRY_SPMM_KERNEL spmm_kernel
-#endif
+// SpMM on the padded row-major (ELL) copy of A: row i's entries sit at
+// [i*W, i*W + W), padding marked by column -1.  The LPR lanes of a row load a
+// chunk of C = LPR*E consecutive entries with one E-wide load each (so the
+// matrix stream is read with fully coalesced loads and no row pointers), and
+// the entries are passed around the row group with lane permutations before
+// the gathers.  The first chunk of the next tile is loaded while the current
+// tile gathers.  Entries are summed in storage order, padding contributing
+// nothing, so the result equals the CSR kernel's bit for bit.
+template <typename T, int S, int VEC, int MODE>
+__global__ __launch_bounds__(kBlock) void spmm_ell_kernel(int64_t n, int W, const int32_t* __restrict__ ecol,
+                                                           const T* __restrict__ eval, int s,
+                                                           const T* __restrict__ X, T* __restrict__ Y,
+                                                           const T* __restrict__ B, T* __restrict__ partial,
+                                                           const int32_t* done) {
+  using L = Layout<T, S, VEC>;
+  constexpr int LPR = L::LPR;
+  constexpr int E = ell_entries_per_lane(LPR);
+  constexpr int C = LPR * E;
+  constexpr int NW = kBlock / kWave;
+  constexpr int RPB = NW * L::RPW;
+  constexpr int GA = MODE ? VEC : 1;
+  constexpr int GB = MODE ? S : 1;
+  __shared__ T sh[MODE ? NW * S * S : 1];
+  if (done && *done) return;
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  const int r = lane / LPR, c = lane % LPR;
+  const int col0 = c * VEC;
+  const bool active = col0 < s;
+  int64_t r0, r1;
+  block_rows(n, blockIdx.x, gridDim.x, RPB, r0, r1);
+  const int64_t step = RPB;
+  T gacc[GA][GB];
+#pragma unroll
+  for (int a = 0; a < GA; ++a)
+#pragma unroll
+    for (int b = 0; b < GB; ++b) gacc[a][b] = T(0);
+  const int64_t roff = wave * L::RPW + r;
+  const int nch = W / C;
+
+  // this lane's E entries of chunk j of row rw (padding outside the range)
+  auto ld = [&](int64_t rw, int j, vec_t<int32_t, E>& cj, vec_t<T, E>& ca) {
+    if (rw < r1) {
+      const int64_t k = rw * W + (int64_t)j * C + c * E;
+      cj = load_vec<int32_t, E>(ecol + k);
+      ca = load_vec<T, E>(eval + k);
+    } else {
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        cj.v[e] = -1;
+        ca.v[e] = T(0);
+      }
+    }
+  };
+  // acc += sum over the chunk's C entries, in storage order
+  auto chunk = [&](const vec_t<int32_t, E>& cj, const vec_t<T, E>& ca, bool rv, vec_t<T, VEC>& acc) {
+    int jj[C];
+    T aa[C];
+    static_for<C>([&](auto u_) {
+      constexpr int u = decltype(u_)::value;
+      jj[u] = group_bcast<LPR, u / E>(cj.v[u % E]);
+      aa[u] = group_bcast<LPR, u / E>(ca.v[u % E]);
+    });
+    vec_t<T, VEC> xx[C];
+#pragma unroll
+    for (int u = 0; u < C; ++u) {
+      const bool ok = rv && (uint32_t)jj[u] < (uint64_t)n;
+      xx[u] = ok ? load_vec<T, VEC>(X + (int64_t)jj[u] * s + col0) : zero_vec<T, VEC>();
+      if (!ok) aa[u] = T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < C; ++u)
+#pragma unroll
+      for (int w = 0; w < VEC; ++w) acc.v[w] = fma(aa[u], xx[u].v[w], acc.v[w]);
+  };
+
+  vec_t<int32_t, E> cj, nj;
+  vec_t<T, E> ca, na;
+  ld(r0 + roff, 0, cj, ca);
+  for (int64_t base = r0; base < r1; base += step) {
+    const int64_t row = base + roff;
+    const bool rv = row < r1 && active;
+    ld(row + step, 0, nj, na);
+    vec_t<T, VEC> own = zero_vec<T, VEC>();
+    if (MODE == 1 && rv) own = load_vec<T, VEC>(X + row * s + col0);
+    if (MODE == 2 && rv) own = load_vec<T, VEC>(B + row * s + col0);
+    vec_t<T, VEC> acc = zero_vec<T, VEC>();
+    chunk(cj, ca, rv, acc);
+    for (int j = 1; j < nch; ++j) {
+      vec_t<int32_t, E> kj;
+      vec_t<T, E> ka;
+      ld(row, j, kj, ka);
+      chunk(kj, ka, rv, acc);
+    }
+    if (MODE == 2) {
+#pragma unroll
+      for (int w = 0; w < VEC; ++w) acc.v[w] = own.v[w] - acc.v[w];
+    }
+    if (rv) store_out<T, VEC>(Y + row * s + col0, acc);
+    if constexpr (MODE == 1) {
+      gram_row<T, S, VEC>(gacc, own, acc, lane);
+    } else if constexpr (MODE == 2) {
+      gram_row<T, S, VEC>(gacc, acc, acc, lane);
+    }
+    cj = nj;
+    ca = na;
+  }
+  if constexpr (MODE != 0) gram_store<T, S, VEC>(gacc, s, partial, sh);
+}
 
 // Workgroups of kernel K that the device holds at once (cached per kernel).
 template <auto K>
@@ -524,22 +445,37 @@ hipError_t launch_spmm(const CsrView& A, int s, const T* X, T* Y, const T* B, in
   hipError_t e = dispatch_s<T>(s, [&](auto S_, auto V_) -> hipError_t {
     constexpr int S = decltype(S_)::value, V = decltype(V_)::value;
     const T* val = static_cast<const T*>(A.val);
-#if BKRY_FIT_GRID
+    if (A.ell_w > 0) {
+      const T* ev = static_cast<const T*>(A.ell_val);
+      if (mode == 0) {
+        nblk = fit_grid<spmm_ell_kernel<T, S, V, 0>>(nblk);
+        hipLaunchKernelGGL((spmm_ell_kernel<T, S, V, 0>), dim3(nblk), dim3(kBlock), 0, st, A.n, A.ell_w, A.ell_col,
+                           ev, s, X, Y, B, partial, done);
+      } else if (mode == 1) {
+        nblk = fit_grid<spmm_ell_kernel<T, S, V, 1>>(nblk);
+        hipLaunchKernelGGL((spmm_ell_kernel<T, S, V, 1>), dim3(nblk), dim3(kBlock), 0, st, A.n, A.ell_w, A.ell_col,
+                           ev, s, X, Y, B, partial, done);
+      } else {
+        nblk = fit_grid<spmm_ell_kernel<T, S, V, 2>>(nblk);
+        hipLaunchKernelGGL((spmm_ell_kernel<T, S, V, 2>), dim3(nblk), dim3(kBlock), 0, st, A.n, A.ell_w, A.ell_col,
+                           ev, s, X, Y, B, partial, done);
+      }
+      return hipGetLastError();
+    }
     if (mode == 0)
-      nblk = fit_grid<BKRY_SPMM_KERNEL<T, S, V, 0>>(nblk);
+      nblk = fit_grid<spmm_csr_kernel<T, S, V, 0>>(nblk);
     else if (mode == 1)
-      nblk = fit_grid<BKRY_SPMM_KERNEL<T, S, V, 1>>(nblk);
+      nblk = fit_grid<spmm_csr_kernel<T, S, V, 1>>(nblk);
     else
-      nblk = fit_grid<BKRY_SPMM_KERNEL<T, S, V, 2>>(nblk);
-#endif
+      nblk = fit_grid<spmm_csr_kernel<T, S, V, 2>>(nblk);
     if (mode == 0)
-      hipLaunchKernelGGL((BKRY_SPMM_KERNEL<T, S, V, 0>), dim3(nblk), dim3(kBlock), 0, st, A.n, A.nnz, A.rowptr,
+      hipLaunchKernelGGL((spmm_csr_kernel<T, S, V, 0>), dim3(nblk), dim3(kBlock), 0, st, A.n, A.nnz, A.rowptr,
                          A.colind, val, s, X, Y, B, partial, bad, done);
     else if (mode == 1)
-      hipLaunchKernelGGL((BKRY_SPMM_KERNEL<T, S, V, 1>), dim3(nblk), dim3(kBlock), 0, st, A.n, A.nnz, A.rowptr,
+      hipLaunchKernelGGL((spmm_csr_kernel<T, S, V, 1>), dim3(nblk), dim3(kBlock), 0, st, A.n, A.nnz, A.rowptr,
                          A.colind, val, s, X, Y, B, partial, bad, done);
     else
-      hipLaunchKernelGGL((BKRY_SPMM_KERNEL<T, S, V, 2>), dim3(nblk), dim3(kBlock), 0, st, A.n, A.nnz, A.rowptr,
+      hipLaunchKernelGGL((spmm_csr_kernel<T, S, V, 2>), dim3(nblk), dim3(kBlock), 0, st, A.n, A.nnz, A.rowptr,
                          A.colind, val, s, X, Y, B, partial, bad, done);
     return hipGetLastError();
   });

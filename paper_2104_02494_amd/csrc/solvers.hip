@@ -251,6 +251,9 @@ hipError_t ir_run(const CsrView& A, Sub sub, const double* B, double* X, double 
   BK_TRY(launch_cast_f32(A.nnz, static_cast<const double*>(A.val), b.A32, st));
   CsrView A32 = A;
   A32.val = b.A32;
+  A32.ell_w = b.ell_w;
+  A32.ell_col = b.ell_col;
+  A32.ell_val = b.ell_val;
   int32_t* dflag = b.flag;
   BK_TRY(hipMemsetAsync(dflag, 0, 4 * sizeof(int32_t), st));
   for (int outer = 0;; ++outer) {

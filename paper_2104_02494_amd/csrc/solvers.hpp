@@ -73,6 +73,10 @@ struct IrBufs {
   int32_t* flag = nullptr;
   uint32_t* cnt = nullptr;
   CgBufs<float> cg;
+  // optional FP32 ELL copy of A for the inner solves (filled by the caller)
+  int ell_w = 0;
+  const int32_t* ell_col = nullptr;
+  const float* ell_val = nullptr;
 };
 IrBufs carve_ir(Carver& c, int64_t n, int64_t nnz, Sub sub, uint32_t* cnt);
 
