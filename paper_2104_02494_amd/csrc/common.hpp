@@ -140,4 +140,31 @@ __device__ __forceinline__ void block_rows(int64_t n, int blk, int nblk, int ste
   if (r0 > n) r0 = n;
 }
 
+// Row range of a workgroup that belongs to a gang of G workgroups on one XCD
+// (workgroups blk = x, x + 8, x + 16, ... run on XCD x): the gang owns one
+// contiguous range and its members take turns on consecutive tiles of
+// `step0` rows, so the gang sweeps its range as one front.  The workgroup
+// starts at r0 (its first tile) and advances by `step` = G * step0; r1 bounds
+// the gang's range.  Gangs of one XCD own adjacent ranges.  When the launch
+// width is not a multiple of 8 * G, this is block_rows with step = step0.
+__device__ __forceinline__ void gang_rows(int64_t n, int blk, int nblk, int step0, int G, int64_t& r0, int64_t& r1,
+                                          int64_t& step) {
+  if (G <= 1 || nblk % (8 * G) != 0) {
+    block_rows(n, blk, nblk, step0, r0, r1);
+    step = step0;
+    return;
+  }
+  const int per_xcd = nblk / 8, xcd = blk % 8, local = blk / 8;
+  const int nstreams = nblk / G;
+  const int stream = xcd * (per_xcd / G) + local / G, sub = local % G;
+  int64_t per = (n + nstreams - 1) / nstreams;
+  per = (per + step0 - 1) / step0 * step0;
+  int64_t g0 = (int64_t)stream * per;
+  r1 = g0 + per;
+  if (r1 > n) r1 = n;
+  r0 = g0 + (int64_t)sub * step0;
+  if (r0 > r1) r0 = r1;
+  step = (int64_t)G * step0;
+}
+
 }  // namespace bkry

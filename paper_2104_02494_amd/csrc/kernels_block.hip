@@ -33,6 +33,8 @@ using IC = std::integral_constant<int, V>;
 
 // Non-zeros per SpMM load batch of the CSR kernel.
 constexpr int kUnroll = 8;
+// Workgroups per gang of the ELL SpMM (see gang_rows).
+constexpr int kGang = 8;
 
 // Calls f(IC<S>, IC<VEC>) for the block width s.  Widths 1, 2 and 4 give a
 // lane a whole row; 8, 16 and 32 move 16 bytes per lane; other widths run one
@@ -312,6 +314,12 @@ __global__ __launch_bounds__(kBlock) void spmm_csr_kernel(int64_t n, int64_t nnz
 // the gathers.  The first chunk of the next tile is loaded while the current
 // tile gathers.  Entries are summed in storage order, padding contributing
 // nothing, so the result equals the CSR kernel's bit for bit.
+//
+// Cache use: every matrix line is consumed by one load, so the matrix stream
+// is read with the non-temporal hint and leaves the L2 to the gathered X
+// rows; gangs of kGang workgroups sweep one row range together (gang_rows),
+// so an XCD runs few concurrent row fronts and the X rows that neighbouring
+// rows share (a banded or stencil pattern) are still in its L2 when reused.
 template <typename T, int S, int VEC, int MODE>
 __global__ __launch_bounds__(kBlock) void spmm_ell_kernel(int64_t n, int W, const int32_t* __restrict__ ecol,
                                                            const T* __restrict__ eval, int s,
@@ -332,9 +340,8 @@ __global__ __launch_bounds__(kBlock) void spmm_ell_kernel(int64_t n, int W, cons
   const int r = lane / LPR, c = lane % LPR;
   const int col0 = c * VEC;
   const bool active = col0 < s;
-  int64_t r0, r1;
-  block_rows(n, blockIdx.x, gridDim.x, RPB, r0, r1);
-  const int64_t step = RPB;
+  int64_t r0, r1, step;
+  gang_rows(n, blockIdx.x, gridDim.x, RPB, kGang, r0, r1, step);
   T gacc[GA][GB];
 #pragma unroll
   for (int a = 0; a < GA; ++a)
@@ -347,8 +354,11 @@ __global__ __launch_bounds__(kBlock) void spmm_ell_kernel(int64_t n, int W, cons
   auto ld = [&](int64_t rw, int j, vec_t<int32_t, E>& cj, vec_t<T, E>& ca) {
     if (rw < r1) {
       const int64_t k = rw * W + (int64_t)j * C + c * E;
-      cj = load_vec<int32_t, E>(ecol + k);
-      ca = load_vec<T, E>(eval + k);
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        cj.v[e] = __builtin_nontemporal_load(ecol + k + e);
+        ca.v[e] = __builtin_nontemporal_load(eval + k + e);
+      }
     } else {
 #pragma unroll
       for (int e = 0; e < E; ++e) {

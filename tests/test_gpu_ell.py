@@ -40,6 +40,23 @@ def test_ell_spmm_integer_bit_exact(orc, hh, s):
     assert np.array_equal(Y, orc.spmm(A, X))
 
 
+@pytest.mark.parametrize("s", [8, 16])
+@pytest.mark.parametrize("mat", ["laplace2d_90", "laplace3d_20"])
+def test_ell_spmm_gangs_integer_bit_exact(orc, hh, s, mat):
+    """Sizes whose launch width is a multiple of 64 workgroups, so that the
+    rows are swept by gangs of workgroups (with a ragged last tile)."""
+    A = W.laplace_2d(90) if mat == "laplace2d_90" else W.laplace_3d(20)
+    X = np.random.default_rng(s).integers(-8, 9, size=(A.n, s)).astype(np.float64)
+    say("ell gangs int", mat, s)
+    Ad, Xd = dev_csr(P, A), to_dev(X)
+    Ye = to_np(P.bkry_spmm(hh["ell"], Ad, Xd))
+    assert np.array_equal(Ye, orc.spmm(A, X))
+    Xg = W.gaussian_block(A.n, s, 3)
+    Ye = to_np(P.bkry_spmm(hh["ell"], Ad, to_dev(Xg)))
+    Yc = to_np(P.bkry_spmm(hh["csr"], Ad, to_dev(Xg)))
+    assert np.array_equal(Ye.view(np.uint64), Yc.view(np.uint64))
+
+
 @pytest.mark.parametrize("s", WIDTHS)
 @pytest.mark.parametrize("mat", ["diffusion27", "random"])
 def test_ell_spmm_matches_csr_bitwise(hh, s, mat):
