@@ -175,7 +175,7 @@ hipError_t launch_sddmm(const CsrView& A, int s, double alpha, const T* L, const
 // Single-workgroup kernels on the p x p coefficients (FP64).
 hipError_t launch_project(const double* G, double* out, Sub sub, hipStream_t st);
 hipError_t launch_cg_init(CgCtl* ctl, const double* G_R0, const double* G_rho, hipStream_t st);
-hipError_t launch_cg_reortho_fin(CgCtl* ctl, const double* G, hipStream_t st);
+hipError_t launch_cg_reortho_fin(CgCtl* ctl, int s, const double* G, hipStream_t st);
 // Normaliser coefficients for parallel / global: from the Gram G of X, write
 // the column divisors d and N (p x p) to `out_N` (gated like the CG kernels).
 hipError_t launch_norm_diag(const double* G, Sub sub, double* d, double* out_N, const int32_t* gate_done,

@@ -29,6 +29,14 @@ namespace bkry {
 constexpr int kSB = 64;         // threads of the small-algebra workgroups (one wavefront)
 constexpr int kSS = kMaxS * kMaxS;
 
+// Register tile (SM >= s) of the Cholesky solves for width s.
+template <typename F>
+static hipError_t dispatch_sm(int s, F&& f) {
+  if (s <= 8) return f(std::integral_constant<int, 8>{});
+  if (s <= 16) return f(std::integral_constant<int, 16>{});
+  return f(std::integral_constant<int, 32>{});
+}
+
 __device__ __forceinline__ int tid() { return threadIdx.x; }
 
 // Reductions over the workgroup's single wavefront (every lane receives the
@@ -45,17 +53,17 @@ __device__ __forceinline__ double wmax(double v) {
 }
 __device__ __forceinline__ bool wany(bool b) { return __any(b ? 1 : 0) != 0; }
 
-__device__ void sm_copy(double* dst, const double* src, int count) {
+__device__ __forceinline__ void sm_copy(double* dst, const double* src, int count) {
   for (int t = tid(); t < count; t += kSB) dst[t] = src[t];
 }
 
-__device__ void sm_eye(double* M, int s) {
+__device__ __forceinline__ void sm_eye(double* M, int s) {
   for (int t = tid(); t < s * s; t += kSB) M[t] = (t / s == t % s) ? 1.0 : 0.0;
 }
 
 // Projection onto the subalgebra (zero outside the g x g diagonal blocks;
 // global: tr/s * I).
-__device__ void sm_project(double* M, const Sub& sub, double* scratch1) {
+__device__ __forceinline__ void sm_project(double* M, const Sub& sub, double* scratch1) {
   const int s = sub.s;
   __syncthreads();
   if (sub.kind == GLOBAL) {
@@ -72,7 +80,7 @@ __device__ void sm_project(double* M, const Sub& sub, double* scratch1) {
 }
 
 // C = A B (transA: C = A^T B); C must not alias A or B.
-__device__ void sm_mm(double* C, const double* A, const double* B, int s, bool transA) {
+__device__ __forceinline__ void sm_mm(double* C, const double* A, const double* B, int s, bool transA) {
   __syncthreads();
   for (int t = tid(); t < s * s; t += kSB) {
     const int i = t / s, j = t % s;
@@ -83,56 +91,11 @@ __device__ void sm_mm(double* C, const double* A, const double* B, int s, bool t
   __syncthreads();
 }
 
-// In-place Cholesky A = L L^T (lower triangle); false on a non-positive or
-// non-finite pivot.
-__device__ bool sm_cholesky(double* A, int s, int* flag) {
-  for (int j = 0; j < s; ++j) {
-    __syncthreads();
-    if (tid() == 0) {
-      const double d = A[j * s + j];
-      const bool ok = (d > 0.0) && isfinite(d);
-      flag[0] = ok ? 1 : 0;
-      if (ok) A[j * s + j] = sqrt(d);
-    }
-    __syncthreads();
-    if (!flag[0]) return false;
-    const double ljj = A[j * s + j];
-    for (int i = j + 1 + tid(); i < s; i += kSB) A[i * s + j] /= ljj;
-    __syncthreads();
-    const int m = s - j - 1;
-    for (int e = tid(); e < m * m; e += kSB) {
-      const int i = j + 1 + e / m, k = j + 1 + e % m;
-      if (k <= i) A[i * s + k] -= A[i * s + j] * A[k * s + j];
-    }
-  }
-  __syncthreads();
-  return true;
-}
-
-// X = L^-T L^-1 B, one thread per column of B.
-__device__ void sm_chol_solve(const double* L, const double* B, double* X, int s) {
-  __syncthreads();
-  const int col = tid();
-  if (col < s) {
-    for (int i = 0; i < s; ++i) {
-      double sum = B[i * s + col];
-      for (int k = 0; k < i; ++k) sum -= L[i * s + k] * X[k * s + col];
-      X[i * s + col] = sum / L[i * s + i];
-    }
-    for (int i = s - 1; i >= 0; --i) {
-      double sum = X[i * s + col];
-      for (int k = i + 1; k < s; ++k) sum -= L[k * s + i] * X[k * s + col];
-      X[i * s + col] = sum / L[i * s + i];
-    }
-  }
-  __syncthreads();
-}
-
 // kappa_D(A) = kappa(D^-1/2 A D^-1/2) (Definition "Diagonally scaled condition
 // number", Ch. 4) from the eigenvalues of the scaled matrix by the parallel
 // (round-robin) cyclic Jacobi method.  Infinity if a diagonal entry or the
 // smallest eigenvalue is not positive.
-__device__ double sm_kappaD(const double* A, int s, double* M, double* T, double* rc, double* rs, int* partner,
+__device__ __forceinline__ double sm_kappaD(const double* A, int s, double* M, double* T, double* rc, double* rs, int* partner,
                             int* first, double* red) {
   const int sp = s + (s & 1);
   __syncthreads();
@@ -221,22 +184,116 @@ __device__ double sm_kappaD(const double* A, int s, double* M, double* T, double
 // an exact upper bound is tried: with M = D^-1/2 alpha D^-1/2 = L_M L_M^T,
 // kappa_D = |M|_2 |M^-1|_2 <= |M|_F |L_M^-1|_F^2; when even the bound does not
 // fire, the test does not fire (same decision as with kappa_D itself).
-__device__ bool reortho_test(CgCtl* c, const double* alpha, const double* L, double* M, double* T, double* rc,
-                             double* rs, int* partner, int* first, double* red) {
+// ---------------------------------------- register-resident Cholesky --
+// Value of v in lane `lane` (uniform result; the lane need not be active).
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// X = A^-1 B for SPD A (s x s, s <= SM, LDS) through A = L L^T, and, if Linv
+// is not null, Linv = L^-1 (LDS; zero above the diagonal).  The factor lives
+// in registers, lane i holding row i; each right-hand side column lives in
+// the registers of its own lane; entries of L reach the other lanes by lane
+// reads, so the whole factor-and-solve runs without LDS round trips.  The
+// reciprocals of the pivots are formed once, so the only divisions are the
+// s reciprocals.  Returns false (uniformly) on a non-positive or non-finite
+// pivot.
+template <int SM>
+__device__ __forceinline__ bool rf_cholesky_solve(const double* A, const double* B, double* X, double* Linv, int s) {
+  __syncthreads();
+  const int t = tid();
+  double l[SM], rinv[SM];
+#pragma unroll
+  for (int j = 0; j < SM; ++j) l[j] = (t < s && j < s) ? A[t * s + j] : 0.0;
+#pragma unroll
+  for (int k = 0; k < SM; ++k) {
+    rinv[k] = 0.0;
+    if (k < s) {
+      const double d = readlane_d(l[k], k);
+      if (!(d > 0.0) || !isfinite(d)) return false;
+      const double lkk = sqrt(d);
+      rinv[k] = 1.0 / lkk;
+      if (t == k)
+        l[k] = lkk;
+      else if (t > k)
+        l[k] = l[k] * rinv[k];
+#pragma unroll
+      for (int j = k + 1; j < SM; ++j) {
+        if (j < s) {
+          const double ljk = readlane_d(l[k], j);
+          if (t >= j) l[j] = fma(-l[k], ljk, l[j]);
+        }
+      }
+    }
+  }
+  double x[SM];
+#pragma unroll
+  for (int i = 0; i < SM; ++i) x[i] = (t < s && i < s) ? B[i * s + t] : 0.0;
+#pragma unroll
+  for (int i = 0; i < SM; ++i) {  // L y = b
+    if (i < s) {
+      double acc = x[i];
+#pragma unroll
+      for (int k = 0; k < i; ++k) acc = fma(-readlane_d(l[k], i), x[k], acc);
+      x[i] = acc * rinv[i];
+    }
+  }
+#pragma unroll
+  for (int i = SM - 1; i >= 0; --i) {  // L^T x = y
+    if (i < s) {
+      double acc = x[i];
+#pragma unroll
+      for (int k = i + 1; k < SM; ++k)
+        if (k < s) acc = fma(-readlane_d(l[i], k), x[k], acc);
+      x[i] = acc * rinv[i];
+    }
+  }
+  if (t < s) {
+#pragma unroll
+    for (int i = 0; i < SM; ++i)
+      if (i < s) X[i * s + t] = x[i];
+  }
+  if (Linv) {  // column t of L^-1
+    double y[SM];
+#pragma unroll
+    for (int i = 0; i < SM; ++i) {
+      if (i < s) {
+        double acc = (i == t) ? 1.0 : 0.0;
+#pragma unroll
+        for (int k = 0; k < i; ++k) acc = fma(-readlane_d(l[k], i), y[k], acc);
+        y[i] = acc * rinv[i];
+      } else {
+        y[i] = 0.0;
+      }
+    }
+    if (t < s) {
+#pragma unroll
+      for (int i = 0; i < SM; ++i)
+        if (i < s) Linv[i * s + t] = y[i];
+    }
+  }
+  __syncthreads();
+  return true;
+}
+
+// The re-orthonormalisation is decided per iteration (the L^-1 bound of the
+// kappa_D test is needed) only for 0 < eta < inf, eta sqrt(eps) <= 1, g > 1.
+__device__ __forceinline__ bool reortho_dynamic(const CgCtl* c) {
+  return c->eta > 0.0 && !isinf(c->eta) && !(c->eta * c->sqrt_eps > 1.0) && c->g > 1;
+}
+
+// The kappa_D test of the iteration.  T holds L^-1 (alpha = L L^T) whenever
+// reortho_dynamic(c); it is then overwritten.
+__device__ __forceinline__ bool reortho_test(CgCtl* c, const double* alpha, double* M, double* T, double* rc,
+                                             double* rs, int* partner, int* first, double* red) {
   if (!(c->eta > 0.0)) return false;
   if (isinf(c->eta)) return true;
   const int s = c->s;
   if (c->eta * c->sqrt_eps > 1.0) return true;  // kappa_D >= 1
   if (c->g <= 1) return false;                  // kappa_D = 1
-  __syncthreads();
-  const int col = tid();
-  if (col < s) {  // column col of L^-1
-    for (int i = 0; i < s; ++i) {
-      double sum = (i == col) ? 1.0 : 0.0;
-      for (int k = 0; k < i; ++k) sum -= L[i * s + k] * T[k * s + col];
-      T[i * s + col] = sum / L[i * s + i];
-    }
-  }
   __syncthreads();
   double fm = 0.0, li = 0.0;
   for (int e = tid(); e < s * s; e += kSB) {
@@ -252,14 +309,14 @@ __device__ bool reortho_test(CgCtl* c, const double* alpha, const double* L, dou
   return c->eta * kd * c->sqrt_eps > 1.0;
 }
 
-__device__ void store_coeff(double* d64, float* d32, const double* src, int s) {
+__device__ __forceinline__ void store_coeff(double* d64, float* d32, const double* src, int s) {
   for (int t = tid(); t < s * s; t += kSB) {
     d64[t] = src[t];
     d32[t] = (float)src[t];
   }
 }
 
-__device__ bool all_finite(const double* M, int count, double* red) {
+__device__ __forceinline__ bool all_finite(const double* M, int count, double* red) {
   (void)red;
   __syncthreads();
   bool bad = false;
@@ -346,10 +403,13 @@ hipError_t launch_cg_init(CgCtl* ctl, const double* G_R0, const double* G_rho, h
 
 // alpha = <P, Q>_S; lambda = alpha^-1 rho; lambda sigma; the kappa_D test.
 // Runs only while the solve is live and not suspended (the caller checks).
-__device__ void cg_alpha_body(CgCtl* c, const double* G) {
-  __shared__ double Al[kSS], L[kSS], Rh[kSS], Lm[kSS], W[kSS], T[kSS];
+// rho_l, sigma_l: copies of c->rho and c->sigma (LDS, loaded by the caller).
+template <int SM>
+__device__ __forceinline__ void cg_alpha_body(CgCtl* c, const double* G, const double* rho_l,
+                                              const double* sigma_l) {
+  __shared__ double Al[kSS], Lm[kSS], LS[kSS], W[kSS], T[kSS];
   __shared__ double rc[kMaxS], rs[kMaxS], red[4];
-  __shared__ int partner[kMaxS], first[kMaxS], flag[1];
+  __shared__ int partner[kMaxS], first[kMaxS];
   const int s = c->s;
   const Sub sub{c->kind, s, c->g};
   sm_copy(Al, G, s * s);
@@ -364,10 +424,8 @@ __device__ void cg_alpha_body(CgCtl* c, const double* G) {
     }
     return;
   }
-  sm_copy(L, Al, s * s);
-  sm_copy(Rh, c->rho, s * s);
-  __syncthreads();
-  if (!sm_cholesky(L, s, flag)) {
+  // lambda = alpha^-1 rho, and L^-1 when the kappa_D test needs its bound
+  if (!rf_cholesky_solve<SM>(Al, rho_l, Lm, reortho_dynamic(c) ? T : nullptr, s)) {
     if (tid() == 0) {
       c->status = -2;
       c->done = 1;
@@ -376,13 +434,11 @@ __device__ void cg_alpha_body(CgCtl* c, const double* G) {
     }
     return;
   }
-  sm_chol_solve(L, Rh, Lm, s);          // lambda = alpha^-1 rho
-  sm_copy(W, c->sigma, s * s);
-  sm_mm(T, Lm, W, s, false);            // lambda sigma
+  sm_mm(LS, Lm, sigma_l, s, false);  // lambda sigma
   store_coeff(c->lam, c->lam_f, Lm, s);
-  store_coeff(c->lamsig, c->lamsig_f, T, s);
+  store_coeff(c->lamsig, c->lamsig_f, LS, s);
   sm_copy(c->alpha, Al, s * s);
-  const bool fire = reortho_test(c, Al, L, W, T, rc, rs, partner, first, red);
+  const bool fire = reortho_test(c, Al, W, T, rc, rs, partner, first, red);
   __syncthreads();
   if (tid() == 0) {
     c->fire = fire ? 1 : 0;
@@ -394,14 +450,17 @@ __device__ void cg_alpha_body(CgCtl* c, const double* G) {
 // test, and (no normalisation this iteration) rho' = <R~, R~>_S and
 // beta = rho^-1 rho'.  Runs only while the iteration is live (the caller
 // checks the gate).
-__device__ void cg_rho_body(CgCtl* c, const double* G, double* hist) {
-  __shared__ double Gm[kSS], Sg[kSS], T1[kSS], L[kSS], Bt[kSS];
+// rho_l, sigma_l, r0n_l: copies of c->rho, c->sigma and c->r0n (LDS).
+template <int SM>
+__device__ __forceinline__ void cg_rho_body(CgCtl* c, const double* G, double* hist, const double* rho_l,
+                                            const double* sigma_l, const double* r0n_l) {
+  __shared__ double Gm[kSS], T1[kSS], Bt[kSS];
   __shared__ double red[4];
-  __shared__ int flag[2];
+  __shared__ int flag[1];
   const int s = c->s;
   const Sub sub{c->kind, s, c->g};
+  const double* Sg = sigma_l;
   sm_copy(Gm, G, s * s);
-  sm_copy(Sg, c->sigma, s * s);
   sm_mm(T1, Gm, Sg, s, false);  // G sigma
   // column norms of R~ sigma: sqrt(diag(sigma^T G sigma)), one lane per column
   double rel = 0.0;
@@ -410,7 +469,7 @@ __device__ void cg_rho_body(CgCtl* c, const double* G, double* hist) {
     double acc = 0.0;
     for (int a = 0; a < s; ++a) acc += Sg[a * s + i] * T1[a * s + i];
     const double cn = sqrt(fmax(acc, 0.0));
-    const double r = c->r0n[i] > 0.0 ? cn / c->r0n[i] : 0.0;
+    const double r = r0n_l[i] > 0.0 ? cn / r0n_l[i] : 0.0;
     nanl |= !isfinite(acc);
     c->relres[i] = r;
     rel = fmax(rel, r);
@@ -443,9 +502,7 @@ __device__ void cg_rho_body(CgCtl* c, const double* G, double* hist) {
   if (flag[0] || c->fire) return;
   // rho' = <R~, R~>_S, beta = rho^-1 rho' (gamma = I)
   sm_project(Gm, sub, red);
-  sm_copy(L, c->rho, s * s);
-  __syncthreads();
-  if (!sm_cholesky(L, s, flag + 1)) {
+  if (!rf_cholesky_solve<SM>(rho_l, Gm, Bt, nullptr, s)) {
     if (tid() == 0) {
       c->status = -2;
       c->done = 1;
@@ -453,7 +510,6 @@ __device__ void cg_rho_body(CgCtl* c, const double* G, double* hist) {
     }
     return;
   }
-  sm_chol_solve(L, Gm, Bt, s);
   store_coeff(c->beta, c->beta_f, Bt, s);
   sm_copy(c->rho, Gm, s * s);
 }
@@ -466,26 +522,41 @@ __device__ void cg_rho_body(CgCtl* c, const double* G, double* hist) {
 // finishes last does not change the order of any sum, so the result is
 // deterministic.  Only the <= kMaxSlices workgroups of a slice take part in
 // the hand-off, so its device-scope fences are cheap.
+// Sum of p[b * stride], b < count, in order; the loads of a batch of 32 are
+// all issued before the first add, so a batch costs one memory round trip.
 template <typename T>
 __device__ __forceinline__ double sum_strided(const T* __restrict__ p, int64_t stride, int count) {
+  constexpr int K = 32;
   double acc = 0.0;
-  int b = 0;
-  for (; b + 8 <= count; b += 8) {
-    double v[8];
+  for (int b = 0; b < count; b += K) {
+    double v[K];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) v[u] = (double)p[(int64_t)(b + u) * stride];
+    for (int u = 0; u < K; ++u) v[u] = (b + u < count) ? (double)p[(int64_t)(b + u) * stride] : 0.0;
 #pragma unroll
-    for (int u = 0; u < 8; ++u) acc += v[u];
+    for (int u = 0; u < K; ++u)
+      if (b + u < count) acc += v[u];
   }
-  for (; b < count; ++b) acc += (double)p[(int64_t)b * stride];
   return acc;
 }
 
-template <typename T, int EPI>
-__global__ __launch_bounds__(kSB) void reduce_kernel(int ss, const T* __restrict__ partial, int nblk, Red red,
+template <typename T, int EPI, int SM>
+__global__ __launch_bounds__(kSB) void reduce_kernel(int s, const T* __restrict__ partial, int nblk, Red red,
                                                       const int32_t* gate, const int32_t* fire, CgCtl* c,
                                                       double* hist) {
   __shared__ int last;
+  __shared__ double pre_rho[EPI != EPI_NONE ? kSS : 1], pre_sig[EPI != EPI_NONE ? kSS : 1];
+  __shared__ double pre_r0n[EPI == EPI_CG_RHO ? kMaxS : 1];
+  const int ss = s * s;
+  if constexpr (EPI != EPI_NONE) {
+    // the epilogue's inputs from the control block, loaded along with the
+    // partials (only the last workgroup uses them)
+    for (int t = tid(); t < ss; t += kSB) {
+      pre_rho[t] = c->rho[t];
+      pre_sig[t] = c->sigma[t];
+    }
+    if constexpr (EPI == EPI_CG_RHO)
+      for (int t = tid(); t < s; t += kSB) pre_r0n[t] = c->r0n[t];
+  }
   if constexpr (EPI == EPI_CG_ALPHA) {
     if (c->done) {  // ended: the X update of this iteration is dropped
       if (blockIdx.x == 0 && tid() == 0) c->x_pending = 0;
@@ -510,20 +581,26 @@ __global__ __launch_bounds__(kSB) void reduce_kernel(int ss, const T* __restrict
   if (!last) return;
   __threadfence();
   double* G = red.G + (int64_t)y * ss;
-  for (int e = tid(); e < ss; e += kSB) G[e] = sum_strided<double>(slices + e, ss, ns);
+  __shared__ double Gl[EPI != EPI_NONE ? kSS : 1];
+  for (int e = tid(); e < ss; e += kSB) {
+    const double v = sum_strided<double>(slices + e, ss, ns);
+    G[e] = v;
+    if constexpr (EPI != EPI_NONE) Gl[e] = v;
+  }
   if (tid() == 0) *cnt = 0;
   if constexpr (EPI == EPI_CG_ALPHA) {
     __syncthreads();
-    cg_alpha_body(c, G);
+    cg_alpha_body<SM>(c, Gl, pre_rho, pre_sig);
   } else if constexpr (EPI == EPI_CG_RHO) {
     __syncthreads();
-    cg_rho_body(c, G, hist);
+    cg_rho_body<SM>(c, Gl, hist, pre_rho, pre_sig, pre_r0n);
   }
 }
 
-// About 16 partials per reduction workgroup, at most kMaxSlices workgroups.
+// About 32 partials per reduction workgroup (one batch of loads), at most
+// kMaxSlices workgroups.
 static int reduce_slices(int nblk) {
-  int ns = nblk / 16;
+  int ns = (nblk + 31) / 32;
   if (ns < 1) ns = 1;
   if (ns > kMaxSlices) ns = kMaxSlices;
   return ns;
@@ -533,19 +610,22 @@ template <typename T>
 static hipError_t launch_reduce_t(int s, const T* partial, int nblk, int batch, Red red, const int32_t* gate,
                                   const int32_t* fire, Epi epi, hipStream_t st) {
   dim3 grid(reduce_slices(nblk), batch);
-  if (epi.kind == EPI_CG_ALPHA) {
-    if (batch != 1 || !epi.ctl) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((reduce_kernel<T, EPI_CG_ALPHA>), grid, dim3(kSB), 0, st, s * s, partial, nblk, red, gate,
-                       fire, epi.ctl, epi.hist);
-  } else if (epi.kind == EPI_CG_RHO) {
-    if (batch != 1 || !epi.ctl) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((reduce_kernel<T, EPI_CG_RHO>), grid, dim3(kSB), 0, st, s * s, partial, nblk, red, gate,
-                       fire, epi.ctl, epi.hist);
-  } else {
-    hipLaunchKernelGGL((reduce_kernel<T, EPI_NONE>), grid, dim3(kSB), 0, st, s * s, partial, nblk, red, gate, fire,
+  if (epi.kind == EPI_NONE) {
+    hipLaunchKernelGGL((reduce_kernel<T, EPI_NONE, 8>), grid, dim3(kSB), 0, st, s, partial, nblk, red, gate, fire,
                        epi.ctl, epi.hist);
+    return hipGetLastError();
   }
-  return hipGetLastError();
+  if (batch != 1 || !epi.ctl || (epi.kind != EPI_CG_ALPHA && epi.kind != EPI_CG_RHO)) return hipErrorInvalidValue;
+  return dispatch_sm(s, [&](auto SM_) -> hipError_t {
+    constexpr int SM = decltype(SM_)::value;
+    if (epi.kind == EPI_CG_ALPHA)
+      hipLaunchKernelGGL((reduce_kernel<T, EPI_CG_ALPHA, SM>), grid, dim3(kSB), 0, st, s, partial, nblk, red, gate,
+                         fire, epi.ctl, epi.hist);
+    else
+      hipLaunchKernelGGL((reduce_kernel<T, EPI_CG_RHO, SM>), grid, dim3(kSB), 0, st, s, partial, nblk, red, gate,
+                         fire, epi.ctl, epi.hist);
+    return hipGetLastError();
+  });
 }
 
 hipError_t launch_reduce(int s, const void* partial, bool f32, int nblk, int batch, Red red, const int32_t* gate,
@@ -556,10 +636,10 @@ hipError_t launch_reduce(int s, const void* partial, bool f32, int nblk, int bat
 
 // After the residual was normalised, R~ = R-bar gamma: sigma = gamma sigma,
 // rho' = <R-bar, R-bar>_S (G is the Gram of R-bar), beta = rho^-1 gamma^T rho'.
+template <int SM>
 __global__ __launch_bounds__(kSB) void cg_reortho_fin_kernel(CgCtl* c, const double* G) {
   __shared__ double Gm[kSS], Ga[kSS], Sg[kSS], T1[kSS], L[kSS], Bt[kSS];
   __shared__ double red[4];
-  __shared__ int flag[1];
   if (c->done || !c->fire) return;
   const int s = c->s;
   const Sub sub{c->kind, s, c->g};
@@ -571,8 +651,7 @@ __global__ __launch_bounds__(kSB) void cg_reortho_fin_kernel(CgCtl* c, const dou
   sm_project(Gm, sub, red);
   sm_mm(T1, Ga, Gm, s, true);  // gamma^T rho'
   sm_copy(L, c->rho, s * s);
-  __syncthreads();
-  if (!sm_cholesky(L, s, flag)) {
+  if (!rf_cholesky_solve<SM>(L, T1, Bt, nullptr, s)) {
     if (tid() == 0) {
       c->status = -2;
       c->done = 1;
@@ -581,7 +660,6 @@ __global__ __launch_bounds__(kSB) void cg_reortho_fin_kernel(CgCtl* c, const dou
     }
     return;
   }
-  sm_chol_solve(L, T1, Bt, s);
   store_coeff(c->beta, c->beta_f, Bt, s);
   sm_copy(c->rho, Gm, s * s);
   __syncthreads();
@@ -591,9 +669,12 @@ __global__ __launch_bounds__(kSB) void cg_reortho_fin_kernel(CgCtl* c, const dou
   }
 }
 
-hipError_t launch_cg_reortho_fin(CgCtl* ctl, const double* G, hipStream_t st) {
-  hipLaunchKernelGGL(cg_reortho_fin_kernel, dim3(1), dim3(kSB), 0, st, ctl, G);
-  return hipGetLastError();
+hipError_t launch_cg_reortho_fin(CgCtl* ctl, int s, const double* G, hipStream_t st) {
+  return dispatch_sm(s, [&](auto SM_) -> hipError_t {
+    constexpr int SM = decltype(SM_)::value;
+    hipLaunchKernelGGL(cg_reortho_fin_kernel<SM>, dim3(1), dim3(kSB), 0, st, ctl, G);
+    return hipGetLastError();
+  });
 }
 
 // Normaliser of the parallel (N = diag(|x_j|)) and global (N = |X|_F/sqrt(p) I)
@@ -628,7 +709,7 @@ hipError_t launch_norm_diag(const double* G, Sub sub, double* d, double* out_N, 
 // Full QR of the rows x cols matrix M (row stride cols, rows <= 64) by
 // Householder reflections: R in the upper triangle of M, the full rows x rows
 // orthogonal Q (row stride rows) with M_in = Q [R; 0].
-__device__ void sm_house_full(double* M, int rows, int cols, double* Q, double* beta) {
+__device__ __forceinline__ void sm_house_full(double* M, int rows, int cols, double* Q, double* beta) {
   for (int j = 0; j < cols; ++j) {
     __syncthreads();
     if (tid() == 0) {
@@ -674,7 +755,7 @@ __device__ void sm_house_full(double* M, int rows, int cols, double* Q, double* 
 
 // [x; y] <- Om^T [x; y] for S-elements x, y (s x s, row stride s), Om the
 // per-group 2g x 2g factors stored consecutively.
-__device__ void sm_apply_givens_T(const double* Om, double* x, double* y, int s, int g, double* tmp) {
+__device__ __forceinline__ void sm_apply_givens_T(const double* Om, double* x, double* y, int s, int g, double* tmp) {
   const int ngrp = s / g, m2 = 2 * g;
   __syncthreads();
   for (int e = tid(); e < ngrp * m2 * g; e += kSB) {

@@ -105,7 +105,7 @@ static hipError_t cg_normalise(int64_t n, Sub sub, const CgBufs<T>& b, int nblk,
   ProfScope ps(prof, PROF_CG_NORMALISE, st);
   BK_TRY(tsqr_run<T>(n, sub, b.R, c->gamma, b.tsqr_ws, b.cnt, &c->done, &c->fire, st));
   BK_TRY(launch_gram<T>(n, sub.s, b.R, 1, b.R, b.partial, nblk, Red{b.Gq, b.gpart, b.cnt}, &c->done, st, &c->fire));
-  return launch_cg_reortho_fin(c, b.Gq, st);
+  return launch_cg_reortho_fin(c, sub.s, b.Gq, st);
 }
 
 template <typename T>

@@ -114,13 +114,23 @@ def test_cg_deterministic(h):
 
 def test_cg_exhausted_krylov_space(orc, h):
     """Rank-deficient residual when the block Krylov space is exhausted:
-    eta = 0 breaks down, eta = inf converges (same as the oracle)."""
+    without re-orthonormalisation (eta = 0) alpha is singular up to rounding,
+    so what happens next depends on the rounding of its last pivot: a
+    non-positive pivot stops the solve (the oracle's case), a positive one of
+    rounding size lets it go on.  Either way the outcome must be reported
+    honestly: an error code, or a result whose convergence flag agrees with
+    the FP64 true residual.  With eta = inf it converges (same as the
+    oracle)."""
     A = W.laplace_2d(7)
     B = W.uniform_block(A.n, 4, 4)
     say("cg exhausted")
-    with pytest.raises(P.BkryError) as e:
-        gpu_cg(h, A, B, eta=0.0, tol=1e-12, maxit=500)
-    assert e.value.code == P.E_BREAKDOWN
+    try:
+        X, info = gpu_cg(h, A, B, eta=0.0, tol=1e-12, maxit=500)
+        if info["converged"]:
+            assert max(info["true_relres"]) <= 1e-10
+            assert rel(X, np.linalg.solve(A.to_dense(), B)) < 1e-8
+    except P.BkryError as e:
+        assert e.code in (P.E_BREAKDOWN, P.E_NONFINITE)
     X, info = gpu_cg(h, A, B, eta=np.inf, tol=1e-12, maxit=500)
     assert info["converged"] and rel(X, np.linalg.solve(A.to_dense(), B)) < 1e-10
 
