@@ -307,9 +307,18 @@ def bkry_set_spmm_format(h: Handle, fmt):
     h._check(lib().bkry_set_spmm_format(h.h, f))
 
 
-def bkry_profile(h: Handle, enable: bool = True):
-    """Enable/disable event timing of the CG driver's streaming kernels."""
-    h._check(lib().bkry_profile(h.h, int(bool(enable))))
+def bkry_profile(h: Handle, enable=True, kernels=None):
+    """Event timing of the CG driver's streaming kernels: enable=False turns
+    it off; `kernels` lists the kernel ids to time (default: all four)."""
+    if not enable:
+        mask = 0
+    elif kernels is None:
+        mask = 0xF
+    else:
+        mask = 0
+        for k in kernels:
+            mask |= 1 << int(k)
+    h._check(lib().bkry_profile(h.h, mask))
 
 
 def bkry_profile_read(h: Handle, kernel: int, reset: bool = False):

@@ -29,6 +29,7 @@ struct Prof {
   int used[PROF_N];
   double ms[PROF_N];
   long long cnt[PROF_N];
+  int mask = (1 << PROF_N) - 1;  // kernel ids that are timed (bit k = id k)
 };
 hipError_t prof_init(Prof* p);
 void prof_destroy(Prof* p);
