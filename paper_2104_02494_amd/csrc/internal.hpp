@@ -149,6 +149,12 @@ hipError_t launch_cg_update(int64_t n, int s, T* R, const T* Q, const CgCtl* ctl
 template <typename T>
 hipError_t launch_cg_pupdate(int64_t n, int s, T* X, T* P, const T* R, const CgCtl* ctl, hipStream_t st);
 
+// X = X C in place (C s x s FP64); with gram, also the Gram X^T X of the
+// result into red.G.  Runs only if gf is null or *gf != 0.
+template <typename T>
+hipError_t launch_rowmul(int64_t n, int s, T* X, const double* C, bool gram, T* partial, int nblk, Red red,
+                         const int32_t* gf, hipStream_t st);
+
 // Y = X C (+ Y if accumulate) for a list of blocks: Y op= sum_j X_j C_j,
 // X_j = X + j*n*s, C_j s x s FP64 at C + j*s*s; sign = +1 or -1.
 template <typename T>
@@ -181,9 +187,22 @@ hipError_t launch_cg_reortho_fin(CgCtl* ctl, int s, const double* G, hipStream_t
 hipError_t launch_norm_diag(const double* G, Sub sub, double* d, double* out_N, const int32_t* gate_done,
                             const int32_t* gate_fire, hipStream_t st);
 
+// CholeskyQR steps of the block / hybrid normaliser (plan: [0] the first
+// Cholesky of X^T X succeeded, [1] the second succeeded, [2] the Householder
+// TSQR must run instead).  stage 1 factors G = X^T X: R1 and Rinv = R1^-1,
+// or R1 = I and plan[2] = 1; it runs only if the gates gd / gf are open, and
+// otherwise clears the plan.  stage 2 (only if plan[0]) factors G = Y^T Y
+// of Y = X R1^-1: Rinv = R2^-1 and N = R2 R1, or plan[2] = 1.  ratio_min is
+// the smallest accepted ratio of the diagonal entries of R1 within a group.
+hipError_t launch_cholqr(int stage, const double* G, Sub sub, double* R1, double* Rinv, double* N, int32_t* plan,
+                         double ratio_min, const int32_t* gd, const int32_t* gf, hipStream_t st);
+// N = Nh R1 (block-diagonal upper triangular factors) if plan[2].
+hipError_t launch_cholqr_compose(const double* Nh, const double* R1, double* N, Sub sub, const int32_t* plan,
+                                 hipStream_t st);
+
 // GMRes small kernels
-hipError_t launch_gm_step(GmCtl* ctl, int k, double* H, double* sig, double* Om, const double* H1, const double* H2,
-                          const double* gamma, double* hist, hipStream_t st);
+hipError_t launch_gm_step(GmCtl* ctl, int s, int k, double* H, double* sig, double* Om, const double* H1,
+                          const double* H2, const double* gamma, double* hist, hipStream_t st);
 hipError_t launch_project_batched(const double* G, double* out, Sub sub, int batch, const int32_t* gate,
                                   hipStream_t st);
 hipError_t launch_ir_check(int s, const double* G, double* r0n, double* scale, double* relres, int32_t* flag,

@@ -141,8 +141,12 @@ __device__ __forceinline__ void row_times(T (&out)[VEC], const vec_t<T, VEC>& mi
 
 // Reduce per-lane Gram accumulators of a workgroup into its s x s partial
 // (partial + ((blockIdx.y * gridDim.x + blockIdx.x) * s * s)).
+// Reduce the per-lane Gram accumulators of the workgroup and write its s x s
+// partial of batch slice `slice` (partial[(slice * gridDim.x + blockIdx.x) *
+// s * s]).  Safe to call several times in a row (LDS is reused).
 template <typename T, int S, int VEC>
-__device__ __forceinline__ void gram_store(T (&acc)[VEC][S], int s, T* partial, T* sh /* [NW][S*S] */) {
+__device__ __forceinline__ void gram_store(T (&acc)[VEC][S], int s, T* partial, T* sh /* [NW][S*S] */,
+                                           int64_t slice = 0) {
   constexpr int LPR = S / VEC;
   constexpr int NW = kBlock / kWave;
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
@@ -158,7 +162,7 @@ __device__ __forceinline__ void gram_store(T (&acc)[VEC][S], int s, T* partial, 
       for (int b = 0; b < S; ++b) sh[wave * S * S + (c * VEC + a) * S + b] = acc[a][b];
   }
   __syncthreads();
-  T* pblk = partial + ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * s * s;
+  T* pblk = partial + (slice * gridDim.x + blockIdx.x) * s * s;
   for (int t = threadIdx.x; t < s * s; t += kBlock) {
     int a = t / s, b = t % s;
     T sum = T(0);
@@ -166,6 +170,7 @@ __device__ __forceinline__ void gram_store(T (&acc)[VEC][S], int s, T* partial, 
     for (int w = 0; w < NW; ++w) sum += sh[w * S * S + a * S + b];
     pblk[t] = sum;
   }
+  __syncthreads();
 }
 
 // ------------------------------------------------------------------ SpMM --
@@ -495,9 +500,11 @@ hipError_t launch_spmm(const CsrView& A, int s, const T* X, T* Y, const T* B, in
 }
 
 // ------------------------------------------------------------------ Gram --
-// blockIdx.y selects X_j = X + j * n * s; partial[(j * gridDim.x + blk) * s*s].
-template <typename T, int S, int VEC>
-__global__ __launch_bounds__(kBlock) void gram_kernel(int64_t n, int s, const T* __restrict__ X,
+// Batch slice j < nx: X_j^T Y with X_j = X + j * n * s, into
+// partial[(j * gridDim.x + blk) * s*s].  A workgroup computes JB consecutive
+// slices (blockIdx.y = slice / JB), so Y is read once per JB blocks X_j.
+template <typename T, int S, int VEC, int JB>
+__global__ __launch_bounds__(kBlock) void gram_kernel(int64_t n, int s, const T* __restrict__ X, int nx,
                                                        const T* __restrict__ Y, T* __restrict__ partial,
                                                        const int32_t* done, const int32_t* fire) {
   using L = Layout<T, S, VEC>;
@@ -509,22 +516,39 @@ __global__ __launch_bounds__(kBlock) void gram_kernel(int64_t n, int s, const T*
   const int r = lane / L::LPR, c = lane % L::LPR;
   const int col0 = c * VEC;
   const bool active = col0 < s;
-  const T* Xj = X + (int64_t)blockIdx.y * n * s;
+  const int j0 = blockIdx.y * JB;
+  const int jn = (nx - j0) < JB ? (nx - j0) : JB;
   int64_t r0, r1;
   block_rows(n, blockIdx.x, gridDim.x, RPB, r0, r1);
-  T gacc[VEC][S];
+  T gacc[JB][VEC][S];
 #pragma unroll
-  for (int a = 0; a < VEC; ++a)
+  for (int jj = 0; jj < JB; ++jj)
 #pragma unroll
-    for (int b = 0; b < S; ++b) gacc[a][b] = T(0);
+    for (int a = 0; a < VEC; ++a)
+#pragma unroll
+      for (int b = 0; b < S; ++b) gacc[jj][a][b] = T(0);
   for (int64_t base = r0; base < r1; base += RPB) {
     const int64_t row = base + wave * L::RPW + r;
     const bool rv = row < r1 && active;
-    vec_t<T, VEC> x = rv ? load_vec<T, VEC>(Xj + row * s + col0) : zero_vec<T, VEC>();
     vec_t<T, VEC> y = rv ? load_vec<T, VEC>(Y + row * s + col0) : zero_vec<T, VEC>();
-    gram_row<T, S, VEC>(gacc, x, y, lane);
+    vec_t<T, VEC> x[JB];
+#pragma unroll
+    for (int jj = 0; jj < JB; ++jj)
+      x[jj] = (rv && jj < jn) ? load_vec<T, VEC>(X + (int64_t)(j0 + jj) * n * s + row * s + col0)
+                              : zero_vec<T, VEC>();
+#pragma unroll
+    for (int jj = 0; jj < JB; ++jj) gram_row<T, S, VEC>(gacc[jj], x[jj], y, lane);
   }
-  gram_store<T, S, VEC>(gacc, s, partial, sh);
+#pragma unroll
+  for (int jj = 0; jj < JB; ++jj)
+    if (jj < jn) gram_store<T, S, VEC>(gacc[jj], s, partial, sh, j0 + jj);
+}
+
+// Slices computed per workgroup for width S (bounded by the registers of
+// the Gram accumulators).
+template <int S>
+constexpr int gram_jb() {
+  return S <= 8 ? 4 : (S <= 16 ? 2 : 1);
 }
 
 template <typename T>
@@ -534,7 +558,14 @@ hipError_t launch_gram(int64_t n, int s, const T* X, int nx, const T* Y, T* part
   if (nx > kMaxBatch) return hipErrorInvalidValue;
   hipError_t e = dispatch_s<T>(s, [&](auto S_, auto V_) -> hipError_t {
     constexpr int S = decltype(S_)::value, V = decltype(V_)::value;
-    hipLaunchKernelGGL((gram_kernel<T, S, V>), dim3(nblk, nx), dim3(kBlock), 0, st, n, s, X, Y, partial, done, fire);
+    if (nx == 1) {
+      hipLaunchKernelGGL((gram_kernel<T, S, V, 1>), dim3(nblk, 1), dim3(kBlock), 0, st, n, s, X, nx, Y, partial,
+                         done, fire);
+    } else {
+      constexpr int JB = gram_jb<S>();
+      hipLaunchKernelGGL((gram_kernel<T, S, V, JB>), dim3(nblk, (nx + JB - 1) / JB), dim3(kBlock), 0, st, n, s, X,
+                         nx, Y, partial, done, fire);
+    }
     return hipGetLastError();
   });
   if (e != hipSuccess) return e;
@@ -665,6 +696,65 @@ hipError_t launch_cg_pupdate(int64_t n, int s, T* X, T* P, const T* R, const CgC
     hipLaunchKernelGGL((cg_pupdate_kernel<T, S, V>), dim3(nblk), dim3(kBlock), 0, st, n, s, X, P, R, ctl);
     return hipGetLastError();
   });
+}
+
+// ------------------------------------------------------ row products --
+// X = X C in place (C s x s FP64, applied to each row), optionally with the
+// Gram partials of the result (GRAM = 1).  Runs only if gf is null or *gf.
+template <typename T, int S, int VEC, int GRAM>
+__global__ __launch_bounds__(kBlock) void rowmul_kernel(int64_t n, int s, T* __restrict__ X,
+                                                         const double* __restrict__ C, T* __restrict__ partial,
+                                                         const int32_t* gf) {
+  using L = Layout<T, S, VEC>;
+  constexpr int NW = kBlock / kWave;
+  constexpr int RPB = NW * L::RPW;
+  __shared__ T cm[S * S];
+  __shared__ T sh[GRAM ? NW * S * S : 1];
+  if (gf && !*gf) return;
+  for (int t = threadIdx.x; t < S * S; t += kBlock) {
+    const int a = t / S, b = t % S;
+    cm[t] = (a < s && b < s) ? (T)C[a * s + b] : T(0);
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  const int r = lane / L::LPR, c = lane % L::LPR;
+  const int col0 = c * VEC;
+  const bool active = col0 < s;
+  int64_t r0, r1;
+  block_rows(n, blockIdx.x, gridDim.x, RPB, r0, r1);
+  T gacc[GRAM ? VEC : 1][GRAM ? S : 1];
+#pragma unroll
+  for (int a = 0; a < (GRAM ? VEC : 1); ++a)
+#pragma unroll
+    for (int b = 0; b < (GRAM ? S : 1); ++b) gacc[a][b] = T(0);
+  for (int64_t base = r0; base < r1; base += RPB) {
+    const int64_t row = base + wave * L::RPW + r;
+    const bool rv = row < r1 && active;
+    vec_t<T, VEC> x = rv ? load_vec<T, VEC>(X + row * s + col0) : zero_vec<T, VEC>();
+    T y[VEC];
+    row_times<T, S, VEC>(y, x, cm, col0, lane);
+    vec_t<T, VEC> out;
+#pragma unroll
+    for (int w = 0; w < VEC; ++w) out.v[w] = y[w];
+    if (rv) store_out<T, VEC>(X + row * s + col0, out);
+    if constexpr (GRAM) gram_row<T, S, VEC>(gacc, out, out, lane);
+  }
+  if constexpr (GRAM) gram_store<T, S, VEC>(gacc, s, partial, sh);
+}
+
+template <typename T>
+hipError_t launch_rowmul(int64_t n, int s, T* X, const double* C, bool gram, T* partial, int nblk, Red red,
+                         const int32_t* gf, hipStream_t st) {
+  hipError_t e = dispatch_s<T>(s, [&](auto S_, auto V_) -> hipError_t {
+    constexpr int S = decltype(S_)::value, V = decltype(V_)::value;
+    if (gram)
+      hipLaunchKernelGGL((rowmul_kernel<T, S, V, 1>), dim3(nblk), dim3(kBlock), 0, st, n, s, X, C, partial, gf);
+    else
+      hipLaunchKernelGGL((rowmul_kernel<T, S, V, 0>), dim3(nblk), dim3(kBlock), 0, st, n, s, X, C, partial, gf);
+    return hipGetLastError();
+  });
+  if (e != hipSuccess || !gram) return e;
+  return launch_reduce(s, partial, sizeof(T) == 4, nblk, 1, red, nullptr, gf, Epi{}, st);
 }
 
 // ----------------------------------------------------- block combination --
@@ -866,6 +956,8 @@ hipError_t launch_cast_f32(int64_t count, const double* in, float* out, hipStrea
   template hipError_t launch_cg_update<T>(int64_t, int, T*, const T*, const CgCtl*, T*, int, Red, hipStream_t,    \
                                           Epi, hipEvent_t);                                                        \
   template hipError_t launch_cg_pupdate<T>(int64_t, int, T*, T*, const T*, const CgCtl*, hipStream_t);             \
+  template hipError_t launch_rowmul<T>(int64_t, int, T*, const double*, bool, T*, int, Red, const int32_t*,        \
+                                       hipStream_t);                                                               \
   template hipError_t launch_block_combine<T>(int64_t, int, const T*, int, const double*, double, T*,               \
                                               const int32_t*, hipStream_t);                                        \
   template hipError_t launch_colscale<T>(int64_t, int, const T*, T*, const double*, int, const int32_t*,           \

@@ -201,11 +201,13 @@ __device__ __forceinline__ double readlane_d(double v, int lane) {
 // reciprocals of the pivots are formed once, so the only divisions are the
 // s reciprocals.  Returns false (uniformly) on a non-positive or non-finite
 // pivot.
+// In-register Cholesky of A (s x s, s <= SM, LDS): on return lane i holds
+// row i of L in l (entries above the diagonal are left over from A) and
+// rinv[k] = 1 / L_kk in every lane.  False (uniformly) on a non-positive or
+// non-finite pivot.
 template <int SM>
-__device__ __forceinline__ bool rf_cholesky_solve(const double* A, const double* B, double* X, double* Linv, int s) {
-  __syncthreads();
+__device__ __forceinline__ bool rf_factor(const double* A, int s, double (&l)[SM], double (&rinv)[SM]) {
   const int t = tid();
-  double l[SM], rinv[SM];
 #pragma unroll
   for (int j = 0; j < SM; ++j) l[j] = (t < s && j < s) ? A[t * s + j] : 0.0;
 #pragma unroll
@@ -229,6 +231,41 @@ __device__ __forceinline__ bool rf_cholesky_solve(const double* A, const double*
       }
     }
   }
+  return true;
+}
+
+// Column t of L^-1 (lane t) by forward substitution.
+template <int SM>
+__device__ __forceinline__ void rf_linv_column(const double (&l)[SM], const double (&rinv)[SM], int s,
+                                               double (&y)[SM]) {
+  const int t = tid();
+#pragma unroll
+  for (int i = 0; i < SM; ++i) {
+    if (i < s) {
+      double acc = (i == t) ? 1.0 : 0.0;
+#pragma unroll
+      for (int k = 0; k < i; ++k) acc = fma(-readlane_d(l[k], i), y[k], acc);
+      y[i] = acc * rinv[i];
+    } else {
+      y[i] = 0.0;
+    }
+  }
+}
+
+// X = A^-1 B for SPD A (s x s, s <= SM, LDS) through A = L L^T, and, if Linv
+// is not null, Linv = L^-1 (LDS; zero above the diagonal).  The factor lives
+// in registers, lane i holding row i; each right-hand side column lives in
+// the registers of its own lane; entries of L reach the other lanes by lane
+// reads, so the whole factor-and-solve runs without LDS round trips.  The
+// reciprocals of the pivots are formed once, so the only divisions are the
+// s reciprocals.  Returns false (uniformly) on a non-positive or non-finite
+// pivot.
+template <int SM>
+__device__ __forceinline__ bool rf_cholesky_solve(const double* A, const double* B, double* X, double* Linv, int s) {
+  __syncthreads();
+  const int t = tid();
+  double l[SM], rinv[SM];
+  if (!rf_factor<SM>(A, s, l, rinv)) return false;
   double x[SM];
 #pragma unroll
   for (int i = 0; i < SM; ++i) x[i] = (t < s && i < s) ? B[i * s + t] : 0.0;
@@ -256,24 +293,37 @@ __device__ __forceinline__ bool rf_cholesky_solve(const double* A, const double*
     for (int i = 0; i < SM; ++i)
       if (i < s) X[i * s + t] = x[i];
   }
-  if (Linv) {  // column t of L^-1
+  if (Linv) {
     double y[SM];
-#pragma unroll
-    for (int i = 0; i < SM; ++i) {
-      if (i < s) {
-        double acc = (i == t) ? 1.0 : 0.0;
-#pragma unroll
-        for (int k = 0; k < i; ++k) acc = fma(-readlane_d(l[k], i), y[k], acc);
-        y[i] = acc * rinv[i];
-      } else {
-        y[i] = 0.0;
-      }
-    }
+    rf_linv_column<SM>(l, rinv, s, y);
     if (t < s) {
 #pragma unroll
       for (int i = 0; i < SM; ++i)
         if (i < s) Linv[i * s + t] = y[i];
     }
+  }
+  __syncthreads();
+  return true;
+}
+
+// A = L L^T with L and L^-1 stored (LDS, zero above the diagonal).
+template <int SM>
+__device__ __forceinline__ bool rf_cholesky_factor(const double* A, double* Lo, double* Linv, int s) {
+  __syncthreads();
+  const int t = tid();
+  double l[SM], rinv[SM];
+  if (!rf_factor<SM>(A, s, l, rinv)) return false;
+  if (t < s) {
+#pragma unroll
+    for (int j = 0; j < SM; ++j)
+      if (j < s) Lo[t * s + j] = (j <= t) ? l[j] : 0.0;
+  }
+  double y[SM];
+  rf_linv_column<SM>(l, rinv, s, y);
+  if (t < s) {
+#pragma unroll
+    for (int i = 0; i < SM; ++i)
+      if (i < s) Linv[i * s + t] = y[i];
   }
   __syncthreads();
   return true;
@@ -677,6 +727,111 @@ hipError_t launch_cg_reortho_fin(CgCtl* ctl, int s, const double* G, hipStream_t
   });
 }
 
+// ------------------------------------------------------------ CholeskyQR --
+// One factorisation step of the block / hybrid normaliser by CholeskyQR2 (see
+// launch_cholqr in internal.hpp for the plan flags).  G is the full Gram of
+// the block; its projection onto the subalgebra is block diagonal, so one
+// Cholesky of the whole matrix is one Cholesky per column group.
+template <int SM>
+__global__ __launch_bounds__(kSB) void cholqr_kernel(int stage, const double* G, Sub sub, double* R1, double* Rinv,
+                                                      double* N, int32_t* plan, double ratio_min, const int32_t* gd,
+                                                      const int32_t* gf) {
+  __shared__ double Gm[kSS], L[kSS], Li[kSS];
+  __shared__ double red[4];
+  const int s = sub.s, t = tid();
+  if (stage == 1) {
+    if ((gd && *gd) || (gf && !*gf)) {
+      if (t == 0) {
+        plan[0] = 0;
+        plan[1] = 0;
+        plan[2] = 0;
+      }
+      return;
+    }
+  } else if (!plan[0]) {
+    return;
+  }
+  sm_copy(Gm, G, s * s);
+  sm_project(Gm, sub, red);
+  bool ok = all_finite(Gm, s * s, red);
+  if (ok) ok = rf_cholesky_factor<SM>(Gm, L, Li, s);
+  if (ok) {
+    bool bad = false;
+    if (stage == 1) {
+      // kappa(X) >= max_j L_jj / min_j L_jj within a group: refuse ratios
+      // beyond what one Cholesky of the Gram can resolve
+      if (t < s) {
+        const int g0 = (t / sub.g) * sub.g;
+        double mx = 0.0;
+        for (int j = g0; j < g0 + sub.g; ++j) mx = fmax(mx, L[j * s + j]);
+        bad = !(L[t * s + t] >= ratio_min * mx);
+      }
+    } else {
+      // Y^T Y must be near the identity for the second pass to finish
+      for (int e = t; e < s * s; e += kSB) {
+        const int i = e / s, j = e % s;
+        if (i / sub.g == j / sub.g) bad |= !(fabs(Gm[e] - (i == j ? 1.0 : 0.0)) <= 0.5);
+      }
+    }
+    ok = !wany(bad);
+  }
+  __syncthreads();
+  if (stage == 1) {
+    for (int e = t; e < s * s; e += kSB) {
+      const int i = e / s, j = e % s;
+      const double id = (i == j) ? 1.0 : 0.0;
+      R1[e] = ok ? L[j * s + i] : id;    // R1 = L^T
+      Rinv[e] = ok ? Li[j * s + i] : id; // R1^-1 = (L^-1)^T
+    }
+    if (t == 0) {
+      plan[0] = ok ? 1 : 0;
+      plan[1] = 0;
+      plan[2] = ok ? 0 : 1;
+    }
+  } else {
+    if (ok) {
+      for (int e = t; e < s * s; e += kSB) {
+        const int i = e / s, j = e % s;
+        Rinv[e] = Li[j * s + i];
+        double acc = 0.0;  // (L^T R1)_ij
+        for (int k = 0; k < s; ++k) acc = fma(L[k * s + i], R1[k * s + j], acc);
+        N[e] = acc;
+      }
+    }
+    if (t == 0) {
+      plan[1] = ok ? 1 : 0;
+      plan[2] = ok ? 0 : 1;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kSB) void cholqr_compose_kernel(const double* Nh, const double* R1, double* N, int s,
+                                                              const int32_t* plan) {
+  if (!plan[2]) return;
+  for (int e = tid(); e < s * s; e += kSB) {
+    const int i = e / s, j = e % s;
+    double acc = 0.0;
+    for (int k = 0; k < s; ++k) acc = fma(Nh[i * s + k], R1[k * s + j], acc);
+    N[e] = acc;
+  }
+}
+
+hipError_t launch_cholqr(int stage, const double* G, Sub sub, double* R1, double* Rinv, double* N, int32_t* plan,
+                         double ratio_min, const int32_t* gd, const int32_t* gf, hipStream_t st) {
+  return dispatch_sm(sub.s, [&](auto SM_) -> hipError_t {
+    constexpr int SM = decltype(SM_)::value;
+    hipLaunchKernelGGL(cholqr_kernel<SM>, dim3(1), dim3(kSB), 0, st, stage, G, sub, R1, Rinv, N, plan, ratio_min,
+                       gd, gf);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_cholqr_compose(const double* Nh, const double* R1, double* N, Sub sub, const int32_t* plan,
+                                 hipStream_t st) {
+  hipLaunchKernelGGL(cholqr_compose_kernel, dim3(1), dim3(kSB), 0, st, Nh, R1, N, sub.s, plan);
+  return hipGetLastError();
+}
+
 // Normaliser of the parallel (N = diag(|x_j|)) and global (N = |X|_F/sqrt(p) I)
 // subalgebras from the Gram matrix G of X.
 __global__ __launch_bounds__(kSB) void norm_diag_kernel(const double* G, Sub sub, double* d, double* N,
@@ -812,29 +967,98 @@ hipError_t launch_gm_cycle_init(GmCtl* ctl, double* sig, const double* sigma0, c
 
 // Step k of a cycle: the new Hessenberg column h_jk = H1_j + H2_j (the two
 // Gram-Schmidt passes) for j <= k and gamma = h_{k+1,k}.
+template <int SM>
 __global__ __launch_bounds__(kSB) void gm_step_kernel(GmCtl* c, int k, double* H, double* sig, double* Om,
                                                        const double* H1, const double* H2, const double* gamma,
                                                        double* hist) {
-  __shared__ double Qf[4 * kMaxS * kMaxS], tmp[2 * kMaxS * kMaxS], gm[kSS];
+  __shared__ double Qf[4 * kMaxS * kMaxS], tmp[2 * kMaxS * kMaxS], gm[kSS], xs[kSS], ys[kSS];
   __shared__ double beta[kMaxS];
   double* M = tmp;  // the Householder input is not live while rotations use tmp
   if (c->done) return;
   const int s = c->s, g = c->g, m = c->m, ss = s * s, ngrp = s / g, m2 = 2 * g;
-  for (int t = tid(); t < (k + 1) * ss; t += kSB) {
+  const int t0 = tid();
+  for (int t = t0; t < (k + 1) * ss; t += kSB) {
     const int j = t / ss, e = t % ss;
     H[((int64_t)j * m + k) * ss + e] = H1[t] + H2[t];
   }
   sm_copy(gm, gamma, ss);
+  for (int e = t0; e < ss; e += kSB) xs[e] = H1[e] + H2[e];
+  // Rotations of the previous steps, j = 0 .. k-1: x carries block j of the
+  // new column, y receives block j+1.  The factor of rotation j+1 and block
+  // j+2 are loaded into registers while rotation j is applied, so memory
+  // latency is exposed about once per step instead of once per rotation.
+  constexpr int RO = (4 * SM * SM + kSB - 1) / kSB;  // factor entries per lane (m2 = 2g <= 2s)
+  constexpr int RS = (SM * SM + kSB - 1) / kSB;      // block entries per lane
+  constexpr int RN = (2 * SM * SM + kSB - 1) / kSB;  // rotated entries per lane
+  const int no = ngrp * m2 * m2, ne = ngrp * m2 * g;
+  double opre[RO], ypre[RS];
+  auto load_next = [&](int j) {
+#pragma unroll
+    for (int r = 0; r < RO; ++r) {
+      const int e = t0 + r * kSB;
+      opre[r] = (j < k && e < no) ? Om[(int64_t)j * no + e] : 0.0;
+    }
+#pragma unroll
+    for (int r = 0; r < RS; ++r) {
+      const int e = t0 + r * kSB;
+      ypre[r] = (j < k && e < ss) ? H1[(int64_t)(j + 1) * ss + e] + H2[(int64_t)(j + 1) * ss + e] : 0.0;
+    }
+  };
+  load_next(0);
+  for (int j = 0; j < k; ++j) {
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < RO; ++r) {
+      const int e = t0 + r * kSB;
+      if (e < no) Qf[e] = opre[r];
+    }
+#pragma unroll
+    for (int r = 0; r < RS; ++r) {
+      const int e = t0 + r * kSB;
+      if (e < ss) ys[e] = ypre[r];
+    }
+    __syncthreads();
+    load_next(j + 1);
+    double out[RN];
+#pragma unroll
+    for (int r = 0; r < RN; ++r) {
+      const int e = t0 + r * kSB;
+      out[r] = 0.0;
+      if (e < ne) {
+        const int grp = e / (m2 * g), rem = e % (m2 * g), i = rem / g, cc = rem % g;
+        const double* O = Qf + grp * m2 * m2;
+        const int o = grp * g;
+        double acc = 0.0;
+        for (int q = 0; q < m2; ++q) {
+          const double col = q < g ? xs[(o + q) * s + o + cc] : ys[(o + q - g) * s + o + cc];
+          acc += O[q * m2 + i] * col;
+        }
+        out[r] = acc;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < RN; ++r) {
+      const int e = t0 + r * kSB;
+      if (e < ne) {
+        const int grp = e / (m2 * g), rem = e % (m2 * g), i = rem / g, cc = rem % g;
+        const int o = grp * g;
+        if (i < g)
+          H[((int64_t)j * m + k) * ss + (o + i) * s + o + cc] = out[r];
+        else
+          xs[(o + i - g) * s + o + cc] = out[r];
+      }
+    }
+  }
   __syncthreads();
-  for (int j = 0; j < k; ++j)
-    sm_apply_givens_T(Om + (int64_t)j * ngrp * m2 * m2, H + ((int64_t)j * m + k) * ss,
-                      H + ((int64_t)(j + 1) * m + k) * ss, s, g, tmp);
   double* hkk = H + ((int64_t)k * m + k) * ss;
+  for (int e = t0; e < ss; e += kSB) hkk[e] = xs[e];
+  __syncthreads();
   double* Omk = Om + (int64_t)k * ngrp * m2 * m2;
   if (g == 1) {
     // 2 x 1 Householder per column
     for (int grp = tid(); grp < ngrp; grp += kSB) {
-      const double x1 = hkk[grp * s + grp], x2 = gm[grp * s + grp];
+      const double x1 = xs[grp * s + grp], x2 = gm[grp * s + grp];
       const double sg = x2 * x2;
       double* O = Omk + grp * 4;
       if (sg == 0.0) {
@@ -854,7 +1078,7 @@ __global__ __launch_bounds__(kSB) void gm_step_kernel(GmCtl* c, int k, double* H
       __syncthreads();
       for (int t = tid(); t < m2 * g; t += kSB) {
         const int i = t / g, cc = t % g;
-        M[t] = i < g ? hkk[(o + i) * s + o + cc] : gm[(o + i - g) * s + o + cc];
+        M[t] = i < g ? xs[(o + i) * s + o + cc] : gm[(o + i - g) * s + o + cc];
       }
       sm_house_full(M, m2, g, Qf, beta);
       for (int t = tid(); t < m2 * m2; t += kSB) Omk[grp * m2 * m2 + t] = Qf[t];
@@ -900,10 +1124,13 @@ __global__ __launch_bounds__(kSB) void gm_step_kernel(GmCtl* c, int k, double* H
   }
 }
 
-hipError_t launch_gm_step(GmCtl* ctl, int k, double* H, double* sig, double* Om, const double* H1, const double* H2,
-                          const double* gamma, double* hist, hipStream_t st) {
-  hipLaunchKernelGGL(gm_step_kernel, dim3(1), dim3(kSB), 0, st, ctl, k, H, sig, Om, H1, H2, gamma, hist);
-  return hipGetLastError();
+hipError_t launch_gm_step(GmCtl* ctl, int s, int k, double* H, double* sig, double* Om, const double* H1,
+                          const double* H2, const double* gamma, double* hist, hipStream_t st) {
+  return dispatch_sm(s, [&](auto SM_) -> hipError_t {
+    constexpr int SM = decltype(SM_)::value;
+    hipLaunchKernelGGL(gm_step_kernel<SM>, dim3(1), dim3(kSB), 0, st, ctl, k, H, sig, Om, H1, H2, gamma, hist);
+    return hipGetLastError();
+  });
 }
 
 // zeta_l = R_ll^-1 (sigma_l - sum_{j>l} H_lj zeta_j), l = kend-1 .. 0; a zero

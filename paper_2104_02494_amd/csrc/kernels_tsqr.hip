@@ -330,33 +330,27 @@ size_t norms_ws(int64_t n, const Sub& sub) {
 
 }  // namespace
 
+// Workspace of the CholeskyQR2 path (placed before the Householder plan).
+template <typename T>
+size_t cholqr_ws(int64_t n, const Sub& sub) {
+  const int s = sub.s;
+  const int nblk = stream_grid(n, s, sizeof(T));
+  return align256(sizeof(T) * (size_t)nblk * s * s) + align256(sizeof(double) * red_gpart_count(nblk, s)) +
+         4 * align256(sizeof(double) * s * s) + align256(4 * sizeof(int32_t));
+}
+
 size_t tsqr_workspace_bytes(int64_t n, Sub sub) {
   if (uses_norms(sub)) return norms_ws<double>(n, sub);
-  size_t a = make_plan<double>(n, sub).total, b = make_plan<float>(n, sub).total;
+  size_t a = cholqr_ws<double>(n, sub) + make_plan<double>(n, sub).total;
+  size_t b = cholqr_ws<float>(n, sub) + make_plan<float>(n, sub).total;
   return a > b ? a : b;
 }
 
+// Householder TSQR of X (in place: Q over X) with the normaliser into N.
 template <typename T>
-hipError_t tsqr_run(int64_t n, Sub sub, T* X, double* N, void* ws, uint32_t* cnt, const int32_t* gd,
-                    const int32_t* gf, hipStream_t st) {
-  char* w = static_cast<char*>(ws);
+static hipError_t hh_tsqr(int64_t n, const Sub& sub, T* X, double* N, char* w, const int32_t* gd,
+                          const int32_t* gf, hipStream_t st) {
   const int s = sub.s;
-  if (uses_norms(sub)) {
-    const int nblk = stream_grid(n, s, sizeof(T));
-    T* part = reinterpret_cast<T*>(w);
-    w += align256(sizeof(T) * (size_t)nblk * s * s);
-    double* G = reinterpret_cast<double*>(w);
-    w += align256(sizeof(double) * s * s);
-    double* d = reinterpret_cast<double*>(w);
-    w += align256(sizeof(double) * s);
-    double* gpart = reinterpret_cast<double*>(w);
-    Sub ns = sub;
-    if (ns.kind == HYBRID) ns.kind = PARALLEL;
-    hipError_t e = launch_gram<T>(n, s, X, 1, X, part, nblk, Red{G, gpart, cnt}, gd, st, gf);
-    if (e == hipSuccess) e = launch_norm_diag(G, ns, d, N, gd, gf, st);
-    if (e == hipSuccess) e = launch_colscale<T>(n, s, X, X, d, ns.kind == GLOBAL, gd, gf, st);
-    return e;
-  }
   const TsqrPlan p = make_plan<T>(n, sub);
   const int g = p.g;
   T* betas_leaf = reinterpret_cast<T*>(w + p.off_betas_leaf);
@@ -378,6 +372,69 @@ hipError_t tsqr_run(int64_t n, Sub sub, T* X, double* N, void* ws, uint32_t* cnt
                        betas_leaf, M(0), p.cnt[0], gd, gf);
     return hipGetLastError();
   });
+}
+
+// Block / hybrid normaliser (FP64 blocks).  For a well-conditioned block the unique QR
+// with positive diagonal is reached by CholeskyQR2: Y = X R1^-1 with R1 from
+// the Cholesky of X^T X, then Q = Y R2^-1 with R2 from the Cholesky of
+// Y^T Y, N = R2 R1 (five block passes, no per-column synchronisation).  When
+// the first Cholesky fails or its pivots spread by more than a factor
+// 1/ratio within a group (X near rank-deficient), or Y^T Y is not near I, the
+// Householder TSQR runs instead, on X or on Y, and N = R_householder R1;
+// that path keeps the normaliser defined for rank-deficient blocks.  All
+// branches are decided on the device (plan flags), so no host round trip.
+template <typename T>
+hipError_t tsqr_run(int64_t n, Sub sub, T* X, double* N, void* ws, uint32_t* cnt, const int32_t* gd,
+                    const int32_t* gf, hipStream_t st) {
+  char* w = static_cast<char*>(ws);
+  const int s = sub.s;
+  if (uses_norms(sub)) {
+    const int nblk = stream_grid(n, s, sizeof(T));
+    T* part = reinterpret_cast<T*>(w);
+    w += align256(sizeof(T) * (size_t)nblk * s * s);
+    double* G = reinterpret_cast<double*>(w);
+    w += align256(sizeof(double) * s * s);
+    double* d = reinterpret_cast<double*>(w);
+    w += align256(sizeof(double) * s);
+    double* gpart = reinterpret_cast<double*>(w);
+    Sub ns = sub;
+    if (ns.kind == HYBRID) ns.kind = PARALLEL;
+    hipError_t e = launch_gram<T>(n, s, X, 1, X, part, nblk, Red{G, gpart, cnt}, gd, st, gf);
+    if (e == hipSuccess) e = launch_norm_diag(G, ns, d, N, gd, gf, st);
+    if (e == hipSuccess) e = launch_colscale<T>(n, s, X, X, d, ns.kind == GLOBAL, gd, gf, st);
+    return e;
+  }
+  if constexpr (sizeof(T) == 4) {
+    // FP32 blocks (the inner solve of iterative refinement): CholeskyQR in
+    // FP32 loses orthogonality to kappa^2 u32 and slowed the inner solves
+    // down; the Householder TSQR (FP64 R combine) is kept there.
+    return hh_tsqr<T>(n, sub, X, N, w + cholqr_ws<T>(n, sub), gd, gf, st);
+  }
+  const int nblk = stream_grid(n, s, sizeof(T));
+  T* part = reinterpret_cast<T*>(w);
+  w += align256(sizeof(T) * (size_t)nblk * s * s);
+  double* gpart = reinterpret_cast<double*>(w);
+  w += align256(sizeof(double) * red_gpart_count(nblk, s));
+  double* G = reinterpret_cast<double*>(w);
+  w += align256(sizeof(double) * s * s);
+  double* R1 = reinterpret_cast<double*>(w);
+  w += align256(sizeof(double) * s * s);
+  double* Rinv = reinterpret_cast<double*>(w);
+  w += align256(sizeof(double) * s * s);
+  double* Nh = reinterpret_cast<double*>(w);
+  w += align256(sizeof(double) * s * s);
+  int32_t* plan = reinterpret_cast<int32_t*>(w);
+  w += align256(4 * sizeof(int32_t));
+  const double ratio = sizeof(T) == 8 ? 1e-6 : 3e-3;
+  const Red red{G, gpart, cnt};
+  hipError_t e = launch_gram<T>(n, s, X, 1, X, part, nblk, red, gd, st, gf);
+  if (e == hipSuccess) e = launch_cholqr(1, G, sub, R1, Rinv, N, plan, ratio, gd, gf, st);
+  if (e == hipSuccess) e = launch_rowmul<T>(n, s, X, Rinv, true, part, nblk, red, plan + 0, st);
+  if (e == hipSuccess) e = launch_cholqr(2, G, sub, R1, Rinv, N, plan, ratio, nullptr, nullptr, st);
+  if (e == hipSuccess) e = launch_rowmul<T>(n, s, X, Rinv, false, part, nblk, Red{}, plan + 1, st);
+  if (e == hipSuccess) e = hh_tsqr<T>(n, sub, X, Nh, w, nullptr, plan + 2, st);
+  if (e == hipSuccess) e = launch_cholqr_compose(Nh, R1, N, sub, plan, st);
+  return e;
 }
 
 template hipError_t tsqr_run<double>(int64_t, Sub, double*, double*, void*, uint32_t*, const int32_t*,

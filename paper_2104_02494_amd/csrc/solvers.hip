@@ -359,7 +359,7 @@ hipError_t gm_run(const CsrView& A, Sub sub, const double* B, double* X, double 
         BK_TRY(launch_block_combine<double>(n, s, b.V, k + 1, Hp[pass], -1.0, W, done, st));
       }
       BK_TRY(tsqr_run<double>(n, sub, W, b.gam, b.tsqr_ws, b.cnt, done, nullptr, st));
-      BK_TRY(launch_gm_step(c, k, b.H, b.sig, b.Om, b.H1, b.H2, b.gam, b.hist, st));
+      BK_TRY(launch_gm_step(c, s, k, b.H, b.sig, b.Om, b.H1, b.H2, b.gam, b.hist, st));
     }
     BK_TRY(hipMemcpyAsync(hflags, c, 16 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
     BK_TRY(hipStreamSynchronize(st));
