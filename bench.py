@@ -155,8 +155,10 @@ def run(args):
     sp_avg = spmm_ms / max(spmm_n, 1) * 1e-3
     achieved = sp_bytes / sp_avg / 1e9
     upd_gbs = 3 * blk / (upd_ms / max(upd_n, 1) * 1e-3) / 1e9
-    pup_gbs = 5 * blk / (pup_ms / max(pup_n, 1) * 1e-3) / 1e9
-    iter_bytes = sp_bytes + 8 * blk          # + residual pass (3 blocks) + direction pass (5 blocks)
+    # the direction update moves 3 blocks (P, R read, P_{k+1} written) and, every
+    # other iteration, 3 more (X read and written, P_{k-1} read): 4.5 on average
+    pup_gbs = 4.5 * blk / (pup_ms / max(pup_n, 1) * 1e-3) / 1e9
+    iter_bytes = sp_bytes + 7.5 * blk        # + residual pass (3 blocks) + direction pass (4.5 blocks)
     traffic = pmc_traffic()
     result = {
         "metric": METRIC,

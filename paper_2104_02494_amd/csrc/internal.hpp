@@ -69,7 +69,9 @@ struct CgCtl {
   int32_t suspended;  // the iteration waits for a re-normalisation launched by the host
   int32_t dynamic;    // the re-orthonormalisation test is decided per iteration
   int32_t kd_jacobi;  // iterations whose kappa_D needed the Jacobi eigenvalues
-  int32_t pad_[7];
+  int32_t xdef_in;    // this iteration's direction update owes X the previous P's term
+  int32_t xdef_pend;  // after this iteration's update, P's term is owed to X
+  int32_t pad_[5];
   double tol, eta, sqrt_eps, pad2_;
   double r0n[kMaxS];
   double relres[kMaxS];
@@ -83,6 +85,8 @@ struct CgCtl {
   float lam_f[kMaxS * kMaxS];
   float lamsig_f[kMaxS * kMaxS];
   float beta_f[kMaxS * kMaxS];
+  double lamsig_prev[kMaxS * kMaxS];  // lambda sigma of the iteration whose X term is owed
+  float lamsig_prev_f[kMaxS * kMaxS];
 };
 constexpr int kCtlHeaderInts = 24;
 
@@ -145,9 +149,13 @@ template <typename T>
 hipError_t launch_cg_update(int64_t n, int s, T* R, const T* Q, const CgCtl* ctl, T* partial, int nblk, Red red,
                             hipStream_t st, Epi epi = Epi{}, hipEvent_t ev_after = nullptr);
 
-// CG direction update X += P (lambda sigma); if not done: P = R + P beta.
+// CG direction update.  X receives the terms P_k (lambda sigma)_k every other
+// iteration, two at a time (P_{k-1} and P_k), and all owed terms once the
+// solve has ended; unless it has ended, Pn = R + P beta, where Pn holds
+// P_{k-1} on entry (read first, row by row) and P_{k+1} on exit.
 template <typename T>
-hipError_t launch_cg_pupdate(int64_t n, int s, T* X, T* P, const T* R, const CgCtl* ctl, hipStream_t st);
+hipError_t launch_cg_pupdate(int64_t n, int s, T* X, const T* P, T* Pn, const T* R, const CgCtl* ctl,
+                             hipStream_t st);
 
 // X = X C in place (C s x s FP64); with gram, also the Gram X^T X of the
 // result into red.G.  Runs only if gf is null or *gf != 0.

@@ -646,20 +646,43 @@ hipError_t launch_cg_update(int64_t n, int s, T* R, const T* Q, const CgCtl* ctl
   return launch_reduce(s, partial, sizeof(T) == 4, nblk, 1, red, &ctl->gate, nullptr, epi, st);
 }
 
-// X += P (lambda sigma); unless the solve has ended: P = R + P beta.
+// Direction update of block CG with the X update deferred by one iteration:
+// the term P_k (lambda sigma)_k of an iteration whose predecessor's term was
+// already added is held back and added together with the next one, so X is
+// read and written every other iteration.  Once the solve has ended every
+// owed term is added.  Unless it has ended, P_{k+1} = R + P_k beta goes into
+// Pn, which holds P_{k-1} on entry (each lane reads its P_{k-1} entries
+// before it overwrites them).
+template <typename T>
+__device__ __forceinline__ const T* ctl_prev(const CgCtl* ctl);
+template <>
+__device__ __forceinline__ const double* ctl_prev<double>(const CgCtl* ctl) {
+  return ctl->lamsig_prev;
+}
+template <>
+__device__ __forceinline__ const float* ctl_prev<float>(const CgCtl* ctl) {
+  return ctl->lamsig_prev_f;
+}
+
 template <typename T, int S, int VEC>
 __global__ __launch_bounds__(kBlock) void cg_pupdate_kernel(int64_t n, int s, T* __restrict__ X,
-                                                             T* __restrict__ P, const T* __restrict__ R,
-                                                             const CgCtl* ctl) {
+                                                             const T* __restrict__ P, T* __restrict__ Pn,
+                                                             const T* __restrict__ R, const CgCtl* ctl) {
   using L = Layout<T, S, VEC>;
   constexpr int NW = kBlock / kWave;
   constexpr int RPB = NW * L::RPW;
-  __shared__ T ls[S * S];
-  __shared__ T bt[S * S];
-  if (!ctl->x_pending || ctl->suspended) return;
-  const bool pdir = !ctl->done;
-  load_coeff<T, S>(ls, ctl_mat<T>(ctl, 1), s);
-  load_coeff<T, S>(bt, ctl_mat<T>(ctl, 2), s);
+  __shared__ T ls[S * S], lp[S * S], bt[S * S];
+  if (ctl->suspended) return;
+  const bool done = ctl->done != 0;
+  const bool xk = ctl->x_pending != 0;  // this iteration's alpha step ran
+  const bool xin = ctl->xdef_in != 0;   // the previous P's term is owed
+  if (!xk && !xin) return;
+  const bool flush = done || xin;
+  const bool addk = xk && flush;
+  const bool pdir = xk && !done;
+  if (addk) load_coeff<T, S>(ls, ctl_mat<T>(ctl, 1), s);
+  if (xin) load_coeff<T, S>(lp, ctl_prev<T>(ctl), s);
+  if (pdir) load_coeff<T, S>(bt, ctl_mat<T>(ctl, 2), s);
   __syncthreads();
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
   const int r = lane / L::LPR, c = lane % L::LPR;
@@ -670,30 +693,42 @@ __global__ __launch_bounds__(kBlock) void cg_pupdate_kernel(int64_t n, int s, T*
   for (int64_t base = r0; base < r1; base += RPB) {
     const int64_t row = base + wave * L::RPW + r;
     const bool rv = row < r1 && active;
-    vec_t<T, VEC> p = rv ? load_vec<T, VEC>(P + row * s + col0) : zero_vec<T, VEC>();
-    vec_t<T, VEC> x = rv ? load_vec<T, VEC>(X + row * s + col0) : zero_vec<T, VEC>();
-    T dx[VEC];
-    row_times<T, S, VEC>(dx, p, ls, col0, lane);
+    const vec_t<T, VEC> p = rv ? load_vec<T, VEC>(P + row * s + col0) : zero_vec<T, VEC>();
+    if (flush) {
+      vec_t<T, VEC> x = rv ? load_vec<T, VEC>(X + row * s + col0) : zero_vec<T, VEC>();
+      if (xin) {
+        const vec_t<T, VEC> pp = rv ? load_vec<T, VEC>(Pn + row * s + col0) : zero_vec<T, VEC>();
+        T dx[VEC];
+        row_times<T, S, VEC>(dx, pp, lp, col0, lane);
 #pragma unroll
-    for (int w = 0; w < VEC; ++w) x.v[w] += dx[w];
-    if (rv) store_out<T, VEC>(X + row * s + col0, x);
+        for (int w = 0; w < VEC; ++w) x.v[w] += dx[w];
+      }
+      if (addk) {
+        T dx[VEC];
+        row_times<T, S, VEC>(dx, p, ls, col0, lane);
+#pragma unroll
+        for (int w = 0; w < VEC; ++w) x.v[w] += dx[w];
+      }
+      if (rv) store_out<T, VEC>(X + row * s + col0, x);
+    }
     if (pdir) {
       vec_t<T, VEC> rr = rv ? load_vec<T, VEC>(R + row * s + col0) : zero_vec<T, VEC>();
       T pb[VEC];
       row_times<T, S, VEC>(pb, p, bt, col0, lane);
 #pragma unroll
       for (int w = 0; w < VEC; ++w) rr.v[w] += pb[w];
-      if (rv) store_out<T, VEC>(P + row * s + col0, rr);
+      if (rv) store_out<T, VEC>(Pn + row * s + col0, rr);
     }
   }
 }
 
 template <typename T>
-hipError_t launch_cg_pupdate(int64_t n, int s, T* X, T* P, const T* R, const CgCtl* ctl, hipStream_t st) {
+hipError_t launch_cg_pupdate(int64_t n, int s, T* X, const T* P, T* Pn, const T* R, const CgCtl* ctl,
+                             hipStream_t st) {
   int nblk = stream_grid(n, s, sizeof(T));
   return dispatch_s<T>(s, [&](auto S_, auto V_) -> hipError_t {
     constexpr int S = decltype(S_)::value, V = decltype(V_)::value;
-    hipLaunchKernelGGL((cg_pupdate_kernel<T, S, V>), dim3(nblk), dim3(kBlock), 0, st, n, s, X, P, R, ctl);
+    hipLaunchKernelGGL((cg_pupdate_kernel<T, S, V>), dim3(nblk), dim3(kBlock), 0, st, n, s, X, P, Pn, R, ctl);
     return hipGetLastError();
   });
 }
@@ -955,7 +990,7 @@ hipError_t launch_cast_f32(int64_t count, const double* in, float* out, hipStrea
                                      hipStream_t, const int32_t*);                                                 \
   template hipError_t launch_cg_update<T>(int64_t, int, T*, const T*, const CgCtl*, T*, int, Red, hipStream_t,    \
                                           Epi, hipEvent_t);                                                        \
-  template hipError_t launch_cg_pupdate<T>(int64_t, int, T*, T*, const T*, const CgCtl*, hipStream_t);             \
+  template hipError_t launch_cg_pupdate<T>(int64_t, int, T*, const T*, T*, const T*, const CgCtl*, hipStream_t);  \
   template hipError_t launch_rowmul<T>(int64_t, int, T*, const double*, bool, T*, int, Red, const int32_t*,        \
                                        hipStream_t);                                                               \
   template hipError_t launch_block_combine<T>(int64_t, int, const T*, int, const double*, double, T*,               \

@@ -423,6 +423,8 @@ __global__ __launch_bounds__(kSB) void cg_init_kernel(CgCtl* c, const double* G_
       c->gate = allzero;
       c->suspended = 0;
       c->kd_jacobi = 0;
+      c->xdef_in = 0;
+      c->xdef_pend = 0;
       c->nreorth = (c->eta > 0.0 && !allzero) ? 1 : 0;
       c->bad_index = 0;
     }
@@ -462,6 +464,20 @@ __device__ __forceinline__ void cg_alpha_body(CgCtl* c, const double* G, const d
   __shared__ int partner[kMaxS], first[kMaxS];
   const int s = c->s;
   const Sub sub{c->kind, s, c->g};
+  // deferred X update: if the previous iteration's term is still owed, keep
+  // its lambda sigma; this iteration's update then adds both, otherwise it
+  // defers its own term
+  const int xin = c->xdef_pend;
+  if (xin)
+    for (int t = tid(); t < s * s; t += kSB) {
+      c->lamsig_prev[t] = c->lamsig[t];
+      c->lamsig_prev_f[t] = c->lamsig_f[t];
+    }
+  __syncthreads();
+  if (tid() == 0) {
+    c->xdef_in = xin;
+    c->xdef_pend = xin ? 0 : 1;
+  }
   sm_copy(Al, G, s * s);
   sm_project(Al, sub, red);
   bool ok = all_finite(Al, s * s, red);
@@ -608,8 +624,11 @@ __global__ __launch_bounds__(kSB) void reduce_kernel(int s, const T* __restrict_
       for (int t = tid(); t < s; t += kSB) pre_r0n[t] = c->r0n[t];
   }
   if constexpr (EPI == EPI_CG_ALPHA) {
-    if (c->done) {  // ended: the X update of this iteration is dropped
-      if (blockIdx.x == 0 && tid() == 0) c->x_pending = 0;
+    if (c->done) {  // ended: nothing of this iteration reaches X (owed terms were added)
+      if (blockIdx.x == 0 && tid() == 0) {
+        c->x_pending = 0;
+        c->xdef_in = 0;
+      }
       return;
     }
     if (c->gate) return;  // suspended: the iteration waits for its re-normalisation

@@ -82,6 +82,7 @@ CgBufs<T> carve_cg(Carver& c, int64_t n, Sub sub, int hist_cap, uint32_t* cnt) {
   const int nblk = stream_grid(n, s, sizeof(T));
   CgBufs<T> b;
   b.P = c.take<T>((size_t)n * s);
+  b.P2 = c.take<T>((size_t)n * s);
   b.Q = c.take<T>((size_t)n * s);
   b.R = c.take<T>((size_t)n * s);
   b.partial = c.take<T>((size_t)nblk * s * s);
@@ -150,14 +151,20 @@ hipError_t cg_run(const CsrView& A, Sub sub, const T* B, T* X, double tol, int m
   BK_TRY(hipMemcpyAsync(b.P, b.R, sizeof(T) * (size_t)n * s, hipMemcpyDeviceToDevice, st));
 
   const CgCtl* hc = reinterpret_cast<const CgCtl*>(hflags);
+  // P_k lives in pbuf[k % 2]; the direction update writes P_{k+1} over
+  // P_{k-1} (the X update is deferred by one iteration, see cg_pupdate_kernel)
+  T* const pbuf[2] = {b.P, b.P2};
+  int k = 0;  // iteration the next enqueued kernels belong to
   int batch = 4, last_iters = -1;
   while (maxit > 0) {
-    for (int it = 0; it < batch; ++it) {
+    for (int it = 0; it < batch; ++it, ++k) {
+      T* const Pk = pbuf[k & 1];
+      T* const Pn = pbuf[(k + 1) & 1];
       {
         // Q = A P and alpha = <P, Q>_S; the reduction's last workgroup
         // computes lambda, lambda sigma and the re-orthonormalisation test
         ProfScope ps(prof, PROF_CG_SPMM, st);
-        BK_TRY(launch_spmm<T>(A, s, b.P, b.Q, nullptr, 1, b.partial, nblk, ra, &c->bad_index, gate, st,
+        BK_TRY(launch_spmm<T>(A, s, Pk, b.Q, nullptr, 1, b.partial, nblk, ra, &c->bad_index, gate, st,
                               Epi{EPI_CG_ALPHA, c, nullptr}, ps.end()));
       }
       {
@@ -169,7 +176,7 @@ hipError_t cg_run(const CsrView& A, Sub sub, const T* B, T* X, double tol, int m
       if (always) BK_TRY(cg_normalise<T>(n, sub, b, nblk, st, prof));
       {
         ProfScope ps(prof, PROF_CG_PUPDATE, st);
-        BK_TRY(launch_cg_pupdate<T>(n, s, X, b.P, b.R, c, st));
+        BK_TRY(launch_cg_pupdate<T>(n, s, X, Pk, Pn, b.R, c, st));
       }
     }
     BK_TRY(hipMemcpyAsync(hflags, c, kCtlHeaderInts * sizeof(int32_t), hipMemcpyDeviceToHost, st));
@@ -177,13 +184,16 @@ hipError_t cg_run(const CsrView& A, Sub sub, const T* B, T* X, double tol, int m
     BK_TRY(prof_flush(prof));
     if (hc->done) break;
     if (hc->suspended) {
-      // the iteration waits for its re-normalisation: run it, finish the
-      // iteration's direction update, continue with short batches
+      // iteration iters-1 waits for its re-normalisation (the later kernels
+      // of the batch were gated off): run it, finish the iteration's
+      // direction update, continue with short batches
+      const int ks = hc->iters - 1;
       BK_TRY(cg_normalise<T>(n, sub, b, nblk, st, prof));
       {
         ProfScope ps(prof, PROF_CG_PUPDATE, st);
-        BK_TRY(launch_cg_pupdate<T>(n, s, X, b.P, b.R, c, st));
+        BK_TRY(launch_cg_pupdate<T>(n, s, X, pbuf[ks & 1], pbuf[(ks + 1) & 1], b.R, c, st));
       }
+      k = ks + 1;
       batch = 2;
     } else {
       if (hc->iters == last_iters) break;  // no progress (cannot happen while live)

@@ -45,7 +45,7 @@ constexpr size_t kCounterInts = (size_t)kMaxBatch * kCntStride;
 
 template <typename T>
 struct CgBufs {
-  T *P = nullptr, *Q = nullptr, *R = nullptr, *partial = nullptr;
+  T *P = nullptr, *P2 = nullptr, *Q = nullptr, *R = nullptr, *partial = nullptr;
   double *Ga = nullptr, *Gr = nullptr, *Gq = nullptr, *gpart = nullptr, *hist = nullptr;
   CgCtl* ctl = nullptr;
   void* tsqr_ws = nullptr;
