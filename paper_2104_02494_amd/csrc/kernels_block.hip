@@ -112,22 +112,22 @@ int stream_grid(int64_t n, int s, int elem_bytes) {
 // Gather the full row (S values) held in chunks by the LPR lanes of a row
 // slot and accumulate acc[a][b] += mine[a] * row[b] for a in the lane's own
 // chunk.  All 64 lanes must execute this (the row slot's lanes are the
-// shuffle sources).
+// sources); for LPR <= 4 the values move by DPP quad permutations.
 template <typename T, int S, int VEC>
 __device__ __forceinline__ void gram_row(T (&acc)[VEC][S], const vec_t<T, VEC>& mine, const vec_t<T, VEC>& other,
                                          int lane) {
   constexpr int LPR = S / VEC;
-  const int base = lane & ~(LPR - 1);
-#pragma unroll
-  for (int cc = 0; cc < LPR; ++cc) {
+  (void)lane;
+  static_for<LPR>([&](auto cc_) {
+    constexpr int cc = decltype(cc_)::value;
     T o[VEC];
 #pragma unroll
-    for (int w = 0; w < VEC; ++w) o[w] = __shfl(other.v[w], base | cc);
+    for (int w = 0; w < VEC; ++w) o[w] = group_bcast<LPR, cc>(other.v[w]);
 #pragma unroll
     for (int a = 0; a < VEC; ++a)
 #pragma unroll
       for (int w = 0; w < VEC; ++w) acc[a][cc * VEC + w] += mine.v[a] * o[w];
-  }
+  });
 }
 
 // out[w] = sum_b row[b] * C[b][col0 + w] with the row gathered from the row
@@ -135,19 +135,19 @@ __device__ __forceinline__ void gram_row(T (&acc)[VEC][S], const vec_t<T, VEC>& 
 template <typename T, int S, int VEC>
 __device__ __forceinline__ void row_times(T (&out)[VEC], const vec_t<T, VEC>& mine, const T* C, int col0, int lane) {
   constexpr int LPR = S / VEC;
-  const int base = lane & ~(LPR - 1);
+  (void)lane;
 #pragma unroll
   for (int w = 0; w < VEC; ++w) out[w] = T(0);
-#pragma unroll
-  for (int cc = 0; cc < LPR; ++cc) {
+  static_for<LPR>([&](auto cc_) {
+    constexpr int cc = decltype(cc_)::value;
 #pragma unroll
     for (int w2 = 0; w2 < VEC; ++w2) {
-      T o = __shfl(mine.v[w2], base | cc);
+      const T o = group_bcast<LPR, cc>(mine.v[w2]);
       const T* crow = C + (cc * VEC + w2) * S + col0;
 #pragma unroll
       for (int w = 0; w < VEC; ++w) out[w] += o * crow[w];
     }
-  }
+  });
 }
 
 // Reduce per-lane Gram accumulators of a workgroup into its s x s partial
