@@ -107,11 +107,13 @@ int bkry_synchronize(bkry_handle h);
 /* Message of the last failing call on this handle (valid until the next call). */
 const char* bkry_last_error(bkry_handle h);
 
-/* Kernel timing (measurement support, not part of the method): `enable` is a
- * bit mask of kernel ids (bit k times id k; 0 turns timing off, 0xF times all
- * four).  The block CG driver brackets each launch of a selected streaming
- * kernel with HIP events on the handle's stream and accumulates the elapsed
- * times (each event pair adds a few microseconds to the solve).  Kernel
+/* Kernel timing (measurement support, not part of the method): bits 0-7 of
+ * `enable` are a mask of kernel ids (bit k times id k; 0 turns timing off,
+ * 0xF times all four), bits 8-15 an optional sampling stride N (time one
+ * launch in N of each kernel; 0 or 1 times every launch).  The block CG
+ * driver brackets each selected launch of a streaming kernel with HIP events
+ * on the handle's stream and accumulates the elapsed times (each event pair
+ * adds a few microseconds to the solve).  Kernel
  * ids: 0 SpMM fused with the alpha Gram partials, 1 residual update fused
  * with the Gram partials of R~ (for 0 and 1 the Gram reductions and
  * coefficient steps that follow are not included), 2 direction update

@@ -307,9 +307,10 @@ def bkry_set_spmm_format(h: Handle, fmt):
     h._check(lib().bkry_set_spmm_format(h.h, f))
 
 
-def bkry_profile(h: Handle, enable=True, kernels=None):
+def bkry_profile(h: Handle, enable=True, kernels=None, every=1):
     """Event timing of the CG driver's streaming kernels: enable=False turns
-    it off; `kernels` lists the kernel ids to time (default: all four)."""
+    it off; `kernels` lists the kernel ids to time (default: all four);
+    `every` times one launch in that many of each kernel."""
     if not enable:
         mask = 0
     elif kernels is None:
@@ -318,7 +319,9 @@ def bkry_profile(h: Handle, enable=True, kernels=None):
         mask = 0
         for k in kernels:
             mask |= 1 << int(k)
-    h._check(lib().bkry_profile(h.h, mask))
+    if mask and not 1 <= int(every) <= 255:
+        raise ValueError("every must be in [1, 255]")
+    h._check(lib().bkry_profile(h.h, mask | ((int(every) if mask else 0) << 8)))
 
 
 def bkry_profile_read(h: Handle, kernel: int, reset: bool = False):

@@ -260,14 +260,16 @@ int bkry_synchronize(bkry_handle h) {
 int bkry_profile(bkry_handle h, int enable) {
   int rc = begin(h);
   if (rc) return rc;
-  if (enable & ~((1 << PROF_N) - 1)) return fail(h, BKRY_E_INVALID, "unknown kernel id in the timing mask");
+  const int mask = enable & 0xFF, every = (enable >> 8) & 0xFF;
+  if (mask & ~((1 << PROF_N) - 1) || (enable >> 16)) return fail(h, BKRY_E_INVALID, "bad kernel timing mask");
   if (enable && !h->prof) {
     h->prof = new (std::nothrow) Prof();
     if (!h->prof) return fail(h, BKRY_E_ALLOC, "profile state");
     API_HIP(prof_init(h->prof), "profile");
   }
   if (enable) {
-    h->prof->mask = enable;
+    h->prof->mask = mask;
+    h->prof->every = every > 1 ? every : 1;
   } else if (h->prof) {
     API_HIP(hipStreamSynchronize(h->stream), "profile");
     prof_destroy(h->prof);

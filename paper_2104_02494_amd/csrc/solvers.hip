@@ -57,7 +57,8 @@ struct ProfScope {
   int k;
   hipStream_t st;
   bool handed = false;
-  ProfScope(Prof* p_, int k_, hipStream_t st_) : p((p_ && (p_->mask >> k_ & 1)) ? p_ : nullptr), k(k_), st(st_) {
+  ProfScope(Prof* p_, int k_, hipStream_t st_)
+      : p((p_ && (p_->mask >> k_ & 1) && p_->seen[k_]++ % p_->every == 0) ? p_ : nullptr), k(k_), st(st_) {
     if (p && p->used[k] < kProfSlots) (void)hipEventRecord(p->ev[k][0][p->used[k]], st);
   }
   // End event for a launcher to record after its streaming kernel (or null).

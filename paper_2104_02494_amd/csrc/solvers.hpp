@@ -30,6 +30,8 @@ struct Prof {
   double ms[PROF_N];
   long long cnt[PROF_N];
   int mask = (1 << PROF_N) - 1;  // kernel ids that are timed (bit k = id k)
+  int every = 1;                  // time one launch in `every` of each kernel
+  long long seen[PROF_N] = {};    // launches seen per kernel id
 };
 hipError_t prof_init(Prof* p);
 void prof_destroy(Prof* p);
