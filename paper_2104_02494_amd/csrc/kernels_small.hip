@@ -112,17 +112,14 @@ __device__ __forceinline__ double sm_kappaD(const double* A, int s, double* M, d
   }
   __syncthreads();
   for (int sweep = 0; sweep < 40; ++sweep) {
-    if (tid() == 0) {
-      double off = 0.0, tot = 0.0;
-      for (int e = 0; e < sp * sp; ++e) {
-        const double v = M[e] * M[e];
-        tot += v;
-        if (e / sp != e % sp) off += v;
-      }
-      red[1] = (off == 0.0 || off <= 1e-30 * tot) ? 1.0 : 0.0;
+    double offl = 0.0, totl = 0.0;
+    for (int e = tid(); e < sp * sp; e += kSB) {
+      const double v = M[e] * M[e];
+      totl += v;
+      if (e / sp != e % sp) offl += v;
     }
-    __syncthreads();
-    if (red[1] != 0.0) break;
+    const double off = wsum(offl), tot = wsum(totl);
+    if (off == 0.0 || off <= 1e-30 * tot) break;
     for (int round = 0; round < sp - 1; ++round) {
       if (tid() < sp / 2) {
         const int pa = tid(), pb = sp - 1 - tid();
@@ -178,12 +175,6 @@ __device__ __forceinline__ double sm_kappaD(const double* A, int s, double* M, d
   return red[2];
 }
 
-// Re-orthonormalisation test: fire iff eta * kappa_D(alpha) * sqrt(eps) > 1
-// (eta = 0 never, eta = infinity always); kappa_D equals 1 for the diagonal
-// subalgebras.  L is the Cholesky factor of alpha.  Before the eigenvalues,
-// an exact upper bound is tried: with M = D^-1/2 alpha D^-1/2 = L_M L_M^T,
-// kappa_D = |M|_2 |M^-1|_2 <= |M|_F |L_M^-1|_F^2; when even the bound does not
-// fire, the test does not fire (same decision as with kappa_D itself).
 // ---------------------------------------- register-resident Cholesky --
 // Value of v in lane `lane` (uniform result; the lane need not be active).
 __device__ __forceinline__ double readlane_d(double v, int lane) {
@@ -205,11 +196,13 @@ __device__ __forceinline__ double readlane_d(double v, int lane) {
 // row i of L in l (entries above the diagonal are left over from A) and
 // rinv[k] = 1 / L_kk in every lane.  False (uniformly) on a non-positive or
 // non-finite pivot.
+// With sa, sh given, the matrix factored is sa A + sh I.
 template <int SM>
-__device__ __forceinline__ bool rf_factor(const double* A, int s, double (&l)[SM], double (&rinv)[SM]) {
+__device__ __forceinline__ bool rf_factor(const double* A, int s, double (&l)[SM], double (&rinv)[SM],
+                                          double sa = 1.0, double sh = 0.0) {
   const int t = tid();
 #pragma unroll
-  for (int j = 0; j < SM; ++j) l[j] = (t < s && j < s) ? A[t * s + j] : 0.0;
+  for (int j = 0; j < SM; ++j) l[j] = (t < s && j < s) ? fma(sa, A[t * s + j], t == j ? sh : 0.0) : 0.0;
 #pragma unroll
   for (int k = 0; k < SM; ++k) {
     rinv[k] = 0.0;
@@ -329,6 +322,40 @@ __device__ __forceinline__ bool rf_cholesky_factor(const double* A, double* Lo, 
   return true;
 }
 
+// Whether sa A + sh I (A symmetric s x s, LDS) is positive definite, by
+// attempting its Cholesky factorisation (uniform result).
+template <int SM>
+__device__ __forceinline__ bool rf_definite(const double* A, int s, double sa, double sh) {
+  double l[SM], rinv[SM];
+  return rf_factor<SM>(A, s, l, rinv, sa, sh);
+}
+
+// Rayleigh quotient of the power iteration for the symmetric s x s matrix A
+// (LDS) from the all-ones vector, after at most 64 steps or once it changes
+// by less than 1e-6 relative.  It never exceeds lambda_max(A) (uniform).
+template <int SM>
+__device__ __forceinline__ double rf_power_lmax(const double* A, int s) {
+  const int t = tid();
+  double a[SM];
+#pragma unroll
+  for (int j = 0; j < SM; ++j) a[j] = (t < s && j < s) ? A[t * s + j] : 0.0;
+  double x = (t < s) ? 1.0 : 0.0, theta = 0.0;
+  for (int it = 0; it < 64; ++it) {
+    double y = 0.0;
+#pragma unroll
+    for (int j = 0; j < SM; ++j)
+      if (j < s) y = fma(a[j], readlane_d(x, j), y);
+    const double xx = wsum(x * x), xy = wsum(x * y), yy = wsum(y * y);
+    const double th = xy / xx;
+    if (!(yy > 0.0) || !isfinite(yy)) return th;
+    x = y / sqrt(yy);
+    const bool settled = it > 0 && fabs(th - theta) <= 1e-6 * fabs(th);
+    theta = th;
+    if (settled) break;
+  }
+  return theta;
+}
+
 // The re-orthonormalisation is decided per iteration (the L^-1 bound of the
 // kappa_D test is needed) only for 0 < eta < inf, eta sqrt(eps) <= 1, g > 1.
 __device__ __forceinline__ bool reortho_dynamic(const CgCtl* c) {
@@ -337,6 +364,14 @@ __device__ __forceinline__ bool reortho_dynamic(const CgCtl* c) {
 
 // The kappa_D test of the iteration.  T holds L^-1 (alpha = L L^T) whenever
 // reortho_dynamic(c); it is then overwritten.
+// Re-orthonormalisation test: fire iff eta * kappa_D(alpha) * sqrt(eps) > 1
+// (eta = 0 never, eta = infinity always); kappa_D equals 1 for the diagonal
+// subalgebras.  T holds L^-1 for the Cholesky factor L of alpha.  The
+// decision is the one kappa_D itself gives; it is reached, cheapest first, by
+// guaranteed bounds on kappa_D, by definiteness tests of shifted copies of
+// M = D^-1/2 alpha D^-1/2, and only when both leave it open by the Jacobi
+// eigenvalues of M.
+template <int SM>
 __device__ __forceinline__ bool reortho_test(CgCtl* c, const double* alpha, double* M, double* T, double* rc,
                                              double* rs, int* partner, int* first, double* red) {
   if (!(c->eta > 0.0)) return false;
@@ -345,6 +380,13 @@ __device__ __forceinline__ bool reortho_test(CgCtl* c, const double* alpha, doub
   if (c->eta * c->sqrt_eps > 1.0) return true;  // kappa_D >= 1
   if (c->g <= 1) return false;                  // kappa_D = 1
   __syncthreads();
+  // Guaranteed bounds on kappa_D = lambda_max(M) / lambda_min(M) for
+  // M = D^-1/2 alpha D^-1/2 = L_M L_M^T, L_M^-1 = L^-1 D^1/2 (T holds L^-1):
+  //   above: lambda_max <= min(|M|_F, |M|_inf) and
+  //          1 / lambda_min = |L_M^-1|_2^2 <= min(|L_M^-1|_F^2, |L_M^-1|_1 |L_M^-1|_inf);
+  //   below: lambda_max >= max(1, 1^T M 1 / s) (unit diagonal, Rayleigh
+  //          quotient) and 1 / lambda_min >= max_i (M^-1)_ii.
+  // The eigenvalues are computed only when the bounds leave the decision open.
   double fm = 0.0, li = 0.0;
   for (int e = tid(); e < s * s; e += kSB) {
     const int i = e / s, j = e % s;
@@ -352,8 +394,44 @@ __device__ __forceinline__ bool reortho_test(CgCtl* c, const double* alpha, doub
     fm += a * a / (alpha[i * s + i] * alpha[j * s + j]);
     li += T[e] * T[e] * alpha[j * s + j];
   }
-  const double bound = sqrt(wsum(fm)) * wsum(li);
-  if (isfinite(bound) && bound * (1.0 + 1e-12) * c->eta * c->sqrt_eps <= 1.0) return false;
+  double rowM = 0.0, sumM = 0.0, rowL = 0.0, colL = 0.0, dinv = 0.0;
+  const int t = tid();
+  if (t < s) {
+    const double at = alpha[t * s + t], st = sqrt(at);
+    for (int j = 0; j < s; ++j) {
+      const double aj = alpha[j * s + j], sj = sqrt(aj);
+      const double mtj = alpha[t * s + j] / (st * sj);
+      rowM += fabs(mtj);
+      sumM += mtj;
+      rowL += fabs(T[t * s + j] * sj);  // row t of L_M^-1
+      const double ljt = T[j * s + t] * st;  // column t of L_M^-1
+      colL += fabs(ljt);
+      dinv += ljt * ljt;
+    }
+  }
+  const double nF = sqrt(wsum(fm)), nInf = wmax(rowM);
+  const double ub = fmin(nF * wsum(li), fmin(nF, nInf) * wmax(colL) * wmax(rowL));
+  const double es = c->eta * c->sqrt_eps;
+  if (isfinite(ub) && ub * (1.0 + 1e-12) * es <= 1.0) return false;
+  const double lb = fmax(1.0, wsum(sumM) / s) * wmax(dinv);
+  if (isfinite(lb) && lb * (1.0 - 1e-12) * es > 1.0) return true;
+  // Definiteness tests, with tau = 1 / es: theta <= lambda_max < mu
+  // (power iteration, then mu I - M positive definite).  M - theta/tau I
+  // not positive definite gives lambda_min <= theta/tau <= lambda_max/tau
+  // (fires); M - mu/tau I positive definite gives lambda_min > lambda_max/tau
+  // (does not fire).  Only a lambda_min between the two shifts is left to
+  // the eigenvalues.
+  for (int e = tid(); e < s * s; e += kSB) {
+    const int i = e / s, j = e % s;
+    M[e] = alpha[e] / sqrt(alpha[i * s + i] * alpha[j * s + j]);
+  }
+  __syncthreads();
+  const double theta = rf_power_lmax<SM>(M, s), mu = theta * (1.0 + 1e-3);
+  if (theta > 0.0 && isfinite(theta) && rf_definite<SM>(M, s, -1.0, mu)) {
+    if (!rf_definite<SM>(M, s, 1.0, -theta * es)) return true;
+    if (rf_definite<SM>(M, s, 1.0, -mu * es)) return false;
+  }
+  __syncthreads();
   const double kd = sm_kappaD(alpha, s, M, T, rc, rs, partner, first, red);
   if (tid() == 0) c->kd_jacobi += 1;
   return c->eta * kd * c->sqrt_eps > 1.0;
@@ -504,7 +582,7 @@ __device__ __forceinline__ void cg_alpha_body(CgCtl* c, const double* G, const d
   store_coeff(c->lam, c->lam_f, Lm, s);
   store_coeff(c->lamsig, c->lamsig_f, LS, s);
   sm_copy(c->alpha, Al, s * s);
-  const bool fire = reortho_test(c, Al, W, T, rc, rs, partner, first, red);
+  const bool fire = reortho_test<SM>(c, Al, W, T, rc, rs, partner, first, red);
   __syncthreads();
   if (tid() == 0) {
     c->fire = fire ? 1 : 0;
@@ -595,12 +673,14 @@ __device__ __forceinline__ double sum_strided(const T* __restrict__ p, int64_t s
   constexpr int K = 32;
   double acc = 0.0;
   for (int b = 0; b < count; b += K) {
-    double v[K];
+    // unconditional loads (indexes past the end re-read the last partial and
+    // are not added): a load under a branch would be waited for on its own
+    T v[K];
 #pragma unroll
-    for (int u = 0; u < K; ++u) v[u] = (b + u < count) ? (double)p[(int64_t)(b + u) * stride] : 0.0;
+    for (int u = 0; u < K; ++u) v[u] = p[(int64_t)min(b + u, count - 1) * stride];
 #pragma unroll
     for (int u = 0; u < K; ++u)
-      if (b + u < count) acc += v[u];
+      if (b + u < count) acc += (double)v[u];
   }
   return acc;
 }
