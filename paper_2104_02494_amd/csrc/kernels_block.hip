@@ -63,6 +63,14 @@ template <typename T, int N>
 __device__ __forceinline__ void store_out(T* p, const vec_t<T, N>& x) {
   store_vec<T, N>(p, x);
 }
+// Store of a streaming output with the non-temporal hint.  On MI355X this
+// is faster for the SpMM output and the direction update (measured), and
+// slower for the in-place residual update, which keeps store_out.
+template <typename T, int N>
+__device__ __forceinline__ void store_nt(T* p, const vec_t<T, N>& x) {
+#pragma unroll
+  for (int i = 0; i < N; ++i) __builtin_nontemporal_store(x.v[i], p + i);
+}
 
 static int next_pow2(int s) {
   int S = 1;
@@ -301,7 +309,7 @@ __global__ __launch_bounds__(kBlock) void spmm_csr_kernel(int64_t n, int64_t nnz
 #pragma unroll
       for (int w = 0; w < VEC; ++w) acc.v[w] = own.v[w] - acc.v[w];
     }
-    if (rv) store_out<T, VEC>(Y + row * s + col0, acc);
+    if (rv) store_nt<T, VEC>(Y + row * s + col0, acc);
     if constexpr (MODE == 1) {
       gram_row<T, S, VEC>(gacc, own, acc, lane);
     } else if constexpr (MODE == 2) {
@@ -427,7 +435,7 @@ __global__ __launch_bounds__(kBlock) void spmm_ell_kernel(int64_t n, int W, cons
 #pragma unroll
       for (int w = 0; w < VEC; ++w) acc.v[w] = own.v[w] - acc.v[w];
     }
-    if (rv) store_out<T, VEC>(Y + row * s + col0, acc);
+    if (rv) store_nt<T, VEC>(Y + row * s + col0, acc);
     if constexpr (MODE == 1) {
       gram_row<T, S, VEC>(gacc, own, acc, lane);
     } else if constexpr (MODE == 2) {
@@ -723,7 +731,7 @@ __global__ __launch_bounds__(kBlock) void cg_pupdate_kernel(int64_t n, int s, T*
 #pragma unroll
         for (int w = 0; w < VEC; ++w) x.v[w] += dx[w];
       }
-      if (rv) store_out<T, VEC>(X + row * s + col0, x);
+      if (rv) store_nt<T, VEC>(X + row * s + col0, x);
     }
     if (pdir) {
       vec_t<T, VEC> rr = rv ? load_vec<T, VEC>(R + row * s + col0) : zero_vec<T, VEC>();
@@ -731,7 +739,7 @@ __global__ __launch_bounds__(kBlock) void cg_pupdate_kernel(int64_t n, int s, T*
       row_times<T, S, VEC>(pb, p, bt, col0, lane);
 #pragma unroll
       for (int w = 0; w < VEC; ++w) rr.v[w] += pb[w];
-      if (rv) store_out<T, VEC>(Pn + row * s + col0, rr);
+      if (rv) store_nt<T, VEC>(Pn + row * s + col0, rr);
     }
   }
 }

@@ -3,8 +3,9 @@
 Solutions are compared at equal iteration counts (tol = 0, same maxit): both
 sides then run the same arithmetic and must agree to a relative error of
 1e-10 in FP64.  Converged solves are compared on iteration counts, residual
-histories and the FP64 true residual.  eta is pinned at 0 and infinity (the
-branch decision of intermediate eta near the kappa_D threshold is unpinned)."""
+histories and the FP64 true residual.  eta is pinned at 0 and infinity, and
+at intermediate values whose kappa_D decisions are clear of the threshold
+(a kappa_D within rounding of the threshold can go either way)."""
 import numpy as np
 import pytest
 
@@ -65,6 +66,38 @@ def test_cg_eta_1e4_converges(orc, h, kind, q):
     assert info["converged"] and max(info["true_relres"]) <= 1.5e-10
     Xs = np.linalg.solve(A.to_dense(), B)
     assert rel(X, Xs) < 1e-7
+
+
+ETAS = [1e2, 1e3, 1e4, 1e5, 1e6, 1e7]
+
+
+@pytest.mark.parametrize("name,s,kind,q", [("poisson32", 4, "block", 1), ("laplace41", 8, "block", 1),
+                                           ("laplace41", 16, "block", 1), ("laplace41", 16, "hybrid", 2)])
+def test_cg_reortho_decisions_match_oracle(orc, h, name, s, kind, q):
+    """Intermediate eta: the kappa_D test fires at the same iterations as
+    the oracle's (same iteration and re-orthonormalisation counts, same
+    residual history).  Each eta is used only where every kappa_D of the
+    oracle's run is at least 1e-6 (relative) away from the threshold
+    1 / (eta sqrt(eps)), so that rounding cannot decide."""
+    if name == "poisson32":
+        A, B, _ = W.build_workload("poisson2d_32x32_s4")
+    else:
+        A = W.laplace_2d(41)
+        B = W.uniform_block(A.n, s, s)
+    sq = np.sqrt(orc.eps_f64())
+    used = 0
+    for eta in ETAS:
+        ro = orc.bcg(A, B, kind=kind, q=q, tol=1e-10, maxit=3000, eta=eta, hist_cap=3000, record_blocks=3000)
+        kd = [orc.kappa_D(orc.bdot(Pk, orc.spmm(A, Pk), kind, q)) for Pk in ro["Pk"]]
+        if min(abs(eta * k * sq - 1.0) for k in kd) < 1e-6:
+            continue
+        used += 1
+        say("cg reortho decisions", name, s, kind, eta)
+        X, info = gpu_cg(h, A, B, kind=kind, q=q, tol=1e-10, maxit=3000, eta=eta, hist_cap=3000)
+        assert info["converged"] and ro["converged"]
+        assert (info["iters"], info["reorth"]) == (ro["iters"], ro["reorth"])
+        assert np.allclose(info["hist"], ro["hist"], rtol=1e-6, atol=1e-15)
+    assert used >= 4
 
 
 def test_cg_edge_cases(orc, h):
