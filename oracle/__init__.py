@@ -61,7 +61,7 @@ def lib():
             "or_kappa_D": (dbl, [i32, ptr]),
             "or_reortho_fires": (i32, [dbl, dbl, dbl]),
             "or_bcg": (i32, [i64, ptr, ptr, ptr, i32, i32, i32, ptr, ptr, dbl, i32, dbl, dbl, ptr, ptr, ptr, i32,
-                             ptr, ptr, i32]),
+                             ptr, ptr, i32, ptr]),
             "or_block_arnoldi": (i32, [i64, ptr, ptr, ptr, i32, i32, i32, ptr, i32, ptr, ptr, ptr]),
             "or_bgmres": (i32, [i64, ptr, ptr, ptr, i32, i32, i32, ptr, ptr, dbl, i32, i32, ptr, ptr, ptr, i32]),
             "or_sddmm": (None, [i64, ptr, ptr, i32, dbl, ptr, ptr, ptr]),
@@ -193,8 +193,10 @@ def eps_f32():
 
 
 def bcg(A, B, X0=None, kind="block", q=1, tol=1e-10, maxit=1000, eta=0.0, eps=None, hist_cap=0,
-        record_blocks=0):
-    """Adaptive block CG.  Returns dict(status, X, iters, reorth, converged, relres, hist, Pk, Rk)."""
+        record_blocks=0, minv=None):
+    """Adaptive block CG, preconditioned by the diagonal M with M^-1 = diag(minv)
+    (minv=None: M = I).  Returns dict(status, X, iters, reorth, converged,
+    relres, hist, Pk, Rk)."""
     n, rp, ci, v = _csr(A)
     B = _f64(B)
     s = B.shape[1]
@@ -205,9 +207,12 @@ def bcg(A, B, X0=None, kind="block", q=1, tol=1e-10, maxit=1000, eta=0.0, eps=No
     Pk = np.zeros((record_blocks, n, s)) if record_blocks else None
     Rk = np.zeros((record_blocks, n, s)) if record_blocks else None
     eps = eps_f64() if eps is None else eps
+    mv = None if minv is None else _f64(minv)
+    if mv is not None and mv.shape != (n,):
+        raise ValueError("minv must hold n entries")
     st = lib().or_bcg(n, _p(rp), _p(ci), _p(v), s, _kind(kind), q, _p(B), _p(X), tol, maxit, eta, eps,
                       _p(info), _p(relres), _p(hist) if hist_cap else None, hist_cap,
-                      _p(Pk), _p(Rk), record_blocks)
+                      _p(Pk), _p(Rk), record_blocks, _p(mv))
     it = int(info[0])
     return dict(status=st, X=X, iters=it, reorth=int(info[1]), converged=bool(info[2]), relres=relres,
                 hist=hist[:min(it, hist_cap)] if hist_cap else None,

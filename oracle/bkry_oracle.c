@@ -396,21 +396,28 @@ static double max_rel(int s, const double* num, const double* den, double* rel) 
   return m;
 }
 
+/* Z = M^-1 R for a diagonal M (row i scaled by minv[i]); minv = NULL: copy. */
+static void apply_minv(i64 n, int s, const double* minv, const double* R, double* Z) {
+  for (i64 i = 0; i < n; ++i)
+    for (int j = 0; j < s; ++j) Z[i * s + j] = minv ? minv[i] * R[i * s + j] : R[i * s + j];
+}
+
 /* ------------------------------------------------------------------------ */
 /* Block CG with adaptive residual re-orthonormalisation (Algorithm          */
-/* "BCG Method with Adaptive Residual Re-Orthonormalization", Ch. 4), with   */
-/* the identity preconditioner, so Z = R-bar and rho = <R-bar, R-bar>_S.     */
+/* "BCG Method with Adaptive Residual Re-Orthonormalization", Ch. 4) with a  */
+/* diagonal preconditioner M: minv[i] = (M^-1)_ii, or minv = NULL for M = I  */
+/* (then Z = R-bar is a plain copy and rho = <R-bar, R-bar>_S).              */
 /*                                                                          */
 /*   R0 = B - A X0                                                           */
 /*   (R-bar, sigma) = Norm_S(R0) if eta > 0, else (R0, I)                    */
-/*   P = R-bar, rho = <P, R-bar>_S                                           */
+/*   P = M^-1 R-bar, rho = <P, R-bar>_S                                      */
 /*   repeat: Q = A P; alpha = <P,Q>_S; lambda = alpha^-1 rho;                */
 /*           X += P lambda sigma; R~ = R-bar - Q lambda;                     */
 /*           if the test fires: (R-bar, gamma) = Norm_S(R~), sigma = gamma sigma */
 /*           else R-bar = R~, gamma = I;                                     */
 /*           stop if max_i |(R-bar sigma)_i| / |R0_i| <= tol;                */
-/*           rho' = <R-bar, R-bar>_S; beta = rho^-1 gamma^T rho';            */
-/*           P = R-bar + P beta; rho = rho'.                                 */
+/*           Z = M^-1 R-bar; rho' = <Z, R-bar>_S; beta = rho^-1 gamma^T rho'; */
+/*           P = Z + P beta; rho = rho'.                                     */
 /*                                                                          */
 /* The stopping norm is the maximum column 2-norm (the thesis' choice),      */
 /* taken relative to the initial residual column.  After a normalisation the */
@@ -426,7 +433,7 @@ static double max_rel(int s, const double* num, const double* den, double* rel) 
 /* ------------------------------------------------------------------------ */
 int or_bcg(i64 n, const int32_t* rowptr, const int32_t* colind, const double* val, int s, int kind, int q,
            const double* B, double* X, double tol, int maxit, double eta, double eps, int32_t* info,
-           double* relres, double* hist, int hist_cap, double* Pk, double* Rk, int cap_blocks) {
+           double* relres, double* hist, int hist_cap, double* Pk, double* Rk, int cap_blocks, const double* minv) {
   if (!valid_subalg(s, kind, q) || s > 64 || n < group_width(s, kind, q)) return OR_E_INVALID;
   size_t blk = (size_t)(n * s);
   double* R = (double*)calloc(blk, sizeof(double));
@@ -458,7 +465,7 @@ int or_bcg(i64 n, const int32_t* rowptr, const int32_t* colind, const double* va
   } else {
     eye(s, sigma);
   }
-  memcpy(P, R, blk * sizeof(double));
+  apply_minv(n, s, minv, R, P);                       /* P = M^-1 R-bar */
   or_bdot(n, s, kind, q, P, R, rho);
 
   for (int k = 0; k < maxit; ++k) {
@@ -506,12 +513,12 @@ int or_bcg(i64 n, const int32_t* rowptr, const int32_t* colind, const double* va
     if (hist && k < hist_cap) hist[k] = m;
     if (isnan(m)) { st = OR_E_NONFINITE; goto done; }
     if (m <= tol) { conv = 1; break; }
-    or_bdot(n, s, kind, q, R, R, rho_new);            /* rho' = <R-bar, R-bar>_S */
+    apply_minv(n, s, minv, R, T);                     /* Z = M^-1 R-bar */
+    or_bdot(n, s, kind, q, T, R, rho_new);            /* rho' = <Z, R-bar>_S */
     mtm(s, gamma, rho_new, tmp);                      /* beta = rho^-1 gamma^T rho' */
     st = or_chol_solve(s, kind, q, rho, tmp, beta);
     if (st != OR_OK) goto done;
-    memcpy(T, R, blk * sizeof(double));               /* P = R-bar + P beta */
-    block_axpy(n, s, P, beta, T);
+    block_axpy(n, s, P, beta, T);                     /* P = Z + P beta */
     memcpy(P, T, blk * sizeof(double));
     memcpy(rho, rho_new, ss * sizeof(double));
   }

@@ -52,6 +52,19 @@ def galerkin_minimiser(A, B, X0, k, kind, q=1):
     return X0 + (U @ c).reshape((n, s), order="F")
 
 
+def galerkin_minimiser_prec(A, B, X0, k, kind, q, minv):
+    """argmin over X0 + K_k^S(M^-1 A, M^-1 R0) of |X - X*|_{A,F} for the
+    diagonal preconditioner M^-1 = diag(minv): the k-th preconditioned block
+    CG iterate (the minimisation property of Ch. 4 with M != I)."""
+    n, s = B.shape
+    R0 = B - A @ X0
+    Mi = np.diag(minv)
+    U = krylov_basis(Mi @ A, Mi @ R0, k, kind, q)
+    Ahat = np.kron(np.eye(s), A)
+    c = np.linalg.solve(U.T @ Ahat @ U, U.T @ R0.reshape(-1, order="F"))
+    return X0 + (U @ c).reshape((n, s), order="F")
+
+
 def residual_minimiser(A, B, X0, k, kind, q=1):
     """argmin over X0 + K_k^S(A, R0) of |B - A X|_F (the block GMRes iterate)."""
     n, s = B.shape

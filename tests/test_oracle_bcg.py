@@ -14,8 +14,8 @@ import numpy as np
 import pytest
 
 import workloads as W
-from krylov_ref import (energy_fro, galerkin_minimiser, laplace2d_eigpair, laplace2d_extremes,
-                        textbook_cg)
+from krylov_ref import (energy_fro, galerkin_minimiser, galerkin_minimiser_prec, laplace2d_eigpair,
+                        laplace2d_extremes, textbook_cg)
 
 SUBALGS = [("block", 1), ("hybrid", 2), ("parallel", 1), ("global", 1)]
 
@@ -203,3 +203,98 @@ def test_bcg_recursive_residual_tracks_true_residual(orc):
         true = np.linalg.norm(B - D @ r["X"], axis=0) / np.linalg.norm(B, axis=0)
         assert np.allclose(true, r["relres"], rtol=1e-3, atol=1e-13)
         assert r["relres"].max() <= 1e-10
+
+
+# ------------------------------------------------ diagonal preconditioner --
+def prec_problem(N=4, s=4, seed=0):
+    """Variable-coefficient 7-point diffusion (diagonal far from constant)
+    with the Jacobi preconditioner M = diag(A)."""
+    A = W.diffusion_7pt_var(N, seed=5 + N)
+    D = A.to_dense()
+    minv = 1.0 / np.diag(D)
+    B = W.uniform_block(A.n, s, seed)
+    return A, D, B, minv
+
+
+@pytest.mark.parametrize("kind,q", SUBALGS)
+@pytest.mark.parametrize("eta", [0.0, np.inf])
+def test_pbcg_iterates_are_energy_minimisers(orc, kind, q, eta):
+    """With M != I the k-th iterate minimises the A-energy error over
+    X0 + K_k^S(M^-1 A, M^-1 R0)."""
+    A, D, B, minv = prec_problem()
+    assert np.ptp(minv) > 0.5 * minv.max()       # a genuinely non-constant M
+    X0 = W.gaussian_block(A.n, 4, 19) * 0.1
+    for k in (1, 2, 3, 4):
+        r = orc.bcg(A, B, X0, kind=kind, q=q, tol=0.0, maxit=k, eta=eta, minv=minv)
+        assert r["iters"] == k
+        Xr = galerkin_minimiser_prec(D, B, X0, k, kind, q, minv)
+        err = np.linalg.norm(r["X"] - Xr) / np.linalg.norm(Xr)
+        assert err < 1e-10, (k, err)
+        # and it is not the unpreconditioned iterate
+        if k > 1:
+            assert np.linalg.norm(r["X"] - galerkin_minimiser(D, B, X0, k, kind, q)) > 1e-6 * np.linalg.norm(Xr)
+
+
+def test_pbcg_s1_and_parallel_are_scipy_pcg(orc):
+    """s = 1 and the parallel subalgebra reduce to textbook preconditioned CG
+    (scipy.sparse.linalg.cg with M = diag(minv)), column by column."""
+    import scipy.sparse as sp
+    from scipy.sparse.linalg import cg
+    A, D, B, minv = prec_problem(N=5, s=3)
+    As, Ms = sp.csr_matrix(D), sp.diags(minv)
+    for k in (1, 2, 5, 9):
+        r1 = orc.bcg(A, B[:, :1], kind="block", tol=0.0, maxit=k, minv=minv)
+        rp = orc.bcg(A, B, kind="parallel", tol=0.0, maxit=k, minv=minv)
+        for j in range(3):
+            x, _ = cg(As, B[:, j], x0=np.zeros(A.n), rtol=0.0, atol=0.0, maxiter=k, M=Ms)
+            sc = np.abs(x).max()
+            assert np.allclose(rp["X"][:, j], x, rtol=0, atol=1e-11 * sc), (k, j)
+            if j == 0:
+                assert np.allclose(r1["X"][:, 0], x, rtol=0, atol=1e-11 * sc), k
+
+
+@pytest.mark.parametrize("kind,q", SUBALGS)
+def test_pbcg_power_of_two_scalar_preconditioner_is_exact(orc, kind, q):
+    """M^-1 = c I with c a power of two scales P, rho and alpha by exact
+    powers of two that cancel in lambda sigma and beta: the iterates equal
+    the unpreconditioned ones bit for bit (a misplaced M^-1, e.g. in rho,
+    leaves a factor c in lambda)."""
+    A, D, B = small_problem(n_grid=6, s=4, seed=4)
+    for eta in (0.0, 1e4, np.inf):
+        r0 = orc.bcg(A, B, kind=kind, q=q, tol=1e-10, maxit=200, eta=eta)
+        r1 = orc.bcg(A, B, kind=kind, q=q, tol=1e-10, maxit=200, eta=eta, minv=np.full(A.n, 0.25))
+        assert r0["iters"] == r1["iters"] and r0["reorth"] == r1["reorth"]
+        assert np.array_equal(r0["X"], r1["X"])
+
+
+@pytest.mark.parametrize("kind,q", SUBALGS)
+def test_pbcg_orthogonality_invariants(orc, kind, q):
+    """<R^k, P^j>_S = 0 (j < k), <P^i, A P^j>_S = 0 (i != j) and the
+    preconditioned residuals are conjugate to the residuals:
+    <M^-1 R^i, R^j>_S = 0 (i != j)."""
+    A, D, B, minv = prec_problem(N=5, s=4)
+    r = orc.bcg(A, B, kind=kind, q=q, tol=0.0, maxit=5, eta=1e4, record_blocks=6, minv=minv)
+    Pk, Rk = r["Pk"], r["Rk"]
+    for k in range(len(Rk)):
+        for j in range(k):
+            G = orc.bdot(Rk[k], Pk[j], kind, q)
+            assert np.abs(G).max() < 1e-11 * np.linalg.norm(Rk[k]) * np.linalg.norm(Pk[j])
+            Z = orc.bdot(minv[:, None] * Rk[j], Rk[k], kind, q)
+            assert np.abs(Z).max() < 1e-11 * np.linalg.norm(minv[:, None] * Rk[j]) * np.linalg.norm(Rk[k])
+    for i in range(len(Pk)):
+        for j in range(len(Pk)):
+            if i != j:
+                G = orc.bdot(Pk[i], D @ Pk[j], kind, q)
+                assert np.abs(G).max() < 1e-11 * np.linalg.norm(Pk[i]) * np.linalg.norm(D @ Pk[j])
+
+
+def test_pbcg_exact_preconditioner_converges_in_one_step(orc):
+    """A diagonal, M = A: M^-1 A = I, so one block iteration is exact."""
+    n = 50
+    d = np.linspace(1.0, 100.0, n)
+    A = W.dense_to_csr(np.diag(d))
+    B = W.uniform_block(n, 4, 2)
+    for kind, q in SUBALGS:
+        r = orc.bcg(A, B, kind=kind, q=q, tol=1e-12, maxit=5, minv=1.0 / d)
+        assert r["converged"] and r["iters"] == 1
+        assert np.allclose(r["X"], B / d[:, None], rtol=1e-12, atol=0)
