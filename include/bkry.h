@@ -170,6 +170,22 @@ int bkry_tsqr(bkry_handle h, int64_t n, int32_t p, bkry_subalg S, double* X_inou
 int bkry_cg_solve(bkry_handle h, const bkry_csr* A, int32_t p, bkry_subalg S, const double* B, double* X,
                   double tol, int32_t maxit, double eta, int32_t prec, bkry_info* info);
 
+/* Preconditioned block CG (the same algorithm with a preconditioner M: the
+ * search directions start from and are updated with Z = M^-1 R-bar, and
+ * rho = <Z, R-bar>_S) for a diagonal SPD M given by minv [device, n
+ * doubles, 8-byte aligned, caller-owned]: minv[i] = (M^-1)_ii > 0.  FP64;
+ * otherwise as bkry_cg_solve (the stopping test uses the unpreconditioned
+ * residual R).  Non-finite or non-positive entries of minv are not checked
+ * and end in BKRY_E_BREAKDOWN or BKRY_E_NONFINITE. */
+int bkry_pcg_solve(bkry_handle h, const bkry_csr* A, int32_t p, bkry_subalg S, const double* B, double* X,
+                   const double* minv, double tol, int32_t maxit, double eta, bkry_info* info);
+
+/* Jacobi preconditioner of bkry_pcg_solve: minv[i] = 1 / A_ii [device, n
+ * doubles, caller-owned].  BKRY_E_INVALID if a row has no diagonal entry or
+ * its diagonal is not positive and finite (duplicates are summed).
+ * Synchronous. */
+int bkry_jacobi_minv(bkry_handle h, const bkry_csr* A, double* minv);
+
 /* Restarted block GMRes (Algorithm "Block GMRes Method", Ch. 5): block
  * Arnoldi with classical Gram-Schmidt applied twice (Algorithm "classical
  * Gram-Schmidt", Ch. 9) and TSQR normalisation of each new block, generalised

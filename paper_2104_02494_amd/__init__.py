@@ -57,8 +57,8 @@ class bkry_info(ctypes.Structure):
 
 EXPORTS = ["bkry_create", "bkry_destroy", "bkry_set_stream", "bkry_synchronize", "bkry_last_error",
            "bkry_profile", "bkry_profile_read", "bkry_set_spmm_format", "bkry_spmm",
-           "bkry_spmm_f32", "bkry_bdot", "bkry_bdot_f32", "bkry_tsqr", "bkry_cg_solve", "bkry_gmres_solve",
-           "bkry_sddmm", "bkry_csr_transpose"]
+           "bkry_spmm_f32", "bkry_bdot", "bkry_bdot_f32", "bkry_tsqr", "bkry_cg_solve", "bkry_pcg_solve",
+           "bkry_jacobi_minv", "bkry_gmres_solve", "bkry_sddmm", "bkry_csr_transpose"]
 
 _lib = None
 
@@ -88,6 +88,8 @@ def lib():
             "bkry_bdot_f32": [H, i64, i32, bkry_subalg, vp, vp, vp],
             "bkry_tsqr": [H, i64, i32, bkry_subalg, vp, vp],
             "bkry_cg_solve": [H, csr_p, i32, bkry_subalg, vp, vp, dbl, i32, dbl, i32, info_p],
+            "bkry_pcg_solve": [H, csr_p, i32, bkry_subalg, vp, vp, vp, dbl, i32, dbl, info_p],
+            "bkry_jacobi_minv": [H, csr_p, vp],
             "bkry_gmres_solve": [H, csr_p, i32, bkry_subalg, vp, vp, dbl, i32, i32, info_p],
             "bkry_sddmm": [H, csr_p, i32, dbl, vp, vp, vp],
             "bkry_csr_transpose": [H, csr_p, vp, vp, vp, vp],
@@ -235,8 +237,10 @@ def _info_dict(rc, info, hist, rel, trel, p):
 
 
 def bkry_cg_solve(h: Handle, A: CsrMatrix, B: torch.Tensor, X: torch.Tensor | None = None, kind="block", q=1,
-                  tol=1e-10, maxit=1000, eta=1e4, prec=F64, hist_cap=0, inner_tol=0.0, max_outer=0):
+                  tol=1e-10, maxit=1000, eta=1e4, prec=F64, hist_cap=0, inner_tol=0.0, max_outer=0, minv=None):
     """Block CG with adaptive residual re-orthonormalisation; X (in/out, zeros if None).
+    minv (FP64 device vector of n entries): diagonal of M^-1 of a diagonal
+    preconditioner M (bkry_pcg_solve); None: no preconditioner.
     Returns (X, info).  Raises on invalid input, breakdown or non-finite values."""
     _block(B)
     X = torch.zeros_like(B) if X is None else _block(X)
@@ -244,10 +248,33 @@ def bkry_cg_solve(h: Handle, A: CsrMatrix, B: torch.Tensor, X: torch.Tensor | No
     info, hist, rel, trel = _info(p, hist_cap, inner_tol, max_outer)
     h._sync_stream()
     d = A.desc()
-    rc = lib().bkry_cg_solve(h.h, ctypes.byref(d), p, _subalg(kind, q), _ptr(B), _ptr(X), float(tol), int(maxit),
-                             float(eta), int(prec), ctypes.byref(info))
+    if minv is not None:
+        if not (minv.is_cuda and minv.dtype == torch.float64 and minv.is_contiguous() and minv.numel() == A.n):
+            raise ValueError("minv must be a contiguous FP64 device vector of n entries")
+        if prec != F64:
+            raise ValueError("the preconditioned solve runs in FP64")
+        rc = lib().bkry_pcg_solve(h.h, ctypes.byref(d), p, _subalg(kind, q), _ptr(B), _ptr(X), _ptr(minv),
+                                  float(tol), int(maxit), float(eta), ctypes.byref(info))
+    else:
+        rc = lib().bkry_cg_solve(h.h, ctypes.byref(d), p, _subalg(kind, q), _ptr(B), _ptr(X), float(tol),
+                                 int(maxit), float(eta), int(prec), ctypes.byref(info))
     h._check(rc, allow=(OK, NOT_CONVERGED))
     return X, _info_dict(rc, info, hist, rel, trel, p)
+
+
+def bkry_pcg_solve(h: Handle, A: CsrMatrix, B: torch.Tensor, minv: torch.Tensor, X: torch.Tensor | None = None,
+                   kind="block", q=1, tol=1e-10, maxit=1000, eta=1e4, hist_cap=0):
+    """Block CG with the diagonal preconditioner M^-1 = diag(minv) (FP64).  Returns (X, info)."""
+    return bkry_cg_solve(h, A, B, X, kind=kind, q=q, tol=tol, maxit=maxit, eta=eta, hist_cap=hist_cap, minv=minv)
+
+
+def bkry_jacobi_minv(h: Handle, A: CsrMatrix) -> torch.Tensor:
+    """minv[i] = 1 / A_ii (the Jacobi preconditioner for bkry_cg_solve(minv=...))."""
+    out = torch.empty(A.n, dtype=torch.float64, device=A.rowptr.device)
+    h._sync_stream()
+    d = A.desc()
+    h._check(lib().bkry_jacobi_minv(h.h, ctypes.byref(d), _ptr(out)))
+    return out
 
 
 def bkry_gmres_solve(h: Handle, A: CsrMatrix, B: torch.Tensor, X: torch.Tensor | None = None, kind="block", q=1,

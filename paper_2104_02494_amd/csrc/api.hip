@@ -25,7 +25,8 @@ struct bkry_handle_s {
   size_t ws_cap = 0;
   int32_t* hflags = nullptr;  // pinned host, kHostFlagsInts
   int32_t* dflags = nullptr;  // device: [0] bad CSR index seen by an asynchronous kernel,
-                              // [1] longest CSR row, [2] bad index seen while building an ELL copy
+                              // [1] longest CSR row, [2] bad index seen while building an ELL copy,
+                              // [4] bad diagonal seen by bkry_jacobi_minv
   uint32_t* cnt = nullptr;    // device: zeroed grid-reduction counters (left zero by every kernel)
   Prof* prof = nullptr;       // kernel timing, when enabled
   int32_t spmm_format = BKRY_FMT_AUTO;
@@ -383,13 +384,15 @@ int bkry_tsqr(bkry_handle h, int64_t n, int32_t p, bkry_subalg S, double* X, dou
   return BKRY_OK;
 }
 
-int bkry_cg_solve(bkry_handle h, const bkry_csr* A, int32_t p, bkry_subalg S, const double* B, double* X,
-                  double tol, int32_t maxit, double eta, int32_t prec, bkry_info* info) {
+namespace {
+int cg_solve_impl(bkry_handle h, const bkry_csr* A, int32_t p, bkry_subalg S, const double* B, double* X,
+                  double tol, int32_t maxit, double eta, int32_t prec, const double* minv, bkry_info* info) {
   int rc = begin(h);
   Sub sub;
   if (!rc) rc = check_csr(h, A, true);
   if (!rc) rc = check_sub(h, p, S, sub);
   if (!rc) rc = check_blocks(h, {B, X});
+  if (!rc && minv && prec != BKRY_F64) rc = fail(h, BKRY_E_INVALID, "the preconditioned solve runs in FP64");
   if (!rc && !(tol >= 0.0)) rc = fail(h, BKRY_E_INVALID, "tol must be >= 0");
   if (!rc && maxit < 0) rc = fail(h, BKRY_E_INVALID, "maxit must be >= 0");
   if (!rc && !(eta >= 0.0)) rc = fail(h, BKRY_E_INVALID, "eta must be >= 0");
@@ -428,7 +431,7 @@ int bkry_cg_solve(bkry_handle h, const bkry_csr* A, int32_t p, bkry_subalg S, co
     if (rc) return rc;
     CgResult r;
     hipError_t e = cg_run<double>(v, sub, B, X, tol, maxit, eta, DBL_EPSILON, hist_cap, cb, h->stream, h->hflags, r,
-                                  h->prof);
+                                  h->prof, minv);
     if (e != hipSuccess) return hip_fail(h, e, "cg_solve");
     status = r.status;
     iters = r.iters;
@@ -499,6 +502,33 @@ int bkry_cg_solve(bkry_handle h, const bkry_csr* A, int32_t p, bkry_subalg S, co
   rc = status_of(status, h);
   if (rc) return rc;
   return conv ? BKRY_OK : BKRY_NOT_CONVERGED;
+}
+}  // namespace
+
+int bkry_cg_solve(bkry_handle h, const bkry_csr* A, int32_t p, bkry_subalg S, const double* B, double* X,
+                  double tol, int32_t maxit, double eta, int32_t prec, bkry_info* info) {
+  return cg_solve_impl(h, A, p, S, B, X, tol, maxit, eta, prec, nullptr, info);
+}
+
+int bkry_pcg_solve(bkry_handle h, const bkry_csr* A, int32_t p, bkry_subalg S, const double* B, double* X,
+                   const double* minv, double tol, int32_t maxit, double eta, bkry_info* info) {
+  if (!h) return BKRY_E_INVALID;
+  if (!minv) return fail(h, BKRY_E_INVALID, "null minv");
+  if ((reinterpret_cast<uintptr_t>(minv) & 7) != 0) return fail(h, BKRY_E_INVALID, "minv must be 8-byte aligned");
+  return cg_solve_impl(h, A, p, S, B, X, tol, maxit, eta, BKRY_F64, minv, info);
+}
+
+int bkry_jacobi_minv(bkry_handle h, const bkry_csr* A, double* minv) {
+  int rc = begin(h);
+  if (!rc) rc = check_csr(h, A, true);
+  if (!rc && !minv) rc = fail(h, BKRY_E_INVALID, "null minv");
+  if (rc) return rc;
+  API_HIP(hipMemsetAsync(h->dflags + 4, 0, sizeof(int32_t), h->stream), "jacobi");
+  API_HIP(launch_jacobi_minv(view(A), minv, h->dflags + 4, h->stream), "jacobi");
+  API_HIP(hipMemcpyAsync(h->hflags, h->dflags + 4, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream), "jacobi");
+  API_HIP(hipStreamSynchronize(h->stream), "jacobi");
+  if (h->hflags[0]) return fail(h, BKRY_E_INVALID, "a diagonal entry of A is missing, not positive or not finite");
+  return BKRY_OK;
 }
 
 int bkry_gmres_solve(bkry_handle h, const bkry_csr* A, int32_t p, bkry_subalg S, const double* B, double* X,

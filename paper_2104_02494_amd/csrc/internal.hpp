@@ -110,7 +110,10 @@ struct GmCtl {
 // (EPI_CG_ALPHA after the SpMM, EPI_CG_RHO after the residual update), so
 // that no separate launch is needed.  The CG epilogues gate themselves on
 // the control block (the reduction's gate / fire arguments are then unused).
-enum EpiKind { EPI_NONE = 0, EPI_CG_ALPHA = 1, EPI_CG_RHO = 2 };
+// EPI_CG_RHO_M: the residual update of the preconditioned CG, whose
+// partials hold two Grams per workgroup ([R~^T R~ | R~^T M^-1 R~], 2*s*s
+// entries); red.G then receives both.
+enum EpiKind { EPI_NONE = 0, EPI_CG_ALPHA = 1, EPI_CG_RHO = 2, EPI_CG_RHO_M = 3 };
 struct Epi {
   int kind = EPI_NONE;
   CgCtl* ctl = nullptr;
@@ -144,18 +147,28 @@ template <typename T>
 hipError_t launch_gram(int64_t n, int s, const T* X, int nx, const T* Y, T* partial, int nblk, Red red,
                        const int32_t* gate, hipStream_t st, const int32_t* fire = nullptr);
 
-// CG residual update R~ = R - Q lambda (in place in R) and the Gram of R~ into red.G.
+// CG residual update R~ = R - Q lambda (in place in R) and the Gram of R~ into
+// red.G.  With minv (the diagonal of M^-1, n entries; FP64 only), also the
+// Gram R~^T M^-1 R~ (partials of 2*s*s entries, epi kind EPI_CG_RHO_M).
 template <typename T>
 hipError_t launch_cg_update(int64_t n, int s, T* R, const T* Q, const CgCtl* ctl, T* partial, int nblk, Red red,
-                            hipStream_t st, Epi epi = Epi{}, hipEvent_t ev_after = nullptr);
+                            hipStream_t st, Epi epi = Epi{}, hipEvent_t ev_after = nullptr,
+                            const double* minv = nullptr);
 
 // CG direction update.  X receives the terms P_k (lambda sigma)_k every other
 // iteration, two at a time (P_{k-1} and P_k), and all owed terms once the
 // solve has ended; unless it has ended, Pn = R + P beta, where Pn holds
 // P_{k-1} on entry (read first, row by row) and P_{k+1} on exit.
+// With minv (diagonal of M^-1), Pn = M^-1 R + P beta.
 template <typename T>
 hipError_t launch_cg_pupdate(int64_t n, int s, T* X, const T* P, T* Pn, const T* R, const CgCtl* ctl,
-                             hipStream_t st);
+                             hipStream_t st, const double* minv = nullptr);
+
+// Z = M^-1 R for the diagonal M^-1 = diag(minv); runs only if *done == 0
+// and (fire null or *fire != 0).
+template <typename T>
+hipError_t launch_row_scale(int64_t n, int s, const double* minv, const T* R, T* Z, const int32_t* done,
+                            const int32_t* fire, hipStream_t st);
 
 // X = X C in place (C s x s FP64); with gram, also the Gram X^T X of the
 // result into red.G.  Runs only if gf is null or *gf != 0.
@@ -231,6 +244,10 @@ hipError_t launch_ell_width(const CsrView& A, int32_t* wmax, hipStream_t st);
 template <typename Tin, typename T>
 hipError_t launch_ell_fill(const CsrView& A, const Tin* val, int W, int32_t* ecol, T* eval, int32_t* bad,
                            hipStream_t st);
+
+// minv[i] = 1 / A_ii (FP64 values); a missing, non-positive or non-finite
+// diagonal sets *bad = 1.
+hipError_t launch_jacobi_minv(const CsrView& A, double* minv, int32_t* bad, hipStream_t st);
 
 // ---------------------------------------------------------------- TSQR ----
 // Workspace (bytes) needed by tsqr_run for n rows, width s, subalgebra sub.

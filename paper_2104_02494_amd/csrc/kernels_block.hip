@@ -165,7 +165,7 @@ __device__ __forceinline__ void row_times(T (&out)[VEC], const vec_t<T, VEC>& mi
 // s * s]).  Safe to call several times in a row (LDS is reused).
 template <typename T, int S, int VEC>
 __device__ __forceinline__ void gram_store(T (&acc)[VEC][S], int s, T* partial, T* sh /* [NW][S*S] */,
-                                           int64_t slice = 0) {
+                                           int64_t slice = 0, int64_t pstride = 0) {
   constexpr int LPR = S / VEC;
   constexpr int NW = kBlock / kWave;
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
@@ -181,7 +181,7 @@ __device__ __forceinline__ void gram_store(T (&acc)[VEC][S], int s, T* partial, 
       for (int b = 0; b < S; ++b) sh[wave * S * S + (c * VEC + a) * S + b] = acc[a][b];
   }
   __syncthreads();
-  T* pblk = partial + (slice * gridDim.x + blockIdx.x) * s * s;
+  T* pblk = partial + (slice * gridDim.x + blockIdx.x) * (pstride > 0 ? pstride : (int64_t)s * s);
   for (int t = threadIdx.x; t < s * s; t += kBlock) {
     int a = t / s, b = t % s;
     T sum = T(0);
@@ -613,11 +613,13 @@ __device__ __forceinline__ void load_coeff(T* dst, const T* src, int s) {
   }
 }
 
-// R~ = R - Q lambda (in place in R); Gram partials of R~^T R~.
-template <typename T, int S, int VEC>
+// R~ = R - Q lambda (in place in R); Gram partials of R~^T R~, and with
+// PC also of R~^T M^-1 R~ (M^-1 = diag(minv)), stored side by side.
+template <typename T, int S, int VEC, bool PC>
 __global__ __launch_bounds__(kBlock) void cg_update_kernel(int64_t n, int s, T* __restrict__ R,
                                                             const T* __restrict__ Q, const CgCtl* ctl,
-                                                            T* __restrict__ partial) {
+                                                            T* __restrict__ partial,
+                                                            const double* __restrict__ minv) {
   using L = Layout<T, S, VEC>;
   constexpr int NW = kBlock / kWave;
   constexpr int RPB = NW * L::RPW;
@@ -634,10 +636,17 @@ __global__ __launch_bounds__(kBlock) void cg_update_kernel(int64_t n, int s, T* 
   int64_t rstep;
   stream_rows(n, RPB, r0, r1, rstep);
   T gacc[VEC][S];
+  T gacc2[PC ? VEC : 1][PC ? S : 1];
 #pragma unroll
   for (int a = 0; a < VEC; ++a)
 #pragma unroll
     for (int b = 0; b < S; ++b) gacc[a][b] = T(0);
+  if constexpr (PC) {
+#pragma unroll
+    for (int a = 0; a < VEC; ++a)
+#pragma unroll
+      for (int b = 0; b < S; ++b) gacc2[a][b] = T(0);
+  }
   for (int64_t base = r0; base < r1; base += rstep) {
     const int64_t row = base + wave * L::RPW + r;
     const bool rv = row < r1 && active;
@@ -650,16 +659,34 @@ __global__ __launch_bounds__(kBlock) void cg_update_kernel(int64_t n, int s, T* 
     for (int w = 0; w < VEC; ++w) out.v[w] = rr.v[w] - ql[w];
     if (rv) store_out<T, VEC>(R + row * s + col0, out);
     gram_row<T, S, VEC>(gacc, out, out, lane);
+    if constexpr (PC) {
+      const T m = rv ? (T)minv[row] : T(0);
+      vec_t<T, VEC> z;
+#pragma unroll
+      for (int w = 0; w < VEC; ++w) z.v[w] = m * out.v[w];
+      gram_row<T, S, VEC>(gacc2, z, out, lane);
+    }
   }
-  gram_store<T, S, VEC>(gacc, s, partial, sh);
+  if constexpr (PC) {
+    gram_store<T, S, VEC>(gacc, s, partial, sh, 0, 2 * (int64_t)s * s);
+    gram_store<T, S, VEC>(gacc2, s, partial + (int64_t)s * s, sh, 0, 2 * (int64_t)s * s);
+  } else {
+    gram_store<T, S, VEC>(gacc, s, partial, sh);
+  }
 }
 
 template <typename T>
 hipError_t launch_cg_update(int64_t n, int s, T* R, const T* Q, const CgCtl* ctl, T* partial, int nblk, Red red,
-                            hipStream_t st, Epi epi, hipEvent_t ev_after) {
+                            hipStream_t st, Epi epi, hipEvent_t ev_after, const double* minv) {
+  if (minv && (sizeof(T) != 8 || epi.kind != EPI_CG_RHO_M)) return hipErrorInvalidValue;
   hipError_t e = dispatch_s<T>(s, [&](auto S_, auto V_) -> hipError_t {
     constexpr int S = decltype(S_)::value, V = decltype(V_)::value;
-    hipLaunchKernelGGL((cg_update_kernel<T, S, V>), dim3(nblk), dim3(kBlock), 0, st, n, s, R, Q, ctl, partial);
+    if (minv)
+      hipLaunchKernelGGL((cg_update_kernel<T, S, V, true>), dim3(nblk), dim3(kBlock), 0, st, n, s, R, Q, ctl,
+                         partial, minv);
+    else
+      hipLaunchKernelGGL((cg_update_kernel<T, S, V, false>), dim3(nblk), dim3(kBlock), 0, st, n, s, R, Q, ctl,
+                         partial, minv);
     return hipGetLastError();
   });
   if (e == hipSuccess && ev_after) e = hipEventRecord(ev_after, st);
@@ -685,10 +712,11 @@ __device__ __forceinline__ const float* ctl_prev<float>(const CgCtl* ctl) {
   return ctl->lamsig_prev_f;
 }
 
-template <typename T, int S, int VEC>
+template <typename T, int S, int VEC, bool PC>
 __global__ __launch_bounds__(kBlock) void cg_pupdate_kernel(int64_t n, int s, T* __restrict__ X,
                                                              const T* __restrict__ P, T* __restrict__ Pn,
-                                                             const T* __restrict__ R, const CgCtl* ctl) {
+                                                             const T* __restrict__ R, const CgCtl* ctl,
+                                                             const double* __restrict__ minv) {
   using L = Layout<T, S, VEC>;
   constexpr int NW = kBlock / kWave;
   constexpr int RPB = NW * L::RPW;
@@ -735,6 +763,11 @@ __global__ __launch_bounds__(kBlock) void cg_pupdate_kernel(int64_t n, int s, T*
     }
     if (pdir) {
       vec_t<T, VEC> rr = rv ? load_vec<T, VEC>(R + row * s + col0) : zero_vec<T, VEC>();
+      if constexpr (PC) {
+        const T m = rv ? (T)minv[row] : T(0);
+#pragma unroll
+        for (int w = 0; w < VEC; ++w) rr.v[w] = m * rr.v[w];
+      }
       T pb[VEC];
       row_times<T, S, VEC>(pb, p, bt, col0, lane);
 #pragma unroll
@@ -746,13 +779,43 @@ __global__ __launch_bounds__(kBlock) void cg_pupdate_kernel(int64_t n, int s, T*
 
 template <typename T>
 hipError_t launch_cg_pupdate(int64_t n, int s, T* X, const T* P, T* Pn, const T* R, const CgCtl* ctl,
-                             hipStream_t st) {
+                             hipStream_t st, const double* minv) {
+  if (minv && sizeof(T) != 8) return hipErrorInvalidValue;
   int nblk = stream_grid_wide(n, s, sizeof(T));
   return dispatch_s<T>(s, [&](auto S_, auto V_) -> hipError_t {
     constexpr int S = decltype(S_)::value, V = decltype(V_)::value;
-    hipLaunchKernelGGL((cg_pupdate_kernel<T, S, V>), dim3(nblk), dim3(kBlock), 0, st, n, s, X, P, Pn, R, ctl);
+    if (minv)
+      hipLaunchKernelGGL((cg_pupdate_kernel<T, S, V, true>), dim3(nblk), dim3(kBlock), 0, st, n, s, X, P, Pn, R,
+                         ctl, minv);
+    else
+      hipLaunchKernelGGL((cg_pupdate_kernel<T, S, V, false>), dim3(nblk), dim3(kBlock), 0, st, n, s, X, P, Pn, R,
+                         ctl, minv);
     return hipGetLastError();
   });
+}
+
+// Z = M^-1 R, M^-1 = diag(minv): one thread per element (the row of an
+// element is its index divided by s).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void row_scale_kernel(int64_t n, int s, const double* __restrict__ minv,
+                                                            const T* __restrict__ R, T* __restrict__ Z,
+                                                            const int32_t* done, const int32_t* fire) {
+  if ((done && *done) || (fire && !*fire)) return;
+  const int64_t total = n * s;
+  for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < total; t += (int64_t)gridDim.x * kBlock)
+    Z[t] = (T)minv[t / s] * R[t];
+}
+
+template <typename T>
+hipError_t launch_row_scale(int64_t n, int s, const double* minv, const T* R, T* Z, const int32_t* done,
+                            const int32_t* fire, hipStream_t st) {
+  const int64_t total = n * s;
+  if (total <= 0) return hipSuccess;
+  int64_t blocks = (total + kBlock - 1) / kBlock;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL((row_scale_kernel<T>), dim3((unsigned)blocks), dim3(kBlock), 0, st, n, s, minv, R, Z, done,
+                     fire);
+  return hipGetLastError();
 }
 
 // ------------------------------------------------------ row products --
@@ -1013,8 +1076,11 @@ hipError_t launch_cast_f32(int64_t count, const double* in, float* out, hipStrea
   template hipError_t launch_gram<T>(int64_t, int, const T*, int, const T*, T*, int, Red, const int32_t*,          \
                                      hipStream_t, const int32_t*);                                                 \
   template hipError_t launch_cg_update<T>(int64_t, int, T*, const T*, const CgCtl*, T*, int, Red, hipStream_t,    \
-                                          Epi, hipEvent_t);                                                        \
-  template hipError_t launch_cg_pupdate<T>(int64_t, int, T*, const T*, T*, const T*, const CgCtl*, hipStream_t);  \
+                                          Epi, hipEvent_t, const double*);                                         \
+  template hipError_t launch_cg_pupdate<T>(int64_t, int, T*, const T*, T*, const T*, const CgCtl*, hipStream_t,   \
+                                           const double*);                                                         \
+  template hipError_t launch_row_scale<T>(int64_t, int, const double*, const T*, T*, const int32_t*,              \
+                                          const int32_t*, hipStream_t);                                            \
   template hipError_t launch_rowmul<T>(int64_t, int, T*, const double*, bool, T*, int, Red, const int32_t*,        \
                                        hipStream_t);                                                               \
   template hipError_t launch_block_combine<T>(int64_t, int, const T*, int, const double*, double, T*,               \

@@ -53,6 +53,39 @@ __global__ __launch_bounds__(kBlock) void ell_fill_kernel(int64_t n, int64_t nnz
   }
 }
 
+// minv[i] = 1 / A_ii (Jacobi preconditioner).  A row without a diagonal
+// entry, or with a diagonal that is not positive and finite, sets *bad = 1
+// (its minv is set to 0).  Duplicate diagonal entries are summed.
+__global__ __launch_bounds__(kBlock) void jacobi_minv_kernel(int64_t n, int64_t nnz, const int32_t* __restrict__ rowptr,
+                                                              const int32_t* __restrict__ colind,
+                                                              const double* __restrict__ val, double* minv,
+                                                              int32_t* bad) {
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+    int64_t k0 = rowptr[i], k1 = rowptr[i + 1];
+    k0 = k0 < 0 ? 0 : (k0 > nnz ? nnz : k0);
+    k1 = k1 < 0 ? 0 : (k1 > nnz ? nnz : k1);
+    double d = 0.0;
+    bool seen = false;
+    for (int64_t k = k0; k < k1; ++k)
+      if (colind[k] == i) {
+        d += val[k];
+        seen = true;
+      }
+    const bool ok = seen && d > 0.0 && isfinite(d);
+    minv[i] = ok ? 1.0 / d : 0.0;
+    if (!ok) *bad = 1;
+  }
+}
+
+hipError_t launch_jacobi_minv(const CsrView& A, double* minv, int32_t* bad, hipStream_t st) {
+  if (A.n <= 0) return hipSuccess;
+  int64_t blocks = (A.n + kBlock - 1) / kBlock;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(jacobi_minv_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, st, A.n, A.nnz, A.rowptr, A.colind,
+                     static_cast<const double*>(A.val), minv, bad);
+  return hipGetLastError();
+}
+
 int ell_chunk(int s, int elem_bytes) {
   const int lpr = spmm_lanes_per_row(s, elem_bytes);
   return lpr * ell_entries_per_lane(lpr);

@@ -591,13 +591,13 @@ __device__ __forceinline__ void cg_alpha_body(CgCtl* c, const double* G, const d
 }
 
 // G = R~^T R~ (full).  Column norms of the true residual R~ sigma, stopping
-// test, and (no normalisation this iteration) rho' = <R~, R~>_S and
-// beta = rho^-1 rho'.  Runs only while the iteration is live (the caller
+// test, and (no normalisation this iteration) rho' = <Z, R~>_S and
+// beta = rho^-1 rho', Z = M^-1 R~ (Gz = R~^T M^-1 R~, or null for M = I).  Runs only while the iteration is live (the caller
 // checks the gate).
 // rho_l, sigma_l, r0n_l: copies of c->rho, c->sigma and c->r0n (LDS).
 template <int SM>
 __device__ __forceinline__ void cg_rho_body(CgCtl* c, const double* G, double* hist, const double* rho_l,
-                                            const double* sigma_l, const double* r0n_l) {
+                                            const double* sigma_l, const double* r0n_l, const double* Gz) {
   __shared__ double Gm[kSS], T1[kSS], Bt[kSS];
   __shared__ double red[4];
   __shared__ int flag[1];
@@ -644,7 +644,12 @@ __device__ __forceinline__ void cg_rho_body(CgCtl* c, const double* G, double* h
   }
   __syncthreads();
   if (flag[0] || c->fire) return;
-  // rho' = <R~, R~>_S, beta = rho^-1 rho' (gamma = I)
+  // rho' = <Z, R~>_S, beta = rho^-1 rho' (gamma = I); Z = R~ unless a
+  // preconditioner's Gram Gz = R~^T M^-1 R~ is given
+  if (Gz) {
+    __syncthreads();
+    sm_copy(Gm, Gz, s * s);
+  }
   sm_project(Gm, sub, red);
   if (!rf_cholesky_solve<SM>(rho_l, Gm, Bt, nullptr, s)) {
     if (tid() == 0) {
@@ -689,10 +694,12 @@ template <typename T, int EPI, int SM>
 __global__ __launch_bounds__(kSB) void reduce_kernel(int s, const T* __restrict__ partial, int nblk, Red red,
                                                       const int32_t* gate, const int32_t* fire, CgCtl* c,
                                                       double* hist) {
+  constexpr bool RHO = EPI == EPI_CG_RHO || EPI == EPI_CG_RHO_M;
+  constexpr int NG = EPI == EPI_CG_RHO_M ? 2 : 1;  // Grams per partial
   __shared__ int last;
   __shared__ double pre_rho[EPI != EPI_NONE ? kSS : 1], pre_sig[EPI != EPI_NONE ? kSS : 1];
-  __shared__ double pre_r0n[EPI == EPI_CG_RHO ? kMaxS : 1];
-  const int ss = s * s;
+  __shared__ double pre_r0n[RHO ? kMaxS : 1];
+  const int ss = s * s, m = NG * ss;
   if constexpr (EPI != EPI_NONE) {
     // the epilogue's inputs from the control block, loaded along with the
     // partials (only the last workgroup uses them)
@@ -700,7 +707,7 @@ __global__ __launch_bounds__(kSB) void reduce_kernel(int s, const T* __restrict_
       pre_rho[t] = c->rho[t];
       pre_sig[t] = c->sigma[t];
     }
-    if constexpr (EPI == EPI_CG_RHO)
+    if constexpr (RHO)
       for (int t = tid(); t < s; t += kSB) pre_r0n[t] = c->r0n[t];
   }
   if constexpr (EPI == EPI_CG_ALPHA) {
@@ -712,16 +719,16 @@ __global__ __launch_bounds__(kSB) void reduce_kernel(int s, const T* __restrict_
       return;
     }
     if (c->gate) return;  // suspended: the iteration waits for its re-normalisation
-  } else if constexpr (EPI == EPI_CG_RHO) {
+  } else if constexpr (RHO) {
     if (c->gate) return;
   } else {
     if ((gate && *gate) || (fire && !*fire)) return;
   }
   const int ns = gridDim.x, sl = blockIdx.x, y = blockIdx.y;
-  const T* P = partial + (int64_t)y * nblk * ss;
+  const T* P = partial + (int64_t)y * nblk * m;
   const int b0 = (int)((int64_t)nblk * sl / ns), b1 = (int)((int64_t)nblk * (sl + 1) / ns);
-  double* slices = red.gpart + (int64_t)y * ns * ss;
-  for (int e = tid(); e < ss; e += kSB) slices[(int64_t)sl * ss + e] = sum_strided<T>(P + (int64_t)b0 * ss + e, ss, b1 - b0);
+  double* slices = red.gpart + (int64_t)y * ns * m;
+  for (int e = tid(); e < m; e += kSB) slices[(int64_t)sl * m + e] = sum_strided<T>(P + (int64_t)b0 * m + e, m, b1 - b0);
   uint32_t* cnt = red.cnt + (int64_t)y * kCntStride;
   __threadfence();
   __syncthreads();
@@ -729,10 +736,10 @@ __global__ __launch_bounds__(kSB) void reduce_kernel(int s, const T* __restrict_
   __syncthreads();
   if (!last) return;
   __threadfence();
-  double* G = red.G + (int64_t)y * ss;
-  __shared__ double Gl[EPI != EPI_NONE ? kSS : 1];
-  for (int e = tid(); e < ss; e += kSB) {
-    const double v = sum_strided<double>(slices + e, ss, ns);
+  double* G = red.G + (int64_t)y * m;
+  __shared__ double Gl[EPI != EPI_NONE ? NG * kSS : 1];
+  for (int e = tid(); e < m; e += kSB) {
+    const double v = sum_strided<double>(slices + e, m, ns);
     G[e] = v;
     if constexpr (EPI != EPI_NONE) Gl[e] = v;
   }
@@ -740,9 +747,9 @@ __global__ __launch_bounds__(kSB) void reduce_kernel(int s, const T* __restrict_
   if constexpr (EPI == EPI_CG_ALPHA) {
     __syncthreads();
     cg_alpha_body<SM>(c, Gl, pre_rho, pre_sig);
-  } else if constexpr (EPI == EPI_CG_RHO) {
+  } else if constexpr (RHO) {
     __syncthreads();
-    cg_rho_body<SM>(c, Gl, hist, pre_rho, pre_sig, pre_r0n);
+    cg_rho_body<SM>(c, Gl, hist, pre_rho, pre_sig, pre_r0n, NG == 2 ? Gl + ss : nullptr);
   }
 }
 
@@ -764,15 +771,22 @@ static hipError_t launch_reduce_t(int s, const T* partial, int nblk, int batch, 
                        epi.ctl, epi.hist);
     return hipGetLastError();
   }
-  if (batch != 1 || !epi.ctl || (epi.kind != EPI_CG_ALPHA && epi.kind != EPI_CG_RHO)) return hipErrorInvalidValue;
+  if (batch != 1 || !epi.ctl ||
+      (epi.kind != EPI_CG_ALPHA && epi.kind != EPI_CG_RHO && epi.kind != EPI_CG_RHO_M))
+    return hipErrorInvalidValue;
   return dispatch_sm(s, [&](auto SM_) -> hipError_t {
     constexpr int SM = decltype(SM_)::value;
     if (epi.kind == EPI_CG_ALPHA)
       hipLaunchKernelGGL((reduce_kernel<T, EPI_CG_ALPHA, SM>), grid, dim3(kSB), 0, st, s, partial, nblk, red, gate,
                          fire, epi.ctl, epi.hist);
-    else
+    else if (epi.kind == EPI_CG_RHO)
       hipLaunchKernelGGL((reduce_kernel<T, EPI_CG_RHO, SM>), grid, dim3(kSB), 0, st, s, partial, nblk, red, gate,
                          fire, epi.ctl, epi.hist);
+    else if constexpr (sizeof(T) == 8)
+      hipLaunchKernelGGL((reduce_kernel<T, EPI_CG_RHO_M, SM>), grid, dim3(kSB), 0, st, s, partial, nblk, red, gate,
+                         fire, epi.ctl, epi.hist);
+    else
+      return hipErrorInvalidValue;
     return hipGetLastError();
   });
 }

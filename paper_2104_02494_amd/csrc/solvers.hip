@@ -86,10 +86,11 @@ CgBufs<T> carve_cg(Carver& c, int64_t n, Sub sub, int hist_cap, uint32_t* cnt) {
   b.P2 = c.take<T>((size_t)n * s);
   b.Q = c.take<T>((size_t)n * s);
   b.R = c.take<T>((size_t)n * s);
-  b.partial = c.take<T>((size_t)nblk * s * s);
-  b.gpart = c.take<double>(red_gpart_count(nblk, s));
+  // room for two Grams per workgroup (the preconditioned residual update)
+  b.partial = c.take<T>((size_t)2 * nblk * s * s);
+  b.gpart = c.take<double>(2 * red_gpart_count(nblk, s));
   b.Ga = c.take<double>((size_t)s * s);
-  b.Gr = c.take<double>((size_t)s * s);
+  b.Gr = c.take<double>((size_t)2 * s * s);
   b.Gq = c.take<double>((size_t)s * s);
   b.hist = c.take<double>((size_t)(hist_cap > 0 ? hist_cap : 1));
   b.ctl = c.take<CgCtl>(1);
@@ -101,18 +102,28 @@ CgBufs<T> carve_cg(Carver& c, int64_t n, Sub sub, int hist_cap, uint32_t* cnt) {
 // Re-normalisation of the residual (R-bar, gamma) = Norm_S(R~), then
 // sigma = gamma sigma, rho' and beta (cg_reortho_fin); runs only while the
 // solve is live and the re-orthonormalisation test fired.
+// With a preconditioner, rho' = <M^-1 R-bar, R-bar>_S (Z = M^-1 R-bar goes
+// through Q, which is free at this point of the iteration).
 template <typename T>
-static hipError_t cg_normalise(int64_t n, Sub sub, const CgBufs<T>& b, int nblk, hipStream_t st, Prof* prof) {
+static hipError_t cg_normalise(int64_t n, Sub sub, const CgBufs<T>& b, int nblk, hipStream_t st, Prof* prof,
+                               const double* minv) {
   CgCtl* c = b.ctl;
   ProfScope ps(prof, PROF_CG_NORMALISE, st);
   BK_TRY(tsqr_run<T>(n, sub, b.R, c->gamma, b.tsqr_ws, b.cnt, &c->done, &c->fire, st));
-  BK_TRY(launch_gram<T>(n, sub.s, b.R, 1, b.R, b.partial, nblk, Red{b.Gq, b.gpart, b.cnt}, &c->done, st, &c->fire));
+  const T* Z = b.R;
+  if (minv) {
+    BK_TRY(launch_row_scale<T>(n, sub.s, minv, b.R, b.Q, &c->done, &c->fire, st));
+    Z = b.Q;
+  }
+  BK_TRY(launch_gram<T>(n, sub.s, Z, 1, b.R, b.partial, nblk, Red{b.Gq, b.gpart, b.cnt}, &c->done, st, &c->fire));
   return launch_cg_reortho_fin(c, sub.s, b.Gq, st);
 }
 
 template <typename T>
 hipError_t cg_run(const CsrView& A, Sub sub, const T* B, T* X, double tol, int maxit, double eta, double eps,
-                  int hist_cap, const CgBufs<T>& b, hipStream_t st, int32_t* hflags, CgResult& res, Prof* prof) {
+                  int hist_cap, const CgBufs<T>& b, hipStream_t st, int32_t* hflags, CgResult& res, Prof* prof,
+                  const double* minv) {
+  if (minv && sizeof(T) != 8) return hipErrorInvalidValue;
   const int64_t n = A.n;
   const int s = sub.s;
   const int nblk = stream_grid(n, s, sizeof(T));
@@ -147,9 +158,16 @@ hipError_t cg_run(const CsrView& A, Sub sub, const T* B, T* X, double tol, int m
   BK_TRY(launch_spmm<T>(A, s, X, b.R, B, 2, b.partial, nblk, ra, &c->bad_index, nullptr, st));
   BK_TRY(launch_cg_init(c, b.Ga, nullptr, st));
   if (eta > 0.0) BK_TRY(tsqr_run<T>(n, sub, b.R, c->sigma, b.tsqr_ws, b.cnt, done, nullptr, st));
-  BK_TRY(launch_gram<T>(n, s, b.R, 1, b.R, b.partial, nblk, rr, done, st));
-  BK_TRY(launch_cg_init(c, nullptr, b.Gr, st));
-  BK_TRY(hipMemcpyAsync(b.P, b.R, sizeof(T) * (size_t)n * s, hipMemcpyDeviceToDevice, st));
+  if (minv) {
+    // P = M^-1 R-bar, rho = <P, R-bar>_S
+    BK_TRY(launch_row_scale<T>(n, s, minv, b.R, b.P, nullptr, nullptr, st));
+    BK_TRY(launch_gram<T>(n, s, b.P, 1, b.R, b.partial, nblk, rr, done, st));
+    BK_TRY(launch_cg_init(c, nullptr, b.Gr, st));
+  } else {
+    BK_TRY(launch_gram<T>(n, s, b.R, 1, b.R, b.partial, nblk, rr, done, st));
+    BK_TRY(launch_cg_init(c, nullptr, b.Gr, st));
+    BK_TRY(hipMemcpyAsync(b.P, b.R, sizeof(T) * (size_t)n * s, hipMemcpyDeviceToDevice, st));
+  }
 
   const CgCtl* hc = reinterpret_cast<const CgCtl*>(hflags);
   // P_k lives in pbuf[k % 2]; the direction update writes P_{k+1} over
@@ -171,13 +189,13 @@ hipError_t cg_run(const CsrView& A, Sub sub, const T* B, T* X, double tol, int m
       {
         // R~ = R - Q lambda and its Gram; then the stopping test, rho' and beta
         ProfScope ps(prof, PROF_CG_UPDATE, st);
-        BK_TRY(launch_cg_update<T>(n, s, b.R, b.Q, c, b.partial, nblk, rr, st, Epi{EPI_CG_RHO, c, b.hist},
-                                   ps.end()));
+        BK_TRY(launch_cg_update<T>(n, s, b.R, b.Q, c, b.partial, nblk, rr, st,
+                                   Epi{minv ? EPI_CG_RHO_M : EPI_CG_RHO, c, b.hist}, ps.end(), minv));
       }
-      if (always) BK_TRY(cg_normalise<T>(n, sub, b, nblk, st, prof));
+      if (always) BK_TRY(cg_normalise<T>(n, sub, b, nblk, st, prof, minv));
       {
         ProfScope ps(prof, PROF_CG_PUPDATE, st);
-        BK_TRY(launch_cg_pupdate<T>(n, s, X, Pk, Pn, b.R, c, st));
+        BK_TRY(launch_cg_pupdate<T>(n, s, X, Pk, Pn, b.R, c, st, minv));
       }
     }
     BK_TRY(hipMemcpyAsync(hflags, c, kCtlHeaderInts * sizeof(int32_t), hipMemcpyDeviceToHost, st));
@@ -189,10 +207,10 @@ hipError_t cg_run(const CsrView& A, Sub sub, const T* B, T* X, double tol, int m
       // of the batch were gated off): run it, finish the iteration's
       // direction update, continue with short batches
       const int ks = hc->iters - 1;
-      BK_TRY(cg_normalise<T>(n, sub, b, nblk, st, prof));
+      BK_TRY(cg_normalise<T>(n, sub, b, nblk, st, prof, minv));
       {
         ProfScope ps(prof, PROF_CG_PUPDATE, st);
-        BK_TRY(launch_cg_pupdate<T>(n, s, X, pbuf[ks & 1], pbuf[(ks + 1) & 1], b.R, c, st));
+        BK_TRY(launch_cg_pupdate<T>(n, s, X, pbuf[ks & 1], pbuf[(ks + 1) & 1], b.R, c, st, minv));
       }
       k = ks + 1;
       batch = 2;
@@ -216,9 +234,9 @@ hipError_t cg_run(const CsrView& A, Sub sub, const T* B, T* X, double tol, int m
 template CgBufs<double> carve_cg<double>(Carver&, int64_t, Sub, int, uint32_t*);
 template CgBufs<float> carve_cg<float>(Carver&, int64_t, Sub, int, uint32_t*);
 template hipError_t cg_run<double>(const CsrView&, Sub, const double*, double*, double, int, double, double, int,
-                                   const CgBufs<double>&, hipStream_t, int32_t*, CgResult&, Prof*);
+                                   const CgBufs<double>&, hipStream_t, int32_t*, CgResult&, Prof*, const double*);
 template hipError_t cg_run<float>(const CsrView&, Sub, const float*, float*, double, int, double, double, int,
-                                  const CgBufs<float>&, hipStream_t, int32_t*, CgResult&, Prof*);
+                                  const CgBufs<float>&, hipStream_t, int32_t*, CgResult&, Prof*, const double*);
 
 // ------------------------------------------------------ true residuals --
 hipError_t true_relres(const CsrView& A, int s, const double* B, const double* X, double* R, double* partial,

@@ -63,11 +63,13 @@ struct CgResult {
 };
 
 // Block CG in element type T (FP64 or FP32 streaming kernels; p x p algebra in
-// FP64).  X holds X0 on entry.  eps is the machine epsilon of T.
+// FP64).  X holds X0 on entry.  eps is the machine epsilon of T.  minv (FP64
+// only; device, n entries): the diagonal of M^-1 of a diagonal preconditioner
+// M (null: M = I).
 template <typename T>
 hipError_t cg_run(const CsrView& A, Sub sub, const T* B, T* X, double tol, int maxit, double eta, double eps,
                   int hist_cap, const CgBufs<T>& b, hipStream_t st, int32_t* hflags, CgResult& res,
-                  Prof* prof = nullptr);
+                  Prof* prof = nullptr, const double* minv = nullptr);
 
 struct IrBufs {
   float *A32 = nullptr, *R32 = nullptr, *X32 = nullptr;

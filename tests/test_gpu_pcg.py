@@ -1,0 +1,152 @@
+"""GPU parity of the preconditioned block CG (bkry_pcg_solve, the Jacobi
+preconditioner M = diag(A) or any positive diagonal) against the oracle.
+
+Fixed iteration counts (tol = 0) run the same arithmetic on both sides and
+must agree to 1e-10 relative in FP64; full solves are compared on iteration
+and re-orthonormalisation counts, residual history and the FP64 true
+residual.  A power-of-two scalar preconditioner must reproduce the
+unpreconditioned GPU iterates bit for bit (every scaling it introduces is
+exact and cancels)."""
+import numpy as np
+import pytest
+
+import workloads as W
+from gpu_util import dev_csr, h, rel, say, to_dev, to_np  # noqa: F401
+
+pytestmark = pytest.mark.gpu
+P = pytest.importorskip("paper_2104_02494_amd")
+
+SUBS = [("block", 1), ("hybrid", 2), ("parallel", 1), ("global", 1)]
+
+
+def _diag(A):
+    rows = np.repeat(np.arange(A.n), np.diff(A.rowptr))
+    m = A.colind == rows
+    d = np.zeros(A.n)
+    np.add.at(d, rows[m], A.val[m])
+    return d
+
+
+def jacobi(A):
+    return 1.0 / _diag(A)
+
+
+def gpu_pcg(h, A, B, minv, X0=None, **kw):
+    X, info = P.bkry_pcg_solve(h, dev_csr(P, A), to_dev(B), to_dev(minv), None if X0 is None else to_dev(X0), **kw)
+    return to_np(X), info
+
+
+def test_jacobi_minv(h):
+    A = W.diffusion_7pt_var(10, seed=3)
+    say("jacobi minv")
+    m = to_np(P.bkry_jacobi_minv(h, dev_csr(P, A)))
+    assert np.array_equal(m, 1.0 / _diag(A))
+    say("jacobi minv: missing / negative diagonal")
+    L = W.laplace_2d(6)
+    keep = L.colind != np.repeat(np.arange(L.n), np.diff(L.rowptr))
+    keep[: L.rowptr[3]] = True                    # row 3 onwards loses its diagonal
+    rp = np.concatenate([[0], np.cumsum([keep[L.rowptr[i]:L.rowptr[i + 1]].sum() for i in range(L.n)])])
+    Lm = W.Csr(L.n, rp.astype(np.int32), L.colind[keep], L.val[keep])
+    with pytest.raises(P.BkryError) as e:
+        P.bkry_jacobi_minv(h, dev_csr(P, Lm))
+    assert e.value.code == P.E_INVALID
+    with pytest.raises(P.BkryError):
+        P.bkry_jacobi_minv(h, dev_csr(P, W.Csr(L.n, L.rowptr, L.colind, -L.val)))
+
+
+@pytest.mark.parametrize("s", [1, 2, 3, 4, 8, 16, 32])
+@pytest.mark.parametrize("kind,q", SUBS)
+@pytest.mark.parametrize("eta", [0.0, np.inf])
+def test_pcg_fixed_iterations(orc, h, s, kind, q, eta):
+    if kind == "hybrid" and s % 2:
+        pytest.skip("q must divide s")
+    A = W.diffusion_7pt_var(12, seed=8)       # n = 1728: several tiles and a ragged tail
+    minv = jacobi(A)
+    B = W.uniform_block(A.n, s, 30 + s)
+    X0 = 0.01 * W.gaussian_block(A.n, s, 40 + s)
+    for k in (1, 6):
+        say("pcg fixed", s, kind, eta, k)
+        X, info = gpu_pcg(h, A, B, minv, X0, kind=kind, q=q, tol=0.0, maxit=k, eta=eta)
+        ro = orc.bcg(A, B, X0, kind=kind, q=q, tol=0.0, maxit=k, eta=eta, minv=minv)
+        assert info["iters"] == ro["iters"] == k
+        assert rel(X, ro["X"]) < 1e-10
+
+
+@pytest.mark.parametrize("kind,q", SUBS)
+@pytest.mark.parametrize("eta", [0.0, 1e4, np.inf])
+def test_pcg_full_solve(orc, h, kind, q, eta):
+    A = W.diffusion_7pt_var(10, seed=9)
+    minv = jacobi(A)
+    B = W.uniform_block(A.n, 4, 7)
+    say("pcg full", kind, eta)
+    X, info = gpu_pcg(h, A, B, minv, kind=kind, q=q, tol=1e-10, maxit=2000, eta=eta, hist_cap=2000)
+    ro = orc.bcg(A, B, kind=kind, q=q, tol=1e-10, maxit=2000, eta=eta, hist_cap=2000, minv=minv)
+    assert info["converged"] and ro["converged"]
+    assert abs(info["iters"] - ro["iters"]) <= 1
+    k = min(len(info["hist"]), len(ro["hist"]))
+    assert np.allclose(info["hist"][:k], ro["hist"][:k], rtol=1e-6, atol=1e-15)
+    assert max(info["true_relres"]) <= 1.5e-10
+    Xs = np.linalg.solve(A.to_dense(), B)
+    assert rel(X, Xs) < 1e-7
+    # the preconditioner changes the iteration (it is not ignored)
+    r0 = orc.bcg(A, B, kind=kind, q=q, tol=1e-10, maxit=2000, eta=eta)
+    assert r0["iters"] != ro["iters"]
+
+
+@pytest.mark.parametrize("kind,q", SUBS)
+@pytest.mark.parametrize("eta", [0.0, np.inf])
+def test_pcg_power_of_two_scalar_is_bitwise_unpreconditioned(h, kind, q, eta):
+    A, B, _ = W.build_workload("poisson2d_32x32_s4")
+    say("pcg scalar 0.25", kind, eta)
+    X1, i1 = gpu_pcg(h, A, B, np.full(A.n, 0.25), kind=kind, q=q, tol=1e-10, maxit=2000, eta=eta)
+    X0, i0 = P.bkry_cg_solve(h, dev_csr(P, A), to_dev(B), kind=kind, q=q, tol=1e-10, maxit=2000, eta=eta)
+    assert i1["iters"] == i0["iters"] and i1["reorth"] == i0["reorth"]
+    assert np.array_equal(X1, to_np(X0))
+
+
+def test_pcg_edge_cases(h):
+    A = W.diffusion_7pt_var(6, seed=2)
+    B = W.uniform_block(A.n, 4, 1)
+    Ad = dev_csr(P, A)
+    say("pcg edges")
+    with pytest.raises(ValueError):
+        P.bkry_pcg_solve(h, Ad, to_dev(B), to_dev(np.ones(A.n - 1)))
+    with pytest.raises(ValueError):
+        P.bkry_cg_solve(h, Ad, to_dev(B), minv=to_dev(np.ones(A.n)), prec=P.F32_IR)
+    X, info = P.bkry_pcg_solve(h, Ad, to_dev(np.zeros_like(B)), to_dev(jacobi(A)), tol=1e-10)
+    assert info["converged"] and info["iters"] == 0 and np.all(to_np(X) == 0)
+    with pytest.raises(P.BkryError) as e:                     # an indefinite M: breakdown
+        m = jacobi(A)
+        m[::2] *= -1.0
+        P.bkry_pcg_solve(h, Ad, to_dev(B), to_dev(m), tol=1e-10, eta=0.0)
+    assert e.value.code in (P.E_BREAKDOWN, P.E_NONFINITE)
+
+
+def test_pcg_full_size_fixed_iterations(orc, h):
+    """The 64^3 variable-coefficient matrix at its full size (8 of the
+    workload's right-hand sides, so that the oracle finishes in seconds),
+    Jacobi preconditioner, 3 iterations, eta = 1e4."""
+    A, B, _ = W.build_workload("diffusion7var_64_s32")
+    B = np.ascontiguousarray(B[:, :8])
+    minv = 1.0 / _diag(A)
+    say("pcg 64^3 fixed")
+    Ad = dev_csr(P, A)
+    mg = to_np(P.bkry_jacobi_minv(h, Ad))
+    assert np.array_equal(mg, minv)
+    X, info = gpu_pcg(h, A, B, minv, tol=0.0, maxit=3, eta=1e4)
+    ro = orc.bcg(A, B, tol=0.0, maxit=3, eta=1e4, minv=minv)
+    assert info["iters"] == 3 and rel(X, ro["X"]) < 1e-10
+
+
+def test_pcg_full_size_time_to_tol(h):
+    """Full solve at full size: converges to 1e-10 (FP64 true residual) in
+    fewer iterations than without the preconditioner."""
+    A, B, _ = W.build_workload("diffusion7var_64_s32")
+    Ad, Bd = dev_csr(P, A), to_dev(B)
+    say("pcg 64^3 solve")
+    minv = P.bkry_jacobi_minv(h, Ad)
+    X, info = P.bkry_pcg_solve(h, Ad, Bd, minv, tol=1e-10, maxit=5000, eta=1e4)
+    assert info["converged"] and max(info["true_relres"]) <= 2e-10
+    X0, i0 = P.bkry_cg_solve(h, Ad, Bd, tol=1e-10, maxit=5000, eta=1e4)
+    assert i0["converged"] and info["iters"] < i0["iters"]
+    say("pcg 64^3 iters", info["iters"], "vs", i0["iters"], "s", info["seconds"], i0["seconds"])
