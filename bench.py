@@ -289,6 +289,24 @@ def extras(P, W, h, dev, A, Ad, Bd, args):
         del A3d, B3d, X64, X32
     except Exception as e:
         ex["ir_diffusion27_96_s16"] = dict(error=str(e))
+    # Jacobi-preconditioned block CG vs no preconditioner, 64^3 variable-coefficient workload
+    try:
+        A5, B5, _ = W.build_workload("diffusion7var_64_s32")
+        A5d = P.CsrMatrix.from_numpy(A5.n, A5.rowptr, A5.colind, A5.val, device=dev)
+        B5d = torch.as_tensor(B5).to(dev)
+        minv = P.bkry_jacobi_minv(h, A5d)
+        P.bkry_pcg_solve(h, A5d, B5d, minv, tol=1e-10, maxit=5000, eta=1e4)
+        Xp, ip = P.bkry_pcg_solve(h, A5d, B5d, minv, tol=1e-10, maxit=5000, eta=1e4)
+        Xn, i0 = P.bkry_cg_solve(h, A5d, B5d, tol=1e-10, maxit=5000, eta=1e4)
+        ex["pcg_jacobi_diffusion7var_64_s32"] = dict(
+            iters=ip["iters"], reorth=ip["reorth"], seconds=round(ip["seconds"], 4),
+            iters_per_s=round(ip["iters"] / ip["seconds"], 1), converged=ip["converged"],
+            true_relres_max=max(ip["true_relres"]), unpreconditioned_iters=i0["iters"],
+            unpreconditioned_seconds=round(i0["seconds"], 4))
+        log("pcg", ex["pcg_jacobi_diffusion7var_64_s32"])
+        del A5d, B5d, Xp, Xn, minv
+    except Exception as e:
+        ex["pcg_jacobi_diffusion7var_64_s32"] = dict(error=str(e))
     # differentiable solve: forward + adjoint on the 64^3 variable-coefficient workload
     try:
         A5, B5, e5 = W.build_workload("diffusion7var_64_s32")
