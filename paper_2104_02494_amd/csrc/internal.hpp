@@ -147,6 +147,15 @@ template <typename T>
 hipError_t launch_gram(int64_t n, int s, const T* X, int nx, const T* Y, T* partial, int nblk, Red red,
                        const int32_t* gate, hipStream_t st, const int32_t* fire = nullptr);
 
+// FP64 Gram X^T Y and row product X = X C on the matrix cores (widths
+// 8 < s <= 32; kernels_mfma.hip); same partial layout as the vector kernels
+// (one s x s partial per workgroup, nblk workgroups).
+bool mfma_width(int s);
+hipError_t launch_gram_mfma(int64_t n, int s, const double* X, const double* Y, double* partial, int nblk,
+                            const int32_t* done, const int32_t* fire, hipStream_t st);
+hipError_t launch_rowmul_mfma(int64_t n, int s, double* X, const double* C, bool gram, double* partial, int nblk,
+                              const int32_t* gf, hipStream_t st);
+
 // CG residual update R~ = R - Q lambda (in place in R) and the Gram of R~ into
 // red.G.  With minv (the diagonal of M^-1, n entries; FP64 only), also the
 // Gram R~^T M^-1 R~ (partials of 2*s*s entries, epi kind EPI_CG_RHO_M).

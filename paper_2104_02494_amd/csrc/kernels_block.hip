@@ -576,6 +576,14 @@ hipError_t launch_gram(int64_t n, int s, const T* X, int nx, const T* Y, T* part
                        const int32_t* done, hipStream_t st, const int32_t* fire) {
   if (nx <= 0) return hipSuccess;
   if (nx > kMaxBatch) return hipErrorInvalidValue;
+  if constexpr (sizeof(T) == 8) {
+    // widths 9..32 in FP64: matrix cores
+    if (nx == 1 && mfma_width(s)) {
+      hipError_t e = launch_gram_mfma(n, s, X, Y, partial, nblk, done, fire, st);
+      if (e != hipSuccess) return e;
+      return launch_reduce(s, partial, false, nblk, 1, red, done, fire, Epi{}, st);
+    }
+  }
   hipError_t e = dispatch_s<T>(s, [&](auto S_, auto V_) -> hipError_t {
     constexpr int S = decltype(S_)::value, V = decltype(V_)::value;
     if (nx == 1) {
@@ -866,6 +874,14 @@ __global__ __launch_bounds__(kBlock) void rowmul_kernel(int64_t n, int s, T* __r
 template <typename T>
 hipError_t launch_rowmul(int64_t n, int s, T* X, const double* C, bool gram, T* partial, int nblk, Red red,
                          const int32_t* gf, hipStream_t st) {
+  if constexpr (sizeof(T) == 8) {
+    // widths 9..32 in FP64: matrix cores
+    if (mfma_width(s)) {
+      hipError_t e = launch_rowmul_mfma(n, s, X, C, gram, partial, nblk, gf, st);
+      if (e != hipSuccess || !gram) return e;
+      return launch_reduce(s, partial, false, nblk, 1, red, nullptr, gf, Epi{}, st);
+    }
+  }
   hipError_t e = dispatch_s<T>(s, [&](auto S_, auto V_) -> hipError_t {
     constexpr int S = decltype(S_)::value, V = decltype(V_)::value;
     if (gram)

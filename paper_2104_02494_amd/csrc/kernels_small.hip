@@ -690,10 +690,16 @@ __device__ __forceinline__ double sum_strided(const T* __restrict__ p, int64_t s
   return acc;
 }
 
+// Plain reductions (no epilogue) run four wavefronts per workgroup, so that
+// wide Grams (s = 32: 1024 entries per partial) are summed by 256 lanes;
+// the CG epilogues need a single wavefront.
+constexpr int kRedPlain = 256;
+
 template <typename T, int EPI, int SM>
-__global__ __launch_bounds__(kSB) void reduce_kernel(int s, const T* __restrict__ partial, int nblk, Red red,
-                                                      const int32_t* gate, const int32_t* fire, CgCtl* c,
-                                                      double* hist) {
+__global__ __launch_bounds__(EPI == EPI_NONE ? kRedPlain : kSB) void reduce_kernel(
+    int s, const T* __restrict__ partial, int nblk, Red red, const int32_t* gate, const int32_t* fire, CgCtl* c,
+    double* hist) {
+  constexpr int NTH = EPI == EPI_NONE ? kRedPlain : kSB;
   constexpr bool RHO = EPI == EPI_CG_RHO || EPI == EPI_CG_RHO_M;
   constexpr int NG = EPI == EPI_CG_RHO_M ? 2 : 1;  // Grams per partial
   __shared__ int last;
@@ -728,7 +734,7 @@ __global__ __launch_bounds__(kSB) void reduce_kernel(int s, const T* __restrict_
   const T* P = partial + (int64_t)y * nblk * m;
   const int b0 = (int)((int64_t)nblk * sl / ns), b1 = (int)((int64_t)nblk * (sl + 1) / ns);
   double* slices = red.gpart + (int64_t)y * ns * m;
-  for (int e = tid(); e < m; e += kSB) slices[(int64_t)sl * m + e] = sum_strided<T>(P + (int64_t)b0 * m + e, m, b1 - b0);
+  for (int e = tid(); e < m; e += NTH) slices[(int64_t)sl * m + e] = sum_strided<T>(P + (int64_t)b0 * m + e, m, b1 - b0);
   uint32_t* cnt = red.cnt + (int64_t)y * kCntStride;
   __threadfence();
   __syncthreads();
@@ -738,7 +744,7 @@ __global__ __launch_bounds__(kSB) void reduce_kernel(int s, const T* __restrict_
   __threadfence();
   double* G = red.G + (int64_t)y * m;
   __shared__ double Gl[EPI != EPI_NONE ? NG * kSS : 1];
-  for (int e = tid(); e < m; e += kSB) {
+  for (int e = tid(); e < m; e += NTH) {
     const double v = sum_strided<double>(slices + e, m, ns);
     G[e] = v;
     if constexpr (EPI != EPI_NONE) Gl[e] = v;
@@ -767,7 +773,7 @@ static hipError_t launch_reduce_t(int s, const T* partial, int nblk, int batch, 
                                   const int32_t* fire, Epi epi, hipStream_t st) {
   dim3 grid(reduce_slices(nblk), batch);
   if (epi.kind == EPI_NONE) {
-    hipLaunchKernelGGL((reduce_kernel<T, EPI_NONE, 8>), grid, dim3(kSB), 0, st, s, partial, nblk, red, gate, fire,
+    hipLaunchKernelGGL((reduce_kernel<T, EPI_NONE, 8>), grid, dim3(kRedPlain), 0, st, s, partial, nblk, red, gate, fire,
                        epi.ctl, epi.hist);
     return hipGetLastError();
   }

@@ -110,6 +110,32 @@ def test_tsqr_block_matches_householder(orc, h, n, s):
     assert rel(Q @ R, X) < 1e-14
 
 
+@pytest.mark.parametrize("s", [9, 12, 16, 20, 24, 31, 32])
+def test_matrix_core_widths(orc, h, s):
+    """Widths 9..32 run the FP64 Gram and row products on the matrix cores
+    (16 x 16 x 4 tiles, columns past s masked, ragged last tile): BDOT within
+    the summation bound, the normaliser against Householder QR."""
+    n = 70_001
+    X = W.gaussian_block(n, s, 50 + s)
+    Y = W.gaussian_block(n, s, 60 + s)
+    say("matrix cores: bdot", n, s)
+    G = to_np(P.bkry_bdot(h, to_dev(X), to_dev(Y), "block"))
+    assert np.all(np.abs(G - orc.bdot(X, Y, "block")) <= gram_bound(X, Y) + 1e-300)
+    say("matrix cores: tsqr", n, s)
+    Xd = to_dev(X)
+    R = to_np(P.bkry_tsqr(h, Xd, "block"))
+    Q = to_np(Xd)
+    Qo, Ro = orc.householder_qr(X)
+    assert rel(R, Ro) < 1e-12 and rel(Q, Qo) < 1e-12
+    assert np.abs(Q.T @ Q - np.eye(s)).max() < 1e-13
+    for kind, q in (("hybrid", 2), ("hybrid", 4)) if s % 4 == 0 else ():
+        say("matrix cores: tsqr", kind, q, s)
+        Xd = to_dev(X)
+        N = to_np(P.bkry_tsqr(h, Xd, kind, q))
+        Yo, No = orc.normalize(X, kind, q)
+        assert rel(N, No) < 1e-12 and rel(to_np(Xd), Yo) < 1e-12
+
+
 @pytest.mark.parametrize("kind,q", SUBS + [("hybrid", 4)])
 def test_tsqr_subalgebras(orc, h, kind, q):
     n, s = 50_000, 8
