@@ -62,6 +62,9 @@ def lib():
             "or_reortho_fires": (i32, [dbl, dbl, dbl]),
             "or_bcg": (i32, [i64, ptr, ptr, ptr, i32, i32, i32, ptr, ptr, dbl, i32, dbl, dbl, ptr, ptr, ptr, i32,
                              ptr, ptr, i32, ptr]),
+            "or_lu_solve": (i32, [i32, i32, i32, ptr, ptr, ptr]),
+            "or_bbicgstab": (i32, [i64, ptr, ptr, ptr, i32, i32, i32, ptr, ptr, dbl, i32, dbl, dbl, ptr, ptr, ptr,
+                                   i32]),
             "or_block_arnoldi": (i32, [i64, ptr, ptr, ptr, i32, i32, i32, ptr, i32, ptr, ptr, ptr]),
             "or_bgmres": (i32, [i64, ptr, ptr, ptr, i32, i32, i32, ptr, ptr, dbl, i32, i32, ptr, ptr, ptr, i32]),
             "or_sddmm": (None, [i64, ptr, ptr, i32, dbl, ptr, ptr, ptr]),
@@ -218,6 +221,31 @@ def bcg(A, B, X0=None, kind="block", q=1, tol=1e-10, maxit=1000, eta=0.0, eps=No
                 hist=hist[:min(it, hist_cap)] if hist_cap else None,
                 Pk=Pk[:min(it, record_blocks)] if record_blocks else None,
                 Rk=Rk[:min(it, record_blocks)] if record_blocks else None)
+
+
+def lu_solve(A, B, kind, q=1):
+    A, B = _f64(A), _f64(B)
+    X = np.zeros_like(A)
+    st = lib().or_lu_solve(A.shape[0], _kind(kind), q, _p(A), _p(B), _p(X))
+    return st, X
+
+
+def bbicgstab(A, B, X0=None, kind="block", q=1, tol=1e-10, maxit=1000, eta=0.0, eps=None, hist_cap=0):
+    """Block BiCGStab with adaptive residual re-orthonormalisation (M = I).
+    Returns dict(status, X, iters, reorth, converged, relres, hist)."""
+    n, rp, ci, v = _csr(A)
+    B = _f64(B)
+    s = B.shape[1]
+    X = np.zeros_like(B) if X0 is None else _f64(X0).copy()
+    info = np.zeros(4, dtype=np.int32)
+    relres = np.zeros(s)
+    hist = np.zeros(max(hist_cap, 1))
+    eps = eps_f64() if eps is None else eps
+    st = lib().or_bbicgstab(n, _p(rp), _p(ci), _p(v), s, _kind(kind), q, _p(B), _p(X), tol, maxit, eta, eps,
+                            _p(info), _p(relres), _p(hist) if hist_cap else None, hist_cap)
+    it = int(info[0])
+    return dict(status=st, X=X, iters=it, reorth=int(info[1]), converged=bool(info[2]), relres=relres,
+                hist=hist[:min(it, hist_cap)] if hist_cap else None)
 
 
 def block_arnoldi(A, R, m, kind="block", q=1):

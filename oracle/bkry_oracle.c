@@ -531,6 +531,179 @@ done:
 }
 
 /* ------------------------------------------------------------------------ */
+/* Solve A X = B inside the subalgebra for a general (non-symmetric) A in S  */
+/* by Gaussian elimination with partial pivoting per S-block (the           */
+/* coefficient systems of block BiCGStab, Ch. 6).  A zero pivot is a         */
+/* breakdown.  Only the S-blocks of B are used; X is returned in S.          */
+/* ------------------------------------------------------------------------ */
+int or_lu_solve(int s, int kind, int q, const double* A, const double* B, double* X) {
+  int g = group_width(s, kind, q);
+  if (g < 1 || g > 64) return OR_E_INVALID;
+  double M[64 * 64], Y[64 * 64];
+  for (int t = 0; t < s * s; ++t) X[t] = 0.0;
+  for (int grp = 0; grp < s / g; ++grp) {
+    int o = grp * g;
+    for (int i = 0; i < g; ++i)
+      for (int j = 0; j < g; ++j) {
+        M[i * g + j] = A[(o + i) * s + o + j];
+        Y[i * g + j] = B[(o + i) * s + o + j];
+      }
+    for (int c = 0; c < g; ++c) {
+      int piv = c;
+      for (int i = c + 1; i < g; ++i)
+        if (fabs(M[i * g + c]) > fabs(M[piv * g + c])) piv = i;
+      if (!(M[piv * g + c] != 0.0) || !isfinite(M[piv * g + c])) return OR_E_BREAKDOWN;
+      if (piv != c)
+        for (int j = 0; j < g; ++j) {
+          double t = M[c * g + j]; M[c * g + j] = M[piv * g + j]; M[piv * g + j] = t;
+          t = Y[c * g + j]; Y[c * g + j] = Y[piv * g + j]; Y[piv * g + j] = t;
+        }
+      for (int i = c + 1; i < g; ++i) {
+        double f = M[i * g + c] / M[c * g + c];
+        for (int j = c; j < g; ++j) M[i * g + j] -= f * M[c * g + j];
+        for (int j = 0; j < g; ++j) Y[i * g + j] -= f * Y[c * g + j];
+      }
+    }
+    for (int col = 0; col < g; ++col)
+      for (int i = g - 1; i >= 0; --i) {
+        double sum = Y[i * g + col];
+        for (int k = i + 1; k < g; ++k) sum -= M[i * g + k] * X[(o + k) * s + o + col];
+        X[(o + i) * s + o + col] = sum / M[i * g + i];
+      }
+  }
+  return OR_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Block BiCGStab with adaptive residual re-orthonormalisation (Algorithm    */
+/* "BBiCGStab with Adaptive Residual Re-Orthonormalization", Ch. 6) without  */
+/* preconditioner (M = I, so Z = Q, V = R-hat and T = S-hat after a          */
+/* re-normalisation), shadow residual R~0 = P-hat^0:                         */
+/*                                                                          */
+/*   R0 = B - A X0; (R^, sigma) = Norm_S(R0) if eta > 0, else (R0, I)        */
+/*   P^ = R^, R~0 = P^, V^ = P^                                              */
+/*   repeat: Q^ = A P^; a = <R~0, Q^>_S; lambda = a^-1 <R~0, R^>_S;          */
+/*           Z^ = Q^; S^ = R^ - Q^ lambda; X += P^ lambda sigma;             */
+/*           if eta kappa_D(<R^, R^>_S) sqrt(eps) > 1:                       */
+/*              (S^, gamma) = Norm_S(S^), sigma = gamma sigma, T^ = S^       */
+/*           else T^ = V^ - Z^ lambda;                                       */
+/*           U^ = A T^; omega = <U^, S^>_F / <U^, U^>_F;                     */
+/*           X += omega T^ sigma; R^ = S^ - omega U^;                        */
+/*           stop if max_i |(R^ sigma)_i| / |R0_i| <= tol;                   */
+/*           V^ = R^; beta = -a^-1 <R~0, U^>_S; P^ = V^ + (P^ - omega Z^) beta. */
+/*                                                                          */
+/* sigma in the two X updates is the current one: after a re-normalisation  */
+/* T^ carries the new transformation (T = T^ gamma sigma), so the second     */
+/* update uses the updated sigma (reading of the listing, which writes       */
+/* sigma^k).  <.,.>_F is the Frobenius inner product sum_ij X_ij Y_ij.       */
+/* info[0] = iterations, info[1] = normalisations (the initial one included),*/
+/* info[2] = converged.                                                      */
+/* ------------------------------------------------------------------------ */
+int or_bbicgstab(i64 n, const int32_t* rowptr, const int32_t* colind, const double* val, int s, int kind, int q,
+                 const double* B, double* X, double tol, int maxit, double eta, double eps, int32_t* info,
+                 double* relres, double* hist, int hist_cap) {
+  if (!valid_subalg(s, kind, q) || s > 64 || n < group_width(s, kind, q)) return OR_E_INVALID;
+  size_t blk = (size_t)(n * s), ss = (size_t)s * s;
+  double* R = (double*)calloc(blk, sizeof(double));
+  double* P = (double*)calloc(blk, sizeof(double));
+  double* Rt = (double*)calloc(blk, sizeof(double));
+  double* Q = (double*)calloc(blk, sizeof(double));
+  double* S = (double*)calloc(blk, sizeof(double));
+  double* T = (double*)calloc(blk, sizeof(double));
+  double* U = (double*)calloc(blk, sizeof(double));
+  double* W = (double*)calloc(blk, sizeof(double));
+  if (!R || !P || !Rt || !Q || !S || !T || !U || !W) {
+    free(R); free(P); free(Rt); free(Q); free(S); free(T); free(U); free(W);
+    return OR_E_INVALID;
+  }
+  double sigma[64 * 64], a[64 * 64], g[64 * 64], lambda[64 * 64], beta[64 * 64], gamma[64 * 64], tmp[64 * 64];
+  double r0n[64], cn[64], rel[64];
+  int st = OR_OK, iters = 0, nro = 0, conv = 0;
+
+  or_residual(n, rowptr, colind, val, s, B, X, R);
+  column_norms(n, s, R, r0n);
+  for (int i = 0; i < s; ++i) rel[i] = (r0n[i] > 0.0) ? 1.0 : 0.0;
+  {
+    int allzero = 1;
+    for (int i = 0; i < s; ++i) allzero &= (r0n[i] == 0.0);
+    if (allzero) {
+      conv = 1;
+      for (int i = 0; i < s; ++i) rel[i] = 0.0;
+      goto done;
+    }
+  }
+  if (eta > 0.0) {
+    st = or_normalize(n, s, kind, q, R, R, sigma);
+    if (st != OR_OK) goto done;
+    nro++;
+  } else {
+    eye(s, sigma);
+  }
+  memcpy(P, R, blk * sizeof(double));                  /* P^ = R^ (M = I)  */
+  memcpy(Rt, P, blk * sizeof(double));                 /* R~0 = P^         */
+
+  for (int k = 0; k < maxit; ++k) {
+    or_spmm(n, rowptr, colind, val, s, P, Q);          /* Q^ = A P^ */
+    or_bdot(n, s, kind, q, Rt, Q, a);                  /* a = <R~0, Q^>_S */
+    or_bdot(n, s, kind, q, Rt, R, g);                  /* <R~0, R^>_S */
+    for (size_t t = 0; t < ss; ++t)
+      if (!isfinite(a[t]) || !isfinite(g[t])) { st = OR_E_NONFINITE; goto done; }
+    st = or_lu_solve(s, kind, q, a, g, lambda);        /* lambda = a^-1 <R~0, R^>_S */
+    if (st != OR_OK) goto done;
+    memcpy(S, R, blk * sizeof(double));                /* S^ = R^ - Q^ lambda */
+    block_axmy(n, s, Q, lambda, S);
+    mm(s, lambda, sigma, tmp);                         /* X += P^ lambda sigma */
+    block_axpy(n, s, P, tmp, X);
+    or_bdot(n, s, kind, q, R, R, g);                   /* test on <R^, R^>_S */
+    int fire = or_reortho_fires(eta, or_kappa_D(s, g), eps);
+    if (fire) {
+      st = or_normalize(n, s, kind, q, S, S, gamma);   /* (S^, gamma) = Norm_S(S^) */
+      if (st != OR_OK) goto done;
+      nro++;
+      mm(s, gamma, sigma, tmp);                        /* sigma = gamma sigma */
+      memcpy(sigma, tmp, ss * sizeof(double));
+      memcpy(T, S, blk * sizeof(double));              /* T^ = M^-1 S^ */
+    } else {
+      memcpy(T, R, blk * sizeof(double));              /* T^ = V^ - Z^ lambda, V^ = R^, Z^ = Q^ */
+      block_axmy(n, s, Q, lambda, T);
+    }
+    or_spmm(n, rowptr, colind, val, s, T, U);          /* U^ = A T^ */
+    double us = 0.0, uu = 0.0;
+    for (size_t t = 0; t < blk; ++t) {
+      us += U[t] * S[t];
+      uu += U[t] * U[t];
+    }
+    if (!(uu > 0.0) || !isfinite(uu) || !isfinite(us)) { st = (uu == 0.0) ? OR_E_BREAKDOWN : OR_E_NONFINITE; goto done; }
+    const double omega = us / uu;
+    for (int i = 0; i < s; ++i)                        /* X += omega T^ sigma */
+      for (int j = 0; j < s; ++j) tmp[i * s + j] = omega * sigma[i * s + j];
+    block_axpy(n, s, T, tmp, X);
+    for (size_t t = 0; t < blk; ++t) R[t] = S[t] - omega * U[t]; /* R^ = S^ - omega U^ */
+    iters = k + 1;
+    memset(W, 0, blk * sizeof(double));                /* stopping test on R^ sigma */
+    block_axpy(n, s, R, sigma, W);
+    column_norms(n, s, W, cn);
+    double m = max_rel(s, cn, r0n, rel);
+    if (hist && k < hist_cap) hist[k] = m;
+    if (isnan(m)) { st = OR_E_NONFINITE; goto done; }
+    if (m <= tol) { conv = 1; break; }
+    or_bdot(n, s, kind, q, Rt, U, g);                  /* beta = -a^-1 <R~0, U^>_S */
+    st = or_lu_solve(s, kind, q, a, g, beta);
+    if (st != OR_OK) goto done;
+    for (size_t t = 0; t < ss; ++t) beta[t] = -beta[t];
+    for (size_t t = 0; t < blk; ++t) W[t] = P[t] - omega * Q[t]; /* P^ = V^ + (P^ - omega Z^) beta */
+    memcpy(P, R, blk * sizeof(double));
+    block_axpy(n, s, W, beta, P);
+  }
+done:
+  if (info) { info[0] = iters; info[1] = nro; info[2] = conv; }
+  if (relres) for (int i = 0; i < s; ++i) relres[i] = rel[i];
+  free(R); free(P); free(Rt); free(Q); free(S); free(T); free(U); free(W);
+  if (st != OR_OK) return st;
+  return conv ? OR_OK : OR_NOT_CONVERGED;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Block Arnoldi step with modified Gram-Schmidt (Algorithm "Block Arnoldi    */
 /* Method", Ch. 5).  Given S-orthonormal V_0..V_k (each n x s, consecutive), */
 /* computes W = A V_k, h_jk = <V_j, W>_S and W -= V_j h_jk for j = 0..k in   */
