@@ -249,8 +249,11 @@ def extras(P, W, h, dev, A, Ad, Bd, args):
         ms, R = timed(tsqr_once, 5)
         ms -= ms_copy
         m, c = Xt.shape
-        ex["tsqr_4194304x32"] = dict(ms=round(ms, 3), GBps_algorithmic=round(2 * m * c * 8 / (ms * 1e-3) / 1e9, 1),
-                                     TFLOPs_algorithmic=round(4 * m * c * c / (ms * 1e-3) / 1e12, 2),
+        gbps = 2 * m * c * 8 / (ms * 1e-3) / 1e9
+        tfl = 4 * m * c * c / (ms * 1e-3) / 1e12
+        ex["tsqr_4194304x32"] = dict(ms=round(ms, 3), GBps_algorithmic=round(gbps, 1),
+                                     TFLOPs_algorithmic=round(tfl, 2), hbm_frac=round(gbps / 8000.0, 4),
+                                     fp64_mfma_frac=round(tfl / 78.6, 4),
                                      orth_err=float((Xw.T @ Xw - torch.eye(c, device=dev, dtype=Xw.dtype))
                                                     .abs().max()))
         del Xt, Xw
@@ -272,6 +275,22 @@ def extras(P, W, h, dev, A, Ad, Bd, args):
         del Acd, Bcd, Xg
     except Exception as e:
         ex["gmres30_convdiff1024"] = dict(error=str(e))
+    # block BiCGStab with adaptive re-orthonormalisation on the same workload
+    try:
+        Ac, Bc, _ = W.build_workload("convdiff2d_1024_s8")
+        Acd = P.CsrMatrix.from_numpy(Ac.n, Ac.rowptr, Ac.colind, Ac.val, device=dev)
+        Bcd = torch.as_tensor(Bc).to(dev)
+        P.bkry_bicgstab_solve(h, Acd, Bcd, tol=0.0, maxit=10, eta=1e4)
+        Xb, bi = P.bkry_bicgstab_solve(h, Acd, Bcd, tol=0.0, maxit=100, eta=1e4)
+        Xb, bt = P.bkry_bicgstab_solve(h, Acd, Bcd, tol=1e-10, maxit=20000, eta=1e4)
+        ex["bicgstab_convdiff1024"] = dict(ms_per_iter=round(bi["seconds"] / 100 * 1e3, 3),
+                                           solve_s=round(bt["seconds"], 3), iters=bt["iters"],
+                                           reorth=bt["reorth"], converged=bt["converged"],
+                                           true_relres_max=max(bt["true_relres"]))
+        log("bicgstab", ex["bicgstab_convdiff1024"])
+        del Acd, Bcd, Xb
+    except Exception as e:
+        ex["bicgstab_convdiff1024"] = dict(error=str(e))
     # FP32-inner iterative refinement vs FP64 on the 27-point variable-coefficient workload
     try:
         A3, B3, _ = W.build_workload("diffusion27_96_s16")

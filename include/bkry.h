@@ -186,6 +186,20 @@ int bkry_pcg_solve(bkry_handle h, const bkry_csr* A, int32_t p, bkry_subalg S, c
  * Synchronous. */
 int bkry_jacobi_minv(bkry_handle h, const bkry_csr* A, double* minv);
 
+/* Block BiCGStab with adaptive residual re-orthonormalisation (Algorithm
+ * "BBiCGStab with Adaptive Residual Re-Orthonormalization", Ch. 6) for
+ * general (non-symmetric) A, without preconditioner; shadow residual R~0 =
+ * the initial (normalised) residual.  Coefficient systems are solved per
+ * S-block by LU with partial pivoting; omega minimises the Frobenius norm of
+ * the transformed residual.  The residual is re-normalised in iteration k
+ * when eta * kappa_D(<R_k, R_k>_S) * sqrt(eps) > 1 (eta = 0 never,
+ * INFINITY always).  Stops when max_i |R_i| / |R0_i| <= tol (recursive
+ * residual R^ sigma) or after maxit iterations; info->true_relres holds the
+ * FP64 true residual.  A zero pivot or <U, U>_F = 0 is BKRY_E_BREAKDOWN.
+ * FP64; X holds X0 on entry; info [host] may be NULL. */
+int bkry_bicgstab_solve(bkry_handle h, const bkry_csr* A, int32_t p, bkry_subalg S, const double* B, double* X,
+                        double tol, int32_t maxit, double eta, bkry_info* info);
+
 /* Restarted block GMRes (Algorithm "Block GMRes Method", Ch. 5): block
  * Arnoldi with classical Gram-Schmidt applied twice (Algorithm "classical
  * Gram-Schmidt", Ch. 9) and TSQR normalisation of each new block, generalised

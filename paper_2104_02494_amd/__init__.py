@@ -58,7 +58,7 @@ class bkry_info(ctypes.Structure):
 EXPORTS = ["bkry_create", "bkry_destroy", "bkry_set_stream", "bkry_synchronize", "bkry_last_error",
            "bkry_profile", "bkry_profile_read", "bkry_set_spmm_format", "bkry_spmm",
            "bkry_spmm_f32", "bkry_bdot", "bkry_bdot_f32", "bkry_tsqr", "bkry_cg_solve", "bkry_pcg_solve",
-           "bkry_jacobi_minv", "bkry_gmres_solve", "bkry_sddmm", "bkry_csr_transpose"]
+           "bkry_jacobi_minv", "bkry_bicgstab_solve", "bkry_gmres_solve", "bkry_sddmm", "bkry_csr_transpose"]
 
 _lib = None
 
@@ -90,6 +90,7 @@ def lib():
             "bkry_cg_solve": [H, csr_p, i32, bkry_subalg, vp, vp, dbl, i32, dbl, i32, info_p],
             "bkry_pcg_solve": [H, csr_p, i32, bkry_subalg, vp, vp, vp, dbl, i32, dbl, info_p],
             "bkry_jacobi_minv": [H, csr_p, vp],
+            "bkry_bicgstab_solve": [H, csr_p, i32, bkry_subalg, vp, vp, dbl, i32, dbl, info_p],
             "bkry_gmres_solve": [H, csr_p, i32, bkry_subalg, vp, vp, dbl, i32, i32, info_p],
             "bkry_sddmm": [H, csr_p, i32, dbl, vp, vp, vp],
             "bkry_csr_transpose": [H, csr_p, vp, vp, vp, vp],
@@ -275,6 +276,22 @@ def bkry_jacobi_minv(h: Handle, A: CsrMatrix) -> torch.Tensor:
     d = A.desc()
     h._check(lib().bkry_jacobi_minv(h.h, ctypes.byref(d), _ptr(out)))
     return out
+
+
+def bkry_bicgstab_solve(h: Handle, A: CsrMatrix, B: torch.Tensor, X: torch.Tensor | None = None, kind="block",
+                        q=1, tol=1e-10, maxit=1000, eta=1e4, hist_cap=0):
+    """Block BiCGStab with adaptive residual re-orthonormalisation (FP64, no
+    preconditioner); X (in/out, zeros if None).  Returns (X, info)."""
+    _block(B)
+    X = torch.zeros_like(B) if X is None else _block(X)
+    p = B.shape[1]
+    info, hist, rel, trel = _info(p, hist_cap)
+    h._sync_stream()
+    d = A.desc()
+    rc = lib().bkry_bicgstab_solve(h.h, ctypes.byref(d), p, _subalg(kind, q), _ptr(B), _ptr(X), float(tol),
+                                   int(maxit), float(eta), ctypes.byref(info))
+    h._check(rc, allow=(OK, NOT_CONVERGED))
+    return X, _info_dict(rc, info, hist, rel, trel, p)
 
 
 def bkry_gmres_solve(h: Handle, A: CsrMatrix, B: torch.Tensor, X: torch.Tensor | None = None, kind="block", q=1,

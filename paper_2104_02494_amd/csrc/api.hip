@@ -607,6 +607,74 @@ int bkry_gmres_solve(bkry_handle h, const bkry_csr* A, int32_t p, bkry_subalg S,
   return r.converged ? BKRY_OK : BKRY_NOT_CONVERGED;
 }
 
+int bkry_bicgstab_solve(bkry_handle h, const bkry_csr* A, int32_t p, bkry_subalg S, const double* B, double* X,
+                        double tol, int32_t maxit, double eta, bkry_info* info) {
+  int rc = begin(h);
+  Sub sub;
+  if (!rc) rc = check_csr(h, A, true);
+  if (!rc) rc = check_sub(h, p, S, sub);
+  if (!rc) rc = check_blocks(h, {B, X});
+  if (!rc && !(tol >= 0.0)) rc = fail(h, BKRY_E_INVALID, "tol must be >= 0");
+  if (!rc && maxit < 0) rc = fail(h, BKRY_E_INVALID, "maxit must be >= 0");
+  if (!rc && !(eta >= 0.0)) rc = fail(h, BKRY_E_INVALID, "eta must be >= 0");
+  if (!rc && (A->n < sub.g || (S.kind == BKRY_GLOBAL && A->n < p)))
+    rc = fail(h, BKRY_E_INVALID, "block BiCGStab needs n >= p (block, global) or n >= p/q (hybrid)");
+  if (rc) return rc;
+  const double t0 = now_s();
+  const int64_t n = A->n;
+  const int hist_cap = (info && info->hist && info->hist_cap > 0) ? info->hist_cap : 0;
+  int W = 0;
+  rc = ell_width_for(h, A, p, sizeof(double), true, W);
+  if (rc) return rc;
+  const size_t ne = (size_t)n * W;
+  Carver c;
+  carve_bc(c, n, sub, hist_cap, h->cnt);
+  c.take<double>(kMaxS);
+  c.take<double>(kMaxS);
+  c.take<int32_t>(4);
+  c.take<int32_t>(ne);
+  c.take<double>(ne);
+  rc = ensure_ws(h, c.off);
+  if (rc) return rc;
+  Carver w{h->ws};
+  BcBufs bb = carve_bc(w, n, sub, hist_cap, h->cnt);
+  double* trr = w.take<double>(kMaxS);
+  double* tsc = w.take<double>(kMaxS);
+  int32_t* tfl = w.take<int32_t>(4);
+  int32_t* ecol = w.take<int32_t>(ne);
+  double* eval = w.take<double>(ne);
+  CsrView v = view(A);
+  rc = ell_build<double, double>(h, A, A->val, W, ecol, eval, v);
+  if (rc) return rc;
+  BcResult r;
+  hipError_t e = bc_run(v, sub, B, X, tol, maxit, eta, hist_cap, bb, h->stream, h->hflags, r);
+  if (e != hipSuccess) return hip_fail(h, e, "bicgstab_solve");
+  double relres[kMaxS], trel[kMaxS];
+  const int hist_len = r.iters < hist_cap ? r.iters : hist_cap;
+  API_HIP(hipMemcpyAsync(relres, bb.ctl->relres, sizeof(double) * p, hipMemcpyDeviceToHost, h->stream), "bicgstab");
+  if (hist_len > 0)
+    API_HIP(hipMemcpyAsync(info->hist, bb.hist, sizeof(double) * hist_len, hipMemcpyDeviceToHost, h->stream),
+            "bicgstab");
+  API_HIP(true_relres(v, p, B, X, bb.W3, bb.partial, bb.gpart, h->cnt, bb.G, bb.ctl->r0n, trr, tfl, tsc, h->stream),
+          "bicgstab");
+  API_HIP(hipMemcpyAsync(trel, trr, sizeof(double) * p, hipMemcpyDeviceToHost, h->stream), "bicgstab");
+  API_HIP(hipStreamSynchronize(h->stream), "bicgstab");
+  if (info) {
+    info->iters = r.iters;
+    info->reorth = r.nreorth;
+    info->outer_iters = 0;
+    info->converged = r.converged;
+    info->hist_len = hist_len;
+    info->seconds = now_s() - t0;
+    if (info->relres) memcpy(info->relres, relres, sizeof(double) * p);
+    if (info->true_relres) memcpy(info->true_relres, trel, sizeof(double) * p);
+  }
+  if (r.bad_index) return fail(h, BKRY_E_INVALID, "a CSR column index was outside [0, n)");
+  rc = status_of(r.status, h);
+  if (rc) return rc;
+  return r.converged ? BKRY_OK : BKRY_NOT_CONVERGED;
+}
+
 int bkry_sddmm(bkry_handle h, const bkry_csr* pattern, int32_t p, double alpha, const double* L, const double* X,
                double* out_val) {
   int rc = begin(h);

@@ -90,6 +90,19 @@ struct CgCtl {
 };
 constexpr int kCtlHeaderInts = 24;
 
+// Coefficients of block BiCGStab beside its CgCtl (which holds the header,
+// sigma, gamma, lambda sigma, r0n and relres): a = <R~0, Q^>_S of the
+// iteration, and the s x s multipliers of its block combinations.
+struct BcAux {
+  double a[kMaxS * kMaxS];
+  double neglam[kMaxS * kMaxS];  // -lambda
+  double omsig[kMaxS * kMaxS];   // omega sigma
+  double negomI[kMaxS * kMaxS];  // -omega I
+  double pbeta[kMaxS * kMaxS];   // beta
+  double qbeta[kMaxS * kMaxS];   // -omega beta
+  double omega, pad_[7];
+};
+
 // Device control block of a block GMRes solve (per-cycle arrays live in
 // separate workspace buffers: H, sig, Om, zeta).
 struct GmCtl {
@@ -257,6 +270,25 @@ hipError_t launch_ell_fill(const CsrView& A, const Tin* val, int W, int32_t* eco
 // minv[i] = 1 / A_ii (FP64 values); a missing, non-positive or non-finite
 // diagonal sets *bad = 1.
 hipError_t launch_jacobi_minv(const CsrView& A, double* minv, int32_t* bad, hipStream_t st);
+
+// ------------------------------------------------------ block BiCGStab ----
+// Coefficient steps of block BiCGStab (single-wavefront kernels, each a no-op
+// once ctl->done is set).  bc_lambda: from Gqr = [Q^T R~0 | R^T R~0] and
+// Grr = R^T R: a, lambda = a^-1 <R~0, R>_S (per-S-block LU with partial
+// pivoting), -lambda, lambda sigma and the re-orthonormalisation test on
+// kappa_D(<R, R>_S).  bc_sigma: sigma = gamma sigma when the test fired.
+// bc_omega: from G3 = [S^T U | U^T U | R~0^T U]: omega = <U, S>_F / <U, U>_F,
+// beta = -a^-1 <R~0, U>_S and the combination multipliers.  bc_stop: column
+// norms of R sigma from Grr, stopping test, history, iteration count.
+hipError_t launch_bc_lambda(CgCtl* ctl, BcAux* aux, int s, const double* Gqr, const double* Grr, hipStream_t st);
+hipError_t launch_bc_sigma(CgCtl* ctl, hipStream_t st);
+hipError_t launch_bc_omega(CgCtl* ctl, BcAux* aux, const double* G3, hipStream_t st);
+hipError_t launch_bc_stop(CgCtl* ctl, const double* Grr, double* hist, hipStream_t st);
+// Y = A0 + X1 C1 (+ X2 C2) for n x s blocks (C: s x s FP64, device); Y may
+// alias A0 but neither X.  Runs only if *done == 0 (done may be null).
+template <typename T>
+hipError_t launch_lincomb(int64_t n, int s, const T* A0, const T* X1, const double* C1, const T* X2,
+                          const double* C2, T* Y, const int32_t* done, hipStream_t st);
 
 // ---------------------------------------------------------------- TSQR ----
 // Workspace (bytes) needed by tsqr_run for n rows, width s, subalgebra sub.

@@ -846,6 +846,222 @@ hipError_t launch_cg_reortho_fin(CgCtl* ctl, int s, const double* G, hipStream_t
   });
 }
 
+// ------------------------------------------------------ block BiCGStab --
+// X = A^-1 B inside the subalgebra for a general A (s x s in LDS, already
+// projected, so its off-block entries are zero and the elimination stays
+// inside each S-block) by Gaussian elimination with partial pivoting: the
+// pivot is the first row of largest magnitude at or below the diagonal.  A
+// and B are overwritten.  False (uniformly) on a zero or non-finite pivot.
+__device__ __forceinline__ bool sm_lu_solve(double* A, double* B, double* X, int s, int* piv_sh) {
+  for (int c = 0; c < s; ++c) {
+    __syncthreads();
+    if (tid() == 0) {
+      int p = c;
+      double best = fabs(A[c * s + c]);
+      for (int i = c + 1; i < s; ++i)
+        if (fabs(A[i * s + c]) > best) {
+          best = fabs(A[i * s + c]);
+          p = i;
+        }
+      piv_sh[0] = p;
+    }
+    __syncthreads();
+    const int p = piv_sh[0];
+    const double pv = A[p * s + c];
+    if (!(pv != 0.0) || !isfinite(pv)) return false;
+    if (p != c)
+      for (int j = tid(); j < s; j += kSB) {
+        double t = A[c * s + j];
+        A[c * s + j] = A[p * s + j];
+        A[p * s + j] = t;
+        t = B[c * s + j];
+        B[c * s + j] = B[p * s + j];
+        B[p * s + j] = t;
+      }
+    __syncthreads();
+    // rows below c: lane i computes its multiplier, then updates its row
+    for (int i = c + 1 + tid(); i < s; i += kSB) {
+      const double f = A[i * s + c] / A[c * s + c];
+      for (int j = c; j < s; ++j) A[i * s + j] -= f * A[c * s + j];
+      for (int j = 0; j < s; ++j) B[i * s + j] -= f * B[c * s + j];
+    }
+  }
+  __syncthreads();
+  for (int col = tid(); col < s; col += kSB)
+    for (int i = s - 1; i >= 0; --i) {
+      double sum = B[i * s + col];
+      for (int k = i + 1; k < s; ++k) sum -= A[i * s + k] * X[k * s + col];
+      X[i * s + col] = sum / A[i * s + i];
+    }
+  __syncthreads();
+  return true;
+}
+
+__device__ __forceinline__ void bc_fail(CgCtl* c, int status) {
+  if (tid() == 0) {
+    c->status = status;
+    c->done = 1;
+    c->fire = 0;
+  }
+}
+
+template <int SM>
+__global__ __launch_bounds__(kSB) void bc_lambda_kernel(CgCtl* c, BcAux* x, const double* Gqr, const double* Grr) {
+  __shared__ double Am[kSS], Bm[kSS], Lm[kSS], Sg[kSS], T1[kSS], Lo[kSS], Li[kSS], W[kSS];
+  __shared__ double rc[kMaxS], rs[kMaxS], red[4];
+  __shared__ int partner[kMaxS], first[kMaxS], piv[1];
+  if (c->done) return;
+  const int s = c->s, ss = s * s;
+  const Sub sub{c->kind, s, c->g};
+  // a = <R~0, Q>_S = proj((Q^T R~0)^T), <R~0, R>_S likewise
+  for (int t = tid(); t < ss; t += kSB) {
+    const int i = t / s, j = t % s;
+    Am[t] = Gqr[j * s + i];
+    Bm[t] = Gqr[ss + j * s + i];
+  }
+  sm_project(Am, sub, red);
+  sm_project(Bm, sub, red);
+  if (!all_finite(Am, ss, red) || !all_finite(Bm, ss, red)) {
+    bc_fail(c, -3);
+    return;
+  }
+  sm_copy(x->a, Am, ss);
+  if (!sm_lu_solve(Am, Bm, Lm, s, piv)) {
+    bc_fail(c, -2);
+    return;
+  }
+  sm_copy(Sg, c->sigma, ss);
+  sm_mm(T1, Lm, Sg, s, false);  // lambda sigma
+  for (int t = tid(); t < ss; t += kSB) {
+    x->neglam[t] = -Lm[t];
+    c->lamsig[t] = T1[t];
+  }
+  // re-orthonormalisation test on kappa_D(<R, R>_S)
+  for (int t = tid(); t < ss; t += kSB) W[t] = Grr[t];
+  sm_project(W, sub, red);
+  sm_copy(Am, W, ss);
+  __syncthreads();
+  bool fire;
+  if (rf_cholesky_factor<SM>(Am, Lo, Li, s))
+    fire = reortho_test<SM>(c, Am, W, Li, rc, rs, partner, first, red);
+  else
+    fire = c->eta > 0.0;  // not positive definite: kappa_D = infinity
+  __syncthreads();
+  if (tid() == 0) {
+    c->fire = fire ? 1 : 0;
+    if (fire) c->nreorth += 1;
+  }
+}
+
+__global__ __launch_bounds__(kSB) void bc_sigma_kernel(CgCtl* c) {
+  __shared__ double Ga[kSS], Sg[kSS], T1[kSS];
+  if (c->done || !c->fire) return;
+  const int s = c->s;
+  sm_copy(Ga, c->gamma, s * s);
+  sm_copy(Sg, c->sigma, s * s);
+  sm_mm(T1, Ga, Sg, s, false);
+  sm_copy(c->sigma, T1, s * s);
+}
+
+__global__ __launch_bounds__(kSB) void bc_omega_kernel(CgCtl* c, BcAux* x, const double* G3) {
+  __shared__ double Am[kSS], Bm[kSS], Bt[kSS], Sg[kSS];
+  __shared__ double red[4];
+  __shared__ int piv[1];
+  if (c->done) return;
+  const int s = c->s, ss = s * s;
+  const Sub sub{c->kind, s, c->g};
+  double us = 0.0, uu = 0.0;
+  for (int i = tid(); i < s; i += kSB) {
+    us += G3[i * s + i];
+    uu += G3[ss + i * s + i];
+  }
+  us = wsum(us);
+  uu = wsum(uu);
+  if (!isfinite(us) || !isfinite(uu)) {
+    bc_fail(c, -3);
+    return;
+  }
+  if (!(uu > 0.0)) {
+    bc_fail(c, -2);
+    return;
+  }
+  const double om = us / uu;
+  sm_copy(Am, x->a, ss);
+  for (int t = tid(); t < ss; t += kSB) Bm[t] = G3[2 * ss + t];  // <R~0, U> = R~0^T U
+  sm_project(Bm, sub, red);
+  if (!sm_lu_solve(Am, Bm, Bt, s, piv)) {
+    bc_fail(c, -2);
+    return;
+  }
+  sm_copy(Sg, c->sigma, ss);
+  for (int t = tid(); t < ss; t += kSB) {
+    const double b = -Bt[t];
+    x->pbeta[t] = b;
+    x->qbeta[t] = -om * b;
+    x->omsig[t] = om * Sg[t];
+    x->negomI[t] = (t / s == t % s) ? -om : 0.0;
+  }
+  if (tid() == 0) x->omega = om;
+}
+
+__global__ __launch_bounds__(kSB) void bc_stop_kernel(CgCtl* c, const double* Grr, double* hist) {
+  __shared__ double Gm[kSS], Sg[kSS], T1[kSS];
+  if (c->done) return;
+  const int s = c->s;
+  sm_copy(Gm, Grr, s * s);
+  sm_copy(Sg, c->sigma, s * s);
+  sm_mm(T1, Gm, Sg, s, false);  // G sigma
+  double rel = 0.0;
+  bool nanl = false;
+  for (int i = tid(); i < s; i += kSB) {
+    double acc = 0.0;
+    for (int a = 0; a < s; ++a) acc += Sg[a * s + i] * T1[a * s + i];
+    const double r = c->r0n[i] > 0.0 ? sqrt(fmax(acc, 0.0)) / c->r0n[i] : 0.0;
+    nanl |= !isfinite(acc);
+    c->relres[i] = r;
+    rel = fmax(rel, r);
+  }
+  const double m = wmax(rel);
+  const bool nan = wany(nanl);
+  if (tid() == 0) {
+    const int it = c->iters;
+    if (hist && it < c->hist_cap) hist[it] = nan ? NAN : m;
+    c->iters = it + 1;
+    if (nan) {
+      c->status = -3;
+      c->done = 1;
+    } else if (m <= c->tol) {
+      c->converged = 1;
+      c->done = 1;
+    } else if (it + 1 >= c->maxit) {
+      c->done = 1;
+    }
+  }
+}
+
+hipError_t launch_bc_lambda(CgCtl* ctl, BcAux* aux, int s, const double* Gqr, const double* Grr, hipStream_t st) {
+  return dispatch_sm(s, [&](auto SM_) -> hipError_t {
+    constexpr int SM = decltype(SM_)::value;
+    hipLaunchKernelGGL(bc_lambda_kernel<SM>, dim3(1), dim3(kSB), 0, st, ctl, aux, Gqr, Grr);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_bc_sigma(CgCtl* ctl, hipStream_t st) {
+  hipLaunchKernelGGL(bc_sigma_kernel, dim3(1), dim3(kSB), 0, st, ctl);
+  return hipGetLastError();
+}
+
+hipError_t launch_bc_omega(CgCtl* ctl, BcAux* aux, const double* G3, hipStream_t st) {
+  hipLaunchKernelGGL(bc_omega_kernel, dim3(1), dim3(kSB), 0, st, ctl, aux, G3);
+  return hipGetLastError();
+}
+
+hipError_t launch_bc_stop(CgCtl* ctl, const double* Grr, double* hist, hipStream_t st) {
+  hipLaunchKernelGGL(bc_stop_kernel, dim3(1), dim3(kSB), 0, st, ctl, Grr, hist);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------------ CholeskyQR --
 // One factorisation step of the block / hybrid normaliser by CholeskyQR2 (see
 // launch_cholqr in internal.hpp for the plan flags).  G is the full Gram of

@@ -9,6 +9,8 @@
 
 #include "solvers.hpp"
 
+#include <utility>
+
 namespace bkry {
 
 #define BK_TRY(x)                       \
@@ -237,6 +239,114 @@ template hipError_t cg_run<double>(const CsrView&, Sub, const double*, double*, 
                                    const CgBufs<double>&, hipStream_t, int32_t*, CgResult&, Prof*, const double*);
 template hipError_t cg_run<float>(const CsrView&, Sub, const float*, float*, double, int, double, double, int,
                                   const CgBufs<float>&, hipStream_t, int32_t*, CgResult&, Prof*, const double*);
+
+// ------------------------------------------------------ block BiCGStab --
+BcBufs carve_bc(Carver& c, int64_t n, Sub sub, int hist_cap, uint32_t* cnt) {
+  const int s = sub.s;
+  const int nblk = stream_grid(n, s, sizeof(double));
+  const size_t blk = (size_t)n * s;
+  BcBufs b;
+  b.P = c.take<double>(blk);
+  b.Pn = c.take<double>(blk);
+  b.W2 = c.take<double>(2 * blk);
+  b.W3 = c.take<double>(3 * blk);
+  b.partial = c.take<double>((size_t)3 * nblk * s * s);
+  b.gpart = c.take<double>(3 * red_gpart_count(nblk, s));
+  b.G = c.take<double>((size_t)3 * s * s);
+  b.Grr = c.take<double>((size_t)s * s);
+  b.hist = c.take<double>((size_t)(hist_cap > 0 ? hist_cap : 1));
+  b.ctl = c.take<CgCtl>(1);
+  b.aux = c.take<BcAux>(1);
+  b.tsqr_ws = c.take<char>(tsqr_workspace_bytes(n, sub));
+  b.cnt = cnt;
+  return b;
+}
+
+// One iteration of Algorithm "BBiCGStab with Adaptive Residual
+// Re-Orthonormalization" (Ch. 6) with M = I, as a sequence of launches that
+// all become no-ops once ctl->done is set:
+//   Q = A P; [Q^T R~0 | R^T R~0]; lambda, kappa_D test (bc_lambda);
+//   S = R - Q lambda; if the test fired: (S, gamma) = Norm_S(S), sigma =
+//   gamma sigma (T = S either way, M = I); U = A S;
+//   [S^T U | U^T U | R~0^T U]; omega, beta (bc_omega);
+//   X += P (lambda sigma_old) + S (omega sigma); R = S - omega U;
+//   R^T R and the stopping test (bc_stop); P' = R + P beta - Q (omega beta).
+// lambda sigma is formed before sigma changes, omega sigma after (the X
+// update by T carries the new transformation).
+hipError_t bc_run(const CsrView& A, Sub sub, const double* B, double* X, double tol, int maxit, double eta,
+                  int hist_cap, const BcBufs& b, hipStream_t st, int32_t* hflags, BcResult& res) {
+  const int64_t n = A.n;
+  const int s = sub.s;
+  const size_t blk = (size_t)n * s;
+  const int nblk = stream_grid(n, s, sizeof(double));
+  CgCtl* c = b.ctl;
+  BcAux* x = b.aux;
+  int32_t* done = &c->done;
+  double* Q = b.W2;
+  double* R = b.W2 + blk;
+  double* S = b.W3;
+  double* U = b.W3 + blk;
+  double* Rt = b.W3 + 2 * blk;
+  const Red red{b.G, b.gpart, b.cnt}, rrr{b.Grr, b.gpart, b.cnt};
+
+  CgCtl* h = reinterpret_cast<CgCtl*>(hflags + 64);
+  memset(h, 0, offsetof(CgCtl, r0n));
+  h->maxit = maxit;
+  h->s = s;
+  h->kind = sub.kind;
+  h->g = sub.g;
+  h->hist_cap = hist_cap;
+  h->tol = tol;
+  h->eta = eta;
+  h->sqrt_eps = sqrt(DBL_EPSILON);
+  BK_TRY(hipMemcpyAsync(c, h, offsetof(CgCtl, r0n), hipMemcpyHostToDevice, st));
+
+  // R0 = B - A X0 and its Gram; initial normalisation; P = R, R~0 = P
+  BK_TRY(launch_spmm<double>(A, s, X, R, B, 2, b.partial, nblk, rrr, &c->bad_index, nullptr, st));
+  BK_TRY(launch_cg_init(c, b.Grr, nullptr, st));
+  if (eta > 0.0) {
+    BK_TRY(tsqr_run<double>(n, sub, R, c->sigma, b.tsqr_ws, b.cnt, done, nullptr, st));
+    BK_TRY(launch_gram<double>(n, s, R, 1, R, b.partial, nblk, rrr, done, st));
+  }
+  BK_TRY(hipMemcpyAsync(b.P, R, sizeof(double) * blk, hipMemcpyDeviceToDevice, st));
+  BK_TRY(hipMemcpyAsync(Rt, R, sizeof(double) * blk, hipMemcpyDeviceToDevice, st));
+
+  const CgCtl* hc = reinterpret_cast<const CgCtl*>(hflags);
+  double* P = b.P;
+  double* Pn = b.Pn;
+  int batch = 4;
+  while (maxit > 0) {
+    for (int it = 0; it < batch; ++it) {
+      BK_TRY(launch_spmm<double>(A, s, P, Q, nullptr, 0, nullptr, nblk, red, &c->bad_index, done, st));
+      BK_TRY(launch_gram<double>(n, s, Q, 2, Rt, b.partial, nblk, red, done, st));  // Q^T R~0, R^T R~0
+      BK_TRY(launch_bc_lambda(c, x, s, b.G, b.Grr, st));
+      BK_TRY(launch_lincomb<double>(n, s, R, Q, x->neglam, nullptr, nullptr, S, done, st));
+      BK_TRY(tsqr_run<double>(n, sub, S, c->gamma, b.tsqr_ws, b.cnt, done, &c->fire, st));
+      BK_TRY(launch_bc_sigma(c, st));
+      BK_TRY(launch_spmm<double>(A, s, S, U, nullptr, 0, nullptr, nblk, red, &c->bad_index, done, st));
+      BK_TRY(launch_gram<double>(n, s, S, 3, U, b.partial, nblk, red, done, st));  // S^T U, U^T U, R~0^T U
+      BK_TRY(launch_bc_omega(c, x, b.G, st));
+      BK_TRY(launch_lincomb<double>(n, s, X, P, c->lamsig, S, x->omsig, X, done, st));
+      BK_TRY(launch_lincomb<double>(n, s, S, U, x->negomI, nullptr, nullptr, R, done, st));
+      BK_TRY(launch_gram<double>(n, s, R, 1, R, b.partial, nblk, rrr, done, st));
+      BK_TRY(launch_bc_stop(c, b.Grr, b.hist, st));
+      BK_TRY(launch_lincomb<double>(n, s, R, P, x->pbeta, Q, x->qbeta, Pn, done, st));
+      std::swap(P, Pn);
+    }
+    BK_TRY(hipMemcpyAsync(hflags, c, kCtlHeaderInts * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    BK_TRY(hipStreamSynchronize(st));
+    if (hc->done) break;
+    if (batch < 32) batch *= 2;
+  }
+  BK_TRY(hipMemcpyAsync(hflags, c, kCtlHeaderInts * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  BK_TRY(hipStreamSynchronize(st));
+  res.status = hc->status;
+  res.iters = hc->iters;
+  res.nreorth = hc->nreorth;
+  res.converged = hc->converged;
+  res.bad_index = hc->bad_index;
+  return hipSuccess;
+}
 
 // ------------------------------------------------------ true residuals --
 hipError_t true_relres(const CsrView& A, int s, const double* B, const double* X, double* R, double* partial,

@@ -109,6 +109,28 @@ struct GmResult {
 hipError_t gm_run(const CsrView& A, Sub sub, const double* B, double* X, double tol, int maxit, int m,
                   int hist_cap, const GmBufs& b, hipStream_t st, int32_t* hflags, GmResult& res);
 
+// ------------------------------------------------------ block BiCGStab --
+struct BcBufs {
+  double *P = nullptr, *Pn = nullptr;
+  double* W2 = nullptr;  // [Q | R]: 2 blocks
+  double* W3 = nullptr;  // [S | U | R~0]: 3 blocks
+  double *partial = nullptr, *gpart = nullptr, *G = nullptr, *Grr = nullptr, *hist = nullptr;
+  CgCtl* ctl = nullptr;
+  BcAux* aux = nullptr;
+  void* tsqr_ws = nullptr;
+  uint32_t* cnt = nullptr;
+};
+BcBufs carve_bc(Carver& c, int64_t n, Sub sub, int hist_cap, uint32_t* cnt);
+
+struct BcResult {
+  int status = 0, iters = 0, nreorth = 0, converged = 0, bad_index = 0;
+};
+
+// Block BiCGStab with adaptive residual re-orthonormalisation (FP64, M = I).
+// X holds X0 on entry.
+hipError_t bc_run(const CsrView& A, Sub sub, const double* B, double* X, double tol, int maxit, double eta,
+                  int hist_cap, const BcBufs& b, hipStream_t st, int32_t* hflags, BcResult& res);
+
 // True relative column residuals |B_i - A X_i| / r0n_i (FP64) into relres
 // (device); R (n x s), partial, gpart, G and scale_scratch are scratch.
 hipError_t true_relres(const CsrView& A, int s, const double* B, const double* X, double* R, double* partial,
