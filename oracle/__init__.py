@@ -24,7 +24,7 @@ _SRC = os.path.join(_HERE, "bkry_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 PARALLEL, GLOBAL, BLOCK, HYBRID = 0, 1, 2, 3
-KINDS = {"parallel": PARALLEL, "global": GLOBAL, "block": BLOCK, "hybrid": HYBRID}
+KINDS = {"parallel": PARALLEL, "global": GLOBAL, "block": BLOCK, "hybrid": HYBRID, "bglobal": 4}
 OK, NOT_CONVERGED, E_INVALID, E_BREAKDOWN, E_NONFINITE = 0, 1, -1, -2, -3
 
 

@@ -22,7 +22,7 @@
 #include <stdlib.h>
 #include <string.h>
 
-enum { OR_PARALLEL = 0, OR_GLOBAL = 1, OR_BLOCK = 2, OR_HYBRID = 3 };
+enum { OR_PARALLEL = 0, OR_GLOBAL = 1, OR_BLOCK = 2, OR_HYBRID = 3, OR_BGLOBAL = 4 };
 enum { OR_OK = 0, OR_NOT_CONVERGED = 1, OR_E_INVALID = -1, OR_E_BREAKDOWN = -2, OR_E_NONFINITE = -3 };
 
 typedef int64_t i64;
@@ -36,6 +36,7 @@ static int group_width(int s, int kind, int q) {
   switch (kind) {
     case OR_BLOCK: return s;
     case OR_HYBRID: return (q > 0 && s % q == 0) ? s / q : -1;
+    case OR_BGLOBAL: return (q > 0 && s % q == 0) ? s / q : -1;
     case OR_PARALLEL: return 1;
     case OR_GLOBAL: return 1;
     default: return -1;
@@ -85,7 +86,10 @@ void or_gram(i64 n, int s, const double* X, i64 ldx, const double* Y, i64 ldy, d
  *   hybrid:   only the q diagonal g x g blocks are kept;
  *   parallel: only the diagonal is kept;
  *   global:   (tr(X^T Y) / s) * I.  The printed definition has no 1/s; the
- *             normality axiom tr<X,Y> = <X,Y>_F requires it. */
+ *             normality axiom tr<X,Y> = <X,Y>_F requires it;
+ *   block-global (q groups of width g): the mean (1/q) sum_i X_i^T Y_i of
+ *             the diagonal g x g blocks, repeated on every diagonal block
+ *             (I_q (x) ...), per Definition "Relevant *-subalgebras". */
 void or_project(int s, int kind, int q, double* G) {
   int g = group_width(s, kind, q);
   if (kind == OR_GLOBAL) {
@@ -94,6 +98,19 @@ void or_project(int s, int kind, int q, double* G) {
     tr /= (double)s;
     for (int a = 0; a < s; ++a)
       for (int b = 0; b < s; ++b) G[a * s + b] = (a == b) ? tr : 0.0;
+    return;
+  }
+  if (kind == OR_BGLOBAL) {
+    /* block-global: (1/q) sum_i X_i^T Y_i on every diagonal g x g block */
+    double avg[64 * 64];
+    for (int a = 0; a < g; ++a)
+      for (int b = 0; b < g; ++b) {
+        double acc = 0.0;
+        for (int grp = 0; grp < s / g; ++grp) acc += G[(grp * g + a) * s + grp * g + b];
+        avg[a * g + b] = acc / (double)(s / g);
+      }
+    for (int a = 0; a < s; ++a)
+      for (int b = 0; b < s; ++b) G[a * s + b] = (a / g == b / g) ? avg[(a % g) * g + b % g] : 0.0;
     return;
   }
   for (int a = 0; a < s; ++a)
@@ -179,6 +196,7 @@ int or_householder_qr(i64 m, int c, const double* X, i64 ldx, double* Q, i64 ldq
 /* rank-deficient ones.                                                      */
 /*   block:    N = R of the QR of X;                                         */
 /*   hybrid:   one QR per column group, N block diagonal;                    */
+/*   block-global: QR of the groups stacked vertically, N = I (x) rho/sqrt q;*/
 /*   parallel: N_jj = |x_j|, y_j = x_j / N_jj, and y_j = e_1 for x_j = 0;    */
 /*   global:   N = c I with c = |X|_F / sqrt(s), Y = X / c; for X = 0 the     */
 /*             columns of Y are e_1, ..., e_s.                               */
@@ -205,6 +223,29 @@ int or_normalize(i64 n, int s, int kind, int q, const double* X, double* Y, doub
     for (int j = 0; j < s; ++j) N[j * s + j] = c;
     for (i64 i = 0; i < n; ++i)
       for (int j = 0; j < s; ++j) Y[i * s + j] = (c > 0.0) ? X[i * s + j] / c : (i == j ? 1.0 : 0.0);
+    return OR_OK;
+  }
+  if (kind == OR_BGLOBAL) {
+    /* QR of the stacked [X_1; ...; X_q] (qn x g) = Y~ rho, N = I (x) rho/sqrt(q),
+     * Y_i = sqrt(q) Y~_i (the block-global example of Ch. 3) */
+    const int nq = s / g;
+    double* Xs = (double*)malloc(sizeof(double) * (size_t)(n * s));
+    double* Qs = (double*)malloc(sizeof(double) * (size_t)(n * s));
+    double* Rs = (double*)malloc(sizeof(double) * (size_t)(g * g));
+    if (!Xs || !Qs || !Rs) { free(Xs); free(Qs); free(Rs); return OR_E_INVALID; }
+    for (int grp = 0; grp < nq; ++grp)
+      for (i64 i = 0; i < n; ++i)
+        for (int j = 0; j < g; ++j) Xs[((i64)grp * n + i) * g + j] = X[i * s + grp * g + j];
+    int st = or_householder_qr(n * nq, g, Xs, g, Qs, g, Rs);
+    if (st != OR_OK) { free(Xs); free(Qs); free(Rs); return st; }
+    const double rq = sqrt((double)nq);
+    for (int grp = 0; grp < nq; ++grp) {
+      for (i64 i = 0; i < n; ++i)
+        for (int j = 0; j < g; ++j) Y[i * s + grp * g + j] = rq * Qs[((i64)grp * n + i) * g + j];
+      for (int a = 0; a < g; ++a)
+        for (int b = 0; b < g; ++b) N[(grp * g + a) * s + grp * g + b] = Rs[a * g + b] / rq;
+    }
+    free(Xs); free(Qs); free(Rs);
     return OR_OK;
   }
   double* Qg = (double*)malloc(sizeof(double) * (size_t)(n * g));
@@ -492,7 +533,7 @@ int or_bcg(i64 n, const int32_t* rowptr, const int32_t* colind, const double* va
       nro++;
       mm(s, gamma, sigma, tmp);                       /* sigma = gamma sigma */
       memcpy(sigma, tmp, ss * sizeof(double));
-      if (kind != OR_GLOBAL) {
+      if (kind != OR_GLOBAL && kind != OR_BGLOBAL) {
         for (int i = 0; i < s; ++i) {
           double acc = 0.0;
           for (int a = 0; a < s; ++a) acc += sigma[a * s + i] * sigma[a * s + i];
@@ -888,7 +929,7 @@ int or_bgmres(i64 n, const int32_t* rowptr, const int32_t* colind, const double*
       kend = k + 1;
       const double* sk = sig + (size_t)(k + 1) * ss;
       double meas;
-      if (kind == OR_GLOBAL) {
+      if (kind == OR_GLOBAL || kind == OR_BGLOBAL) {
         double f = 0.0;
         for (size_t t = 0; t < ss; ++t) f += sk[t] * sk[t];
         meas = sqrt(f) / r0F;

@@ -14,6 +14,15 @@ def subalgebra_basis(s, kind, q=1):
         return [np.eye(s)]
     if kind == "parallel":
         return [np.diag(np.eye(s)[i]) for i in range(s)]
+    if kind == "bglobal":
+        g = s // q
+        out = []
+        for a in range(g):
+            for b in range(g):
+                E = np.zeros((g, g))
+                E[a, b] = 1.0
+                out.append(np.kron(np.eye(q), E))
+        return out
     g = s if kind == "block" else s // q
     out = []
     for a in range(s):

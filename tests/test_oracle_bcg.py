@@ -17,7 +17,7 @@ import workloads as W
 from krylov_ref import (energy_fro, galerkin_minimiser, galerkin_minimiser_prec, laplace2d_eigpair,
                         laplace2d_extremes, textbook_cg)
 
-SUBALGS = [("block", 1), ("hybrid", 2), ("parallel", 1), ("global", 1)]
+SUBALGS = [("block", 1), ("hybrid", 2), ("parallel", 1), ("global", 1), ("bglobal", 2)]
 
 
 def small_problem(n_grid=6, s=4, seed=0):
@@ -77,7 +77,7 @@ def test_bcg_hybrid_is_independent_block_solves(orc):
 @pytest.mark.parametrize("s", [1, 2, 4])
 @pytest.mark.parametrize("kind,q", SUBALGS)
 def test_bcg_matches_dense_solution(orc, kind, q, s):
-    if kind == "hybrid" and s % 2:
+    if kind in ("hybrid", "bglobal") and s % 2:
         pytest.skip("q must divide s")
     grid = small_problem(n_grid=7, s=s, seed=s)
     A2 = W.random_spd_csr(60, 0.1, seed=s, shift=1.0)
@@ -298,3 +298,38 @@ def test_pbcg_exact_preconditioner_converges_in_one_step(orc):
         r = orc.bcg(A, B, kind=kind, q=q, tol=1e-12, maxit=5, minv=1.0 / d)
         assert r["converged"] and r["iters"] == 1
         assert np.allclose(r["X"], B / d[:, None], rtol=1e-12, atol=0)
+
+
+# --------------------------------------------------- block-global subalgebra --
+def test_block_global_inner_product_and_normaliser(orc):
+    """S_BG(q) (Definition "Relevant *-subalgebras", Ch. 3): <X, Y> =
+    (1/q) sum_i I_q (x) X_i^T Y_i; the normaliser is the QR of the stacked
+    groups, N = I_q (x) rho / sqrt(q), Y = sqrt(q) Y~ (example "Normalizer in
+    the block-global *-subalgebra"), checked against numpy's QR."""
+    X = W.gaussian_block(300, 8, 31)
+    Y = W.gaussian_block(300, 8, 32)
+    for q in (2, 4):
+        g = 8 // q
+        mean = sum(X[:, i * g:(i + 1) * g].T @ Y[:, i * g:(i + 1) * g] for i in range(q)) / q
+        assert np.allclose(orc.bdot(X, Y, "bglobal", q), np.kron(np.eye(q), mean), rtol=1e-13, atol=1e-13)
+        Yn, N = orc.normalize(X, "bglobal", q)
+        stacked = np.vstack([X[:, i * g:(i + 1) * g] for i in range(q)])
+        _, rho = np.linalg.qr(stacked)
+        rho = rho * np.sign(np.diag(rho))[:, None]
+        assert np.allclose(N, np.kron(np.eye(q), rho / np.sqrt(q)), rtol=1e-12, atol=1e-12)
+        assert np.allclose(orc.bdot(Yn, Yn, "bglobal", q), np.eye(8), atol=1e-13)
+        assert np.allclose(Yn @ N, X, atol=1e-12)
+
+
+def test_block_global_lattice(orc):
+    """S_G subset S_BG(q) subset S_B (Lemma "Embeddings of *-subalgebras"):
+    the block Krylov spaces are nested, so the energy errors at equal k are
+    ordered global >= block-global >= block."""
+    A, D, B = small_problem(n_grid=8, s=8, seed=5)
+    Xs = np.linalg.solve(D, B)
+    for k in (2, 4, 6):
+        e = {}
+        for kind, q in (("global", 1), ("bglobal", 2), ("block", 1)):
+            r = orc.bcg(A, B, kind=kind, q=q, tol=0.0, maxit=k, eta=np.inf)
+            e[kind] = energy_fro(D, r["X"] - Xs)
+        assert e["global"] >= e["bglobal"] * (1 - 1e-10) >= e["block"] * (1 - 1e-10), (k, e)

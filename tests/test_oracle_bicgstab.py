@@ -15,7 +15,7 @@ from scipy.sparse.linalg import bicgstab
 
 import workloads as W
 
-SUBALGS = [("block", 1), ("hybrid", 2), ("parallel", 1), ("global", 1)]
+SUBALGS = [("block", 1), ("hybrid", 2), ("parallel", 1), ("global", 1), ("bglobal", 2)]
 
 
 def test_lu_solve_matches_numpy(orc):
