@@ -52,11 +52,17 @@ extern "C" {
  *   BKRY_GLOBAL    multiples of I, <X,Y> = tr(X^T Y)/p * I;
  *   BKRY_BLOCK     all p x p matrices, <X,Y> = X^T Y;
  *   BKRY_HYBRID    block-parallel with q contiguous column groups of width p/q,
- *                  <X,Y> = blockdiag(X_1^T Y_1, ..., X_q^T Y_q).            */
+ *                  <X,Y> = blockdiag(X_1^T Y_1, ..., X_q^T Y_q);
+ *   BKRY_BLOCK_GLOBAL  block-global, q contiguous column groups of width g = p/q,
+ *                  <X,Y> = I_q (x) (1/q) sum_i X_i^T Y_i; its normaliser is the
+ *                  QR of the stacked [X_1; ...; X_q] = Q rho with Y_i = sqrt(q) Q_i
+ *                  and N = I_q (x) rho / sqrt(q).  q = 1 is BKRY_BLOCK and q = p
+ *                  is BKRY_GLOBAL (the call runs those).                     */
 #define BKRY_PARALLEL 0
 #define BKRY_GLOBAL 1
 #define BKRY_BLOCK 2
 #define BKRY_HYBRID 3
+#define BKRY_BLOCK_GLOBAL 4
 
 /* arithmetic of a CG solve */
 #define BKRY_F64 0    /* everything in FP64 */
@@ -67,8 +73,9 @@ extern "C" {
 typedef struct bkry_handle_s* bkry_handle;
 
 typedef struct {
-  int32_t kind; /* BKRY_PARALLEL / GLOBAL / BLOCK / HYBRID */
-  int32_t q;    /* number of column groups for BKRY_HYBRID (p % q == 0); ignored otherwise */
+  int32_t kind; /* BKRY_PARALLEL / GLOBAL / BLOCK / HYBRID / BLOCK_GLOBAL */
+  int32_t q;    /* number of column groups for BKRY_HYBRID and BKRY_BLOCK_GLOBAL (p % q == 0);
+                   ignored otherwise */
 } bkry_subalg;
 
 typedef struct {

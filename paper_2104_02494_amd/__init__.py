@@ -24,8 +24,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("BKRY_LIB") or os.path.join(_HERE, "libbkry.so")
 
 OK, NOT_CONVERGED, E_INVALID, E_BREAKDOWN, E_NONFINITE, E_HIP, E_ALLOC = 0, 1, -1, -2, -3, -4, -5
-PARALLEL, GLOBAL, BLOCK, HYBRID = 0, 1, 2, 3
-KINDS = {"parallel": PARALLEL, "global": GLOBAL, "block": BLOCK, "hybrid": HYBRID}
+PARALLEL, GLOBAL, BLOCK, HYBRID, BLOCK_GLOBAL = 0, 1, 2, 3, 4
+KINDS = {"parallel": PARALLEL, "global": GLOBAL, "block": BLOCK, "hybrid": HYBRID, "bglobal": BLOCK_GLOBAL}
 F64, F32_IR = 0, 1
 _CODES = {E_INVALID: "invalid argument", E_BREAKDOWN: "breakdown", E_NONFINITE: "non-finite",
           E_HIP: "HIP error", E_ALLOC: "allocation failure"}

@@ -91,6 +91,12 @@ int check_sub(bkry_handle h, int32_t p, bkry_subalg S, Sub& sub) {
       if (S.q < 1 || p % S.q != 0) return fail(h, BKRY_E_INVALID, "hybrid subalgebra needs q >= 1 dividing p");
       sub.g = p / S.q;
       break;
+    case BKRY_BLOCK_GLOBAL:
+      if (S.q < 1 || p % S.q != 0) return fail(h, BKRY_E_INVALID, "block-global subalgebra needs q >= 1 dividing p");
+      sub.g = p / S.q;
+      // one group is the block subalgebra, groups of one column the global one
+      sub.kind = sub.g == p ? BLOCK : (sub.g == 1 ? GLOBAL : BGLOBAL);
+      break;
     default: return fail(h, BKRY_E_INVALID, "unknown subalgebra kind");
   }
   return BKRY_OK;
@@ -373,8 +379,8 @@ int bkry_tsqr(bkry_handle h, int64_t n, int32_t p, bkry_subalg S, double* X, dou
   int rc = begin(h);
   Sub sub;
   if (!rc) rc = check_sub(h, p, S, sub);
-  if (!rc && (n < sub.g || (S.kind == BKRY_GLOBAL && n < p)))
-    rc = fail(h, BKRY_E_INVALID, "the normaliser needs n >= p (block, global) or n >= p/q (hybrid)");
+  if (!rc && (n < sub.g || (sub.kind == GLOBAL && n < p)))
+    rc = fail(h, BKRY_E_INVALID, "the normaliser needs n >= p (block, global) or n >= p/q (hybrid, block-global)");
   if (!rc) rc = check_blocks(h, {X});
   if (!rc && !R) rc = fail(h, BKRY_E_INVALID, "null R");
   if (rc) return rc;
@@ -397,7 +403,7 @@ int cg_solve_impl(bkry_handle h, const bkry_csr* A, int32_t p, bkry_subalg S, co
   if (!rc && maxit < 0) rc = fail(h, BKRY_E_INVALID, "maxit must be >= 0");
   if (!rc && !(eta >= 0.0)) rc = fail(h, BKRY_E_INVALID, "eta must be >= 0");
   if (!rc && prec != BKRY_F64 && prec != BKRY_F32_IR) rc = fail(h, BKRY_E_INVALID, "unknown precision");
-  if (!rc && eta > 0.0 && (A->n < sub.g || (S.kind == BKRY_GLOBAL && A->n < p)))
+  if (!rc && eta > 0.0 && (A->n < sub.g || (sub.kind == GLOBAL && A->n < p)))
     rc = fail(h, BKRY_E_INVALID, "re-orthonormalisation needs n >= p (block, global) or n >= p/q (hybrid)");
   if (rc) return rc;
   const double t0 = now_s();
@@ -617,7 +623,7 @@ int bkry_bicgstab_solve(bkry_handle h, const bkry_csr* A, int32_t p, bkry_subalg
   if (!rc && !(tol >= 0.0)) rc = fail(h, BKRY_E_INVALID, "tol must be >= 0");
   if (!rc && maxit < 0) rc = fail(h, BKRY_E_INVALID, "maxit must be >= 0");
   if (!rc && !(eta >= 0.0)) rc = fail(h, BKRY_E_INVALID, "eta must be >= 0");
-  if (!rc && (A->n < sub.g || (S.kind == BKRY_GLOBAL && A->n < p)))
+  if (!rc && (A->n < sub.g || (sub.kind == GLOBAL && A->n < p)))
     rc = fail(h, BKRY_E_INVALID, "block BiCGStab needs n >= p (block, global) or n >= p/q (hybrid)");
   if (rc) return rc;
   const double t0 = now_s();

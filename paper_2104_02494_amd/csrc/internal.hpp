@@ -12,11 +12,12 @@ namespace bkry {
 constexpr int kMaxS = 32;
 constexpr int kBlock = 256;  // threads per workgroup of the streaming kernels
 
-enum Kind { PARALLEL = 0, GLOBAL = 1, BLOCK = 2, HYBRID = 3 };
+enum Kind { PARALLEL = 0, GLOBAL = 1, BLOCK = 2, HYBRID = 3, BGLOBAL = 4 };
 
-// Subalgebra in the library's terms: group width g (block: s, hybrid: s/q,
-// parallel and global: 1) plus the kind (global differs from parallel only in
-// the projection and the normaliser).
+// Subalgebra in the library's terms: group width g (block: s, hybrid and
+// block-global: s/q, parallel and global: 1) plus the kind (global differs
+// from parallel, and block-global from hybrid, only in the projection and the
+// normaliser).
 struct Sub {
   int kind;
   int s;
@@ -227,6 +228,9 @@ hipError_t launch_cg_init(CgCtl* ctl, const double* G_R0, const double* G_rho, h
 hipError_t launch_cg_reortho_fin(CgCtl* ctl, int s, const double* G, hipStream_t st);
 // Normaliser coefficients for parallel / global: from the Gram G of X, write
 // the column divisors d and N (p x p) to `out_N` (gated like the CG kernels).
+// N = I_q (x) rho / sqrt(q) from the g x g rho; d[j] = 1/sqrt(q).
+hipError_t launch_bg_expand(const double* rho, Sub sub, double* N, double* d, const int32_t* gate_done,
+                            const int32_t* gate_fire, hipStream_t st);
 hipError_t launch_norm_diag(const double* G, Sub sub, double* d, double* out_N, const int32_t* gate_done,
                             const int32_t* gate_fire, hipStream_t st);
 

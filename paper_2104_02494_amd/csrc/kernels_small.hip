@@ -62,11 +62,38 @@ __device__ __forceinline__ void sm_eye(double* M, int s) {
 }
 
 // Projection onto the subalgebra (zero outside the g x g diagonal blocks;
-// global: tr/s * I).
+// global: tr/s * I; block-global: the mean of the q diagonal blocks on every
+// diagonal block).
 __device__ __forceinline__ void sm_project(double* M, const Sub& sub, double* scratch1) {
   const int s = sub.s;
   __syncthreads();
-  if (sub.kind == GLOBAL) {
+  if (sub.kind == BGLOBAL) {
+    // g <= s/2 <= 16: each lane owns at most 256/kSB entries of the g x g mean
+    constexpr int kPer = (kMaxS / 2) * (kMaxS / 2) / kSB;
+    const int g = sub.g, q = s / g;
+    double v[kPer];
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int e = tid() + u * kSB;
+      double acc = 0.0;
+      if (e < g * g) {
+        const int a = e / g, b = e % g;
+        for (int k = 0; k < q; ++k) acc += M[(k * g + a) * s + k * g + b];
+      }
+      v[u] = acc / (double)q;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int e = tid() + u * kSB;
+      if (e < g * g) {
+        const int a = e / g, b = e % g;
+        for (int k = 0; k < q; ++k) M[(k * g + a) * s + k * g + b] = v[u];
+      }
+    }
+    for (int t = tid(); t < s * s; t += kSB)
+      if ((t / s) / g != (t % s) / g) M[t] = 0.0;
+  } else if (sub.kind == GLOBAL) {
     double d = 0.0;
     for (int a = tid(); a < s; a += kSB) d += M[a * s + a];
     const double v = wsum(d) / (double)s;
@@ -1195,6 +1222,28 @@ hipError_t launch_norm_diag(const double* G, Sub sub, double* d, double* out_N, 
   return hipGetLastError();
 }
 
+// Block-global normaliser from the R factor rho (g x g) of the stacked
+// groups: N = I_q (x) rho / sqrt(q), and d[j] = 1/sqrt(q) (the column divisor
+// that turns the stacked Q into Y = sqrt(q) Q).
+__global__ __launch_bounds__(kSB) void bg_expand_kernel(const double* rho, Sub sub, double* N, double* d,
+                                                        const int32_t* gd, const int32_t* gf) {
+  if (gd && *gd) return;
+  if (gf && !*gf) return;
+  const int s = sub.s, g = sub.g;
+  const double rq = sqrt((double)(s / g));
+  for (int t = tid(); t < s * s; t += kSB) {
+    const int i = t / s, j = t % s;
+    N[t] = (i / g == j / g) ? rho[(i % g) * g + j % g] / rq : 0.0;
+  }
+  for (int j = tid(); j < s; j += kSB) d[j] = 1.0 / rq;
+}
+
+hipError_t launch_bg_expand(const double* rho, Sub sub, double* N, double* d, const int32_t* gate_done,
+                            const int32_t* gate_fire, hipStream_t st) {
+  hipLaunchKernelGGL(bg_expand_kernel, dim3(1), dim3(kSB), 0, st, rho, sub, N, d, gate_done, gate_fire);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ GMRes --
 // Full QR of the rows x cols matrix M (row stride cols, rows <= 64) by
 // Householder reflections: R in the upper triangle of M, the full rows x rows
@@ -1429,7 +1478,7 @@ __global__ __launch_bounds__(kSB) void gm_step_kernel(GmCtl* c, int k, double* H
     const double* sk = sig + (int64_t)(k + 1) * ss;
     double meas = 0.0;
     bool nan = false;
-    if (c->kind == GLOBAL) {
+    if (c->kind == GLOBAL || c->kind == BGLOBAL) {
       double f = 0.0;
       for (int t = 0; t < ss; ++t) f += sk[t] * sk[t];
       meas = sqrt(f) / c->r0F;

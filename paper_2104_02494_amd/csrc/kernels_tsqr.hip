@@ -339,7 +339,12 @@ size_t cholqr_ws(int64_t n, const Sub& sub) {
          4 * align256(sizeof(double) * s * s) + align256(4 * sizeof(int32_t));
 }
 
+// Block-global: rho (g x g) and the column divisors ahead of the workspace of
+// the block normaliser of the (n q) x g stacked view.
+static size_t bg_head(const Sub& sub) { return align256(sizeof(double) * sub.g * sub.g) + align256(sizeof(double) * sub.s); }
+
 size_t tsqr_workspace_bytes(int64_t n, Sub sub) {
+  if (sub.kind == BGLOBAL) return bg_head(sub) + tsqr_workspace_bytes(n * (sub.s / sub.g), Sub{BLOCK, sub.g, sub.g});
   if (uses_norms(sub)) return norms_ws<double>(n, sub);
   size_t a = cholqr_ws<double>(n, sub) + make_plan<double>(n, sub).total;
   size_t b = cholqr_ws<float>(n, sub) + make_plan<float>(n, sub).total;
@@ -388,6 +393,19 @@ hipError_t tsqr_run(int64_t n, Sub sub, T* X, double* N, void* ws, uint32_t* cnt
                     const int32_t* gf, hipStream_t st) {
   char* w = static_cast<char*>(ws);
   const int s = sub.s;
+  if (sub.kind == BGLOBAL) {
+    // Row r of the n x s row-major block, cut into q rows of width g, is row r
+    // of every group X_1, ..., X_q: the buffer read as (n q) x g is a row
+    // permutation of the stacked [X_1; ...; X_q], whose QR (Q rho) has the
+    // same rho and the rows of Q permuted alike.  Y = sqrt(q) Q.
+    const int g = sub.g, q = s / g;
+    double* rho = reinterpret_cast<double*>(w);
+    double* d = reinterpret_cast<double*>(w + align256(sizeof(double) * g * g));
+    hipError_t e = tsqr_run<T>(n * q, Sub{BLOCK, g, g}, X, rho, w + bg_head(sub), cnt, gd, gf, st);
+    if (e == hipSuccess) e = launch_bg_expand(rho, sub, N, d, gd, gf, st);
+    if (e == hipSuccess) e = launch_colscale<T>(n, s, X, X, d, 0, gd, gf, st);
+    return e;
+  }
   if (uses_norms(sub)) {
     const int nblk = stream_grid(n, s, sizeof(T));
     T* part = reinterpret_cast<T*>(w);

@@ -14,7 +14,7 @@ from gpu_util import dev_csr, h, rel, say, to_dev, to_np  # noqa: F401
 pytestmark = pytest.mark.gpu
 P = pytest.importorskip("paper_2104_02494_amd")
 
-SUBS = [("block", 1), ("hybrid", 2), ("parallel", 1), ("global", 1)]
+SUBS = [("block", 1), ("hybrid", 2), ("parallel", 1), ("global", 1), ("bglobal", 2)]
 
 
 def gpu_bc(h, A, B, X0=None, **kw):
@@ -26,7 +26,7 @@ def gpu_bc(h, A, B, X0=None, **kw):
 @pytest.mark.parametrize("kind,q", SUBS)
 @pytest.mark.parametrize("eta", [0.0, np.inf])
 def test_bicgstab_fixed_iterations(orc, h, s, kind, q, eta):
-    if kind == "hybrid" and s % 2:
+    if kind in ("hybrid", "bglobal") and s % q:
         pytest.skip("q must divide s")
     A = W.convdiff_2d(40)                     # n = 1600: several tiles and a ragged tail
     B = W.gaussian_block(A.n, s, 70 + s)

@@ -15,7 +15,7 @@ from gpu_util import dev_csr, h, rel, say, to_dev, to_np  # noqa: F401
 pytestmark = pytest.mark.gpu
 P = pytest.importorskip("paper_2104_02494_amd")
 
-SUBS = [("block", 1), ("hybrid", 2), ("parallel", 1), ("global", 1)]
+SUBS = [("block", 1), ("hybrid", 2), ("parallel", 1), ("global", 1), ("bglobal", 2)]
 
 
 def gpu_cg(h, A, B, X0=None, **kw):
@@ -42,10 +42,10 @@ def test_cg_poisson32_full_solve(orc, h, kind, q, eta):
 
 
 @pytest.mark.parametrize("s", [1, 2, 3, 4, 5, 8, 16, 32])
-@pytest.mark.parametrize("kind,q", [("block", 1), ("parallel", 1), ("hybrid", 2)])
+@pytest.mark.parametrize("kind,q", [("block", 1), ("parallel", 1), ("hybrid", 2), ("bglobal", 2)])
 @pytest.mark.parametrize("eta", [0.0, np.inf])
 def test_cg_widths_fixed_iterations(orc, h, s, kind, q, eta):
-    if kind == "hybrid" and s % 2:
+    if kind in ("hybrid", "bglobal") and s % q:
         pytest.skip("q must divide s")
     A = W.laplace_2d(41)                    # n = 1681: several tiles and a ragged tail
     B = W.uniform_block(A.n, s, s)

@@ -14,7 +14,7 @@ from gpu_util import dev_csr, h, rel, say, to_dev, to_np  # noqa: F401
 pytestmark = pytest.mark.gpu
 P = pytest.importorskip("paper_2104_02494_amd")
 
-SUBS = [("block", 1), ("hybrid", 2), ("parallel", 1), ("global", 1)]
+SUBS = [("block", 1), ("hybrid", 2), ("parallel", 1), ("global", 1), ("bglobal", 2)]
 
 
 def gpu_gm(h, A, B, **kw):

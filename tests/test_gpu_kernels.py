@@ -12,7 +12,7 @@ from gpu_util import EPS, EPS32, dev_csr, gram_bound, h, rel, say, spmm_bound, t
 pytestmark = pytest.mark.gpu
 P = pytest.importorskip("paper_2104_02494_amd")
 
-SUBS = [("block", 1), ("hybrid", 2), ("parallel", 1), ("global", 1)]
+SUBS = [("block", 1), ("hybrid", 2), ("parallel", 1), ("global", 1), ("bglobal", 2)]
 WIDTHS = [1, 2, 3, 4, 5, 8, 16, 32]
 
 
@@ -59,7 +59,7 @@ def test_spmm_bad_index_reported(h):
 @pytest.mark.parametrize("s", WIDTHS)
 @pytest.mark.parametrize("kind,q", SUBS)
 def test_bdot(orc, h, s, kind, q):
-    if kind == "hybrid" and s % 2:
+    if kind in ("hybrid", "bglobal") and s % q:
         pytest.skip("q must divide s")
     n = 70_001
     X = W.gaussian_block(n, s, 1)
@@ -128,7 +128,7 @@ def test_matrix_core_widths(orc, h, s):
     Qo, Ro = orc.householder_qr(X)
     assert rel(R, Ro) < 1e-12 and rel(Q, Qo) < 1e-12
     assert np.abs(Q.T @ Q - np.eye(s)).max() < 1e-13
-    for kind, q in (("hybrid", 2), ("hybrid", 4)) if s % 4 == 0 else ():
+    for kind, q in (("hybrid", 2), ("hybrid", 4), ("bglobal", 2), ("bglobal", 4)) if s % 4 == 0 else ():
         say("matrix cores: tsqr", kind, q, s)
         Xd = to_dev(X)
         N = to_np(P.bkry_tsqr(h, Xd, kind, q))
@@ -136,7 +136,7 @@ def test_matrix_core_widths(orc, h, s):
         assert rel(N, No) < 1e-12 and rel(to_np(Xd), Yo) < 1e-12
 
 
-@pytest.mark.parametrize("kind,q", SUBS + [("hybrid", 4)])
+@pytest.mark.parametrize("kind,q", SUBS + [("hybrid", 4), ("bglobal", 4), ("bglobal", 8)])
 def test_tsqr_subalgebras(orc, h, kind, q):
     n, s = 50_000, 8
     X = W.gaussian_block(n, s, 4)

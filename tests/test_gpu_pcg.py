@@ -16,7 +16,7 @@ from gpu_util import dev_csr, h, rel, say, to_dev, to_np  # noqa: F401
 pytestmark = pytest.mark.gpu
 P = pytest.importorskip("paper_2104_02494_amd")
 
-SUBS = [("block", 1), ("hybrid", 2), ("parallel", 1), ("global", 1)]
+SUBS = [("block", 1), ("hybrid", 2), ("parallel", 1), ("global", 1), ("bglobal", 2)]
 
 
 def _diag(A):
@@ -58,7 +58,7 @@ def test_jacobi_minv(h):
 @pytest.mark.parametrize("kind,q", SUBS)
 @pytest.mark.parametrize("eta", [0.0, np.inf])
 def test_pcg_fixed_iterations(orc, h, s, kind, q, eta):
-    if kind == "hybrid" and s % 2:
+    if kind in ("hybrid", "bglobal") and s % q:
         pytest.skip("q must divide s")
     A = W.diffusion_7pt_var(12, seed=8)       # n = 1728: several tiles and a ragged tail
     minv = jacobi(A)
