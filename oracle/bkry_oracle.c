@@ -572,6 +572,125 @@ done:
 }
 
 /* ------------------------------------------------------------------------ */
+/* Block CG with one reduction per iteration (alg:1R-CG, Ch. 8, "Fusing      */
+/* Inner Block Products"): the auxiliary block U = A Z is formed right after */
+/* the preconditioner, Q = A P is carried by the recursion Q = U + Q beta,   */
+/* and alpha by alpha' = delta - beta^T alpha beta with delta = <Z, U>_S     */
+/* (the derivation around eq. alpha_k+1), so rho', delta and the residual    */
+/* norm can share one reduction.  In exact arithmetic the iterates are those */
+/* of alg:bcgaro.  Same arguments, outputs and stopping test as or_bcg (the  */
+/* column norms after a re-normalisation, and all norms of the global and    */
+/* block-global subalgebras, as there).                                      */
+/* ------------------------------------------------------------------------ */
+int or_bcg1r(i64 n, const int32_t* rowptr, const int32_t* colind, const double* val, int s, int kind, int q,
+             const double* B, double* X, double tol, int maxit, double eta, double eps, int32_t* info,
+             double* relres, double* hist, int hist_cap, const double* minv) {
+  if (!valid_subalg(s, kind, q) || s > 64 || n < group_width(s, kind, q)) return OR_E_INVALID;
+  size_t blk = (size_t)(n * s);
+  double* R = (double*)calloc(blk, sizeof(double));
+  double* P = (double*)calloc(blk, sizeof(double));
+  double* Qb = (double*)calloc(blk, sizeof(double));
+  double* Z = (double*)calloc(blk, sizeof(double));
+  double* U = (double*)calloc(blk, sizeof(double));
+  double* T = (double*)calloc(blk, sizeof(double));
+  if (!R || !P || !Qb || !Z || !U || !T) {
+    free(R); free(P); free(Qb); free(Z); free(U); free(T);
+    return OR_E_INVALID;
+  }
+  size_t ss = (size_t)s * s;
+  double sigma[64 * 64], alpha[64 * 64], rho[64 * 64], rho_new[64 * 64], delta[64 * 64], lambda[64 * 64];
+  double gamma[64 * 64], beta[64 * 64], tmp[64 * 64], tmp2[64 * 64], lamsig[64 * 64];
+  double r0n[64], cn[64], rel[64];
+  int st = OR_OK, iters = 0, nro = 0, conv = 0;
+
+  or_residual(n, rowptr, colind, val, s, B, X, R);
+  column_norms(n, s, R, r0n);
+  for (int i = 0; i < s; ++i) rel[i] = (r0n[i] > 0.0) ? 1.0 : 0.0;
+  {
+    int allzero = 1;
+    for (int i = 0; i < s; ++i) allzero &= (r0n[i] == 0.0);
+    if (allzero) {
+      conv = 1;
+      for (int i = 0; i < s; ++i) rel[i] = 0.0;
+      goto done;
+    }
+  }
+  if (eta > 0.0) {
+    st = or_normalize(n, s, kind, q, R, R, sigma);
+    if (st != OR_OK) goto done;
+    nro++;
+  } else {
+    eye(s, sigma);
+  }
+  apply_minv(n, s, minv, R, P);                       /* P^0 = M^-1 R-bar^0 */
+  or_bdot(n, s, kind, q, P, R, rho);                  /* rho^0 = <P^0, R-bar^0>_S */
+  or_spmm(n, rowptr, colind, val, s, P, Qb);          /* Q^0 = A P^0 */
+  or_bdot(n, s, kind, q, P, Qb, alpha);               /* alpha^0 = <P^0, Q^0>_S */
+
+  for (int k = 0; k < maxit; ++k) {
+    for (size_t t = 0; t < ss; ++t)
+      if (!isfinite(alpha[t])) { st = OR_E_NONFINITE; goto done; }
+    st = or_chol_solve(s, kind, q, alpha, rho, lambda); /* lambda = alpha^-1 rho */
+    if (st != OR_OK) goto done;
+    block_axmy(n, s, Qb, lambda, R);                  /* R~ = R-bar - Q lambda */
+    mm(s, lambda, sigma, lamsig);                     /* lambda^k sigma^k (before sigma changes) */
+    iters = k + 1;
+    int fire = or_reortho_fires(eta, or_kappa_D(s, alpha), eps);
+    if (fire) {
+      st = or_normalize(n, s, kind, q, R, R, gamma);  /* (R-bar, gamma) = Norm_S(R~) */
+      if (st != OR_OK) goto done;
+      nro++;
+      mm(s, gamma, sigma, tmp);                       /* sigma = gamma sigma */
+      memcpy(sigma, tmp, ss * sizeof(double));
+      if (kind != OR_GLOBAL && kind != OR_BGLOBAL) {
+        for (int i = 0; i < s; ++i) {
+          double acc = 0.0;
+          for (int a = 0; a < s; ++a) acc += sigma[a * s + i] * sigma[a * s + i];
+          cn[i] = sqrt(acc);
+        }
+      } else {
+        memset(T, 0, blk * sizeof(double));
+        block_axpy(n, s, R, sigma, T);
+        column_norms(n, s, T, cn);
+      }
+    } else {
+      eye(s, gamma);
+      memset(T, 0, blk * sizeof(double));
+      block_axpy(n, s, R, sigma, T);
+      column_norms(n, s, T, cn);
+    }
+    block_axpy(n, s, P, lamsig, X);                   /* X += P lambda sigma */
+    apply_minv(n, s, minv, R, Z);                     /* Z = M^-1 R-bar */
+    or_bdot(n, s, kind, q, Z, R, rho_new);            /* rho' = <Z, R-bar>_S */
+    or_spmm(n, rowptr, colind, val, s, Z, U);         /* U = A Z */
+    or_bdot(n, s, kind, q, Z, U, delta);              /* delta = <Z, U>_S */
+    double m = max_rel(s, cn, r0n, rel);
+    if (hist && k < hist_cap) hist[k] = m;
+    if (isnan(m)) { st = OR_E_NONFINITE; goto done; }
+    if (m <= tol) { conv = 1; break; }
+    mtm(s, gamma, rho_new, tmp);                      /* beta = rho^-1 gamma^T rho' */
+    st = or_chol_solve(s, kind, q, rho, tmp, beta);
+    if (st != OR_OK) goto done;
+    memcpy(T, Z, blk * sizeof(double));               /* P = Z + P beta */
+    block_axpy(n, s, P, beta, T);
+    memcpy(P, T, blk * sizeof(double));
+    memcpy(T, U, blk * sizeof(double));               /* Q = U + Q beta */
+    block_axpy(n, s, Qb, beta, T);
+    memcpy(Qb, T, blk * sizeof(double));
+    mm(s, alpha, beta, tmp);                          /* alpha = delta - beta^T alpha beta */
+    mtm(s, beta, tmp, tmp2);
+    for (size_t t = 0; t < ss; ++t) alpha[t] = delta[t] - tmp2[t];
+    memcpy(rho, rho_new, ss * sizeof(double));
+  }
+done:
+  if (info) { info[0] = iters; info[1] = nro; info[2] = conv; }
+  if (relres) for (int i = 0; i < s; ++i) relres[i] = rel[i];
+  free(R); free(P); free(Qb); free(Z); free(U); free(T);
+  if (st != OR_OK) return st;
+  return conv ? OR_OK : OR_NOT_CONVERGED;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Solve A X = B inside the subalgebra for a general (non-symmetric) A in S  */
 /* by Gaussian elimination with partial pivoting per S-block (the           */
 /* coefficient systems of block BiCGStab, Ch. 6).  A zero pivot is a         */
