@@ -187,6 +187,17 @@ int bkry_cg_solve(bkry_handle h, const bkry_csr* A, int32_t p, bkry_subalg S, co
 int bkry_pcg_solve(bkry_handle h, const bkry_csr* A, int32_t p, bkry_subalg S, const double* B, double* X,
                    const double* minv, double tol, int32_t maxit, double eta, bkry_info* info);
 
+/* Block CG with one reduction per iteration (Algorithm "BCG with One
+ * Reduction", Ch. 8): the same iteration as bkry_cg_solve in exact
+ * arithmetic, with U = A R-bar formed right after the residual update,
+ * Q = A P carried by Q = U + Q beta and alpha by alpha' = delta -
+ * beta^T alpha beta (delta = <R-bar, U>_S), so that the residual norms, rho
+ * and delta of an iteration share one reduction.  Needs two more n x p
+ * blocks of workspace than bkry_cg_solve.  FP64, M = I; arguments, stopping
+ * test, re-normalisation rule and info as bkry_cg_solve (prec is FP64). */
+int bkry_cg1r_solve(bkry_handle h, const bkry_csr* A, int32_t p, bkry_subalg S, const double* B, double* X,
+                    double tol, int32_t maxit, double eta, bkry_info* info);
+
 /* Jacobi preconditioner of bkry_pcg_solve: minv[i] = 1 / A_ii [device, n
  * doubles, caller-owned].  BKRY_E_INVALID if a row has no diagonal entry or
  * its diagonal is not positive and finite (duplicates are summed).

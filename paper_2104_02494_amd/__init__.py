@@ -58,7 +58,7 @@ class bkry_info(ctypes.Structure):
 EXPORTS = ["bkry_create", "bkry_destroy", "bkry_set_stream", "bkry_synchronize", "bkry_last_error",
            "bkry_profile", "bkry_profile_read", "bkry_set_spmm_format", "bkry_spmm",
            "bkry_spmm_f32", "bkry_bdot", "bkry_bdot_f32", "bkry_tsqr", "bkry_cg_solve", "bkry_pcg_solve",
-           "bkry_jacobi_minv", "bkry_bicgstab_solve", "bkry_gmres_solve", "bkry_sddmm", "bkry_csr_transpose"]
+           "bkry_cg1r_solve", "bkry_jacobi_minv", "bkry_bicgstab_solve", "bkry_gmres_solve", "bkry_sddmm", "bkry_csr_transpose"]
 
 _lib = None
 
@@ -89,6 +89,7 @@ def lib():
             "bkry_tsqr": [H, i64, i32, bkry_subalg, vp, vp],
             "bkry_cg_solve": [H, csr_p, i32, bkry_subalg, vp, vp, dbl, i32, dbl, i32, info_p],
             "bkry_pcg_solve": [H, csr_p, i32, bkry_subalg, vp, vp, vp, dbl, i32, dbl, info_p],
+            "bkry_cg1r_solve": [H, csr_p, i32, bkry_subalg, vp, vp, dbl, i32, dbl, info_p],
             "bkry_jacobi_minv": [H, csr_p, vp],
             "bkry_bicgstab_solve": [H, csr_p, i32, bkry_subalg, vp, vp, dbl, i32, dbl, info_p],
             "bkry_gmres_solve": [H, csr_p, i32, bkry_subalg, vp, vp, dbl, i32, i32, info_p],
@@ -267,6 +268,22 @@ def bkry_pcg_solve(h: Handle, A: CsrMatrix, B: torch.Tensor, minv: torch.Tensor,
                    kind="block", q=1, tol=1e-10, maxit=1000, eta=1e4, hist_cap=0):
     """Block CG with the diagonal preconditioner M^-1 = diag(minv) (FP64).  Returns (X, info)."""
     return bkry_cg_solve(h, A, B, X, kind=kind, q=q, tol=tol, maxit=maxit, eta=eta, hist_cap=hist_cap, minv=minv)
+
+
+def bkry_cg1r_solve(h: Handle, A: CsrMatrix, B: torch.Tensor, X: torch.Tensor | None = None, kind="block", q=1,
+                    tol=1e-10, maxit=1000, eta=1e4, hist_cap=0):
+    """Block CG with one reduction per iteration (FP64, no preconditioner);
+    X (in/out, zeros if None).  Returns (X, info)."""
+    _block(B)
+    X = torch.zeros_like(B) if X is None else _block(X)
+    p = B.shape[1]
+    info, hist, rel, trel = _info(p, hist_cap)
+    h._sync_stream()
+    d = A.desc()
+    rc = lib().bkry_cg1r_solve(h.h, ctypes.byref(d), p, _subalg(kind, q), _ptr(B), _ptr(X), float(tol), int(maxit),
+                               float(eta), ctypes.byref(info))
+    h._check(rc, allow=(OK, NOT_CONVERGED))
+    return X, _info_dict(rc, info, hist, rel, trel, p)
 
 
 def bkry_jacobi_minv(h: Handle, A: CsrMatrix) -> torch.Tensor:

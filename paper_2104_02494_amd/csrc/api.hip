@@ -392,7 +392,8 @@ int bkry_tsqr(bkry_handle h, int64_t n, int32_t p, bkry_subalg S, double* X, dou
 
 namespace {
 int cg_solve_impl(bkry_handle h, const bkry_csr* A, int32_t p, bkry_subalg S, const double* B, double* X,
-                  double tol, int32_t maxit, double eta, int32_t prec, const double* minv, bkry_info* info) {
+                  double tol, int32_t maxit, double eta, int32_t prec, const double* minv, bkry_info* info,
+                  bool one_reduction = false) {
   int rc = begin(h);
   Sub sub;
   if (!rc) rc = check_csr(h, A, true);
@@ -436,8 +437,10 @@ int cg_solve_impl(bkry_handle h, const bkry_csr* A, int32_t p, bkry_subalg S, co
     rc = ell_build<double, double>(h, A, A->val, W, ecol, eval, v);
     if (rc) return rc;
     CgResult r;
-    hipError_t e = cg_run<double>(v, sub, B, X, tol, maxit, eta, DBL_EPSILON, hist_cap, cb, h->stream, h->hflags, r,
-                                  h->prof, minv);
+    hipError_t e = one_reduction
+                       ? cg1r_run(v, sub, B, X, tol, maxit, eta, hist_cap, cb, h->stream, h->hflags, r, h->prof)
+                       : cg_run<double>(v, sub, B, X, tol, maxit, eta, DBL_EPSILON, hist_cap, cb, h->stream,
+                                        h->hflags, r, h->prof, minv);
     if (e != hipSuccess) return hip_fail(h, e, "cg_solve");
     status = r.status;
     iters = r.iters;
@@ -514,6 +517,11 @@ int cg_solve_impl(bkry_handle h, const bkry_csr* A, int32_t p, bkry_subalg S, co
 int bkry_cg_solve(bkry_handle h, const bkry_csr* A, int32_t p, bkry_subalg S, const double* B, double* X,
                   double tol, int32_t maxit, double eta, int32_t prec, bkry_info* info) {
   return cg_solve_impl(h, A, p, S, B, X, tol, maxit, eta, prec, nullptr, info);
+}
+
+int bkry_cg1r_solve(bkry_handle h, const bkry_csr* A, int32_t p, bkry_subalg S, const double* B, double* X,
+                    double tol, int32_t maxit, double eta, bkry_info* info) {
+  return cg_solve_impl(h, A, p, S, B, X, tol, maxit, eta, BKRY_F64, nullptr, info, true);
 }
 
 int bkry_pcg_solve(bkry_handle h, const bkry_csr* A, int32_t p, bkry_subalg S, const double* B, double* X,

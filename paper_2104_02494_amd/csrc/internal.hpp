@@ -72,7 +72,8 @@ struct CgCtl {
   int32_t kd_jacobi;  // iterations whose kappa_D needed the Jacobi eigenvalues
   int32_t xdef_in;    // this iteration's direction update owes X the previous P's term
   int32_t xdef_pend;  // after this iteration's update, P's term is owed to X
-  int32_t pad_[5];
+  int32_t lam_iter;   // one-reduction CG: iteration whose lambda was computed last (-1: none)
+  int32_t pad_[4];
   double tol, eta, sqrt_eps, pad2_;
   double r0n[kMaxS];
   double relres[kMaxS];
@@ -127,7 +128,11 @@ struct GmCtl {
 // EPI_CG_RHO_M: the residual update of the preconditioned CG, whose
 // partials hold two Grams per workgroup ([R~^T R~ | R~^T M^-1 R~], 2*s*s
 // entries); red.G then receives both.
-enum EpiKind { EPI_NONE = 0, EPI_CG_ALPHA = 1, EPI_CG_RHO = 2, EPI_CG_RHO_M = 3 };
+// EPI_CG_1R: the one reduction of an iteration of the one-reduction block CG,
+// partials [R^T R | R^T A R] (2*s*s entries) written by two producers (the
+// fused update pass and the SpMM); its epilogue does the whole coefficient
+// step.
+enum EpiKind { EPI_NONE = 0, EPI_CG_ALPHA = 1, EPI_CG_RHO = 2, EPI_CG_RHO_M = 3, EPI_CG_1R = 4 };
 struct Epi {
   int kind = EPI_NONE;
   CgCtl* ctl = nullptr;
@@ -149,10 +154,17 @@ int stream_grid(int64_t n, int s, int elem_bytes);
 // 2 Y = B - A X and the Gram Y^T Y into red.G.  partial: nblk*s*s of T.
 // ev_after (optional): recorded on st right after the streaming kernel,
 // before its reduction (kernel timing).
+// gram_slot / ngram: the Gram partial of workgroup b goes to
+// partial + (b * ngram + gram_slot) * s*s (several Grams per partial, the
+// others written by other kernels); the reduction then reads ngram Grams per
+// partial from `partial`.  nblk may be lowered to what the kernel keeps
+// resident (spmm_grid gives the value used).
 template <typename T>
 hipError_t launch_spmm(const CsrView& A, int s, const T* X, T* Y, const T* B, int mode, T* partial,
                        int nblk, Red red, int32_t* bad, const int32_t* gate, hipStream_t st, Epi epi = Epi{},
-                       hipEvent_t ev_after = nullptr);
+                       hipEvent_t ev_after = nullptr, int gram_slot = 0, int ngram = 1);
+template <typename T>
+int spmm_grid(const CsrView& A, int s, int mode, int nblk);
 
 // Gram X_j^T Y for X_j = X + j*n*s, j < nx, into red.G + j*s*s (batched:
 // partial, gpart and counters are per slice).  Optional second gate `fire`:
@@ -226,6 +238,21 @@ hipError_t launch_sddmm(const CsrView& A, int s, double alpha, const T* L, const
 hipError_t launch_project(const double* G, double* out, Sub sub, hipStream_t st);
 hipError_t launch_cg_init(CgCtl* ctl, const double* G_R0, const double* G_rho, hipStream_t st);
 hipError_t launch_cg_reortho_fin(CgCtl* ctl, int s, const double* G, hipStream_t st);
+
+// One-reduction block CG.  Fused pass of iteration k (runs only if lambda^k
+// was computed and the solve is live): P = R + P beta, Q = U + Q beta
+// (P = R, Q = U for k = 0), for odd k X += P_old (lambda sigma)_{k-1} +
+// P (lambda sigma)_k, R = R - Q lambda and, unless the residual is
+// re-normalised next, the Gram partials of R into slot 0 of 2.
+// mode 1: only the Gram partials of R (after a re-normalisation of iteration
+// k, or unconditionally for k < 0).
+// mode 2: X += P (lambda sigma) (the term an even last iteration owes X;
+// runs also after the end).
+hipError_t launch_cg1r_pass(int64_t n, int s, double* R, const double* U, double* P, double* Q, double* X,
+                            const CgCtl* ctl, double* partial, int nblk, int k, int mode, hipStream_t st);
+// After the residual was re-normalised: sigma = gamma sigma, the count, and
+// the iteration resumes.
+hipError_t launch_cg1r_fin(CgCtl* ctl, int s, hipStream_t st);
 // Normaliser coefficients for parallel / global: from the Gram G of X, write
 // the column divisors d and N (p x p) to `out_N` (gated like the CG kernels).
 // N = I_q (x) rho / sqrt(q) from the g x g rho; d[j] = 1/sqrt(q).

@@ -207,7 +207,7 @@ __global__ __launch_bounds__(kBlock) void spmm_csr_kernel(int64_t n, int64_t nnz
                                                           const T* __restrict__ val, int s, const T* __restrict__ X,
                                                           T* __restrict__ Y, const T* __restrict__ B,
                                                           T* __restrict__ partial, int32_t* bad,
-                                                          const int32_t* done) {
+                                                          const int32_t* done, int64_t pstride) {
   using L = Layout<T, S, VEC>;
   constexpr int NW = kBlock / kWave;
   constexpr int RPB = NW * L::RPW;
@@ -327,7 +327,7 @@ __global__ __launch_bounds__(kBlock) void spmm_csr_kernel(int64_t n, int64_t nnz
     }
   }
   if (badidx && bad) *bad = 1;
-  if constexpr (MODE != 0) gram_store<T, S, VEC>(gacc, s, partial, sh);
+  if constexpr (MODE != 0) gram_store<T, S, VEC>(gacc, s, partial, sh, 0, pstride);
 }
 
 // SpMM on the padded row-major (ELL) copy of A: row i's entries sit at
@@ -349,7 +349,7 @@ __global__ __launch_bounds__(kBlock) void spmm_ell_kernel(int64_t n, int W, cons
                                                            const T* __restrict__ eval, int s,
                                                            const T* __restrict__ X, T* __restrict__ Y,
                                                            const T* __restrict__ B, T* __restrict__ partial,
-                                                           const int32_t* done) {
+                                                           const int32_t* done, int64_t pstride) {
   using L = Layout<T, S, VEC>;
   constexpr int LPR = L::LPR;
   constexpr int E = ell_entries_per_lane(LPR);
@@ -444,7 +444,7 @@ __global__ __launch_bounds__(kBlock) void spmm_ell_kernel(int64_t n, int W, cons
     cj = nj;
     ca = na;
   }
-  if constexpr (MODE != 0) gram_store<T, S, VEC>(gacc, s, partial, sh);
+  if constexpr (MODE != 0) gram_store<T, S, VEC>(gacc, s, partial, sh, 0, pstride);
 }
 
 // Workgroups of kernel K that the device holds at once (cached per kernel).
@@ -475,7 +475,11 @@ static int fit_grid(int nblk) {
 
 template <typename T>
 hipError_t launch_spmm(const CsrView& A, int s, const T* X, T* Y, const T* B, int mode, T* partial, int nblk,
-                       Red red, int32_t* bad, const int32_t* done, hipStream_t st, Epi epi, hipEvent_t ev_after) {
+                       Red red, int32_t* bad, const int32_t* done, hipStream_t st, Epi epi, hipEvent_t ev_after,
+                       int gram_slot, int ngram) {
+  T* const pbase = partial;
+  const int64_t pstride = ngram > 1 ? (int64_t)ngram * s * s : 0;
+  partial += (int64_t)gram_slot * s * s;
   hipError_t e = dispatch_s<T>(s, [&](auto S_, auto V_) -> hipError_t {
     constexpr int S = decltype(S_)::value, V = decltype(V_)::value;
     const T* val = static_cast<const T*>(A.val);
@@ -484,15 +488,15 @@ hipError_t launch_spmm(const CsrView& A, int s, const T* X, T* Y, const T* B, in
       if (mode == 0) {
         nblk = fit_grid<spmm_ell_kernel<T, S, V, 0>>(nblk);
         hipLaunchKernelGGL((spmm_ell_kernel<T, S, V, 0>), dim3(nblk), dim3(kBlock), 0, st, A.n, A.ell_w, A.ell_col,
-                           ev, s, X, Y, B, partial, done);
+                           ev, s, X, Y, B, partial, done, pstride);
       } else if (mode == 1) {
         nblk = fit_grid<spmm_ell_kernel<T, S, V, 1>>(nblk);
         hipLaunchKernelGGL((spmm_ell_kernel<T, S, V, 1>), dim3(nblk), dim3(kBlock), 0, st, A.n, A.ell_w, A.ell_col,
-                           ev, s, X, Y, B, partial, done);
+                           ev, s, X, Y, B, partial, done, pstride);
       } else {
         nblk = fit_grid<spmm_ell_kernel<T, S, V, 2>>(nblk);
         hipLaunchKernelGGL((spmm_ell_kernel<T, S, V, 2>), dim3(nblk), dim3(kBlock), 0, st, A.n, A.ell_w, A.ell_col,
-                           ev, s, X, Y, B, partial, done);
+                           ev, s, X, Y, B, partial, done, pstride);
       }
       return hipGetLastError();
     }
@@ -504,18 +508,37 @@ hipError_t launch_spmm(const CsrView& A, int s, const T* X, T* Y, const T* B, in
       nblk = fit_grid<spmm_csr_kernel<T, S, V, 2>>(nblk);
     if (mode == 0)
       hipLaunchKernelGGL((spmm_csr_kernel<T, S, V, 0>), dim3(nblk), dim3(kBlock), 0, st, A.n, A.nnz, A.rowptr,
-                         A.colind, val, s, X, Y, B, partial, bad, done);
+                         A.colind, val, s, X, Y, B, partial, bad, done, pstride);
     else if (mode == 1)
       hipLaunchKernelGGL((spmm_csr_kernel<T, S, V, 1>), dim3(nblk), dim3(kBlock), 0, st, A.n, A.nnz, A.rowptr,
-                         A.colind, val, s, X, Y, B, partial, bad, done);
+                         A.colind, val, s, X, Y, B, partial, bad, done, pstride);
     else
       hipLaunchKernelGGL((spmm_csr_kernel<T, S, V, 2>), dim3(nblk), dim3(kBlock), 0, st, A.n, A.nnz, A.rowptr,
-                         A.colind, val, s, X, Y, B, partial, bad, done);
+                         A.colind, val, s, X, Y, B, partial, bad, done, pstride);
     return hipGetLastError();
   });
   if (e == hipSuccess && ev_after) e = hipEventRecord(ev_after, st);
   if (e != hipSuccess || mode == 0) return e;
-  return launch_reduce(s, partial, sizeof(T) == 4, nblk, 1, red, done, nullptr, epi, st);
+  return launch_reduce(s, pbase, sizeof(T) == 4, nblk, 1, red, done, nullptr, epi, st);
+}
+
+// Workgroups launch_spmm uses for a requested nblk (its kernels' residency cap).
+template <typename T>
+int spmm_grid(const CsrView& A, int s, int mode, int nblk) {
+  int out = nblk;
+  (void)dispatch_s<T>(s, [&](auto S_, auto V_) -> hipError_t {
+    constexpr int S = decltype(S_)::value, V = decltype(V_)::value;
+    if (A.ell_w > 0)
+      out = mode == 0 ? fit_grid<spmm_ell_kernel<T, S, V, 0>>(nblk)
+                      : (mode == 1 ? fit_grid<spmm_ell_kernel<T, S, V, 1>>(nblk)
+                                   : fit_grid<spmm_ell_kernel<T, S, V, 2>>(nblk));
+    else
+      out = mode == 0 ? fit_grid<spmm_csr_kernel<T, S, V, 0>>(nblk)
+                      : (mode == 1 ? fit_grid<spmm_csr_kernel<T, S, V, 1>>(nblk)
+                                   : fit_grid<spmm_csr_kernel<T, S, V, 2>>(nblk));
+    return hipSuccess;
+  });
+  return out;
 }
 
 // ------------------------------------------------------------------ Gram --
@@ -798,6 +821,133 @@ hipError_t launch_cg_pupdate(int64_t n, int s, T* X, const T* P, T* Pn, const T*
     else
       hipLaunchKernelGGL((cg_pupdate_kernel<T, S, V, false>), dim3(nblk), dim3(kBlock), 0, st, n, s, X, P, Pn, R,
                          ctl, minv);
+    return hipGetLastError();
+  });
+}
+
+// ------------------------------------------------- one-reduction block CG --
+// Fused pass of iteration k of the one-reduction block CG (MODE 0), the Gram
+// of a re-normalised residual (MODE 1) and the final owed X term (MODE 2);
+// see launch_cg1r_pass.  Every update is row-local, so P, Q, R and X are
+// overwritten in place.  X takes the terms of two iterations every other
+// iteration: the odd iteration k adds P_{k-1} (lambda sigma)_{k-1}, read
+// anyway for the direction update, and P_k (lambda sigma)_k.
+template <int S, int VEC, int MODE>
+__global__ __launch_bounds__(kBlock) void cg1r_pass_kernel(int64_t n, int s, double* __restrict__ R,
+                                                            const double* __restrict__ U, double* __restrict__ P,
+                                                            double* __restrict__ Q, double* __restrict__ X,
+                                                            const CgCtl* ctl, double* __restrict__ partial, int k) {
+  using T = double;
+  using L = Layout<T, S, VEC>;
+  constexpr int NW = kBlock / kWave;
+  constexpr int RPB = NW * L::RPW;
+  __shared__ T lam[MODE == 0 ? S * S : 1], bt[MODE == 0 ? S * S : 1], cs[MODE != 1 ? S * S : 1],
+      cp[MODE == 0 ? S * S : 1];
+  __shared__ T sh[MODE != 2 ? NW * S * S : 1];
+  // MODE 2 runs after the end; MODE 1 with k < 0 (the initial residual)
+  // does not depend on a re-normalisation decision
+  if (MODE != 2 && ctl->done) return;
+  if (MODE == 0 && ctl->lam_iter != k) return;
+  if (MODE == 1 && k >= 0 && !ctl->fire) return;
+  const bool first = k == 0, xodd = (k & 1) != 0;
+  const bool gram = MODE == 1 || (MODE == 0 && !ctl->fire);
+  if constexpr (MODE == 0) {
+    load_coeff<T, S>(lam, ctl->lam, s);
+    if (!first) load_coeff<T, S>(bt, ctl->beta, s);
+    if (xodd) {
+      load_coeff<T, S>(cs, ctl->lamsig, s);
+      load_coeff<T, S>(cp, ctl->lamsig_prev, s);
+    }
+  } else if constexpr (MODE == 2) {
+    load_coeff<T, S>(cs, ctl->lamsig, s);
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  const int r = lane / L::LPR, c = lane % L::LPR;
+  const int col0 = c * VEC;
+  const bool active = col0 < s;
+  int64_t r0, r1;
+  int64_t rstep;
+  stream_rows(n, RPB, r0, r1, rstep);
+  T gacc[MODE != 2 ? VEC : 1][MODE != 2 ? S : 1];
+  if constexpr (MODE != 2) {
+#pragma unroll
+    for (int a = 0; a < VEC; ++a)
+#pragma unroll
+      for (int b = 0; b < S; ++b) gacc[a][b] = T(0);
+  }
+  for (int64_t base = r0; base < r1; base += rstep) {
+    const int64_t row = base + wave * L::RPW + r;
+    const bool rv = row < r1 && active;
+    const int64_t o = row * s + col0;
+    if constexpr (MODE == 2) {
+      const vec_t<T, VEC> p = rv ? load_vec<T, VEC>(P + o) : zero_vec<T, VEC>();
+      vec_t<T, VEC> x = rv ? load_vec<T, VEC>(X + o) : zero_vec<T, VEC>();
+      T dx[VEC];
+      row_times<T, S, VEC>(dx, p, cs, col0, lane);
+#pragma unroll
+      for (int w = 0; w < VEC; ++w) x.v[w] += dx[w];
+      if (rv) store_nt<T, VEC>(X + o, x);
+    } else if constexpr (MODE == 1) {
+      const vec_t<T, VEC> rr = rv ? load_vec<T, VEC>(R + o) : zero_vec<T, VEC>();
+      gram_row<T, S, VEC>(gacc, rr, rr, lane);
+    } else {
+      const vec_t<T, VEC> rr = rv ? load_vec<T, VEC>(R + o) : zero_vec<T, VEC>();
+      const vec_t<T, VEC> u = rv ? load_vec<T, VEC>(U + o) : zero_vec<T, VEC>();
+      vec_t<T, VEC> p = rr, q = u;
+      vec_t<T, VEC> po = zero_vec<T, VEC>();
+      if (!first) {
+        po = rv ? load_vec<T, VEC>(P + o) : zero_vec<T, VEC>();
+        const vec_t<T, VEC> qo = rv ? load_vec<T, VEC>(Q + o) : zero_vec<T, VEC>();
+        T pb[VEC], qb[VEC];
+        row_times<T, S, VEC>(pb, po, bt, col0, lane);
+        row_times<T, S, VEC>(qb, qo, bt, col0, lane);
+#pragma unroll
+        for (int w = 0; w < VEC; ++w) {
+          p.v[w] += pb[w];
+          q.v[w] += qb[w];
+        }
+      }
+      if (xodd) {
+        vec_t<T, VEC> x = rv ? load_vec<T, VEC>(X + o) : zero_vec<T, VEC>();
+        T d1[VEC], d2[VEC];
+        row_times<T, S, VEC>(d1, po, cp, col0, lane);
+        row_times<T, S, VEC>(d2, p, cs, col0, lane);
+#pragma unroll
+        for (int w = 0; w < VEC; ++w) x.v[w] += d1[w] + d2[w];
+        if (rv) store_nt<T, VEC>(X + o, x);
+      }
+      T ql[VEC];
+      row_times<T, S, VEC>(ql, q, lam, col0, lane);
+      vec_t<T, VEC> rn;
+#pragma unroll
+      for (int w = 0; w < VEC; ++w) rn.v[w] = rr.v[w] - ql[w];
+      if (rv) {
+        store_out<T, VEC>(P + o, p);
+        store_out<T, VEC>(Q + o, q);
+        store_out<T, VEC>(R + o, rn);
+      }
+      if (gram) gram_row<T, S, VEC>(gacc, rn, rn, lane);
+    }
+  }
+  if constexpr (MODE != 2)
+    if (gram) gram_store<T, S, VEC>(gacc, s, partial, sh, 0, 2 * (int64_t)s * s);
+}
+
+hipError_t launch_cg1r_pass(int64_t n, int s, double* R, const double* U, double* P, double* Q, double* X,
+                            const CgCtl* ctl, double* partial, int nblk, int k, int mode, hipStream_t st) {
+  if (mode < 0 || mode > 2) return hipErrorInvalidValue;
+  return dispatch_s<double>(s, [&](auto S_, auto V_) -> hipError_t {
+    constexpr int S = decltype(S_)::value, V = decltype(V_)::value;
+    if (mode == 0)
+      hipLaunchKernelGGL((cg1r_pass_kernel<S, V, 0>), dim3(nblk), dim3(kBlock), 0, st, n, s, R, U, P, Q, X, ctl,
+                         partial, k);
+    else if (mode == 1)
+      hipLaunchKernelGGL((cg1r_pass_kernel<S, V, 1>), dim3(nblk), dim3(kBlock), 0, st, n, s, R, U, P, Q, X, ctl,
+                         partial, k);
+    else
+      hipLaunchKernelGGL((cg1r_pass_kernel<S, V, 2>), dim3(nblk), dim3(kBlock), 0, st, n, s, R, U, P, Q, X, ctl,
+                         partial, k);
     return hipGetLastError();
   });
 }
@@ -1088,7 +1238,8 @@ hipError_t launch_cast_f32(int64_t count, const double* in, float* out, hipStrea
 // ------------------------------------------------------ instantiations --
 #define BKRY_INST(T)                                                                                              \
   template hipError_t launch_spmm<T>(const CsrView&, int, const T*, T*, const T*, int, T*, int, Red, int32_t*,     \
-                                     const int32_t*, hipStream_t, Epi, hipEvent_t);                                \
+                                     const int32_t*, hipStream_t, Epi, hipEvent_t, int, int);                      \
+  template int spmm_grid<T>(const CsrView&, int, int, int);                                                       \
   template hipError_t launch_gram<T>(int64_t, int, const T*, int, const T*, T*, int, Red, const int32_t*,          \
                                      hipStream_t, const int32_t*);                                                 \
   template hipError_t launch_cg_update<T>(int64_t, int, T*, const T*, const CgCtl*, T*, int, Red, hipStream_t,    \

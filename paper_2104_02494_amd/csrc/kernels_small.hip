@@ -530,6 +530,7 @@ __global__ __launch_bounds__(kSB) void cg_init_kernel(CgCtl* c, const double* G_
       c->kd_jacobi = 0;
       c->xdef_in = 0;
       c->xdef_pend = 0;
+      c->lam_iter = -1;
       c->nreorth = (c->eta > 0.0 && !allzero) ? 1 : 0;
       c->bad_index = 0;
     }
@@ -690,6 +691,134 @@ __device__ __forceinline__ void cg_rho_body(CgCtl* c, const double* G, double* h
   sm_copy(c->rho, Gm, s * s);
 }
 
+// One-reduction block CG (alg:1R-CG, Ch. 8): the coefficient step of
+// iteration k from the Grams of R-bar^k, G = [R^T R | R^T A R] (full, s x s
+// each).  k > 0: column norms of R-bar^k sigma^k and the stopping test
+// (iteration k ends there), beta^{k-1} = rho^-1 gamma^T rho^k (gamma = I
+// unless iteration k-1 re-normalised) and alpha^k = delta^k - beta^T alpha
+// beta; k = 0: alpha^0 = delta^0.  Then lambda^k = alpha^-1 rho^k, lambda
+// sigma (the previous one kept for the X update) and the kappa_D test of
+// alpha^k, which decides whether R~^{k+1} is re-normalised.
+// rho_l, sigma_l, r0n_l: copies of c->rho, c->sigma and c->r0n (LDS).
+template <int SM>
+__device__ __forceinline__ void cg1r_body(CgCtl* c, const double* G, double* hist, const double* rho_l,
+                                          const double* sigma_l, const double* r0n_l) {
+  __shared__ double Rh[kSS], Dl[kSS], T1[kSS], Bt[kSS], Al[kSS], Lm[kSS], W[kSS], Tt[kSS];
+  __shared__ double rc[kMaxS], rs[kMaxS], red[4];
+  __shared__ int partner[kMaxS], first[kMaxS], flag[1];
+  const int s = c->s, ss = s * s;
+  const Sub sub{c->kind, s, c->g};
+  const int k = c->lam_iter + 1;
+  auto fail = [&](int status) {
+    if (tid() == 0) {
+      c->status = status;
+      c->done = 1;
+      c->gate = 1;
+    }
+  };
+  if (k > 0) {
+    sm_mm(T1, G, sigma_l, s, false);  // G sigma
+    double rel = 0.0;
+    bool nanl = false;
+    for (int i = tid(); i < s; i += kSB) {
+      double acc = 0.0;
+      for (int a = 0; a < s; ++a) acc += sigma_l[a * s + i] * T1[a * s + i];
+      const double cn = sqrt(fmax(acc, 0.0));
+      const double r = r0n_l[i] > 0.0 ? cn / r0n_l[i] : 0.0;
+      nanl |= !isfinite(acc);
+      c->relres[i] = r;
+      rel = fmax(rel, r);
+    }
+    const double m = wmax(rel);
+    const bool nan = wany(nanl);
+    if (tid() == 0) {
+      if (hist && k - 1 < c->hist_cap) hist[k - 1] = nan ? NAN : m;
+      c->iters = k;
+      int state = 0;
+      if (nan) {
+        c->status = -3;
+        state = 1;
+      } else if (m <= c->tol) {
+        c->converged = 1;
+        state = 1;
+      } else if (k >= c->maxit) {
+        state = 1;
+      }
+      c->done = state;
+      c->gate = state;
+      flag[0] = state;
+    }
+    __syncthreads();
+    if (flag[0]) return;
+  }
+  sm_copy(Rh, G, ss);
+  sm_project(Rh, sub, red);
+  sm_copy(Dl, G + ss, ss);
+  sm_project(Dl, sub, red);
+  if (!all_finite(Rh, ss, red) || !all_finite(Dl, ss, red)) return fail(-3);
+  if (k > 0) {
+    if (c->fire) {  // gamma^T rho'
+      sm_copy(W, c->gamma, ss);
+      sm_mm(T1, W, Rh, s, true);
+    } else {
+      sm_copy(T1, Rh, ss);
+    }
+    if (!rf_cholesky_solve<SM>(rho_l, T1, Bt, nullptr, s)) return fail(-2);
+    sm_copy(W, c->alpha, ss);
+    sm_mm(T1, W, Bt, s, false);  // alpha beta
+    sm_mm(Tt, Bt, T1, s, true);  // beta^T alpha beta
+    for (int t = tid(); t < ss; t += kSB) Al[t] = Dl[t] - Tt[t];
+  } else {
+    for (int t = tid(); t < ss; t += kSB) {
+      Bt[t] = 0.0;
+      Al[t] = Dl[t];
+    }
+  }
+  if (!all_finite(Al, ss, red)) return fail(-3);
+  if (!rf_cholesky_solve<SM>(Al, Rh, Lm, reortho_dynamic(c) ? Tt : nullptr, s)) return fail(-2);
+  sm_mm(T1, Lm, sigma_l, s, false);  // lambda sigma
+  for (int t = tid(); t < ss; t += kSB) c->lamsig_prev[t] = c->lamsig[t];
+  store_coeff(c->lam, c->lam_f, Lm, s);
+  store_coeff(c->lamsig, c->lamsig_f, T1, s);
+  store_coeff(c->beta, c->beta_f, Bt, s);
+  sm_copy(c->alpha, Al, ss);
+  sm_copy(c->rho, Rh, ss);
+  const bool fire = reortho_test<SM>(c, Al, W, Tt, rc, rs, partner, first, red);
+  __syncthreads();
+  if (tid() == 0) {
+    c->fire = fire ? 1 : 0;
+    c->lam_iter = k;
+    // a dynamically decided re-normalisation suspends the iteration after
+    // its fused pass; the host launches it at its next read-back
+    c->suspended = (fire && c->dynamic) ? 1 : 0;
+    c->gate = c->suspended;
+  }
+}
+
+// After R~^{k+1} was re-normalised (gamma in c->gamma): sigma = gamma sigma,
+// count it, resume.
+__global__ __launch_bounds__(kSB) void cg1r_fin_kernel(CgCtl* c) {
+  __shared__ double Ga[kSS], Sg[kSS], T1[kSS];
+  if (c->done || !c->fire) return;
+  const int s = c->s;
+  sm_copy(Ga, c->gamma, s * s);
+  sm_copy(Sg, c->sigma, s * s);
+  sm_mm(T1, Ga, Sg, s, false);
+  sm_copy(c->sigma, T1, s * s);
+  __syncthreads();
+  if (tid() == 0) {
+    c->nreorth += 1;
+    c->suspended = 0;
+    c->gate = 0;
+  }
+}
+
+hipError_t launch_cg1r_fin(CgCtl* ctl, int s, hipStream_t st) {
+  (void)s;
+  hipLaunchKernelGGL(cg1r_fin_kernel, dim3(1), dim3(kSB), 0, st, ctl);
+  return hipGetLastError();
+}
+
 // --------------------------------------------------- Gram reduction --
 // grid (ns, batch), one wavefront per workgroup: workgroup (sl, y) sums the
 // partials [b0, b1) of batch slice y in block order into red.gpart[y][sl];
@@ -728,10 +857,11 @@ __global__ __launch_bounds__(EPI == EPI_NONE ? kRedPlain : kSB) void reduce_kern
     double* hist) {
   constexpr int NTH = EPI == EPI_NONE ? kRedPlain : kSB;
   constexpr bool RHO = EPI == EPI_CG_RHO || EPI == EPI_CG_RHO_M;
-  constexpr int NG = EPI == EPI_CG_RHO_M ? 2 : 1;  // Grams per partial
+  constexpr bool NORMS = RHO || EPI == EPI_CG_1R;
+  constexpr int NG = (EPI == EPI_CG_RHO_M || EPI == EPI_CG_1R) ? 2 : 1;  // Grams per partial
   __shared__ int last;
   __shared__ double pre_rho[EPI != EPI_NONE ? kSS : 1], pre_sig[EPI != EPI_NONE ? kSS : 1];
-  __shared__ double pre_r0n[RHO ? kMaxS : 1];
+  __shared__ double pre_r0n[NORMS ? kMaxS : 1];
   const int ss = s * s, m = NG * ss;
   if constexpr (EPI != EPI_NONE) {
     // the epilogue's inputs from the control block, loaded along with the
@@ -740,7 +870,7 @@ __global__ __launch_bounds__(EPI == EPI_NONE ? kRedPlain : kSB) void reduce_kern
       pre_rho[t] = c->rho[t];
       pre_sig[t] = c->sigma[t];
     }
-    if constexpr (RHO)
+    if constexpr (NORMS)
       for (int t = tid(); t < s; t += kSB) pre_r0n[t] = c->r0n[t];
   }
   if constexpr (EPI == EPI_CG_ALPHA) {
@@ -752,7 +882,7 @@ __global__ __launch_bounds__(EPI == EPI_NONE ? kRedPlain : kSB) void reduce_kern
       return;
     }
     if (c->gate) return;  // suspended: the iteration waits for its re-normalisation
-  } else if constexpr (RHO) {
+  } else if constexpr (NORMS) {
     if (c->gate) return;
   } else {
     if ((gate && *gate) || (fire && !*fire)) return;
@@ -783,6 +913,9 @@ __global__ __launch_bounds__(EPI == EPI_NONE ? kRedPlain : kSB) void reduce_kern
   } else if constexpr (RHO) {
     __syncthreads();
     cg_rho_body<SM>(c, Gl, hist, pre_rho, pre_sig, pre_r0n, NG == 2 ? Gl + ss : nullptr);
+  } else if constexpr (EPI == EPI_CG_1R) {
+    __syncthreads();
+    cg1r_body<SM>(c, Gl, hist, pre_rho, pre_sig, pre_r0n);
   }
 }
 
@@ -805,7 +938,7 @@ static hipError_t launch_reduce_t(int s, const T* partial, int nblk, int batch, 
     return hipGetLastError();
   }
   if (batch != 1 || !epi.ctl ||
-      (epi.kind != EPI_CG_ALPHA && epi.kind != EPI_CG_RHO && epi.kind != EPI_CG_RHO_M))
+      (epi.kind != EPI_CG_ALPHA && epi.kind != EPI_CG_RHO && epi.kind != EPI_CG_RHO_M && epi.kind != EPI_CG_1R))
     return hipErrorInvalidValue;
   return dispatch_sm(s, [&](auto SM_) -> hipError_t {
     constexpr int SM = decltype(SM_)::value;
@@ -815,11 +948,16 @@ static hipError_t launch_reduce_t(int s, const T* partial, int nblk, int batch, 
     else if (epi.kind == EPI_CG_RHO)
       hipLaunchKernelGGL((reduce_kernel<T, EPI_CG_RHO, SM>), grid, dim3(kSB), 0, st, s, partial, nblk, red, gate,
                          fire, epi.ctl, epi.hist);
-    else if constexpr (sizeof(T) == 8)
-      hipLaunchKernelGGL((reduce_kernel<T, EPI_CG_RHO_M, SM>), grid, dim3(kSB), 0, st, s, partial, nblk, red, gate,
-                         fire, epi.ctl, epi.hist);
-    else
+    else if constexpr (sizeof(T) == 8) {
+      if (epi.kind == EPI_CG_RHO_M)
+        hipLaunchKernelGGL((reduce_kernel<T, EPI_CG_RHO_M, SM>), grid, dim3(kSB), 0, st, s, partial, nblk, red, gate,
+                           fire, epi.ctl, epi.hist);
+      else
+        hipLaunchKernelGGL((reduce_kernel<T, EPI_CG_1R, SM>), grid, dim3(kSB), 0, st, s, partial, nblk, red, gate,
+                           fire, epi.ctl, epi.hist);
+    } else {
       return hipErrorInvalidValue;
+    }
     return hipGetLastError();
   });
 }

@@ -240,6 +240,109 @@ template hipError_t cg_run<double>(const CsrView&, Sub, const double*, double*, 
 template hipError_t cg_run<float>(const CsrView&, Sub, const float*, float*, double, int, double, double, int,
                                   const CgBufs<float>&, hipStream_t, int32_t*, CgResult&, Prof*, const double*);
 
+// ------------------------------------------------- one-reduction block CG --
+// Per iteration k: the SpMM U = A R-bar^k writes the Gram partials R^T U
+// into slot 1 of the partials whose slot 0 the previous fused pass filled
+// with R^T R; the one reduction's epilogue runs the whole coefficient step
+// (cg1r_body); the fused pass updates P, Q, X and R-bar (and the next slot
+// 0).  Three launches and one reduction per iteration.
+static hipError_t cg1r_normalise(int64_t n, Sub sub, const CgBufs<double>& b, int nblk, int k, hipStream_t st,
+                                 Prof* prof) {
+  CgCtl* c = b.ctl;
+  ProfScope ps(prof, PROF_CG_NORMALISE, st);
+  BK_TRY(tsqr_run<double>(n, sub, b.R, c->gamma, b.tsqr_ws, b.cnt, &c->done, &c->fire, st));
+  BK_TRY(launch_cg1r_fin(c, sub.s, st));
+  return launch_cg1r_pass(n, sub.s, b.R, b.P2, b.P, b.Q, nullptr, c, b.partial, nblk, k, 1, st);
+}
+
+hipError_t cg1r_run(const CsrView& A, Sub sub, const double* B, double* X, double tol, int maxit, double eta,
+                    int hist_cap, const CgBufs<double>& b, hipStream_t st, int32_t* hflags, CgResult& res,
+                    Prof* prof) {
+  const int64_t n = A.n;
+  const int s = sub.s;
+  const double eps = DBL_EPSILON;
+  // the fused pass and the SpMM write the two halves of one partial per
+  // workgroup: both run on the SpMM's grid
+  const int nblk = spmm_grid<double>(A, s, 1, stream_grid(n, s, sizeof(double)));
+  CgCtl* c = b.ctl;
+  int32_t* gate = &c->gate;
+  const bool always = eta > 0.0 && (isinf(eta) || eta * sqrt(eps) > 1.0);
+  const bool dynamic = eta > 0.0 && !always && sub.g > 1;
+
+  CgCtl* h = reinterpret_cast<CgCtl*>(hflags + 64);
+  memset(h, 0, offsetof(CgCtl, r0n));
+  h->maxit = maxit;
+  h->s = s;
+  h->kind = sub.kind;
+  h->g = sub.g;
+  h->hist_cap = hist_cap;
+  h->dynamic = dynamic ? 1 : 0;
+  h->tol = tol;
+  h->eta = eta;
+  h->sqrt_eps = sqrt(eps);
+  BK_TRY(hipMemcpyAsync(c, h, offsetof(CgCtl, r0n), hipMemcpyHostToDevice, st));
+
+  // R0 = B - A X0 and its column norms; initial normalisation; slot 0 of the
+  // partials: the Gram of R-bar^0
+  BK_TRY(launch_spmm<double>(A, s, X, b.R, B, 2, b.partial, stream_grid(n, s, sizeof(double)),
+                             Red{b.Ga, b.gpart, b.cnt}, &c->bad_index, nullptr, st));
+  BK_TRY(launch_cg_init(c, b.Ga, nullptr, st));
+  if (eta > 0.0) BK_TRY(tsqr_run<double>(n, sub, b.R, c->sigma, b.tsqr_ws, b.cnt, &c->done, nullptr, st));
+  BK_TRY(launch_cg1r_pass(n, s, b.R, b.P2, b.P, b.Q, X, c, b.partial, nblk, -1, 1, st));
+
+  const CgCtl* hc = reinterpret_cast<const CgCtl*>(hflags);
+  const Red red{b.Gr, b.gpart, b.cnt};
+  int k = 0, batch = 4, last_iters = -1;
+  while (maxit > 0) {
+    for (int it = 0; it < batch; ++it, ++k) {
+      {
+        ProfScope ps(prof, PROF_CG_SPMM, st);
+        BK_TRY(launch_spmm<double>(A, s, b.R, b.P2, nullptr, 1, b.partial, nblk, red, &c->bad_index, gate, st,
+                                   Epi{EPI_CG_1R, c, b.hist}, ps.end(), 1, 2));
+      }
+      {
+        ProfScope ps(prof, PROF_CG_UPDATE, st);
+        BK_TRY(launch_cg1r_pass(n, s, b.R, b.P2, b.P, b.Q, X, c, b.partial, nblk, k, 0, st));
+      }
+      if (always) BK_TRY(cg1r_normalise(n, sub, b, nblk, k, st, prof));
+    }
+    BK_TRY(hipMemcpyAsync(hflags, c, kCtlHeaderInts * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    BK_TRY(hipStreamSynchronize(st));
+    BK_TRY(prof_flush(prof));
+    if (hc->done) break;
+    if (hc->suspended) {
+      // iteration j fired: its fused pass ran, the later kernels of the batch
+      // were gated off; re-normalise R~^{j+1} and resume at iteration j + 1
+      const int j = hc->lam_iter;
+      BK_TRY(cg1r_normalise(n, sub, b, nblk, j, st, prof));
+      k = j + 1;
+      batch = 2;
+    } else {
+      if (hc->iters == last_iters && hc->lam_iter + 1 == k) {
+        // no progress although live (cannot happen): stop
+        break;
+      }
+      if (batch < 32) batch *= 2;
+    }
+    last_iters = hc->iters;
+  }
+  BK_TRY(hipMemcpyAsync(hflags, c, kCtlHeaderInts * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  BK_TRY(hipStreamSynchronize(st));
+  // an even last iteration j deferred its X term P_j (lambda sigma)_j
+  const int j = hc->lam_iter;
+  if (j >= 0 && (j & 1) == 0) {
+    BK_TRY(launch_cg1r_pass(n, s, b.R, b.P2, b.P, b.Q, X, c, b.partial, nblk, j, 2, st));
+    BK_TRY(hipStreamSynchronize(st));
+  }
+  res.status = hc->status;
+  res.iters = hc->iters;
+  res.nreorth = hc->nreorth;
+  res.converged = hc->converged;
+  res.bad_index = hc->bad_index;
+  res.kd_jacobi = hc->kd_jacobi;
+  return hipSuccess;
+}
+
 // ------------------------------------------------------ block BiCGStab --
 BcBufs carve_bc(Carver& c, int64_t n, Sub sub, int hist_cap, uint32_t* cnt) {
   const int s = sub.s;

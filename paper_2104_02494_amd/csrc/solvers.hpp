@@ -71,6 +71,12 @@ hipError_t cg_run(const CsrView& A, Sub sub, const T* B, T* X, double tol, int m
                   int hist_cap, const CgBufs<T>& b, hipStream_t st, int32_t* hflags, CgResult& res,
                   Prof* prof = nullptr, const double* minv = nullptr);
 
+// Block CG with one reduction per iteration (alg:1R-CG), FP64, M = I.  Uses
+// the CgBufs of the same n and sub: R holds R-bar, P2 holds U = A R-bar.
+hipError_t cg1r_run(const CsrView& A, Sub sub, const double* B, double* X, double tol, int maxit, double eta,
+                    int hist_cap, const CgBufs<double>& b, hipStream_t st, int32_t* hflags, CgResult& res,
+                    Prof* prof = nullptr);
+
 struct IrBufs {
   float *A32 = nullptr, *R32 = nullptr, *X32 = nullptr;
   double *R64 = nullptr, *partial = nullptr, *gpart = nullptr, *G = nullptr, *r0n = nullptr, *scale = nullptr;

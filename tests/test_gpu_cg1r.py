@@ -1,0 +1,126 @@
+"""GPU parity of the one-reduction block CG (bkry_cg1r_solve, Algorithm "BCG
+with One Reduction", Ch. 8) against the oracle's implementation of the same
+algorithm.
+
+Fixed iteration counts (tol = 0) run the same arithmetic on both sides and
+must agree to 1e-10 relative in FP64; odd and even counts cover both ends of
+the every-other-iteration X update.  Full solves are compared on iteration
+and re-orthonormalisation counts, residual history and the FP64 true
+residual; the two-reduction GPU solver gives the same solution."""
+import numpy as np
+import pytest
+
+import workloads as W
+from gpu_util import dev_csr, h, rel, say, to_dev, to_np  # noqa: F401
+
+pytestmark = pytest.mark.gpu
+P = pytest.importorskip("paper_2104_02494_amd")
+
+SUBS = [("block", 1), ("hybrid", 2), ("parallel", 1), ("global", 1), ("bglobal", 2)]
+
+
+def gpu_cg1r(h, A, B, X0=None, **kw):
+    X, info = P.bkry_cg1r_solve(h, dev_csr(P, A), to_dev(B), None if X0 is None else to_dev(X0), **kw)
+    return to_np(X), info
+
+
+@pytest.mark.parametrize("s", [1, 2, 3, 4, 8, 16, 32])
+@pytest.mark.parametrize("kind,q", SUBS)
+@pytest.mark.parametrize("eta", [0.0, np.inf])
+def test_cg1r_fixed_iterations(orc, h, s, kind, q, eta):
+    if kind in ("hybrid", "bglobal") and s % q:
+        pytest.skip("q must divide s")
+    A = W.laplace_2d(41)                    # n = 1681: several tiles and a ragged tail
+    B = W.uniform_block(A.n, s, s)
+    X0 = 0.01 * W.gaussian_block(A.n, s, 100 + s)
+    for k in (1, 2, 7):
+        say("cg1r fixed", s, kind, eta, k)
+        X, info = gpu_cg1r(h, A, B, X0, kind=kind, q=q, tol=0.0, maxit=k, eta=eta, hist_cap=k)
+        ro = orc.bcg1r(A, B, X0, kind=kind, q=q, tol=0.0, maxit=k, eta=eta, hist_cap=k)
+        assert info["iters"] == ro["iters"] == k and info["status"] == P.NOT_CONVERGED
+        assert info["reorth"] == ro["reorth"]
+        assert rel(X, ro["X"]) < 1e-10
+        assert np.allclose(info["hist"], ro["hist"], rtol=1e-9, atol=1e-15)
+
+
+@pytest.mark.parametrize("kind,q", SUBS)
+@pytest.mark.parametrize("eta", [0.0, 1e4, np.inf])
+def test_cg1r_full_solve(orc, h, kind, q, eta):
+    A, B, _ = W.build_workload("poisson2d_32x32_s4")
+    say("cg1r poisson32", kind, eta)
+    X, info = gpu_cg1r(h, A, B, kind=kind, q=q, tol=1e-10, maxit=2000, eta=eta, hist_cap=2000)
+    ro = orc.bcg1r(A, B, kind=kind, q=q, tol=1e-10, maxit=2000, eta=eta, hist_cap=2000)
+    assert info["converged"] and ro["converged"]
+    assert abs(info["iters"] - ro["iters"]) <= 1
+    assert abs(info["reorth"] - ro["reorth"]) <= 1
+    k = min(len(info["hist"]), len(ro["hist"]))
+    assert np.allclose(info["hist"][:k], ro["hist"][:k], rtol=1e-6, atol=1e-15)
+    assert max(info["true_relres"]) <= 1.5e-10
+    assert rel(X, np.linalg.solve(A.to_dense(), B)) < 1e-7
+    # the same solution as the two-reduction solver
+    X2, i2 = P.bkry_cg_solve(h, dev_csr(P, A), to_dev(B), kind=kind, q=q, tol=1e-10, maxit=2000, eta=eta)
+    assert abs(i2["iters"] - info["iters"]) <= 1
+    assert rel(X, to_np(X2)) < 1e-8
+
+
+def test_cg1r_edge_cases(orc, h):
+    A, B, _ = W.build_workload("poisson2d_32x32_s4")
+    say("cg1r edges: zero rhs")
+    X, info = gpu_cg1r(h, A, np.zeros_like(B), tol=1e-10)
+    assert info["converged"] and info["iters"] == 0 and np.all(X == 0)
+    say("cg1r edges: maxit 0 and 1")
+    X0 = W.gaussian_block(A.n, 4, 3)
+    X, info = gpu_cg1r(h, A, B, X0, tol=1e-10, maxit=0)
+    assert info["iters"] == 0 and np.array_equal(X, X0)
+    X, info = gpu_cg1r(h, A, B, tol=1e-10, maxit=1)
+    ro = orc.bcg1r(A, B, tol=1e-10, maxit=1, eta=1e4)
+    assert info["status"] == P.NOT_CONVERGED and info["iters"] == 1 and rel(X, ro["X"]) < 1e-12
+    say("cg1r edges: zero column, eta 0 -> breakdown; eta inf converges")
+    Bz = B.copy()
+    Bz[:, 2] = 0.0
+    with pytest.raises(P.BkryError) as e:
+        gpu_cg1r(h, A, Bz, eta=0.0, tol=1e-10)
+    assert e.value.code == P.E_BREAKDOWN
+    X, info = gpu_cg1r(h, A, Bz, eta=np.inf, tol=1e-10, maxit=2000)
+    assert info["converged"] and np.abs(X[:, 2]).max() < 1e-12
+    say("cg1r edges: non-SPD, nan, invalid q")
+    with pytest.raises(P.BkryError) as e:
+        gpu_cg1r(h, W.Csr(A.n, A.rowptr, A.colind, -A.val), B, eta=0.0)
+    assert e.value.code == P.E_BREAKDOWN
+    Bn = B.copy()
+    Bn[5, 1] = np.nan
+    with pytest.raises(P.BkryError) as e:
+        gpu_cg1r(h, A, Bn, eta=0.0, tol=1e-10)
+    assert e.value.code == P.E_NONFINITE
+    with pytest.raises(P.BkryError):
+        gpu_cg1r(h, A, B, kind="hybrid", q=3)
+    say("cg1r edges: deterministic")
+    X1, i1 = gpu_cg1r(h, A, B, tol=1e-10, eta=1e4)
+    X2, i2 = gpu_cg1r(h, A, B, tol=1e-10, eta=1e4)
+    assert np.array_equal(X1, X2) and i1["iters"] == i2["iters"]
+
+
+@pytest.mark.parametrize("kind,q", [("block", 1), ("hybrid", 2)])
+def test_cg1r_laplace128_full_size_fixed_iterations(orc, h, kind, q):
+    """The 128^3 / p = 8 workload at its full size, 3 and 4 iterations,
+    eta = inf and eta = 1e4."""
+    A, B, _ = W.build_workload("laplace3d_128_s8")
+    for k, eta in ((3, np.inf), (4, 1e4)):
+        say("cg1r 128^3 fixed", kind, k, eta)
+        X, info = gpu_cg1r(h, A, B, kind=kind, q=q, tol=0.0, maxit=k, eta=eta)
+        ro = orc.bcg1r(A, B, kind=kind, q=q, tol=0.0, maxit=k, eta=eta)
+        assert info["reorth"] == ro["reorth"]
+        assert rel(X, ro["X"]) < 1e-10
+
+
+def test_cg1r_laplace128_time_to_tol(h):
+    """Full solve at full size: the FP64 true residual meets 1e-10 and the
+    iteration count is within one of the two-reduction solver's."""
+    A, B, _ = W.build_workload("laplace3d_128_s8")
+    Ad, Bd = dev_csr(P, A), to_dev(B)
+    say("cg1r 128^3 solve")
+    X, info = P.bkry_cg1r_solve(h, Ad, Bd, tol=1e-10, maxit=3000, eta=1e4)
+    assert info["converged"] and max(info["true_relres"]) <= 2e-10
+    X2, i2 = P.bkry_cg_solve(h, Ad, Bd, tol=1e-10, maxit=3000, eta=1e4)
+    assert abs(info["iters"] - i2["iters"]) <= 1
+    say("cg1r 128^3 iters", info["iters"], "s", info["seconds"], "two-reduction", i2["iters"], i2["seconds"])
