@@ -118,9 +118,10 @@ def run(args):
     Ad = P.CsrMatrix.from_numpy(A.n, A.rowptr, A.colind, A.val, device=dev)
     Bd = torch.as_tensor(B).to(dev)
     opts = dict(kind="block", q=1, tol=1e-10, maxit=args.maxit, eta=1e4)
+    solve = P.bkry_cg1r_solve if args.solver == "cg1r" else P.bkry_cg_solve
 
     for w in range(args.warmup):
-        X, info = P.bkry_cg_solve(h, Ad, Bd, **opts)
+        X, info = solve(h, Ad, Bd, **opts)
         log(f"warmup {w}: iters {info['iters']} reorth {info['reorth']} {info['seconds']*1e3:.1f} ms")
     P.bkry_profile(h, True, kernels=[P.PROF_CG_SPMM], every=PROF_EVERY)
     for k in range(4):
@@ -130,7 +131,7 @@ def run(args):
     iters = 0
     infos = []
     for k in range(args.steps):
-        X, info = P.bkry_cg_solve(h, Ad, Bd, **opts)
+        X, info = solve(h, Ad, Bd, **opts)
         iters += info["iters"]
         infos.append(info)
         log(f"step {k}: iters {info['iters']} reorth {info['reorth']} {info['seconds']*1e3:.1f} ms "
@@ -146,7 +147,7 @@ def run(args):
     P.bkry_profile(h, True)
     for k in range(4):
         P.bkry_profile_read(h, k, reset=True)
-    P.bkry_cg_solve(h, Ad, Bd, **opts)
+    solve(h, Ad, Bd, **opts)
     upd_ms, upd_n = P.bkry_profile_read(h, P.PROF_CG_UPDATE)
     pup_ms, pup_n = P.bkry_profile_read(h, P.PROF_CG_PUPDATE)
     sp2_ms, sp2_n = P.bkry_profile_read(h, P.PROF_CG_SPMM)
@@ -155,11 +156,19 @@ def run(args):
     sp_bytes = spmm_bytes(A, s)
     sp_avg = spmm_ms / max(spmm_n, 1) * 1e-3
     achieved = sp_bytes / sp_avg / 1e9
-    upd_gbs = 3 * blk / (upd_ms / max(upd_n, 1) * 1e-3) / 1e9
-    # the direction update moves 3 blocks (P, R read, P_{k+1} written) and, every
-    # other iteration, 3 more (X read and written, P_{k-1} read): 4.5 on average
-    pup_gbs = 4.5 * blk / (pup_ms / max(pup_n, 1) * 1e-3) / 1e9
-    iter_bytes = sp_bytes + 7.5 * blk        # + residual pass (3 blocks) + direction pass (4.5 blocks)
+    if args.solver == "cg1r":
+        # fused pass: R, U, P, Q read, P, Q, R written, X read and written every
+        # other iteration: 8 blocks on average
+        upd_gbs = 8 * blk / (upd_ms / max(upd_n, 1) * 1e-3) / 1e9
+        iter_bytes = sp_bytes + 8 * blk
+        per_kernel = {"fused_pass": round(upd_gbs, 1)}
+    else:
+        upd_gbs = 3 * blk / (upd_ms / max(upd_n, 1) * 1e-3) / 1e9
+        # the direction update moves 3 blocks (P, R read, P_{k+1} written) and, every
+        # other iteration, 3 more (X read and written, P_{k-1} read): 4.5 on average
+        pup_gbs = 4.5 * blk / (pup_ms / max(pup_n, 1) * 1e-3) / 1e9
+        iter_bytes = sp_bytes + 7.5 * blk        # + residual pass (3 blocks) + direction pass (4.5 blocks)
+        per_kernel = {"residual_update_gram": round(upd_gbs, 1), "direction_update": round(pup_gbs, 1)}
     traffic = pmc_traffic()
     result = {
         "metric": METRIC,
@@ -175,7 +184,9 @@ def run(args):
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "laplace3d_128_s8: 3D 7-point Laplacian 128^3 (n=2097152, nnz=14581760), "
-                               "p=8 uniform[-1,1] seed 1002, block CG, block subalgebra, eta=1e4, tol=1e-10, X0=0",
+                               "p=8 uniform[-1,1] seed 1002, "
+                               + ("one-reduction block CG" if args.solver == "cg1r" else "block CG")
+                               + ", block subalgebra, eta=1e4, tol=1e-10, X0=0",
                    "global_batch": s, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4),
@@ -190,7 +201,7 @@ def run(args):
         "cg_iteration_GBps_algorithmic": round(iter_bytes * value / 1e9, 1),
         "kernels_GBps": {"spmm_alpha_gram": round(achieved, 1),
                          "spmm_alpha_gram_all_timed": round(sp_bytes / (sp2_ms / max(sp2_n, 1) * 1e-3) / 1e9, 1),
-                         "residual_update_gram": round(upd_gbs, 1), "direction_update": round(pup_gbs, 1)},
+                         **per_kernel},
     }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
@@ -260,6 +271,32 @@ def extras(P, W, h, dev, A, Ad, Bd, args):
         log("tsqr", ex["tsqr_4194304x32"])
     except Exception as e:  # report, do not hide
         ex["tsqr_4194304x32"] = dict(error=str(e))
+    # one-reduction block CG on the same 128^3 workload (same options as the headline solve)
+    try:
+        P.bkry_cg1r_solve(h, Ad, Bd, kind="block", tol=1e-10, maxit=args.maxit, eta=1e4)
+        X1, i1 = P.bkry_cg1r_solve(h, Ad, Bd, kind="block", tol=1e-10, maxit=args.maxit, eta=1e4)
+        P.bkry_profile(h, True)
+        for k in range(4):
+            P.bkry_profile_read(h, k, reset=True)
+        P.bkry_cg1r_solve(h, Ad, Bd, kind="block", tol=1e-10, maxit=args.maxit, eta=1e4)
+        sp_ms, sp_n = P.bkry_profile_read(h, P.PROF_CG_SPMM)
+        fu_ms, fu_n = P.bkry_profile_read(h, P.PROF_CG_UPDATE)
+        P.bkry_profile(h, False)
+        blk = A.n * s * 8
+        # fused pass: R, U, P, Q read, P, Q, R written, X read and written every
+        # other iteration: 8 blocks on average
+        ex["cg1r_laplace3d_128_s8"] = dict(
+            iters=i1["iters"], reorth=i1["reorth"], seconds=round(i1["seconds"], 4),
+            iters_per_s=round(i1["iters"] / i1["seconds"], 1), converged=i1["converged"],
+            true_relres_max=max(i1["true_relres"]),
+            spmm_us=round(sp_ms / max(sp_n, 1) * 1e3, 2),
+            spmm_GBps=round(spmm_bytes(A, s) / (sp_ms / max(sp_n, 1) * 1e-3) / 1e9, 1),
+            fused_pass_us=round(fu_ms / max(fu_n, 1) * 1e3, 2),
+            fused_pass_GBps=round(8 * blk / (fu_ms / max(fu_n, 1) * 1e-3) / 1e9, 1))
+        log("cg1r", ex["cg1r_laplace3d_128_s8"])
+        del X1
+    except Exception as e:
+        ex["cg1r_laplace3d_128_s8"] = dict(error=str(e))
     # block GMRes(30): one cycle on the convection-diffusion workload
     try:
         Ac, Bc, _ = W.build_workload("convdiff2d_1024_s8")
@@ -371,10 +408,12 @@ def main():
     ap.add_argument("--extras", dest="extras", action="store_true", default=True)
     ap.add_argument("--no-extras", dest="extras", action="store_false")
     ap.add_argument("--copy-probe", action="store_true")
+    ap.add_argument("--solver", choices=["cg", "cg1r"], default="cg",
+                    help="block CG of the timed solves: two reductions per iteration (default) or one")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: this build runs the whole hot path on a single MI355X "
+        print("bench.py measures one GPU only: the solvers run on a single MI355X "
               "(no multi-GPU path); run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
     if args.copy_probe:
