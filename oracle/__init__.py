@@ -62,6 +62,10 @@ def lib():
             "or_reortho_fires": (i32, [dbl, dbl, dbl]),
             "or_bcg": (i32, [i64, ptr, ptr, ptr, i32, i32, i32, ptr, ptr, dbl, i32, dbl, dbl, ptr, ptr, ptr, i32,
                              ptr, ptr, i32, ptr]),
+            "or_color_greedy": (i32, [i64, ptr, ptr, ptr, ptr]),
+            "or_ssor_apply": (i32, [i64, ptr, ptr, ptr, ptr, i32, dbl, i32, ptr, ptr]),
+            "or_bcg_ssor": (i32, [i64, ptr, ptr, ptr, i32, i32, i32, ptr, ptr, dbl, i32, dbl, dbl, ptr, ptr, ptr,
+                                  i32, ptr, i32, dbl]),
             "or_bcg1r": (i32, [i64, ptr, ptr, ptr, i32, i32, i32, ptr, ptr, dbl, i32, dbl, dbl, ptr, ptr, ptr, i32,
                                ptr]),
             "or_lu_solve": (i32, [i32, i32, i32, ptr, ptr, ptr]),
@@ -223,6 +227,50 @@ def bcg(A, B, X0=None, kind="block", q=1, tol=1e-10, maxit=1000, eta=0.0, eps=No
                 hist=hist[:min(it, hist_cap)] if hist_cap else None,
                 Pk=Pk[:min(it, record_blocks)] if record_blocks else None,
                 Rk=Rk[:min(it, record_blocks)] if record_blocks else None)
+
+
+def color_greedy(A, prio):
+    """Greedy colouring in decreasing priority (prio: n uint32).  Returns
+    (colors int32[n], ncolors)."""
+    n, rp, ci, _ = _csr(A)
+    pr = np.ascontiguousarray(prio, dtype=np.uint32)
+    if pr.shape != (n,):
+        raise ValueError("prio must hold n entries")
+    colors = np.zeros(n, dtype=np.int32)
+    nc = lib().or_color_greedy(n, _p(rp), _p(ci), _p(pr), _p(colors))
+    return colors, nc
+
+
+def ssor_apply(A, colors, omega, R):
+    """Z = M^-1 R for the multicolour SSOR preconditioner.  Returns (status, Z)."""
+    n, rp, ci, v = _csr(A)
+    R = _f64(R)
+    cl = np.ascontiguousarray(colors, dtype=np.int32)
+    Z = np.zeros_like(R)
+    st = lib().or_ssor_apply(n, _p(rp), _p(ci), _p(v), _p(cl), int(cl.max()) + 1 if n else 0, float(omega),
+                             R.shape[1], _p(R), _p(Z))
+    return st, Z
+
+
+def bcg_ssor(A, B, colors, omega, X0=None, kind="block", q=1, tol=1e-10, maxit=1000, eta=0.0, eps=None,
+             hist_cap=0):
+    """Block CG preconditioned by multicolour SSOR.  Returns dict(status, X,
+    iters, reorth, converged, relres, hist)."""
+    n, rp, ci, v = _csr(A)
+    B = _f64(B)
+    s = B.shape[1]
+    X = np.zeros_like(B) if X0 is None else _f64(X0).copy()
+    cl = np.ascontiguousarray(colors, dtype=np.int32)
+    info = np.zeros(4, dtype=np.int32)
+    relres = np.zeros(s)
+    hist = np.zeros(max(hist_cap, 1))
+    eps = eps_f64() if eps is None else eps
+    st = lib().or_bcg_ssor(n, _p(rp), _p(ci), _p(v), s, _kind(kind), q, _p(B), _p(X), tol, maxit, eta, eps,
+                           _p(info), _p(relres), _p(hist) if hist_cap else None, hist_cap, _p(cl),
+                           int(cl.max()) + 1, float(omega))
+    it = int(info[0])
+    return dict(status=st, X=X, iters=it, reorth=int(info[1]), converged=bool(info[2]), relres=relres,
+                hist=hist[:min(it, hist_cap)] if hist_cap else None)
 
 
 def bcg1r(A, B, X0=None, kind="block", q=1, tol=1e-10, maxit=1000, eta=0.0, eps=None, hist_cap=0, minv=None):

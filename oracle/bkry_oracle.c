@@ -444,6 +444,114 @@ static void apply_minv(i64 n, int s, const double* minv, const double* R, double
 }
 
 /* ------------------------------------------------------------------------ */
+/* Multicolour ordering for SSOR: the greedy colouring in order of           */
+/* decreasing priority (ties: smaller row index first).  Each row takes the  */
+/* smallest colour that no already coloured neighbour (an off-diagonal       */
+/* column of its row) holds.  For a symmetric pattern this is the colouring  */
+/* the parallel Jones-Plassmann rounds produce with the same priorities.     */
+/* Returns the number of colours, or OR_E_INVALID (bad column index).        */
+/* ------------------------------------------------------------------------ */
+static int cmp_u64(const void* a, const void* b) {
+  uint64_t x = *(const uint64_t*)a, y = *(const uint64_t*)b;
+  return x < y ? -1 : (x > y ? 1 : 0);
+}
+
+int or_color_greedy(i64 n, const int32_t* rowptr, const int32_t* colind, const uint32_t* prio, int32_t* colors) {
+  uint64_t* key = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)(n > 0 ? n : 1));
+  int32_t* mark = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n + 2));
+  if (!key || !mark) { free(key); free(mark); return OR_E_INVALID; }
+  for (i64 i = 0; i < n; ++i) {
+    key[i] = ((uint64_t)(~prio[i]) << 32) | (uint64_t)i;  /* ascending key = priority descending */
+    colors[i] = -1;
+  }
+  qsort(key, (size_t)n, sizeof(uint64_t), cmp_u64);
+  for (i64 i = 0; i < n + 2; ++i) mark[i] = -1;
+  int ncol = 0, st = OR_OK;
+  for (i64 t = 0; t < n; ++t) {
+    const i64 v = (i64)(key[t] & 0xffffffffu);
+    for (int32_t k = rowptr[v]; k < rowptr[v + 1]; ++k) {
+      const int32_t u = colind[k];
+      if (u < 0 || u >= n) { st = OR_E_INVALID; goto out; }
+      if (u != v && colors[u] >= 0) mark[colors[u]] = (int32_t)v;
+    }
+    int c = 0;
+    while (mark[c] == (int32_t)v) ++c;
+    colors[v] = c;
+    if (c + 1 > ncol) ncol = c + 1;
+  }
+out:
+  free(key);
+  free(mark);
+  return st != OR_OK ? st : ncol;
+}
+
+/* Multicolour symmetric SOR preconditioner (the SSOR-type preconditioners of */
+/* the experiments, Ch. 4), on the rows ordered by colour: with A = L + D + U */
+/* split in that order (L: entries whose column has a smaller colour),        */
+/*   M = (D + omega L) D^-1 (D + omega U) / (omega (2 - omega)),              */
+/* SPD for SPD A and 0 < omega < 2.  Z = M^-1 R by a forward sweep           */
+/* y = (D + omega L)^-1 R, colour by colour upwards, then a backward sweep    */
+/* Z = (D + omega U)^-1 (omega (2 - omega) D y), colour by colour downwards   */
+/* (Z computed in place over y).  Rows of one colour share no entry, so each  */
+/* row only reads finished values.  Duplicate diagonal entries are summed.    */
+/* OR_E_INVALID: a row without a positive diagonal, or two coupled rows of   */
+/* one colour.                                                               */
+int or_ssor_apply(i64 n, const int32_t* rowptr, const int32_t* colind, const double* val, const int32_t* colors,
+                  int ncolors, double omega, int s, const double* R, double* Z) {
+  double* d = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+  if (!d) return OR_E_INVALID;
+  for (i64 i = 0; i < n; ++i) {
+    double di = 0.0;
+    for (int32_t k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+      const int32_t j = colind[k];
+      if (j == i) di += val[k];
+      else if (colors[j] == colors[i]) { free(d); return OR_E_INVALID; }
+    }
+    if (!(di > 0.0)) { free(d); return OR_E_INVALID; }
+    d[i] = di;
+  }
+  for (int c = 0; c < ncolors; ++c)
+    for (i64 i = 0; i < n; ++i) {
+      if (colors[i] != c) continue;
+      for (int col = 0; col < s; ++col) {
+        double acc = R[i * s + col];
+        for (int32_t k = rowptr[i]; k < rowptr[i + 1]; ++k)
+          if (colors[colind[k]] < c) acc -= (omega * val[k]) * Z[(i64)colind[k] * s + col];
+        Z[i * s + col] = acc / d[i];
+      }
+    }
+  const double f = omega * (2.0 - omega);
+  for (int c = ncolors - 1; c >= 0; --c)
+    for (i64 i = 0; i < n; ++i) {
+      if (colors[i] != c) continue;
+      for (int col = 0; col < s; ++col) {
+        double acc = (f * d[i]) * Z[i * s + col];
+        for (int32_t k = rowptr[i]; k < rowptr[i + 1]; ++k)
+          if (colors[colind[k]] > c) acc -= (omega * val[k]) * Z[(i64)colind[k] * s + col];
+        Z[i * s + col] = acc / d[i];
+      }
+    }
+  free(d);
+  return OR_OK;
+}
+
+/* The preconditioner of the block CG: diagonal (minv, NULL = identity) or    */
+/* multicolour SSOR (ssor non-NULL).                                          */
+typedef struct {
+  const int32_t* rowptr;
+  const int32_t* colind;
+  const double* val;
+  const int32_t* colors;
+  int ncolors;
+  double omega;
+} or_ssor_t;
+
+static void apply_prec(i64 n, int s, const double* minv, const or_ssor_t* ss, const double* R, double* Z) {
+  if (ss) (void)or_ssor_apply(n, ss->rowptr, ss->colind, ss->val, ss->colors, ss->ncolors, ss->omega, s, R, Z);
+  else apply_minv(n, s, minv, R, Z);
+}
+
+/* ------------------------------------------------------------------------ */
 /* Block CG with adaptive residual re-orthonormalisation (Algorithm          */
 /* "BCG Method with Adaptive Residual Re-Orthonormalization", Ch. 4) with a  */
 /* diagonal preconditioner M: minv[i] = (M^-1)_ii, or minv = NULL for M = I  */
@@ -472,9 +580,10 @@ static void apply_minv(i64 n, int s, const double* minv, const double* R, double
 /* Pk/Rk (optional, cap_blocks n x s blocks) record P^k and the true residual */
 /* R^k = R-bar^k sigma^k for k = 0, 1, ... (for invariant checks).           */
 /* ------------------------------------------------------------------------ */
-int or_bcg(i64 n, const int32_t* rowptr, const int32_t* colind, const double* val, int s, int kind, int q,
-           const double* B, double* X, double tol, int maxit, double eta, double eps, int32_t* info,
-           double* relres, double* hist, int hist_cap, double* Pk, double* Rk, int cap_blocks, const double* minv) {
+static int bcg_impl(i64 n, const int32_t* rowptr, const int32_t* colind, const double* val, int s, int kind, int q,
+                    const double* B, double* X, double tol, int maxit, double eta, double eps, int32_t* info,
+                    double* relres, double* hist, int hist_cap, double* Pk, double* Rk, int cap_blocks,
+                    const double* minv, const or_ssor_t* ssor) {
   if (!valid_subalg(s, kind, q) || s > 64 || n < group_width(s, kind, q)) return OR_E_INVALID;
   size_t blk = (size_t)(n * s);
   double* R = (double*)calloc(blk, sizeof(double));
@@ -506,7 +615,7 @@ int or_bcg(i64 n, const int32_t* rowptr, const int32_t* colind, const double* va
   } else {
     eye(s, sigma);
   }
-  apply_minv(n, s, minv, R, P);                       /* P = M^-1 R-bar */
+  apply_prec(n, s, minv, ssor, R, P);                 /* P = M^-1 R-bar */
   or_bdot(n, s, kind, q, P, R, rho);
 
   for (int k = 0; k < maxit; ++k) {
@@ -554,7 +663,7 @@ int or_bcg(i64 n, const int32_t* rowptr, const int32_t* colind, const double* va
     if (hist && k < hist_cap) hist[k] = m;
     if (isnan(m)) { st = OR_E_NONFINITE; goto done; }
     if (m <= tol) { conv = 1; break; }
-    apply_minv(n, s, minv, R, T);                     /* Z = M^-1 R-bar */
+    apply_prec(n, s, minv, ssor, R, T);               /* Z = M^-1 R-bar */
     or_bdot(n, s, kind, q, T, R, rho_new);            /* rho' = <Z, R-bar>_S */
     mtm(s, gamma, rho_new, tmp);                      /* beta = rho^-1 gamma^T rho' */
     st = or_chol_solve(s, kind, q, rho, tmp, beta);
@@ -569,6 +678,29 @@ done:
   free(R); free(P); free(Qb); free(T);
   if (st != OR_OK) return st;
   return conv ? OR_OK : OR_NOT_CONVERGED;
+}
+
+int or_bcg(i64 n, const int32_t* rowptr, const int32_t* colind, const double* val, int s, int kind, int q,
+           const double* B, double* X, double tol, int maxit, double eta, double eps, int32_t* info,
+           double* relres, double* hist, int hist_cap, double* Pk, double* Rk, int cap_blocks, const double* minv) {
+  return bcg_impl(n, rowptr, colind, val, s, kind, q, B, X, tol, maxit, eta, eps, info, relres, hist, hist_cap, Pk,
+                  Rk, cap_blocks, minv, NULL);
+}
+
+/* The same block CG preconditioned by multicolour SSOR (or_ssor_apply) with */
+/* the given colouring and omega.                                             */
+int or_bcg_ssor(i64 n, const int32_t* rowptr, const int32_t* colind, const double* val, int s, int kind, int q,
+                const double* B, double* X, double tol, int maxit, double eta, double eps, int32_t* info,
+                double* relres, double* hist, int hist_cap, const int32_t* colors, int ncolors, double omega) {
+  const or_ssor_t ss = {rowptr, colind, val, colors, ncolors, omega};
+  double* T = (double*)calloc((size_t)(n * s), sizeof(double));
+  double* Zt = (double*)calloc((size_t)(n * s), sizeof(double));
+  if (!T || !Zt) { free(T); free(Zt); return OR_E_INVALID; }
+  int st = or_ssor_apply(n, rowptr, colind, val, colors, ncolors, omega, s, T, Zt);  /* validates the colouring */
+  free(T); free(Zt);
+  if (st != OR_OK) return st;
+  return bcg_impl(n, rowptr, colind, val, s, kind, q, B, X, tol, maxit, eta, eps, info, relres, hist, hist_cap, NULL,
+                  NULL, 0, NULL, &ss);
 }
 
 /* ------------------------------------------------------------------------ */

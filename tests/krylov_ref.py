@@ -74,6 +74,29 @@ def galerkin_minimiser_prec(A, B, X0, k, kind, q, minv):
     return X0 + (U @ c).reshape((n, s), order="F")
 
 
+def galerkin_minimiser_precmat(A, B, X0, k, kind, q, Minv):
+    """As galerkin_minimiser_prec for a dense M^-1 (any SPD preconditioner)."""
+    n, s = B.shape
+    R0 = B - A @ X0
+    U = krylov_basis(Minv @ A, Minv @ R0, k, kind, q)
+    Ahat = np.kron(np.eye(s), A)
+    c = np.linalg.solve(U.T @ Ahat @ U, U.T @ R0.reshape(-1, order="F"))
+    return X0 + (U @ c).reshape((n, s), order="F")
+
+
+def ssor_matrix(A, colors, omega):
+    """The multicolour SSOR matrix written out from its definition: with the
+    rows ordered by colour, A = L + D + U (L: columns of smaller colour),
+    M = (D + omega L) D^-1 (D + omega U) / (omega (2 - omega))."""
+    d = np.diag(A).copy()
+    lower = colors[None, :] < colors[:, None]
+    upper = colors[None, :] > colors[:, None]
+    L = np.where(lower, A, 0.0)
+    U = np.where(upper, A, 0.0)
+    D = np.diag(d)
+    return (D + omega * L) @ np.diag(1.0 / d) @ (D + omega * U) / (omega * (2.0 - omega))
+
+
 def residual_minimiser(A, B, X0, k, kind, q=1):
     """argmin over X0 + K_k^S(A, R0) of |B - A X|_F (the block GMRes iterate)."""
     n, s = B.shape

@@ -180,6 +180,11 @@ def gaussian_block(n: int, s: int, seed: int) -> np.ndarray:
     return np.random.default_rng(seed).standard_normal((n, s))
 
 
+def color_priorities(n: int, seed: int) -> np.ndarray:
+    """Uniform uint32 priorities for the multicolour ordering (one per row)."""
+    return np.random.default_rng(seed).integers(0, 1 << 32, size=n, dtype=np.uint32)
+
+
 def random_spd_csr(n: int, density: float, seed: int, shift: float = 1.0) -> Csr:
     """Small random sparse SPD matrix (symmetric pattern, diagonally dominant),
     for tests over shapes that are not grids.  Integer-valued off-diagonals."""
