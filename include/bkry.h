@@ -187,6 +187,36 @@ int bkry_cg_solve(bkry_handle h, const bkry_csr* A, int32_t p, bkry_subalg S, co
 int bkry_pcg_solve(bkry_handle h, const bkry_csr* A, int32_t p, bkry_subalg S, const double* B, double* X,
                    const double* minv, double tol, int32_t maxit, double eta, bkry_info* info);
 
+/* Multicolour ordering for the SSOR preconditioner: colors[i] [device, n
+ * int32, caller-owned] = the greedy colouring of the graph of A in order of
+ * decreasing prio[i] [device, n uint32] (ties: smaller row first), computed by
+ * parallel Jones-Plassmann rounds; *ncolors [host] = number of colours.  The
+ * pattern of A must be symmetric (the SSOR calls reject a colouring that
+ * leaves two coupled rows in one colour).  Values of A are not read.
+ * BKRY_E_INVALID for a column index outside [0, n) or more than 4096
+ * colours. */
+int bkry_color(bkry_handle h, const bkry_csr* A, const uint32_t* prio, int32_t* colors, int32_t* ncolors);
+
+/* Multicolour SSOR preconditioner (the SSOR-type preconditioners of the
+ * experiments, Ch. 4): with the rows ordered by colour and A = L + D + U in
+ * that order (L: entries whose column has a smaller colour),
+ * M = (D + omega L) D^-1 (D + omega U) / (omega (2 - omega)), SPD for SPD A and
+ * 0 < omega < 2.  Z = M^-1 R by a forward and a backward colour sweep (one
+ * launch per colour and sweep).  R, Z [device, n x p row-major FP64, no
+ * aliasing]; colors [device, n int32] as from bkry_color.  BKRY_E_INVALID if
+ * two coupled rows share a colour, a colour is outside [0, 4096), a diagonal
+ * entry is missing or not positive, or omega is outside (0, 2). */
+int bkry_ssor_apply(bkry_handle h, const bkry_csr* A, int32_t p, const int32_t* colors, double omega,
+                    const double* R, double* Z);
+
+/* Block CG with adaptive residual re-orthonormalisation preconditioned by the
+ * multicolour SSOR of bkry_ssor_apply (colors, omega as there); FP64;
+ * otherwise as bkry_pcg_solve.  The stopping test uses the unpreconditioned
+ * residual. */
+int bkry_pcg_ssor_solve(bkry_handle h, const bkry_csr* A, int32_t p, bkry_subalg S, const double* B, double* X,
+                        const int32_t* colors, double omega, double tol, int32_t maxit, double eta,
+                        bkry_info* info);
+
 /* Block CG with one reduction per iteration (Algorithm "BCG with One
  * Reduction", Ch. 8): the same iteration as bkry_cg_solve in exact
  * arithmetic, with U = A R-bar formed right after the residual update,

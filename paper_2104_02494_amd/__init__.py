@@ -58,7 +58,7 @@ class bkry_info(ctypes.Structure):
 EXPORTS = ["bkry_create", "bkry_destroy", "bkry_set_stream", "bkry_synchronize", "bkry_last_error",
            "bkry_profile", "bkry_profile_read", "bkry_set_spmm_format", "bkry_spmm",
            "bkry_spmm_f32", "bkry_bdot", "bkry_bdot_f32", "bkry_tsqr", "bkry_cg_solve", "bkry_pcg_solve",
-           "bkry_cg1r_solve", "bkry_jacobi_minv", "bkry_bicgstab_solve", "bkry_gmres_solve", "bkry_sddmm", "bkry_csr_transpose"]
+           "bkry_cg1r_solve", "bkry_color", "bkry_ssor_apply", "bkry_pcg_ssor_solve", "bkry_jacobi_minv", "bkry_bicgstab_solve", "bkry_gmres_solve", "bkry_sddmm", "bkry_csr_transpose"]
 
 _lib = None
 
@@ -90,6 +90,9 @@ def lib():
             "bkry_cg_solve": [H, csr_p, i32, bkry_subalg, vp, vp, dbl, i32, dbl, i32, info_p],
             "bkry_pcg_solve": [H, csr_p, i32, bkry_subalg, vp, vp, vp, dbl, i32, dbl, info_p],
             "bkry_cg1r_solve": [H, csr_p, i32, bkry_subalg, vp, vp, dbl, i32, dbl, info_p],
+            "bkry_color": [H, csr_p, vp, vp, ctypes.POINTER(i32)],
+            "bkry_ssor_apply": [H, csr_p, i32, vp, dbl, vp, vp],
+            "bkry_pcg_ssor_solve": [H, csr_p, i32, bkry_subalg, vp, vp, vp, dbl, dbl, i32, dbl, info_p],
             "bkry_jacobi_minv": [H, csr_p, vp],
             "bkry_bicgstab_solve": [H, csr_p, i32, bkry_subalg, vp, vp, dbl, i32, dbl, info_p],
             "bkry_gmres_solve": [H, csr_p, i32, bkry_subalg, vp, vp, dbl, i32, i32, info_p],
@@ -282,6 +285,54 @@ def bkry_cg1r_solve(h: Handle, A: CsrMatrix, B: torch.Tensor, X: torch.Tensor | 
     d = A.desc()
     rc = lib().bkry_cg1r_solve(h.h, ctypes.byref(d), p, _subalg(kind, q), _ptr(B), _ptr(X), float(tol), int(maxit),
                                float(eta), ctypes.byref(info))
+    h._check(rc, allow=(OK, NOT_CONVERGED))
+    return X, _info_dict(rc, info, hist, rel, trel, p)
+
+
+def bkry_color(h: Handle, A: CsrMatrix, prio: torch.Tensor):
+    """Greedy multicolour ordering in decreasing priority (prio: uint32 device
+    vector of n entries, passed as int32 storage).  Returns (colors int32
+    device tensor, ncolors)."""
+    if not (prio.is_cuda and prio.dtype in (torch.int32, torch.uint32) and prio.is_contiguous()
+            and prio.numel() == A.n):
+        raise ValueError("prio must be a contiguous 32-bit device vector of n entries")
+    colors = torch.empty(A.n, dtype=torch.int32, device=A.rowptr.device)
+    nc = ctypes.c_int32(0)
+    h._sync_stream()
+    d = A.desc()
+    h._check(lib().bkry_color(h.h, ctypes.byref(d), _ptr(prio), _ptr(colors), ctypes.byref(nc)))
+    return colors, int(nc.value)
+
+
+def _colors(A, colors):
+    if not (colors.is_cuda and colors.dtype == torch.int32 and colors.is_contiguous() and colors.numel() == A.n):
+        raise ValueError("colors must be a contiguous int32 device vector of n entries")
+
+
+def bkry_ssor_apply(h: Handle, A: CsrMatrix, colors: torch.Tensor, omega: float, R: torch.Tensor) -> torch.Tensor:
+    """Z = M^-1 R for the multicolour SSOR preconditioner."""
+    _block(R)
+    _colors(A, colors)
+    Z = torch.empty_like(R)
+    h._sync_stream()
+    d = A.desc()
+    h._check(lib().bkry_ssor_apply(h.h, ctypes.byref(d), R.shape[1], _ptr(colors), float(omega), _ptr(R), _ptr(Z)))
+    return Z
+
+
+def bkry_pcg_ssor_solve(h: Handle, A: CsrMatrix, B: torch.Tensor, colors: torch.Tensor, omega=1.0,
+                        X: torch.Tensor | None = None, kind="block", q=1, tol=1e-10, maxit=1000, eta=1e4,
+                        hist_cap=0):
+    """Block CG preconditioned by multicolour SSOR (FP64).  Returns (X, info)."""
+    _block(B)
+    _colors(A, colors)
+    X = torch.zeros_like(B) if X is None else _block(X)
+    p = B.shape[1]
+    info, hist, rel, trel = _info(p, hist_cap)
+    h._sync_stream()
+    d = A.desc()
+    rc = lib().bkry_pcg_ssor_solve(h.h, ctypes.byref(d), p, _subalg(kind, q), _ptr(B), _ptr(X), _ptr(colors),
+                                   float(omega), float(tol), int(maxit), float(eta), ctypes.byref(info))
     h._check(rc, allow=(OK, NOT_CONVERGED))
     return X, _info_dict(rc, info, hist, rel, trel, p)
 

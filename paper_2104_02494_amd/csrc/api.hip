@@ -391,9 +391,16 @@ int bkry_tsqr(bkry_handle h, int64_t n, int32_t p, bkry_subalg S, double* X, dou
 }
 
 namespace {
+int ssor_fail(bkry_handle h, int err) {
+  if (err == 1) return fail(h, BKRY_E_INVALID, "a colour is outside [0, 4096)");
+  if (err == 2) return fail(h, BKRY_E_INVALID, "two rows of one colour are coupled (not a colouring of A), or a "
+                                               "column index is outside [0, n)");
+  return fail(h, BKRY_E_INVALID, "a diagonal entry of A is missing, not positive or not finite");
+}
+
 int cg_solve_impl(bkry_handle h, const bkry_csr* A, int32_t p, bkry_subalg S, const double* B, double* X,
                   double tol, int32_t maxit, double eta, int32_t prec, const double* minv, bkry_info* info,
-                  bool one_reduction = false) {
+                  bool one_reduction = false, const int32_t* ssor_colors = nullptr, double omega = 1.0) {
   int rc = begin(h);
   Sub sub;
   if (!rc) rc = check_csr(h, A, true);
@@ -424,6 +431,7 @@ int cg_solve_impl(bkry_handle h, const bkry_csr* A, int32_t p, bkry_subalg S, co
     c.take<int32_t>(4);
     c.take<int32_t>(ne);
     c.take<double>(ne);
+    if (ssor_colors) ssor_carve(c, n);
     rc = ensure_ws(h, c.off);
     if (rc) return rc;
     Carver w{h->ws};
@@ -433,11 +441,21 @@ int cg_solve_impl(bkry_handle h, const bkry_csr* A, int32_t p, bkry_subalg S, co
     int32_t* tfl = w.take<int32_t>(4);
     int32_t* ecol = w.take<int32_t>(ne);
     double* eval = w.take<double>(ne);
+    SsorWs sw;
+    if (ssor_colors) sw = ssor_carve(w, n);
     CsrView v = view(A);
     rc = ell_build<double, double>(h, A, A->val, W, ecol, eval, v);
     if (rc) return rc;
+    SsorPlan plan;
+    if (ssor_colors) {
+      int err = 0;
+      API_HIP(ssor_plan_build(v, ssor_colors, omega, sw, h->stream, plan, err), "ssor plan");
+      if (err) return ssor_fail(h, err);
+    }
     CgResult r;
-    hipError_t e = one_reduction
+    hipError_t e = ssor_colors ? pcg_ssor_run(v, sub, B, X, tol, maxit, eta, hist_cap, cb, plan, h->stream,
+                                              h->hflags, r, h->prof)
+                   : one_reduction
                        ? cg1r_run(v, sub, B, X, tol, maxit, eta, hist_cap, cb, h->stream, h->hflags, r, h->prof)
                        : cg_run<double>(v, sub, B, X, tol, maxit, eta, DBL_EPSILON, hist_cap, cb, h->stream,
                                         h->hflags, r, h->prof, minv);
@@ -522,6 +540,81 @@ int bkry_cg_solve(bkry_handle h, const bkry_csr* A, int32_t p, bkry_subalg S, co
 int bkry_cg1r_solve(bkry_handle h, const bkry_csr* A, int32_t p, bkry_subalg S, const double* B, double* X,
                     double tol, int32_t maxit, double eta, bkry_info* info) {
   return cg_solve_impl(h, A, p, S, B, X, tol, maxit, eta, BKRY_F64, nullptr, info, true);
+}
+
+int bkry_pcg_ssor_solve(bkry_handle h, const bkry_csr* A, int32_t p, bkry_subalg S, const double* B, double* X,
+                        const int32_t* colors, double omega, double tol, int32_t maxit, double eta,
+                        bkry_info* info) {
+  if (!h) return BKRY_E_INVALID;
+  if (!colors) return fail(h, BKRY_E_INVALID, "null colors");
+  if (!(omega > 0.0 && omega < 2.0)) return fail(h, BKRY_E_INVALID, "omega must be in (0, 2)");
+  return cg_solve_impl(h, A, p, S, B, X, tol, maxit, eta, BKRY_F64, nullptr, info, false, colors, omega);
+}
+
+int bkry_color(bkry_handle h, const bkry_csr* A, const uint32_t* prio, int32_t* colors, int32_t* ncolors) {
+  int rc = begin(h);
+  if (!rc) rc = check_csr(h, A, false);
+  if (!rc && (!prio || !colors || !ncolors)) rc = fail(h, BKRY_E_INVALID, "null prio, colors or ncolors");
+  if (rc) return rc;
+  constexpr int kMaxRounds = 4096;
+  const int64_t n = A->n;
+  Carver c;
+  c.take<int32_t>((size_t)n);
+  c.take<int32_t>(kMaxRounds);
+  c.take<int32_t>(4);
+  rc = ensure_ws(h, c.off);
+  if (rc) return rc;
+  Carver w{h->ws};
+  int32_t* state = w.take<int32_t>((size_t)n);
+  int32_t* more = w.take<int32_t>(kMaxRounds);
+  int32_t* misc = w.take<int32_t>(4);
+  API_HIP(hipMemsetAsync(state, 0xff, sizeof(int32_t) * (size_t)n, h->stream), "color");
+  API_HIP(hipMemsetAsync(more, 0, sizeof(int32_t) * kMaxRounds, h->stream), "color");
+  API_HIP(hipMemsetAsync(misc, 0, sizeof(int32_t) * 4, h->stream), "color");
+  const CsrView v = view(A);
+  int r = 0;
+  bool finished = false;
+  while (r < kMaxRounds && !finished) {
+    const int r1 = r + 16 < kMaxRounds ? r + 16 : kMaxRounds;
+    for (; r < r1; ++r) API_HIP(launch_jp_round(v, prio, state, r, more, misc + 1, h->stream), "color");
+    API_HIP(hipMemcpyAsync(h->hflags, more + r - 1, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream), "color");
+    API_HIP(hipMemcpyAsync(h->hflags + 1, misc + 1, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream), "color");
+    API_HIP(hipStreamSynchronize(h->stream), "color");
+    if (h->hflags[1]) return fail(h, BKRY_E_INVALID, "a CSR column index was outside [0, n)");
+    finished = h->hflags[0] == 0;
+  }
+  if (!finished) return fail(h, BKRY_E_INVALID, "the colouring did not finish within 4096 rounds");
+  API_HIP(launch_jp_final(n, state, colors, misc, h->stream), "color");
+  API_HIP(hipMemcpyAsync(h->hflags, misc, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream), "color");
+  API_HIP(hipStreamSynchronize(h->stream), "color");
+  *ncolors = h->hflags[0];
+  if (*ncolors > kMaxColors) return fail(h, BKRY_E_INVALID, "more than 4096 colours");
+  return BKRY_OK;
+}
+
+int bkry_ssor_apply(bkry_handle h, const bkry_csr* A, int32_t p, const int32_t* colors, double omega,
+                    const double* R, double* Z) {
+  int rc = begin(h);
+  if (!rc) rc = check_csr(h, A, true);
+  if (!rc && (p < 1 || p > kMaxS)) rc = fail(h, BKRY_E_INVALID, "p must be in [1, 32]");
+  if (!rc) rc = check_blocks(h, {R, Z});
+  if (!rc && !colors) rc = fail(h, BKRY_E_INVALID, "null colors");
+  if (!rc && R == Z) rc = fail(h, BKRY_E_INVALID, "Z must not alias R");
+  if (!rc && !(omega > 0.0 && omega < 2.0)) rc = fail(h, BKRY_E_INVALID, "omega must be in (0, 2)");
+  if (rc) return rc;
+  Carver c;
+  ssor_carve(c, A->n);
+  rc = ensure_ws(h, c.off);
+  if (rc) return rc;
+  Carver w{h->ws};
+  const SsorWs sw = ssor_carve(w, A->n);
+  SsorPlan plan;
+  int err = 0;
+  API_HIP(ssor_plan_build(view(A), colors, omega, sw, h->stream, plan, err), "ssor plan");
+  if (err) return ssor_fail(h, err);
+  API_HIP(launch_ssor_apply(plan, p, R, Z, nullptr, nullptr, nullptr, h->stream), "ssor apply");
+  API_HIP(hipStreamSynchronize(h->stream), "ssor apply");
+  return BKRY_OK;
 }
 
 int bkry_pcg_solve(bkry_handle h, const bkry_csr* A, int32_t p, bkry_subalg S, const double* B, double* X,

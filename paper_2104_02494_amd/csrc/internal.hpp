@@ -239,6 +239,47 @@ hipError_t launch_project(const double* G, double* out, Sub sub, hipStream_t st)
 hipError_t launch_cg_init(CgCtl* ctl, const double* G_R0, const double* G_rho, hipStream_t st);
 hipError_t launch_cg_reortho_fin(CgCtl* ctl, int s, const double* G, hipStream_t st);
 
+// ------------------------------------------------- multicolour SSOR ----
+constexpr int kMaxColors = 4096;
+// The preconditioner of one solve: A (FP64 CSR), its colouring, the
+// diagonal d, the rows bucketed by colour (perm[off[c] .. off[c+1]) hold the
+// rows of colour c) and omega.
+struct SsorPlan {
+  CsrView A;
+  const int32_t* colors = nullptr;
+  const double* d = nullptr;
+  const int32_t* perm = nullptr;
+  const int32_t* off = nullptr;
+  int ncolors = 0;
+  int64_t count_max = 0;  // rows of the largest colour
+  double omega = 1.0;
+};
+// One Jones-Plassmann round (state: -1 or (round << 16) | colour; more[round]
+// = 1 if a row is left uncoloured; bad = 1 for a column index outside [0, n)).
+hipError_t launch_jp_round(const CsrView& A, const uint32_t* prio, int32_t* state, int round, int32_t* more,
+                           int32_t* bad, hipStream_t st);
+hipError_t launch_jp_final(int64_t n, const int32_t* state, int32_t* colors, int32_t* ncolors, hipStream_t st);
+// Colouring check (bad[0]: colour outside [0, kMaxColors); bad[1]: coupled
+// rows of one colour or a bad column index; bad[2]: a row without a positive
+// diagonal), diagonal d, ncolors (atomic max, zeroed by the caller) and
+// colour counts (zeroed by the caller).
+hipError_t launch_ssor_check(const CsrView& A, const int32_t* colors, double* d, int32_t* ncolors, int32_t* count,
+                             int32_t* bad, hipStream_t st);
+hipError_t launch_ssor_bucket(int64_t n, const int32_t* colors, const int32_t* count, const int32_t* ncolors,
+                              int32_t* off, int32_t* cursor, int32_t* perm, hipStream_t st);
+// Z = M^-1 R (Z must not alias R); skipped if *skip_a or *skip_b, or if
+// need is given and *need == 0 (null pointers: no condition).
+hipError_t launch_ssor_apply(const SsorPlan& m, int s, const double* R, double* Z, const int32_t* skip_a,
+                             const int32_t* skip_b, const int32_t* need, hipStream_t st);
+// Gram partials X^T Y into partial (stride pstride per workgroup), no
+// reduction; skipped like launch_ssor_apply.
+hipError_t launch_gram_partials(int64_t n, int s, const double* X, const double* Y, double* partial, int nblk,
+                                int64_t pstride, const int32_t* skip_a, const int32_t* skip_b, hipStream_t st);
+// R~ = R - Q lambda with the Gram partials of R~ at stride pstride, without
+// the reduction (FP64).
+hipError_t launch_cg_update_partials(int64_t n, int s, double* R, const double* Q, const CgCtl* ctl, double* partial,
+                                     int nblk, int64_t pstride, hipStream_t st);
+
 // One-reduction block CG.  Fused pass of iteration k (runs only if lambda^k
 // was computed and the solve is live): P = R + P beta, Q = U + Q beta
 // (P = R, Q = U for k = 0), for odd k X += P_old (lambda sigma)_{k-1} +

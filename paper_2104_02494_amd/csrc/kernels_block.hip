@@ -650,7 +650,7 @@ template <typename T, int S, int VEC, bool PC>
 __global__ __launch_bounds__(kBlock) void cg_update_kernel(int64_t n, int s, T* __restrict__ R,
                                                             const T* __restrict__ Q, const CgCtl* ctl,
                                                             T* __restrict__ partial,
-                                                            const double* __restrict__ minv) {
+                                                            const double* __restrict__ minv, int64_t pstride) {
   using L = Layout<T, S, VEC>;
   constexpr int NW = kBlock / kWave;
   constexpr int RPB = NW * L::RPW;
@@ -702,7 +702,7 @@ __global__ __launch_bounds__(kBlock) void cg_update_kernel(int64_t n, int s, T* 
     gram_store<T, S, VEC>(gacc, s, partial, sh, 0, 2 * (int64_t)s * s);
     gram_store<T, S, VEC>(gacc2, s, partial + (int64_t)s * s, sh, 0, 2 * (int64_t)s * s);
   } else {
-    gram_store<T, S, VEC>(gacc, s, partial, sh);
+    gram_store<T, S, VEC>(gacc, s, partial, sh, 0, pstride);
   }
 }
 
@@ -714,15 +714,68 @@ hipError_t launch_cg_update(int64_t n, int s, T* R, const T* Q, const CgCtl* ctl
     constexpr int S = decltype(S_)::value, V = decltype(V_)::value;
     if (minv)
       hipLaunchKernelGGL((cg_update_kernel<T, S, V, true>), dim3(nblk), dim3(kBlock), 0, st, n, s, R, Q, ctl,
-                         partial, minv);
+                         partial, minv, (int64_t)0);
     else
       hipLaunchKernelGGL((cg_update_kernel<T, S, V, false>), dim3(nblk), dim3(kBlock), 0, st, n, s, R, Q, ctl,
-                         partial, minv);
+                         partial, minv, (int64_t)0);
     return hipGetLastError();
   });
   if (e == hipSuccess && ev_after) e = hipEventRecord(ev_after, st);
   if (e != hipSuccess) return e;
   return launch_reduce(s, partial, sizeof(T) == 4, nblk, 1, red, &ctl->gate, nullptr, epi, st);
+}
+
+hipError_t launch_cg_update_partials(int64_t n, int s, double* R, const double* Q, const CgCtl* ctl, double* partial,
+                                     int nblk, int64_t pstride, hipStream_t st) {
+  return dispatch_s<double>(s, [&](auto S_, auto V_) -> hipError_t {
+    constexpr int S = decltype(S_)::value, V = decltype(V_)::value;
+    hipLaunchKernelGGL((cg_update_kernel<double, S, V, false>), dim3(nblk), dim3(kBlock), 0, st, n, s, R, Q, ctl,
+                       partial, (const double*)nullptr, pstride);
+    return hipGetLastError();
+  });
+}
+
+// Gram partials X^T Y (no reduction) at stride pstride per workgroup.
+template <int S, int VEC>
+__global__ __launch_bounds__(kBlock) void gram_pair_kernel(int64_t n, int s, const double* __restrict__ X,
+                                                            const double* __restrict__ Y,
+                                                            double* __restrict__ partial, int64_t pstride,
+                                                            const int32_t* skip_a, const int32_t* skip_b) {
+  using T = double;
+  using L = Layout<T, S, VEC>;
+  constexpr int NW = kBlock / kWave;
+  constexpr int RPB = NW * L::RPW;
+  __shared__ T sh[NW * S * S];
+  if ((skip_a && *skip_a) || (skip_b && *skip_b)) return;
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  const int r = lane / L::LPR, c = lane % L::LPR;
+  const int col0 = c * VEC;
+  const bool active = col0 < s;
+  int64_t r0, r1, rstep;
+  stream_rows(n, RPB, r0, r1, rstep);
+  T gacc[VEC][S];
+#pragma unroll
+  for (int a = 0; a < VEC; ++a)
+#pragma unroll
+    for (int b = 0; b < S; ++b) gacc[a][b] = T(0);
+  for (int64_t base = r0; base < r1; base += rstep) {
+    const int64_t row = base + wave * L::RPW + r;
+    const bool rv = row < r1 && active;
+    const vec_t<T, VEC> x = rv ? load_vec<T, VEC>(X + row * s + col0) : zero_vec<T, VEC>();
+    const vec_t<T, VEC> y = rv ? load_vec<T, VEC>(Y + row * s + col0) : zero_vec<T, VEC>();
+    gram_row<T, S, VEC>(gacc, x, y, lane);
+  }
+  gram_store<T, S, VEC>(gacc, s, partial, sh, 0, pstride);
+}
+
+hipError_t launch_gram_partials(int64_t n, int s, const double* X, const double* Y, double* partial, int nblk,
+                                int64_t pstride, const int32_t* skip_a, const int32_t* skip_b, hipStream_t st) {
+  return dispatch_s<double>(s, [&](auto S_, auto V_) -> hipError_t {
+    constexpr int S = decltype(S_)::value, V = decltype(V_)::value;
+    hipLaunchKernelGGL((gram_pair_kernel<S, V>), dim3(nblk), dim3(kBlock), 0, st, n, s, X, Y, partial, pstride,
+                       skip_a, skip_b);
+    return hipGetLastError();
+  });
 }
 
 // Direction update of block CG with the X update deferred by one iteration:

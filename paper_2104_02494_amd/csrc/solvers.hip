@@ -240,6 +240,156 @@ template hipError_t cg_run<double>(const CsrView&, Sub, const double*, double*, 
 template hipError_t cg_run<float>(const CsrView&, Sub, const float*, float*, double, int, double, double, int,
                                   const CgBufs<float>&, hipStream_t, int32_t*, CgResult&, Prof*, const double*);
 
+// ------------------------------------------------------ multicolour SSOR --
+SsorWs ssor_carve(Carver& c, int64_t n) {
+  SsorWs w;
+  w.d = c.take<double>((size_t)n);
+  w.perm = c.take<int32_t>((size_t)n);
+  w.off = c.take<int32_t>(kMaxColors + 1);
+  w.cursor = c.take<int32_t>(kMaxColors);
+  w.count = c.take<int32_t>(kMaxColors);
+  w.misc = c.take<int32_t>(4);  // ncolors, bad[3]
+  return w;
+}
+
+hipError_t ssor_plan_build(const CsrView& A, const int32_t* colors, double omega, const SsorWs& w, hipStream_t st,
+                           SsorPlan& plan, int& err) {
+  err = 0;
+  BK_TRY(hipMemsetAsync(w.count, 0, sizeof(int32_t) * kMaxColors, st));
+  BK_TRY(hipMemsetAsync(w.misc, 0, sizeof(int32_t) * 4, st));
+  BK_TRY(launch_ssor_check(A, colors, w.d, w.misc, w.count, w.misc + 1, st));
+  int32_t misc[4];
+  BK_TRY(hipMemcpyAsync(misc, w.misc, sizeof(misc), hipMemcpyDeviceToHost, st));
+  BK_TRY(hipStreamSynchronize(st));
+  if (misc[1]) err = 1;
+  else if (misc[2]) err = 2;
+  else if (misc[3]) err = 3;
+  if (err) return hipSuccess;
+  const int nc = misc[0];
+  BK_TRY(launch_ssor_bucket(A.n, colors, w.count, w.misc, w.off, w.cursor, w.perm, st));
+  static thread_local int32_t cnt[kMaxColors];
+  BK_TRY(hipMemcpyAsync(cnt, w.count, sizeof(int32_t) * nc, hipMemcpyDeviceToHost, st));
+  BK_TRY(hipStreamSynchronize(st));
+  int64_t cmax = 0;
+  for (int c = 0; c < nc; ++c) cmax = cnt[c] > cmax ? cnt[c] : cmax;
+  plan.A = A;
+  plan.colors = colors;
+  plan.d = w.d;
+  plan.perm = w.perm;
+  plan.off = w.off;
+  plan.ncolors = nc;
+  plan.count_max = cmax;
+  plan.omega = omega;
+  return hipSuccess;
+}
+
+// Re-normalisation with the SSOR preconditioner: (R-bar, gamma) = Norm_S(R~),
+// Z = M^-1 R-bar into Q, rho' = <Z, R-bar>_S, then sigma, beta (cg_reortho_fin).
+static hipError_t ssor_normalise(int64_t n, Sub sub, const CgBufs<double>& b, const SsorPlan& m, int nblk,
+                                 hipStream_t st, Prof* prof) {
+  CgCtl* c = b.ctl;
+  ProfScope ps(prof, PROF_CG_NORMALISE, st);
+  BK_TRY(tsqr_run<double>(n, sub, b.R, c->gamma, b.tsqr_ws, b.cnt, &c->done, &c->fire, st));
+  BK_TRY(launch_ssor_apply(m, sub.s, b.R, b.Q, &c->done, nullptr, &c->fire, st));
+  BK_TRY(launch_gram<double>(n, sub.s, b.Q, 1, b.R, b.partial, nblk, Red{b.Gq, b.gpart, b.cnt}, &c->done, st,
+                             &c->fire));
+  return launch_cg_reortho_fin(c, sub.s, b.Gq, st);
+}
+
+hipError_t pcg_ssor_run(const CsrView& A, Sub sub, const double* B, double* X, double tol, int maxit, double eta,
+                        int hist_cap, const CgBufs<double>& b, const SsorPlan& m, hipStream_t st, int32_t* hflags,
+                        CgResult& res, Prof* prof) {
+  const int64_t n = A.n;
+  const int s = sub.s;
+  const double eps = DBL_EPSILON;
+  const int nblk = stream_grid(n, s, sizeof(double));
+  const int64_t ss = (int64_t)s * s;
+  CgCtl* c = b.ctl;
+  int32_t* done = &c->done;
+  int32_t* gate = &c->gate;
+  const Red ra{b.Ga, b.gpart, b.cnt}, rr{b.Gr, b.gpart, b.cnt};
+  const bool always = eta > 0.0 && (isinf(eta) || eta * sqrt(eps) > 1.0);
+  const bool dynamic = eta > 0.0 && !always && sub.g > 1;
+
+  CgCtl* h = reinterpret_cast<CgCtl*>(hflags + 64);
+  memset(h, 0, offsetof(CgCtl, r0n));
+  h->maxit = maxit;
+  h->s = s;
+  h->kind = sub.kind;
+  h->g = sub.g;
+  h->hist_cap = hist_cap;
+  h->dynamic = dynamic ? 1 : 0;
+  h->tol = tol;
+  h->eta = eta;
+  h->sqrt_eps = sqrt(eps);
+  BK_TRY(hipMemcpyAsync(c, h, offsetof(CgCtl, r0n), hipMemcpyHostToDevice, st));
+
+  // R0 = B - A X0; initial normalisation; P = M^-1 R-bar, rho = <P, R-bar>_S
+  BK_TRY(launch_spmm<double>(A, s, X, b.R, B, 2, b.partial, nblk, ra, &c->bad_index, nullptr, st));
+  BK_TRY(launch_cg_init(c, b.Ga, nullptr, st));
+  if (eta > 0.0) BK_TRY(tsqr_run<double>(n, sub, b.R, c->sigma, b.tsqr_ws, b.cnt, done, nullptr, st));
+  BK_TRY(launch_ssor_apply(m, s, b.R, b.P, done, nullptr, nullptr, st));
+  BK_TRY(launch_gram<double>(n, s, b.P, 1, b.R, b.partial, nblk, rr, done, st));
+  BK_TRY(launch_cg_init(c, nullptr, b.Gr, st));
+
+  const CgCtl* hc = reinterpret_cast<const CgCtl*>(hflags);
+  double* const pbuf[2] = {b.P, b.P2};
+  int k = 0, batch = 4, last_iters = -1;
+  while (maxit > 0) {
+    for (int it = 0; it < batch; ++it, ++k) {
+      double* const Pk = pbuf[k & 1];
+      double* const Pn = pbuf[(k + 1) & 1];
+      {
+        ProfScope ps(prof, PROF_CG_SPMM, st);
+        BK_TRY(launch_spmm<double>(A, s, Pk, b.Q, nullptr, 1, b.partial, nblk, ra, &c->bad_index, gate, st,
+                                   Epi{EPI_CG_ALPHA, c, nullptr}, ps.end()));
+      }
+      {
+        // R~ = R - Q lambda (Gram of R~ into the first half of each partial);
+        // unless R~ is re-normalised, Z = M^-1 R~ into Q and <Z, R~> into the
+        // second half; one reduction for both (stopping test, rho', beta)
+        ProfScope ps(prof, PROF_CG_UPDATE, st);
+        BK_TRY(launch_cg_update_partials(n, s, b.R, b.Q, c, b.partial, nblk, 2 * ss, st));
+        BK_TRY(launch_ssor_apply(m, s, b.R, b.Q, gate, &c->fire, nullptr, st));
+        BK_TRY(launch_gram_partials(n, s, b.Q, b.R, b.partial + ss, nblk, 2 * ss, gate, &c->fire, st));
+        BK_TRY(launch_reduce(s, b.partial, false, nblk, 1, rr, gate, nullptr, Epi{EPI_CG_RHO_M, c, b.hist}, st));
+      }
+      if (always) BK_TRY(ssor_normalise(n, sub, b, m, nblk, st, prof));
+      {
+        ProfScope ps(prof, PROF_CG_PUPDATE, st);
+        BK_TRY(launch_cg_pupdate<double>(n, s, X, Pk, Pn, b.Q, c, st, nullptr));
+      }
+    }
+    BK_TRY(hipMemcpyAsync(hflags, c, kCtlHeaderInts * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    BK_TRY(hipStreamSynchronize(st));
+    BK_TRY(prof_flush(prof));
+    if (hc->done) break;
+    if (hc->suspended) {
+      const int ks = hc->iters - 1;
+      BK_TRY(ssor_normalise(n, sub, b, m, nblk, st, prof));
+      {
+        ProfScope ps(prof, PROF_CG_PUPDATE, st);
+        BK_TRY(launch_cg_pupdate<double>(n, s, X, pbuf[ks & 1], pbuf[(ks + 1) & 1], b.Q, c, st, nullptr));
+      }
+      k = ks + 1;
+      batch = 2;
+    } else {
+      if (hc->iters == last_iters) break;
+      if (batch < 32) batch *= 2;
+    }
+    last_iters = hc->iters;
+  }
+  BK_TRY(hipMemcpyAsync(hflags, c, kCtlHeaderInts * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  BK_TRY(hipStreamSynchronize(st));
+  res.status = hc->status;
+  res.iters = hc->iters;
+  res.nreorth = hc->nreorth;
+  res.converged = hc->converged;
+  res.bad_index = hc->bad_index;
+  res.kd_jacobi = hc->kd_jacobi;
+  return hipSuccess;
+}
+
 // ------------------------------------------------- one-reduction block CG --
 // Per iteration k: the SpMM U = A R-bar^k writes the Gram partials R^T U
 // into slot 1 of the partials whose slot 0 the previous fused pass filled

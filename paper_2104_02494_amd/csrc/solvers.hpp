@@ -77,6 +77,25 @@ hipError_t cg1r_run(const CsrView& A, Sub sub, const double* B, double* X, doubl
                     int hist_cap, const CgBufs<double>& b, hipStream_t st, int32_t* hflags, CgResult& res,
                     Prof* prof = nullptr);
 
+// Workspace of a multicolour SSOR plan (ssor_carve) and its construction:
+// checks the colouring against A (err: 0, or 1 colour out of range, 2 coupled
+// rows of one colour or a bad column index, 3 a row without a positive
+// diagonal), the diagonal, the rows bucketed by colour.  Synchronises st.
+struct SsorWs {
+  double* d = nullptr;
+  int32_t *perm = nullptr, *off = nullptr, *cursor = nullptr, *count = nullptr, *misc = nullptr;
+};
+SsorWs ssor_carve(Carver& c, int64_t n);
+hipError_t ssor_plan_build(const CsrView& A, const int32_t* colors, double omega, const SsorWs& w, hipStream_t st,
+                           SsorPlan& plan, int& err);
+
+// Block CG preconditioned by multicolour SSOR (FP64): as cg_run with Z =
+// M^-1 R-bar from the colour sweeps (Z goes through Q, which is free after
+// the residual update).
+hipError_t pcg_ssor_run(const CsrView& A, Sub sub, const double* B, double* X, double tol, int maxit, double eta,
+                        int hist_cap, const CgBufs<double>& b, const SsorPlan& m, hipStream_t st, int32_t* hflags,
+                        CgResult& res, Prof* prof = nullptr);
+
 struct IrBufs {
   float *A32 = nullptr, *R32 = nullptr, *X32 = nullptr;
   double *R64 = nullptr, *partial = nullptr, *gpart = nullptr, *G = nullptr, *r0n = nullptr, *scale = nullptr;
