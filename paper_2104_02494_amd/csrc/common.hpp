@@ -42,6 +42,31 @@ __device__ __forceinline__ vec_t<T, N> zero_vec() {
   return z;
 }
 
+template <int V>
+using IC = std::integral_constant<int, V>;
+
+// Calls f(IC<S>, IC<VEC>) for the block width s.  Widths 1, 2 and 4 give a
+// lane a whole row; 8, 16 and 32 move 16 bytes per lane; other widths run one
+// element per lane in the next power of two.
+template <typename T, typename F>
+hipError_t dispatch_s(int s, F&& f) {
+  constexpr int v16 = 16 / (int)sizeof(T);
+  switch (s) {
+    case 1: return f(IC<1>{}, IC<1>{});
+    case 2: return f(IC<2>{}, IC<2>{});
+    case 4: return f(IC<4>{}, IC<4>{});
+    case 8: return f(IC<8>{}, IC<v16>{});
+    case 16: return f(IC<16>{}, IC<v16>{});
+    case 32: return f(IC<32>{}, IC<v16>{});
+    default: break;
+  }
+  if (s == 3) return f(IC<4>{}, IC<1>{});
+  if (s >= 5 && s <= 7) return f(IC<8>{}, IC<1>{});
+  if (s >= 9 && s <= 15) return f(IC<16>{}, IC<1>{});
+  if (s >= 17 && s <= 31) return f(IC<32>{}, IC<1>{});
+  return hipErrorInvalidValue;
+}
+
 // Compile-time layout of a block kernel for element type T and width S.
 template <typename T, int S_, int VEC_>
 struct Layout {

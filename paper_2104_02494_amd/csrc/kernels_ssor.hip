@@ -195,13 +195,13 @@ hipError_t launch_ssor_bucket(int64_t n, const int32_t* colors, const int32_t* c
   return hipGetLastError();
 }
 
-// One colour of a sweep: thread (r, col) updates column col of the r-th row
-// of colour c.  Forward (BACK = false): Z_i = (R_i - omega sum_{colour(j) <
-// c} a_ij Z_j) / d_i.  Backward: Z_i = (f d_i Z_i - omega sum_{colour(j) > c}
-// a_ij Z_j) / d_i with f = omega (2 - omega).  The s threads of a row read
-// its entries together (one load per wavefront) and s consecutive values of
-// each gathered row.
-template <bool BACK>
+// One colour of a sweep, in the row-slot layout of the streaming kernels
+// (a row held by LPR = S / VEC lanes, VEC contiguous columns each).  Forward
+// (BACK = false): Z_i = (R_i - omega sum_{colour(j) < c} a_ij Z_j) / d_i.
+// Backward: Z_i = (f d_i Z_i - omega sum_{colour(j) > c} a_ij Z_j) / d_i with
+// f = omega (2 - omega).  The lanes of a row slot read its entries together
+// (one load per row slot) and VEC consecutive values of each gathered row.
+template <bool BACK, int S, int VEC>
 __global__ __launch_bounds__(kBlock) void ssor_sweep_kernel(int s, const int32_t* __restrict__ rowptr,
                                                              const int32_t* __restrict__ colind,
                                                              const double* __restrict__ val,
@@ -212,41 +212,69 @@ __global__ __launch_bounds__(kBlock) void ssor_sweep_kernel(int s, const int32_t
                                                              const double* __restrict__ R, double* Z,
                                                              const int32_t* skip_a, const int32_t* skip_b,
                                                              const int32_t* need) {
+  using L = Layout<double, S, VEC>;
+  constexpr int NW = kBlock / kWave;
+  constexpr int RPB = NW * L::RPW;
   if ((skip_a && *skip_a) || (skip_b && *skip_b) || (need && !*need)) return;
   const int64_t o0 = off[c], cnt = (int64_t)off[c + 1] - o0;
   const double f = omega * (2.0 - omega);
-  for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < cnt * s; t += (int64_t)gridDim.x * kBlock) {
-    const int64_t r = t / s;
-    const int col = (int)(t - r * s);
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  const int col0 = (lane % L::LPR) * VEC;
+  if (col0 >= s) return;
+  for (int64_t base = (int64_t)blockIdx.x * RPB; base < cnt; base += (int64_t)gridDim.x * RPB) {
+    const int64_t r = base + wave * L::RPW + lane / L::LPR;
+    if (r >= cnt) continue;
     const int64_t i = perm[o0 + r];
     const double di = d[i];
-    double acc = BACK ? (f * di) * Z[i * s + col] : R[i * s + col];
-    for (int32_t k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+    vec_t<double, VEC> acc;
+    if (BACK) {
+      acc = load_vec<double, VEC>(Z + i * s + col0);
+#pragma unroll
+      for (int w = 0; w < VEC; ++w) acc.v[w] = (f * di) * acc.v[w];
+    } else {
+      acc = load_vec<double, VEC>(R + i * s + col0);
+    }
+    const int32_t k1 = rowptr[i + 1];
+    for (int32_t k = rowptr[i]; k < k1; ++k) {
       const int32_t j = colind[k];
       const int32_t cj = colors[j];
-      if (BACK ? cj > c : cj < c) acc = fma(-(omega * val[k]), Z[(int64_t)j * s + col], acc);
+      if (BACK ? cj > c : cj < c) {
+        const double a = -(omega * val[k]);
+        const vec_t<double, VEC> zj = load_vec<double, VEC>(Z + (int64_t)j * s + col0);
+#pragma unroll
+        for (int w = 0; w < VEC; ++w) acc.v[w] = fma(a, zj.v[w], acc.v[w]);
+      }
     }
-    Z[i * s + col] = acc / di;
+#pragma unroll
+    for (int w = 0; w < VEC; ++w) acc.v[w] = acc.v[w] / di;
+    store_vec<double, VEC>(Z + i * s + col0, acc);
   }
 }
 
 hipError_t launch_ssor_apply(const SsorPlan& m, int s, const double* R, double* Z, const int32_t* skip_a,
                              const int32_t* skip_b, const int32_t* need, hipStream_t st) {
   const double* val = static_cast<const double*>(m.A.val);
-  for (int pass = 0; pass < 2; ++pass)
-    for (int k = 0; k < m.ncolors; ++k) {
-      const int c = pass == 0 ? k : m.ncolors - 1 - k;
-      int64_t b = ((int64_t)m.count_max * s + kBlock - 1) / kBlock;
-      if (b > 8192) b = 8192;
-      if (b < 1) b = 1;
-      if (pass == 0)
-        hipLaunchKernelGGL(ssor_sweep_kernel<false>, dim3((unsigned)b), dim3(kBlock), 0, st, s, m.A.rowptr,
-                           m.A.colind, val, m.colors, m.d, m.perm, m.off, c, m.omega, R, Z, skip_a, skip_b, need);
-      else
-        hipLaunchKernelGGL(ssor_sweep_kernel<true>, dim3((unsigned)b), dim3(kBlock), 0, st, s, m.A.rowptr,
-                           m.A.colind, val, m.colors, m.d, m.perm, m.off, c, m.omega, R, Z, skip_a, skip_b, need);
-    }
-  return hipGetLastError();
+  return dispatch_s<double>(s, [&](auto S_, auto V_) -> hipError_t {
+    constexpr int S = decltype(S_)::value, V = decltype(V_)::value;
+    using L = Layout<double, S, V>;
+    constexpr int RPB = (kBlock / kWave) * L::RPW;
+    int64_t b = (m.count_max + RPB - 1) / RPB;
+    if (b > 8192) b = 8192;
+    if (b < 1) b = 1;
+    for (int pass = 0; pass < 2; ++pass)
+      for (int k = 0; k < m.ncolors; ++k) {
+        const int c = pass == 0 ? k : m.ncolors - 1 - k;
+        if (pass == 0)
+          hipLaunchKernelGGL((ssor_sweep_kernel<false, S, V>), dim3((unsigned)b), dim3(kBlock), 0, st, s,
+                             m.A.rowptr, m.A.colind, val, m.colors, m.d, m.perm, m.off, c, m.omega, R, Z, skip_a,
+                             skip_b, need);
+        else
+          hipLaunchKernelGGL((ssor_sweep_kernel<true, S, V>), dim3((unsigned)b), dim3(kBlock), 0, st, s,
+                             m.A.rowptr, m.A.colind, val, m.colors, m.d, m.perm, m.off, c, m.omega, R, Z, skip_a,
+                             skip_b, need);
+      }
+    return hipGetLastError();
+  });
 }
 
 }  // namespace bkry
