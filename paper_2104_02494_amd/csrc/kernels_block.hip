@@ -93,25 +93,56 @@ int stream_grid(int64_t n, int s, int elem_bytes) {
   return (int)(g < 8 ? 8 : g);
 }
 
+// Row slots of 8 or more lanes (S = 16, 32 with 16-byte chunks, and the
+// one-element layouts of the odd widths) share rows through LDS: each lane
+// stores its chunk, then every lane reads the whole row with vector loads
+// that all lanes of the slot issue together (broadcast reads).  That replaces
+// S cross-lane permutes per row, whose latency serialised the wide kernels.
+// The slot's lanes are in one wavefront, whose LDS accesses execute in order,
+// so no barrier is needed.  Each row slot of the workgroup owns S entries.
+template <typename T, int S, int VEC>
+__device__ __forceinline__ const T* lds_row(const vec_t<T, VEC>& v) {
+  constexpr int LPR = S / VEC;
+  __shared__ __align__(16) T rows[kBlock / LPR * S];
+  T* r = rows + (threadIdx.x / LPR) * S;
+  store_vec<T, VEC>(r + (threadIdx.x % LPR) * VEC, v);
+  __builtin_amdgcn_wave_barrier();
+  return r;
+}
+
 // Gather the full row (S values) held in chunks by the LPR lanes of a row
 // slot and accumulate acc[a][b] += mine[a] * row[b] for a in the lane's own
 // chunk.  All 64 lanes must execute this (the row slot's lanes are the
-// sources); for LPR <= 4 the values move by DPP quad permutations.
+// sources); for LPR <= 4 the values move by DPP quad permutations, wider
+// slots go through LDS (lds_row).
 template <typename T, int S, int VEC>
 __device__ __forceinline__ void gram_row(T (&acc)[VEC][S], const vec_t<T, VEC>& mine, const vec_t<T, VEC>& other,
                                          int lane) {
   constexpr int LPR = S / VEC;
   (void)lane;
-  static_for<LPR>([&](auto cc_) {
-    constexpr int cc = decltype(cc_)::value;
-    T o[VEC];
+  if constexpr (LPR >= 8) {
+    const T* r = lds_row<T, S, VEC>(other);
 #pragma unroll
-    for (int w = 0; w < VEC; ++w) o[w] = group_bcast<LPR, cc>(other.v[w]);
+    for (int b0 = 0; b0 < S; b0 += 2) {
+      const vec_t<T, 2> o = load_vec<T, 2>(r + b0);
 #pragma unroll
-    for (int a = 0; a < VEC; ++a)
+      for (int a = 0; a < VEC; ++a) {
+        acc[a][b0] += mine.v[a] * o.v[0];
+        acc[a][b0 + 1] += mine.v[a] * o.v[1];
+      }
+    }
+  } else {
+    static_for<LPR>([&](auto cc_) {
+      constexpr int cc = decltype(cc_)::value;
+      T o[VEC];
 #pragma unroll
-      for (int w = 0; w < VEC; ++w) acc[a][cc * VEC + w] += mine.v[a] * o[w];
-  });
+      for (int w = 0; w < VEC; ++w) o[w] = group_bcast<LPR, cc>(other.v[w]);
+#pragma unroll
+      for (int a = 0; a < VEC; ++a)
+#pragma unroll
+        for (int w = 0; w < VEC; ++w) acc[a][cc * VEC + w] += mine.v[a] * o[w];
+    });
+  }
 }
 
 // out[w] = sum_b row[b] * C[b][col0 + w] with the row gathered from the row
@@ -122,16 +153,30 @@ __device__ __forceinline__ void row_times(T (&out)[VEC], const vec_t<T, VEC>& mi
   (void)lane;
 #pragma unroll
   for (int w = 0; w < VEC; ++w) out[w] = T(0);
-  static_for<LPR>([&](auto cc_) {
-    constexpr int cc = decltype(cc_)::value;
+  if constexpr (LPR >= 8) {
+    const T* r = lds_row<T, S, VEC>(mine);
 #pragma unroll
-    for (int w2 = 0; w2 < VEC; ++w2) {
-      const T o = group_bcast<LPR, cc>(mine.v[w2]);
-      const T* crow = C + (cc * VEC + w2) * S + col0;
+    for (int b0 = 0; b0 < S; b0 += 2) {
+      const vec_t<T, 2> o = load_vec<T, 2>(r + b0);
 #pragma unroll
-      for (int w = 0; w < VEC; ++w) out[w] += o * crow[w];
+      for (int h = 0; h < 2; ++h) {
+        const T* crow = C + (b0 + h) * S + col0;
+#pragma unroll
+        for (int w = 0; w < VEC; ++w) out[w] += o.v[h] * crow[w];
+      }
     }
-  });
+  } else {
+    static_for<LPR>([&](auto cc_) {
+      constexpr int cc = decltype(cc_)::value;
+#pragma unroll
+      for (int w2 = 0; w2 < VEC; ++w2) {
+        const T o = group_bcast<LPR, cc>(mine.v[w2]);
+        const T* crow = C + (cc * VEC + w2) * S + col0;
+#pragma unroll
+        for (int w = 0; w < VEC; ++w) out[w] += o * crow[w];
+      }
+    });
+  }
 }
 
 // Reduce per-lane Gram accumulators of a workgroup into its s x s partial
@@ -368,14 +413,40 @@ __global__ __launch_bounds__(kBlock) void spmm_ell_kernel(int64_t n, int W, cons
     }
   };
   // acc += sum over the chunk's C entries, in storage order
+  // (slots of 8 or more lanes share the chunk's entries through LDS, as
+  // lds_row does for rows)
   auto chunk = [&](const vec_t<int32_t, E>& cj, const vec_t<T, E>& ca, bool rv, vec_t<T, VEC>& acc) {
     int jj[C];
     T aa[C];
-    static_for<C>([&](auto u_) {
-      constexpr int u = decltype(u_)::value;
-      jj[u] = group_bcast<LPR, u / E>(cj.v[u % E]);
-      aa[u] = group_bcast<LPR, u / E>(ca.v[u % E]);
-    });
+    if constexpr (LPR >= 8) {
+      __shared__ __align__(16) int32_t js[kBlock / LPR * C];
+      __shared__ __align__(16) T as[kBlock / LPR * C];
+      const int base = (threadIdx.x / LPR) * C;
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        js[base + c * E + e] = cj.v[e];
+        as[base + c * E + e] = ca.v[e];
+      }
+      __builtin_amdgcn_wave_barrier();
+#pragma unroll
+      for (int u = 0; u < C; u += 4) {
+        const vec_t<int32_t, 4> q = load_vec<int32_t, 4>(js + base + u);
+#pragma unroll
+        for (int h = 0; h < 4; ++h) jj[u + h] = q.v[h];
+      }
+#pragma unroll
+      for (int u = 0; u < C; u += 2) {
+        const vec_t<T, 2> q = load_vec<T, 2>(as + base + u);
+        aa[u] = q.v[0];
+        aa[u + 1] = q.v[1];
+      }
+    } else {
+      static_for<C>([&](auto u_) {
+        constexpr int u = decltype(u_)::value;
+        jj[u] = group_bcast<LPR, u / E>(cj.v[u % E]);
+        aa[u] = group_bcast<LPR, u / E>(ca.v[u % E]);
+      });
+    }
     vec_t<T, VEC> xx[C];
 #pragma unroll
     for (int u = 0; u < C; ++u) {

@@ -851,10 +851,12 @@ __device__ __forceinline__ double sum_strided(const T* __restrict__ p, int64_t s
 // the CG epilogues need a single wavefront.
 constexpr int kRedPlain = 256;
 
+// ng: Grams per partial of a plain reduction (EPI_NONE); the epilogue kinds
+// fix their own.
 template <typename T, int EPI, int SM>
 __global__ __launch_bounds__(EPI == EPI_NONE ? kRedPlain : kSB) void reduce_kernel(
     int s, const T* __restrict__ partial, int nblk, Red red, const int32_t* gate, const int32_t* fire, CgCtl* c,
-    double* hist) {
+    double* hist, int ng) {
   constexpr int NTH = EPI == EPI_NONE ? kRedPlain : kSB;
   constexpr bool RHO = EPI == EPI_CG_RHO || EPI == EPI_CG_RHO_M;
   constexpr bool NORMS = RHO || EPI == EPI_CG_1R;
@@ -862,7 +864,7 @@ __global__ __launch_bounds__(EPI == EPI_NONE ? kRedPlain : kSB) void reduce_kern
   __shared__ int last;
   __shared__ double pre_rho[EPI != EPI_NONE ? kSS : 1], pre_sig[EPI != EPI_NONE ? kSS : 1];
   __shared__ double pre_r0n[NORMS ? kMaxS : 1];
-  const int ss = s * s, m = NG * ss;
+  const int ss = s * s, m = (EPI == EPI_NONE ? ng : NG) * ss;
   if constexpr (EPI != EPI_NONE) {
     // the epilogue's inputs from the control block, loaded along with the
     // partials (only the last workgroup uses them)
@@ -919,6 +921,42 @@ __global__ __launch_bounds__(EPI == EPI_NONE ? kRedPlain : kSB) void reduce_kern
   }
 }
 
+// The coefficient step of a CG reduction in a launch of its own, after a
+// plain reduction into G (wide Grams: the plain reduction's four wavefronts
+// sum s x s partials of s > 16 several times faster than the single
+// wavefront an epilogue runs on).  Same gating and inputs as the fused form.
+template <int EPI, int SM>
+__global__ __launch_bounds__(kSB) void cg_epi_kernel(const double* G, CgCtl* c, double* hist) {
+  constexpr bool RHO = EPI == EPI_CG_RHO || EPI == EPI_CG_RHO_M;
+  constexpr int NG = (EPI == EPI_CG_RHO_M || EPI == EPI_CG_1R) ? 2 : 1;
+  __shared__ double pre_rho[kSS], pre_sig[kSS], pre_r0n[kMaxS], Gl[NG * kSS];
+  if constexpr (EPI == EPI_CG_ALPHA) {
+    if (c->done) {
+      if (tid() == 0) {
+        c->x_pending = 0;
+        c->xdef_in = 0;
+      }
+      return;
+    }
+  }
+  if (c->gate) return;
+  const int s = c->s, ss = s * s;
+  for (int t = tid(); t < ss; t += kSB) {
+    pre_rho[t] = c->rho[t];
+    pre_sig[t] = c->sigma[t];
+  }
+  for (int t = tid(); t < s; t += kSB) pre_r0n[t] = c->r0n[t];
+  for (int e = tid(); e < NG * ss; e += kSB) Gl[e] = G[e];
+  __syncthreads();
+  if constexpr (EPI == EPI_CG_ALPHA) {
+    cg_alpha_body<SM>(c, Gl, pre_rho, pre_sig);
+  } else if constexpr (RHO) {
+    cg_rho_body<SM>(c, Gl, hist, pre_rho, pre_sig, pre_r0n, NG == 2 ? Gl + ss : nullptr);
+  } else {
+    cg1r_body<SM>(c, Gl, hist, pre_rho, pre_sig, pre_r0n);
+  }
+}
+
 // About 32 partials per reduction workgroup (one batch of loads), at most
 // kMaxSlices workgroups.
 static int reduce_slices(int nblk) {
@@ -934,27 +972,44 @@ static hipError_t launch_reduce_t(int s, const T* partial, int nblk, int batch, 
   dim3 grid(reduce_slices(nblk), batch);
   if (epi.kind == EPI_NONE) {
     hipLaunchKernelGGL((reduce_kernel<T, EPI_NONE, 8>), grid, dim3(kRedPlain), 0, st, s, partial, nblk, red, gate, fire,
-                       epi.ctl, epi.hist);
+                       epi.ctl, epi.hist, 1);
     return hipGetLastError();
   }
   if (batch != 1 || !epi.ctl ||
       (epi.kind != EPI_CG_ALPHA && epi.kind != EPI_CG_RHO && epi.kind != EPI_CG_RHO_M && epi.kind != EPI_CG_1R))
     return hipErrorInvalidValue;
+  if ((epi.kind == EPI_CG_RHO_M || epi.kind == EPI_CG_1R) && sizeof(T) != 8) return hipErrorInvalidValue;
+  if (s > 16) {
+    // wide Grams: plain reduction (gated like the epilogue), then the
+    // coefficient step in its own single-wavefront launch
+    const int ng = (epi.kind == EPI_CG_RHO_M || epi.kind == EPI_CG_1R) ? 2 : 1;
+    hipLaunchKernelGGL((reduce_kernel<T, EPI_NONE, 8>), grid, dim3(kRedPlain), 0, st, s, partial, nblk, red,
+                       &epi.ctl->gate, nullptr, nullptr, nullptr, ng);
+    if (epi.kind == EPI_CG_ALPHA)
+      hipLaunchKernelGGL((cg_epi_kernel<EPI_CG_ALPHA, 32>), dim3(1), dim3(kSB), 0, st, red.G, epi.ctl, epi.hist);
+    else if (epi.kind == EPI_CG_RHO)
+      hipLaunchKernelGGL((cg_epi_kernel<EPI_CG_RHO, 32>), dim3(1), dim3(kSB), 0, st, red.G, epi.ctl, epi.hist);
+    else if (epi.kind == EPI_CG_RHO_M)
+      hipLaunchKernelGGL((cg_epi_kernel<EPI_CG_RHO_M, 32>), dim3(1), dim3(kSB), 0, st, red.G, epi.ctl, epi.hist);
+    else
+      hipLaunchKernelGGL((cg_epi_kernel<EPI_CG_1R, 32>), dim3(1), dim3(kSB), 0, st, red.G, epi.ctl, epi.hist);
+    return hipGetLastError();
+  }
   return dispatch_sm(s, [&](auto SM_) -> hipError_t {
     constexpr int SM = decltype(SM_)::value;
     if (epi.kind == EPI_CG_ALPHA)
       hipLaunchKernelGGL((reduce_kernel<T, EPI_CG_ALPHA, SM>), grid, dim3(kSB), 0, st, s, partial, nblk, red, gate,
-                         fire, epi.ctl, epi.hist);
+                         fire, epi.ctl, epi.hist, 1);
     else if (epi.kind == EPI_CG_RHO)
       hipLaunchKernelGGL((reduce_kernel<T, EPI_CG_RHO, SM>), grid, dim3(kSB), 0, st, s, partial, nblk, red, gate,
-                         fire, epi.ctl, epi.hist);
+                         fire, epi.ctl, epi.hist, 1);
     else if constexpr (sizeof(T) == 8) {
       if (epi.kind == EPI_CG_RHO_M)
         hipLaunchKernelGGL((reduce_kernel<T, EPI_CG_RHO_M, SM>), grid, dim3(kSB), 0, st, s, partial, nblk, red, gate,
-                           fire, epi.ctl, epi.hist);
+                           fire, epi.ctl, epi.hist, 1);
       else
         hipLaunchKernelGGL((reduce_kernel<T, EPI_CG_1R, SM>), grid, dim3(kSB), 0, st, s, partial, nblk, red, gate,
-                           fire, epi.ctl, epi.hist);
+                           fire, epi.ctl, epi.hist, 1);
     } else {
       return hipErrorInvalidValue;
     }
