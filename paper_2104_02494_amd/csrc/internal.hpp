@@ -358,6 +358,11 @@ hipError_t launch_bc_omega(CgCtl* ctl, BcAux* aux, const double* G3, hipStream_t
 hipError_t launch_bc_stop(CgCtl* ctl, const double* Grr, double* hist, hipStream_t st);
 // Y = A0 + X1 C1 (+ X2 C2) for n x s blocks (C: s x s FP64, device); Y may
 // alias A0 but neither X.  Runs only if *done == 0 (done may be null).
+// X += P (lambda sigma) + S (omega sigma), R = S - omega U, P' = R + P beta -
+// Q (omega beta) in one pass (the coefficients from lamsig and x).
+hipError_t launch_bc_tail(int64_t n, int s, double* X, const double* P, const double* S, const double* U,
+                          const double* Q, double* R, double* Pn, const double* lamsig, const BcAux* x,
+                          const int32_t* done, hipStream_t st);
 template <typename T>
 hipError_t launch_lincomb(int64_t n, int s, const T* A0, const T* X1, const double* C1, const T* X2,
                           const double* C2, T* Y, const int32_t* done, hipStream_t st);

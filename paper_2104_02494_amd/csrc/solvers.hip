@@ -579,11 +579,10 @@ hipError_t bc_run(const CsrView& A, Sub sub, const double* B, double* X, double 
       BK_TRY(launch_spmm<double>(A, s, S, U, nullptr, 0, nullptr, nblk, red, &c->bad_index, done, st));
       BK_TRY(launch_gram<double>(n, s, S, 3, U, b.partial, nblk, red, done, st));  // S^T U, U^T U, R~0^T U
       BK_TRY(launch_bc_omega(c, x, b.G, st));
-      BK_TRY(launch_lincomb<double>(n, s, X, P, c->lamsig, S, x->omsig, X, done, st));
-      BK_TRY(launch_lincomb<double>(n, s, S, U, x->negomI, nullptr, nullptr, R, done, st));
+      // X, R and P' in one pass (P' of the last iteration is never used)
+      BK_TRY(launch_bc_tail(n, s, X, P, S, U, Q, R, Pn, c->lamsig, x, done, st));
       BK_TRY(launch_gram<double>(n, s, R, 1, R, b.partial, nblk, rrr, done, st));
       BK_TRY(launch_bc_stop(c, b.Grr, b.hist, st));
-      BK_TRY(launch_lincomb<double>(n, s, R, P, x->pbeta, Q, x->qbeta, Pn, done, st));
       std::swap(P, Pn);
     }
     BK_TRY(hipMemcpyAsync(hflags, c, kCtlHeaderInts * sizeof(int32_t), hipMemcpyDeviceToHost, st));
