@@ -363,6 +363,11 @@ hipError_t launch_bc_stop(CgCtl* ctl, const double* Grr, double* hist, hipStream
 hipError_t launch_bc_tail(int64_t n, int s, double* X, const double* P, const double* S, const double* U,
                           const double* Q, double* R, double* Pn, const double* lamsig, const BcAux* x,
                           const int32_t* done, hipStream_t st);
+// The same pass in the row-slot layout of the streaming kernels (kernels_block.hip).
+hipError_t launch_bc_tail_rs(int64_t n, int s, double* X, const double* P, const double* S, const double* U,
+                             const double* Q, double* R, double* Pn, const double* lamsig, const double* omsig,
+                             const double* negomI, const double* pbeta, const double* qbeta, const int32_t* done,
+                             hipStream_t st);
 template <typename T>
 hipError_t launch_lincomb(int64_t n, int s, const T* A0, const T* X1, const double* C1, const T* X2,
                           const double* C2, T* Y, const int32_t* done, hipStream_t st);

@@ -55,64 +55,16 @@ hipError_t launch_lincomb(int64_t n, int s, const T* A0, const T* X1, const doub
   return hipGetLastError();
 }
 
-// The three combinations that end an iteration once omega and beta are known,
-// in one pass: X += P (lambda sigma) + S (omega sigma), R = S - omega U,
-// P' = R + P beta - Q (omega beta).  Element (i, j) runs the same fused
-// multiply-adds in the same order as the three separate combinations; X is
-// updated in place, R and P' go to their own blocks.
-__global__ __launch_bounds__(kBlock) void bc_tail_kernel(int64_t n, int s, double* X, const double* __restrict__ P,
-                                                          const double* __restrict__ S,
-                                                          const double* __restrict__ U,
-                                                          const double* __restrict__ Q, double* __restrict__ R,
-                                                          double* __restrict__ Pn, const double* __restrict__ lamsig,
-                                                          const double* __restrict__ omsig,
-                                                          const double* __restrict__ negomI,
-                                                          const double* __restrict__ pbeta,
-                                                          const double* __restrict__ qbeta, const int32_t* done) {
-  __shared__ double cl[kMaxS * kMaxS], co[kMaxS * kMaxS], cu[kMaxS * kMaxS], cp[kMaxS * kMaxS],
-      cq[kMaxS * kMaxS];
-  if (done && *done) return;
-  for (int t = threadIdx.x; t < s * s; t += kBlock) {
-    cl[t] = lamsig[t];
-    co[t] = omsig[t];
-    cu[t] = negomI[t];
-    cp[t] = pbeta[t];
-    cq[t] = qbeta[t];
-  }
-  __syncthreads();
-  const int64_t total = n * s;
-  for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < total; e += (int64_t)gridDim.x * kBlock) {
-    const int64_t i = e / s;
-    const int j = (int)(e - i * s);
-    const double* p = P + i * s;
-    const double* sr = S + i * s;
-    const double* u = U + i * s;
-    const double* q = Q + i * s;
-    double x = X[e];
-    for (int k = 0; k < s; ++k) x = fma(p[k], cl[k * s + j], x);
-    for (int k = 0; k < s; ++k) x = fma(sr[k], co[k * s + j], x);
-    X[e] = x;
-    double r = sr[j];
-    for (int k = 0; k < s; ++k) r = fma(u[k], cu[k * s + j], r);
-    R[e] = r;
-    double pn = r;
-    for (int k = 0; k < s; ++k) pn = fma(p[k], cp[k * s + j], pn);
-    for (int k = 0; k < s; ++k) pn = fma(q[k], cq[k * s + j], pn);
-    Pn[e] = pn;
-  }
-}
-
+// The three combinations that end an iteration once omega and beta are known
+// (X += P (lambda sigma) + S (omega sigma), R = S - omega U, P' = R + P beta -
+// Q (omega beta)) run as one pass in the row-slot layout of the streaming
+// kernels (bc_tail_rs_kernel, kernels_block.hip).
 hipError_t launch_bc_tail(int64_t n, int s, double* X, const double* P, const double* S, const double* U,
                           const double* Q, double* R, double* Pn, const double* lamsig, const BcAux* x,
                           const int32_t* done, hipStream_t st) {
   if (s < 1 || s > kMaxS) return hipErrorInvalidValue;
-  const int64_t total = n * s;
-  if (total <= 0) return hipSuccess;
-  int64_t blocks = (total + kBlock - 1) / kBlock;
-  if (blocks > 4096) blocks = 4096;
-  hipLaunchKernelGGL(bc_tail_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, st, n, s, X, P, S, U, Q, R, Pn, lamsig,
-                     x->omsig, x->negomI, x->pbeta, x->qbeta, done);
-  return hipGetLastError();
+  if (n <= 0) return hipSuccess;
+  return launch_bc_tail_rs(n, s, X, P, S, U, Q, R, Pn, lamsig, x->omsig, x->negomI, x->pbeta, x->qbeta, done, st);
 }
 
 template hipError_t launch_lincomb<double>(int64_t, int, const double*, const double*, const double*, const double*,

@@ -145,6 +145,38 @@ __device__ __forceinline__ void gram_row(T (&acc)[VEC][S], const vec_t<T, VEC>& 
   }
 }
 
+// out[w] += sum_b row[b] * C[b][col0 + w] (one fused multiply-add per term, b
+// in order) with the row gathered from the row slot's lanes and C an S x S
+// matrix (stride S) in LDS.
+template <typename T, int S, int VEC>
+__device__ __forceinline__ void row_times_acc(T (&out)[VEC], const vec_t<T, VEC>& mine, const T* C, int col0) {
+  constexpr int LPR = S / VEC;
+  if constexpr (LPR >= 8) {
+    const T* r = lds_row<T, S, VEC>(mine);
+#pragma unroll
+    for (int b0 = 0; b0 < S; b0 += 2) {
+      const vec_t<T, 2> o = load_vec<T, 2>(r + b0);
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const T* crow = C + (b0 + h) * S + col0;
+#pragma unroll
+        for (int w = 0; w < VEC; ++w) out[w] = fma(o.v[h], crow[w], out[w]);
+      }
+    }
+  } else {
+    static_for<LPR>([&](auto cc_) {
+      constexpr int cc = decltype(cc_)::value;
+#pragma unroll
+      for (int w2 = 0; w2 < VEC; ++w2) {
+        const T o = group_bcast<LPR, cc>(mine.v[w2]);
+        const T* crow = C + (cc * VEC + w2) * S + col0;
+#pragma unroll
+        for (int w = 0; w < VEC; ++w) out[w] = fma(o, crow[w], out[w]);
+      }
+    });
+  }
+}
+
 // out[w] = sum_b row[b] * C[b][col0 + w] with the row gathered from the row
 // slot's lanes and C an S x S matrix (stride S) in LDS.
 template <typename T, int S, int VEC>
@@ -921,6 +953,78 @@ hipError_t launch_cg_pupdate(int64_t n, int s, T* X, const T* P, T* Pn, const T*
     else
       hipLaunchKernelGGL((cg_pupdate_kernel<T, S, V, false>), dim3(nblk), dim3(kBlock), 0, st, n, s, X, P, Pn, R,
                          ctl, minv);
+    return hipGetLastError();
+  });
+}
+
+// ------------------------------------------------------ block BiCGStab --
+// The three combinations that end a block BiCGStab iteration once omega and
+// beta are known, in one pass over the rows in the streaming layout:
+// X += P (lambda sigma) + S (omega sigma), R = S - omega U,
+// P' = R + P beta - Q (omega beta).  Each entry runs the same fused
+// multiply-adds, in the same order, as the one-thread-per-entry combinations.
+template <int S_, int VEC>
+__global__ __launch_bounds__(kBlock) void bc_tail_rs_kernel(int64_t n, int s, double* __restrict__ X,
+                                                             const double* __restrict__ P,
+                                                             const double* __restrict__ Sb,
+                                                             const double* __restrict__ U,
+                                                             const double* __restrict__ Q, double* __restrict__ R,
+                                                             double* __restrict__ Pn, const double* lamsig,
+                                                             const double* omsig, const double* negomI,
+                                                             const double* pbeta, const double* qbeta,
+                                                             const int32_t* done) {
+  using T = double;
+  using L = Layout<T, S_, VEC>;
+  constexpr int S = S_;
+  constexpr int NW = kBlock / kWave;
+  constexpr int RPB = NW * L::RPW;
+  __shared__ T cl[S * S], co[S * S], cu[S * S], cp[S * S], cq[S * S];
+  if (done && *done) return;
+  load_coeff<T, S>(cl, lamsig, s);
+  load_coeff<T, S>(co, omsig, s);
+  load_coeff<T, S>(cu, negomI, s);
+  load_coeff<T, S>(cp, pbeta, s);
+  load_coeff<T, S>(cq, qbeta, s);
+  __syncthreads();
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  const int r = lane / L::LPR, c = lane % L::LPR;
+  const int col0 = c * VEC;
+  const bool active = col0 < s;
+  int64_t r0, r1, rstep;
+  stream_rows(n, RPB, r0, r1, rstep);
+  for (int64_t base = r0; base < r1; base += rstep) {
+    const int64_t row = base + wave * L::RPW + r;
+    const bool rv = row < r1 && active;
+    const int64_t o = row * s + col0;
+    const vec_t<T, VEC> p = rv ? load_vec<T, VEC>(P + o) : zero_vec<T, VEC>();
+    const vec_t<T, VEC> sr = rv ? load_vec<T, VEC>(Sb + o) : zero_vec<T, VEC>();
+    const vec_t<T, VEC> u = rv ? load_vec<T, VEC>(U + o) : zero_vec<T, VEC>();
+    const vec_t<T, VEC> q = rv ? load_vec<T, VEC>(Q + o) : zero_vec<T, VEC>();
+    vec_t<T, VEC> x = rv ? load_vec<T, VEC>(X + o) : zero_vec<T, VEC>();
+    row_times_acc<T, S, VEC>(x.v, p, cl, col0);
+    row_times_acc<T, S, VEC>(x.v, sr, co, col0);
+    vec_t<T, VEC> rn = sr;
+    row_times_acc<T, S, VEC>(rn.v, u, cu, col0);
+    vec_t<T, VEC> pn = rn;
+    row_times_acc<T, S, VEC>(pn.v, p, cp, col0);
+    row_times_acc<T, S, VEC>(pn.v, q, cq, col0);
+    if (rv) {
+      store_nt<T, VEC>(X + o, x);
+      store_out<T, VEC>(R + o, rn);
+      store_nt<T, VEC>(Pn + o, pn);
+    }
+  }
+}
+
+hipError_t launch_bc_tail_rs(int64_t n, int s, double* X, const double* P, const double* S, const double* U,
+                             const double* Q, double* R, double* Pn, const double* lamsig, const double* omsig,
+                             const double* negomI, const double* pbeta, const double* qbeta, const int32_t* done,
+                             hipStream_t st) {
+  const int nblk = stream_grid_wide(n, s, sizeof(double));
+  return dispatch_s<double>(s, [&](auto S_, auto V_) -> hipError_t {
+    constexpr int SS = decltype(S_)::value, V = decltype(V_)::value;
+    hipLaunchKernelGGL((bc_tail_rs_kernel<SS, V>), dim3(nblk), dim3(kBlock), 0, st, n, s, X, P, S, U, Q, R, Pn,
+                       lamsig, omsig, negomI, pbeta, qbeta, done);
     return hipGetLastError();
   });
 }
