@@ -49,7 +49,7 @@ METRIC = "block-CG iters/s + SpMM/BDOT HBM GB/s (p=8, 128³ Laplacian); time-to-
 PMC_FILE = os.path.join(ROOT, "profiles", "spmm_laplace3d_128_s8_pmc.txt")
 KERNEL_SRCS = [os.path.join(ROOT, "paper_2104_02494_amd", "csrc", f) for f in ("kernels_block.hip", "common.hpp")]
 ROOFLINE_KERNEL = "spmm_ell_kernel<double, 8, 2, 1>"
-PROF_EVERY = 4          # HIP events around one SpMM launch in 4 of the timed solves
+PROF_EVERY = 8          # HIP events around one SpMM launch in 8 of the timed solves
 
 
 def log(*a):
