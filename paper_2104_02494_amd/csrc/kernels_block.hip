@@ -692,9 +692,15 @@ hipError_t launch_gram(int64_t n, int s, const T* X, int nx, const T* Y, T* part
       hipLaunchKernelGGL((gram_kernel<T, S, V, 1>), dim3(nblk, 1), dim3(kBlock), 0, st, n, s, X, nx, Y, partial,
                          done, fire);
     } else {
+      // batched: about 2048 workgroups in all (each grid row re-reads Y, and
+      // every workgroup adds nx partials to the reduction), a multiple of 8
       constexpr int JB = gram_jb<S>();
-      hipLaunchKernelGGL((gram_kernel<T, S, V, JB>), dim3(nblk, (nx + JB - 1) / JB), dim3(kBlock), 0, st, n, s, X,
-                         nx, Y, partial, done, fire);
+      const int gy = (nx + JB - 1) / JB;
+      int nb = 2048 / gy / 8 * 8;
+      if (nb < 64) nb = 64;
+      if (nb < nblk) nblk = nb;
+      hipLaunchKernelGGL((gram_kernel<T, S, V, JB>), dim3(nblk, gy), dim3(kBlock), 0, st, n, s, X, nx, Y, partial,
+                         done, fire);
     }
     return hipGetLastError();
   });
