@@ -1274,6 +1274,18 @@ __global__ __launch_bounds__(kBlock) void combine_kernel(int64_t n, int s, const
   int64_t r0, r1;
   int64_t rstep;
   stream_rows(n, RPB, r0, r1, rstep);
+  auto load_cs = [&](int j0, int jn) {
+    for (int t = threadIdx.x; t < jn * S * S; t += kBlock) {
+      int jj = t / (S * S), e = t % (S * S), a = e / S, b = e % S;
+      cs[t] = (a < s && b < s) ? (T)(sign * C[(int64_t)(j0 + jj) * s * s + a * s + b]) : T(0);
+    }
+  };
+  // all coefficient blocks fit (the usual case): load them once per workgroup
+  const bool once = nx <= JC;
+  if (once) {
+    load_cs(0, nx);
+    __syncthreads();
+  }
   for (int64_t base = r0; base < r1; base += rstep) {
     const int64_t row = base + wave * L::RPW + r;
     const bool rv = row < r1 && active;
@@ -1282,19 +1294,29 @@ __global__ __launch_bounds__(kBlock) void combine_kernel(int64_t n, int s, const
     for (int w = 0; w < VEC; ++w) acc[w] = T(0);
     for (int j0 = 0; j0 < nx; j0 += JC) {
       const int jn = (nx - j0) < JC ? (nx - j0) : JC;
-      __syncthreads();
-      for (int t = threadIdx.x; t < jn * S * S; t += kBlock) {
-        int jj = t / (S * S), e = t % (S * S), a = e / S, b = e % S;
-        cs[t] = (a < s && b < s) ? (T)(sign * C[(int64_t)(j0 + jj) * s * s + a * s + b]) : T(0);
+      if (!once) {
+        __syncthreads();
+        load_cs(j0, jn);
+        __syncthreads();
       }
-      __syncthreads();
-      for (int jj = 0; jj < jn; ++jj) {
-        const T* Xj = X + (int64_t)(j0 + jj) * n * s;
-        vec_t<T, VEC> x = rv ? load_vec<T, VEC>(Xj + row * s + col0) : zero_vec<T, VEC>();
-        T d[VEC];
-        row_times<T, S, VEC>(d, x, cs + jj * S * S, col0, lane);
+      // rows of four blocks are loaded before their products, so one memory
+      // round trip covers four terms; the terms are still added in order
+      for (int jb = 0; jb < jn; jb += 4) {
+        vec_t<T, VEC> x[4];
 #pragma unroll
-        for (int w = 0; w < VEC; ++w) acc[w] += d[w];
+        for (int u = 0; u < 4; ++u) {
+          const T* Xj = X + (int64_t)(j0 + jb + u) * n * s;
+          x[u] = (rv && jb + u < jn) ? load_vec<T, VEC>(Xj + row * s + col0) : zero_vec<T, VEC>();
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          if (jb + u < jn) {
+            T d[VEC];
+            row_times<T, S, VEC>(d, x[u], cs + (jb + u) * S * S, col0, lane);
+#pragma unroll
+            for (int w = 0; w < VEC; ++w) acc[w] += d[w];
+          }
+        }
       }
     }
     if (rv) {
