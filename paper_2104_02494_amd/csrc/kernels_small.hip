@@ -224,9 +224,13 @@ __device__ __forceinline__ double readlane_d(double v, int lane) {
 // rinv[k] = 1 / L_kk in every lane.  False (uniformly) on a non-positive or
 // non-finite pivot.
 // With sa, sh given, the matrix factored is sa A + sh I.
-template <int SM>
+// EX: s == SM, known at compile time (every size guard folds away, which
+// keeps the unrolled code of the widest factor small enough for the
+// instruction cache).
+template <int SM, bool EX>
 __device__ __forceinline__ bool rf_factor(const double* A, int s, double (&l)[SM], double (&rinv)[SM],
                                           double sa = 1.0, double sh = 0.0) {
+  if constexpr (EX) s = SM;
   const int t = tid();
 #pragma unroll
   for (int j = 0; j < SM; ++j) l[j] = (t < s && j < s) ? fma(sa, A[t * s + j], t == j ? sh : 0.0) : 0.0;
@@ -255,9 +259,10 @@ __device__ __forceinline__ bool rf_factor(const double* A, int s, double (&l)[SM
 }
 
 // Column t of L^-1 (lane t) by forward substitution.
-template <int SM>
+template <int SM, bool EX>
 __device__ __forceinline__ void rf_linv_column(const double (&l)[SM], const double (&rinv)[SM], int s,
                                                double (&y)[SM]) {
+  if constexpr (EX) s = SM;
   const int t = tid();
 #pragma unroll
   for (int i = 0; i < SM; ++i) {
@@ -280,12 +285,13 @@ __device__ __forceinline__ void rf_linv_column(const double (&l)[SM], const doub
 // reciprocals of the pivots are formed once, so the only divisions are the
 // s reciprocals.  Returns false (uniformly) on a non-positive or non-finite
 // pivot.
-template <int SM>
-__device__ __forceinline__ bool rf_cholesky_solve(const double* A, const double* B, double* X, double* Linv, int s) {
+template <int SM, bool EX>
+__device__ __forceinline__ bool rf_cholesky_solve_x(const double* A, const double* B, double* X, double* Linv, int s) {
+  if constexpr (EX) s = SM;
   __syncthreads();
   const int t = tid();
   double l[SM], rinv[SM];
-  if (!rf_factor<SM>(A, s, l, rinv)) return false;
+  if (!rf_factor<SM, EX>(A, s, l, rinv)) return false;
   double x[SM];
 #pragma unroll
   for (int i = 0; i < SM; ++i) x[i] = (t < s && i < s) ? B[i * s + t] : 0.0;
@@ -315,7 +321,7 @@ __device__ __forceinline__ bool rf_cholesky_solve(const double* A, const double*
   }
   if (Linv) {
     double y[SM];
-    rf_linv_column<SM>(l, rinv, s, y);
+    rf_linv_column<SM, EX>(l, rinv, s, y);
     if (t < s) {
 #pragma unroll
       for (int i = 0; i < SM; ++i)
@@ -325,21 +331,26 @@ __device__ __forceinline__ bool rf_cholesky_solve(const double* A, const double*
   __syncthreads();
   return true;
 }
+template <int SM>
+__device__ __forceinline__ bool rf_cholesky_solve(const double* A, const double* B, double* X, double* Linv, int s) {
+  return s == SM ? rf_cholesky_solve_x<SM, true>(A, B, X, Linv, s) : rf_cholesky_solve_x<SM, false>(A, B, X, Linv, s);
+}
 
 // A = L L^T with L and L^-1 stored (LDS, zero above the diagonal).
-template <int SM>
-__device__ __forceinline__ bool rf_cholesky_factor(const double* A, double* Lo, double* Linv, int s) {
+template <int SM, bool EX>
+__device__ __forceinline__ bool rf_cholesky_factor_x(const double* A, double* Lo, double* Linv, int s) {
+  if constexpr (EX) s = SM;
   __syncthreads();
   const int t = tid();
   double l[SM], rinv[SM];
-  if (!rf_factor<SM>(A, s, l, rinv)) return false;
+  if (!rf_factor<SM, EX>(A, s, l, rinv)) return false;
   if (t < s) {
 #pragma unroll
     for (int j = 0; j < SM; ++j)
       if (j < s) Lo[t * s + j] = (j <= t) ? l[j] : 0.0;
   }
   double y[SM];
-  rf_linv_column<SM>(l, rinv, s, y);
+  rf_linv_column<SM, EX>(l, rinv, s, y);
   if (t < s) {
 #pragma unroll
     for (int i = 0; i < SM; ++i)
@@ -348,20 +359,25 @@ __device__ __forceinline__ bool rf_cholesky_factor(const double* A, double* Lo, 
   __syncthreads();
   return true;
 }
+template <int SM>
+__device__ __forceinline__ bool rf_cholesky_factor(const double* A, double* Lo, double* Linv, int s) {
+  return s == SM ? rf_cholesky_factor_x<SM, true>(A, Lo, Linv, s) : rf_cholesky_factor_x<SM, false>(A, Lo, Linv, s);
+}
 
 // Whether sa A + sh I (A symmetric s x s, LDS) is positive definite, by
 // attempting its Cholesky factorisation (uniform result).
 template <int SM>
 __device__ __forceinline__ bool rf_definite(const double* A, int s, double sa, double sh) {
   double l[SM], rinv[SM];
-  return rf_factor<SM>(A, s, l, rinv, sa, sh);
+  return s == SM ? rf_factor<SM, true>(A, s, l, rinv, sa, sh) : rf_factor<SM, false>(A, s, l, rinv, sa, sh);
 }
 
 // Rayleigh quotient of the power iteration for the symmetric s x s matrix A
 // (LDS) from the all-ones vector, after at most 64 steps or once it changes
 // by less than 1e-6 relative.  It never exceeds lambda_max(A) (uniform).
-template <int SM>
-__device__ __forceinline__ double rf_power_lmax(const double* A, int s) {
+template <int SM, bool EX>
+__device__ __forceinline__ double rf_power_lmax_x(const double* A, int s) {
+  if constexpr (EX) s = SM;
   const int t = tid();
   double a[SM];
 #pragma unroll
@@ -381,6 +397,10 @@ __device__ __forceinline__ double rf_power_lmax(const double* A, int s) {
     if (settled) break;
   }
   return theta;
+}
+template <int SM>
+__device__ __forceinline__ double rf_power_lmax(const double* A, int s) {
+  return s == SM ? rf_power_lmax_x<SM, true>(A, s) : rf_power_lmax_x<SM, false>(A, s);
 }
 
 // The re-orthonormalisation is decided per iteration (the L^-1 bound of the
