@@ -124,3 +124,32 @@ def test_cg1r_laplace128_time_to_tol(h):
     X2, i2 = P.bkry_cg_solve(h, Ad, Bd, tol=1e-10, maxit=3000, eta=1e4)
     assert abs(info["iters"] - i2["iters"]) <= 1
     say("cg1r 128^3 iters", info["iters"], "s", info["seconds"], "two-reduction", i2["iters"], i2["seconds"])
+
+
+@pytest.mark.parametrize("s,kind,q", [(8, "block", 1), (16, "block", 1), (16, "hybrid", 2), (16, "bglobal", 2)])
+def test_cg1r_reortho_decisions_match_oracle(orc, h, s, kind, q):
+    """Intermediate eta: the one-reduction solver suspends the iteration after
+    its fused pass whenever the kappa_D test fires and re-normalises the
+    residual before the next SpMM; iteration and re-normalisation counts and
+    the residual history must equal the oracle's.  Each eta is used only where
+    every kappa_D of the (two-reduction) oracle run is at least 1e-6
+    (relative) away from the threshold, so rounding cannot decide."""
+    A = W.laplace_2d(41)
+    B = W.uniform_block(A.n, s, s)
+    sq = np.sqrt(orc.eps_f64())
+    used = fired = 0
+    for eta in (1e2, 1e3, 1e4, 1e5, 1e6, 1e7):
+        r2 = orc.bcg(A, B, kind=kind, q=q, tol=1e-10, maxit=3000, eta=eta, record_blocks=3000)
+        kd = [orc.kappa_D(orc.bdot(Pk, orc.spmm(A, Pk), kind, q)) for Pk in r2["Pk"]]
+        if min(abs(eta * k * sq - 1.0) for k in kd) < 1e-6:
+            continue
+        used += 1
+        say("cg1r reortho decisions", s, kind, eta)
+        X, info = gpu_cg1r(h, A, B, kind=kind, q=q, tol=1e-10, maxit=3000, eta=eta, hist_cap=3000)
+        ro = orc.bcg1r(A, B, kind=kind, q=q, tol=1e-10, maxit=3000, eta=eta, hist_cap=3000)
+        assert info["converged"] and ro["converged"]
+        assert (info["iters"], info["reorth"]) == (ro["iters"], ro["reorth"])
+        assert np.allclose(info["hist"], ro["hist"], rtol=1e-6, atol=1e-15)
+        assert max(info["true_relres"]) <= 1.5e-10
+        fired += ro["reorth"] > 1
+    assert used >= 4 and fired >= 1
