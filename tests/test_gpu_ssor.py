@@ -165,3 +165,24 @@ def test_pcg_ssor_full_size(orc, h):
     Xj, ij = P.bkry_pcg_solve(h, Ad, Bd, P.bkry_jacobi_minv(h, Ad), tol=1e-10, maxit=5000, eta=1e4)
     assert info["iters"] < ij["iters"]
     say("pcg ssor 64^3 iters", info["iters"], "s", info["seconds"], "jacobi", ij["iters"], ij["seconds"])
+
+
+@pytest.mark.parametrize("eta", [1e6, 1e7])
+def test_pcg_ssor_mid_solve_renormalisation(orc, h, eta):
+    """Intermediate eta where the kappa_D test fires several times mid-solve:
+    the solver suspends, re-normalises the residual, forms Z = M^-1 R-bar
+    again and resumes; counts and residual history follow the oracle's."""
+    A = W.diffusion_7pt_var(12, seed=9)
+    cdev, co = setup(h, orc, A)
+    B = W.uniform_block(A.n, 16, 7)
+    say("pcg ssor mid-solve renormalisation", eta)
+    X, info = P.bkry_pcg_ssor_solve(h, dev_csr(P, A), to_dev(B), cdev, 1.0, tol=1e-10, maxit=2000, eta=eta,
+                                    hist_cap=2000)
+    ro = orc.bcg_ssor(A, B, co, 1.0, tol=1e-10, maxit=2000, eta=eta, hist_cap=2000)
+    assert ro["reorth"] >= 4
+    assert info["converged"] and abs(info["iters"] - ro["iters"]) <= 1
+    assert abs(info["reorth"] - ro["reorth"]) <= 1
+    k = min(len(info["hist"]), len(ro["hist"]))
+    assert np.allclose(info["hist"][:k], ro["hist"][:k], rtol=1e-6, atol=1e-15)
+    assert max(info["true_relres"]) <= 1.5e-10
+    assert rel(to_np(X), np.linalg.solve(A.to_dense(), B)) < 1e-7
