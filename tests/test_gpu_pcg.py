@@ -150,3 +150,24 @@ def test_pcg_full_size_time_to_tol(h):
     X0, i0 = P.bkry_cg_solve(h, Ad, Bd, tol=1e-10, maxit=5000, eta=1e4)
     assert i0["converged"] and info["iters"] < i0["iters"]
     say("pcg 64^3 iters", info["iters"], "vs", i0["iters"], "s", info["seconds"], i0["seconds"])
+
+
+@pytest.mark.parametrize("s,eta", [(4, 1e7), (16, 1e6), (16, 1e7)])
+def test_pcg_mid_solve_renormalisation(orc, h, s, eta):
+    """Intermediate eta where the kappa_D test fires several times mid-solve:
+    the Jacobi-preconditioned solver suspends, re-normalises the residual,
+    forms Z = M^-1 R-bar from the new residual and resumes; counts and the
+    residual history follow the oracle's."""
+    A = W.diffusion_7pt_var(12, seed=9)
+    minv = jacobi(A)
+    B = W.uniform_block(A.n, s, 7)
+    say("pcg mid-solve renormalisation", s, eta)
+    X, info = gpu_pcg(h, A, B, minv, tol=1e-10, maxit=2000, eta=eta, hist_cap=2000)
+    ro = orc.bcg(A, B, tol=1e-10, maxit=2000, eta=eta, hist_cap=2000, minv=minv)
+    assert ro["reorth"] >= 3
+    assert info["converged"] and abs(info["iters"] - ro["iters"]) <= 1
+    assert abs(info["reorth"] - ro["reorth"]) <= 1
+    k = min(len(info["hist"]), len(ro["hist"]))
+    assert np.allclose(info["hist"][:k], ro["hist"][:k], rtol=1e-6, atol=1e-15)
+    assert max(info["true_relres"]) <= 1.5e-10
+    assert rel(X, np.linalg.solve(A.to_dense(), B)) < 1e-7
