@@ -74,3 +74,19 @@ def test_ir_full_size_workload(orc, h):
     assert i64["converged"] and max(i64["true_relres"]) <= 2e-10
     say("ir 96^3 outer", i32["outer_iters"], "inner", i32["iters"], "fp64 iters", i64["iters"])
     assert rel(to_np(X32), to_np(X64)) <= 1e-6
+
+
+@pytest.mark.parametrize("s,kind,q", [(32, "block", 1), (24, "hybrid", 3), (16, "bglobal", 2), (32, "bglobal", 4)])
+def test_ir_wide_blocks_and_block_global(orc, h, s, kind, q):
+    """Widths above 16 (the FP32 partials then go through the plain
+    reduction before the coefficient step) and the block-global subalgebra
+    in the FP32 inner solve; the solution error within kappa * tol of the
+    oracle's."""
+    A = W.laplace_2d(24)
+    B = W.uniform_block(A.n, s, 50 + s)
+    say("ir wide", s, kind, q)
+    X, info = P.bkry_cg_solve(h, dev_csr(P, A), to_dev(B), kind=kind, q=q, tol=1e-10, maxit=5000, eta=np.inf,
+                              prec=P.F32_IR)
+    assert info["converged"] and max(info["true_relres"]) <= 1e-10
+    ro = orc.bcg(A, B, kind=kind, q=q, tol=1e-13, maxit=5000, eta=np.inf)
+    assert rel(to_np(X), ro["X"]) <= 2 * kappa_dense(A) * 1e-10
