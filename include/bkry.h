@@ -160,9 +160,17 @@ int bkry_bdot_f32(bkry_handle h, int64_t n, int32_t p, bkry_subalg S, const floa
 /* Normaliser / S-QR decomposition (Definition "normalizer", Ch. 3; TSQR,
  * Ch. 7): X = Q R with <Q,Q>_S = I and R in S upper triangular per S-block,
  * diag(R) >= 0; Q overwrites X, R (p x p) goes to device memory.  Block and
- * hybrid use a Householder tall-skinny QR (tile QRs, then a tree of R
- * combines); parallel normalises columns and global scales by
- * |X|_F / sqrt(p).  Rank-deficient X is allowed: Q is still S-orthonormal.
+ * hybrid: CholeskyQR2 by default (R1 = chol(X^T X) per group, Y = X R1^-1,
+ * R2 = chol(Y^T Y), Q = Y R2^-1, R = R2 R1); the second pass is skipped when
+ * Y^T Y is already within rounding of I (Q = Y, R = R1).  When the first
+ * Cholesky fails or its pivots spread by more than 1e6 within a group (X
+ * near rank-deficient), or Y^T Y is not near I, a Householder tall-skinny QR
+ * (tile QRs, a tree of R combines, Q formation) runs instead, on X or on Y
+ * with R = R_householder R1.  All of this is decided on the device.
+ * For full-rank X the result is the unique QR with diag(R) > 0 up to
+ * rounding.  Block-global: the same QR of the q stacked column groups.
+ * Parallel normalises columns and global scales by |X|_F / sqrt(p).
+ * Rank-deficient X is allowed: Q is still S-orthonormal.
  * Requires n >= p (block/global) or n >= p/q (hybrid). */
 int bkry_tsqr(bkry_handle h, int64_t n, int32_t p, bkry_subalg S, double* X_inout_Q, double* R);
 
@@ -173,7 +181,11 @@ int bkry_tsqr(bkry_handle h, int64_t n, int32_t p, bkry_subalg S, double* X_inou
  * iterations.  The residual is re-normalised in iteration k when
  * eta * kappa_D(alpha_k) * sqrt(eps) > 1 (eps of the working precision);
  * eta = 0 never, eta = INFINITY always.  prec = BKRY_F64 or BKRY_F32_IR.
- * info [host] may be NULL. */
+ * With BKRY_F32_IR an inner FP32 solve that breaks down or meets non-finite
+ * values ends the refinement with that status if it made no progress or the
+ * previous inner solve failed the same way; a refinement that ends
+ * unconverged after such an inner failure returns its status instead of
+ * BKRY_NOT_CONVERGED.  info [host] may be NULL. */
 int bkry_cg_solve(bkry_handle h, const bkry_csr* A, int32_t p, bkry_subalg S, const double* B, double* X,
                   double tol, int32_t maxit, double eta, int32_t prec, bkry_info* info);
 
@@ -243,7 +255,10 @@ int bkry_jacobi_minv(bkry_handle h, const bkry_csr* A, double* minv);
  * when eta * kappa_D(<R_k, R_k>_S) * sqrt(eps) > 1 (eta = 0 never,
  * INFINITY always).  Stops when max_i |R_i| / |R0_i| <= tol (recursive
  * residual R^ sigma) or after maxit iterations; info->true_relres holds the
- * FP64 true residual.  A zero pivot or <U, U>_F = 0 is BKRY_E_BREAKDOWN.
+ * FP64 true residual.  info->converged (and BKRY_OK) requires the FP64 true
+ * residual to meet tol too: when the recursion's residual drifts from the
+ * true one the call returns BKRY_NOT_CONVERGED with X as reached.  A zero
+ * pivot or <U, U>_F = 0 is BKRY_E_BREAKDOWN.
  * FP64; X holds X0 on entry; info [host] may be NULL. */
 int bkry_bicgstab_solve(bkry_handle h, const bkry_csr* A, int32_t p, bkry_subalg S, const double* B, double* X,
                         double tol, int32_t maxit, double eta, bkry_info* info);

@@ -296,6 +296,7 @@ int bkry_profile_read(bkry_handle h, int32_t kernel, double* total_ms, int64_t* 
   if (reset) {
     h->prof->ms[kernel] = 0.0;
     h->prof->cnt[kernel] = 0;
+    h->prof->dropped[kernel] = 0;
   }
   return BKRY_OK;
 }
@@ -766,6 +767,14 @@ int bkry_bicgstab_solve(bkry_handle h, const bkry_csr* A, int32_t p, bkry_subalg
           "bicgstab");
   API_HIP(hipMemcpyAsync(trel, trr, sizeof(double) * p, hipMemcpyDeviceToHost, h->stream), "bicgstab");
   API_HIP(hipStreamSynchronize(h->stream), "bicgstab");
+  // The recursion's residual can drift from the true one (BiCGStab's residual
+  // gap): the solve counts as converged only if the FP64 true residual meets
+  // tol as well.
+  if (r.converged && tol > 0.0) {
+    double tmax = 0.0;
+    for (int i = 0; i < p; ++i) tmax = trel[i] > tmax ? trel[i] : tmax;
+    if (!(tmax <= tol)) r.converged = 0;
+  }
   if (info) {
     info->iters = r.iters;
     info->reorth = r.nreorth;

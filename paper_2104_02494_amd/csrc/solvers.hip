@@ -25,6 +25,7 @@ hipError_t prof_init(Prof* p) {
     p->used[k] = 0;
     p->ms[k] = 0.0;
     p->cnt[k] = 0;
+    p->dropped[k] = 0;
     for (int e = 0; e < 2; ++e)
       for (int i = 0; i < kProfSlots; ++i) BK_TRY(hipEventCreate(&p->ev[k][e][i]));
   }
@@ -37,10 +38,15 @@ void prof_destroy(Prof* p) {
       for (int i = 0; i < kProfSlots; ++i) (void)hipEventDestroy(p->ev[k][e][i]);
 }
 
-hipError_t prof_flush(Prof* p) {
+hipError_t prof_flush(Prof* p, const int* live) {
   if (!p) return hipSuccess;
   for (int k = 0; k < PROF_N; ++k) {
+    const int lim = live ? live[k] : 0x7fffffff;
     for (int i = 0; i < p->used[k]; ++i) {
+      if (p->iter[k][i] >= 0 && p->iter[k][i] >= lim) {
+        p->dropped[k] += 1;
+        continue;
+      }
       float ms = 0.0f;
       BK_TRY(hipEventElapsedTime(&ms, p->ev[k][0][i], p->ev[k][1][i]));
       p->ms[k] += ms;
@@ -59,9 +65,13 @@ struct ProfScope {
   int k;
   hipStream_t st;
   bool handed = false;
-  ProfScope(Prof* p_, int k_, hipStream_t st_)
+  // iter: the solver iteration the launch belongs to (-1: always live).
+  ProfScope(Prof* p_, int k_, hipStream_t st_, int iter = -1)
       : p((p_ && (p_->mask >> k_ & 1) && p_->seen[k_]++ % p_->every == 0) ? p_ : nullptr), k(k_), st(st_) {
-    if (p && p->used[k] < kProfSlots) (void)hipEventRecord(p->ev[k][0][p->used[k]], st);
+    if (p && p->used[k] < kProfSlots) {
+      p->iter[k][p->used[k]] = iter;
+      (void)hipEventRecord(p->ev[k][0][p->used[k]], st);
+    }
   }
   // End event for a launcher to record after its streaming kernel (or null).
   hipEvent_t end() {
@@ -184,25 +194,31 @@ hipError_t cg_run(const CsrView& A, Sub sub, const T* B, T* X, double tol, int m
       {
         // Q = A P and alpha = <P, Q>_S; the reduction's last workgroup
         // computes lambda, lambda sigma and the re-orthonormalisation test
-        ProfScope ps(prof, PROF_CG_SPMM, st);
+        ProfScope ps(prof, PROF_CG_SPMM, st, k);
         BK_TRY(launch_spmm<T>(A, s, Pk, b.Q, nullptr, 1, b.partial, nblk, ra, &c->bad_index, gate, st,
                               Epi{EPI_CG_ALPHA, c, nullptr}, ps.end()));
       }
       {
         // R~ = R - Q lambda and its Gram; then the stopping test, rho' and beta
-        ProfScope ps(prof, PROF_CG_UPDATE, st);
+        ProfScope ps(prof, PROF_CG_UPDATE, st, k);
         BK_TRY(launch_cg_update<T>(n, s, b.R, b.Q, c, b.partial, nblk, rr, st,
                                    Epi{minv ? EPI_CG_RHO_M : EPI_CG_RHO, c, b.hist}, ps.end(), minv));
       }
       if (always) BK_TRY(cg_normalise<T>(n, sub, b, nblk, st, prof, minv));
       {
-        ProfScope ps(prof, PROF_CG_PUPDATE, st);
+        ProfScope ps(prof, PROF_CG_PUPDATE, st, k);
         BK_TRY(launch_cg_pupdate<T>(n, s, X, Pk, Pn, b.R, c, st, minv));
       }
     }
     BK_TRY(hipMemcpyAsync(hflags, c, kCtlHeaderInts * sizeof(int32_t), hipMemcpyDeviceToHost, st));
     BK_TRY(hipStreamSynchronize(st));
-    BK_TRY(prof_flush(prof));
+    {
+      // two-reduction loop: iteration iters-1 is the last whose SpMM and
+      // residual update ran; a suspended iteration's direction update waits
+      const int it = hc->iters, itp = hc->suspended ? hc->iters - 1 : hc->iters;
+      const int live[PROF_N] = {it, it, itp, 0x7fffffff};
+      BK_TRY(prof_flush(prof, live));
+    }
     if (hc->done) break;
     if (hc->suspended) {
       // iteration iters-1 waits for its re-normalisation (the later kernels
@@ -340,7 +356,7 @@ hipError_t pcg_ssor_run(const CsrView& A, Sub sub, const double* B, double* X, d
       double* const Pk = pbuf[k & 1];
       double* const Pn = pbuf[(k + 1) & 1];
       {
-        ProfScope ps(prof, PROF_CG_SPMM, st);
+        ProfScope ps(prof, PROF_CG_SPMM, st, k);
         BK_TRY(launch_spmm<double>(A, s, Pk, b.Q, nullptr, 1, b.partial, nblk, ra, &c->bad_index, gate, st,
                                    Epi{EPI_CG_ALPHA, c, nullptr}, ps.end()));
       }
@@ -348,7 +364,7 @@ hipError_t pcg_ssor_run(const CsrView& A, Sub sub, const double* B, double* X, d
         // R~ = R - Q lambda (Gram of R~ into the first half of each partial);
         // unless R~ is re-normalised, Z = M^-1 R~ into Q and <Z, R~> into the
         // second half; one reduction for both (stopping test, rho', beta)
-        ProfScope ps(prof, PROF_CG_UPDATE, st);
+        ProfScope ps(prof, PROF_CG_UPDATE, st, k);
         BK_TRY(launch_cg_update_partials(n, s, b.R, b.Q, c, b.partial, nblk, 2 * ss, st));
         BK_TRY(launch_ssor_apply(m, s, b.R, b.Q, gate, &c->fire, nullptr, st));
         BK_TRY(launch_gram_partials(n, s, b.Q, b.R, b.partial + ss, nblk, 2 * ss, gate, &c->fire, st));
@@ -356,13 +372,19 @@ hipError_t pcg_ssor_run(const CsrView& A, Sub sub, const double* B, double* X, d
       }
       if (always) BK_TRY(ssor_normalise(n, sub, b, m, nblk, st, prof));
       {
-        ProfScope ps(prof, PROF_CG_PUPDATE, st);
+        ProfScope ps(prof, PROF_CG_PUPDATE, st, k);
         BK_TRY(launch_cg_pupdate<double>(n, s, X, Pk, Pn, b.Q, c, st, nullptr));
       }
     }
     BK_TRY(hipMemcpyAsync(hflags, c, kCtlHeaderInts * sizeof(int32_t), hipMemcpyDeviceToHost, st));
     BK_TRY(hipStreamSynchronize(st));
-    BK_TRY(prof_flush(prof));
+    {
+      // two-reduction loop: iteration iters-1 is the last whose SpMM and
+      // residual update ran; a suspended iteration's direction update waits
+      const int it = hc->iters, itp = hc->suspended ? hc->iters - 1 : hc->iters;
+      const int live[PROF_N] = {it, it, itp, 0x7fffffff};
+      BK_TRY(prof_flush(prof, live));
+    }
     if (hc->done) break;
     if (hc->suspended) {
       const int ks = hc->iters - 1;
@@ -446,19 +468,25 @@ hipError_t cg1r_run(const CsrView& A, Sub sub, const double* B, double* X, doubl
   while (maxit > 0) {
     for (int it = 0; it < batch; ++it, ++k) {
       {
-        ProfScope ps(prof, PROF_CG_SPMM, st);
+        ProfScope ps(prof, PROF_CG_SPMM, st, k);
         BK_TRY(launch_spmm<double>(A, s, b.R, b.P2, nullptr, 1, b.partial, nblk, red, &c->bad_index, gate, st,
                                    Epi{EPI_CG_1R, c, b.hist}, ps.end(), 1, 2));
       }
       {
-        ProfScope ps(prof, PROF_CG_UPDATE, st);
+        ProfScope ps(prof, PROF_CG_UPDATE, st, k);
         BK_TRY(launch_cg1r_pass(n, s, b.R, b.P2, b.P, b.Q, X, c, b.partial, nblk, k, 0, st));
       }
       if (always) BK_TRY(cg1r_normalise(n, sub, b, nblk, k, st, prof));
     }
     BK_TRY(hipMemcpyAsync(hflags, c, kCtlHeaderInts * sizeof(int32_t), hipMemcpyDeviceToHost, st));
     BK_TRY(hipStreamSynchronize(st));
-    BK_TRY(prof_flush(prof));
+    {
+      // one-reduction loop: the SpMM of iteration iters decided the end (or
+      // the suspension); the fused pass of that iteration ran unless it ended
+      const int it = hc->iters + 1, itp = hc->done ? hc->iters : hc->iters + 1;
+      const int live[PROF_N] = {it, itp, 0x7fffffff, 0x7fffffff};
+      BK_TRY(prof_flush(prof, live));
+    }
     if (hc->done) break;
     if (hc->suspended) {
       // iteration j fired: its fused pass ran, the later kernels of the batch
@@ -668,7 +696,10 @@ hipError_t ir_run(const CsrView& A, Sub sub, const double* B, double* X, double 
       res.converged = 1;
       return hipSuccess;
     }
-    if (outer >= max_outer) return hipSuccess;
+    if (outer >= max_outer) {
+      res.status = res.inner_status;
+      return hipSuccess;
+    }
     BK_TRY(launch_cast_scale_f32(n, s, b.R64, b.scale, b.R32, st));
     BK_TRY(hipMemsetAsync(b.X32, 0, sizeof(float) * (size_t)n * s, st));
     CgResult r;
@@ -680,10 +711,17 @@ hipError_t ir_run(const CsrView& A, Sub sub, const double* B, double* X, double 
       res.bad_index = 1;
       return hipSuccess;
     }
-    if (r.status != 0 && r.iters <= 1) {
+    // An inner breakdown or non-finite value ends the refinement when the
+    // inner solve made no progress, or when the previous outer step's inner
+    // solve failed the same way; otherwise its partial correction is kept and
+    // the failure is remembered (and reported if the refinement ends
+    // unconverged).
+    if (r.status != 0 && (r.iters <= 1 || r.status == res.inner_status)) {
       res.status = r.status;
+      res.inner_status = r.status;
       return hipSuccess;
     }
+    res.inner_status = r.status;
     BK_TRY(launch_accum_scaled(n, s, b.X32, b.scale, X, st));
   }
 }

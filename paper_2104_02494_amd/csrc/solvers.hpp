@@ -27,8 +27,10 @@ constexpr int kProfSlots = 64;
 struct Prof {
   hipEvent_t ev[PROF_N][2][kProfSlots];
   int used[PROF_N];
+  int iter[PROF_N][kProfSlots];  // iteration of the timed launch (-1: always live)
   double ms[PROF_N];
   long long cnt[PROF_N];
+  long long dropped[PROF_N];     // timed launches discarded as gated off
   int mask = (1 << PROF_N) - 1;  // kernel ids that are timed (bit k = id k)
   int every = 1;                  // time one launch in `every` of each kernel
   long long seen[PROF_N] = {};    // launches seen per kernel id
@@ -36,7 +38,11 @@ struct Prof {
 hipError_t prof_init(Prof* p);
 void prof_destroy(Prof* p);
 // Accumulates the recorded pairs (the stream must have been synchronised).
-hipError_t prof_flush(Prof* p);
+// live (null: every launch counts): per kernel id, the first iteration whose
+// launches found the solve ended or suspended and returned at once; timings
+// of launches of iterations >= live[id] are discarded, so averages cover
+// only launches that did the work.
+hipError_t prof_flush(Prof* p, const int* live = nullptr);
 
 // Pinned host staging area shared by the drivers: ints [0, 64) receive
 // read-backs, ints [64, 256) stage uploads.
@@ -112,6 +118,7 @@ IrBufs carve_ir(Carver& c, int64_t n, int64_t nnz, Sub sub, uint32_t* cnt);
 
 struct IrResult {
   int status = 0, converged = 0, outer = 0, inner_iters = 0, nreorth = 0, bad_index = 0, hist_len = 0;
+  int inner_status = 0;  // status of the last inner solve (0, -2 breakdown, -3 non-finite)
 };
 hipError_t ir_run(const CsrView& A, Sub sub, const double* B, double* X, double tol, int maxit, double eta,
                   double inner_tol, int max_outer, double* hist_host, int hist_cap, const IrBufs& b, hipStream_t st,
