@@ -70,14 +70,14 @@ void or_residual(i64 n, const int32_t* rowptr, const int32_t* colind, const doub
   for (i64 t = 0; t < n * s; ++t) R[t] = B[t] - R[t];
 }
 
-/* Full Gram matrix G = X^T Y (s x s), rows summed in ascending order. */
+/* Full Gram matrix G = X^T Y (s x s), rows summed in ascending order.  Every
+ * entry is its own running sum over the rows; the rows are visited once, in
+ * order, so the blocks are read row by row. */
 void or_gram(i64 n, int s, const double* X, i64 ldx, const double* Y, i64 ldy, double* G) {
-  for (int a = 0; a < s; ++a)
-    for (int b = 0; b < s; ++b) {
-      double acc = 0.0;
-      for (i64 i = 0; i < n; ++i) acc += X[i * ldx + a] * Y[i * ldy + b];
-      G[a * s + b] = acc;
-    }
+  for (int t = 0; t < s * s; ++t) G[t] = 0.0;
+  for (i64 i = 0; i < n; ++i)
+    for (int a = 0; a < s; ++a)
+      for (int b = 0; b < s; ++b) G[a * s + b] += X[i * ldx + a] * Y[i * ldy + b];
 }
 
 /* Projection of a full Gram matrix onto the subalgebra, which turns X^T Y into
@@ -138,7 +138,8 @@ int or_householder_qr(i64 m, int c, const double* X, i64 ldx, double* Q, i64 ldq
   if (m < c || c < 1) return OR_E_INVALID;
   double* A = (double*)malloc(sizeof(double) * (size_t)(m * c));
   double* beta = (double*)malloc(sizeof(double) * (size_t)c);
-  if (!A || !beta) { free(A); free(beta); return OR_E_INVALID; }
+  double* w = (double*)malloc(sizeof(double) * (size_t)c);
+  if (!A || !beta || !w) { free(A); free(beta); free(w); return OR_E_INVALID; }
   for (i64 i = 0; i < m; ++i)
     for (int j = 0; j < c; ++j) A[i * c + j] = X[i * ldx + j];
 
@@ -155,13 +156,15 @@ int or_householder_qr(i64 m, int c, const double* X, i64 ldx, double* Q, i64 ldq
     beta[j] = 2.0 * v1 * v1 / (sig + v1 * v1);
     for (i64 i = j + 1; i < m; ++i) A[i * c + j] /= v1; /* v = [1; x(2:)/v1] */
     A[(i64)j * c + j] = mu;
-    /* apply H_j = I - beta v v^T to the trailing columns */
-    for (int cc = j + 1; cc < c; ++cc) {
-      double w = A[(i64)j * c + cc];
-      for (i64 i = j + 1; i < m; ++i) w += A[i * c + j] * A[i * c + cc];
-      A[(i64)j * c + cc] -= beta[j] * w;
-      for (i64 i = j + 1; i < m; ++i) A[i * c + cc] -= beta[j] * A[i * c + j] * w;
-    }
+    /* apply H_j = I - beta v v^T to the trailing columns: w_cc = v^T a_cc
+     * (a running sum over the rows in ascending order per column), then
+     * a_cc -= beta v w_cc */
+    for (int cc = j + 1; cc < c; ++cc) w[cc] = A[(i64)j * c + cc];
+    for (i64 i = j + 1; i < m; ++i)
+      for (int cc = j + 1; cc < c; ++cc) w[cc] += A[i * c + j] * A[i * c + cc];
+    for (int cc = j + 1; cc < c; ++cc) A[(i64)j * c + cc] -= beta[j] * w[cc];
+    for (i64 i = j + 1; i < m; ++i)
+      for (int cc = j + 1; cc < c; ++cc) A[i * c + cc] -= beta[j] * A[i * c + j] * w[cc];
   }
   for (int a = 0; a < c; ++a)
     for (int b = 0; b < c; ++b) R[a * c + b] = (b >= a) ? A[(i64)a * c + b] : 0.0;
@@ -171,12 +174,12 @@ int or_householder_qr(i64 m, int c, const double* X, i64 ldx, double* Q, i64 ldq
     for (int j = 0; j < c; ++j) Q[i * ldq + j] = (i == j) ? 1.0 : 0.0;
   for (int j = c - 1; j >= 0; --j) {
     if (beta[j] == 0.0) continue;
-    for (int cc = j; cc < c; ++cc) {
-      double w = Q[(i64)j * ldq + cc];
-      for (i64 i = j + 1; i < m; ++i) w += A[i * c + j] * Q[i * ldq + cc];
-      Q[(i64)j * ldq + cc] -= beta[j] * w;
-      for (i64 i = j + 1; i < m; ++i) Q[i * ldq + cc] -= beta[j] * A[i * c + j] * w;
-    }
+    for (int cc = j; cc < c; ++cc) w[cc] = Q[(i64)j * ldq + cc];
+    for (i64 i = j + 1; i < m; ++i)
+      for (int cc = j; cc < c; ++cc) w[cc] += A[i * c + j] * Q[i * ldq + cc];
+    for (int cc = j; cc < c; ++cc) Q[(i64)j * ldq + cc] -= beta[j] * w[cc];
+    for (i64 i = j + 1; i < m; ++i)
+      for (int cc = j; cc < c; ++cc) Q[i * ldq + cc] -= beta[j] * A[i * c + j] * w[cc];
   }
   /* canonical signs: diag(R) >= 0 */
   for (int j = 0; j < c; ++j) {
@@ -187,6 +190,7 @@ int or_householder_qr(i64 m, int c, const double* X, i64 ldx, double* Q, i64 ldq
   }
   free(A);
   free(beta);
+  free(w);
   return OR_OK;
 }
 
@@ -419,11 +423,10 @@ static void block_axmy(i64 n, int s, const double* X, const double* c, double* Y
     }
 }
 static void column_norms(i64 n, int s, const double* X, double* out) {
-  for (int j = 0; j < s; ++j) {
-    double acc = 0.0;
-    for (i64 i = 0; i < n; ++i) acc += X[i * s + j] * X[i * s + j];
-    out[j] = sqrt(acc);
-  }
+  for (int j = 0; j < s; ++j) out[j] = 0.0;
+  for (i64 i = 0; i < n; ++i)
+    for (int j = 0; j < s; ++j) out[j] += X[i * s + j] * X[i * s + j];
+  for (int j = 0; j < s; ++j) out[j] = sqrt(out[j]);
 }
 /* max_i num_i / den_i over columns with den_i > 0 (a column whose initial
  * residual is zero counts as converged) */
