@@ -48,6 +48,22 @@ def test_adjoint_vs_oracle(orc, h):
     assert rel(dv, dv_or) < 1e-9
 
 
+def test_adjoint_vs_oracle_wide(orc, h):
+    """The 32 right-hand sides of the 64^3 workload on a 16^3 instance of its
+    generator (n = 4,096): solution, dL/dB and dL/dvalues against the
+    oracle's adjoint (oracle block CG on A^T, then the sampled product)."""
+    A = W.diffusion_7pt_var(16, seed=1005)
+    B = W.gaussian_block(A.n, 32, 2005)
+    T = W.gaussian_block(A.n, 32, 3005)
+    say("adjoint vs oracle p=32 16^3")
+    X, dv, dB = grads(h, A, B, T)
+    ro = orc.bcg(A, B, tol=1e-13, maxit=5000, eta=np.inf)
+    lam, dv_or, _ = orc.adjoint(A, ro["X"], ro["X"] - T, eta=np.inf)
+    assert rel(X, ro["X"]) < 1e-10
+    assert rel(dB, lam) < 1e-9
+    assert rel(dv, dv_or) < 1e-9
+
+
 def pair_index(A):
     """k -> position of the transposed entry (j, i) of entry k = (i, j)."""
     pos = {}
@@ -96,9 +112,10 @@ def test_adjoint_finite_differences(h):
 
 
 def test_adjoint_full_size_finite_differences(h):
-    """The 64^3 / p = 32 workload itself, 4 sampled entries."""
+    """The 64^3 / p = 32 workload itself, 64 pattern entries sampled
+    uniformly (seed 5005), two perturbed solves each."""
     A, B, extra = W.build_workload("diffusion7var_64_s32")
     T = extra["target"]
-    entries = np.random.default_rng(5005).choice(A.nnz, size=4, replace=False)
+    entries = np.random.default_rng(5005).choice(A.nnz, size=64, replace=False)
     say("adjoint FD 64^3")
     assert fd_check(h, A, B, T, entries) <= 1e-5

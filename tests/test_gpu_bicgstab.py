@@ -115,7 +115,9 @@ def test_bicgstab_residual_gap_matches_oracle(orc, h):
         u = np.random.default_rng(seed).uniform(-1.0, 1.0, B.shape)
         say("bicgstab 128^2 solve", seed)
         X, info = gpu_bc(h, A, B * (1.0 + 4e-16 * u), tol=1e-10, maxit=5000, eta=1e4)
-        assert info["converged"]
+        # the recursion met the tolerance; converged reports the true residual
+        assert max(info["relres"]) <= 1e-10
+        assert info["converged"] == (max(info["true_relres"]) <= 1e-10)
         assert abs(info["iters"] - ro["iters"]) <= max(5, ro["iters"] // 10)
         gaps.append(max(info["true_relres"]))
     assert np.median(gaps) <= 10.0 * true_o.max() + 1e-10, (gaps, true_o.max())
@@ -130,4 +132,6 @@ def test_bicgstab_full_size_time_to_tol(h):
     say("bicgstab 1024^2 solve")
     X, info = P.bkry_bicgstab_solve(h, dev_csr(P, A), to_dev(B), tol=1e-10, maxit=20000, eta=1e4)
     say("bicgstab 1024^2 iters", info["iters"], "reorth", info["reorth"], "s", info["seconds"])
-    assert info["converged"] and max(info["true_relres"]) < 1e-6
+    assert max(info["relres"]) <= 1e-10
+    assert info["converged"] == (max(info["true_relres"]) <= 1e-10)
+    assert max(info["true_relres"]) < 1e-6

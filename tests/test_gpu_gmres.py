@@ -15,6 +15,9 @@ pytestmark = pytest.mark.gpu
 P = pytest.importorskip("paper_2104_02494_amd")
 
 SUBS = [("block", 1), ("hybrid", 2), ("parallel", 1), ("global", 1), ("bglobal", 2)]
+# widths: 4, the 8 of the 1024^2 convection-diffusion workload, and the wide
+# blocks whose CGS2 block combinations and Givens steps take other code paths
+WIDTHS = [4, 8, 16, 32]
 
 
 def gpu_gm(h, A, B, **kw):
@@ -22,12 +25,19 @@ def gpu_gm(h, A, B, **kw):
     return to_np(X), info
 
 
+def fixed_problem(p):
+    # the block Krylov space after the longest case (17 steps) stays well
+    # inside the space: 17 p < n
+    A = W.convdiff_2d(24 if p <= 8 else 40)     # nonsymmetric, n = 576 or 1600
+    return A, W.gaussian_block(A.n, p, 7 + p)
+
+
+@pytest.mark.parametrize("p", WIDTHS)
 @pytest.mark.parametrize("kind,q", SUBS)
 @pytest.mark.parametrize("steps,restart", [(1, 30), (6, 30), (17, 30), (23, 5)])
-def test_gmres_fixed_steps(orc, h, kind, q, steps, restart):
-    A = W.convdiff_2d(24)                       # nonsymmetric, n = 576
-    B = W.gaussian_block(A.n, 4, 7)
-    say("gmres fixed", kind, steps, restart)
+def test_gmres_fixed_steps(orc, h, p, kind, q, steps, restart):
+    A, B = fixed_problem(p)
+    say("gmres fixed", p, kind, steps, restart)
     X, info = gpu_gm(h, A, B, kind=kind, q=q, tol=0.0, maxit=steps, restart=restart)
     ro = orc.bgmres(A, B, kind=kind, q=q, tol=0.0, maxit=steps, restart=restart)
     assert info["iters"] == ro["iters"] == steps
@@ -35,18 +45,29 @@ def test_gmres_fixed_steps(orc, h, kind, q, steps, restart):
     assert rel(X, ro["X"]) < 1e-10
 
 
+@pytest.mark.parametrize("p", WIDTHS)
 @pytest.mark.parametrize("kind,q", SUBS)
-def test_gmres_converges_like_oracle(orc, h, kind, q):
+def test_gmres_converges_like_oracle(orc, h, p, kind, q):
     A = W.convdiff_2d(32)
-    B = W.gaussian_block(A.n, 4, 8)
-    say("gmres solve", kind)
+    B = W.gaussian_block(A.n, p, 8 + p)
+    say("gmres solve", p, kind)
     X, info = gpu_gm(h, A, B, kind=kind, q=q, tol=1e-10, maxit=3000, restart=30, hist_cap=3000)
     ro = orc.bgmres(A, B, kind=kind, q=q, tol=1e-10, maxit=3000, restart=30, hist_cap=3000)
     assert info["converged"] and ro["converged"]
     assert abs(info["iters"] - ro["iters"]) <= 1
     assert max(info["true_relres"]) <= 1e-9
     k = min(len(info["hist"]), len(ro["hist"])) - 1
-    assert np.allclose(info["hist"][:k], ro["hist"][:k], rtol=1e-6, atol=1e-14)
+    hg, ho = np.asarray(info["hist"][:k]), np.asarray(ro["hist"][:k])
+    # relative agreement while the residual is large; near the tolerance the
+    # two orthogonalisations (CGS2 here, MGS in the oracle) differ by their
+    # rounding: MGS loses orthogonality in proportion to |R0| / |R_k|, so the
+    # histories differ by an absolute amount of about eps kappa(A) k sqrt(k p)
+    # (in units of |R0|; measured up to 2.4e-11 at p = 32, where 30 steps
+    # span 960 of the 1024 dimensions).  Half the stopping tolerance bounds
+    # it and keeps the stopping steps within one of each other.
+    diff = np.abs(hg - ho)
+    say("gmres hist worst rel", float((diff / ho).max()), "worst abs", float(diff.max()))
+    assert np.all(diff <= 1e-6 * ho + 5e-11)
 
 
 def test_gmres_edge_cases(orc, h):
@@ -78,6 +99,19 @@ def test_gmres_deterministic(h):
     X1, i1 = gpu_gm(h, A, B, tol=1e-10, maxit=500)
     X2, i2 = gpu_gm(h, A, B, tol=1e-10, maxit=500)
     assert np.array_equal(X1, X2) and i1["iters"] == i2["iters"]
+
+
+def test_gmres_full_size_first_cycle_vs_oracle(orc, h):
+    """The 1024^2 convection-diffusion workload with 8 right-hand sides: the
+    first GMRes(30) cycle (30 Arnoldi steps from X0 = 0) against the oracle's
+    modified Gram-Schmidt Arnoldi at equal step counts."""
+    A, B, _ = W.build_workload("convdiff2d_1024_s8")
+    say("gmres 1024^2 first cycle vs oracle")
+    X, info = gpu_gm(h, A, B, kind="block", tol=0.0, maxit=30, restart=30)
+    assert info["iters"] == 30 and info["outer_iters"] == 1
+    ro = orc.bgmres(A, B, kind="block", tol=0.0, maxit=30, restart=30)
+    assert ro["iters"] == 30
+    assert rel(X, ro["X"]) < 1e-10
 
 
 def test_gmres_full_size_cycle(h):

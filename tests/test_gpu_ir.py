@@ -60,6 +60,36 @@ def test_ir_outer_cap(h):
     assert 1e-10 < max(info["true_relres"]) <= 1e-4
 
 
+def test_ir_largest_oracle_instance(orc, h):
+    """The 27-point log-normal diffusion on a 32^3 grid (n = 32,768, 16
+    right-hand sides; the largest instance of the 96^3 workload's generator
+    whose FP64 oracle solve fits the test budget) against the oracle solved
+    to 1e-12.  X_IR - X_or = A^-1 (R_or - R_IR) for the two residuals
+    R = B - A X, so |X_IR - X_or|_F <= |R_IR - R_or|_F / lambda_min(A); the
+    residuals are recomputed here in FP64 and lambda_min comes from a
+    shift-invert Lanczos run (scipy's eigsh)."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as sla
+    A = W.diffusion_27pt(32, seed=1003)
+    B = W.gaussian_block(A.n, 16, 2003)
+    say("ir diffusion27 32^3 vs oracle")
+    X, info = P.bkry_cg_solve(h, dev_csr(P, A), to_dev(B), tol=1e-10, maxit=20000, eta=1.0, prec=P.F32_IR)
+    X = to_np(X)
+    assert info["converged"] and max(info["true_relres"]) <= 1e-10
+    ro = orc.bcg(A, B, tol=1e-12, maxit=20000, eta=np.inf)
+    assert ro["converged"]
+    M = sp.csr_matrix((A.val, A.colind, A.rowptr), shape=(A.n, A.n))
+    lmin = sla.eigsh(M, k=1, sigma=0, which="LM", return_eigenvectors=False)[0]
+    R_ir, R_or = B - M @ X, B - M @ ro["X"]
+    # rounding of the recomputed residuals: gamma_27 |A| |X| per entry
+    round_err = 27 * 2.3e-16 * np.linalg.norm(abs(M) @ abs(X))
+    bound = (np.linalg.norm(R_ir - R_or) + 2 * round_err) / lmin / np.linalg.norm(ro["X"])
+    err = rel(X, ro["X"])
+    say("ir 32^3 error vs oracle", err, "bound", bound, "outer", info["outer_iters"], "inner", info["iters"])
+    assert err <= 1.01 * bound
+    assert np.linalg.norm(R_ir, axis=0).max() / np.linalg.norm(B, axis=0).min() <= 1.5e-10
+
+
 def test_ir_full_size_workload(orc, h):
     """The 96^3 27-point workload itself: IR reaches the FP64 tolerance, and
     its solution agrees with the FP64 GPU solve to the stated bound

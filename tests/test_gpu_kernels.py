@@ -110,6 +110,23 @@ def test_tsqr_block_matches_householder(orc, h, n, s):
     assert rel(Q @ R, X) < 1e-14
 
 
+def test_tsqr_full_size_vs_householder(orc, h):
+    """The standalone TSQR workload itself: 4,194,304 x 32 Gaussian (seed
+    1044) against one Householder QR of the whole matrix in the oracle
+    (about 17 GFLOP on one core), after sign canonicalisation."""
+    X = W.tsqr_input()
+    say("tsqr 4194304 x 32 vs householder")
+    Xd = to_dev(X)
+    R = to_np(P.bkry_tsqr(h, Xd, "block"))
+    Q = to_np(Xd)
+    del Xd
+    Qo, Ro = orc.householder_qr(X)
+    assert np.all(np.diag(R) >= 0) and np.allclose(np.tril(R, -1), 0)
+    assert rel(R, Ro) < 1e-12 and rel(Q, Qo) < 1e-12
+    assert np.abs(Q.T @ Q - np.eye(32)).max() < 1e-13
+    assert rel(Q @ R, X) < 1e-13
+
+
 @pytest.mark.parametrize("s", [9, 12, 16, 20, 24, 31, 32])
 def test_matrix_core_widths(orc, h, s):
     """Widths 9..32 run the FP64 Gram and row products on the matrix cores
