@@ -73,6 +73,9 @@ def lib():
                                    i32]),
             "or_block_arnoldi": (i32, [i64, ptr, ptr, ptr, i32, i32, i32, ptr, i32, ptr, ptr, ptr]),
             "or_bgmres": (i32, [i64, ptr, ptr, ptr, i32, i32, i32, ptr, ptr, dbl, i32, i32, ptr, ptr, ptr, i32]),
+            "or_bgmres_pipelined": (i32, [i64, ptr, ptr, ptr, i32, i32, i32, ptr, ptr, dbl, i32, i32, i32, ptr, ptr,
+                                          ptr, i32]),
+            "or_block_arnoldi_pipelined": (i32, [i64, ptr, ptr, ptr, i32, i32, i32, ptr, i32, i32, ptr, ptr, ptr]),
             "or_sddmm": (None, [i64, ptr, ptr, i32, dbl, ptr, ptr, ptr]),
             "or_csr_transpose": (None, [i64, ptr, ptr, ptr, ptr, ptr, ptr, ptr]),
             "or_eps_f64": (dbl, []),
@@ -320,19 +323,27 @@ def bbicgstab(A, B, X0=None, kind="block", q=1, tol=1e-10, maxit=1000, eta=0.0, 
                 hist=hist[:min(it, hist_cap)] if hist_cap else None)
 
 
-def block_arnoldi(A, R, m, kind="block", q=1):
+def block_arnoldi(A, R, m, kind="block", q=1, pipelined=None):
+    """Block Arnoldi with modified Gram-Schmidt, or with the pipelined
+    Gram-Schmidt of window `pipelined` (an int >= 0)."""
     n, rp, ci, v = _csr(A)
     R = _f64(R)
     s = R.shape[1]
     V = np.zeros((m + 1, n, s))
     H = np.zeros((m + 1, m, s, s))
     sig0 = np.zeros((s, s))
-    st = lib().or_block_arnoldi(n, _p(rp), _p(ci), _p(v), s, _kind(kind), q, _p(R), m, _p(V), _p(H), _p(sig0))
+    if pipelined is None:
+        st = lib().or_block_arnoldi(n, _p(rp), _p(ci), _p(v), s, _kind(kind), q, _p(R), m, _p(V), _p(H), _p(sig0))
+    else:
+        st = lib().or_block_arnoldi_pipelined(n, _p(rp), _p(ci), _p(v), s, _kind(kind), q, _p(R), m,
+                                              int(pipelined), _p(V), _p(H), _p(sig0))
     return st, V, H, sig0
 
 
-def bgmres(A, B, X0=None, kind="block", q=1, tol=1e-10, maxit=1000, restart=30, hist_cap=0):
-    """Restarted block GMRes.  Returns dict(status, X, iters, cycles, converged, relres, hist)."""
+def bgmres(A, B, X0=None, kind="block", q=1, tol=1e-10, maxit=1000, restart=30, hist_cap=0, pipelined=None):
+    """Restarted block GMRes (modified Gram-Schmidt, or the pipelined
+    Gram-Schmidt of window `pipelined`).  Returns dict(status, X, iters,
+    cycles, converged, relres, hist)."""
     n, rp, ci, v = _csr(A)
     B = _f64(B)
     s = B.shape[1]
@@ -340,8 +351,13 @@ def bgmres(A, B, X0=None, kind="block", q=1, tol=1e-10, maxit=1000, restart=30, 
     info = np.zeros(4, dtype=np.int32)
     relres = np.zeros(s)
     hist = np.zeros(max(hist_cap, 1))
-    st = lib().or_bgmres(n, _p(rp), _p(ci), _p(v), s, _kind(kind), q, _p(B), _p(X), tol, maxit, restart,
-                         _p(info), _p(relres), _p(hist) if hist_cap else None, hist_cap)
+    if pipelined is None:
+        st = lib().or_bgmres(n, _p(rp), _p(ci), _p(v), s, _kind(kind), q, _p(B), _p(X), tol, maxit, restart,
+                             _p(info), _p(relres), _p(hist) if hist_cap else None, hist_cap)
+    else:
+        st = lib().or_bgmres_pipelined(n, _p(rp), _p(ci), _p(v), s, _kind(kind), q, _p(B), _p(X), tol, maxit,
+                                       restart, int(pipelined), _p(info), _p(relres),
+                                       _p(hist) if hist_cap else None, hist_cap)
     it = int(info[0])
     return dict(status=st, X=X, iters=it, cycles=int(info[1]), converged=bool(info[2]), relres=relres,
                 hist=hist[:min(it, hist_cap)] if hist_cap else None)

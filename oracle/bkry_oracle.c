@@ -1019,6 +1019,34 @@ static int arnoldi_step(i64 n, const int32_t* rowptr, const int32_t* colind, con
   return or_normalize(n, s, kind, q, W, W, h + (size_t)(k + 1) * ss);
 }
 
+/* ------------------------------------------------------------------------ */
+/* Block Arnoldi step with the pipelined Gram-Schmidt orthogonalisation of   */
+/* Ch. 9 (Algorithm "Pipelined Gram-Schmidt Orthogonalization") with window  */
+/* r: the inner products of the first r basis blocks are formed first; then  */
+/* each further inner product h_i = <V_i, W>_S is formed before the update   */
+/* with basis block i - r is subtracted; the last r updates follow; finally  */
+/* (V_{k+1}, gamma) = Norm_S(W).  Readings: the window is min(r, k) (the     */
+/* listing asks for 1 <= r <= k); the closing loop subtracts the blocks      */
+/* k - r + 1 .. k, the ones the middle loop has not subtracted (the printed  */
+/* lower bound k - r would subtract block k - r twice; with k - r + 1, r = 0 */
+/* is modified and r = k classical Gram-Schmidt, as the text states); h_i =  */
+/* <V_i, W>_S as for modified Gram-Schmidt above.                            */
+/* ------------------------------------------------------------------------ */
+static int arnoldi_step_pipelined(i64 n, const int32_t* rowptr, const int32_t* colind, const double* val, int s,
+                                  int kind, int q, double* V, int k, int r, double* h /* (k+2) s x s */) {
+  size_t blk = (size_t)(n * s), ss = (size_t)s * s;
+  double* W = V + (size_t)(k + 1) * blk;
+  const int w = r < k ? r : k;
+  or_spmm(n, rowptr, colind, val, s, V + (size_t)k * blk, W);
+  for (int i = 0; i < w; ++i) or_bdot(n, s, kind, q, V + (size_t)i * blk, W, h + (size_t)i * ss);
+  for (int i = w; i <= k; ++i) {
+    or_bdot(n, s, kind, q, V + (size_t)i * blk, W, h + (size_t)i * ss);
+    block_axmy(n, s, V + (size_t)(i - w) * blk, h + (size_t)(i - w) * ss, W);
+  }
+  for (int i = k - w + 1; i <= k; ++i) block_axmy(n, s, V + (size_t)i * blk, h + (size_t)i * ss, W);
+  return or_normalize(n, s, kind, q, W, W, h + (size_t)(k + 1) * ss);
+}
+
 /* Block Arnoldi with m steps from V0 = Norm_S(R) (for the Arnoldi relation
  * checks).  V gets m+1 blocks; H ((m+1) x m S-elements, entry (j,k) at
  * H[(j*m + k) * s*s]) the block Hessenberg matrix with A V~ = V H. */
@@ -1132,9 +1160,12 @@ static void apply_givens_T(int s, int g, const double* Om /* per group 2g x 2g *
 /* relres[s] = true relative column residuals at exit; hist = per step       */
 /* residual measure.                                                         */
 /* ------------------------------------------------------------------------ */
-int or_bgmres(i64 n, const int32_t* rowptr, const int32_t* colind, const double* val, int s, int kind, int q,
-              const double* B, double* X, double tol, int maxit, int restart, int32_t* info, double* relres,
-              double* hist, int hist_cap) {
+/* orth < 0: modified Gram-Schmidt; orth = r >= 0: pipelined Gram-Schmidt
+ * with window r (r = 0 is modified Gram-Schmidt again, r >= restart - 1
+ * classical Gram-Schmidt). */
+static int bgmres_impl(i64 n, const int32_t* rowptr, const int32_t* colind, const double* val, int s, int kind,
+                       int q, const double* B, double* X, double tol, int maxit, int restart, int orth,
+                       int32_t* info, double* relres, double* hist, int hist_cap) {
   int g = group_width(s, kind, q);
   if (g < 1 || s > 64 || restart < 1 || n < s) return OR_E_INVALID;
   int m = restart, ngrp = s / g;
@@ -1168,7 +1199,8 @@ int or_bgmres(i64 n, const int32_t* rowptr, const int32_t* colind, const double*
     if (st != OR_OK) goto finish;
     int kend = 0;
     for (int k = 0; k < m; ++k) {
-      st = arnoldi_step(n, rowptr, colind, val, s, kind, q, V, k, h);
+      st = orth < 0 ? arnoldi_step(n, rowptr, colind, val, s, kind, q, V, k, h)
+                    : arnoldi_step_pipelined(n, rowptr, colind, val, s, kind, q, V, k, orth, h);
       if (st != OR_OK) goto finish;
       for (int j = 0; j <= k; ++j) memcpy(H + ((size_t)j * m + k) * ss, h + (size_t)j * ss, ss * sizeof(double));
       double* gam = h + (size_t)(k + 1) * ss;
@@ -1239,6 +1271,43 @@ finish:
   free(V); free(R); free(H); free(sig); free(Om); free(zeta); free(h);
   if (st != OR_OK) return st;
   return conv ? OR_OK : OR_NOT_CONVERGED;
+}
+
+int or_bgmres(i64 n, const int32_t* rowptr, const int32_t* colind, const double* val, int s, int kind, int q,
+              const double* B, double* X, double tol, int maxit, int restart, int32_t* info, double* relres,
+              double* hist, int hist_cap) {
+  return bgmres_impl(n, rowptr, colind, val, s, kind, q, B, X, tol, maxit, restart, -1, info, relres, hist,
+                     hist_cap);
+}
+
+/* Block GMRes with the pipelined Gram-Schmidt orthogonalisation of window r
+ * (Ch. 9) in every Arnoldi step. */
+int or_bgmres_pipelined(i64 n, const int32_t* rowptr, const int32_t* colind, const double* val, int s, int kind,
+                        int q, const double* B, double* X, double tol, int maxit, int restart, int r,
+                        int32_t* info, double* relres, double* hist, int hist_cap) {
+  if (r < 0) return OR_E_INVALID;
+  return bgmres_impl(n, rowptr, colind, val, s, kind, q, B, X, tol, maxit, restart, r, info, relres, hist,
+                     hist_cap);
+}
+
+/* Block Arnoldi (m steps from V0 = Norm_S(R)) with the pipelined
+ * Gram-Schmidt of window r; V, H, sigma0 as or_block_arnoldi. */
+int or_block_arnoldi_pipelined(i64 n, const int32_t* rowptr, const int32_t* colind, const double* val, int s,
+                               int kind, int q, const double* R, int m, int r, double* V, double* H,
+                               double* sigma0) {
+  if (!valid_subalg(s, kind, q) || s > 64 || r < 0) return OR_E_INVALID;
+  size_t ss = (size_t)s * s;
+  int st = or_normalize(n, s, kind, q, R, V, sigma0);
+  if (st != OR_OK) return st;
+  double* h = (double*)malloc(sizeof(double) * (size_t)(m + 1) * ss);
+  memset(H, 0, sizeof(double) * (size_t)(m + 1) * m * ss);
+  for (int k = 0; k < m; ++k) {
+    st = arnoldi_step_pipelined(n, rowptr, colind, val, s, kind, q, V, k, r, h);
+    if (st != OR_OK) break;
+    for (int j = 0; j <= k + 1; ++j) memcpy(H + ((size_t)j * m + k) * ss, h + (size_t)j * ss, ss * sizeof(double));
+  }
+  free(h);
+  return st;
 }
 
 /* ------------------------------------------------------------------------ */

@@ -116,3 +116,78 @@ def test_gmres_rank_deficient_rhs(orc):
     r = orc.bgmres(A, B, kind="block", tol=1e-11, maxit=500, restart=20)
     assert r["converged"]
     assert np.allclose(r["X"], np.linalg.solve(D, B), atol=1e-9)
+
+
+# ---- pipelined Gram-Schmidt orthogonalisation (Ch. 9, window r) ----------
+# In exact arithmetic every orthogonalisation gives the same Arnoldi basis,
+# so the pipelined variants are pinned by the same independent checks as
+# modified Gram-Schmidt: the residual-minimiser property of the iterates, the
+# Arnoldi relation with an S-orthonormal basis, and implicit = true residual.
+# A misplaced window (an update subtracted twice or not at all, an inner
+# product taken before the wrong update) breaks orthogonality at the first
+# step where it matters and fails the relation checks.
+
+@pytest.mark.parametrize("r", [0, 1, 2, 3, 30])
+@pytest.mark.parametrize("kind,q", SUBALGS)
+def test_pipelined_gmres_iterates_are_residual_minimisers(orc, kind, q, r):
+    A, D, B = small_nonsym()
+    X0 = W.gaussian_block(A.n, 4, 5) * 0.1
+    for k in (1, 2, 3, 5):
+        res = orc.bgmres(A, B, X0, kind=kind, q=q, tol=0.0, maxit=k, restart=10, pipelined=r)
+        assert res["iters"] == k and res["cycles"] == 1
+        Xr = residual_minimiser(D, B, X0, k, kind, q)
+        err = np.linalg.norm(res["X"] - Xr) / np.linalg.norm(Xr)
+        assert err < 1e-9, (k, err)
+
+
+@pytest.mark.parametrize("r", [1, 2, 4, 6])
+@pytest.mark.parametrize("kind,q", SUBALGS)
+def test_pipelined_block_arnoldi_relation(orc, kind, q, r):
+    A, D, B = small_nonsym(N=7)
+    m = 6
+    st, V, H, sig0 = orc.block_arnoldi(A, B, m, kind, q, pipelined=r)
+    assert st == 0
+    assert np.allclose(V[0] @ sig0, B, atol=1e-12)
+    for k in range(m):
+        lhs = D @ V[k]
+        rhs = sum(V[j] @ H[j, k] for j in range(k + 2))
+        assert np.allclose(lhs, rhs, atol=1e-12)
+    for i in range(m + 1):
+        for j in range(m + 1):
+            G = orc.bdot(V[i], V[j], kind, q)
+            assert np.allclose(G, np.eye(4) if i == j else 0.0, atol=1e-10)
+
+
+def test_pipelined_window_zero_is_modified_gram_schmidt(orc):
+    """r = 0: every inner product is taken after all earlier updates, which is
+    modified Gram-Schmidt operation for operation."""
+    A, D, B = small_nonsym(N=8, seed=3)
+    for kind, q in SUBALGS:
+        a = orc.bgmres(A, B, kind=kind, q=q, tol=0.0, maxit=14, restart=6)
+        b = orc.bgmres(A, B, kind=kind, q=q, tol=0.0, maxit=14, restart=6, pipelined=0)
+        assert np.array_equal(a["X"], b["X"])
+
+
+def test_pipelined_full_window_is_classical_gram_schmidt(orc):
+    """r >= k: every inner product is taken with the unmodified block, i.e.
+    classical Gram-Schmidt applied once; the Hessenberg column then equals
+    V^T (A V_k) block by block (checked on the first steps, where the basis
+    is orthonormal to rounding)."""
+    A, D, B = small_nonsym(N=7)
+    m = 4
+    st, V, H, sig0 = orc.block_arnoldi(A, B, m, "block", 1, pipelined=m)
+    assert st == 0
+    for k in range(m):
+        W = D @ V[k]
+        for j in range(k + 1):
+            assert np.allclose(H[j, k], V[j].T @ W, atol=1e-12)
+
+
+def test_pipelined_gmres_converges_with_restarts(orc):
+    A, D, B = small_nonsym(N=10, s=4, seed=6)
+    Xs = np.linalg.solve(D, B)
+    for r in (1, 3, 29):
+        res = orc.bgmres(A, B, tol=1e-10, maxit=2000, restart=30, pipelined=r, hist_cap=2000)
+        assert res["converged"]
+        assert np.linalg.norm(res["X"] - Xs) / np.linalg.norm(Xs) < 1e-7
+        assert np.all(np.diff(res["hist"][:30]) <= 1e-12)
