@@ -157,6 +157,20 @@ int bkry_bdot(bkry_handle h, int64_t n, int32_t p, bkry_subalg S, const double* 
 /* FP32 BDOT with FP32 accumulation inside each workgroup; G in FP64. */
 int bkry_bdot_f32(bkry_handle h, int64_t n, int32_t p, bkry_subalg S, const float* X, const float* Y, double* G);
 
+/* bkry_bdot for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops): the same kernels and the same result,
+ * bit for bit, but the partial Grams, slice sums and reduction counter live
+ * in a fixed 5 MiB scratch array per GPU (held until the process ends)
+ * instead of the handle's workspace, so the call allocates nothing (the
+ * handle must have been created beforehand).  Every call on one GPU shares
+ * that GPU's array: calls that overlap on one GPU (several handles or
+ * streams) race and must be serialised by the caller.  The counter is
+ * cleared by a kernel on each call.  Asynchronous on the handle's stream.
+ * BKRY_E_INVALID if the call would need more scratch than the array holds
+ * (not reachable for p <= 32). */
+int bkry_bdot_noalloc(bkry_handle h, int64_t n, int32_t p, bkry_subalg S, const double* X, const double* Y,
+                      double* G);
+
 /* Normaliser / S-QR decomposition (Definition "normalizer", Ch. 3; TSQR,
  * Ch. 7): X = Q R with <Q,Q>_S = I and R in S upper triangular per S-block,
  * diag(R) >= 0; Q overwrites X, R (p x p) goes to device memory.  Block and

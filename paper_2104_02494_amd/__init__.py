@@ -58,7 +58,7 @@ class bkry_info(ctypes.Structure):
 EXPORTS = ["bkry_create", "bkry_destroy", "bkry_set_stream", "bkry_synchronize", "bkry_last_error",
            "bkry_profile", "bkry_profile_read", "bkry_set_spmm_format", "bkry_spmm",
            "bkry_spmm_f32", "bkry_bdot", "bkry_bdot_f32", "bkry_tsqr", "bkry_cg_solve", "bkry_pcg_solve",
-           "bkry_cg1r_solve", "bkry_color", "bkry_ssor_apply", "bkry_pcg_ssor_solve", "bkry_jacobi_minv", "bkry_bicgstab_solve", "bkry_gmres_solve", "bkry_sddmm", "bkry_csr_transpose"]
+           "bkry_cg1r_solve", "bkry_color", "bkry_ssor_apply", "bkry_pcg_ssor_solve", "bkry_jacobi_minv", "bkry_bicgstab_solve", "bkry_gmres_solve", "bkry_sddmm", "bkry_csr_transpose", "bkry_bdot_noalloc"]
 
 _lib = None
 
@@ -86,6 +86,7 @@ def lib():
             "bkry_spmm_f32": [H, i64, i64, vp, vp, vp, i32, vp, vp],
             "bkry_bdot": [H, i64, i32, bkry_subalg, vp, vp, vp],
             "bkry_bdot_f32": [H, i64, i32, bkry_subalg, vp, vp, vp],
+            "bkry_bdot_noalloc": [H, i64, i32, bkry_subalg, vp, vp, vp],
             "bkry_tsqr": [H, i64, i32, bkry_subalg, vp, vp],
             "bkry_cg_solve": [H, csr_p, i32, bkry_subalg, vp, vp, dbl, i32, dbl, i32, info_p],
             "bkry_pcg_solve": [H, csr_p, i32, bkry_subalg, vp, vp, vp, dbl, i32, dbl, info_p],
@@ -213,6 +214,20 @@ def bkry_bdot(h: Handle, X: torch.Tensor, Y: torch.Tensor, kind="block", q=1) ->
     h._sync_stream()
     fn = lib().bkry_bdot_f32 if f32 else lib().bkry_bdot
     h._check(fn(h.h, X.shape[0], p, _subalg(kind, q), _ptr(X), _ptr(Y), _ptr(G)))
+    return G
+
+
+def bkry_bdot_noalloc(h: Handle, X: torch.Tensor, Y: torch.Tensor, G: torch.Tensor, kind="block", q=1) -> torch.Tensor:
+    """G = <X, Y>_S into the caller's p x p float64 device tensor G, with the
+    library's fixed per-GPU scratch array instead of its workspace (the call
+    allocates no device memory)."""
+    _block(X)
+    _block(Y)
+    p = X.shape[1]
+    if not (G.is_cuda and G.dtype == torch.float64 and G.is_contiguous() and tuple(G.shape) == (p, p)):
+        raise ValueError("G must be a contiguous p x p float64 device tensor")
+    h._sync_stream()
+    h._check(lib().bkry_bdot_noalloc(h.h, X.shape[0], p, _subalg(kind, q), _ptr(X), _ptr(Y), _ptr(G)))
     return G
 
 

@@ -10,6 +10,7 @@
 #include <string.h>
 
 #include <chrono>
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -197,6 +198,35 @@ int bdot_impl(bkry_handle h, int64_t n, int32_t p, bkry_subalg S, const T* X, co
   return BKRY_OK;
 }
 
+// ------------------------------------------------ allocation-free scratch --
+// Device memory of the allocation-free entry points: one fixed array per GPU,
+// held for the life of the process.  Host code never passes `scratch` itself
+// to a kernel (in host code it names a host-side stand-in); it uses the
+// device address resolved once per device by resolve_scratch.
+constexpr size_t kScratchBytes = (size_t)5 << 20;
+static __device__ __align__(256) char scratch[kScratchBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch[kMaxDevices] = {};
+
+// With `device` current: the device address of this GPU's scratch array.
+hipError_t resolve_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch[device]) return hipSuccess;
+  char* ptr = nullptr;
+  hipError_t e = hipGetSymbolAddress(reinterpret_cast<void**>(&ptr), HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  if (!ptr) return hipErrorInvalidSymbol;
+  g_scratch[device] = ptr;
+  return hipSuccess;
+}
+
+char* scratch_of(int device) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return (device >= 0 && device < kMaxDevices) ? g_scratch[device] : nullptr;
+}
+
 }  // namespace
 
 extern "C" {
@@ -215,6 +245,7 @@ int bkry_create(bkry_handle* out, int device, void* stream) {
   if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&h->cnt), kCounterInts * sizeof(uint32_t));
   if (e == hipSuccess) e = hipMemsetAsync(h->cnt, 0, kCounterInts * sizeof(uint32_t), h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e == hipSuccess) e = resolve_scratch(device);
   if (e != hipSuccess) {
     if (h->hflags) (void)hipHostFree(h->hflags);
     if (h->dflags) (void)hipFree(h->dflags);
@@ -374,6 +405,41 @@ int bkry_bdot(bkry_handle h, int64_t n, int32_t p, bkry_subalg S, const double* 
 
 int bkry_bdot_f32(bkry_handle h, int64_t n, int32_t p, bkry_subalg S, const float* X, const float* Y, double* G) {
   return bdot_impl<float>(h, n, p, S, X, Y, G);
+}
+
+int bkry_bdot_noalloc(bkry_handle h, int64_t n, int32_t p, bkry_subalg S, const double* X, const double* Y,
+                      double* G) {
+  int rc = begin(h);
+  Sub sub;
+  if (!rc) rc = check_sub(h, p, S, sub);
+  if (!rc && n < 1) rc = fail(h, BKRY_E_INVALID, "n must be >= 1");
+  if (!rc) rc = check_blocks(h, {X, Y});
+  if (!rc && !G) rc = fail(h, BKRY_E_INVALID, "null G");
+  if (rc) return rc;
+  char* base = scratch_of(h->device);
+  if (!base) return fail(h, BKRY_E_HIP, "bdot_noalloc: the scratch array of this device was not resolved");
+  // the same partials, slice sums and Gram as bkry_bdot, plus one counter
+  // slice, carved from the device's scratch array
+  const int nblk = stream_grid(n, p, sizeof(double));
+  Carver c;
+  c.take<double>((size_t)nblk * p * p);
+  c.take<double>(red_gpart_count(nblk, p));
+  c.take<double>((size_t)p * p);
+  c.take<uint32_t>(kCntStride);
+  if (c.off > kScratchBytes)
+    return fail(h, BKRY_E_INVALID, "bdot_noalloc needs " + std::to_string(c.off) + " bytes of scratch, more than the " +
+                                       std::to_string(kScratchBytes) + " it holds");
+  Carver w{base};
+  double* part = w.take<double>((size_t)nblk * p * p);
+  double* gpart = w.take<double>(red_gpart_count(nblk, p));
+  double* Gf = w.take<double>((size_t)p * p);
+  uint32_t* cnt = w.take<uint32_t>(kCntStride);
+  // the reduction's hand-off counter must start at zero; a fill kernel (not
+  // a memset) keeps the call capturable in a HIP graph
+  API_HIP(launch_fill_u32(cnt, kCntStride, 0u, h->stream), "bdot_noalloc");
+  API_HIP(launch_gram<double>(n, p, X, 1, Y, part, nblk, Red{Gf, gpart, cnt}, nullptr, h->stream), "bdot_noalloc");
+  API_HIP(launch_project(Gf, G, sub, h->stream), "bdot_noalloc");
+  return BKRY_OK;
 }
 
 int bkry_tsqr(bkry_handle h, int64_t n, int32_t p, bkry_subalg S, double* X, double* R) {

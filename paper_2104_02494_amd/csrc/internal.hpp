@@ -236,6 +236,8 @@ hipError_t launch_sddmm(const CsrView& A, int s, double alpha, const T* L, const
 // ----------------------------------------------------- small algebra ----
 // Single-workgroup kernels on the p x p coefficients (FP64).
 hipError_t launch_project(const double* G, double* out, Sub sub, hipStream_t st);
+// p[0, count) = v (a kernel, so that the call can be captured in a graph).
+hipError_t launch_fill_u32(uint32_t* p, int64_t count, uint32_t v, hipStream_t st);
 hipError_t launch_cg_init(CgCtl* ctl, const double* G_R0, const double* G_rho, hipStream_t st);
 hipError_t launch_cg_reortho_fin(CgCtl* ctl, int s, const double* G, hipStream_t st);
 
