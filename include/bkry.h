@@ -287,6 +287,19 @@ int bkry_bicgstab_solve(bkry_handle h, const bkry_csr* A, int32_t p, bkry_subalg
 int bkry_gmres_solve(bkry_handle h, const bkry_csr* A, int32_t p, bkry_subalg S, const double* B, double* X,
                      double tol, int32_t maxit, int32_t restart, bkry_info* info);
 
+/* Restarted block GMRes as bkry_gmres_solve, with the pipelined Gram-Schmidt
+ * orthogonalisation of window r >= 1 (Algorithm "Pipelined Gram-Schmidt
+ * Orthogonalization", Ch. 9) in every Arnoldi step instead of classical
+ * Gram-Schmidt applied twice: the inner product with basis block i is taken
+ * after the updates with blocks 0 .. i - r - 1 (window min(r, k) in step k;
+ * r >= restart - 1 is classical Gram-Schmidt applied once).  Each pass over W
+ * subtracts up to min(r, 4 / 2 / 1 for p <= 8 / 16 / 32) updates and takes
+ * the inner products of as many blocks, so a step moves about half the block
+ * traffic of the default at large r; stability decreases as r grows (the
+ * text's trade-off).  BKRY_E_INVALID for r < 1; otherwise as bkry_gmres_solve. */
+int bkry_gmres_pipelined_solve(bkry_handle h, const bkry_csr* A, int32_t p, bkry_subalg S, const double* B,
+                               double* X, double tol, int32_t maxit, int32_t restart, int32_t r, bkry_info* info);
+
 /* Sampled product on the pattern of A: out_val[k] = alpha * sum_c L[i][c] X[j][c]
  * for the k-th stored entry (i, j).  With L the adjoint solution and
  * alpha = -1 this is the gradient of a loss with respect to the values of A. */

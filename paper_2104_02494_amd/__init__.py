@@ -58,7 +58,7 @@ class bkry_info(ctypes.Structure):
 EXPORTS = ["bkry_create", "bkry_destroy", "bkry_set_stream", "bkry_synchronize", "bkry_last_error",
            "bkry_profile", "bkry_profile_read", "bkry_set_spmm_format", "bkry_spmm",
            "bkry_spmm_f32", "bkry_bdot", "bkry_bdot_f32", "bkry_tsqr", "bkry_cg_solve", "bkry_pcg_solve",
-           "bkry_cg1r_solve", "bkry_color", "bkry_ssor_apply", "bkry_pcg_ssor_solve", "bkry_jacobi_minv", "bkry_bicgstab_solve", "bkry_gmres_solve", "bkry_sddmm", "bkry_csr_transpose", "bkry_bdot_noalloc"]
+           "bkry_cg1r_solve", "bkry_color", "bkry_ssor_apply", "bkry_pcg_ssor_solve", "bkry_jacobi_minv", "bkry_bicgstab_solve", "bkry_gmres_solve", "bkry_sddmm", "bkry_csr_transpose", "bkry_bdot_noalloc", "bkry_gmres_pipelined_solve"]
 
 _lib = None
 
@@ -97,6 +97,7 @@ def lib():
             "bkry_jacobi_minv": [H, csr_p, vp],
             "bkry_bicgstab_solve": [H, csr_p, i32, bkry_subalg, vp, vp, dbl, i32, dbl, info_p],
             "bkry_gmres_solve": [H, csr_p, i32, bkry_subalg, vp, vp, dbl, i32, i32, info_p],
+            "bkry_gmres_pipelined_solve": [H, csr_p, i32, bkry_subalg, vp, vp, dbl, i32, i32, i32, info_p],
             "bkry_sddmm": [H, csr_p, i32, dbl, vp, vp, vp],
             "bkry_csr_transpose": [H, csr_p, vp, vp, vp, vp],
         }
@@ -378,18 +379,32 @@ def bkry_bicgstab_solve(h: Handle, A: CsrMatrix, B: torch.Tensor, X: torch.Tenso
 
 
 def bkry_gmres_solve(h: Handle, A: CsrMatrix, B: torch.Tensor, X: torch.Tensor | None = None, kind="block", q=1,
-                     tol=1e-10, maxit=1000, restart=30, hist_cap=0):
-    """Restarted block GMRes (CGS2 + TSQR Arnoldi).  Returns (X, info)."""
+                     tol=1e-10, maxit=1000, restart=30, hist_cap=0, pipelined=None):
+    """Restarted block GMRes (TSQR Arnoldi with classical Gram-Schmidt applied
+    twice, or with the pipelined Gram-Schmidt of window `pipelined` >= 1
+    through bkry_gmres_pipelined_solve).  Returns (X, info)."""
     _block(B)
     X = torch.zeros_like(B) if X is None else _block(X)
     p = B.shape[1]
     info, hist, rel, trel = _info(p, hist_cap)
     h._sync_stream()
     d = A.desc()
-    rc = lib().bkry_gmres_solve(h.h, ctypes.byref(d), p, _subalg(kind, q), _ptr(B), _ptr(X), float(tol),
-                                int(maxit), int(restart), ctypes.byref(info))
+    if pipelined is None:
+        rc = lib().bkry_gmres_solve(h.h, ctypes.byref(d), p, _subalg(kind, q), _ptr(B), _ptr(X), float(tol),
+                                    int(maxit), int(restart), ctypes.byref(info))
+    else:
+        rc = lib().bkry_gmres_pipelined_solve(h.h, ctypes.byref(d), p, _subalg(kind, q), _ptr(B), _ptr(X),
+                                              float(tol), int(maxit), int(restart), int(pipelined),
+                                              ctypes.byref(info))
     h._check(rc, allow=(OK, NOT_CONVERGED))
     return X, _info_dict(rc, info, hist, rel, trel, p)
+
+
+def bkry_gmres_pipelined_solve(h: Handle, A: CsrMatrix, B: torch.Tensor, r: int, X: torch.Tensor | None = None,
+                               kind="block", q=1, tol=1e-10, maxit=1000, restart=30, hist_cap=0):
+    """Restarted block GMRes with the pipelined Gram-Schmidt of window r >= 1."""
+    return bkry_gmres_solve(h, A, B, X, kind=kind, q=q, tol=tol, maxit=maxit, restart=restart, hist_cap=hist_cap,
+                            pipelined=r)
 
 
 def bkry_sddmm(h: Handle, A: CsrMatrix, L: torch.Tensor, X: torch.Tensor, alpha=-1.0) -> torch.Tensor:

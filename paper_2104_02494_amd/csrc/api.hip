@@ -705,8 +705,11 @@ int bkry_jacobi_minv(bkry_handle h, const bkry_csr* A, double* minv) {
   return BKRY_OK;
 }
 
-int bkry_gmres_solve(bkry_handle h, const bkry_csr* A, int32_t p, bkry_subalg S, const double* B, double* X,
-                     double tol, int32_t maxit, int32_t restart, bkry_info* info) {
+}  // extern "C"
+
+namespace {
+int gmres_impl(bkry_handle h, const bkry_csr* A, int32_t p, bkry_subalg S, const double* B, double* X, double tol,
+               int32_t maxit, int32_t restart, int32_t orth, bkry_info* info) {
   int rc = begin(h);
   Sub sub;
   if (!rc) rc = check_csr(h, A, true);
@@ -743,7 +746,7 @@ int bkry_gmres_solve(bkry_handle h, const bkry_csr* A, int32_t p, bkry_subalg S,
   if (rc) return rc;
   GmResult r;
   if (maxit > 0) {
-    hipError_t e = gm_run(v, sub, B, X, tol, maxit, restart, hist_cap, gb, h->stream, h->hflags, r);
+    hipError_t e = gm_run(v, sub, B, X, tol, maxit, restart, hist_cap, gb, h->stream, h->hflags, r, orth);
     if (e != hipSuccess) return hip_fail(h, e, "gmres_solve");
   } else {
     // no step allowed: only the initial residual norms
@@ -779,6 +782,23 @@ int bkry_gmres_solve(bkry_handle h, const bkry_csr* A, int32_t p, bkry_subalg S,
   rc = status_of(r.status, h);
   if (rc) return rc;
   return r.converged ? BKRY_OK : BKRY_NOT_CONVERGED;
+}
+}  // namespace
+
+extern "C" {
+
+int bkry_gmres_solve(bkry_handle h, const bkry_csr* A, int32_t p, bkry_subalg S, const double* B, double* X,
+                     double tol, int32_t maxit, int32_t restart, bkry_info* info) {
+  return gmres_impl(h, A, p, S, B, X, tol, maxit, restart, 0, info);
+}
+
+int bkry_gmres_pipelined_solve(bkry_handle h, const bkry_csr* A, int32_t p, bkry_subalg S, const double* B,
+                               double* X, double tol, int32_t maxit, int32_t restart, int32_t r, bkry_info* info) {
+  if (h && r < 1) {
+    h->err = "the pipelined Gram-Schmidt window r must be >= 1";
+    return BKRY_E_INVALID;
+  }
+  return gmres_impl(h, A, p, S, B, X, tol, maxit, restart, r, info);
 }
 
 int bkry_bicgstab_solve(bkry_handle h, const bkry_csr* A, int32_t p, bkry_subalg S, const double* B, double* X,

@@ -211,6 +211,14 @@ template <typename T>
 hipError_t launch_rowmul(int64_t n, int s, T* X, const double* C, bool gram, T* partial, int nblk, Red red,
                          const int32_t* gf, hipStream_t st);
 
+// Pipelined Gram-Schmidt pass (see pgs_pass_kernel): updates u0 .. u0+nu-1
+// of W with the basis blocks of V and coefficients C (block u at C + u s^2),
+// Gram partials of V_{g0+j}^T W for j < ng taken before update j.  At most
+// pgs_max_updates(s) updates per pass; nblk as for launch_gram.
+int pgs_max_updates(int s);
+hipError_t launch_pgs_pass(int64_t n, int s, const double* V, double* W, int u0, int nu, const double* C, int g0,
+                           int ng, double* partial, int nblk, const int32_t* done, hipStream_t st);
+
 // Y = X C (+ Y if accumulate) for a list of blocks: Y op= sum_j X_j C_j,
 // X_j = X + j*n*s, C_j s x s FP64 at C + j*s*s; sign = +1 or -1.
 template <typename T>
@@ -309,7 +317,9 @@ hipError_t launch_norm_diag(const double* G, Sub sub, double* d, double* out_N, 
 // TSQR must run instead).  stage 1 factors G = X^T X: R1 and Rinv = R1^-1,
 // or R1 = I and plan[2] = 1; it runs only if the gates gd / gf are open, and
 // otherwise clears the plan.  stage 2 (only if plan[0]) factors G = Y^T Y
-// of Y = X R1^-1: Rinv = R2^-1 and N = R2 R1, or plan[2] = 1.  ratio_min is
+// of Y = X R1^-1: Rinv = R2^-1 and N = R2 R1, or plan[2] = 1; when G is
+// already within 8 s eps of the identity it sets N = R1 and clears plan[1]
+// (Q = Y, no second row product).  ratio_min is
 // the smallest accepted ratio of the diagonal entries of R1 within a group.
 hipError_t launch_cholqr(int stage, const double* G, Sub sub, double* R1, double* Rinv, double* N, int32_t* plan,
                          double ratio_min, const int32_t* gd, const int32_t* gf, hipStream_t st);

@@ -1341,6 +1341,95 @@ hipError_t launch_block_combine(int64_t n, int s, const T* X, int nx, const doub
   });
 }
 
+// ------------------------------------------- pipelined Gram-Schmidt pass --
+// One pass of the pipelined Gram-Schmidt orthogonalisation (Ch. 9): with the
+// window w, the inner product of basis block g = u + w is taken with W as it
+// stands right before the update with basis block u is subtracted.  The pass
+// applies the updates u0 .. u0 + nu - 1 (their coefficients C_u, s x s, are
+// known from earlier passes) row by row, and for the first ng of them
+// accumulates V_{g0 + j}^T W^(u0 + j) (g0 = u0 + w) before update j, so W is
+// read and written once for nu updates and ng inner products:
+//   q = W_row;  for j < nu:  [j < ng] G_{g0+j} += V_{g0+j,row}^T q;  q -= V_{u0+j,row} C_{u0+j}
+// Each update is subtracted on its own, as the listing's loop does.  Gram
+// partials as gram_kernel's (slice j: partial[(j * gridDim.x + blk) s^2]).
+template <int S, int VEC, int NU>
+__global__ __launch_bounds__(kBlock) void pgs_pass_kernel(int64_t n, int s, const double* __restrict__ V,
+                                                           double* __restrict__ W, int u0, int nu,
+                                                           const double* __restrict__ C, int g0, int ng,
+                                                           double* __restrict__ partial, const int32_t* done) {
+  using L = Layout<double, S, VEC>;
+  constexpr int NW = kBlock / kWave;
+  constexpr int RPB = NW * L::RPW;
+  __shared__ double cs[NU * S * S];
+  __shared__ double sh[NW * S * S];
+  if (done && *done) return;
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  const int r = lane / L::LPR, c = lane % L::LPR;
+  const int col0 = c * VEC;
+  const bool active = col0 < s;
+  for (int t = threadIdx.x; t < nu * S * S; t += kBlock) {
+    const int j = t / (S * S), e = t % (S * S), a = e / S, b = e % S;
+    cs[t] = (a < s && b < s) ? C[(int64_t)(u0 + j) * s * s + a * s + b] : 0.0;
+  }
+  __syncthreads();
+  int64_t r0, r1, rstep;
+  stream_rows(n, RPB, r0, r1, rstep);
+  double gacc[NU][VEC][S];
+#pragma unroll
+  for (int j = 0; j < NU; ++j)
+#pragma unroll
+    for (int a = 0; a < VEC; ++a)
+#pragma unroll
+      for (int b = 0; b < S; ++b) gacc[j][a][b] = 0.0;
+  const int64_t blk = n * (int64_t)s;
+  for (int64_t base = r0; base < r1; base += rstep) {
+    const int64_t row = base + wave * L::RPW + r;
+    const bool rv = row < r1 && active;
+    vec_t<double, VEC> q = rv ? load_vec<double, VEC>(W + row * s + col0) : zero_vec<double, VEC>();
+    vec_t<double, VEC> vu[NU], vg[NU];
+#pragma unroll
+    for (int j = 0; j < NU; ++j) {
+      vu[j] = (rv && j < nu) ? load_vec<double, VEC>(V + (u0 + j) * blk + row * s + col0) : zero_vec<double, VEC>();
+      vg[j] = (rv && j < ng) ? load_vec<double, VEC>(V + (g0 + j) * blk + row * s + col0) : zero_vec<double, VEC>();
+    }
+#pragma unroll
+    for (int j = 0; j < NU; ++j) {
+      if (j < ng) gram_row<double, S, VEC>(gacc[j], vg[j], q, lane);
+      if (j < nu) {
+        double d[VEC];
+        row_times<double, S, VEC>(d, vu[j], cs + j * S * S, col0, lane);
+#pragma unroll
+        for (int w = 0; w < VEC; ++w) q.v[w] -= d[w];
+      }
+    }
+    if (rv) store_vec<double, VEC>(W + row * s + col0, q);
+  }
+#pragma unroll
+  for (int j = 0; j < NU; ++j)
+    if (j < ng) gram_store<double, S, VEC>(gacc[j], s, partial, sh, j);
+}
+
+int pgs_max_updates(int s) {
+  int nu = 1;
+  (void)dispatch_s<double>(s, [&](auto S_, auto) -> hipError_t {
+    nu = gram_jb<decltype(S_)::value>();
+    return hipSuccess;
+  });
+  return nu;
+}
+
+hipError_t launch_pgs_pass(int64_t n, int s, const double* V, double* W, int u0, int nu, const double* C, int g0,
+                           int ng, double* partial, int nblk, const int32_t* done, hipStream_t st) {
+  if (nu <= 0 || ng > nu || nu > pgs_max_updates(s)) return hipErrorInvalidValue;
+  return dispatch_s<double>(s, [&](auto S_, auto V_) -> hipError_t {
+    constexpr int S = decltype(S_)::value, VV = decltype(V_)::value;
+    constexpr int NU = gram_jb<S>();
+    hipLaunchKernelGGL((pgs_pass_kernel<S, VV, NU>), dim3(nblk), dim3(kBlock), 0, st, n, s, V, W, u0, nu, C, g0, ng,
+                       partial, done);
+    return hipGetLastError();
+  });
+}
+
 // ----------------------------------------------------------------- SDDMM --
 template <typename T, int S, int VEC>
 __global__ __launch_bounds__(kBlock) void sddmm_kernel(int64_t n, int64_t nnz, const int32_t* __restrict__ rowptr,

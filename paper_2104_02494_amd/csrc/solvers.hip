@@ -753,7 +753,7 @@ GmBufs carve_gm(Carver& c, int64_t n, Sub sub, int m, int hist_cap, uint32_t* cn
 }
 
 hipError_t gm_run(const CsrView& A, Sub sub, const double* B, double* X, double tol, int maxit, int m,
-                  int hist_cap, const GmBufs& b, hipStream_t st, int32_t* hflags, GmResult& res) {
+                  int hist_cap, const GmBufs& b, hipStream_t st, int32_t* hflags, GmResult& res, int orth) {
   const int64_t n = A.n;
   const int s = sub.s;
   const size_t blk = (size_t)n * s;
@@ -771,6 +771,11 @@ hipError_t gm_run(const CsrView& A, Sub sub, const double* B, double* X, double 
   h->hist_cap = hist_cap;
   h->tol = tol;
   BK_TRY(hipMemcpyAsync(c, h, sizeof(GmCtl), hipMemcpyHostToDevice, st));
+  const size_t ss = (size_t)s * s;
+  // the step kernel adds the coefficients of two passes; the pipelined
+  // orthogonalisation has one, so the second stays zero
+  if (orth > 0) BK_TRY(hipMemsetAsync(b.H2, 0, sizeof(double) * (size_t)(m + 1) * ss, st));
+  const int lmax = pgs_max_updates(s);
   for (int cycle = 0;; ++cycle) {
     // R = B - A X into V_0, its Gram; V_0 sigma_0 = Norm_S(R)
     BK_TRY(launch_spmm<double>(A, s, X, b.V, B, 2, b.partial, nblk, red, &c->bad_index, nullptr, st));
@@ -780,12 +785,32 @@ hipError_t gm_run(const CsrView& A, Sub sub, const double* B, double* X, double 
       double* Vk = b.V + (size_t)k * blk;
       double* W = b.V + (size_t)(k + 1) * blk;
       BK_TRY(launch_spmm<double>(A, s, Vk, W, nullptr, 0, nullptr, nblk, red, &c->bad_index, done, st));
-      // classical Gram-Schmidt, twice: H_j = <V_j, W>_S, W -= sum_j V_j H_j
-      double* Hp[2] = {b.H1, b.H2};
-      for (int pass = 0; pass < 2; ++pass) {
-        BK_TRY(launch_gram<double>(n, s, b.V, k + 1, W, b.partial, nblk, red, done, st));
-        BK_TRY(launch_project_batched(b.Gb, Hp[pass], sub, k + 1, done, st));
-        BK_TRY(launch_block_combine<double>(n, s, b.V, k + 1, Hp[pass], -1.0, W, done, st));
+      if (orth > 0) {
+        // pipelined Gram-Schmidt, window w: H_i = <V_i, W>_S for i < w from
+        // W as it comes; then passes of at most min(w, lmax) updates, each
+        // taking the inner products of the blocks w places further on
+        const int w = orth < k ? (orth > 0 ? orth : 1) : (k > 0 ? k : 1);
+        const int L = w < lmax ? w : lmax;
+        BK_TRY(launch_gram<double>(n, s, b.V, w < k + 1 ? w : k + 1, W, b.partial, nblk, red, done, st));
+        BK_TRY(launch_project_batched(b.Gb, b.H1, sub, w < k + 1 ? w : k + 1, done, st));
+        for (int u0 = 0; u0 <= k; u0 += L) {
+          const int nu = (k + 1 - u0) < L ? (k + 1 - u0) : L;
+          const int g0 = u0 + w;
+          const int ng = g0 > k ? 0 : ((k + 1 - g0) < nu ? (k + 1 - g0) : nu);
+          BK_TRY(launch_pgs_pass(n, s, b.V, W, u0, nu, b.H1, g0, ng, b.partial, nblk, done, st));
+          if (ng > 0) {
+            BK_TRY(launch_reduce(s, b.partial, false, nblk, ng, red, done, nullptr, Epi{}, st));
+            BK_TRY(launch_project_batched(b.Gb, b.H1 + (size_t)g0 * ss, sub, ng, done, st));
+          }
+        }
+      } else {
+        // classical Gram-Schmidt, twice: H_j = <V_j, W>_S, W -= sum_j V_j H_j
+        double* Hp[2] = {b.H1, b.H2};
+        for (int pass = 0; pass < 2; ++pass) {
+          BK_TRY(launch_gram<double>(n, s, b.V, k + 1, W, b.partial, nblk, red, done, st));
+          BK_TRY(launch_project_batched(b.Gb, Hp[pass], sub, k + 1, done, st));
+          BK_TRY(launch_block_combine<double>(n, s, b.V, k + 1, Hp[pass], -1.0, W, done, st));
+        }
       }
       BK_TRY(tsqr_run<double>(n, sub, W, b.gam, b.tsqr_ws, b.cnt, done, nullptr, st));
       BK_TRY(launch_gm_step(c, s, k, b.H, b.sig, b.Om, b.H1, b.H2, b.gam, b.hist, st));

@@ -138,8 +138,10 @@ GmBufs carve_gm(Carver& c, int64_t n, Sub sub, int m, int hist_cap, uint32_t* cn
 struct GmResult {
   int status = 0, converged = 0, steps = 0, cycles = 0, bad_index = 0;
 };
+// orth = 0: classical Gram-Schmidt applied twice; orth = r >= 1: the
+// pipelined Gram-Schmidt of window r (Ch. 9).
 hipError_t gm_run(const CsrView& A, Sub sub, const double* B, double* X, double tol, int maxit, int m,
-                  int hist_cap, const GmBufs& b, hipStream_t st, int32_t* hflags, GmResult& res);
+                  int hist_cap, const GmBufs& b, hipStream_t st, int32_t* hflags, GmResult& res, int orth = 0);
 
 // ------------------------------------------------------ block BiCGStab --
 struct BcBufs {

@@ -127,3 +127,54 @@ def test_gmres_full_size_cycle(h):
     implicit = info["hist"][-1]
     true = max(info["true_relres"])
     assert abs(implicit - true) <= 1e-6 * true
+
+
+# ---- pipelined Gram-Schmidt (bkry_gmres_pipelined_solve) against the oracle's
+# pipelined orthogonalisation with the same window ---------------------------
+@pytest.mark.parametrize("r", [1, 2, 3, 30])
+@pytest.mark.parametrize("p", WIDTHS)
+@pytest.mark.parametrize("kind,q", SUBS)
+@pytest.mark.parametrize("steps,restart", [(1, 30), (9, 30), (17, 30), (23, 5)])
+def test_pipelined_gmres_fixed_steps(orc, h, r, p, kind, q, steps, restart):
+    A, B = fixed_problem(p)
+    say("pipelined gmres fixed", r, p, kind, steps, restart)
+    X, info = gpu_gm(h, A, B, kind=kind, q=q, tol=0.0, maxit=steps, restart=restart, pipelined=r)
+    ro = orc.bgmres(A, B, kind=kind, q=q, tol=0.0, maxit=steps, restart=restart, pipelined=r)
+    assert info["iters"] == ro["iters"] == steps
+    assert info["outer_iters"] == ro["cycles"]
+    assert rel(X, ro["X"]) < 1e-10
+
+
+@pytest.mark.parametrize("r", [1, 3, 29])
+@pytest.mark.parametrize("p", [4, 8])
+def test_pipelined_gmres_converges_like_oracle(orc, h, r, p):
+    A = W.convdiff_2d(32)
+    B = W.gaussian_block(A.n, p, 8 + p)
+    say("pipelined gmres solve", r, p)
+    X, info = gpu_gm(h, A, B, tol=1e-10, maxit=3000, restart=30, hist_cap=3000, pipelined=r)
+    ro = orc.bgmres(A, B, tol=1e-10, maxit=3000, restart=30, hist_cap=3000, pipelined=r)
+    assert info["converged"] and ro["converged"]
+    assert abs(info["iters"] - ro["iters"]) <= 1
+    assert max(info["true_relres"]) <= 1e-9
+    k = min(len(info["hist"]), len(ro["hist"])) - 1
+    hg, ho = np.asarray(info["hist"][:k]), np.asarray(ro["hist"][:k])
+    assert np.all(np.abs(hg - ho) <= 1e-6 * ho + 5e-11)
+
+
+def test_pipelined_gmres_rejects_window_zero(h):
+    A = W.convdiff_2d(16)
+    B = W.gaussian_block(A.n, 4, 9)
+    with pytest.raises(P.BkryError):
+        gpu_gm(h, A, B, pipelined=0)
+
+
+def test_pipelined_gmres_full_size_cycle(h):
+    """One GMRes(30) cycle with window 3 on the 1024^2 workload (p = 8): the
+    implicit residual of the last step equals the FP64 true residual."""
+    A, B, _ = W.build_workload("convdiff2d_1024_s8")
+    say("pipelined gmres 1024^2 cycle")
+    X, info = gpu_gm(h, A, B, kind="block", tol=0.0, maxit=30, restart=30, hist_cap=30, pipelined=3)
+    assert info["iters"] == 30 and info["outer_iters"] == 1
+    implicit = info["hist"][-1]
+    true = max(info["true_relres"])
+    assert abs(implicit - true) <= 1e-6 * true
