@@ -68,6 +68,8 @@ def lib():
                                   i32, ptr, i32, dbl]),
             "or_bcg1r": (i32, [i64, ptr, ptr, ptr, i32, i32, i32, ptr, ptr, dbl, i32, dbl, dbl, ptr, ptr, ptr, i32,
                                ptr]),
+            "or_bcg_gropp": (i32, [i64, ptr, ptr, ptr, i32, i32, i32, ptr, ptr, dbl, i32, dbl, dbl, ptr, ptr, ptr, i32,
+                               ptr]),
             "or_lu_solve": (i32, [i32, i32, i32, ptr, ptr, ptr]),
             "or_bbicgstab": (i32, [i64, ptr, ptr, ptr, i32, i32, i32, ptr, ptr, dbl, i32, dbl, dbl, ptr, ptr, ptr,
                                    i32]),
@@ -292,6 +294,28 @@ def bcg1r(A, B, X0=None, kind="block", q=1, tol=1e-10, maxit=1000, eta=0.0, eps=
     if mv is not None and mv.shape != (n,):
         raise ValueError("minv must hold n entries")
     st = lib().or_bcg1r(n, _p(rp), _p(ci), _p(v), s, _kind(kind), q, _p(B), _p(X), tol, maxit, eta, eps,
+                        _p(info), _p(relres), _p(hist) if hist_cap else None, hist_cap, _p(mv))
+    it = int(info[0])
+    return dict(status=st, X=X, iters=it, reorth=int(info[1]), converged=bool(info[2]), relres=relres,
+                hist=hist[:min(it, hist_cap)] if hist_cap else None)
+
+
+def bcg_gropp(A, B, X0=None, kind="block", q=1, tol=1e-10, maxit=1000, eta=0.0, eps=None, hist_cap=0, minv=None):
+    """Gropp's block CG (alg:gropps_block_cg: Q and Z by recurrences),
+    preconditioned by M^-1 = diag(minv) (None: M = I).  Returns dict(status,
+    X, iters, reorth, converged, relres, hist)."""
+    n, rp, ci, v = _csr(A)
+    B = _f64(B)
+    s = B.shape[1]
+    X = np.zeros_like(B) if X0 is None else _f64(X0).copy()
+    info = np.zeros(4, dtype=np.int32)
+    relres = np.zeros(s)
+    hist = np.zeros(max(hist_cap, 1))
+    eps = eps_f64() if eps is None else eps
+    mv = None if minv is None else _f64(minv)
+    if mv is not None and mv.shape != (n,):
+        raise ValueError("minv must hold n entries")
+    st = lib().or_bcg_gropp(n, _p(rp), _p(ci), _p(v), s, _kind(kind), q, _p(B), _p(X), tol, maxit, eta, eps,
                         _p(info), _p(relres), _p(hist) if hist_cap else None, hist_cap, _p(mv))
     it = int(info[0])
     return dict(status=st, X=X, iters=it, reorth=int(info[1]), converged=bool(info[2]), relres=relres,

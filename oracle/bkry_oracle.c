@@ -717,6 +717,125 @@ int or_bcg_ssor(i64 n, const int32_t* rowptr, const int32_t* colind, const doubl
 /* column norms after a re-normalisation, and all norms of the global and    */
 /* block-global subalgebras, as there).                                      */
 /* ------------------------------------------------------------------------ */
+/* ------------------------------------------------------------------------ */
+/* Gropp's block CG (Algorithm "Gropp's BCG", Ch. 8) with a diagonal         */
+/* preconditioner M (minv = diag(M^-1); NULL: M = I).  Besides P, Q = A P    */
+/* and R-bar it carries Z = M^-1 R-bar, V = M^-1 Q and U = A Z, and updates  */
+/* Q = U + Q beta and, unless the residual is re-normalised, Z = Z - V       */
+/* lambda by recurrences instead of forming A P and M^-1 R-bar anew; after a */
+/* re-normalisation Z = M^-1 R-bar is formed directly, as the listing says.  */
+/* The reductions (alpha; rho' and the stopping norms) and the updates are   */
+/* taken in the listing's order; the stopping test and its norms are those   */
+/* of the other block CG forms here (readings as in or_bcg).                 */
+/* ------------------------------------------------------------------------ */
+int or_bcg_gropp(i64 n, const int32_t* rowptr, const int32_t* colind, const double* val, int s, int kind, int q,
+                 const double* B, double* X, double tol, int maxit, double eta, double eps, int32_t* info,
+                 double* relres, double* hist, int hist_cap, const double* minv) {
+  if (!valid_subalg(s, kind, q) || s > 64 || n < group_width(s, kind, q)) return OR_E_INVALID;
+  size_t blk = (size_t)(n * s);
+  double* R = (double*)calloc(blk, sizeof(double));
+  double* P = (double*)calloc(blk, sizeof(double));
+  double* Qb = (double*)calloc(blk, sizeof(double));
+  double* Z = (double*)calloc(blk, sizeof(double));
+  double* V = (double*)calloc(blk, sizeof(double));
+  double* U = (double*)calloc(blk, sizeof(double));
+  double* T = (double*)calloc(blk, sizeof(double));
+  if (!R || !P || !Qb || !Z || !V || !U || !T) {
+    free(R); free(P); free(Qb); free(Z); free(V); free(U); free(T);
+    return OR_E_INVALID;
+  }
+  size_t ss = (size_t)s * s;
+  double sigma[64 * 64], alpha[64 * 64], rho[64 * 64], rho_new[64 * 64], lambda[64 * 64];
+  double gamma[64 * 64], beta[64 * 64], tmp[64 * 64], lamsig[64 * 64];
+  double r0n[64], cn[64], rel[64];
+  int st = OR_OK, iters = 0, nro = 0, conv = 0;
+
+  or_residual(n, rowptr, colind, val, s, B, X, R);
+  column_norms(n, s, R, r0n);
+  for (int i = 0; i < s; ++i) rel[i] = (r0n[i] > 0.0) ? 1.0 : 0.0;
+  {
+    int allzero = 1;
+    for (int i = 0; i < s; ++i) allzero &= (r0n[i] == 0.0);
+    if (allzero) {
+      conv = 1;
+      for (int i = 0; i < s; ++i) rel[i] = 0.0;
+      goto done;
+    }
+  }
+  if (eta > 0.0) {
+    st = or_normalize(n, s, kind, q, R, R, sigma);
+    if (st != OR_OK) goto done;
+    nro++;
+  } else {
+    eye(s, sigma);
+  }
+  apply_minv(n, s, minv, R, P);                       /* P^0 = M^-1 R-bar^0 */
+  or_spmm(n, rowptr, colind, val, s, P, Qb);          /* Q^0 = A P^0 */
+  memcpy(Z, P, blk * sizeof(double));                 /* Z^0 = P^0 */
+  or_bdot(n, s, kind, q, P, R, rho);                  /* rho^0 = <P^0, R-bar^0>_S */
+
+  for (int k = 0; k < maxit; ++k) {
+    or_bdot(n, s, kind, q, P, Qb, alpha);             /* alpha = <P, Q>_S */
+    apply_minv(n, s, minv, Qb, V);                    /* V = M^-1 Q */
+    for (size_t t = 0; t < ss; ++t)
+      if (!isfinite(alpha[t])) { st = OR_E_NONFINITE; goto done; }
+    st = or_chol_solve(s, kind, q, alpha, rho, lambda); /* lambda = alpha^-1 rho */
+    if (st != OR_OK) goto done;
+    block_axmy(n, s, Qb, lambda, R);                  /* R~ = R-bar - Q lambda */
+    mm(s, lambda, sigma, lamsig);                     /* lambda sigma (before sigma changes) */
+    iters = k + 1;
+    int fire = or_reortho_fires(eta, or_kappa_D(s, alpha), eps);
+    if (fire) {
+      st = or_normalize(n, s, kind, q, R, R, gamma);  /* (R-bar, gamma) = Norm_S(R~) */
+      if (st != OR_OK) goto done;
+      nro++;
+      mm(s, gamma, sigma, tmp);                       /* sigma = gamma sigma */
+      memcpy(sigma, tmp, ss * sizeof(double));
+      if (kind != OR_GLOBAL && kind != OR_BGLOBAL) {
+        for (int i = 0; i < s; ++i) {
+          double acc = 0.0;
+          for (int a = 0; a < s; ++a) acc += sigma[a * s + i] * sigma[a * s + i];
+          cn[i] = sqrt(acc);
+        }
+      } else {
+        memset(T, 0, blk * sizeof(double));
+        block_axpy(n, s, R, sigma, T);
+        column_norms(n, s, T, cn);
+      }
+      apply_minv(n, s, minv, R, Z);                   /* Z = M^-1 R-bar */
+    } else {
+      eye(s, gamma);
+      memset(T, 0, blk * sizeof(double));
+      block_axpy(n, s, R, sigma, T);
+      column_norms(n, s, T, cn);
+      block_axmy(n, s, V, lambda, Z);                 /* Z = Z - V lambda */
+    }
+    block_axpy(n, s, P, lamsig, X);                   /* X += P lambda sigma */
+    or_bdot(n, s, kind, q, Z, R, rho_new);            /* rho' = <Z, R-bar>_S */
+    or_spmm(n, rowptr, colind, val, s, Z, U);         /* U = A Z */
+    double m = max_rel(s, cn, r0n, rel);
+    if (hist && k < hist_cap) hist[k] = m;
+    if (isnan(m)) { st = OR_E_NONFINITE; goto done; }
+    if (m <= tol) { conv = 1; break; }
+    mtm(s, gamma, rho_new, tmp);                      /* beta = rho^-1 gamma^T rho' */
+    st = or_chol_solve(s, kind, q, rho, tmp, beta);
+    if (st != OR_OK) goto done;
+    memcpy(T, Z, blk * sizeof(double));               /* P = Z + P beta */
+    block_axpy(n, s, P, beta, T);
+    memcpy(P, T, blk * sizeof(double));
+    memcpy(T, U, blk * sizeof(double));               /* Q = U + Q beta */
+    block_axpy(n, s, Qb, beta, T);
+    memcpy(Qb, T, blk * sizeof(double));
+    memcpy(rho, rho_new, ss * sizeof(double));
+  }
+done:
+  if (info) { info[0] = iters; info[1] = nro; info[2] = conv; }
+  if (relres) for (int i = 0; i < s; ++i) relres[i] = rel[i];
+  free(R); free(P); free(Qb); free(Z); free(V); free(U); free(T);
+  if (st != OR_OK) return st;
+  return conv ? OR_OK : OR_NOT_CONVERGED;
+}
+
 int or_bcg1r(i64 n, const int32_t* rowptr, const int32_t* colind, const double* val, int s, int kind, int q,
              const double* B, double* X, double tol, int maxit, double eta, double eps, int32_t* info,
              double* relres, double* hist, int hist_cap, const double* minv) {
