@@ -73,6 +73,8 @@ def lib():
             "or_lu_solve": (i32, [i32, i32, i32, ptr, ptr, ptr]),
             "or_bbicgstab": (i32, [i64, ptr, ptr, ptr, i32, i32, i32, ptr, ptr, dbl, i32, dbl, dbl, ptr, ptr, ptr,
                                    i32]),
+            "or_bbicgstab_restarted": (i32, [i64, ptr, ptr, ptr, i32, i32, i32, ptr, ptr, dbl, i32, dbl, dbl, i32,
+                                             ptr, ptr, ptr, i32]),
             "or_block_arnoldi": (i32, [i64, ptr, ptr, ptr, i32, i32, i32, ptr, i32, ptr, ptr, ptr]),
             "or_bgmres": (i32, [i64, ptr, ptr, ptr, i32, i32, i32, ptr, ptr, dbl, i32, i32, ptr, ptr, ptr, i32]),
             "or_bgmres_pipelined": (i32, [i64, ptr, ptr, ptr, i32, i32, i32, ptr, ptr, dbl, i32, i32, i32, ptr, ptr,
@@ -329,9 +331,12 @@ def lu_solve(A, B, kind, q=1):
     return st, X
 
 
-def bbicgstab(A, B, X0=None, kind="block", q=1, tol=1e-10, maxit=1000, eta=0.0, eps=None, hist_cap=0):
-    """Block BiCGStab with adaptive residual re-orthonormalisation (M = I).
-    Returns dict(status, X, iters, reorth, converged, relres, hist)."""
+def bbicgstab(A, B, X0=None, kind="block", q=1, tol=1e-10, maxit=1000, eta=0.0, eps=None, hist_cap=0,
+              max_restarts=None):
+    """Block BiCGStab with adaptive residual re-orthonormalisation (M = I);
+    with max_restarts (an int >= 0) restarted on the true residual until it
+    meets tol.  Returns dict(status, X, iters, reorth, converged, relres,
+    hist, restarts)."""
     n, rp, ci, v = _csr(A)
     B = _f64(B)
     s = B.shape[1]
@@ -340,11 +345,16 @@ def bbicgstab(A, B, X0=None, kind="block", q=1, tol=1e-10, maxit=1000, eta=0.0, 
     relres = np.zeros(s)
     hist = np.zeros(max(hist_cap, 1))
     eps = eps_f64() if eps is None else eps
-    st = lib().or_bbicgstab(n, _p(rp), _p(ci), _p(v), s, _kind(kind), q, _p(B), _p(X), tol, maxit, eta, eps,
-                            _p(info), _p(relres), _p(hist) if hist_cap else None, hist_cap)
+    if max_restarts is None:
+        st = lib().or_bbicgstab(n, _p(rp), _p(ci), _p(v), s, _kind(kind), q, _p(B), _p(X), tol, maxit, eta, eps,
+                                _p(info), _p(relres), _p(hist) if hist_cap else None, hist_cap)
+    else:
+        st = lib().or_bbicgstab_restarted(n, _p(rp), _p(ci), _p(v), s, _kind(kind), q, _p(B), _p(X), tol, maxit,
+                                          eta, eps, int(max_restarts), _p(info), _p(relres),
+                                          _p(hist) if hist_cap else None, hist_cap)
     it = int(info[0])
     return dict(status=st, X=X, iters=it, reorth=int(info[1]), converged=bool(info[2]), relres=relres,
-                hist=hist[:min(it, hist_cap)] if hist_cap else None)
+                hist=hist[:min(it, hist_cap)] if hist_cap else None, restarts=int(info[3]))
 
 
 def block_arnoldi(A, R, m, kind="block", q=1, pipelined=None):

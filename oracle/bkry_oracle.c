@@ -1013,9 +1013,12 @@ int or_lu_solve(int s, int kind, int q, const double* A, const double* B, double
 /* info[0] = iterations, info[1] = normalisations (the initial one included),*/
 /* info[2] = converged.                                                      */
 /* ------------------------------------------------------------------------ */
-int or_bbicgstab(i64 n, const int32_t* rowptr, const int32_t* colind, const double* val, int s, int kind, int q,
-                 const double* B, double* X, double tol, int maxit, double eta, double eps, int32_t* info,
-                 double* relres, double* hist, int hist_cap) {
+/* r0n_fixed (NULL: the column norms of B - A X0): the denominators of the
+ * stopping test, kept from an earlier run when the iteration is restarted. */
+static int bbicgstab_impl(i64 n, const int32_t* rowptr, const int32_t* colind, const double* val, int s, int kind,
+                          int q, const double* B, double* X, double tol, int maxit, double eta, double eps,
+                          int32_t* info, double* relres, double* hist, int hist_cap, const double* r0n_fixed,
+                          double* r0n_out) {
   if (!valid_subalg(s, kind, q) || s > 64 || n < group_width(s, kind, q)) return OR_E_INVALID;
   size_t blk = (size_t)(n * s), ss = (size_t)s * s;
   double* R = (double*)calloc(blk, sizeof(double));
@@ -1036,10 +1039,14 @@ int or_bbicgstab(i64 n, const int32_t* rowptr, const int32_t* colind, const doub
 
   or_residual(n, rowptr, colind, val, s, B, X, R);
   column_norms(n, s, R, r0n);
-  for (int i = 0; i < s; ++i) rel[i] = (r0n[i] > 0.0) ? 1.0 : 0.0;
   {
     int allzero = 1;
     for (int i = 0; i < s; ++i) allzero &= (r0n[i] == 0.0);
+    if (r0n_fixed)
+      for (int i = 0; i < s; ++i) r0n[i] = r0n_fixed[i];
+    if (r0n_out)
+      for (int i = 0; i < s; ++i) r0n_out[i] = r0n[i];
+    for (int i = 0; i < s; ++i) rel[i] = (r0n[i] > 0.0) ? 1.0 : 0.0;
     if (allzero) {
       conv = 1;
       for (int i = 0; i < s; ++i) rel[i] = 0.0;
@@ -1114,6 +1121,54 @@ done:
   if (relres) for (int i = 0; i < s; ++i) relres[i] = rel[i];
   free(R); free(P); free(Rt); free(Q); free(S); free(T); free(U); free(W);
   if (st != OR_OK) return st;
+  return conv ? OR_OK : OR_NOT_CONVERGED;
+}
+
+int or_bbicgstab(i64 n, const int32_t* rowptr, const int32_t* colind, const double* val, int s, int kind, int q,
+                 const double* B, double* X, double tol, int maxit, double eta, double eps, int32_t* info,
+                 double* relres, double* hist, int hist_cap) {
+  return bbicgstab_impl(n, rowptr, colind, val, s, kind, q, B, X, tol, maxit, eta, eps, info, relres, hist,
+                        hist_cap, NULL, NULL);
+}
+
+/* Block BiCGStab restarted on the true residual (a reading beyond the
+ * listing, which stops on the recursive residual R^ sigma): when the
+ * recursion meets tol but the true residual B - A X does not (the residual
+ * gap of BiCGStab), the iteration starts again from the current X (new
+ * residual, normalised, and new shadow residual), with the stopping test's
+ * denominators kept from the first start; at most max_restarts times, the
+ * iterations of all runs counting against maxit.  info[3] = restarts;
+ * converged only if the true residual meets tol. */
+int or_bbicgstab_restarted(i64 n, const int32_t* rowptr, const int32_t* colind, const double* val, int s,
+                           int kind, int q, const double* B, double* X, double tol, int maxit, double eta,
+                           double eps, int max_restarts, int32_t* info, double* relres, double* hist,
+                           int hist_cap) {
+  if (!valid_subalg(s, kind, q) || s > 64 || n < group_width(s, kind, q) || max_restarts < 0) return OR_E_INVALID;
+  double r0n[64], cn[64], rel[64];
+  double* R = (double*)malloc(sizeof(double) * (size_t)(n * s));
+  if (!R) return OR_E_INVALID;
+  int32_t sub[4];
+  int total = 0, nro = 0, restarts = 0, conv = 0, st = OR_OK;
+  for (;;) {
+    const int used = total;
+    st = bbicgstab_impl(n, rowptr, colind, val, s, kind, q, B, X, tol, maxit - used, eta, eps, sub, rel,
+                        hist ? hist + (used < hist_cap ? used : hist_cap) : NULL,
+                        hist_cap > used ? hist_cap - used : 0, restarts ? r0n : NULL, restarts ? NULL : r0n);
+    total += sub[0];
+    nro += sub[1];
+    if (st != OR_OK && st != OR_NOT_CONVERGED) break;
+    if (!sub[2]) break;                                 /* stopped at maxit */
+    or_residual(n, rowptr, colind, val, s, B, X, R);    /* true residual */
+    column_norms(n, s, R, cn);
+    double m = max_rel(s, cn, r0n, rel);
+    if (m <= tol) { conv = 1; break; }
+    if (restarts == max_restarts || total >= maxit) break;
+    restarts++;
+  }
+  if (info) { info[0] = total; info[1] = nro; info[2] = conv; info[3] = restarts; }
+  if (relres) for (int i = 0; i < s; ++i) relres[i] = rel[i];
+  free(R);
+  if (st != OR_OK && st != OR_NOT_CONVERGED) return st;
   return conv ? OR_OK : OR_NOT_CONVERGED;
 }
 

@@ -97,3 +97,44 @@ def test_edge_cases(orc):
     assert r["converged"]
     r0 = orc.bbicgstab(A, Bd, tol=1e-10, maxit=500, eta=0.0)
     assert r0["status"] != 0
+
+
+# ---- restart on the true residual (reading beyond the listing) -----------
+def test_restarted_bicgstab_closes_the_residual_gap(orc):
+    """On the 128^2 convection-diffusion problem the plain iteration stops at
+    1e-10 on its recursive residual with a true residual near 2.5e-8; the
+    restarted one continues from that iterate until the true residual,
+    recomputed here with numpy, meets 1e-10."""
+    A = W.convdiff_2d(128)
+    B = W.gaussian_block(A.n, 8, 1004)
+    M = sp.csr_matrix((A.val, A.colind, A.rowptr), shape=(A.n, A.n))
+    plain = orc.bbicgstab(A, B, tol=1e-10, maxit=5000, eta=1e4)
+    true_plain = np.linalg.norm(B - M @ plain["X"], axis=0) / np.linalg.norm(B, axis=0)
+    assert plain["converged"] and true_plain.max() > 1e-10
+    r = orc.bbicgstab(A, B, tol=1e-10, maxit=5000, eta=1e4, max_restarts=10)
+    true_r = np.linalg.norm(B - M @ r["X"], axis=0) / np.linalg.norm(B, axis=0)
+    assert r["converged"] and r["restarts"] >= 1
+    assert true_r.max() <= 1e-10
+    assert np.allclose(r["relres"], true_r, rtol=1e-6, atol=1e-16)
+    assert r["iters"] > plain["iters"]
+
+
+def test_restarted_bicgstab_without_restarts_is_the_plain_iteration(orc):
+    A = W.convdiff_2d(24)
+    B = W.gaussian_block(A.n, 4, 9)
+    for kind, q in SUBALGS:
+        a = orc.bbicgstab(A, B, kind=kind, q=q, tol=0.0, maxit=12, eta=1e4)
+        b = orc.bbicgstab(A, B, kind=kind, q=q, tol=0.0, maxit=12, eta=1e4, max_restarts=3)
+        assert np.array_equal(a["X"], b["X"]) and b["restarts"] == 0 and b["iters"] == 12
+        c = orc.bbicgstab(A, B, kind=kind, q=q, tol=1e-10, maxit=1000, eta=1e4, max_restarts=0)
+        d = orc.bbicgstab(A, B, kind=kind, q=q, tol=1e-10, maxit=1000, eta=1e4)
+        assert np.array_equal(c["X"], d["X"]) and c["iters"] == d["iters"]
+        true_c = np.linalg.norm(B - A.to_dense() @ c["X"], axis=0) / np.linalg.norm(B, axis=0)
+        assert c["converged"] == bool(true_c.max() <= 1e-10)
+
+
+def test_restarted_bicgstab_respects_the_iteration_budget(orc):
+    A = W.convdiff_2d(64)
+    B = W.gaussian_block(A.n, 4, 11)
+    r = orc.bbicgstab(A, B, tol=1e-14, maxit=150, eta=1e4, max_restarts=50)
+    assert r["iters"] <= 150 and not r["converged"]
