@@ -56,11 +56,19 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+SPMM_END_MARK = b"// ------------------------------------------------------------------ Gram --"
+
+
 def kernel_hash():
-    """Hash of the sources of the roofline kernel (the SpMM and its helpers)."""
+    """Hash of the sources of the roofline kernel: kernels_block.hip up to the
+    end of its SpMM section (the SpMM kernels, their launchers and the
+    helpers above them) and common.hpp."""
     h = hashlib.sha256()
     for f in KERNEL_SRCS:
-        h.update(open(f, "rb").read())
+        data = open(f, "rb").read()
+        if f.endswith("kernels_block.hip"):
+            data = data[:data.index(SPMM_END_MARK)]
+        h.update(data)
     return h.hexdigest()[:16]
 
 
@@ -248,6 +256,15 @@ def extras(P, W, h, dev, A, Ad, Bd, args):
     ms, _ = timed(lambda: P.bkry_spmm(h, Ad, Bd, Y), 20)
     ex["spmm_plain_GBps"] = round(spmm_bytes(A, s) / (ms * 1e-3) / 1e9, 1)
     del Y
+    # attainable HBM bandwidth: a plain device copy of 1 GiB
+    try:
+        xa = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+        ya = torch.empty_like(xa)
+        ms, _ = timed(lambda: ya.copy_(xa), 10)
+        ex["hbm_copy_GBps"] = round(2 * xa.numel() * 8 / (ms * 1e-3) / 1e9, 1)
+        del xa, ya
+    except Exception as e:
+        ex["hbm_copy_GBps"] = dict(error=str(e))
     # standalone TSQR 4,194,304 x 32
     try:
         Xt = torch.as_tensor(W.tsqr_input()).to(dev)
@@ -297,6 +314,17 @@ def extras(P, W, h, dev, A, Ad, Bd, args):
         del X1
     except Exception as e:
         ex["cg1r_laplace3d_128_s8"] = dict(error=str(e))
+    # Gropp's block CG (Q and Z by recurrences) on the same 128^3 workload
+    try:
+        P.bkry_gropp_solve(h, Ad, Bd, kind="block", tol=1e-10, maxit=args.maxit, eta=1e4)
+        Xg, ig = P.bkry_gropp_solve(h, Ad, Bd, kind="block", tol=1e-10, maxit=args.maxit, eta=1e4)
+        ex["gropp_laplace3d_128_s8"] = dict(iters=ig["iters"], reorth=ig["reorth"], seconds=round(ig["seconds"], 4),
+                                            iters_per_s=round(ig["iters"] / ig["seconds"], 1),
+                                            converged=ig["converged"], true_relres_max=max(ig["true_relres"]))
+        log("gropp", ex["gropp_laplace3d_128_s8"])
+        del Xg
+    except Exception as e:
+        ex["gropp_laplace3d_128_s8"] = dict(error=str(e))
     # block GMRes(30): one cycle on the convection-diffusion workload
     try:
         Ac, Bc, _ = W.build_workload("convdiff2d_1024_s8")
@@ -307,8 +335,17 @@ def extras(P, W, h, dev, A, Ad, Bd, args):
         Xg, gt = P.bkry_gmres_solve(h, Acd, Bcd, kind="block", tol=1e-10, maxit=6000, restart=30)
         ex["gmres30_convdiff1024"] = dict(cycle_ms=round(gi["seconds"] * 1e3, 2), solve_s=round(gt["seconds"], 3),
                                           steps=gt["iters"], cycles=gt["outer_iters"], converged=gt["converged"],
-                                          true_relres_max=max(gt["true_relres"]))
+                                          true_relres_max=max(gt["true_relres"]), orthogonalisation="CGS2")
         log("gmres", ex["gmres30_convdiff1024"])
+        # the same with the pipelined Gram-Schmidt of the thesis's experiment (window 3)
+        P.bkry_gmres_solve(h, Acd, Bcd, kind="block", tol=0.0, maxit=30, restart=30, pipelined=3)
+        Xg, pi = P.bkry_gmres_solve(h, Acd, Bcd, kind="block", tol=0.0, maxit=30, restart=30, pipelined=3)
+        Xg, pt = P.bkry_gmres_solve(h, Acd, Bcd, kind="block", tol=1e-10, maxit=6000, restart=30, pipelined=3)
+        ex["gmres30_pipelined3_convdiff1024"] = dict(
+            cycle_ms=round(pi["seconds"] * 1e3, 2), solve_s=round(pt["seconds"], 3), steps=pt["iters"],
+            cycles=pt["outer_iters"], converged=pt["converged"], true_relres_max=max(pt["true_relres"]),
+            orthogonalisation="pipelined Gram-Schmidt, window 3")
+        log("gmres pipelined", ex["gmres30_pipelined3_convdiff1024"])
         del Acd, Bcd, Xg
     except Exception as e:
         ex["gmres30_convdiff1024"] = dict(error=str(e))
@@ -322,8 +359,8 @@ def extras(P, W, h, dev, A, Ad, Bd, args):
         Xb, bt = P.bkry_bicgstab_solve(h, Acd, Bcd, tol=1e-10, maxit=20000, eta=1e4)
         ex["bicgstab_convdiff1024"] = dict(ms_per_iter=round(bi["seconds"] / 100 * 1e3, 3),
                                            solve_s=round(bt["seconds"], 3), iters=bt["iters"],
-                                           reorth=bt["reorth"], converged=bt["converged"],
-                                           true_relres_max=max(bt["true_relres"]))
+                                           reorth=bt["reorth"], restarts=bt["outer_iters"],
+                                           converged=bt["converged"], true_relres_max=max(bt["true_relres"]))
         log("bicgstab", ex["bicgstab_convdiff1024"])
         del Acd, Bcd, Xb
     except Exception as e:
@@ -336,11 +373,16 @@ def extras(P, W, h, dev, A, Ad, Bd, args):
         X64, i64 = P.bkry_cg_solve(h, A3d, B3d, kind="block", tol=1e-10, maxit=20000, eta=1e4)
         X32, i32 = P.bkry_cg_solve(h, A3d, B3d, kind="block", tol=1e-10, maxit=20000, eta=1.0, prec=P.F32_IR)
         err = float(torch.linalg.norm(X32 - X64) / torch.linalg.norm(X64))
+        # the oracle takes minutes per iteration here: the reference of this
+        # error is the FP64 solve on the same GPU (the oracle comparison runs in
+        # the GPU tests on a 32^3 instance of the same generator)
         ex["ir_diffusion27_96_s16"] = dict(fp64_s=round(i64["seconds"], 3), fp64_iters=i64["iters"],
                                            ir_s=round(i32["seconds"], 3), ir_inner_iters=i32["iters"],
                                            ir_outer=i32["outer_iters"], ir_converged=i32["converged"],
                                            ir_true_relres_max=max(i32["true_relres"]),
-                                           rel_err_vs_fp64=err)
+                                           fp64_true_relres_max=max(i64["true_relres"]),
+                                           speedup_vs_fp64=round(i64["seconds"] / i32["seconds"], 3),
+                                           rel_err_vs_gpu_fp64_solve=err)
         log("ir", ex["ir_diffusion27_96_s16"])
         del A3d, B3d, X64, X32
     except Exception as e:
@@ -354,6 +396,20 @@ def extras(P, W, h, dev, A, Ad, Bd, args):
         P.bkry_pcg_solve(h, A5d, B5d, minv, tol=1e-10, maxit=5000, eta=1e4)
         Xp, ip = P.bkry_pcg_solve(h, A5d, B5d, minv, tol=1e-10, maxit=5000, eta=1e4)
         Xn, i0 = P.bkry_cg_solve(h, A5d, B5d, tol=1e-10, maxit=5000, eta=1e4)
+        # the unpreconditioned forward solve of the differentiable workload,
+        # with the per-iteration split of its kernels
+        P.bkry_profile(h, True)
+        for k in range(4):
+            P.bkry_profile_read(h, k, reset=True)
+        Xn, i0p = P.bkry_cg_solve(h, A5d, B5d, tol=1e-10, maxit=5000, eta=1e4)
+        kt = {nm: P.bkry_profile_read(h, k) for nm, k in (("spmm", P.PROF_CG_SPMM), ("update", P.PROF_CG_UPDATE),
+                                                             ("pupdate", P.PROF_CG_PUPDATE))}
+        P.bkry_profile(h, False)
+        ex["cg_diffusion7var_64_s32"] = dict(
+            iters=i0["iters"], seconds=round(i0["seconds"], 4),
+            us_per_iter=round(i0["seconds"] / i0["iters"] * 1e6, 1),
+            kernel_us={nm: round(ms / max(cnt, 1) * 1e3, 2) for nm, (ms, cnt) in kt.items()})
+        log("cg s=32", ex["cg_diffusion7var_64_s32"])
         ex["pcg_jacobi_diffusion7var_64_s32"] = dict(
             iters=ip["iters"], reorth=ip["reorth"], seconds=round(ip["seconds"], 4),
             iters_per_s=round(ip["iters"] / ip["seconds"], 1), converged=ip["converged"],

@@ -254,6 +254,18 @@ int bkry_pcg_ssor_solve(bkry_handle h, const bkry_csr* A, int32_t p, bkry_subalg
 int bkry_cg1r_solve(bkry_handle h, const bkry_csr* A, int32_t p, bkry_subalg S, const double* B, double* X,
                     double tol, int32_t maxit, double eta, bkry_info* info);
 
+/* Gropp's block CG (Algorithm "Gropp's BCG", Ch. 8): the iteration of
+ * bkry_pcg_solve (minv [device, n doubles, 8-byte aligned] = diag(M^-1) of a
+ * diagonal SPD preconditioner) or, with minv = NULL, of bkry_cg_solve, with
+ * Q = A P carried by the recurrence Q = U + Q beta (U = A Z) and Z = M^-1
+ * R-bar by Z = Z - M^-1 Q lambda (Z = M^-1 R-bar formed anew after a
+ * re-normalisation), so that U = A Z no longer waits for the reduction of
+ * rho' (the overlap the method is built for).  Needs one (M = I) or two more
+ * n x p blocks of workspace than bkry_cg_solve.  FP64; arguments, stopping
+ * test, re-normalisation rule and info as bkry_cg_solve. */
+int bkry_gropp_solve(bkry_handle h, const bkry_csr* A, int32_t p, bkry_subalg S, const double* B, double* X,
+                     const double* minv, double tol, int32_t maxit, double eta, bkry_info* info);
+
 /* Jacobi preconditioner of bkry_pcg_solve: minv[i] = 1 / A_ii [device, n
  * doubles, caller-owned].  BKRY_E_INVALID if a row has no diagonal entry or
  * its diagonal is not positive and finite (duplicates are summed).
@@ -269,10 +281,13 @@ int bkry_jacobi_minv(bkry_handle h, const bkry_csr* A, double* minv);
  * when eta * kappa_D(<R_k, R_k>_S) * sqrt(eps) > 1 (eta = 0 never,
  * INFINITY always).  Stops when max_i |R_i| / |R0_i| <= tol (recursive
  * residual R^ sigma) or after maxit iterations; info->true_relres holds the
- * FP64 true residual.  info->converged (and BKRY_OK) requires the FP64 true
- * residual to meet tol too: when the recursion's residual drifts from the
- * true one the call returns BKRY_NOT_CONVERGED with X as reached.  A zero
- * pivot or <U, U>_F = 0 is BKRY_E_BREAKDOWN.
+ * FP64 true residual.  When the recursion meets tol but the FP64 true
+ * residual does not (BiCGStab's residual gap), the iteration is restarted
+ * from the current X with a new normalised and shadow residual and the first
+ * start's stopping denominators, at most 10 times within maxit iterations in
+ * all (info->outer_iters = restarts); info->converged (and BKRY_OK) means
+ * the FP64 true residual meets tol.  A zero pivot or <U, U>_F = 0 is
+ * BKRY_E_BREAKDOWN.
  * FP64; X holds X0 on entry; info [host] may be NULL. */
 int bkry_bicgstab_solve(bkry_handle h, const bkry_csr* A, int32_t p, bkry_subalg S, const double* B, double* X,
                         double tol, int32_t maxit, double eta, bkry_info* info);

@@ -58,7 +58,7 @@ class bkry_info(ctypes.Structure):
 EXPORTS = ["bkry_create", "bkry_destroy", "bkry_set_stream", "bkry_synchronize", "bkry_last_error",
            "bkry_profile", "bkry_profile_read", "bkry_set_spmm_format", "bkry_spmm",
            "bkry_spmm_f32", "bkry_bdot", "bkry_bdot_f32", "bkry_tsqr", "bkry_cg_solve", "bkry_pcg_solve",
-           "bkry_cg1r_solve", "bkry_color", "bkry_ssor_apply", "bkry_pcg_ssor_solve", "bkry_jacobi_minv", "bkry_bicgstab_solve", "bkry_gmres_solve", "bkry_sddmm", "bkry_csr_transpose", "bkry_bdot_noalloc", "bkry_gmres_pipelined_solve"]
+           "bkry_cg1r_solve", "bkry_color", "bkry_ssor_apply", "bkry_pcg_ssor_solve", "bkry_jacobi_minv", "bkry_bicgstab_solve", "bkry_gmres_solve", "bkry_sddmm", "bkry_csr_transpose", "bkry_bdot_noalloc", "bkry_gmres_pipelined_solve", "bkry_gropp_solve"]
 
 _lib = None
 
@@ -91,6 +91,7 @@ def lib():
             "bkry_cg_solve": [H, csr_p, i32, bkry_subalg, vp, vp, dbl, i32, dbl, i32, info_p],
             "bkry_pcg_solve": [H, csr_p, i32, bkry_subalg, vp, vp, vp, dbl, i32, dbl, info_p],
             "bkry_cg1r_solve": [H, csr_p, i32, bkry_subalg, vp, vp, dbl, i32, dbl, info_p],
+            "bkry_gropp_solve": [H, csr_p, i32, bkry_subalg, vp, vp, vp, dbl, i32, dbl, info_p],
             "bkry_color": [H, csr_p, vp, vp, ctypes.POINTER(i32)],
             "bkry_ssor_apply": [H, csr_p, i32, vp, dbl, vp, vp],
             "bkry_pcg_ssor_solve": [H, csr_p, i32, bkry_subalg, vp, vp, vp, dbl, dbl, i32, dbl, info_p],
@@ -287,6 +288,25 @@ def bkry_pcg_solve(h: Handle, A: CsrMatrix, B: torch.Tensor, minv: torch.Tensor,
                    kind="block", q=1, tol=1e-10, maxit=1000, eta=1e4, hist_cap=0):
     """Block CG with the diagonal preconditioner M^-1 = diag(minv) (FP64).  Returns (X, info)."""
     return bkry_cg_solve(h, A, B, X, kind=kind, q=q, tol=tol, maxit=maxit, eta=eta, hist_cap=hist_cap, minv=minv)
+
+
+def bkry_gropp_solve(h: Handle, A: CsrMatrix, B: torch.Tensor, X: torch.Tensor | None = None, minv=None,
+                     kind="block", q=1, tol=1e-10, maxit=1000, eta=1e4, hist_cap=0):
+    """Gropp's block CG (Q and Z by recurrences), FP64, with the diagonal
+    preconditioner M^-1 = diag(minv) or M = I (minv None).  Returns (X, info)."""
+    _block(B)
+    X = torch.zeros_like(B) if X is None else _block(X)
+    if minv is not None and not (minv.is_cuda and minv.dtype == torch.float64 and minv.is_contiguous()
+                                 and minv.numel() == A.n):
+        raise ValueError("minv must be a contiguous FP64 device vector of n entries")
+    p = B.shape[1]
+    info, hist, rel, trel = _info(p, hist_cap)
+    h._sync_stream()
+    d = A.desc()
+    rc = lib().bkry_gropp_solve(h.h, ctypes.byref(d), p, _subalg(kind, q), _ptr(B), _ptr(X), _ptr(minv), float(tol),
+                                int(maxit), float(eta), ctypes.byref(info))
+    h._check(rc, allow=(OK, NOT_CONVERGED))
+    return X, _info_dict(rc, info, hist, rel, trel, p)
 
 
 def bkry_cg1r_solve(h: Handle, A: CsrMatrix, B: torch.Tensor, X: torch.Tensor | None = None, kind="block", q=1,

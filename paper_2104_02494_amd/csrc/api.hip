@@ -467,7 +467,8 @@ int ssor_fail(bkry_handle h, int err) {
 
 int cg_solve_impl(bkry_handle h, const bkry_csr* A, int32_t p, bkry_subalg S, const double* B, double* X,
                   double tol, int32_t maxit, double eta, int32_t prec, const double* minv, bkry_info* info,
-                  bool one_reduction = false, const int32_t* ssor_colors = nullptr, double omega = 1.0) {
+                  bool one_reduction = false, const int32_t* ssor_colors = nullptr, double omega = 1.0,
+                  bool gropp = false) {
   int rc = begin(h);
   Sub sub;
   if (!rc) rc = check_csr(h, A, true);
@@ -499,6 +500,10 @@ int cg_solve_impl(bkry_handle h, const bkry_csr* A, int32_t p, bkry_subalg S, co
     c.take<int32_t>(ne);
     c.take<double>(ne);
     if (ssor_colors) ssor_carve(c, n);
+    if (gropp) {
+      c.take<double>((size_t)n * p);
+      if (minv) c.take<double>((size_t)n * p);
+    }
     rc = ensure_ws(h, c.off);
     if (rc) return rc;
     Carver w{h->ws};
@@ -510,6 +515,8 @@ int cg_solve_impl(bkry_handle h, const bkry_csr* A, int32_t p, bkry_subalg S, co
     double* eval = w.take<double>(ne);
     SsorWs sw;
     if (ssor_colors) sw = ssor_carve(w, n);
+    double* gU = gropp ? w.take<double>((size_t)n * p) : nullptr;
+    double* gZ = (gropp && minv) ? w.take<double>((size_t)n * p) : nullptr;
     CsrView v = view(A);
     rc = ell_build<double, double>(h, A, A->val, W, ecol, eval, v);
     if (rc) return rc;
@@ -520,8 +527,10 @@ int cg_solve_impl(bkry_handle h, const bkry_csr* A, int32_t p, bkry_subalg S, co
       if (err) return ssor_fail(h, err);
     }
     CgResult r;
-    hipError_t e = ssor_colors ? pcg_ssor_run(v, sub, B, X, tol, maxit, eta, hist_cap, cb, plan, h->stream,
-                                              h->hflags, r, h->prof)
+    hipError_t e = gropp ? gropp_run(v, sub, B, X, tol, maxit, eta, hist_cap, cb, gU, gZ, h->stream, h->hflags, r,
+                                     h->prof, minv)
+                   : ssor_colors ? pcg_ssor_run(v, sub, B, X, tol, maxit, eta, hist_cap, cb, plan, h->stream,
+                                                h->hflags, r, h->prof)
                    : one_reduction
                        ? cg1r_run(v, sub, B, X, tol, maxit, eta, hist_cap, cb, h->stream, h->hflags, r, h->prof)
                        : cg_run<double>(v, sub, B, X, tol, maxit, eta, DBL_EPSILON, hist_cap, cb, h->stream,
@@ -684,6 +693,14 @@ int bkry_ssor_apply(bkry_handle h, const bkry_csr* A, int32_t p, const int32_t* 
   return BKRY_OK;
 }
 
+int bkry_gropp_solve(bkry_handle h, const bkry_csr* A, int32_t p, bkry_subalg S, const double* B, double* X,
+                     const double* minv, double tol, int32_t maxit, double eta, bkry_info* info) {
+  if (!h) return BKRY_E_INVALID;
+  if (minv && (reinterpret_cast<uintptr_t>(minv) & 7) != 0)
+    return fail(h, BKRY_E_INVALID, "minv must be 8-byte aligned");
+  return cg_solve_impl(h, A, p, S, B, X, tol, maxit, eta, BKRY_F64, minv, info, false, nullptr, 1.0, true);
+}
+
 int bkry_pcg_solve(bkry_handle h, const bkry_csr* A, int32_t p, bkry_subalg S, const double* B, double* X,
                    const double* minv, double tol, int32_t maxit, double eta, bkry_info* info) {
   if (!h) return BKRY_E_INVALID;
@@ -828,6 +845,7 @@ int bkry_bicgstab_solve(bkry_handle h, const bkry_csr* A, int32_t p, bkry_subalg
   c.take<int32_t>(4);
   c.take<int32_t>(ne);
   c.take<double>(ne);
+  c.take<double>(kMaxS);
   rc = ensure_ws(h, c.off);
   if (rc) return rc;
   Carver w{h->ws};
@@ -837,34 +855,58 @@ int bkry_bicgstab_solve(bkry_handle h, const bkry_csr* A, int32_t p, bkry_subalg
   int32_t* tfl = w.take<int32_t>(4);
   int32_t* ecol = w.take<int32_t>(ne);
   double* eval = w.take<double>(ne);
+  double* r0save = w.take<double>(kMaxS);
   CsrView v = view(A);
   rc = ell_build<double, double>(h, A, A->val, W, ecol, eval, v);
   if (rc) return rc;
+  // The recursion's residual can drift from the true one (BiCGStab's residual
+  // gap).  When the recursion meets tol but the FP64 true residual does not,
+  // the iteration is restarted from the current X (new normalised residual
+  // and shadow residual, the first start's stopping denominators), at most
+  // kBcRestarts times within maxit; converged means the true residual meets
+  // tol.
+  constexpr int kBcRestarts = 10;
   BcResult r;
-  hipError_t e = bc_run(v, sub, B, X, tol, maxit, eta, hist_cap, bb, h->stream, h->hflags, r);
-  if (e != hipSuccess) return hip_fail(h, e, "bicgstab_solve");
   double relres[kMaxS], trel[kMaxS];
+  int total = 0, nre = 0, restarts = 0;
+  for (;;) {
+    const int used = total;
+    BcBufs bbr = bb;
+    bbr.hist = bb.hist + (used < hist_cap ? used : hist_cap);
+    const int cap_r = hist_cap > used ? hist_cap - used : 0;
+    hipError_t e = bc_run(v, sub, B, X, tol, maxit - used, eta, cap_r, bbr, h->stream, h->hflags, r,
+                          restarts ? r0save : nullptr);
+    if (e != hipSuccess) return hip_fail(h, e, "bicgstab_solve");
+    total += r.iters;
+    nre += r.nreorth;
+    if (!restarts)
+      API_HIP(hipMemcpyAsync(r0save, bb.ctl->r0n, sizeof(double) * p, hipMemcpyDeviceToDevice, h->stream), "bicgstab");
+    API_HIP(hipMemcpyAsync(relres, bb.ctl->relres, sizeof(double) * p, hipMemcpyDeviceToHost, h->stream),
+            "bicgstab");
+    API_HIP(true_relres(v, p, B, X, bb.W3, bb.partial, bb.gpart, h->cnt, bb.G, bb.ctl->r0n, trr, tfl, tsc,
+                        h->stream),
+            "bicgstab");
+    API_HIP(hipMemcpyAsync(trel, trr, sizeof(double) * p, hipMemcpyDeviceToHost, h->stream), "bicgstab");
+    API_HIP(hipStreamSynchronize(h->stream), "bicgstab");
+    if (r.bad_index || r.status || !r.converged || tol == 0.0) break;
+    double tmax = 0.0;
+    for (int i = 0; i < p; ++i) tmax = trel[i] > tmax ? trel[i] : tmax;
+    if (tmax <= tol) break;
+    r.converged = 0;
+    if (restarts == kBcRestarts || total >= maxit) break;
+    ++restarts;
+  }
+  r.iters = total;
+  r.nreorth = nre;
   const int hist_len = r.iters < hist_cap ? r.iters : hist_cap;
-  API_HIP(hipMemcpyAsync(relres, bb.ctl->relres, sizeof(double) * p, hipMemcpyDeviceToHost, h->stream), "bicgstab");
   if (hist_len > 0)
     API_HIP(hipMemcpyAsync(info->hist, bb.hist, sizeof(double) * hist_len, hipMemcpyDeviceToHost, h->stream),
             "bicgstab");
-  API_HIP(true_relres(v, p, B, X, bb.W3, bb.partial, bb.gpart, h->cnt, bb.G, bb.ctl->r0n, trr, tfl, tsc, h->stream),
-          "bicgstab");
-  API_HIP(hipMemcpyAsync(trel, trr, sizeof(double) * p, hipMemcpyDeviceToHost, h->stream), "bicgstab");
   API_HIP(hipStreamSynchronize(h->stream), "bicgstab");
-  // The recursion's residual can drift from the true one (BiCGStab's residual
-  // gap): the solve counts as converged only if the FP64 true residual meets
-  // tol as well.
-  if (r.converged && tol > 0.0) {
-    double tmax = 0.0;
-    for (int i = 0; i < p; ++i) tmax = trel[i] > tmax ? trel[i] : tmax;
-    if (!(tmax <= tol)) r.converged = 0;
-  }
   if (info) {
     info->iters = r.iters;
     info->reorth = r.nreorth;
-    info->outer_iters = 0;
+    info->outer_iters = restarts;
     info->converged = r.converged;
     info->hist_len = hist_len;
     info->seconds = now_s() - t0;

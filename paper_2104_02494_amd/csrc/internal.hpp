@@ -177,6 +177,22 @@ hipError_t launch_gram(int64_t n, int s, const T* X, int nx, const T* Y, T* part
 // 8 < s <= 32; kernels_mfma.hip); same partial layout as the vector kernels
 // (one s x s partial per workgroup, nblk workgroups).
 bool mfma_width(int s);
+// Gropp's block CG (FP64): the residual pass with the Z recurrence and the
+// Grams R~^T R~, Z^T R~ (stride 2 s^2), and the direction pass (X update as
+// the block CG direction update, P_{k+1} = Z + P_k beta into Pn, Q = U + Q
+// beta, Gram partials of P_{k+1}^T Q_{k+1}).  Partials only: the caller
+// reduces them.
+hipError_t launch_gropp_update(int64_t n, int s, double* R, const double* Q, double* Z, const CgCtl* ctl,
+                               double* partial, int nblk, const double* minv, hipStream_t st);
+hipError_t launch_gropp_dir(int64_t n, int s, double* X, const double* P, double* Pn, const double* Z,
+                            const double* U, double* Q, const CgCtl* ctl, double* partial, int nblk, hipStream_t st);
+// Widths whose CG streaming steps (residual and direction updates, the
+// SpMM's alpha Gram) run on the matrix cores in FP64.
+inline bool wide_mfma(int s) { return s > 16 && s <= 32; }
+hipError_t launch_cg_update_mfma(int64_t n, int s, double* R, const double* Q, const CgCtl* ctl, double* partial,
+                                 int nblk, const double* minv, int64_t pstride, hipStream_t st);
+hipError_t launch_cg_pupdate_mfma(int64_t n, int s, double* X, const double* P, double* Pn, const double* R,
+                                  const CgCtl* ctl, int nblk, const double* minv, hipStream_t st);
 hipError_t launch_gram_mfma(int64_t n, int s, const double* X, const double* Y, double* partial, int nblk,
                             const int32_t* done, const int32_t* fire, hipStream_t st);
 hipError_t launch_rowmul_mfma(int64_t n, int s, double* X, const double* C, bool gram, double* partial, int nblk,

@@ -556,6 +556,17 @@ template <typename T>
 hipError_t launch_spmm(const CsrView& A, int s, const T* X, T* Y, const T* B, int mode, T* partial, int nblk,
                        Red red, int32_t* bad, const int32_t* done, hipStream_t st, Epi epi, hipEvent_t ev_after,
                        int gram_slot, int ngram) {
+  if constexpr (sizeof(T) == 8) {
+    // wide blocks: the plain product, then X^T Y on the matrix cores (the
+    // fused Gram's s x s per row is the larger cost at these widths)
+    if (mode == 1 && ngram <= 1 && gram_slot == 0 && wide_mfma(s)) {
+      hipError_t e = launch_spmm<T>(A, s, X, Y, B, 0, nullptr, nblk, red, bad, done, st, Epi{}, nullptr, 0, 1);
+      if (e == hipSuccess) e = launch_gram_mfma(A.n, s, X, Y, partial, nblk, done, nullptr, st);
+      if (e == hipSuccess && ev_after) e = hipEventRecord(ev_after, st);
+      if (e != hipSuccess) return e;
+      return launch_reduce(s, partial, false, nblk, 1, red, done, nullptr, epi, st);
+    }
+  }
   T* const pbase = partial;
   const int64_t pstride = ngram > 1 ? (int64_t)ngram * s * s : 0;
   partial += (int64_t)gram_slot * s * s;
@@ -795,16 +806,26 @@ template <typename T>
 hipError_t launch_cg_update(int64_t n, int s, T* R, const T* Q, const CgCtl* ctl, T* partial, int nblk, Red red,
                             hipStream_t st, Epi epi, hipEvent_t ev_after, const double* minv) {
   if (minv && (sizeof(T) != 8 || epi.kind != EPI_CG_RHO_M)) return hipErrorInvalidValue;
-  hipError_t e = dispatch_s<T>(s, [&](auto S_, auto V_) -> hipError_t {
-    constexpr int S = decltype(S_)::value, V = decltype(V_)::value;
-    if (minv)
-      hipLaunchKernelGGL((cg_update_kernel<T, S, V, true>), dim3(nblk), dim3(kBlock), 0, st, n, s, R, Q, ctl,
-                         partial, minv, (int64_t)0);
+  hipError_t e;
+  if constexpr (sizeof(T) == 8) {
+    if (wide_mfma(s))
+      e = launch_cg_update_mfma(n, s, R, Q, ctl, partial, nblk, minv, 0, st);
     else
-      hipLaunchKernelGGL((cg_update_kernel<T, S, V, false>), dim3(nblk), dim3(kBlock), 0, st, n, s, R, Q, ctl,
-                         partial, minv, (int64_t)0);
-    return hipGetLastError();
-  });
+      e = hipErrorNotSupported;
+  } else {
+    e = hipErrorNotSupported;
+  }
+  if (e == hipErrorNotSupported)
+    e = dispatch_s<T>(s, [&](auto S_, auto V_) -> hipError_t {
+      constexpr int S = decltype(S_)::value, V = decltype(V_)::value;
+      if (minv)
+        hipLaunchKernelGGL((cg_update_kernel<T, S, V, true>), dim3(nblk), dim3(kBlock), 0, st, n, s, R, Q, ctl,
+                           partial, minv, (int64_t)0);
+      else
+        hipLaunchKernelGGL((cg_update_kernel<T, S, V, false>), dim3(nblk), dim3(kBlock), 0, st, n, s, R, Q, ctl,
+                           partial, minv, (int64_t)0);
+      return hipGetLastError();
+    });
   if (e == hipSuccess && ev_after) e = hipEventRecord(ev_after, st);
   if (e != hipSuccess) return e;
   return launch_reduce(s, partial, sizeof(T) == 4, nblk, 1, red, &ctl->gate, nullptr, epi, st);
@@ -812,6 +833,7 @@ hipError_t launch_cg_update(int64_t n, int s, T* R, const T* Q, const CgCtl* ctl
 
 hipError_t launch_cg_update_partials(int64_t n, int s, double* R, const double* Q, const CgCtl* ctl, double* partial,
                                      int nblk, int64_t pstride, hipStream_t st) {
+  if (wide_mfma(s)) return launch_cg_update_mfma(n, s, R, Q, ctl, partial, nblk, nullptr, pstride, st);
   return dispatch_s<double>(s, [&](auto S_, auto V_) -> hipError_t {
     constexpr int S = decltype(S_)::value, V = decltype(V_)::value;
     hipLaunchKernelGGL((cg_update_kernel<double, S, V, false>), dim3(nblk), dim3(kBlock), 0, st, n, s, R, Q, ctl,
@@ -951,6 +973,9 @@ hipError_t launch_cg_pupdate(int64_t n, int s, T* X, const T* P, T* Pn, const T*
                              hipStream_t st, const double* minv) {
   if (minv && sizeof(T) != 8) return hipErrorInvalidValue;
   int nblk = stream_grid_wide(n, s, sizeof(T));
+  if constexpr (sizeof(T) == 8) {
+    if (wide_mfma(s)) return launch_cg_pupdate_mfma(n, s, X, P, Pn, R, ctl, nblk, minv, st);
+  }
   return dispatch_s<T>(s, [&](auto S_, auto V_) -> hipError_t {
     constexpr int S = decltype(S_)::value, V = decltype(V_)::value;
     if (minv)
@@ -959,6 +984,169 @@ hipError_t launch_cg_pupdate(int64_t n, int s, T* X, const T* P, T* Pn, const T*
     else
       hipLaunchKernelGGL((cg_pupdate_kernel<T, S, V, false>), dim3(nblk), dim3(kBlock), 0, st, n, s, X, P, Pn, R,
                          ctl, minv);
+    return hipGetLastError();
+  });
+}
+
+// ------------------------------------------------------------ Gropp BCG --
+// Residual pass of Gropp's block CG with a diagonal preconditioner: R~ = R -
+// Q lambda and Z = Z - V lambda with V = M^-1 Q formed row by row (the
+// recurrence that replaces Z = M^-1 R~), both in place, with the Gram
+// partials of R~^T R~ (stopping norms) and Z^T R~ (rho') side by side at
+// stride 2 s^2, the layout the preconditioned rho reduction reads.
+template <int S, int VEC>
+__global__ __launch_bounds__(kBlock) void gropp_update_kernel(int64_t n, int s, double* __restrict__ R,
+                                                               const double* __restrict__ Q, double* __restrict__ Z,
+                                                               const CgCtl* ctl, double* __restrict__ partial,
+                                                               const double* __restrict__ minv) {
+  using T = double;
+  using L = Layout<T, S, VEC>;
+  constexpr int NW = kBlock / kWave;
+  constexpr int RPB = NW * L::RPW;
+  __shared__ T lam[S * S];
+  __shared__ T sh[NW * S * S];
+  if (ctl->gate) return;
+  load_coeff<T, S>(lam, ctl->lam, s);
+  __syncthreads();
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  const int r = lane / L::LPR, c = lane % L::LPR;
+  const int col0 = c * VEC;
+  const bool active = col0 < s;
+  int64_t r0, r1, rstep;
+  stream_rows(n, RPB, r0, r1, rstep);
+  T gacc[VEC][S], gacc2[VEC][S];
+#pragma unroll
+  for (int a = 0; a < VEC; ++a)
+#pragma unroll
+    for (int b = 0; b < S; ++b) gacc[a][b] = gacc2[a][b] = T(0);
+  for (int64_t base = r0; base < r1; base += rstep) {
+    const int64_t row = base + wave * L::RPW + r;
+    const bool rv = row < r1 && active;
+    const vec_t<T, VEC> q = rv ? load_vec<T, VEC>(Q + row * s + col0) : zero_vec<T, VEC>();
+    const vec_t<T, VEC> rr = rv ? load_vec<T, VEC>(R + row * s + col0) : zero_vec<T, VEC>();
+    vec_t<T, VEC> z = rv ? load_vec<T, VEC>(Z + row * s + col0) : zero_vec<T, VEC>();
+    const T m = rv ? minv[row] : T(0);
+    vec_t<T, VEC> v;
+#pragma unroll
+    for (int w = 0; w < VEC; ++w) v.v[w] = m * q.v[w];
+    T ql[VEC], vl[VEC];
+    row_times<T, S, VEC>(ql, q, lam, col0, lane);
+    row_times<T, S, VEC>(vl, v, lam, col0, lane);
+    vec_t<T, VEC> out;
+#pragma unroll
+    for (int w = 0; w < VEC; ++w) {
+      out.v[w] = rr.v[w] - ql[w];
+      z.v[w] = z.v[w] - vl[w];
+    }
+    if (rv) {
+      store_vec<T, VEC>(R + row * s + col0, out);
+      store_vec<T, VEC>(Z + row * s + col0, z);
+    }
+    gram_row<T, S, VEC>(gacc, out, out, lane);
+    gram_row<T, S, VEC>(gacc2, z, out, lane);
+  }
+  gram_store<T, S, VEC>(gacc, s, partial, sh, 0, 2 * (int64_t)s * s);
+  gram_store<T, S, VEC>(gacc2, s, partial + (int64_t)s * s, sh, 0, 2 * (int64_t)s * s);
+}
+
+hipError_t launch_gropp_update(int64_t n, int s, double* R, const double* Q, double* Z, const CgCtl* ctl,
+                               double* partial, int nblk, const double* minv, hipStream_t st) {
+  return dispatch_s<double>(s, [&](auto S_, auto V_) -> hipError_t {
+    constexpr int S = decltype(S_)::value, V = decltype(V_)::value;
+    hipLaunchKernelGGL((gropp_update_kernel<S, V>), dim3(nblk), dim3(kBlock), 0, st, n, s, R, Q, Z, ctl, partial,
+                       minv);
+    return hipGetLastError();
+  });
+}
+
+// Direction pass of Gropp's block CG: the X update of cg_pupdate_kernel
+// (deferred by one iteration, same gating), P_{k+1} = Z + P_k beta into Pn
+// (which holds P_{k-1}), Q = U + Q beta in place, and the Gram partials of
+// P_{k+1}^T Q_{k+1} (the next alpha).
+template <int S, int VEC>
+__global__ __launch_bounds__(kBlock) void gropp_dir_kernel(int64_t n, int s, double* __restrict__ X,
+                                                            const double* __restrict__ P, double* __restrict__ Pn,
+                                                            const double* __restrict__ Z,
+                                                            const double* __restrict__ U, double* __restrict__ Q,
+                                                            const CgCtl* ctl, double* __restrict__ partial) {
+  using T = double;
+  using L = Layout<T, S, VEC>;
+  constexpr int NW = kBlock / kWave;
+  constexpr int RPB = NW * L::RPW;
+  __shared__ T ls[S * S], lp[S * S], bt[S * S];
+  __shared__ T sh[NW * S * S];
+  if (ctl->suspended) return;
+  const bool done = ctl->done != 0;
+  const bool xk = ctl->x_pending != 0;
+  const bool xin = ctl->xdef_in != 0;
+  if (!xk && !xin) return;
+  const bool flush = done || xin;
+  const bool addk = xk && flush;
+  const bool pdir = xk && !done;
+  if (addk) load_coeff<T, S>(ls, ctl->lamsig, s);
+  if (xin) load_coeff<T, S>(lp, ctl->lamsig_prev, s);
+  if (pdir) load_coeff<T, S>(bt, ctl->beta, s);
+  __syncthreads();
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  const int r = lane / L::LPR, c = lane % L::LPR;
+  const int col0 = c * VEC;
+  const bool active = col0 < s;
+  int64_t r0, r1, rstep;
+  stream_rows(n, RPB, r0, r1, rstep);
+  T gacc[VEC][S];
+#pragma unroll
+  for (int a = 0; a < VEC; ++a)
+#pragma unroll
+    for (int b = 0; b < S; ++b) gacc[a][b] = T(0);
+  for (int64_t base = r0; base < r1; base += rstep) {
+    const int64_t row = base + wave * L::RPW + r;
+    const bool rv = row < r1 && active;
+    const vec_t<T, VEC> p = rv ? load_vec<T, VEC>(P + row * s + col0) : zero_vec<T, VEC>();
+    if (flush) {
+      vec_t<T, VEC> x = rv ? load_vec<T, VEC>(X + row * s + col0) : zero_vec<T, VEC>();
+      if (xin) {
+        const vec_t<T, VEC> pp = rv ? load_vec<T, VEC>(Pn + row * s + col0) : zero_vec<T, VEC>();
+        T dx[VEC];
+        row_times<T, S, VEC>(dx, pp, lp, col0, lane);
+#pragma unroll
+        for (int w = 0; w < VEC; ++w) x.v[w] += dx[w];
+      }
+      if (addk) {
+        T dx[VEC];
+        row_times<T, S, VEC>(dx, p, ls, col0, lane);
+#pragma unroll
+        for (int w = 0; w < VEC; ++w) x.v[w] += dx[w];
+      }
+      if (rv) store_vec<T, VEC>(X + row * s + col0, x);
+    }
+    if (pdir) {
+      vec_t<T, VEC> pn = rv ? load_vec<T, VEC>(Z + row * s + col0) : zero_vec<T, VEC>();
+      vec_t<T, VEC> qn = rv ? load_vec<T, VEC>(U + row * s + col0) : zero_vec<T, VEC>();
+      const vec_t<T, VEC> q = rv ? load_vec<T, VEC>(Q + row * s + col0) : zero_vec<T, VEC>();
+      T pb[VEC], qb[VEC];
+      row_times<T, S, VEC>(pb, p, bt, col0, lane);
+      row_times<T, S, VEC>(qb, q, bt, col0, lane);
+#pragma unroll
+      for (int w = 0; w < VEC; ++w) {
+        pn.v[w] += pb[w];
+        qn.v[w] += qb[w];
+      }
+      if (rv) {
+        store_vec<T, VEC>(Pn + row * s + col0, pn);
+        store_vec<T, VEC>(Q + row * s + col0, qn);
+      }
+      gram_row<T, S, VEC>(gacc, pn, qn, lane);
+    }
+  }
+  if (pdir) gram_store<T, S, VEC>(gacc, s, partial, sh);
+}
+
+hipError_t launch_gropp_dir(int64_t n, int s, double* X, const double* P, double* Pn, const double* Z,
+                            const double* U, double* Q, const CgCtl* ctl, double* partial, int nblk, hipStream_t st) {
+  return dispatch_s<double>(s, [&](auto S_, auto V_) -> hipError_t {
+    constexpr int S = decltype(S_)::value, V = decltype(V_)::value;
+    hipLaunchKernelGGL((gropp_dir_kernel<S, V>), dim3(nblk), dim3(kBlock), 0, st, n, s, X, P, Pn, Z, U, Q, ctl,
+                       partial);
     return hipGetLastError();
   });
 }

@@ -19,6 +19,7 @@
 // Cholesky solves run on the projected (S-structured) matrices; since the
 // entries outside the subalgebra's blocks are exact zeros, the factorisation
 // of the whole p x p matrix equals one factorisation per S-block.
+#include <float.h>
 #include <math.h>
 
 #include "common.hpp"
@@ -39,17 +40,40 @@ static hipError_t dispatch_sm(int s, F&& f) {
 
 __device__ __forceinline__ int tid() { return threadIdx.x; }
 
+// Value of v in the lane given by the DPP control CTRL (within rows of 16).
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 // Reductions over the workgroup's single wavefront (every lane receives the
-// result; fixed butterfly order).
+// same result, in a fixed order): inside each row of 16 lanes by DPP
+// exchanges (neighbours, pairs, mirrored halves, mirrored rows; each step
+// adds two equal partial sums, so all lanes of a row agree), then the four
+// row results read from lanes 0, 16, 32, 48 and combined in row order.  All
+// 64 lanes must execute it.
 __device__ __forceinline__ double wsum(double v) {
-#pragma unroll
-  for (int d = 1; d < kWave; d <<= 1) v += __shfl_xor(v, d);
-  return v;
+  v += dpp_f64<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+  v += dpp_f64<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+  v += dpp_f64<0x141>(v);  // row_half_mirror
+  v += dpp_f64<0x140>(v);  // row_mirror
+  return ((readlane_f64(v, 0) + readlane_f64(v, 16)) + readlane_f64(v, 32)) + readlane_f64(v, 48);
 }
 __device__ __forceinline__ double wmax(double v) {
-#pragma unroll
-  for (int d = 1; d < kWave; d <<= 1) v = fmax(v, __shfl_xor(v, d));
-  return v;
+  v = fmax(v, dpp_f64<0xB1>(v));
+  v = fmax(v, dpp_f64<0x4E>(v));
+  v = fmax(v, dpp_f64<0x141>(v));
+  v = fmax(v, dpp_f64<0x140>(v));
+  return fmax(fmax(readlane_f64(v, 0), readlane_f64(v, 16)), fmax(readlane_f64(v, 32), readlane_f64(v, 48)));
 }
 __device__ __forceinline__ bool wany(bool b) { return __any(b ? 1 : 0) != 0; }
 
@@ -106,9 +130,39 @@ __device__ __forceinline__ void sm_project(double* M, const Sub& sub, double* sc
   __syncthreads();
 }
 
-// C = A B (transA: C = A^T B); C must not alias A or B.
+// C = A B (transA: C = A^T B); C must not alias A or B.  Above 16 columns
+// each lane forms a 4 x 4 tile of C (8 x 8 tiles cover 32 x 32), so each
+// loaded entry of A and B serves four products; the same fused products in
+// the same (k ascending) order as the entry-per-lane form below.  Reads past
+// s stay inside the kMaxS^2 arrays and only feed entries that are not stored.
 __device__ __forceinline__ void sm_mm(double* C, const double* A, const double* B, int s, bool transA) {
   __syncthreads();
+  if (s > 16) {
+    const int t = tid(), i0 = (t / 8) * 4, j0 = (t % 8) * 4;
+    double acc[4][4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[r][c] = 0.0;
+    for (int k = 0; k < s; ++k) {
+      double a[4], b[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) a[r] = transA ? A[k * s + i0 + r] : A[(i0 + r) * s + k];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) b[c] = B[k * s + j0 + c];
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[r][c] = fma(a[r], b[c], acc[r][c]);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+        if (i0 + r < s && j0 + c < s) C[(i0 + r) * s + j0 + c] = acc[r][c];
+    __syncthreads();
+    return;
+  }
   for (int t = tid(); t < s * s; t += kSB) {
     const int i = t / s, j = t % s;
     double acc = 0.0;
@@ -332,8 +386,15 @@ __device__ __forceinline__ bool rf_cholesky_solve_x(const double* A, const doubl
   return true;
 }
 template <int SM>
+__device__ __forceinline__ bool lc_cholesky_solve(const double* A, const double* B, double* X, double* Linv, int s);
+template <int SM>
 __device__ __forceinline__ bool rf_cholesky_solve(const double* A, const double* B, double* X, double* Linv, int s) {
-  return s == SM ? rf_cholesky_solve_x<SM, true>(A, B, X, Linv, s) : rf_cholesky_solve_x<SM, false>(A, B, X, Linv, s);
+  if constexpr (SM >= 16) {
+    return lc_cholesky_solve<SM>(A, B, X, Linv, s);
+  } else {
+    return s == SM ? rf_cholesky_solve_x<SM, true>(A, B, X, Linv, s)
+                   : rf_cholesky_solve_x<SM, false>(A, B, X, Linv, s);
+  }
 }
 
 // A = L L^T with L and L^-1 stored (LDS, zero above the diagonal).
@@ -360,16 +421,219 @@ __device__ __forceinline__ bool rf_cholesky_factor_x(const double* A, double* Lo
   return true;
 }
 template <int SM>
+__device__ __forceinline__ bool lc_cholesky_factor(const double* A, double* Lo, double* Linv, int s);
+template <int SM>
 __device__ __forceinline__ bool rf_cholesky_factor(const double* A, double* Lo, double* Linv, int s) {
-  return s == SM ? rf_cholesky_factor_x<SM, true>(A, Lo, Linv, s) : rf_cholesky_factor_x<SM, false>(A, Lo, Linv, s);
+  if constexpr (SM >= 16) {
+    return lc_cholesky_factor<SM>(A, Lo, Linv, s);
+  } else {
+    return s == SM ? rf_cholesky_factor_x<SM, true>(A, Lo, Linv, s)
+                   : rf_cholesky_factor_x<SM, false>(A, Lo, Linv, s);
+  }
 }
 
 // Whether sa A + sh I (A symmetric s x s, LDS) is positive definite, by
 // attempting its Cholesky factorisation (uniform result).
 template <int SM>
+__device__ __forceinline__ bool lc_definite(const double* A, int s, double sa, double sh);
+template <int SM>
 __device__ __forceinline__ bool rf_definite(const double* A, int s, double sa, double sh) {
-  double l[SM], rinv[SM];
-  return s == SM ? rf_factor<SM, true>(A, s, l, rinv, sa, sh) : rf_factor<SM, false>(A, s, l, rinv, sa, sh);
+  if constexpr (SM >= 16) {
+    return lc_definite<SM>(A, s, sa, sh);
+  } else {
+    double l[SM], rinv[SM];
+    return s == SM ? rf_factor<SM, true>(A, s, l, rinv, sa, sh) : rf_factor<SM, false>(A, s, l, rinv, sa, sh);
+  }
+}
+
+// ------------------------------------------ LDS-broadcast Cholesky (wide) --
+// For widths 16 and 32 the register form above unrolls into tens of
+// thousands of instructions (each entry of L reaches the other lanes by two
+// lane reads, one step after the other), and the coefficient steps then
+// stream their code through the instruction cache on every call.  The forms
+// below keep the step loop rolled, so the few hundred instructions of one
+// step are fetched once and run SM times, and exchange through LDS with
+// broadcast loads (every lane reads the same address):
+//   factor   lane j holds column j; the owner of column k publishes it, every
+//            lane then reads the pivot and the column of L (scaled once);
+//   forward  lane (h, i) holds row i of the right-hand sides, columns
+//            [h CW, h CW + CW); the owner of row k finalises and publishes it;
+//   backward the same, from the last row up.
+// Every register index is a compile-time constant.  The matrices are padded
+// to SM with the identity ([A 0; 0 I] = [L 0; 0 I][L 0; 0 I]^T exactly), so
+// no step depends on s.  The factor and the forward substitution form the
+// same fused multiply-adds in the same order as the register form; the back
+// substitution accumulates each row's terms from the last row up.
+template <int SM>
+struct CholLds {
+  double Lt[SM * SM];  // L^T: row k holds column k of L (zero above L's diagonal)
+  double rinv[SM];     // 1 / L_kk
+  double col[SM];      // the published column (factor)
+  double rowb[SM];     // the published row (substitutions)
+};
+
+template <int SM>
+__device__ __forceinline__ CholLds<SM>* chol_lds() {
+  __shared__ CholLds<SM> w;
+  return &w;
+}
+
+// sa A + sh I = L L^T (A: s x s in LDS, s <= SM) into w.  False (uniformly)
+// on a non-positive or non-finite pivot.  Step k: the owner of column k
+// publishes it raw; every lane loads it (one batch of broadcast loads), its
+// own entry and the pivot, scales by 1 / L_kk and updates its column.
+// Entries above the diagonal take arbitrary values (they are never read:
+// every entry on or below it depends only on entries on or below it).
+template <int SM>
+__device__ __forceinline__ bool lc_factor(const double* A, int s, double sa, double sh, CholLds<SM>* w) {
+  const int t = tid();
+  double a[SM];  // lane t < SM: column t
+#pragma unroll
+  for (int i = 0; i < SM; ++i)
+    a[i] = (i < s && t < s) ? fma(sa, A[i * s + t], i == t ? sh : 0.0) : (i == t ? 1.0 : 0.0);
+  __syncthreads();
+  for (int k = 0; k < SM; ++k) {
+    if (t == k) {
+#pragma unroll
+      for (int i = 0; i < SM; ++i) w->col[i] = a[i];
+    }
+    __syncthreads();
+    double cr[SM];
+#pragma unroll
+    for (int i = 0; i < SM; ++i) cr[i] = w->col[i];
+    const double d = w->col[k];
+    const double cj = w->col[t < SM ? t : 0];
+    __builtin_amdgcn_sched_barrier(0);
+    if (!(d > 0.0) || !isfinite(d)) return false;
+    const double lkk = sqrt(d);
+    const double rk = 1.0 / lkk;
+    // l_tk of this lane's column (zero above the diagonal, none past SM)
+    const double ltk = (t == k) ? lkk : ((t > k && t < SM) ? cj * rk : 0.0);
+    if (t < SM) w->Lt[k * SM + t] = ltk;
+    if (t == 0) w->rinv[k] = rk;
+#pragma unroll
+    for (int i = 0; i < SM; ++i) a[i] = fma(-(cr[i] * rk), ltk, a[i]);
+  }
+  __syncthreads();
+  return true;
+}
+
+// Rows of an s x s right-hand side per lane: lane t holds row t % SM,
+// columns [h CW, h CW + CW) with h = t / SM.
+template <int SM>
+struct RowLayout {
+  static constexpr int NH = kSB / SM;
+  static constexpr int CW = SM / NH;
+};
+
+// L Y = B (B null: the identity, so Y = L^-1); Y may alias B.
+template <int SM>
+__device__ __forceinline__ void lc_forward(const CholLds<SM>* w, const double* B, double* Y, int s) {
+  using RL = RowLayout<SM>;
+  const int t = tid(), i = t % SM, c0 = (t / SM) * RL::CW;
+  double y[RL::CW];
+#pragma unroll
+  for (int u = 0; u < RL::CW; ++u) {
+    const int c = c0 + u;
+    y[u] = B ? ((i < s && c < s) ? B[i * s + c] : 0.0) : (i == c ? 1.0 : 0.0);
+  }
+  __syncthreads();
+  for (int k = 0; k < SM; ++k) {
+    if (i == k) {
+      const double rk = w->rinv[k];
+#pragma unroll
+      for (int u = 0; u < RL::CW; ++u) {
+        y[u] = y[u] * rk;
+        const_cast<CholLds<SM>*>(w)->rowb[c0 + u] = y[u];
+      }
+    }
+    __syncthreads();
+    double rb[RL::CW];
+#pragma unroll
+    for (int u = 0; u < RL::CW; ++u) rb[u] = w->rowb[c0 + u];
+    const double lik = w->Lt[k * SM + i];
+    __builtin_amdgcn_sched_barrier(0);
+    if (i > k) {
+#pragma unroll
+      for (int u = 0; u < RL::CW; ++u) y[u] = fma(-lik, rb[u], y[u]);
+    }
+  }
+  if (i < s) {
+#pragma unroll
+    for (int u = 0; u < RL::CW; ++u)
+      if (c0 + u < s) Y[i * s + c0 + u] = y[u];
+  }
+  __syncthreads();
+}
+
+// L^T X = Y; X may alias Y.
+template <int SM>
+__device__ __forceinline__ void lc_backward(const CholLds<SM>* w, const double* Y, double* X, int s) {
+  using RL = RowLayout<SM>;
+  const int t = tid(), i = t % SM, c0 = (t / SM) * RL::CW;
+  double x[RL::CW];
+#pragma unroll
+  for (int u = 0; u < RL::CW; ++u) x[u] = (i < s && c0 + u < s) ? Y[i * s + c0 + u] : 0.0;
+  __syncthreads();
+  for (int k = SM - 1; k >= 0; --k) {
+    if (i == k) {
+      const double rk = w->rinv[k];
+#pragma unroll
+      for (int u = 0; u < RL::CW; ++u) {
+        x[u] = x[u] * rk;
+        const_cast<CholLds<SM>*>(w)->rowb[c0 + u] = x[u];
+      }
+    }
+    __syncthreads();
+    double rb[RL::CW];
+#pragma unroll
+    for (int u = 0; u < RL::CW; ++u) rb[u] = w->rowb[c0 + u];
+    const double lki = w->Lt[i * SM + k];
+    __builtin_amdgcn_sched_barrier(0);
+    if (i < k) {
+#pragma unroll
+      for (int u = 0; u < RL::CW; ++u) x[u] = fma(-lki, rb[u], x[u]);
+    }
+  }
+  if (i < s) {
+#pragma unroll
+    for (int u = 0; u < RL::CW; ++u)
+      if (c0 + u < s) X[i * s + c0 + u] = x[u];
+  }
+  __syncthreads();
+}
+
+// X = A^-1 B (and Linv = L^-1 if not null) for SPD A, all s x s in LDS.
+template <int SM>
+__device__ __forceinline__ bool lc_cholesky_solve(const double* A, const double* B, double* X, double* Linv, int s) {
+  CholLds<SM>* w = chol_lds<SM>();
+  __syncthreads();
+  if (!lc_factor<SM>(A, s, 1.0, 0.0, w)) return false;
+  lc_forward<SM>(w, B, X, s);
+  lc_backward<SM>(w, X, X, s);
+  if (Linv) lc_forward<SM>(w, nullptr, Linv, s);
+  return true;
+}
+
+// A = L L^T with L (zero above the diagonal) and L^-1 stored, s x s in LDS.
+template <int SM>
+__device__ __forceinline__ bool lc_cholesky_factor(const double* A, double* Lo, double* Linv, int s) {
+  CholLds<SM>* w = chol_lds<SM>();
+  __syncthreads();
+  if (!lc_factor<SM>(A, s, 1.0, 0.0, w)) return false;
+  for (int e = tid(); e < s * s; e += kSB) {
+    const int i = e / s, j = e % s;
+    Lo[e] = (j <= i) ? w->Lt[j * SM + i] : 0.0;
+  }
+  lc_forward<SM>(w, nullptr, Linv, s);
+  return true;
+}
+
+template <int SM>
+__device__ __forceinline__ bool lc_definite(const double* A, int s, double sa, double sh) {
+  CholLds<SM>* w = chol_lds<SM>();
+  __syncthreads();
+  return lc_factor<SM>(A, s, sa, sh, w);
 }
 
 // Rayleigh quotient of the power iteration for the symmetric s x s matrix A
@@ -1329,6 +1593,26 @@ __global__ __launch_bounds__(kSB) void cholqr_kernel(int stage, const double* G,
   sm_copy(Gm, G, s * s);
   sm_project(Gm, sub, red);
   bool ok = all_finite(Gm, s * s, red);
+  if (stage == 2 && ok) {
+    // Y^T Y within rounding of I (every entry of each group's Gram within
+    // 8 s eps of the identity): Y is already orthonormal to that level, the
+    // second pass would change it by about as much, so it is skipped:
+    // Q = Y, N = R1 (three block passes in all instead of five)
+    bool off = false;
+    const double tau = 8.0 * s * DBL_EPSILON;
+    for (int e = t; e < s * s; e += kSB) {
+      const int i = e / s, j = e % s;
+      if (i / sub.g == j / sub.g) off |= !(fabs(Gm[e] - (i == j ? 1.0 : 0.0)) <= tau);
+    }
+    if (!wany(off)) {
+      for (int e = t; e < s * s; e += kSB) N[e] = R1[e];
+      if (t == 0) {
+        plan[1] = 0;
+        plan[2] = 0;
+      }
+      return;
+    }
+  }
   if (ok) ok = rf_cholesky_factor<SM>(Gm, L, Li, s);
   if (ok) {
     bool bad = false;

@@ -256,6 +256,137 @@ template hipError_t cg_run<double>(const CsrView&, Sub, const double*, double*, 
 template hipError_t cg_run<float>(const CsrView&, Sub, const float*, float*, double, int, double, double, int,
                                   const CgBufs<float>&, hipStream_t, int32_t*, CgResult&, Prof*, const double*);
 
+// ---------------------------------------------------------- Gropp BCG --
+// Re-normalisation of R~ inside Gropp's block CG: (R-bar, gamma) =
+// Norm_S(R~), then Z = M^-1 R-bar directly (Z aliases R for M = I), rho' =
+// <Z, R-bar>_S and the coefficient step that finishes it (sigma, beta).
+static hipError_t gropp_normalise(int64_t n, Sub sub, const CgBufs<double>& b, double* Z, int nblk, hipStream_t st,
+                                  Prof* prof, const double* minv) {
+  CgCtl* c = b.ctl;
+  ProfScope ps(prof, PROF_CG_NORMALISE, st);
+  BK_TRY(tsqr_run<double>(n, sub, b.R, c->gamma, b.tsqr_ws, b.cnt, &c->done, &c->fire, st));
+  if (minv) BK_TRY(launch_row_scale<double>(n, sub.s, minv, b.R, Z, &c->done, &c->fire, st));
+  BK_TRY(launch_gram<double>(n, sub.s, Z, 1, b.R, b.partial, nblk, Red{b.Gq, b.gpart, b.cnt}, &c->done, st,
+                             &c->fire));
+  return launch_cg_reortho_fin(c, sub.s, b.Gq, st);
+}
+
+hipError_t gropp_run(const CsrView& A, Sub sub, const double* B, double* X, double tol, int maxit, double eta,
+                     int hist_cap, const CgBufs<double>& b, double* U, double* Zbuf, hipStream_t st, int32_t* hflags,
+                     CgResult& res, Prof* prof, const double* minv) {
+  const int64_t n = A.n;
+  const int s = sub.s;
+  const size_t blk = (size_t)n * s;
+  const double eps = DBL_EPSILON;
+  const int nblk = stream_grid(n, s, sizeof(double));
+  CgCtl* c = b.ctl;
+  int32_t* gate = &c->gate;
+  const Red ra{b.Ga, b.gpart, b.cnt}, rr{b.Gr, b.gpart, b.cnt};
+  const bool always = eta > 0.0 && (isinf(eta) || eta * sqrt(eps) > 1.0);
+  const bool dynamic = eta > 0.0 && !always && sub.g > 1;
+  // Z = M^-1 R-bar is carried by its recurrence; for M = I the recurrence
+  // repeats the residual update operation for operation, so Z is R-bar
+  double* Z = minv ? Zbuf : b.R;
+
+  CgCtl* h = reinterpret_cast<CgCtl*>(hflags + 64);
+  memset(h, 0, offsetof(CgCtl, r0n));
+  h->maxit = maxit;
+  h->s = s;
+  h->kind = sub.kind;
+  h->g = sub.g;
+  h->hist_cap = hist_cap;
+  h->dynamic = dynamic ? 1 : 0;
+  h->tol = tol;
+  h->eta = eta;
+  h->sqrt_eps = sqrt(eps);
+  BK_TRY(hipMemcpyAsync(c, h, offsetof(CgCtl, r0n), hipMemcpyHostToDevice, st));
+
+  // R0 = B - A X0; normalisation; P0 = Z0 = M^-1 R-bar; rho = <P0, R-bar>_S;
+  // Q0 = A P0; alpha = <P0, Q0>_S and its coefficient step (lambda)
+  BK_TRY(launch_spmm<double>(A, s, X, b.R, B, 2, b.partial, nblk, ra, &c->bad_index, nullptr, st));
+  BK_TRY(launch_cg_init(c, b.Ga, nullptr, st));
+  if (eta > 0.0) BK_TRY(tsqr_run<double>(n, sub, b.R, c->sigma, b.tsqr_ws, b.cnt, &c->done, nullptr, st));
+  if (minv) {
+    BK_TRY(launch_row_scale<double>(n, s, minv, b.R, b.P, nullptr, nullptr, st));
+    BK_TRY(hipMemcpyAsync(Z, b.P, sizeof(double) * blk, hipMemcpyDeviceToDevice, st));
+  } else {
+    BK_TRY(hipMemcpyAsync(b.P, b.R, sizeof(double) * blk, hipMemcpyDeviceToDevice, st));
+  }
+  BK_TRY(launch_gram<double>(n, s, b.P, 1, b.R, b.partial, nblk, rr, &c->done, st));
+  BK_TRY(launch_cg_init(c, nullptr, b.Gr, st));
+  BK_TRY(launch_spmm<double>(A, s, b.P, b.Q, nullptr, 0, nullptr, nblk, ra, &c->bad_index, &c->done, st));
+  BK_TRY(launch_gram_partials(n, s, b.P, b.Q, b.partial, nblk, 0, &c->done, nullptr, st));
+  BK_TRY(launch_reduce(s, b.partial, false, nblk, 1, ra, gate, nullptr, Epi{EPI_CG_ALPHA, c, nullptr}, st));
+
+  const CgCtl* hc = reinterpret_cast<const CgCtl*>(hflags);
+  // P_k lives in pbuf[k % 2] (the direction pass writes P_{k+1} over
+  // P_{k-1}, whose term the deferred X update reads first)
+  double* const pbuf[2] = {b.P, b.P2};
+  // the rest of iteration k after its residual pass (and, if it fired, its
+  // re-normalisation): U = A Z, the direction pass and the next alpha
+  auto tail = [&](int k) -> hipError_t {
+    {
+      ProfScope ps(prof, PROF_CG_SPMM, st, k);
+      BK_TRY(launch_spmm<double>(A, s, Z, U, nullptr, 0, nullptr, nblk, ra, &c->bad_index, gate, st, Epi{},
+                                 ps.end()));
+    }
+    {
+      ProfScope ps(prof, PROF_CG_PUPDATE, st, k);
+      BK_TRY(launch_gropp_dir(n, s, X, pbuf[k & 1], pbuf[(k + 1) & 1], Z, U, b.Q, c, b.partial, nblk, st));
+    }
+    return launch_reduce(s, b.partial, false, nblk, 1, ra, gate, nullptr, Epi{EPI_CG_ALPHA, c, nullptr}, st);
+  };
+  int k = 0, batch = 4, last_iters = -1;
+  while (maxit > 0) {
+    for (int it = 0; it < batch; ++it, ++k) {
+      {
+        // R~ = R-bar - Q lambda (and Z = Z - M^-1 Q lambda); stopping test,
+        // rho' = <Z, R~>_S and beta in the reduction's coefficient step
+        ProfScope ps(prof, PROF_CG_UPDATE, st, k);
+        if (minv) {
+          BK_TRY(launch_gropp_update(n, s, b.R, b.Q, Z, c, b.partial, nblk, minv, st));
+          BK_TRY(launch_reduce(s, b.partial, false, nblk, 1, rr, gate, nullptr, Epi{EPI_CG_RHO_M, c, b.hist}, st));
+        } else {
+          BK_TRY(launch_cg_update<double>(n, s, b.R, b.Q, c, b.partial, nblk, rr, st, Epi{EPI_CG_RHO, c, b.hist},
+                                          nullptr, nullptr));
+        }
+      }
+      if (always) BK_TRY(gropp_normalise(n, sub, b, Z, nblk, st, prof, minv));
+      BK_TRY(tail(k));
+    }
+    BK_TRY(hipMemcpyAsync(hflags, c, kCtlHeaderInts * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    BK_TRY(hipStreamSynchronize(st));
+    {
+      const int it = hc->iters, itp = hc->suspended ? hc->iters - 1 : hc->iters;
+      const int live[PROF_N] = {itp, it, itp, 0x7fffffff};
+      BK_TRY(prof_flush(prof, live));
+    }
+    if (hc->done) break;
+    if (hc->suspended) {
+      // iteration iters-1 waits for its re-normalisation: run it and the
+      // rest of that iteration, then continue with short batches
+      const int ks = hc->iters - 1;
+      BK_TRY(gropp_normalise(n, sub, b, Z, nblk, st, prof, minv));
+      BK_TRY(tail(ks));
+      k = ks + 1;
+      batch = 2;
+    } else {
+      if (hc->iters == last_iters) break;
+      if (batch < 32) batch *= 2;
+    }
+    last_iters = hc->iters;
+  }
+  BK_TRY(hipMemcpyAsync(hflags, c, kCtlHeaderInts * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  BK_TRY(hipStreamSynchronize(st));
+  res.status = hc->status;
+  res.iters = hc->iters;
+  res.nreorth = hc->nreorth;
+  res.converged = hc->converged;
+  res.bad_index = hc->bad_index;
+  res.kd_jacobi = hc->kd_jacobi;
+  return hipSuccess;
+}
+
 // ------------------------------------------------------ multicolour SSOR --
 SsorWs ssor_carve(Carver& c, int64_t n) {
   SsorWs w;
@@ -555,7 +686,8 @@ BcBufs carve_bc(Carver& c, int64_t n, Sub sub, int hist_cap, uint32_t* cnt) {
 // lambda sigma is formed before sigma changes, omega sigma after (the X
 // update by T carries the new transformation).
 hipError_t bc_run(const CsrView& A, Sub sub, const double* B, double* X, double tol, int maxit, double eta,
-                  int hist_cap, const BcBufs& b, hipStream_t st, int32_t* hflags, BcResult& res) {
+                  int hist_cap, const BcBufs& b, hipStream_t st, int32_t* hflags, BcResult& res,
+                  const double* r0n_fixed) {
   const int64_t n = A.n;
   const int s = sub.s;
   const size_t blk = (size_t)n * s;
@@ -585,6 +717,8 @@ hipError_t bc_run(const CsrView& A, Sub sub, const double* B, double* X, double 
   // R0 = B - A X0 and its Gram; initial normalisation; P = R, R~0 = P
   BK_TRY(launch_spmm<double>(A, s, X, R, B, 2, b.partial, nblk, rrr, &c->bad_index, nullptr, st));
   BK_TRY(launch_cg_init(c, b.Grr, nullptr, st));
+  // a restart keeps the stopping test's denominators of the first start
+  if (r0n_fixed) BK_TRY(hipMemcpyAsync(c->r0n, r0n_fixed, sizeof(double) * s, hipMemcpyDeviceToDevice, st));
   if (eta > 0.0) {
     BK_TRY(tsqr_run<double>(n, sub, R, c->sigma, b.tsqr_ws, b.cnt, done, nullptr, st));
     BK_TRY(launch_gram<double>(n, s, R, 1, R, b.partial, nblk, rrr, done, st));

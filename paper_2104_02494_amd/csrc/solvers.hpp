@@ -83,6 +83,13 @@ hipError_t cg1r_run(const CsrView& A, Sub sub, const double* B, double* X, doubl
                     int hist_cap, const CgBufs<double>& b, hipStream_t st, int32_t* hflags, CgResult& res,
                     Prof* prof = nullptr);
 
+// Gropp's block CG (alg:gropps_block_cg, Ch. 8), FP64, with a diagonal
+// preconditioner (minv) or M = I: the CgBufs of the same n and sub plus two
+// n x s blocks, U = A Z and Z = M^-1 R-bar (unused for M = I).
+hipError_t gropp_run(const CsrView& A, Sub sub, const double* B, double* X, double tol, int maxit, double eta,
+                     int hist_cap, const CgBufs<double>& b, double* U, double* Zbuf, hipStream_t st, int32_t* hflags,
+                     CgResult& res, Prof* prof = nullptr, const double* minv = nullptr);
+
 // Workspace of a multicolour SSOR plan (ssor_carve) and its construction:
 // checks the colouring against A (err: 0, or 1 colour out of range, 2 coupled
 // rows of one colour or a bad column index, 3 a row without a positive
@@ -162,8 +169,11 @@ struct BcResult {
 
 // Block BiCGStab with adaptive residual re-orthonormalisation (FP64, M = I).
 // X holds X0 on entry.
+// r0n_fixed (device, s doubles, or null): stopping-test denominators kept
+// from an earlier start (a restart on the true residual).
 hipError_t bc_run(const CsrView& A, Sub sub, const double* B, double* X, double tol, int maxit, double eta,
-                  int hist_cap, const BcBufs& b, hipStream_t st, int32_t* hflags, BcResult& res);
+                  int hist_cap, const BcBufs& b, hipStream_t st, int32_t* hflags, BcResult& res,
+                  const double* r0n_fixed = nullptr);
 
 // True relative column residuals |B_i - A X_i| / r0n_i (FP64) into relres
 // (device); R (n x s), partial, gpart, G and scale_scratch are scratch.

@@ -96,42 +96,32 @@ def test_bicgstab_full_size_fixed_iterations(orc, h):
     assert info["iters"] == 2 and rel(X, ro["X"]) < 1e-9
 
 
-def test_bicgstab_residual_gap_matches_oracle(orc, h):
-    """The recursive residual of BiCGStab drifts from the true one (no
-    residual replacement in the algorithm): on the 128^2 convection-diffusion
-    problem the oracle stops at 1e-10 with a true residual of about 2.5e-8.
-    The size of this gap depends chaotically on rounding (perturbing B by
-    4 eps spreads it over 2e-8 ... 5e-8 on both sides, with rare outliers
-    several times larger), so the GPU is run on three such perturbations and
-    their median must be of the oracle's order, after about as many
-    iterations."""
+def test_bicgstab_restart_closes_residual_gap_like_oracle(orc, h):
+    """The recursive residual of BiCGStab drifts from the true one: on the
+    128^2 convection-diffusion problem the plain iteration stops at 1e-10
+    with a true residual of about 2.5e-8.  Both the GPU and the oracle then
+    restart from the current iterate until the FP64 true residual meets the
+    tolerance.  The size of the gap depends chaotically on rounding, so the
+    restart counts may differ; the results must not."""
     A = W.convdiff_2d(128)
     B = W.gaussian_block(A.n, 8, 1004)
-    ro = orc.bbicgstab(A, B, tol=1e-10, maxit=5000, eta=1e4)
-    true_o = np.linalg.norm(B - orc.spmm(A, ro["X"]), axis=0) / np.linalg.norm(B, axis=0)
-    assert ro["converged"]
-    gaps = []
-    for seed in (1, 2, 3):
-        u = np.random.default_rng(seed).uniform(-1.0, 1.0, B.shape)
-        say("bicgstab 128^2 solve", seed)
-        X, info = gpu_bc(h, A, B * (1.0 + 4e-16 * u), tol=1e-10, maxit=5000, eta=1e4)
-        # the recursion met the tolerance; converged reports the true residual
-        assert max(info["relres"]) <= 1e-10
-        assert info["converged"] == (max(info["true_relres"]) <= 1e-10)
-        assert abs(info["iters"] - ro["iters"]) <= max(5, ro["iters"] // 10)
-        gaps.append(max(info["true_relres"]))
-    assert np.median(gaps) <= 10.0 * true_o.max() + 1e-10, (gaps, true_o.max())
+    ro = orc.bbicgstab(A, B, tol=1e-10, maxit=5000, eta=1e4, max_restarts=10)
+    assert ro["converged"] and ro["restarts"] >= 1
+    say("bicgstab 128^2 restarted solve")
+    X, info = gpu_bc(h, A, B, tol=1e-10, maxit=5000, eta=1e4)
+    assert info["converged"] and info["outer_iters"] >= 1
+    assert max(info["true_relres"]) <= 1e-10
+    assert abs(info["iters"] - ro["iters"]) <= max(20, ro["iters"] // 5)
+    Xs = ro["X"]
+    assert rel(X, Xs) < 1e-7
 
 
 def test_bicgstab_full_size_time_to_tol(h):
-    """Full solve at full size: converges to 1e-10 (recursive residual); the
-    FP64 true residual stays within the gap the algorithm allows (see the
-    test above; property check at a size the oracle cannot repeat
-    quickly)."""
+    """Full solve at full size: the FP64 true residual meets 1e-10 (with the
+    restarts that close the recursion's residual gap; property check at a
+    size the oracle cannot repeat quickly)."""
     A, B, _ = W.build_workload("convdiff2d_1024_s8")
     say("bicgstab 1024^2 solve")
     X, info = P.bkry_bicgstab_solve(h, dev_csr(P, A), to_dev(B), tol=1e-10, maxit=20000, eta=1e4)
     say("bicgstab 1024^2 iters", info["iters"], "reorth", info["reorth"], "s", info["seconds"])
-    assert max(info["relres"]) <= 1e-10
-    assert info["converged"] == (max(info["true_relres"]) <= 1e-10)
-    assert max(info["true_relres"]) < 1e-6
+    assert info["converged"] and max(info["true_relres"]) <= 1e-10
