@@ -446,194 +446,437 @@ __device__ __forceinline__ bool rf_definite(const double* A, int s, double sa, d
   }
 }
 
-// ------------------------------------------ LDS-broadcast Cholesky (wide) --
-// For widths 16 and 32 the register form above unrolls into tens of
+// ------------------------------------------------------ wide helpers --
+// For widths 16 and 32 the register forms above unroll into tens of
 // thousands of instructions (each entry of L reaches the other lanes by two
-// lane reads, one step after the other), and the coefficient steps then
-// stream their code through the instruction cache on every call.  The forms
-// below keep the step loop rolled, so the few hundred instructions of one
-// step are fetched once and run SM times, and exchange through LDS with
-// broadcast loads (every lane reads the same address):
-//   factor   lane j holds column j; the owner of column k publishes it, every
-//            lane then reads the pivot and the column of L (scaled once);
-//   forward  lane (h, i) holds row i of the right-hand sides, columns
-//            [h CW, h CW + CW); the owner of row k finalises and publishes it;
-//   backward the same, from the last row up.
-// Every register index is a compile-time constant.  The matrices are padded
-// to SM with the identity ([A 0; 0 I] = [L 0; 0 I][L 0; 0 I]^T exactly), so
-// no step depends on s.  The factor and the forward substitution form the
-// same fused multiply-adds in the same order as the register form; the back
-// substitution accumulates each row's terms from the last row up.
+// lane reads, one step after the other), which the coefficient steps would
+// stream through the instruction cache on every call.  The wide forms below
+// spread every vector over all 64 lanes and exchange through LDS.
 template <int SM>
-struct CholLds {
-  double Lt[SM * SM];  // L^T: row k holds column k of L (zero above L's diagonal)
-  double rinv[SM];     // 1 / L_kk
-  double col[SM];      // the published column (factor)
-  double rowb[SM];     // the published row (substitutions)
+struct Seg {
+  static constexpr int NQ = kSB / SM;  // lanes per row
+  static constexpr int RW = SM / NQ;   // entries per lane
+  // segment stride in doubles: the NQ segments read by one instruction start
+  // 16 bytes apart modulo the bank width, so their 16-byte reads do not collide
+  static constexpr int ST = RW + 2;
+  static constexpr int LEN = NQ * ST;
+  __device__ static constexpr int at(int i) { return (i / RW) * ST + i % RW; }
 };
 
 template <int SM>
-__device__ __forceinline__ CholLds<SM>* chol_lds() {
-  __shared__ CholLds<SM> w;
+struct PowLds {
+  __align__(16) double xs[Seg<SM>::LEN];  // the iterate, segmented
+  double part[kSB];                       // partial row sums
+};
+
+template <int SM>
+__device__ __forceinline__ PowLds<SM>* pow_lds() {
+  __shared__ PowLds<SM> w;
   return &w;
 }
 
-// sa A + sh I = L L^T (A: s x s in LDS, s <= SM) into w.  False (uniformly)
-// on a non-positive or non-finite pivot.  Step k: the owner of column k
-// publishes it raw; every lane loads it (one batch of broadcast loads), its
-// own entry and the pivot, scales by 1 / L_kk and updates its column.
-// Entries above the diagonal take arbitrary values (they are never read:
-// every entry on or below it depends only on entries on or below it).
+__device__ __forceinline__ void st2(double* p, double a, double b) {
+  *reinterpret_cast<double2*>(p) = make_double2(a, b);
+}
+__device__ __forceinline__ double2 ld2(const double* p) { return *reinterpret_cast<const double2*>(p); }
+
+// ------------------------------ blocked Cholesky on the matrix cores (wide) --
+// The same factorisation in blocks of 4 columns, so a width-32 matrix takes 8
+// dependent steps instead of 32, each a handful of instructions plus a few
+// v_mfma_f64_16x16x4f64 products.  The trailing matrix and the right-hand
+// sides stay in accumulator layout for the whole factorisation (lane l holds
+// entries (16 a + 4 v + l / 16, 16 b + l % 16) of tile (a, b), v = 0..3).
+// Block step K (columns 4K .. 4K + 3):
+//   the panel (those 4 columns) goes through LDS into row layout; every lane
+//   factors the 4 x 4 diagonal block, D = L_KK L_KK^T, and forms W = L_KK^-1
+//   (pivot reciprocals d^-1/2, L_kk = d * d^-1/2); lane (k = l / 16, row r)
+//   forms its panel entry L[r][4K + k] = sum_m P[r][m] W[k][m], which is at
+//   once the A operand (rows) and the B operand (columns) of the rank-4
+//   update of the trailing matrix, A -= L_K L_K^T, one product per tile;
+//   the right-hand sides' rows 4K .. 4K + 3 become Y_K = W B_K (forward
+//   substitution) and the rows below lose L_K Y_K, one product per tile.
+// The back substitution L^T X = Y runs the same blocks from the last up:
+// X_K = W^T Y_K, then the rows above lose L_K^T X_K.  Rows and columns past
+// s are padded with the identity (right-hand sides with zeros), so no step
+// depends on s.  A single wavefront's LDS accesses are carried out in program
+// order, so the exchanges need no barrier.
+typedef double mf_d4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ mf_d4 mf_mma(double a, double b, mf_d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
 template <int SM>
-__device__ __forceinline__ bool lc_factor(const double* A, int s, double sa, double sh, CholLds<SM>* w) {
-  const int t = tid();
-  double a[SM];  // lane t < SM: column t
+struct MfLds {
+  __align__(16) double Pn[SM * 4];       // panel rows (row-major, 4 columns)
+  __align__(16) double Yb[2 * SM * 4];   // the block's right-hand-side rows, by column
+  __align__(16) double Ws[SM / 4 * 16];  // W = L_KK^-1 of every diagonal block (row-major 4 x 4)
+  double Ls[SM * (SM + 1)];              // L, rows padded to SM + 1
+};
+
+template <int SM>
+__device__ __forceinline__ MfLds<SM>* mf_lds() {
+  __shared__ MfLds<SM> w;
+  return &w;
+}
+
+// d = L L^T for the 4 x 4 block d (row-major, lower part read): L and
+// W = L^-1 (row-major, zero above the diagonal).  bad: a pivot that is not
+// positive or not finite.
+__device__ __forceinline__ void mf_diag4(const double (&d)[16], double (&L)[16], double (&W)[16], bool& bad) {
 #pragma unroll
-  for (int i = 0; i < SM; ++i)
-    a[i] = (i < s && t < s) ? fma(sa, A[i * s + t], i == t ? sh : 0.0) : (i == t ? 1.0 : 0.0);
+  for (int i = 0; i < 16; ++i) L[i] = W[i] = 0.0;
+  double p = d[0];
+  bad |= !(p > 0.0) || !isfinite(p);
+  const double r0 = rsqrt(p);
+  L[0] = p * r0;
+  L[4] = d[4] * r0;
+  L[8] = d[8] * r0;
+  L[12] = d[12] * r0;
+  p = fma(-L[4], L[4], d[5]);
+  bad |= !(p > 0.0) || !isfinite(p);
+  const double r1 = rsqrt(p);
+  L[5] = p * r1;
+  L[9] = fma(-L[8], L[4], d[9]) * r1;
+  L[13] = fma(-L[12], L[4], d[13]) * r1;
+  p = fma(-L[9], L[9], fma(-L[8], L[8], d[10]));
+  bad |= !(p > 0.0) || !isfinite(p);
+  const double r2 = rsqrt(p);
+  L[10] = p * r2;
+  L[14] = fma(-L[13], L[9], fma(-L[12], L[8], d[14])) * r2;
+  p = fma(-L[14], L[14], fma(-L[13], L[13], fma(-L[12], L[12], d[15])));
+  bad |= !(p > 0.0) || !isfinite(p);
+  const double r3 = rsqrt(p);
+  L[15] = p * r3;
+  W[0] = r0;
+  W[5] = r1;
+  W[10] = r2;
+  W[15] = r3;
+  W[4] = -(L[4] * r0) * r1;
+  W[9] = -(L[9] * r1) * r2;
+  W[14] = -(L[14] * r2) * r3;
+  W[8] = -fma(L[9], W[4], L[8] * r0) * r2;
+  W[13] = -fma(L[14], W[9], L[13] * r1) * r3;
+  W[12] = -fma(L[14], W[8], fma(L[13], W[4], L[12] * r0)) * r3;
+}
+
+// Element k (0..3, this lane's) of the four values v[0..3].
+__device__ __forceinline__ double mf_pick(const double (&v)[4], int k) {
+  return k == 0 ? v[0] : (k == 1 ? v[1] : (k == 2 ? v[2] : v[3]));
+}
+
+// sa A + sh I = L L^T (A: s x s in LDS); RHS: X = (sa A + sh I)^-1 B (BACK)
+// or Y = L^-1 B (no BACK) into X; INV: Linv = L^-1; LO: Lo = L (zero above the
+// diagonal).  All s x s, row-major, in LDS; X may alias B.  False (uniformly)
+// on a pivot that is not positive or not finite.
+template <int SM, bool RHS, bool INV, bool BACK, bool LO>
+__device__ __forceinline__ bool mf_chol(const double* A, int s, double sa, double sh, const double* B, double* X,
+                                        double* Linv, double* Lo) {
+  constexpr int NT = SM / 16, NB = SM / 4;
+  constexpr int NR = RHS ? NT : 0, NC = NR + (INV ? NT : 0), NCA = NC > 0 ? NC : 1;
+  constexpr bool KEEP_L = BACK || LO;
+  MfLds<SM>* w = mf_lds<SM>();
+  const int l = tid(), lr = l / 16, lc = l % 16;
+  mf_d4 at[NT][NT];
+  mf_d4 bt[NT][NCA];
   __syncthreads();
-  for (int k = 0; k < SM; ++k) {
-    if (t == k) {
+  static_for<NT>([&](auto A_) {
+    constexpr int a = decltype(A_)::value;
+    static_for<NT>([&](auto B_) {
+      constexpr int b = decltype(B_)::value;
+      if constexpr (b <= a) {
 #pragma unroll
-      for (int i = 0; i < SM; ++i) w->col[i] = a[i];
+        for (int v = 0; v < 4; ++v) {
+          const int r = 16 * a + 4 * v + lr, c = 16 * b + lc;
+          at[a][b][v] = (r < s && c < s) ? fma(sa, A[r * s + c], r == c ? sh : 0.0) : (r == c ? 1.0 : 0.0);
+        }
+      }
+    });
+    static_for<NCA>([&](auto C_) {
+      constexpr int cc = decltype(C_)::value;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = 16 * a + 4 * v + lr;
+        if constexpr (cc < NR) {
+          const int c = 16 * cc + lc;
+          bt[a][cc][v] = (r < s && c < s) ? B[r * s + c] : 0.0;
+        } else {
+          bt[a][cc][v] = (r == 16 * (cc - NR) + lc) ? 1.0 : 0.0;
+        }
+      }
+    });
+  });
+  __syncthreads();
+  bool bad = false;
+  static_for<NB>([&](auto K_) {
+    constexpr int K = decltype(K_)::value, ta = K / 4, kb = K % 4;
+    // publish the panel and the block's right-hand-side rows
+    if (lc / 4 == kb) {
+      static_for<NT>([&](auto A_) {
+        constexpr int a = decltype(A_)::value;
+        if constexpr (a >= ta) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) w->Pn[(16 * a + 4 * v + lr) * 4 + lc % 4] = at[a][ta][v];
+        }
+      });
     }
+    if constexpr (NC > 0) {
+#pragma unroll
+      for (int c = 0; c < NC; ++c) w->Yb[(16 * c + lc) * 4 + lr] = bt[ta][c][kb];
+    }
+    __builtin_amdgcn_wave_barrier();
+    double d[16];
+#pragma unroll
+    for (int i = 0; i < 16; i += 2) {
+      const double2 q = ld2(w->Pn + 16 * K + i);
+      d[i] = q.x;
+      d[i + 1] = q.y;
+    }
+    double pr[NT][4];
+    static_for<NT>([&](auto A_) {
+      constexpr int a = decltype(A_)::value;
+      if constexpr (a >= ta) {
+        const double2 q0 = ld2(w->Pn + (16 * a + lc) * 4), q1 = ld2(w->Pn + (16 * a + lc) * 4 + 2);
+        pr[a][0] = q0.x;
+        pr[a][1] = q0.y;
+        pr[a][2] = q1.x;
+        pr[a][3] = q1.y;
+      }
+    });
+    double yb[NCA][4];
+    if constexpr (NC > 0) {
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        const double2 q0 = ld2(w->Yb + (16 * c + lc) * 4), q1 = ld2(w->Yb + (16 * c + lc) * 4 + 2);
+        yb[c][0] = q0.x;
+        yb[c][1] = q0.y;
+        yb[c][2] = q1.x;
+        yb[c][3] = q1.y;
+      }
+    }
+    double L4[16], W4[16];
+    mf_diag4(d, L4, W4, bad);
+    // this lane's panel entries L[16 a + lc][4K + lr]: the rows of the block
+    // take L_KK itself, the rows above it zero
+    double lv[NT], op[NT];
+    static_for<NT>([&](auto A_) {
+      constexpr int a = decltype(A_)::value;
+      if constexpr (a < ta) {
+        lv[a] = 0.0;
+        op[a] = 0.0;
+      } else {
+        double pl[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          double x = pr[a][0] * W4[4 * k];
+#pragma unroll
+          for (int m = 1; m <= k; ++m) x = fma(pr[a][m], W4[4 * k + m], x);
+          pl[k] = x;
+        }
+        const int r = 16 * a + lc;
+        const double trail = mf_pick(pl, lr);
+        if constexpr (a == ta) {
+          const int rr = r - 4 * K;  // 0..3 on the block's rows
+          double lrow[4];
+#pragma unroll
+          for (int k = 0; k < 4; ++k)
+            lrow[k] = rr == 0 ? L4[k] : (rr == 1 ? L4[4 + k] : (rr == 2 ? L4[8 + k] : L4[12 + k]));
+          lv[a] = (r < 4 * K) ? 0.0 : (r < 4 * K + 4 ? mf_pick(lrow, lr) : trail);
+        } else {
+          lv[a] = trail;
+        }
+        op[a] = (r < 4 * K + 4) ? 0.0 : trail;
+      }
+    });
+    if constexpr (KEEP_L) {
+      static_for<NT>([&](auto A_) {
+        constexpr int a = decltype(A_)::value;
+        if constexpr (a >= ta) w->Ls[(16 * a + lc) * (SM + 1) + 4 * K + lr] = lv[a];
+      });
+    }
+    if constexpr (BACK) {
+      if (l == 0) {
+#pragma unroll
+        for (int i = 0; i < 16; i += 2) st2(w->Ws + 16 * K + i, W4[i], W4[i + 1]);
+      }
+    }
+    // rank-4 update of the trailing matrix
+    static_for<NT>([&](auto A_) {
+      constexpr int a = decltype(A_)::value;
+      static_for<NT>([&](auto B_) {
+        constexpr int b = decltype(B_)::value;
+        if constexpr (a >= ta && b >= ta && b <= a) at[a][b] = mf_mma(-op[a], op[b], at[a][b]);
+      });
+    });
+    // forward substitution: Y_K = W B_K, then the rows below
+    if constexpr (NC > 0) {
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        double yk[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          double x = W4[4 * k] * yb[c][0];
+#pragma unroll
+          for (int m = 1; m <= k; ++m) x = fma(W4[4 * k + m], yb[c][m], x);
+          yk[k] = x;
+        }
+        const double y = mf_pick(yk, lr);
+        bt[ta][c][kb] = y;
+        static_for<NT>([&](auto A_) {
+          constexpr int a = decltype(A_)::value;
+          if constexpr (a >= ta) bt[a][c] = mf_mma(-op[a], y, bt[a][c]);
+        });
+      }
+    }
+  });
+  if (bad) {
     __syncthreads();
-    double cr[SM];
+    return false;
+  }
+  if constexpr (INV) {
+    static_for<NT>([&](auto A_) {
+      constexpr int a = decltype(A_)::value;
 #pragma unroll
-    for (int i = 0; i < SM; ++i) cr[i] = w->col[i];
-    const double d = w->col[k];
-    const double cj = w->col[t < SM ? t : 0];
-    __builtin_amdgcn_sched_barrier(0);
-    if (!(d > 0.0) || !isfinite(d)) return false;
-    const double lkk = sqrt(d);
-    const double rk = 1.0 / lkk;
-    // l_tk of this lane's column (zero above the diagonal, none past SM)
-    const double ltk = (t == k) ? lkk : ((t > k && t < SM) ? cj * rk : 0.0);
-    if (t < SM) w->Lt[k * SM + t] = ltk;
-    if (t == 0) w->rinv[k] = rk;
+      for (int c = 0; c < NT; ++c)
 #pragma unroll
-    for (int i = 0; i < SM; ++i) a[i] = fma(-(cr[i] * rk), ltk, a[i]);
+        for (int v = 0; v < 4; ++v) {
+          const int r = 16 * a + 4 * v + lr, cl = 16 * c + lc;
+          if (r < s && cl < s) Linv[r * s + cl] = bt[a][NR + c][v];
+        }
+    });
+  }
+  if constexpr (BACK) {
+    static_for<NB>([&](auto J_) {
+      constexpr int K = NB - 1 - decltype(J_)::value, ta = K / 4, kb = K % 4;
+#pragma unroll
+      for (int c = 0; c < NR; ++c) w->Yb[(16 * c + lc) * 4 + lr] = bt[ta][c][kb];
+      __builtin_amdgcn_wave_barrier();
+      double W4[16];
+#pragma unroll
+      for (int i = 0; i < 16; i += 2) {
+        const double2 q = ld2(w->Ws + 16 * K + i);
+        W4[i] = q.x;
+        W4[i + 1] = q.y;
+      }
+      double op[NT];
+      static_for<NT>([&](auto A_) {
+        constexpr int a = decltype(A_)::value;
+        if constexpr (a <= ta) {
+          const int r = 16 * a + lc;
+          const double v = w->Ls[(4 * K + lr) * (SM + 1) + r];
+          op[a] = (r < 4 * K) ? v : 0.0;
+        }
+      });
+#pragma unroll
+      for (int c = 0; c < NR; ++c) {
+        const double2 q0 = ld2(w->Yb + (16 * c + lc) * 4), q1 = ld2(w->Yb + (16 * c + lc) * 4 + 2);
+        const double y[4] = {q0.x, q0.y, q1.x, q1.y};
+        double xk[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          double x = W4[12 + k] * y[3];
+#pragma unroll
+          for (int m = 2; m >= k; --m) x = fma(W4[4 * m + k], y[m], x);
+          xk[k] = x;
+        }
+        const double x = mf_pick(xk, lr);
+        bt[ta][c][kb] = x;
+        static_for<NT>([&](auto A_) {
+          constexpr int a = decltype(A_)::value;
+          if constexpr (a <= ta) bt[a][c] = mf_mma(-op[a], x, bt[a][c]);
+        });
+      }
+    });
+  }
+  if constexpr (RHS) {
+    __syncthreads();
+    static_for<NT>([&](auto A_) {
+      constexpr int a = decltype(A_)::value;
+#pragma unroll
+      for (int c = 0; c < NR; ++c)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int r = 16 * a + 4 * v + lr, cl = 16 * c + lc;
+          if (r < s && cl < s) X[r * s + cl] = bt[a][c][v];
+        }
+    });
+  }
+  if constexpr (LO) {
+    __syncthreads();
+    for (int e = tid(); e < s * s; e += kSB) {
+      const int i = e / s, j = e % s;
+      Lo[e] = (j <= i) ? w->Ls[i * (SM + 1) + j] : 0.0;
+    }
   }
   __syncthreads();
   return true;
-}
-
-// Rows of an s x s right-hand side per lane: lane t holds row t % SM,
-// columns [h CW, h CW + CW) with h = t / SM.
-template <int SM>
-struct RowLayout {
-  static constexpr int NH = kSB / SM;
-  static constexpr int CW = SM / NH;
-};
-
-// L Y = B (B null: the identity, so Y = L^-1); Y may alias B.
-template <int SM>
-__device__ __forceinline__ void lc_forward(const CholLds<SM>* w, const double* B, double* Y, int s) {
-  using RL = RowLayout<SM>;
-  const int t = tid(), i = t % SM, c0 = (t / SM) * RL::CW;
-  double y[RL::CW];
-#pragma unroll
-  for (int u = 0; u < RL::CW; ++u) {
-    const int c = c0 + u;
-    y[u] = B ? ((i < s && c < s) ? B[i * s + c] : 0.0) : (i == c ? 1.0 : 0.0);
-  }
-  __syncthreads();
-  for (int k = 0; k < SM; ++k) {
-    if (i == k) {
-      const double rk = w->rinv[k];
-#pragma unroll
-      for (int u = 0; u < RL::CW; ++u) {
-        y[u] = y[u] * rk;
-        const_cast<CholLds<SM>*>(w)->rowb[c0 + u] = y[u];
-      }
-    }
-    __syncthreads();
-    double rb[RL::CW];
-#pragma unroll
-    for (int u = 0; u < RL::CW; ++u) rb[u] = w->rowb[c0 + u];
-    const double lik = w->Lt[k * SM + i];
-    __builtin_amdgcn_sched_barrier(0);
-    if (i > k) {
-#pragma unroll
-      for (int u = 0; u < RL::CW; ++u) y[u] = fma(-lik, rb[u], y[u]);
-    }
-  }
-  if (i < s) {
-#pragma unroll
-    for (int u = 0; u < RL::CW; ++u)
-      if (c0 + u < s) Y[i * s + c0 + u] = y[u];
-  }
-  __syncthreads();
-}
-
-// L^T X = Y; X may alias Y.
-template <int SM>
-__device__ __forceinline__ void lc_backward(const CholLds<SM>* w, const double* Y, double* X, int s) {
-  using RL = RowLayout<SM>;
-  const int t = tid(), i = t % SM, c0 = (t / SM) * RL::CW;
-  double x[RL::CW];
-#pragma unroll
-  for (int u = 0; u < RL::CW; ++u) x[u] = (i < s && c0 + u < s) ? Y[i * s + c0 + u] : 0.0;
-  __syncthreads();
-  for (int k = SM - 1; k >= 0; --k) {
-    if (i == k) {
-      const double rk = w->rinv[k];
-#pragma unroll
-      for (int u = 0; u < RL::CW; ++u) {
-        x[u] = x[u] * rk;
-        const_cast<CholLds<SM>*>(w)->rowb[c0 + u] = x[u];
-      }
-    }
-    __syncthreads();
-    double rb[RL::CW];
-#pragma unroll
-    for (int u = 0; u < RL::CW; ++u) rb[u] = w->rowb[c0 + u];
-    const double lki = w->Lt[i * SM + k];
-    __builtin_amdgcn_sched_barrier(0);
-    if (i < k) {
-#pragma unroll
-      for (int u = 0; u < RL::CW; ++u) x[u] = fma(-lki, rb[u], x[u]);
-    }
-  }
-  if (i < s) {
-#pragma unroll
-    for (int u = 0; u < RL::CW; ++u)
-      if (c0 + u < s) X[i * s + c0 + u] = x[u];
-  }
-  __syncthreads();
 }
 
 // X = A^-1 B (and Linv = L^-1 if not null) for SPD A, all s x s in LDS.
 template <int SM>
 __device__ __forceinline__ bool lc_cholesky_solve(const double* A, const double* B, double* X, double* Linv, int s) {
-  CholLds<SM>* w = chol_lds<SM>();
-  __syncthreads();
-  if (!lc_factor<SM>(A, s, 1.0, 0.0, w)) return false;
-  lc_forward<SM>(w, B, X, s);
-  lc_backward<SM>(w, X, X, s);
-  if (Linv) lc_forward<SM>(w, nullptr, Linv, s);
-  return true;
+  if (Linv) return mf_chol<SM, true, true, true, false>(A, s, 1.0, 0.0, B, X, Linv, nullptr);
+  return mf_chol<SM, true, false, true, false>(A, s, 1.0, 0.0, B, X, nullptr, nullptr);
 }
 
 // A = L L^T with L (zero above the diagonal) and L^-1 stored, s x s in LDS.
 template <int SM>
 __device__ __forceinline__ bool lc_cholesky_factor(const double* A, double* Lo, double* Linv, int s) {
-  CholLds<SM>* w = chol_lds<SM>();
-  __syncthreads();
-  if (!lc_factor<SM>(A, s, 1.0, 0.0, w)) return false;
-  for (int e = tid(); e < s * s; e += kSB) {
-    const int i = e / s, j = e % s;
-    Lo[e] = (j <= i) ? w->Lt[j * SM + i] : 0.0;
-  }
-  lc_forward<SM>(w, nullptr, Linv, s);
-  return true;
+  return mf_chol<SM, false, true, false, true>(A, s, 1.0, 0.0, nullptr, nullptr, Linv, Lo);
 }
 
 template <int SM>
 __device__ __forceinline__ bool lc_definite(const double* A, int s, double sa, double sh) {
-  CholLds<SM>* w = chol_lds<SM>();
+  return mf_chol<SM, false, false, false, false>(A, s, sa, sh, nullptr, nullptr, nullptr, nullptr);
+}
+
+// Power iteration (as rf_power_lmax_x) with the matrix in registers, lane
+// (q, i) holding row i, columns [q RW, q RW + RW); the iterate lives in LDS
+// (one wavefront: its LDS accesses are carried out in program order, so the
+// exchanges need no barrier).
+template <int SM>
+__device__ __forceinline__ double lc_power_lmax(const double* A, int s) {
+  using G = Seg<SM>;
+  PowLds<SM>* w = pow_lds<SM>();
+  const int t = tid(), i = t % SM, q = t / SM, c0 = q * G::RW;
+  double m[G::RW];
+#pragma unroll
+  for (int u = 0; u < G::RW; ++u) m[u] = (i < s && c0 + u < s) ? A[i * s + c0 + u] : 0.0;
+  double* xs = w->xs;
+  const double* seg = xs + q * G::ST;
   __syncthreads();
-  return lc_factor<SM>(A, s, sa, sh, w);
+  if (q == 0) xs[G::at(i)] = (i < s) ? 1.0 : 0.0;
+  __builtin_amdgcn_wave_barrier();
+  double theta = 0.0;
+  for (int it = 0; it < 64; ++it) {
+    double p = 0.0;
+#pragma unroll
+    for (int u = 0; u < G::RW; u += 2) {
+      const double2 v = ld2(seg + u);
+      p = fma(m[u], v.x, p);
+      p = fma(m[u + 1], v.y, p);
+    }
+    const double x = xs[G::at(i)];
+    w->part[t] = p;
+    __builtin_amdgcn_wave_barrier();
+    double y = 0.0;
+#pragma unroll
+    for (int h = 0; h < G::NQ; ++h) y += w->part[h * SM + i];
+    const bool mine = q == 0;
+    const double xx = wsum(mine ? x * x : 0.0), xy = wsum(mine ? x * y : 0.0), yy = wsum(mine ? y * y : 0.0);
+    const double th = xy / xx;
+    if (!(yy > 0.0) || !isfinite(yy)) {
+      __syncthreads();
+      return th;
+    }
+    if (mine) xs[G::at(i)] = y / sqrt(yy);
+    __builtin_amdgcn_wave_barrier();
+    const bool settled = it > 0 && fabs(th - theta) <= 1e-6 * fabs(th);
+    theta = th;
+    if (settled) break;
+  }
+  __syncthreads();
+  return theta;
 }
 
 // Rayleigh quotient of the power iteration for the symmetric s x s matrix A
@@ -664,7 +907,10 @@ __device__ __forceinline__ double rf_power_lmax_x(const double* A, int s) {
 }
 template <int SM>
 __device__ __forceinline__ double rf_power_lmax(const double* A, int s) {
-  return s == SM ? rf_power_lmax_x<SM, true>(A, s) : rf_power_lmax_x<SM, false>(A, s);
+  if constexpr (SM >= 16)
+    return lc_power_lmax<SM>(A, s);
+  else
+    return s == SM ? rf_power_lmax_x<SM, true>(A, s) : rf_power_lmax_x<SM, false>(A, s);
 }
 
 // The re-orthonormalisation is decided per iteration (the L^-1 bound of the
