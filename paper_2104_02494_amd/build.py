@@ -2,7 +2,7 @@
 
 Each translation unit under csrc/ is compiled with hipcc for gfx950 (in
 parallel), then linked into ``libbkry.so`` next to this file.  Packed FP32
-instructions are disabled for every HIP file.
+instructions are disabled for every HIP file; FILE_FLAGS adds per-file flags.
 """
 from __future__ import annotations
 
@@ -23,13 +23,19 @@ CFLAGS = [f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-Wall",
           "-I", os.path.join(ROOT, "include"), "-I", SRC]
 
 
+# Per-file flags.  kernels_small.hip: its blocked Cholesky reads and writes
+# single accumulator entries between matrix-core products, so the products
+# keep their accumulators in ordinary VGPRs (no copies to and from AGPRs).
+FILE_FLAGS = {"kernels_small.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
+
+
 def sources():
     return sorted(os.path.join(SRC, f) for f in os.listdir(SRC) if f.endswith(".hip"))
 
 
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.basename(src)[:-4] + ".o")
-    cmd = [HIPCC, *CFLAGS, "-c", src, "-o", obj]
+    cmd = [HIPCC, *CFLAGS, *FILE_FLAGS.get(os.path.basename(src), []), "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     err = "\n".join(l for l in (r.stderr or "").splitlines() if "packed-fp32-ops" not in l)
     if r.returncode != 0:

@@ -40,6 +40,17 @@ static hipError_t dispatch_sm(int s, F&& f) {
 
 __device__ __forceinline__ int tid() { return threadIdx.x; }
 
+// t / d and t % d for 0 <= t < 1024 and 1 <= d <= 32 by one multiply: with
+// m = ceil(2^16 / d), e = m d - 2^16 < d, t m / 2^16 = t / d + t e / (d 2^16)
+// and t e < 2^16, so the floor is t / d's (the loops over s x s entries would
+// otherwise run two integer divisions, some 40 instructions, per entry).
+struct SmDiv {
+  int d, m;
+  __device__ explicit SmDiv(int d_) : d(d_), m((65536 + d_ - 1) / d_) {}
+  __device__ int q(int t) const { return (t * m) >> 16; }
+  __device__ int r(int t) const { return t - q(t) * d; }
+};
+
 // Value of v in the lane given by the DPP control CTRL (within rows of 16).
 template <int CTRL>
 __device__ __forceinline__ double dpp_f64(double v) {
@@ -81,8 +92,28 @@ __device__ __forceinline__ void sm_copy(double* dst, const double* src, int coun
   for (int t = tid(); t < count; t += kSB) dst[t] = src[t];
 }
 
+// dst = src (count <= N entries, typically global memory into LDS) with every
+// lane's loads issued before its first store: one memory round trip instead
+// of one per kSB entries (a copy loop waits for each load before its store).
+template <int N, typename T>
+__device__ __forceinline__ void sm_fetch(T* dst, const T* src, int count) {
+  constexpr int U = (N + kSB - 1) / kSB;
+  T v[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int t = tid() + u * kSB;
+    if (u * kSB < count) v[u] = src[t < count ? t : count - 1];
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int t = tid() + u * kSB;
+    if (t < count) dst[t] = v[u];
+  }
+}
+
 __device__ __forceinline__ void sm_eye(double* M, int s) {
-  for (int t = tid(); t < s * s; t += kSB) M[t] = (t / s == t % s) ? 1.0 : 0.0;
+  const SmDiv ds(s);
+  for (int t = tid(); t < s * s; t += kSB) M[t] = (ds.q(t) == ds.r(t)) ? 1.0 : 0.0;
 }
 
 // Projection onto the subalgebra (zero outside the g x g diagonal blocks;
@@ -90,6 +121,7 @@ __device__ __forceinline__ void sm_eye(double* M, int s) {
 // diagonal block).
 __device__ __forceinline__ void sm_project(double* M, const Sub& sub, double* scratch1) {
   const int s = sub.s;
+  const SmDiv ds(s), dg(sub.g);
   __syncthreads();
   if (sub.kind == BGLOBAL) {
     // g <= s/2 <= 16: each lane owns at most 256/kSB entries of the g x g mean
@@ -101,7 +133,7 @@ __device__ __forceinline__ void sm_project(double* M, const Sub& sub, double* sc
       const int e = tid() + u * kSB;
       double acc = 0.0;
       if (e < g * g) {
-        const int a = e / g, b = e % g;
+        const int a = dg.q(e), b = dg.r(e);
         for (int k = 0; k < q; ++k) acc += M[(k * g + a) * s + k * g + b];
       }
       v[u] = acc / (double)q;
@@ -111,55 +143,80 @@ __device__ __forceinline__ void sm_project(double* M, const Sub& sub, double* sc
     for (int u = 0; u < kPer; ++u) {
       const int e = tid() + u * kSB;
       if (e < g * g) {
-        const int a = e / g, b = e % g;
+        const int a = dg.q(e), b = dg.r(e);
         for (int k = 0; k < q; ++k) M[(k * g + a) * s + k * g + b] = v[u];
       }
     }
     for (int t = tid(); t < s * s; t += kSB)
-      if ((t / s) / g != (t % s) / g) M[t] = 0.0;
+      if (dg.q(ds.q(t)) != dg.q(ds.r(t))) M[t] = 0.0;
   } else if (sub.kind == GLOBAL) {
     double d = 0.0;
     for (int a = tid(); a < s; a += kSB) d += M[a * s + a];
     const double v = wsum(d) / (double)s;
     __syncthreads();
-    for (int t = tid(); t < s * s; t += kSB) M[t] = (t / s == t % s) ? v : 0.0;
-  } else {
+    for (int t = tid(); t < s * s; t += kSB) M[t] = (ds.q(t) == ds.r(t)) ? v : 0.0;
+  } else if (sub.g < s) {  // block with g = s: nothing lies outside the one block
     for (int t = tid(); t < s * s; t += kSB)
-      if ((t / s) / sub.g != (t % s) / sub.g) M[t] = 0.0;
+      if (dg.q(ds.q(t)) != dg.q(ds.r(t))) M[t] = 0.0;
   }
   __syncthreads();
 }
 
+// FP64 16 x 16 x 4 product on the matrix cores, D = A B + C: lane l supplies
+// A[l % 16][l / 16] and B[l / 16][l % 16] and holds D[4 v + l / 16][l % 16]
+// in element v (the layout measured on gfx950).
+typedef double mf_d4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ mf_d4 mf_mma(double a, double b, mf_d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// An empty asm statement that makes x opaque to the compiler: a value used
+// only in one arm of a lane-dependent selection is then not sunk into a
+// divergent branch of its own (every lane of a wavefront would run all arms
+// in turn), and a guarded load is issued unconditionally.
+__device__ __forceinline__ void mf_opaque(double& x) { asm volatile("" : "+v"(x)); }
+
 // C = A B (transA: C = A^T B); C must not alias A or B.  Above 16 columns
-// each lane forms a 4 x 4 tile of C (8 x 8 tiles cover 32 x 32), so each
-// loaded entry of A and B serves four products; the same fused products in
-// the same (k ascending) order as the entry-per-lane form below.  Reads past
-// s stay inside the kMaxS^2 arrays and only feed entries that are not stored.
+// on the matrix cores: 2 x 2 tiles of 16 x 16, 8 steps of k each; entries
+// past s are read (they stay inside the kMaxS^2 arrays) and replaced by zero.
+// Up to 16 columns each entry of C is one lane's dot product in k order.
 __device__ __forceinline__ void sm_mm(double* C, const double* A, const double* B, int s, bool transA) {
   __syncthreads();
   if (s > 16) {
-    const int t = tid(), i0 = (t / 8) * 4, j0 = (t % 8) * 4;
-    double acc[4][4];
+    const int l = tid(), lr = l / 16, lc = l % 16;
+    mf_d4 acc[2][2];
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
+    for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
-      for (int c = 0; c < 4; ++c) acc[r][c] = 0.0;
-    for (int k = 0; k < s; ++k) {
-      double a[4], b[4];
+      for (int tj = 0; tj < 2; ++tj) acc[ti][tj] = mf_d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int r = 0; r < 4; ++r) a[r] = transA ? A[k * s + i0 + r] : A[(i0 + r) * s + k];
+    for (int kk = 0; kk < 8; ++kk) {
+      const int k = 4 * kk + lr;
+      double a[2], b[2];
 #pragma unroll
-      for (int c = 0; c < 4; ++c) b[c] = B[k * s + j0 + c];
+      for (int t = 0; t < 2; ++t) {
+        const int i = 16 * t + lc;
+        double av = transA ? A[k * s + i] : A[i * s + k], bv = B[k * s + i];
+        mf_opaque(av);
+        mf_opaque(bv);
+        a[t] = (i < s && k < s) ? av : 0.0;
+        b[t] = (i < s && k < s) ? bv : 0.0;
+      }
 #pragma unroll
-      for (int r = 0; r < 4; ++r)
+      for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) acc[r][c] = fma(a[r], b[c], acc[r][c]);
+        for (int tj = 0; tj < 2; ++tj) acc[ti][tj] = mf_mma(a[ti], b[tj], acc[ti][tj]);
     }
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
+    for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
-      for (int c = 0; c < 4; ++c)
-        if (i0 + r < s && j0 + c < s) C[(i0 + r) * s + j0 + c] = acc[r][c];
+      for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = 16 * ti + 4 * v + lr, j = 16 * tj + lc;
+          if (i < s && j < s) C[i * s + j] = acc[ti][tj][v];
+        }
     __syncthreads();
     return;
   }
@@ -500,11 +557,6 @@ __device__ __forceinline__ double2 ld2(const double* p) { return *reinterpret_ca
 // s are padded with the identity (right-hand sides with zeros), so no step
 // depends on s.  A single wavefront's LDS accesses are carried out in program
 // order, so the exchanges need no barrier.
-typedef double mf_d4 __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ mf_d4 mf_mma(double a, double b, mf_d4 c) {
-  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-}
 
 template <int SM>
 struct MfLds {
@@ -560,15 +612,20 @@ __device__ __forceinline__ void mf_diag4(const double (&d)[16], double (&L)[16],
   W[12] = -fma(L[14], W[8], fma(L[13], W[4], L[12] * r0)) * r3;
 }
 
-// Element k (0..3, this lane's) of the four values v[0..3].
-__device__ __forceinline__ double mf_pick(const double (&v)[4], int k) {
-  return k == 0 ? v[0] : (k == 1 ? v[1] : (k == 2 ? v[2] : v[3]));
+// Element k (0..3, this lane's) of the four values v[0..3], by selects (the
+// values are made opaque first, see mf_opaque).
+__device__ __forceinline__ double mf_pick(double (&v)[4], int k) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i) mf_opaque(v[i]);
+  const double lo = (k & 1) ? v[1] : v[0], hi = (k & 1) ? v[3] : v[2];
+  return (k & 2) ? hi : lo;
 }
 
 // sa A + sh I = L L^T (A: s x s in LDS); RHS: X = (sa A + sh I)^-1 B (BACK)
 // or Y = L^-1 B (no BACK) into X; INV: Linv = L^-1; LO: Lo = L (zero above the
-// diagonal).  All s x s, row-major, in LDS; X may alias B.  False (uniformly)
-// on a pivot that is not positive or not finite.
+// diagonal).  All s x s, row-major, in LDS, in arrays of at least SM x SM
+// entries (the loads are not guarded); X may alias B.  False (uniformly) on a
+// pivot that is not positive or not finite.
 template <int SM, bool RHS, bool INV, bool BACK, bool LO>
 __device__ __forceinline__ bool mf_chol(const double* A, int s, double sa, double sh, const double* B, double* X,
                                         double* Linv, double* Lo) {
@@ -587,8 +644,12 @@ __device__ __forceinline__ bool mf_chol(const double* A, int s, double sa, doubl
       if constexpr (b <= a) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
+          // the load is unconditional (r s + c < SM^2 stays inside the
+          // caller's s x s <= SM x SM array) so no load waits in a branch
           const int r = 16 * a + 4 * v + lr, c = 16 * b + lc;
-          at[a][b][v] = (r < s && c < s) ? fma(sa, A[r * s + c], r == c ? sh : 0.0) : (r == c ? 1.0 : 0.0);
+          double av = A[r * s + c];
+          mf_opaque(av);
+          at[a][b][v] = (r < s && c < s) ? fma(sa, av, r == c ? sh : 0.0) : (r == c ? 1.0 : 0.0);
         }
       }
     });
@@ -599,7 +660,9 @@ __device__ __forceinline__ bool mf_chol(const double* A, int s, double sa, doubl
         const int r = 16 * a + 4 * v + lr;
         if constexpr (cc < NR) {
           const int c = 16 * cc + lc;
-          bt[a][cc][v] = (r < s && c < s) ? B[r * s + c] : 0.0;
+          double bv = B[r * s + c];
+          mf_opaque(bv);
+          bt[a][cc][v] = (r < s && c < s) ? bv : 0.0;
         } else {
           bt[a][cc][v] = (r == 16 * (cc - NR) + lc) ? 1.0 : 0.0;
         }
@@ -675,15 +738,21 @@ __device__ __forceinline__ bool mf_chol(const double* A, int s, double sa, doubl
         }
         const int r = 16 * a + lc;
         const double trail = mf_pick(pl, lr);
-        if constexpr (a == ta) {
-          const int rr = r - 4 * K;  // 0..3 on the block's rows
+        if constexpr (a == ta && LO) {
+          // the block's own rows take L_KK as factored (only the stored L
+          // reads them)
+          const int rr = (r - 4 * K) & 3;  // the block row, on the block's rows
           double lrow[4];
 #pragma unroll
-          for (int k = 0; k < 4; ++k)
-            lrow[k] = rr == 0 ? L4[k] : (rr == 1 ? L4[4 + k] : (rr == 2 ? L4[8 + k] : L4[12 + k]));
-          lv[a] = (r < 4 * K) ? 0.0 : (r < 4 * K + 4 ? mf_pick(lrow, lr) : trail);
+          for (int k = 0; k < 4; ++k) {
+            double col[4] = {L4[k], L4[4 + k], L4[8 + k], L4[12 + k]};
+            lrow[k] = mf_pick(col, rr);
+          }
+          double x = mf_pick(lrow, lr);
+          x = (r >= 4 * K + 4) ? trail : x;
+          lv[a] = (r < 4 * K) ? 0.0 : x;
         } else {
-          lv[a] = trail;
+          lv[a] = (a == ta && r < 4 * K) ? 0.0 : trail;
         }
         op[a] = (r < 4 * K + 4) ? 0.0 : trail;
       }
@@ -803,8 +872,9 @@ __device__ __forceinline__ bool mf_chol(const double* A, int s, double sa, doubl
   }
   if constexpr (LO) {
     __syncthreads();
+    const SmDiv ds(s);
     for (int e = tid(); e < s * s; e += kSB) {
-      const int i = e / s, j = e % s;
+      const int i = ds.q(e), j = ds.r(e);
       Lo[e] = (j <= i) ? w->Ls[i * (SM + 1) + j] : 0.0;
     }
   }
@@ -944,23 +1014,32 @@ __device__ __forceinline__ bool reortho_test(CgCtl* c, const double* alpha, doub
   //   below: lambda_max >= max(1, 1^T M 1 / s) (unit diagonal, Rayleigh
   //          quotient) and 1 / lambda_min >= max_i (M^-1)_ii.
   // The eigenvalues are computed only when the bounds leave the decision open.
+  // (rc, rs: the square roots of alpha's diagonal and their reciprocals; the
+  // slack of 1e-12 in the tests below covers the few roundings of each entry)
+  const int t = tid();
+  for (int i = t; i < s; i += kSB) {
+    const double si = sqrt(alpha[i * s + i]);
+    rc[i] = si;
+    rs[i] = 1.0 / si;
+  }
+  __syncthreads();
   double fm = 0.0, li = 0.0;
-  for (int e = tid(); e < s * s; e += kSB) {
-    const int i = e / s, j = e % s;
-    const double a = alpha[e];
-    fm += a * a / (alpha[i * s + i] * alpha[j * s + j]);
-    li += T[e] * T[e] * alpha[j * s + j];
+  const SmDiv ds(s);
+  for (int e = t; e < s * s; e += kSB) {
+    const int i = ds.q(e), j = ds.r(e);
+    const double m = alpha[e] * rs[i] * rs[j], u = T[e] * rc[j];
+    fm += m * m;
+    li += u * u;
   }
   double rowM = 0.0, sumM = 0.0, rowL = 0.0, colL = 0.0, dinv = 0.0;
-  const int t = tid();
   if (t < s) {
-    const double at = alpha[t * s + t], st = sqrt(at);
+    const double st = rc[t], rt = rs[t];
+#pragma unroll 4
     for (int j = 0; j < s; ++j) {
-      const double aj = alpha[j * s + j], sj = sqrt(aj);
-      const double mtj = alpha[t * s + j] / (st * sj);
+      const double mtj = alpha[t * s + j] * rt * rs[j];
       rowM += fabs(mtj);
       sumM += mtj;
-      rowL += fabs(T[t * s + j] * sj);  // row t of L_M^-1
+      rowL += fabs(T[t * s + j] * rc[j]);  // row t of L_M^-1
       const double ljt = T[j * s + t] * st;  // column t of L_M^-1
       colL += fabs(ljt);
       dinv += ljt * ljt;
@@ -979,8 +1058,8 @@ __device__ __forceinline__ bool reortho_test(CgCtl* c, const double* alpha, doub
   // (does not fire).  Only a lambda_min between the two shifts is left to
   // the eigenvalues.
   for (int e = tid(); e < s * s; e += kSB) {
-    const int i = e / s, j = e % s;
-    M[e] = alpha[e] / sqrt(alpha[i * s + i] * alpha[j * s + j]);
+    const int i = ds.q(e), j = ds.r(e);
+    M[e] = alpha[e] * rs[i] * rs[j];
   }
   __syncthreads();
   const double theta = rf_power_lmax<SM>(M, s), mu = theta * (1.0 + 1e-3);
@@ -1104,11 +1183,10 @@ __device__ __forceinline__ void cg_alpha_body(CgCtl* c, const double* G, const d
   // its lambda sigma; this iteration's update then adds both, otherwise it
   // defers its own term
   const int xin = c->xdef_pend;
-  if (xin)
-    for (int t = tid(); t < s * s; t += kSB) {
-      c->lamsig_prev[t] = c->lamsig[t];
-      c->lamsig_prev_f[t] = c->lamsig_f[t];
-    }
+  if (xin) {
+    sm_fetch<kSS>(c->lamsig_prev, c->lamsig, s * s);
+    sm_fetch<kSS>(c->lamsig_prev_f, c->lamsig_f, s * s);
+  }
   __syncthreads();
   if (tid() == 0) {
     c->xdef_in = xin;
@@ -1169,6 +1247,7 @@ __device__ __forceinline__ void cg_rho_body(CgCtl* c, const double* G, double* h
   bool nanl = false;
   for (int i = tid(); i < s; i += kSB) {
     double acc = 0.0;
+#pragma unroll 8
     for (int a = 0; a < s; ++a) acc += Sg[a * s + i] * T1[a * s + i];
     const double cn = sqrt(fmax(acc, 0.0));
     const double r = r0n_l[i] > 0.0 ? cn / r0n_l[i] : 0.0;
@@ -1307,7 +1386,7 @@ __device__ __forceinline__ void cg1r_body(CgCtl* c, const double* G, double* his
   if (!all_finite(Al, ss, red)) return fail(-3);
   if (!rf_cholesky_solve<SM>(Al, Rh, Lm, reortho_dynamic(c) ? Tt : nullptr, s)) return fail(-2);
   sm_mm(T1, Lm, sigma_l, s, false);  // lambda sigma
-  for (int t = tid(); t < ss; t += kSB) c->lamsig_prev[t] = c->lamsig[t];
+  sm_fetch<kSS>(c->lamsig_prev, c->lamsig, ss);
   store_coeff(c->lam, c->lam_f, Lm, s);
   store_coeff(c->lamsig, c->lamsig_f, T1, s);
   store_coeff(c->beta, c->beta_f, Bt, s);
@@ -1398,12 +1477,9 @@ __global__ __launch_bounds__(EPI == EPI_NONE ? kRedPlain : kSB) void reduce_kern
   if constexpr (EPI != EPI_NONE) {
     // the epilogue's inputs from the control block, loaded along with the
     // partials (only the last workgroup uses them)
-    for (int t = tid(); t < ss; t += kSB) {
-      pre_rho[t] = c->rho[t];
-      pre_sig[t] = c->sigma[t];
-    }
-    if constexpr (NORMS)
-      for (int t = tid(); t < s; t += kSB) pre_r0n[t] = c->r0n[t];
+    sm_fetch<SM * SM>(pre_rho, c->rho, ss);
+    sm_fetch<SM * SM>(pre_sig, c->sigma, ss);
+    if constexpr (NORMS) sm_fetch<SM>(pre_r0n, c->r0n, s);
   }
   if constexpr (EPI == EPI_CG_ALPHA) {
     if (c->done) {  // ended: nothing of this iteration reaches X (owed terms were added)
@@ -1471,12 +1547,10 @@ __global__ __launch_bounds__(kSB) void cg_epi_kernel(const double* G, CgCtl* c, 
   }
   if (c->gate) return;
   const int s = c->s, ss = s * s;
-  for (int t = tid(); t < ss; t += kSB) {
-    pre_rho[t] = c->rho[t];
-    pre_sig[t] = c->sigma[t];
-  }
-  for (int t = tid(); t < s; t += kSB) pre_r0n[t] = c->r0n[t];
-  for (int e = tid(); e < NG * ss; e += kSB) Gl[e] = G[e];
+  sm_fetch<kSS>(pre_rho, c->rho, ss);
+  sm_fetch<kSS>(pre_sig, c->sigma, ss);
+  sm_fetch<kMaxS>(pre_r0n, c->r0n, s);
+  sm_fetch<NG * kSS>(Gl, G, NG * ss);
   __syncthreads();
   if constexpr (EPI == EPI_CG_ALPHA) {
     cg_alpha_body<SM>(c, Gl, pre_rho, pre_sig);
@@ -1765,6 +1839,7 @@ __global__ __launch_bounds__(kSB) void bc_stop_kernel(CgCtl* c, const double* Gr
   bool nanl = false;
   for (int i = tid(); i < s; i += kSB) {
     double acc = 0.0;
+#pragma unroll 8
     for (int a = 0; a < s; ++a) acc += Sg[a * s + i] * T1[a * s + i];
     const double r = c->r0n[i] > 0.0 ? sqrt(fmax(acc, 0.0)) / c->r0n[i] : 0.0;
     nanl |= !isfinite(acc);
