@@ -480,6 +480,57 @@ def copy_probe():
     print(json.dumps({"copy_probe_bytes_read": n * 8, "copy_probe_bytes_written": n * 8}))
 
 
+PROFILE_WORKLOADS = ("cg32", "ir96", "tsqr", "gmres")
+
+
+def profile_run(which):
+    """Two runs of one workload, for kernel traces (rocprofv3 --kernel-trace):
+    cg32   block CG, 64^3 variable-coefficient problem, 32 right-hand sides;
+    ir96   FP64 block CG and FP32-inner IR, 27-point 96^3 problem, 16 right-hand sides;
+    tsqr   the normaliser of a 4,194,304 x 32 Gaussian block (six calls);
+    gmres  two GMRes(30) cycles on the 1024^2 convection-diffusion problem,
+           classical Gram-Schmidt twice, then the pipelined form (window 3)."""
+    import torch
+    import paper_2104_02494_amd as P
+    import workloads as W
+    h = P.Handle(0)
+
+    def dev(name):
+        A, B, _ = W.build_workload(name)
+        return P.CsrMatrix.from_numpy(A.n, A.rowptr, A.colind, A.val), torch.as_tensor(B).cuda()
+    if which == "cg32":
+        Ad, Bd = dev("diffusion7var_64_s32")
+        for r in range(2):
+            _, info = P.bkry_cg_solve(h, Ad, Bd, tol=1e-10, maxit=5000, eta=1e4)
+            log("profile cg32", r, info["iters"], info["reorth"], round(info["seconds"], 4))
+    elif which == "ir96":
+        Ad, Bd = dev("diffusion27_96_s16")
+        for r in range(2):
+            _, i64 = P.bkry_cg_solve(h, Ad, Bd, tol=1e-10, maxit=20000, eta=1e4)
+            _, i32 = P.bkry_cg_solve(h, Ad, Bd, tol=1e-10, maxit=20000, eta=1.0, prec=P.F32_IR)
+            log("profile ir96", r, "fp64", i64["iters"], round(i64["seconds"], 4), "ir", i32["outer_iters"],
+                i32["iters"], round(i32["seconds"], 4))
+    elif which == "tsqr":
+        Xt = torch.as_tensor(W.tsqr_input()).cuda()
+        Xw = torch.empty_like(Xt)
+        for r in range(6):
+            Xw.copy_(Xt)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            P.bkry_tsqr(h, Xw, "block")
+            torch.cuda.synchronize()
+            log("profile tsqr", r, round((time.perf_counter() - t0) * 1e3, 3), "ms")
+    elif which == "gmres":
+        Ad, Bd = dev("convdiff2d_1024_s8")
+        for r in range(2):
+            _, info = P.bkry_gmres_solve(h, Ad, Bd, tol=0.0, maxit=60, restart=30)
+            log("profile gmres", r, info["iters"], round(info["seconds"], 4))
+        for r in range(2):
+            _, info = P.bkry_gmres_pipelined_solve(h, Ad, Bd, 3, tol=0.0, maxit=60, restart=30)
+            log("profile gmres pipelined", r, info["iters"], round(info["seconds"], 4))
+    h.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -490,6 +541,8 @@ def main():
     ap.add_argument("--extras", dest="extras", action="store_true", default=True)
     ap.add_argument("--no-extras", dest="extras", action="store_false")
     ap.add_argument("--copy-probe", action="store_true")
+    ap.add_argument("--profile", choices=PROFILE_WORKLOADS, default=None,
+                    help="run one workload twice for a kernel trace and exit (no JSON line)")
     ap.add_argument("--solver", choices=["cg", "cg1r"], default="cg",
                     help="block CG of the timed solves: two reductions per iteration (default) or one")
     args = ap.parse_args()
@@ -500,6 +553,9 @@ def main():
         sys.exit(2)
     if args.copy_probe:
         copy_probe()
+        return
+    if args.profile:
+        profile_run(args.profile)
         return
     run(args)
 

@@ -350,7 +350,8 @@ hipError_t launch_project_batched(const double* G, double* out, Sub sub, int bat
                                   hipStream_t st);
 hipError_t launch_ir_check(int s, const double* G, double* r0n, double* scale, double* relres, int32_t* flag,
                            double tol, int first, hipStream_t st);
-hipError_t launch_gm_backsub(GmCtl* ctl, const double* H, const double* sig, double* zeta, hipStream_t st);
+hipError_t launch_gm_backsub(GmCtl* ctl, int s, int kend, const double* H, const double* sig, double* zeta,
+                             hipStream_t st);
 hipError_t launch_gm_cycle_init(GmCtl* ctl, double* sig, const double* sigma0, const double* G_R,
                                 int first_cycle, hipStream_t st);
 

@@ -40,10 +40,11 @@ static hipError_t dispatch_sm(int s, F&& f) {
 
 __device__ __forceinline__ int tid() { return threadIdx.x; }
 
-// t / d and t % d for 0 <= t < 1024 and 1 <= d <= 32 by one multiply: with
-// m = ceil(2^16 / d), e = m d - 2^16 < d, t m / 2^16 = t / d + t e / (d 2^16)
-// and t e < 2^16, so the floor is t / d's (the loops over s x s entries would
-// otherwise run two integer divisions, some 40 instructions, per entry).
+// t / d and t % d for 0 <= t < 2048 and 1 <= d <= 32 by one multiply: with
+// m = ceil(2^16 / d), e = m d - 2^16 <= d - 1, t m / 2^16 = t / d + t e / (d
+// 2^16) and t e <= 2047 * 31 < 2^16, so the floor is t / d's (the loops over
+// s x s entries would otherwise run two integer divisions, some 40
+// instructions, per entry).
 struct SmDiv {
   int d, m;
   __device__ explicit SmDiv(int d_) : d(d_), m((65536 + d_ - 1) / d_) {}
@@ -1215,11 +1216,13 @@ __device__ __forceinline__ void cg_alpha_body(CgCtl* c, const double* G, const d
     return;
   }
   sm_mm(LS, Lm, sigma_l, s, false);  // lambda sigma
+  // the coefficients go to global memory after the kappa_D test: a workgroup
+  // barrier after a global store waits for the store
+  const bool fire = reortho_test<SM>(c, Al, W, T, rc, rs, partner, first, red);
+  __syncthreads();
   store_coeff(c->lam, c->lam_f, Lm, s);
   store_coeff(c->lamsig, c->lamsig_f, LS, s);
   sm_copy(c->alpha, Al, s * s);
-  const bool fire = reortho_test<SM>(c, Al, W, T, rc, rs, partner, first, red);
-  __syncthreads();
   if (tid() == 0) {
     c->fire = fire ? 1 : 0;
     c->x_pending = 1;
@@ -1386,14 +1389,15 @@ __device__ __forceinline__ void cg1r_body(CgCtl* c, const double* G, double* his
   if (!all_finite(Al, ss, red)) return fail(-3);
   if (!rf_cholesky_solve<SM>(Al, Rh, Lm, reortho_dynamic(c) ? Tt : nullptr, s)) return fail(-2);
   sm_mm(T1, Lm, sigma_l, s, false);  // lambda sigma
+  // global stores after the kappa_D test (see cg_alpha_body)
+  const bool fire = reortho_test<SM>(c, Al, W, Tt, rc, rs, partner, first, red);
+  __syncthreads();
   sm_fetch<kSS>(c->lamsig_prev, c->lamsig, ss);
   store_coeff(c->lam, c->lam_f, Lm, s);
   store_coeff(c->lamsig, c->lamsig_f, T1, s);
   store_coeff(c->beta, c->beta_f, Bt, s);
   sm_copy(c->alpha, Al, ss);
   sm_copy(c->rho, Rh, ss);
-  const bool fire = reortho_test<SM>(c, Al, W, Tt, rc, rs, partner, first, red);
-  __syncthreads();
   if (tid() == 0) {
     c->fire = fire ? 1 : 0;
     c->lam_iter = k;
@@ -1570,13 +1574,55 @@ static int reduce_slices(int nblk) {
   return ns;
 }
 
+// Plain reduction of partials of m >= 64 entries (s x s Grams from s = 8
+// up): workgroup (x, y) owns entries [x kWideE, x kWideE + kWideE) of
+// batch slice y, its threads being kWideE entries x kWideL partial lanes;
+// lane q sums the partials q, q + kWideL, ... in order (one batch of loads
+// for up to 32 of them), and the kWideL lane sums are added in lane order
+// into red.G.  Every workgroup writes its own entries, so there is no
+// hand-off between workgroups; the summation order is fixed, so the result
+// is deterministic.  Gated like the plain form of reduce_kernel.
+constexpr int kWideE = 16, kWideL = kRedPlain / kWideE;
+
+template <typename T>
+__global__ __launch_bounds__(kRedPlain) void reduce_wide_kernel(int m, const T* __restrict__ partial, int nblk,
+                                                                 Red red, const int32_t* gate, const int32_t* fire) {
+  __shared__ double part[kRedPlain];
+  if ((gate && *gate) || (fire && !*fire)) return;
+  const int y = blockIdx.y, x = threadIdx.x % kWideE, q = threadIdx.x / kWideE;
+  const int e = blockIdx.x * kWideE + x;
+  const T* P = partial + (int64_t)y * nblk * m;
+  double acc = 0.0;
+  if (e < m && q < nblk) acc = sum_strided<T>(P + (int64_t)q * m + e, (int64_t)kWideL * m, (nblk - q + kWideL - 1) / kWideL);
+  part[threadIdx.x] = acc;
+  __syncthreads();
+  if (q == 0 && e < m) {
+    double v = 0.0;
+#pragma unroll
+    for (int k = 0; k < kWideL; ++k) v += part[k * kWideE + x];
+    red.G[(int64_t)y * m + e] = v;
+  }
+}
+
+template <typename T>
+static void launch_reduce_plain(int m, const T* partial, int nblk, int batch, Red red, const int32_t* gate,
+                                const int32_t* fire, int s, int ng, hipStream_t st) {
+  if (m >= 64) {
+    hipLaunchKernelGGL(reduce_wide_kernel<T>, dim3((m + kWideE - 1) / kWideE, batch), dim3(kRedPlain), 0, st, m,
+                       partial, nblk, red, gate, fire);
+  } else {
+    dim3 grid(reduce_slices(nblk), batch);
+    hipLaunchKernelGGL((reduce_kernel<T, EPI_NONE, 8>), grid, dim3(kRedPlain), 0, st, s, partial, nblk, red, gate,
+                       fire, nullptr, nullptr, ng);
+  }
+}
+
 template <typename T>
 static hipError_t launch_reduce_t(int s, const T* partial, int nblk, int batch, Red red, const int32_t* gate,
                                   const int32_t* fire, Epi epi, hipStream_t st) {
   dim3 grid(reduce_slices(nblk), batch);
   if (epi.kind == EPI_NONE) {
-    hipLaunchKernelGGL((reduce_kernel<T, EPI_NONE, 8>), grid, dim3(kRedPlain), 0, st, s, partial, nblk, red, gate, fire,
-                       epi.ctl, epi.hist, 1);
+    launch_reduce_plain<T>(s * s, partial, nblk, batch, red, gate, fire, s, 1, st);
     return hipGetLastError();
   }
   if (batch != 1 || !epi.ctl ||
@@ -1587,8 +1633,7 @@ static hipError_t launch_reduce_t(int s, const T* partial, int nblk, int batch, 
     // wide Grams: plain reduction (gated like the epilogue), then the
     // coefficient step in its own single-wavefront launch
     const int ng = (epi.kind == EPI_CG_RHO_M || epi.kind == EPI_CG_1R) ? 2 : 1;
-    hipLaunchKernelGGL((reduce_kernel<T, EPI_NONE, 8>), grid, dim3(kRedPlain), 0, st, s, partial, nblk, red,
-                       &epi.ctl->gate, nullptr, nullptr, nullptr, ng);
+    launch_reduce_plain<T>(ng * s * s, partial, nblk, 1, red, &epi.ctl->gate, nullptr, s, ng, st);
     if (epi.kind == EPI_CG_ALPHA)
       hipLaunchKernelGGL((cg_epi_kernel<EPI_CG_ALPHA, 32>), dim3(1), dim3(kSB), 0, st, red.G, epi.ctl, epi.hist);
     else if (epi.kind == EPI_CG_RHO)
@@ -2066,45 +2111,68 @@ hipError_t launch_bg_expand(const double* rho, Sub sub, double* N, double* d, co
 // Full QR of the rows x cols matrix M (row stride cols, rows <= 64) by
 // Householder reflections: R in the upper triangle of M, the full rows x rows
 // orthogonal Q (row stride rows) with M_in = Q [R; 0].
+template <int SM>
 __device__ __forceinline__ void sm_house_full(double* M, int rows, int cols, double* Q, double* beta) {
+  // rows <= 2 SM <= kSB (lane t holds row t of the reflected column), cols <= SM
+  constexpr int RM = 2 * SM;
+  const int t = tid();
   for (int j = 0; j < cols; ++j) {
     __syncthreads();
-    if (tid() == 0) {
-      const double x1 = M[j * cols + j];
-      double sig = 0.0;
-      for (int i = j + 1; i < rows; ++i) sig += M[i * cols + j] * M[i * cols + j];
-      if (sig == 0.0) {
-        beta[j] = 0.0;
-      } else {
-        const double mu = sqrt(x1 * x1 + sig);
-        const double v1 = (x1 <= 0.0) ? (x1 - mu) : (-sig / (x1 + mu));
-        beta[j] = 2.0 * v1 * v1 / (sig + v1 * v1);
-        for (int i = j + 1; i < rows; ++i) M[i * cols + j] /= v1;
-        M[j * cols + j] = mu;
-      }
+    const double xi = (t > j && t < rows) ? M[t * cols + j] : 0.0;
+    const double sig = wsum(xi * xi);
+    const double x1 = M[j * cols + j];
+    double b = 0.0, v1 = 1.0, mu = 0.0;
+    if (sig != 0.0) {
+      mu = sqrt(x1 * x1 + sig);
+      v1 = (x1 <= 0.0) ? (x1 - mu) : (-sig / (x1 + mu));
+      b = 2.0 * v1 * v1 / (sig + v1 * v1);
     }
     __syncthreads();
-    const double b = beta[j];
+    if (sig != 0.0) {
+      if (t > j && t < rows) M[t * cols + j] = xi / v1;
+      if (t == j) M[j * cols + j] = mu;
+    }
+    if (t == 0) beta[j] = b;
+    __syncthreads();
     if (b != 0.0) {
-      for (int cc = j + 1 + tid(); cc < cols; cc += kSB) {
+      for (int cc = j + 1 + t; cc < cols; cc += kSB) {
         double w = M[j * cols + cc];
-        for (int i = j + 1; i < rows; ++i) w += M[i * cols + j] * M[i * cols + cc];
+#pragma unroll
+        for (int i = 1; i < RM; ++i) {
+          const int r = j + i;
+          if (r < rows) w += M[r * cols + j] * M[r * cols + cc];
+        }
         M[j * cols + cc] -= b * w;
-        for (int i = j + 1; i < rows; ++i) M[i * cols + cc] -= b * M[i * cols + j] * w;
+#pragma unroll
+        for (int i = 1; i < RM; ++i) {
+          const int r = j + i;
+          if (r < rows) M[r * cols + cc] -= b * M[r * cols + j] * w;
+        }
       }
     }
   }
   __syncthreads();
-  for (int t = tid(); t < rows * rows; t += kSB) Q[t] = (t / rows == t % rows) ? 1.0 : 0.0;
+  for (int e = t; e < rows * rows; e += kSB) Q[e] = 0.0;
+  __syncthreads();
+  if (t < rows) Q[t * rows + t] = 1.0;
   for (int j = cols - 1; j >= 0; --j) {
     __syncthreads();
     const double b = beta[j];
     if (b == 0.0) continue;
-    for (int cc = tid(); cc < rows; cc += kSB) {
+    if (t < rows) {
+      const int cc = t;
       double w = Q[j * rows + cc];
-      for (int i = j + 1; i < rows; ++i) w += M[i * cols + j] * Q[i * rows + cc];
+#pragma unroll
+      for (int i = 1; i < RM; ++i) {
+        const int r = j + i;
+        if (r < rows) w += M[r * cols + j] * Q[r * rows + cc];
+      }
       Q[j * rows + cc] -= b * w;
-      for (int i = j + 1; i < rows; ++i) Q[i * rows + cc] -= b * M[i * cols + j] * w;
+#pragma unroll
+      for (int i = 1; i < RM; ++i) {
+        const int r = j + i;
+        if (r < rows) Q[r * rows + cc] -= b * M[r * cols + j] * w;
+      }
     }
   }
   __syncthreads();
@@ -2112,6 +2180,7 @@ __device__ __forceinline__ void sm_house_full(double* M, int rows, int cols, dou
 
 // [x; y] <- Om^T [x; y] for S-elements x, y (s x s, row stride s), Om the
 // per-group 2g x 2g factors stored consecutively.
+template <int SM>
 __device__ __forceinline__ void sm_apply_givens_T(const double* Om, double* x, double* y, int s, int g, double* tmp) {
   const int ngrp = s / g, m2 = 2 * g;
   __syncthreads();
@@ -2120,9 +2189,12 @@ __device__ __forceinline__ void sm_apply_givens_T(const double* Om, double* x, d
     const double* O = Om + (int64_t)grp * m2 * m2;
     const int o = grp * g;
     double acc = 0.0;
-    for (int k = 0; k < m2; ++k) {
-      const double col = k < g ? x[(o + k) * s + o + cc] : y[(o + k - g) * s + o + cc];
-      acc += O[k * m2 + i] * col;
+#pragma unroll
+    for (int k = 0; k < 2 * SM; ++k) {
+      if (k < m2) {
+        const double col = k < g ? x[(o + k) * s + o + cc] : y[(o + k - g) * s + o + cc];
+        acc += O[k * m2 + i] * col;
+      }
     }
     tmp[e] = acc;
   }
@@ -2169,30 +2241,84 @@ hipError_t launch_gm_cycle_init(GmCtl* ctl, double* sig, const double* sigma0, c
 
 // Step k of a cycle: the new Hessenberg column h_jk = H1_j + H2_j (the two
 // Gram-Schmidt passes) for j <= k and gamma = h_{k+1,k}.
+// Rotations staged in LDS at once (width <= 8, k <= kGmStage): the factor of
+// each previous rotation and the next block, kGmStage x (4 g^2 + s^2) <= 40 x
+// 320 entries.
+constexpr int kGmStage = 40;
+
 template <int SM>
 __global__ __launch_bounds__(kSB) void gm_step_kernel(GmCtl* c, int k, double* H, double* sig, double* Om,
                                                        const double* H1, const double* H2, const double* gamma,
                                                        double* hist) {
-  __shared__ double Qf[4 * kMaxS * kMaxS], tmp[2 * kMaxS * kMaxS], gm[kSS], xs[kSS], ys[kSS];
-  __shared__ double beta[kMaxS];
+  constexpr int NO = 4 * SM * SM;  // entries of one rotation's factors (ngrp m2^2 <= (2 SM)^2)
+  constexpr bool STAGE = SM <= 8;
+  __shared__ double Qf[NO], tmp[2 * SM * SM], gm[SM * SM], xs[SM * SM], ys[SM * SM];
+  __shared__ double stage[STAGE ? kGmStage * (NO + SM * SM) : 1];
+  // staged: the rotated blocks j < k of the new column, written to H once
+  // after the rotations (a workgroup barrier after a global store waits for
+  // the store, which would expose one memory round trip per rotation)
+  __shared__ double hrot[STAGE ? kGmStage * SM * SM : 1];
+  __shared__ double beta[SM];
   double* M = tmp;  // the Householder input is not live while rotations use tmp
   if (c->done) return;
   const int s = c->s, g = c->g, m = c->m, ss = s * s, ngrp = s / g, m2 = 2 * g;
   const int t0 = tid();
-  for (int t = t0; t < (k + 1) * ss; t += kSB) {
-    const int j = t / ss, e = t % ss;
-    H[((int64_t)j * m + k) * ss + e] = H1[t] + H2[t];
+  const int no = ngrp * m2 * m2, ne = ngrp * m2 * g;
+  const bool staged = STAGE && k <= kGmStage;
+  // The new column, h_jk = H1_j + H2_j for j <= k (blocks j < k are replaced
+  // by their rotated values below); with staging, also every previous
+  // rotation's factor and block j + 1 of the new column into LDS.  Loads in
+  // chunks of 8 per lane, all issued before the chunk's stores.
+  {
+    constexpr int U = 8;
+    const int total = (k + 1) * ss;
+    for (int base = 0; base < total; base += U * kSB) {
+      double v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int t = base + t0 + u * kSB;
+        v[u] = t < total ? H1[t] + H2[t] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int t = base + t0 + u * kSB;
+        if (t < total) {
+          const int j = t / ss, e = t - j * ss;
+          H[((int64_t)j * m + k) * ss + e] = v[u];
+          if (staged && j >= 1) stage[(j - 1) * (NO + SM * SM) + NO + e] = v[u];
+        }
+      }
+    }
+    if (staged) {
+      const int tot = k * no;
+      for (int base = 0; base < tot; base += U * kSB) {
+        double v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int t = base + t0 + u * kSB;
+          v[u] = t < tot ? Om[t] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int t = base + t0 + u * kSB;
+          if (t < tot) {
+            const int j = t / no, e = t - j * no;
+            stage[j * (NO + SM * SM) + e] = v[u];
+          }
+        }
+      }
+    }
   }
   sm_copy(gm, gamma, ss);
   for (int e = t0; e < ss; e += kSB) xs[e] = H1[e] + H2[e];
   // Rotations of the previous steps, j = 0 .. k-1: x carries block j of the
-  // new column, y receives block j+1.  The factor of rotation j+1 and block
-  // j+2 are loaded into registers while rotation j is applied, so memory
-  // latency is exposed about once per step instead of once per rotation.
-  constexpr int RO = (4 * SM * SM + kSB - 1) / kSB;  // factor entries per lane (m2 = 2g <= 2s)
-  constexpr int RS = (SM * SM + kSB - 1) / kSB;      // block entries per lane
+  // new column, y receives block j+1.  Unstaged, the factor of rotation j+1
+  // and block j+2 are loaded into registers while rotation j is applied, so
+  // memory latency is exposed about once per rotation.
+  constexpr int RO = (NO + kSB - 1) / kSB;       // factor entries per lane (m2 = 2g <= 2s)
+  constexpr int RS = (SM * SM + kSB - 1) / kSB;  // block entries per lane
   constexpr int RN = (2 * SM * SM + kSB - 1) / kSB;  // rotated entries per lane
-  const int no = ngrp * m2 * m2, ne = ngrp * m2 * g;
+  const SmDiv dg(g);
   double opre[RO], ypre[RS];
   auto load_next = [&](int j) {
 #pragma unroll
@@ -2206,34 +2332,46 @@ __global__ __launch_bounds__(kSB) void gm_step_kernel(GmCtl* c, int k, double* H
       ypre[r] = (j < k && e < ss) ? H1[(int64_t)(j + 1) * ss + e] + H2[(int64_t)(j + 1) * ss + e] : 0.0;
     }
   };
-  load_next(0);
+  if (!staged) load_next(0);
   for (int j = 0; j < k; ++j) {
     __syncthreads();
+    const double* O0 = Qf;
+    const double* Y = ys;
+    if (staged) {
+      O0 = stage + j * (NO + SM * SM);
+      Y = O0 + NO;
+    } else {
 #pragma unroll
-    for (int r = 0; r < RO; ++r) {
-      const int e = t0 + r * kSB;
-      if (e < no) Qf[e] = opre[r];
-    }
+      for (int r = 0; r < RO; ++r) {
+        const int e = t0 + r * kSB;
+        if (e < no) Qf[e] = opre[r];
+      }
 #pragma unroll
-    for (int r = 0; r < RS; ++r) {
-      const int e = t0 + r * kSB;
-      if (e < ss) ys[e] = ypre[r];
+      for (int r = 0; r < RS; ++r) {
+        const int e = t0 + r * kSB;
+        if (e < ss) ys[e] = ypre[r];
+      }
+      __syncthreads();
+      load_next(j + 1);
     }
-    __syncthreads();
-    load_next(j + 1);
     double out[RN];
 #pragma unroll
     for (int r = 0; r < RN; ++r) {
       const int e = t0 + r * kSB;
       out[r] = 0.0;
       if (e < ne) {
-        const int grp = e / (m2 * g), rem = e % (m2 * g), i = rem / g, cc = rem % g;
-        const double* O = Qf + grp * m2 * m2;
+        const int ge = dg.q(e), grp = dg.q(ge) / 2, i = ge - grp * m2, cc = e - ge * g;
+        const double* O = O0 + grp * m2 * m2;
         const int o = grp * g;
         double acc = 0.0;
-        for (int q = 0; q < m2; ++q) {
-          const double col = q < g ? xs[(o + q) * s + o + cc] : ys[(o + q - g) * s + o + cc];
-          acc += O[q * m2 + i] * col;
+        // compile-time trip count (m2 <= 2 SM): every LDS load of the
+        // product is issued before the first add instead of one per add
+#pragma unroll
+        for (int q = 0; q < 2 * SM; ++q) {
+          if (q < m2) {
+            const double col = q < g ? xs[(o + q) * s + o + cc] : Y[(o + q - g) * s + o + cc];
+            acc += O[q * m2 + i] * col;
+          }
         }
         out[r] = acc;
       }
@@ -2243,13 +2381,26 @@ __global__ __launch_bounds__(kSB) void gm_step_kernel(GmCtl* c, int k, double* H
     for (int r = 0; r < RN; ++r) {
       const int e = t0 + r * kSB;
       if (e < ne) {
-        const int grp = e / (m2 * g), rem = e % (m2 * g), i = rem / g, cc = rem % g;
+        const int ge = dg.q(e), grp = dg.q(ge) / 2, i = ge - grp * m2, cc = e - ge * g;
         const int o = grp * g;
-        if (i < g)
-          H[((int64_t)j * m + k) * ss + (o + i) * s + o + cc] = out[r];
-        else
+        if (i >= g)
           xs[(o + i - g) * s + o + cc] = out[r];
+        else if (staged)
+          hrot[j * SM * SM + (o + i) * s + o + cc] = out[r];
+        else
+          H[((int64_t)j * m + k) * ss + (o + i) * s + o + cc] = out[r];
       }
+    }
+  }
+  if (staged) {
+    __syncthreads();
+    // blocks j < k of the new column: the rotated group entries (the rest of
+    // each block keeps the value written above)
+    for (int t = t0; t < k * ne; t += kSB) {
+      const int j = t / ne, e = t - j * ne;
+      const int ge = dg.q(e), grp = dg.q(ge) / 2, i = ge - grp * m2, cc = e - ge * g;
+      const int o = grp * g;
+      if (i < g) H[((int64_t)j * m + k) * ss + (o + i) * s + o + cc] = hrot[j * SM * SM + (o + i) * s + o + cc];
     }
   }
   __syncthreads();
@@ -2282,7 +2433,7 @@ __global__ __launch_bounds__(kSB) void gm_step_kernel(GmCtl* c, int k, double* H
         const int i = t / g, cc = t % g;
         M[t] = i < g ? xs[(o + i) * s + o + cc] : gm[(o + i - g) * s + o + cc];
       }
-      sm_house_full(M, m2, g, Qf, beta);
+      sm_house_full<SM>(M, m2, g, Qf, beta);
       for (int t = tid(); t < m2 * m2; t += kSB) Omk[grp * m2 * m2 + t] = Qf[t];
       for (int t = tid(); t < g * g; t += kSB) {
         const int i = t / g, cc = t % g;
@@ -2291,25 +2442,36 @@ __global__ __launch_bounds__(kSB) void gm_step_kernel(GmCtl* c, int k, double* H
     }
   }
   __syncthreads();
-  sm_apply_givens_T(Omk, sig + (int64_t)k * ss, sig + (int64_t)(k + 1) * ss, s, g, tmp);
-  if (tid() == 0) {
-    const double* sk = sig + (int64_t)(k + 1) * ss;
-    double meas = 0.0;
-    bool nan = false;
+  // sigma_k and sigma_{k+1} are rotated in LDS (xs and ys are free by now)
+  sm_fetch<SM * SM>(xs, sig + (int64_t)k * ss, ss);
+  sm_fetch<SM * SM>(ys, sig + (int64_t)(k + 1) * ss, ss);
+  sm_apply_givens_T<SM>(Omk, xs, ys, s, g, tmp);
+  for (int e = t0; e < ss; e += kSB) {
+    sig[(int64_t)k * ss + e] = xs[e];
+    sig[(int64_t)(k + 1) * ss + e] = ys[e];
+  }
+  // residual measure from sigma_{k+1}: column norms (lane i: column i), or
+  // the Frobenius norm for the global subalgebras
+  double meas;
+  bool nan;
+  {
+    const double* sk = ys;
+    double acc = 0.0;
+    if (t0 < s) {
+#pragma unroll 8
+      for (int a = 0; a < s; ++a) acc += sk[a * s + t0] * sk[a * s + t0];
+    }
     if (c->kind == GLOBAL || c->kind == BGLOBAL) {
-      double f = 0.0;
-      for (int t = 0; t < ss; ++t) f += sk[t] * sk[t];
+      const double f = wsum(acc);
       meas = sqrt(f) / c->r0F;
       nan = !isfinite(f);
     } else {
-      for (int i = 0; i < s; ++i) {
-        double acc = 0.0;
-        for (int a = 0; a < s; ++a) acc += sk[a * s + i] * sk[a * s + i];
-        nan |= !isfinite(acc);
-        const double rel = c->r0n[i] > 0.0 ? sqrt(acc) / c->r0n[i] : 0.0;
-        meas = fmax(meas, rel);
-      }
+      const double rel = (t0 < s && c->r0n[t0] > 0.0) ? sqrt(acc) / c->r0n[t0] : 0.0;
+      meas = wmax(rel);
+      nan = wany(!isfinite(acc));
     }
+  }
+  if (tid() == 0) {
     const int tot = c->total;
     if (hist && tot < c->hist_cap) hist[tot] = nan ? NAN : meas;
     c->total = tot + 1;
@@ -2372,8 +2534,77 @@ __global__ __launch_bounds__(kSB) void gm_backsub_kernel(GmCtl* c, const double*
   }
 }
 
-hipError_t launch_gm_backsub(GmCtl* ctl, const double* H, const double* sig, double* zeta, hipStream_t st) {
-  hipLaunchKernelGGL(gm_backsub_kernel, dim3(1), dim3(kSB), 0, st, ctl, H, sig, zeta);
+// The same back substitution for widths s <= 8 and kend <= kGmStage, right-
+// looking: once zeta_j is known, every right-hand side l < j loses H_lj
+// zeta_j.  The right-hand sides stay in LDS; lane q < s^2 holds entry q of
+// every block, and the blocks H_lj, l < j, of the next step are loaded into
+// registers while this step runs, so each step waits for memory about once
+// (the left-looking form above waits for every block it reads).
+__global__ __launch_bounds__(kSB) void gm_backsub8_kernel(GmCtl* c, const double* H, const double* sig,
+                                                           double* zeta) {
+  constexpr int SS = 64, NB = kGmStage;
+  __shared__ double rhs[NB * SS], hb[NB * SS], zj[SS], zl[NB * SS];
+  const int s = c->s, g = c->g, m = c->m, ss = s * s, kend = c->kend;
+  const int q = tid();
+  const bool own = q < ss;
+  double hv[NB];
+  auto load_col = [&](int j) {  // H_lj, l <= j, entry q
+#pragma unroll
+    for (int l = 0; l < NB; ++l) hv[l] = (own && l <= j) ? H[((int64_t)l * m + j) * ss + q] : 0.0;
+  };
+  load_col(kend - 1);
+#pragma unroll
+  for (int l = 0; l < NB; ++l)
+    if (own && l < kend) rhs[l * SS + q] = sig[(int64_t)l * ss + q];
+#pragma unroll
+  for (int l = 0; l < NB; ++l)
+    if (own && l < kend) hb[l * SS + q] = hv[l];
+  for (int j = kend - 1; j >= 0; --j) {
+    __syncthreads();
+    if (j > 0) load_col(j - 1);
+    // zeta_j = R_jj^-1 rhs_j per (group, column): thread e = o + b
+    if (own) zj[q] = 0.0;
+    __syncthreads();
+    const double* T = hb + j * SS;
+    const double* r = rhs + j * SS;
+    for (int e = q; e < s; e += kSB) {
+      const int grp = e / g, b = e % g, o = grp * g;
+      for (int a = g - 1; a >= 0; --a) {
+        double acc = r[(o + a) * s + o + b];
+        for (int cc = a + 1; cc < g; ++cc) acc -= T[(o + a) * s + o + cc] * zj[(o + cc) * s + o + b];
+        const double piv = T[(o + a) * s + o + a];
+        zj[(o + a) * s + o + b] = piv != 0.0 ? acc / piv : 0.0;
+      }
+    }
+    __syncthreads();
+    if (own) {
+      zl[j * SS + q] = zj[q];  // written to zeta at the end (see hrot in gm_step_kernel)
+      // rhs_l -= H_lj zeta_j, l < j: entry q = (a, b) of every block
+      const int a = q / s, b = q - a * s;
+      for (int l = 0; l < j; ++l) {
+        double d = 0.0;
+        for (int cc = 0; cc < s; ++cc) d += hb[l * SS + a * s + cc] * zj[cc * s + b];
+        rhs[l * SS + q] -= d;
+      }
+    }
+    __syncthreads();
+    if (j > 0) {
+#pragma unroll
+      for (int l = 0; l < NB; ++l)
+        if (own && l < j) hb[l * SS + q] = hv[l];
+    }
+  }
+  __syncthreads();
+  if (own)
+    for (int l = 0; l < kend; ++l) zeta[(int64_t)l * ss + q] = zl[l * SS + q];
+}
+
+hipError_t launch_gm_backsub(GmCtl* ctl, int s, int kend, const double* H, const double* sig, double* zeta,
+                             hipStream_t st) {
+  if (s <= 8 && kend <= kGmStage)
+    hipLaunchKernelGGL(gm_backsub8_kernel, dim3(1), dim3(kSB), 0, st, ctl, H, sig, zeta);
+  else
+    hipLaunchKernelGGL(gm_backsub_kernel, dim3(1), dim3(kSB), 0, st, ctl, H, sig, zeta);
   return hipGetLastError();
 }
 

@@ -960,7 +960,7 @@ hipError_t gm_run(const CsrView& A, Sub sub, const double* B, double* X, double 
     res.bad_index = hc->bad_index;
     if (res.bad_index || res.status) return hipSuccess;
     if (kend > 0) {
-      BK_TRY(launch_gm_backsub(c, b.H, b.sig, b.zeta, st));
+      BK_TRY(launch_gm_backsub(c, s, kend, b.H, b.sig, b.zeta, st));
       BK_TRY(launch_block_combine<double>(n, s, b.V, kend, b.zeta, 1.0, X, nullptr, st));
     }
     if (res.converged || res.steps >= maxit || kend == 0) break;
