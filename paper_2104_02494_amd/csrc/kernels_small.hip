@@ -2111,12 +2111,21 @@ hipError_t launch_bg_expand(const double* rho, Sub sub, double* N, double* d, co
 // Full QR of the rows x cols matrix M (row stride cols, rows <= 64) by
 // Householder reflections: R in the upper triangle of M, the full rows x rows
 // orthogonal Q (row stride rows) with M_in = Q [R; 0].
-template <int SM>
+// GC > 0: cols = GC and rows = 2 GC known at compile time (every loop
+// unrolled without guards, so no load waits inside a branch); GC = 0: any
+// cols <= SM, rows = 2 cols.
+template <int SM, int GC = 0>
 __device__ __forceinline__ void sm_house_full(double* M, int rows, int cols, double* Q, double* beta) {
   // rows <= 2 SM <= kSB (lane t holds row t of the reflected column), cols <= SM
   constexpr int RM = 2 * SM;
+  if constexpr (GC > 0) {
+    rows = 2 * GC;
+    cols = GC;
+  }
   const int t = tid();
-  for (int j = 0; j < cols; ++j) {
+#pragma unroll
+  for (int j = 0; j < (GC > 0 ? GC : SM); ++j) {
+    if (GC == 0 && j >= cols) break;
     __syncthreads();
     const double xi = (t > j && t < rows) ? M[t * cols + j] : 0.0;
     const double sig = wsum(xi * xi);
@@ -2155,7 +2164,10 @@ __device__ __forceinline__ void sm_house_full(double* M, int rows, int cols, dou
   for (int e = t; e < rows * rows; e += kSB) Q[e] = 0.0;
   __syncthreads();
   if (t < rows) Q[t * rows + t] = 1.0;
-  for (int j = cols - 1; j >= 0; --j) {
+#pragma unroll
+  for (int jj = (GC > 0 ? GC : SM) - 1; jj >= 0; --jj) {
+    const int j = (GC > 0) ? jj : jj - (SM - cols);
+    if (j < 0) continue;
     __syncthreads();
     const double b = beta[j];
     if (b == 0.0) continue;
@@ -2180,8 +2192,9 @@ __device__ __forceinline__ void sm_house_full(double* M, int rows, int cols, dou
 
 // [x; y] <- Om^T [x; y] for S-elements x, y (s x s, row stride s), Om the
 // per-group 2g x 2g factors stored consecutively.
-template <int SM>
+template <int SM, int GC = 0>
 __device__ __forceinline__ void sm_apply_givens_T(const double* Om, double* x, double* y, int s, int g, double* tmp) {
+  if constexpr (GC > 0) g = GC;
   const int ngrp = s / g, m2 = 2 * g;
   __syncthreads();
   for (int e = tid(); e < ngrp * m2 * g; e += kSB) {
@@ -2190,8 +2203,8 @@ __device__ __forceinline__ void sm_apply_givens_T(const double* Om, double* x, d
     const int o = grp * g;
     double acc = 0.0;
 #pragma unroll
-    for (int k = 0; k < 2 * SM; ++k) {
-      if (k < m2) {
+    for (int k = 0; k < 2 * (GC > 0 ? GC : SM); ++k) {
+      if (GC > 0 || k < m2) {
         const double col = k < g ? x[(o + k) * s + o + cc] : y[(o + k - g) * s + o + cc];
         acc += O[k * m2 + i] * col;
       }
@@ -2270,7 +2283,7 @@ __global__ __launch_bounds__(kSB) void gm_step_kernel(GmCtl* c, int k, double* H
   // rotation's factor and block j + 1 of the new column into LDS.  Loads in
   // chunks of 8 per lane, all issued before the chunk's stores.
   {
-    constexpr int U = 8;
+    constexpr int U = 32;
     const int total = (k + 1) * ss;
     for (int base = 0; base < total; base += U * kSB) {
       double v[U];
@@ -2319,6 +2332,7 @@ __global__ __launch_bounds__(kSB) void gm_step_kernel(GmCtl* c, int k, double* H
   constexpr int RS = (SM * SM + kSB - 1) / kSB;  // block entries per lane
   constexpr int RN = (2 * SM * SM + kSB - 1) / kSB;  // rotated entries per lane
   const SmDiv dg(g);
+  const bool full = g == SM && s == SM;  // one group of full width: m2 = 2 SM
   double opre[RO], ypre[RS];
   auto load_next = [&](int j) {
 #pragma unroll
@@ -2364,13 +2378,21 @@ __global__ __launch_bounds__(kSB) void gm_step_kernel(GmCtl* c, int k, double* H
         const double* O = O0 + grp * m2 * m2;
         const int o = grp * g;
         double acc = 0.0;
-        // compile-time trip count (m2 <= 2 SM): every LDS load of the
-        // product is issued before the first add instead of one per add
+        // compile-time trip count (m2 <= 2 SM; exactly 2 SM when g = SM):
+        // every LDS load of the product is issued before the first add
+        if (full) {
 #pragma unroll
-        for (int q = 0; q < 2 * SM; ++q) {
-          if (q < m2) {
-            const double col = q < g ? xs[(o + q) * s + o + cc] : Y[(o + q - g) * s + o + cc];
-            acc += O[q * m2 + i] * col;
+          for (int q = 0; q < 2 * SM; ++q) {
+            const double col = q < SM ? xs[q * s + cc] : Y[(q - SM) * s + cc];
+            acc += O[q * 2 * SM + i] * col;
+          }
+        } else {
+#pragma unroll
+          for (int q = 0; q < 2 * SM; ++q) {
+            if (q < m2) {
+              const double col = q < g ? xs[(o + q) * s + o + cc] : Y[(o + q - g) * s + o + cc];
+              acc += O[q * m2 + i] * col;
+            }
           }
         }
         out[r] = acc;
@@ -2396,11 +2418,14 @@ __global__ __launch_bounds__(kSB) void gm_step_kernel(GmCtl* c, int k, double* H
     __syncthreads();
     // blocks j < k of the new column: the rotated group entries (the rest of
     // each block keeps the value written above)
-    for (int t = t0; t < k * ne; t += kSB) {
-      const int j = t / ne, e = t - j * ne;
-      const int ge = dg.q(e), grp = dg.q(ge) / 2, i = ge - grp * m2, cc = e - ge * g;
-      const int o = grp * g;
-      if (i < g) H[((int64_t)j * m + k) * ss + (o + i) * s + o + cc] = hrot[j * SM * SM + (o + i) * s + o + cc];
+    for (int j = 0; j < k; ++j) {
+      double* Hj = H + ((int64_t)j * m + k) * ss;
+      const double* hj = hrot + j * SM * SM;
+      for (int e = t0; e < ne; e += kSB) {
+        const int ge = dg.q(e), grp = dg.q(ge) / 2, i = ge - grp * m2, cc = e - ge * g;
+        const int o = grp * g;
+        if (i < g) Hj[(o + i) * s + o + cc] = hj[(o + i) * s + o + cc];
+      }
     }
   }
   __syncthreads();
@@ -2433,7 +2458,10 @@ __global__ __launch_bounds__(kSB) void gm_step_kernel(GmCtl* c, int k, double* H
         const int i = t / g, cc = t % g;
         M[t] = i < g ? xs[(o + i) * s + o + cc] : gm[(o + i - g) * s + o + cc];
       }
-      sm_house_full<SM>(M, m2, g, Qf, beta);
+      if (g == SM)
+        sm_house_full<SM, SM>(M, m2, g, Qf, beta);
+      else
+        sm_house_full<SM>(M, m2, g, Qf, beta);
       for (int t = tid(); t < m2 * m2; t += kSB) Omk[grp * m2 * m2 + t] = Qf[t];
       for (int t = tid(); t < g * g; t += kSB) {
         const int i = t / g, cc = t % g;
@@ -2445,7 +2473,10 @@ __global__ __launch_bounds__(kSB) void gm_step_kernel(GmCtl* c, int k, double* H
   // sigma_k and sigma_{k+1} are rotated in LDS (xs and ys are free by now)
   sm_fetch<SM * SM>(xs, sig + (int64_t)k * ss, ss);
   sm_fetch<SM * SM>(ys, sig + (int64_t)(k + 1) * ss, ss);
-  sm_apply_givens_T<SM>(Omk, xs, ys, s, g, tmp);
+  if (g == SM)
+    sm_apply_givens_T<SM, SM>(Omk, xs, ys, s, g, tmp);
+  else
+    sm_apply_givens_T<SM>(Omk, xs, ys, s, g, tmp);
   for (int e = t0; e < ss; e += kSB) {
     sig[(int64_t)k * ss + e] = xs[e];
     sig[(int64_t)(k + 1) * ss + e] = ys[e];
