@@ -406,10 +406,14 @@ hipError_t launch_lincomb(int64_t n, int s, const T* A0, const T* X1, const doub
 size_t tsqr_workspace_bytes(int64_t n, Sub sub);
 // Normalise X (n x s, row stride s, element T) in place; N (s x s FP64,
 // device) receives the normaliser.  gate_done / gate_fire (may be null): run
-// only if *gate_done == 0 and *gate_fire != 0.
+// only if *gate_done == 0 and *gate_fire != 0.  plan (4 device ints, may be
+// null): where the CholeskyQR path records its decisions (plan[2] != 0: the
+// Householder fallback was needed); fallback = false: the fallback launches
+// are not enqueued, so with plan[2] != 0 the result is not the normaliser
+// and the caller redoes the work with fallback = true.
 template <typename T>
 hipError_t tsqr_run(int64_t n, Sub sub, T* X, double* N, void* ws, uint32_t* cnt, const int32_t* gate_done,
-                    const int32_t* gate_fire, hipStream_t st);
+                    const int32_t* gate_fire, hipStream_t st, int32_t* plan = nullptr, bool fallback = true);
 
 // -------------------------------------------------------- transpose ----
 hipError_t csr_transpose_run(int64_t n, int64_t nnz, const int32_t* rowptr, const int32_t* colind,

@@ -2292,13 +2292,20 @@ __global__ __launch_bounds__(kSB) void gm_step_kernel(GmCtl* c, int k, double* H
         const int t = base + t0 + u * kSB;
         v[u] = t < total ? H1[t] + H2[t] : 0.0;
       }
+      // block j and entry e of t = base + t0 + u kSB, advanced by kSB per
+      // u (one division per batch instead of one per entry)
+      int j = (base + t0) / ss, e = base + t0 - j * ss;
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int t = base + t0 + u * kSB;
         if (t < total) {
-          const int j = t / ss, e = t - j * ss;
           H[((int64_t)j * m + k) * ss + e] = v[u];
           if (staged && j >= 1) stage[(j - 1) * (NO + SM * SM) + NO + e] = v[u];
+        }
+        e += kSB;
+        while (e >= ss) {
+          e -= ss;
+          ++j;
         }
       }
     }
@@ -2311,12 +2318,15 @@ __global__ __launch_bounds__(kSB) void gm_step_kernel(GmCtl* c, int k, double* H
           const int t = base + t0 + u * kSB;
           v[u] = t < tot ? Om[t] : 0.0;
         }
+        int j = (base + t0) / no, e = base + t0 - j * no;
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           const int t = base + t0 + u * kSB;
-          if (t < tot) {
-            const int j = t / no, e = t - j * no;
-            stage[j * (NO + SM * SM) + e] = v[u];
+          if (t < tot) stage[j * (NO + SM * SM) + e] = v[u];
+          e += kSB;
+          while (e >= no) {
+            e -= no;
+            ++j;
           }
         }
       }
@@ -2418,13 +2428,23 @@ __global__ __launch_bounds__(kSB) void gm_step_kernel(GmCtl* c, int k, double* H
     __syncthreads();
     // blocks j < k of the new column: the rotated group entries (the rest of
     // each block keeps the value written above)
-    for (int j = 0; j < k; ++j) {
-      double* Hj = H + ((int64_t)j * m + k) * ss;
-      const double* hj = hrot + j * SM * SM;
-      for (int e = t0; e < ne; e += kSB) {
-        const int ge = dg.q(e), grp = dg.q(ge) / 2, i = ge - grp * m2, cc = e - ge * g;
-        const int o = grp * g;
-        if (i < g) Hj[(o + i) * s + o + cc] = hj[(o + i) * s + o + cc];
+    if (full) {
+      // one group of full width: the rotated part of block j is all of it
+#pragma unroll 4
+      for (int j = 0; j < k; ++j) {
+        double* Hj = H + ((int64_t)j * m + k) * ss;
+        const double* hj = hrot + j * SM * SM;
+        for (int e = t0; e < ss; e += kSB) Hj[e] = hj[e];
+      }
+    } else {
+      for (int j = 0; j < k; ++j) {
+        double* Hj = H + ((int64_t)j * m + k) * ss;
+        const double* hj = hrot + j * SM * SM;
+        for (int e = t0; e < ne; e += kSB) {
+          const int ge = dg.q(e), grp = dg.q(ge) / 2, i = ge - grp * m2, cc = e - ge * g;
+          const int o = grp * g;
+          if (i < g) Hj[(o + i) * s + o + cc] = hj[(o + i) * s + o + cc];
+        }
       }
     }
   }

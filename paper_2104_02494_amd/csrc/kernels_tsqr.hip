@@ -390,7 +390,7 @@ static hipError_t hh_tsqr(int64_t n, const Sub& sub, T* X, double* N, char* w, c
 // branches are decided on the device (plan flags), so no host round trip.
 template <typename T>
 hipError_t tsqr_run(int64_t n, Sub sub, T* X, double* N, void* ws, uint32_t* cnt, const int32_t* gd,
-                    const int32_t* gf, hipStream_t st) {
+                    const int32_t* gf, hipStream_t st, int32_t* plan_ext, bool fallback) {
   char* w = static_cast<char*>(ws);
   const int s = sub.s;
   if (sub.kind == BGLOBAL) {
@@ -401,7 +401,7 @@ hipError_t tsqr_run(int64_t n, Sub sub, T* X, double* N, void* ws, uint32_t* cnt
     const int g = sub.g, q = s / g;
     double* rho = reinterpret_cast<double*>(w);
     double* d = reinterpret_cast<double*>(w + align256(sizeof(double) * g * g));
-    hipError_t e = tsqr_run<T>(n * q, Sub{BLOCK, g, g}, X, rho, w + bg_head(sub), cnt, gd, gf, st);
+    hipError_t e = tsqr_run<T>(n * q, Sub{BLOCK, g, g}, X, rho, w + bg_head(sub), cnt, gd, gf, st, plan_ext, fallback);
     if (e == hipSuccess) e = launch_bg_expand(rho, sub, N, d, gd, gf, st);
     if (e == hipSuccess) e = launch_colscale<T>(n, s, X, X, d, 0, gd, gf, st);
     return e;
@@ -441,7 +441,7 @@ hipError_t tsqr_run(int64_t n, Sub sub, T* X, double* N, void* ws, uint32_t* cnt
   w += align256(sizeof(double) * s * s);
   double* Nh = reinterpret_cast<double*>(w);
   w += align256(sizeof(double) * s * s);
-  int32_t* plan = reinterpret_cast<int32_t*>(w);
+  int32_t* plan = plan_ext ? plan_ext : reinterpret_cast<int32_t*>(w);
   w += align256(4 * sizeof(int32_t));
   const double ratio = sizeof(T) == 8 ? 1e-6 : 3e-3;
   const Red red{G, gpart, cnt};
@@ -450,14 +450,15 @@ hipError_t tsqr_run(int64_t n, Sub sub, T* X, double* N, void* ws, uint32_t* cnt
   if (e == hipSuccess) e = launch_rowmul<T>(n, s, X, Rinv, true, part, nblk, red, plan + 0, st);
   if (e == hipSuccess) e = launch_cholqr(2, G, sub, R1, Rinv, N, plan, ratio, nullptr, nullptr, st);
   if (e == hipSuccess) e = launch_rowmul<T>(n, s, X, Rinv, false, part, nblk, Red{}, plan + 1, st);
+  if (!fallback) return e;
   if (e == hipSuccess) e = hh_tsqr<T>(n, sub, X, Nh, w, nullptr, plan + 2, st);
   if (e == hipSuccess) e = launch_cholqr_compose(Nh, R1, N, sub, plan, st);
   return e;
 }
 
 template hipError_t tsqr_run<double>(int64_t, Sub, double*, double*, void*, uint32_t*, const int32_t*,
-                                     const int32_t*, hipStream_t);
+                                     const int32_t*, hipStream_t, int32_t*, bool);
 template hipError_t tsqr_run<float>(int64_t, Sub, float*, double*, void*, uint32_t*, const int32_t*,
-                                    const int32_t*, hipStream_t);
+                                    const int32_t*, hipStream_t, int32_t*, bool);
 
 }  // namespace bkry

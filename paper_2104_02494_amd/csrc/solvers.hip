@@ -10,6 +10,7 @@
 #include "solvers.hpp"
 
 #include <utility>
+#include <vector>
 
 namespace bkry {
 
@@ -880,6 +881,7 @@ GmBufs carve_gm(Carver& c, int64_t n, Sub sub, int m, int hist_cap, uint32_t* cn
   b.hist = c.take<double>((size_t)(hist_cap > 0 ? hist_cap : 1));
   b.relres = c.take<double>(kMaxS);
   b.flag = c.take<int32_t>(4);
+  b.plans = c.take<int32_t>((size_t)4 * (m + 1));
   b.ctl = c.take<GmCtl>(1);
   b.tsqr_ws = c.take<char>(tsqr_workspace_bytes(n, sub));
   b.cnt = cnt;
@@ -893,6 +895,10 @@ hipError_t gm_run(const CsrView& A, Sub sub, const double* B, double* X, double 
   const size_t blk = (size_t)n * s;
   const int nblk = stream_grid(n, s, sizeof(double));
   const Red red{b.Gb, b.gpart, b.cnt};
+  // The block subalgebra's projection is the identity: its batched Grams are
+  // reduced straight into H instead of through Gb and a projection launch.
+  const bool proj_id = sub.kind == BLOCK;
+  auto red_to = [&](double* target) { return proj_id ? Red{target, b.gpart, b.cnt} : red; };
   GmCtl* c = b.ctl;
   int32_t* done = &c->done;
   GmCtl* h = reinterpret_cast<GmCtl*>(hflags + 64);
@@ -910,7 +916,19 @@ hipError_t gm_run(const CsrView& A, Sub sub, const double* B, double* X, double 
   // orthogonalisation has one, so the second stays zero
   if (orth > 0) BK_TRY(hipMemsetAsync(b.H2, 0, sizeof(double) * (size_t)(m + 1) * ss, st));
   const int lmax = pgs_max_updates(s);
+  // The Arnoldi normalisers are enqueued without the Householder fallback
+  // of CholeskyQR (its launches, gated off when unused, cost more than the
+  // rest of the normaliser at this width); each step records its CholeskyQR
+  // decisions, and a cycle in which one step needed the fallback is redone
+  // with it, from the control block as it was before the cycle.
+  GmCtl before;
+  std::vector<int32_t> hplans((size_t)4 * (m + 1));
+  bool safe = false;
   for (int cycle = 0;; ++cycle) {
+    if (cycle > 0 || safe) BK_TRY(hipMemcpyAsync(&before, c, sizeof(GmCtl), hipMemcpyDeviceToHost, st));
+    BK_TRY(hipStreamSynchronize(st));
+    if (cycle == 0 && !safe) before = *h;
+    BK_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(b.plans), 4 * (m + 1), 0u, st));
     // R = B - A X into V_0, its Gram; V_0 sigma_0 = Norm_S(R)
     BK_TRY(launch_spmm<double>(A, s, X, b.V, B, 2, b.partial, nblk, red, &c->bad_index, nullptr, st));
     BK_TRY(tsqr_run<double>(n, sub, b.V, b.sigma0, b.tsqr_ws, b.cnt, nullptr, nullptr, st));
@@ -925,32 +943,47 @@ hipError_t gm_run(const CsrView& A, Sub sub, const double* B, double* X, double 
         // taking the inner products of the blocks w places further on
         const int w = orth < k ? (orth > 0 ? orth : 1) : (k > 0 ? k : 1);
         const int L = w < lmax ? w : lmax;
-        BK_TRY(launch_gram<double>(n, s, b.V, w < k + 1 ? w : k + 1, W, b.partial, nblk, red, done, st));
-        BK_TRY(launch_project_batched(b.Gb, b.H1, sub, w < k + 1 ? w : k + 1, done, st));
+        BK_TRY(launch_gram<double>(n, s, b.V, w < k + 1 ? w : k + 1, W, b.partial, nblk, red_to(b.H1), done, st));
+        if (!proj_id) BK_TRY(launch_project_batched(b.Gb, b.H1, sub, w < k + 1 ? w : k + 1, done, st));
         for (int u0 = 0; u0 <= k; u0 += L) {
           const int nu = (k + 1 - u0) < L ? (k + 1 - u0) : L;
           const int g0 = u0 + w;
           const int ng = g0 > k ? 0 : ((k + 1 - g0) < nu ? (k + 1 - g0) : nu);
           BK_TRY(launch_pgs_pass(n, s, b.V, W, u0, nu, b.H1, g0, ng, b.partial, nblk, done, st));
           if (ng > 0) {
-            BK_TRY(launch_reduce(s, b.partial, false, nblk, ng, red, done, nullptr, Epi{}, st));
-            BK_TRY(launch_project_batched(b.Gb, b.H1 + (size_t)g0 * ss, sub, ng, done, st));
+            BK_TRY(launch_reduce(s, b.partial, false, nblk, ng, red_to(b.H1 + (size_t)g0 * ss), done, nullptr,
+                                 Epi{}, st));
+            if (!proj_id) BK_TRY(launch_project_batched(b.Gb, b.H1 + (size_t)g0 * ss, sub, ng, done, st));
           }
         }
       } else {
         // classical Gram-Schmidt, twice: H_j = <V_j, W>_S, W -= sum_j V_j H_j
         double* Hp[2] = {b.H1, b.H2};
         for (int pass = 0; pass < 2; ++pass) {
-          BK_TRY(launch_gram<double>(n, s, b.V, k + 1, W, b.partial, nblk, red, done, st));
-          BK_TRY(launch_project_batched(b.Gb, Hp[pass], sub, k + 1, done, st));
+          BK_TRY(launch_gram<double>(n, s, b.V, k + 1, W, b.partial, nblk, red_to(Hp[pass]), done, st));
+          if (!proj_id) BK_TRY(launch_project_batched(b.Gb, Hp[pass], sub, k + 1, done, st));
           BK_TRY(launch_block_combine<double>(n, s, b.V, k + 1, Hp[pass], -1.0, W, done, st));
         }
       }
-      BK_TRY(tsqr_run<double>(n, sub, W, b.gam, b.tsqr_ws, b.cnt, done, nullptr, st));
+      BK_TRY(tsqr_run<double>(n, sub, W, b.gam, b.tsqr_ws, b.cnt, done, nullptr, st, b.plans + 4 * k, safe));
       BK_TRY(launch_gm_step(c, s, k, b.H, b.sig, b.Om, b.H1, b.H2, b.gam, b.hist, st));
     }
     BK_TRY(hipMemcpyAsync(hflags, c, 16 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    if (!safe)
+      BK_TRY(hipMemcpyAsync(hplans.data(), b.plans, sizeof(int32_t) * 4 * m, hipMemcpyDeviceToHost, st));
     BK_TRY(hipStreamSynchronize(st));
+    if (!safe) {
+      bool redo = false;
+      for (int k = 0; k < m; ++k) redo |= hplans[(size_t)4 * k + 2] != 0;
+      if (redo) {
+        // restore the control block and run this cycle again with the fallback
+        BK_TRY(hipMemcpyAsync(c, &before, sizeof(GmCtl), hipMemcpyHostToDevice, st));
+        safe = true;
+        --cycle;
+        continue;
+      }
+    }
+    safe = false;
     const GmCtl* hc = reinterpret_cast<const GmCtl*>(hflags);
     const int kend = hc->kend;
     res.status = hc->status;

@@ -136,6 +136,7 @@ struct GmBufs {
   double *H = nullptr, *sig = nullptr, *Om = nullptr, *zeta = nullptr, *sigma0 = nullptr, *gam = nullptr;
   double *hist = nullptr, *relres = nullptr;
   int32_t* flag = nullptr;
+  int32_t* plans = nullptr;  // the CholeskyQR decisions of each Arnoldi step, 4 ints each
   GmCtl* ctl = nullptr;
   void* tsqr_ws = nullptr;
   uint32_t* cnt = nullptr;

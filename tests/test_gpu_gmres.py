@@ -92,6 +92,29 @@ def test_gmres_edge_cases(orc, h):
         gpu_gm(h, A, B, restart=201)
 
 
+@pytest.mark.parametrize("r", [0, 2])
+def test_gmres_invariant_krylov_space(h, r):
+    """A with three distinct eigenvalues: the block Krylov space of 4
+    right-hand sides is invariant after three steps, so the third Arnoldi
+    block is zero and its CholeskyQR fails (the Householder fallback of the
+    normaliser is needed inside a cycle).  The cycle must still end with the
+    exact solution."""
+    rng = np.random.default_rng(31)
+    d = rng.choice([1.0, 2.0, 5.0], size=300)
+    A = W.dense_to_csr(np.diag(d))
+    B = W.gaussian_block(A.n, 4, 32)
+    say("gmres invariant space", r)
+    kw = dict(tol=1e-10, maxit=60, restart=30)
+    if r:
+        X, info = P.bkry_gmres_pipelined_solve(h, dev_csr(P, A), to_dev(B), r, **kw)
+    else:
+        X, info = P.bkry_gmres_solve(h, dev_csr(P, A), to_dev(B), **kw)
+    X = to_np(X)
+    assert info["converged"] and info["iters"] <= 4, info
+    assert max(info["true_relres"]) <= 1e-9
+    assert rel(X, B / d[:, None]) < 1e-9
+
+
 def test_gmres_deterministic(h):
     A = W.convdiff_2d(24)
     B = W.gaussian_block(A.n, 8, 3)

@@ -3,6 +3,8 @@ bkry_bdot: the same kernels on a fixed per-GPU scratch array instead of the
 handle's workspace, so the Grams must agree bit for bit.  Two calls in a row,
 the second with a smaller input, so stale scratch contents from the first
 call would show; every subalgebra; device memory use checked unchanged."""
+import gc
+
 import numpy as np
 import pytest
 
@@ -25,11 +27,19 @@ def test_noalloc_bdot_matches_bdot(h, p, kind, q):
         say("bdot_noalloc", n, p, kind, q)
         ref = to_np(P.bkry_bdot(h, X, Y, kind, q))
         G = torch.full((p, p), float("nan"), dtype=torch.float64, device=X.device)
-        torch.cuda.synchronize()
-        before = torch.cuda.memory_allocated()
-        P.bkry_bdot_noalloc(h, X, Y, G, kind, q)
-        torch.cuda.synchronize()
-        assert torch.cuda.memory_allocated() == before
+        # no garbage collection inside the measured window: a collection could
+        # free tensors of earlier tests there and move the count down
+        gc.collect()
+        gc.disable()
+        try:
+            torch.cuda.synchronize()
+            before = torch.cuda.memory_allocated()
+            P.bkry_bdot_noalloc(h, X, Y, G, kind, q)
+            torch.cuda.synchronize()
+            after = torch.cuda.memory_allocated()
+        finally:
+            gc.enable()
+        assert after == before
         assert np.array_equal(to_np(G), ref)
 
 
