@@ -40,6 +40,13 @@ static hipError_t dispatch_sm(int s, F&& f) {
 
 __device__ __forceinline__ int tid() { return threadIdx.x; }
 
+// Ordering point between the lanes of the workgroup's single wavefront for
+// data exchanged through LDS only: the wavefront's LDS accesses are carried
+// out in program order, so no workgroup barrier (and no wait for outstanding
+// accesses) is needed, only a point the compiler does not move accesses
+// across.  Not for data exchanged through global memory.
+__device__ __forceinline__ void sm_wave_sync() { __builtin_amdgcn_wave_barrier(); }
+
 // t / d and t % d for 0 <= t < 2048 and 1 <= d <= 32 by one multiply: with
 // m = ceil(2^16 / d), e = m d - 2^16 <= d - 1, t m / 2^16 = t / d + t e / (d
 // 2^16) and t e <= 2047 * 31 < 2^16, so the floor is t / d's (the loops over
@@ -2126,7 +2133,7 @@ __device__ __forceinline__ void sm_house_full(double* M, int rows, int cols, dou
 #pragma unroll
   for (int j = 0; j < (GC > 0 ? GC : SM); ++j) {
     if (GC == 0 && j >= cols) break;
-    __syncthreads();
+    sm_wave_sync();
     const double xi = (t > j && t < rows) ? M[t * cols + j] : 0.0;
     const double sig = wsum(xi * xi);
     const double x1 = M[j * cols + j];
@@ -2136,58 +2143,69 @@ __device__ __forceinline__ void sm_house_full(double* M, int rows, int cols, dou
       v1 = (x1 <= 0.0) ? (x1 - mu) : (-sig / (x1 + mu));
       b = 2.0 * v1 * v1 / (sig + v1 * v1);
     }
-    __syncthreads();
+    sm_wave_sync();
     if (sig != 0.0) {
       if (t > j && t < rows) M[t * cols + j] = xi / v1;
       if (t == j) M[j * cols + j] = mu;
     }
     if (t == 0) beta[j] = b;
-    __syncthreads();
+    sm_wave_sync();
     if (b != 0.0) {
+      // the two columns are read into registers before any store: a store
+      // to column cc might alias a later load of column j for all the
+      // compiler knows, which would order every load after the stores
       for (int cc = j + 1 + t; cc < cols; cc += kSB) {
-        double w = M[j * cols + cc];
+        double vj[RM], vc[RM];
 #pragma unroll
-        for (int i = 1; i < RM; ++i) {
+        for (int i = 0; i < RM; ++i) {
           const int r = j + i;
-          if (r < rows) w += M[r * cols + j] * M[r * cols + cc];
+          vj[i] = (r < rows) ? M[r * cols + j] : 0.0;
+          vc[i] = (r < rows) ? M[r * cols + cc] : 0.0;
         }
-        M[j * cols + cc] -= b * w;
+        double w = vc[0];
+#pragma unroll
+        for (int i = 1; i < RM; ++i) w += vj[i] * vc[i];
+        M[j * cols + cc] = vc[0] - b * w;
 #pragma unroll
         for (int i = 1; i < RM; ++i) {
           const int r = j + i;
-          if (r < rows) M[r * cols + cc] -= b * M[r * cols + j] * w;
+          if (r < rows) M[r * cols + cc] = vc[i] - b * vj[i] * w;
         }
       }
     }
   }
-  __syncthreads();
+  sm_wave_sync();
   for (int e = t; e < rows * rows; e += kSB) Q[e] = 0.0;
-  __syncthreads();
+  sm_wave_sync();
   if (t < rows) Q[t * rows + t] = 1.0;
 #pragma unroll
   for (int jj = (GC > 0 ? GC : SM) - 1; jj >= 0; --jj) {
     const int j = (GC > 0) ? jj : jj - (SM - cols);
     if (j < 0) continue;
-    __syncthreads();
+    sm_wave_sync();
     const double b = beta[j];
     if (b == 0.0) continue;
     if (t < rows) {
       const int cc = t;
-      double w = Q[j * rows + cc];
+      double vj[RM], vc[RM];
 #pragma unroll
-      for (int i = 1; i < RM; ++i) {
+      for (int i = 0; i < RM; ++i) {
         const int r = j + i;
-        if (r < rows) w += M[r * cols + j] * Q[r * rows + cc];
+        vj[i] = (r < rows && i > 0) ? M[r * cols + j] : 0.0;
+        vc[i] = (r < rows) ? Q[r * rows + cc] : 0.0;
       }
-      Q[j * rows + cc] -= b * w;
+      double w = vc[0];
+#pragma unroll
+      for (int i = 1; i < RM; ++i) w += vj[i] * vc[i];
+      Q[j * rows + cc] = vc[0] - b * w;
 #pragma unroll
       for (int i = 1; i < RM; ++i) {
         const int r = j + i;
-        if (r < rows) Q[r * rows + cc] -= b * M[r * cols + j] * w;
+        if (r < rows) Q[r * rows + cc] = vc[i] - b * vj[i] * w;
       }
     }
   }
-  __syncthreads();
+  sm_wave_sync();
 }
 
 // [x; y] <- Om^T [x; y] for S-elements x, y (s x s, row stride s), Om the
@@ -2357,10 +2375,45 @@ __global__ __launch_bounds__(kSB) void gm_step_kernel(GmCtl* c, int k, double* H
     }
   };
   if (!staged) load_next(0);
+  if (staged && full) __syncthreads();  // the staged data, before the LDS-only rotations
   for (int j = 0; j < k; ++j) {
-    __syncthreads();
+    if (staged && full)
+      sm_wave_sync();
+    else
+      __syncthreads();
     const double* O0 = Qf;
     const double* Y = ys;
+    if constexpr (SM == 8) {
+      if (staged && full) {
+        // [x; y] <- O^T [x; y] (16 x 8) as four 16 x 16 x 4 products on the
+        // matrix cores (lane layout of mf_mma): A[i][q] = O[q][i], B[q][c] =
+        // row q of [x; y] (columns 8 .. 15 zero), D[i][c] = the rotated row i
+        const double* O = stage + j * (NO + SM * SM);
+        const double* Ys = O + NO;
+        const int lr = t0 / 16, lc = t0 % 16;
+        mf_d4 acc = mf_d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+          const int q = 4 * kk + lr;
+          const double a = O[q * 16 + lc];
+          double bv = 0.0;
+          if (lc < 8) bv = q < 8 ? xs[q * 8 + lc] : Ys[(q - 8) * 8 + lc];
+          acc = mf_mma(a, bv, acc);
+        }
+        sm_wave_sync();
+        if (lc < 8) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int i = 4 * v + lr;
+            if (i < 8)
+              hrot[j * SM * SM + i * 8 + lc] = acc[v];
+            else
+              xs[(i - 8) * 8 + lc] = acc[v];
+          }
+        }
+        continue;
+      }
+    }
     if (staged) {
       O0 = stage + j * (NO + SM * SM);
       Y = O0 + NO;
