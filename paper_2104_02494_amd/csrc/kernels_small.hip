@@ -119,6 +119,29 @@ __device__ __forceinline__ void sm_fetch(T* dst, const T* src, int count) {
   }
 }
 
+// sm_fetch in two halves (registers in between), so that the loads of
+// several blocks, and other loads, are in flight before the first wait.
+template <int N, typename T>
+struct SmRegs {
+  T v[(N + kSB - 1) / kSB];
+};
+template <int N, typename T>
+__device__ __forceinline__ void sm_load(SmRegs<N, T>& r, const T* src, int count) {
+#pragma unroll
+  for (int u = 0; u < (N + kSB - 1) / kSB; ++u) {
+    const int t = tid() + u * kSB;
+    if (u * kSB < count) r.v[u] = src[t < count ? t : count - 1];
+  }
+}
+template <int N, typename T>
+__device__ __forceinline__ void sm_store(T* dst, const SmRegs<N, T>& r, int count) {
+#pragma unroll
+  for (int u = 0; u < (N + kSB - 1) / kSB; ++u) {
+    const int t = tid() + u * kSB;
+    if (t < count) dst[t] = r.v[u];
+  }
+}
+
 __device__ __forceinline__ void sm_eye(double* M, int s) {
   const SmDiv ds(s);
   for (int t = tid(); t < s * s; t += kSB) M[t] = (ds.q(t) == ds.r(t)) ? 1.0 : 0.0;
@@ -908,87 +931,129 @@ __device__ __forceinline__ bool lc_definite(const double* A, int s, double sa, d
   return mf_chol<SM, false, false, false, false>(A, s, sa, sh, nullptr, nullptr, nullptr, nullptr);
 }
 
-// Power iteration (as rf_power_lmax_x) with the matrix in registers, lane
-// (q, i) holding row i, columns [q RW, q RW + RW); the iterate lives in LDS
-// (one wavefront: its LDS accesses are carried out in program order, so the
-// exchanges need no barrier).
-template <int SM>
-__device__ __forceinline__ double lc_power_lmax(const double* A, int s) {
-  using G = Seg<SM>;
-  PowLds<SM>* w = pow_lds<SM>();
-  const int t = tid(), i = t % SM, q = t / SM, c0 = q * G::RW;
-  double m[G::RW];
-#pragma unroll
-  for (int u = 0; u < G::RW; ++u) m[u] = (i < s && c0 + u < s) ? A[i * s + c0 + u] : 0.0;
-  double* xs = w->xs;
-  const double* seg = xs + q * G::ST;
-  __syncthreads();
-  if (q == 0) xs[G::at(i)] = (i < s) ? 1.0 : 0.0;
-  __builtin_amdgcn_wave_barrier();
-  double theta = 0.0;
-  for (int it = 0; it < 64; ++it) {
-    double p = 0.0;
-#pragma unroll
-    for (int u = 0; u < G::RW; u += 2) {
-      const double2 v = ld2(seg + u);
-      p = fma(m[u], v.x, p);
-      p = fma(m[u + 1], v.y, p);
-    }
-    const double x = xs[G::at(i)];
-    w->part[t] = p;
-    __builtin_amdgcn_wave_barrier();
-    double y = 0.0;
-#pragma unroll
-    for (int h = 0; h < G::NQ; ++h) y += w->part[h * SM + i];
-    const bool mine = q == 0;
-    const double xx = wsum(mine ? x * x : 0.0), xy = wsum(mine ? x * y : 0.0), yy = wsum(mine ? y * y : 0.0);
-    const double th = xy / xx;
-    if (!(yy > 0.0) || !isfinite(yy)) {
-      __syncthreads();
-      return th;
-    }
-    if (mine) xs[G::at(i)] = y / sqrt(yy);
-    __builtin_amdgcn_wave_barrier();
-    const bool settled = it > 0 && fabs(th - theta) <= 1e-6 * fabs(th);
-    theta = th;
-    if (settled) break;
+// Largest eigenvalue of the symmetric tridiagonal matrix with diagonal
+// a[0 .. j) and off-diagonal b[0 .. j - 1) (LDS, read alike by all lanes),
+// from below: bisection on Sturm counts (the negative pivots of the LDL^T
+// factorisation of T - sigma I count the eigenvalues below sigma), with the
+// 64 lanes testing 64 shifts of the bracket at once, so that each pass
+// narrows it 65-fold; four passes from the Gershgorin interval.  Returns the
+// lower end of the final bracket.
+__device__ __forceinline__ double tridiag_lmax(const double* a, const double* b, int j) {
+  double lo = a[0], hi = a[0];
+  for (int i = 0; i < j; ++i) {
+    const double r = (i > 0 ? fabs(b[i - 1]) : 0.0) + (i + 1 < j ? fabs(b[i]) : 0.0);
+    lo = fmin(lo, a[i] - r);
+    hi = fmax(hi, a[i] + r);
   }
-  __syncthreads();
-  return theta;
+  const double pivmin = 1e-290 + 1e-30 * (hi - lo);
+  const int t = tid();
+  for (int pass = 0; pass < 4; ++pass) {
+    const double w = (hi - lo) / 65.0;
+    const double sg = lo + w * (t + 1);
+    int cnt = 0;
+    double d = 1.0;
+    for (int i = 0; i < j; ++i) {
+      const double bb = i > 0 ? b[i - 1] * b[i - 1] : 0.0;
+      d = (a[i] - sg) - bb / d;
+      if (fabs(d) < pivmin) d = -pivmin;
+      cnt += d < 0.0 ? 1 : 0;
+    }
+    // the smallest shift with all j eigenvalues below it bounds lambda_max
+    const unsigned long long m = __ballot(cnt == j);
+    if (m == 0) {
+      lo += 64.0 * w;
+    } else {
+      const int k = __builtin_ctzll(m);
+      hi = lo + w * (k + 1);
+      lo += w * k;
+    }
+  }
+  return lo;
 }
 
-// Rayleigh quotient of the power iteration for the symmetric s x s matrix A
-// (LDS) from the all-ones vector, after at most 64 steps or once it changes
-// by less than 1e-6 relative.  It never exceeds lambda_max(A) (uniform).
-template <int SM, bool EX>
-__device__ __forceinline__ double rf_power_lmax_x(const double* A, int s) {
-  if constexpr (EX) s = SM;
-  const int t = tid();
-  double a[SM];
-#pragma unroll
-  for (int j = 0; j < SM; ++j) a[j] = (t < s && j < s) ? A[t * s + j] : 0.0;
-  double x = (t < s) ? 1.0 : 0.0, theta = 0.0;
-  for (int it = 0; it < 64; ++it) {
-    double y = 0.0;
-#pragma unroll
-    for (int j = 0; j < SM; ++j)
-      if (j < s) y = fma(a[j], readlane_d(x, j), y);
-    const double xx = wsum(x * x), xy = wsum(x * y), yy = wsum(y * y);
-    const double th = xy / xx;
-    if (!(yy > 0.0) || !isfinite(yy)) return th;
-    x = y / sqrt(yy);
-    const bool settled = it > 0 && fabs(th - theta) <= 1e-6 * fabs(th);
-    theta = th;
-    if (settled) break;
-  }
-  return theta;
-}
+// Lanczos estimate of lambda_max of the symmetric s x s matrix A (LDS) from
+// the normalised all-ones vector: the largest eigenvalue of the Lanczos
+// tridiagonal matrix T_j (a Ritz value, so at most lambda_max up to
+// rounding), taken every four steps from j = 8 until it changes by at most
+// 1e-6 relative, the subspace is invariant, or j = s (T_s has the spectrum
+// of A).  Far fewer matrix-vector products than the power iteration where
+// the largest eigenvalues are close.  Uniform result.  The owner of row i
+// is lane i; for SM >= 16 the matrix sits in registers by row segments (lane
+// (q, i) holding row i, columns [q RW, q RW + RW)) and the vector in LDS,
+// for SM <= 8 lane i holds row i and the vector moves by lane reads.  A
+// single wavefront's LDS accesses are carried out in program order, so the
+// exchanges need no barrier.
 template <int SM>
-__device__ __forceinline__ double rf_power_lmax(const double* A, int s) {
-  if constexpr (SM >= 16)
-    return lc_power_lmax<SM>(A, s);
-  else
-    return s == SM ? rf_power_lmax_x<SM, true>(A, s) : rf_power_lmax_x<SM, false>(A, s);
+__device__ __forceinline__ double lanczos_lmax(const double* A, int s) {
+  __shared__ double ta[kMaxS], tb[kMaxS];
+  const int t = tid();
+  constexpr bool WIDE = SM >= 16;
+  using G = Seg<WIDE ? SM : 16>;
+  const int i = WIDE ? t % SM : t, q = WIDE ? t / SM : 0, c0 = q * G::RW;
+  constexpr int NR = WIDE ? G::RW : SM;
+  double m[NR];
+#pragma unroll
+  for (int u = 0; u < NR; ++u) {
+    const int c = WIDE ? c0 + u : u;
+    m[u] = (i < s && c < s) ? A[i * s + c] : 0.0;
+  }
+  PowLds<WIDE ? SM : 16>* w = nullptr;
+  if constexpr (WIDE) w = pow_lds<SM>();
+  __syncthreads();
+  // y = (A x)_i on every lane of row i (x held by the owner lanes, zero elsewhere)
+  auto matvec = [&](double x) {
+    double y = 0.0;
+    if constexpr (WIDE) {
+      if (q == 0) w->xs[G::at(i)] = x;
+      __builtin_amdgcn_wave_barrier();
+      const double* seg = w->xs + q * G::ST;
+      double p0 = 0.0, p1 = 0.0;
+#pragma unroll
+      for (int u = 0; u < NR; u += 2) {
+        const double2 v = ld2(seg + u);
+        p0 = fma(m[u], v.x, p0);
+        p1 = fma(m[u + 1], v.y, p1);
+      }
+      w->part[t] = p0 + p1;
+      __builtin_amdgcn_wave_barrier();
+#pragma unroll
+      for (int h = 0; h < G::NQ; ++h) y += w->part[h * SM + i];
+      __builtin_amdgcn_wave_barrier();
+    } else {
+#pragma unroll
+      for (int c = 0; c < NR; ++c) y = fma(m[c], readlane_d(x, c), y);
+    }
+    return y;
+  };
+  const bool own = WIDE ? (q == 0 && i < s) : (t < s);
+  double v = own ? 1.0 / sqrt((double)s) : 0.0, vp = 0.0, bprev = 0.0, anorm = 0.0;
+  double theta = 0.0, prev = 0.0;
+  bool have = false;
+  for (int j = 1; j <= s; ++j) {
+    double y = matvec(v);
+    y = own ? y - bprev * vp : 0.0;
+    const double al = wsum(y * v);
+    y = own ? y - al * v : 0.0;
+    const double bt = sqrt(wsum(y * y));
+    if (t == 0) {
+      ta[j - 1] = al;
+      tb[j - 1] = bt;
+    }
+    __builtin_amdgcn_wave_barrier();
+    anorm = fmax(anorm, fabs(al) + bt + bprev);
+    const bool last = j == s || !(bt > 1e-14 * anorm);
+    if (last || (j >= 8 && j % 4 == 0)) {
+      theta = tridiag_lmax(ta, tb, j);
+      if (last || (have && fabs(theta - prev) <= 1e-6 * fabs(theta))) break;
+      prev = theta;
+      have = true;
+    }
+    vp = v;
+    v = y / bt;
+    bprev = bt;
+  }
+  __syncthreads();
+  return theta;
 }
 
 // The re-orthonormalisation is decided per iteration (the L^-1 bound of the
@@ -1057,20 +1122,27 @@ __device__ __forceinline__ bool reortho_test(CgCtl* c, const double* alpha, doub
   const double ub = fmin(nF * wsum(li), fmin(nF, nInf) * wmax(colL) * wmax(rowL));
   const double es = c->eta * c->sqrt_eps;
   if (isfinite(ub) && ub * (1.0 + 1e-12) * es <= 1.0) return false;
-  const double lb = fmax(1.0, wsum(sumM) / s) * wmax(dinv);
+  const double lmax_lo = fmax(1.0, wsum(sumM) / s), lmax_hi = fmin(nF, nInf);
+  const double lb = lmax_lo * wmax(dinv);
   if (isfinite(lb) && lb * (1.0 - 1e-12) * es > 1.0) return true;
-  // Definiteness tests, with tau = 1 / es: theta <= lambda_max < mu
-  // (power iteration, then mu I - M positive definite).  M - theta/tau I
-  // not positive definite gives lambda_min <= theta/tau <= lambda_max/tau
-  // (fires); M - mu/tau I positive definite gives lambda_min > lambda_max/tau
-  // (does not fire).  Only a lambda_min between the two shifts is left to
-  // the eigenvalues.
+  // Definiteness tests, with tau = 1 / es, which bound lambda_min exactly:
+  // M - l/tau I positive definite gives lambda_min > l/tau, not positive
+  // definite lambda_min <= l/tau.  First against the bounds on lambda_max
+  // above (M - lmax_hi/tau I positive definite: does not fire; M -
+  // lmax_lo/tau I not positive definite: fires), which decides every
+  // kappa_D farther from the threshold than their ratio; then with
+  // theta <= lambda_max < mu (Lanczos estimate, then mu I - M positive
+  // definite): M - theta/tau I not positive definite fires, M - mu/tau I
+  // positive definite does not.  Only a lambda_min between the last two
+  // shifts is left to the eigenvalues.
   for (int e = tid(); e < s * s; e += kSB) {
     const int i = ds.q(e), j = ds.r(e);
     M[e] = alpha[e] * rs[i] * rs[j];
   }
   __syncthreads();
-  const double theta = rf_power_lmax<SM>(M, s), mu = theta * (1.0 + 1e-3);
+  if (isfinite(lmax_hi) && rf_definite<SM>(M, s, 1.0, -lmax_hi * es)) return false;
+  if (isfinite(lmax_lo) && !rf_definite<SM>(M, s, 1.0, -lmax_lo * es)) return true;
+  const double theta = lanczos_lmax<SM>(M, s), mu = theta * (1.0 + 1e-3);
   if (theta > 0.0 && isfinite(theta) && rf_definite<SM>(M, s, -1.0, mu)) {
     if (!rf_definite<SM>(M, s, 1.0, -theta * es)) return true;
     if (rf_definite<SM>(M, s, 1.0, -mu * es)) return false;
@@ -1190,11 +1262,21 @@ __device__ __forceinline__ void cg_alpha_body(CgCtl* c, const double* G, const d
   // deferred X update: if the previous iteration's term is still owed, keep
   // its lambda sigma; this iteration's update then adds both, otherwise it
   // defers its own term
+  // (the copy is loaded here and stored before the new lambda sigma, so
+  // that no wait for it falls on the critical path)
   const int xin = c->xdef_pend;
+  SmRegs<SM * SM, double> r_ls;
+  SmRegs<SM * SM, float> r_lsf;
   if (xin) {
-    sm_fetch<kSS>(c->lamsig_prev, c->lamsig, s * s);
-    sm_fetch<kSS>(c->lamsig_prev_f, c->lamsig_f, s * s);
+    sm_load(r_ls, c->lamsig, s * s);
+    sm_load(r_lsf, c->lamsig_f, s * s);
   }
+  auto keep_prev = [&] {
+    if (xin) {
+      sm_store(c->lamsig_prev, r_ls, s * s);
+      sm_store(c->lamsig_prev_f, r_lsf, s * s);
+    }
+  };
   __syncthreads();
   if (tid() == 0) {
     c->xdef_in = xin;
@@ -1204,6 +1286,7 @@ __device__ __forceinline__ void cg_alpha_body(CgCtl* c, const double* G, const d
   sm_project(Al, sub, red);
   bool ok = all_finite(Al, s * s, red);
   if (!ok) {
+    keep_prev();
     if (tid() == 0) {
       c->status = -3;
       c->done = 1;
@@ -1214,6 +1297,7 @@ __device__ __forceinline__ void cg_alpha_body(CgCtl* c, const double* G, const d
   }
   // lambda = alpha^-1 rho, and L^-1 when the kappa_D test needs its bound
   if (!rf_cholesky_solve<SM>(Al, rho_l, Lm, reortho_dynamic(c) ? T : nullptr, s)) {
+    keep_prev();
     if (tid() == 0) {
       c->status = -2;
       c->done = 1;
@@ -1226,6 +1310,7 @@ __device__ __forceinline__ void cg_alpha_body(CgCtl* c, const double* G, const d
   // the coefficients go to global memory after the kappa_D test: a workgroup
   // barrier after a global store waits for the store
   const bool fire = reortho_test<SM>(c, Al, W, T, rc, rs, partner, first, red);
+  keep_prev();
   __syncthreads();
   store_coeff(c->lam, c->lam_f, Lm, s);
   store_coeff(c->lamsig, c->lamsig_f, LS, s);
@@ -1485,26 +1570,36 @@ __global__ __launch_bounds__(EPI == EPI_NONE ? kRedPlain : kSB) void reduce_kern
   __shared__ double pre_rho[EPI != EPI_NONE ? kSS : 1], pre_sig[EPI != EPI_NONE ? kSS : 1];
   __shared__ double pre_r0n[NORMS ? kMaxS : 1];
   const int ss = s * s, m = (EPI == EPI_NONE ? ng : NG) * ss;
+  // Every load of the prologue is issued before the first wait: the control
+  // words and the epilogue's inputs from the control block (kept in
+  // registers; only the last workgroup stores them to LDS), then, once the
+  // gate is known, the partials.
+  SmRegs<SM * SM, double> r_rho, r_sig;
+  SmRegs<SM, double> r_r0n;
+  int32_t cdone = 0, cgate = 0, gv = 0, fv = 1;
   if constexpr (EPI != EPI_NONE) {
-    // the epilogue's inputs from the control block, loaded along with the
-    // partials (only the last workgroup uses them)
-    sm_fetch<SM * SM>(pre_rho, c->rho, ss);
-    sm_fetch<SM * SM>(pre_sig, c->sigma, ss);
-    if constexpr (NORMS) sm_fetch<SM>(pre_r0n, c->r0n, s);
+    if constexpr (EPI == EPI_CG_ALPHA) cdone = c->done;
+    cgate = c->gate;
+    sm_load(r_rho, c->rho, ss);
+    sm_load(r_sig, c->sigma, ss);
+    if constexpr (NORMS) sm_load(r_r0n, c->r0n, s);
+  } else {
+    if (gate) gv = *gate;
+    if (fire) fv = *fire;
   }
   if constexpr (EPI == EPI_CG_ALPHA) {
-    if (c->done) {  // ended: nothing of this iteration reaches X (owed terms were added)
+    if (cdone) {  // ended: nothing of this iteration reaches X (owed terms were added)
       if (blockIdx.x == 0 && tid() == 0) {
         c->x_pending = 0;
         c->xdef_in = 0;
       }
       return;
     }
-    if (c->gate) return;  // suspended: the iteration waits for its re-normalisation
+    if (cgate) return;  // suspended: the iteration waits for its re-normalisation
   } else if constexpr (NORMS) {
-    if (c->gate) return;
+    if (cgate) return;
   } else {
-    if ((gate && *gate) || (fire && !*fire)) return;
+    if (gv || !fv) return;
   }
   const int ns = gridDim.x, sl = blockIdx.x, y = blockIdx.y;
   const T* P = partial + (int64_t)y * nblk * m;
@@ -1526,6 +1621,11 @@ __global__ __launch_bounds__(EPI == EPI_NONE ? kRedPlain : kSB) void reduce_kern
     if constexpr (EPI != EPI_NONE) Gl[e] = v;
   }
   if (tid() == 0) *cnt = 0;
+  if constexpr (EPI != EPI_NONE) {
+    sm_store(pre_rho, r_rho, ss);
+    sm_store(pre_sig, r_sig, ss);
+    if constexpr (NORMS) sm_store(pre_r0n, r_r0n, s);
+  }
   if constexpr (EPI == EPI_CG_ALPHA) {
     __syncthreads();
     cg_alpha_body<SM>(c, Gl, pre_rho, pre_sig);
@@ -1543,12 +1643,23 @@ __global__ __launch_bounds__(EPI == EPI_NONE ? kRedPlain : kSB) void reduce_kern
 // sum s x s partials of s > 16 several times faster than the single
 // wavefront an epilogue runs on).  Same gating and inputs as the fused form.
 template <int EPI, int SM>
-__global__ __launch_bounds__(kSB) void cg_epi_kernel(const double* G, CgCtl* c, double* hist) {
+__global__ __launch_bounds__(kSB) void cg_epi_kernel(int s, const double* G, CgCtl* c, double* hist) {
   constexpr bool RHO = EPI == EPI_CG_RHO || EPI == EPI_CG_RHO_M;
   constexpr int NG = (EPI == EPI_CG_RHO_M || EPI == EPI_CG_1R) ? 2 : 1;
   __shared__ double pre_rho[kSS], pre_sig[kSS], pre_r0n[kMaxS], Gl[NG * kSS];
+  // the control words and every input block are requested before the first
+  // wait (s = c->s, passed by the host)
+  const int ss = s * s;
+  const int32_t cdone = EPI == EPI_CG_ALPHA ? c->done : 0, cgate = c->gate;
+  SmRegs<SM * SM, double> r_rho, r_sig;
+  SmRegs<SM, double> r_r0n;
+  SmRegs<NG * SM * SM, double> r_g;
+  sm_load(r_rho, c->rho, ss);
+  sm_load(r_sig, c->sigma, ss);
+  sm_load(r_r0n, c->r0n, s);
+  sm_load(r_g, G, NG * ss);
   if constexpr (EPI == EPI_CG_ALPHA) {
-    if (c->done) {
+    if (cdone) {
       if (tid() == 0) {
         c->x_pending = 0;
         c->xdef_in = 0;
@@ -1556,12 +1667,11 @@ __global__ __launch_bounds__(kSB) void cg_epi_kernel(const double* G, CgCtl* c, 
       return;
     }
   }
-  if (c->gate) return;
-  const int s = c->s, ss = s * s;
-  sm_fetch<kSS>(pre_rho, c->rho, ss);
-  sm_fetch<kSS>(pre_sig, c->sigma, ss);
-  sm_fetch<kMaxS>(pre_r0n, c->r0n, s);
-  sm_fetch<NG * kSS>(Gl, G, NG * ss);
+  if (cgate) return;
+  sm_store(pre_rho, r_rho, ss);
+  sm_store(pre_sig, r_sig, ss);
+  sm_store(pre_r0n, r_r0n, s);
+  sm_store(Gl, r_g, NG * ss);
   __syncthreads();
   if constexpr (EPI == EPI_CG_ALPHA) {
     cg_alpha_body<SM>(c, Gl, pre_rho, pre_sig);
@@ -1642,13 +1752,13 @@ static hipError_t launch_reduce_t(int s, const T* partial, int nblk, int batch, 
     const int ng = (epi.kind == EPI_CG_RHO_M || epi.kind == EPI_CG_1R) ? 2 : 1;
     launch_reduce_plain<T>(ng * s * s, partial, nblk, 1, red, &epi.ctl->gate, nullptr, s, ng, st);
     if (epi.kind == EPI_CG_ALPHA)
-      hipLaunchKernelGGL((cg_epi_kernel<EPI_CG_ALPHA, 32>), dim3(1), dim3(kSB), 0, st, red.G, epi.ctl, epi.hist);
+      hipLaunchKernelGGL((cg_epi_kernel<EPI_CG_ALPHA, 32>), dim3(1), dim3(kSB), 0, st, s, red.G, epi.ctl, epi.hist);
     else if (epi.kind == EPI_CG_RHO)
-      hipLaunchKernelGGL((cg_epi_kernel<EPI_CG_RHO, 32>), dim3(1), dim3(kSB), 0, st, red.G, epi.ctl, epi.hist);
+      hipLaunchKernelGGL((cg_epi_kernel<EPI_CG_RHO, 32>), dim3(1), dim3(kSB), 0, st, s, red.G, epi.ctl, epi.hist);
     else if (epi.kind == EPI_CG_RHO_M)
-      hipLaunchKernelGGL((cg_epi_kernel<EPI_CG_RHO_M, 32>), dim3(1), dim3(kSB), 0, st, red.G, epi.ctl, epi.hist);
+      hipLaunchKernelGGL((cg_epi_kernel<EPI_CG_RHO_M, 32>), dim3(1), dim3(kSB), 0, st, s, red.G, epi.ctl, epi.hist);
     else
-      hipLaunchKernelGGL((cg_epi_kernel<EPI_CG_1R, 32>), dim3(1), dim3(kSB), 0, st, red.G, epi.ctl, epi.hist);
+      hipLaunchKernelGGL((cg_epi_kernel<EPI_CG_1R, 32>), dim3(1), dim3(kSB), 0, st, s, red.G, epi.ctl, epi.hist);
     return hipGetLastError();
   }
   return dispatch_sm(s, [&](auto SM_) -> hipError_t {
