@@ -353,14 +353,6 @@ __device__ __forceinline__ double readlane_d(double v, int lane) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-// X = A^-1 B for SPD A (s x s, s <= SM, LDS) through A = L L^T, and, if Linv
-// is not null, Linv = L^-1 (LDS; zero above the diagonal).  The factor lives
-// in registers, lane i holding row i; each right-hand side column lives in
-// the registers of its own lane; entries of L reach the other lanes by lane
-// reads, so the whole factor-and-solve runs without LDS round trips.  The
-// reciprocals of the pivots are formed once, so the only divisions are the
-// s reciprocals.  Returns false (uniformly) on a non-positive or non-finite
-// pivot.
 // In-register Cholesky of A (s x s, s <= SM, LDS): on return lane i holds
 // row i of L in l (entries above the diagonal are left over from A) and
 // rinv[k] = 1 / L_kk in every lane.  False (uniformly) on a non-positive or
@@ -382,8 +374,9 @@ __device__ __forceinline__ bool rf_factor(const double* A, int s, double (&l)[SM
     if (k < s) {
       const double d = readlane_d(l[k], k);
       if (!(d > 0.0) || !isfinite(d)) return false;
-      const double lkk = sqrt(d);
-      rinv[k] = 1.0 / lkk;
+      // pivot reciprocal d^-1/2 first, L_kk = d d^-1/2 (no division)
+      rinv[k] = rsqrt(d);
+      const double lkk = d * rinv[k];
       if (t == k)
         l[k] = lkk;
       else if (t > k)
@@ -424,9 +417,8 @@ __device__ __forceinline__ void rf_linv_column(const double (&l)[SM], const doub
 // in registers, lane i holding row i; each right-hand side column lives in
 // the registers of its own lane; entries of L reach the other lanes by lane
 // reads, so the whole factor-and-solve runs without LDS round trips.  The
-// reciprocals of the pivots are formed once, so the only divisions are the
-// s reciprocals.  Returns false (uniformly) on a non-positive or non-finite
-// pivot.
+// pivots' reciprocal square roots are formed once, so there is no division.
+// Returns false (uniformly) on a non-positive or non-finite pivot.
 template <int SM, bool EX>
 __device__ __forceinline__ bool rf_cholesky_solve_x(const double* A, const double* B, double* X, double* Linv, int s) {
   if constexpr (EX) s = SM;
@@ -1544,6 +1536,9 @@ __device__ __forceinline__ double sum_strided(const T* __restrict__ p, int64_t s
     T v[K];
 #pragma unroll
     for (int u = 0; u < K; ++u) v[u] = p[(int64_t)min(b + u, count - 1) * stride];
+    // keep the scheduler from moving the first adds (and so the first
+    // wait) in between the loads: all K are in flight before the first wait
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int u = 0; u < K; ++u)
       if (b + u < count) acc += (double)v[u];
