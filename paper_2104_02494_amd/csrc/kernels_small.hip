@@ -1050,8 +1050,34 @@ __device__ __forceinline__ double lanczos_lmax(const double* A, int s) {
 
 // The re-orthonormalisation is decided per iteration (the L^-1 bound of the
 // kappa_D test is needed) only for 0 < eta < inf, eta sqrt(eps) <= 1, g > 1.
-__device__ __forceinline__ bool reortho_dynamic(const CgCtl* c) {
-  return c->eta > 0.0 && !isinf(c->eta) && !(c->eta * c->sqrt_eps > 1.0) && c->g > 1;
+// The control block's scalars that a coefficient step reads, loaded in one
+// batch at its start (the control block is written during the step, so the
+// compiler cannot keep its fields in scalar loads, and every separate read
+// would cost a memory round trip before its use).
+struct CgHead {
+  int32_t s, kind, g, fire, iters, maxit, hist_cap, dynamic, xdef_pend, lam_iter;
+  double tol, eta, sqrt_eps;
+};
+__device__ __forceinline__ CgHead cg_head(const CgCtl* c) {
+  CgHead h;
+  h.s = c->s;
+  h.kind = c->kind;
+  h.g = c->g;
+  h.fire = c->fire;
+  h.iters = c->iters;
+  h.maxit = c->maxit;
+  h.hist_cap = c->hist_cap;
+  h.dynamic = c->dynamic;
+  h.xdef_pend = c->xdef_pend;
+  h.lam_iter = c->lam_iter;
+  h.tol = c->tol;
+  h.eta = c->eta;
+  h.sqrt_eps = c->sqrt_eps;
+  return h;
+}
+
+__device__ __forceinline__ bool reortho_dynamic(const CgHead& h) {
+  return h.eta > 0.0 && !isinf(h.eta) && !(h.eta * h.sqrt_eps > 1.0) && h.g > 1;
 }
 
 // The kappa_D test of the iteration.  T holds L^-1 (alpha = L L^T) whenever
@@ -1064,13 +1090,13 @@ __device__ __forceinline__ bool reortho_dynamic(const CgCtl* c) {
 // M = D^-1/2 alpha D^-1/2, and only when both leave it open by the Jacobi
 // eigenvalues of M.
 template <int SM>
-__device__ __forceinline__ bool reortho_test(CgCtl* c, const double* alpha, double* M, double* T, double* rc,
-                                             double* rs, int* partner, int* first, double* red) {
-  if (!(c->eta > 0.0)) return false;
-  if (isinf(c->eta)) return true;
-  const int s = c->s;
-  if (c->eta * c->sqrt_eps > 1.0) return true;  // kappa_D >= 1
-  if (c->g <= 1) return false;                  // kappa_D = 1
+__device__ __forceinline__ bool reortho_test(CgCtl* c, const CgHead& h, const double* alpha, double* M, double* T,
+                                             double* rc, double* rs, int* partner, int* first, double* red) {
+  if (!(h.eta > 0.0)) return false;
+  if (isinf(h.eta)) return true;
+  const int s = h.s;
+  if (h.eta * h.sqrt_eps > 1.0) return true;  // kappa_D >= 1
+  if (h.g <= 1) return false;                 // kappa_D = 1
   __syncthreads();
   // Guaranteed bounds on kappa_D = lambda_max(M) / lambda_min(M) for
   // M = D^-1/2 alpha D^-1/2 = L_M L_M^T, L_M^-1 = L^-1 D^1/2 (T holds L^-1):
@@ -1112,7 +1138,7 @@ __device__ __forceinline__ bool reortho_test(CgCtl* c, const double* alpha, doub
   }
   const double nF = sqrt(wsum(fm)), nInf = wmax(rowM);
   const double ub = fmin(nF * wsum(li), fmin(nF, nInf) * wmax(colL) * wmax(rowL));
-  const double es = c->eta * c->sqrt_eps;
+  const double es = h.eta * h.sqrt_eps;
   if (isfinite(ub) && ub * (1.0 + 1e-12) * es <= 1.0) return false;
   const double lmax_lo = fmax(1.0, wsum(sumM) / s), lmax_hi = fmin(nF, nInf);
   const double lb = lmax_lo * wmax(dinv);
@@ -1142,7 +1168,7 @@ __device__ __forceinline__ bool reortho_test(CgCtl* c, const double* alpha, doub
   __syncthreads();
   const double kd = sm_kappaD(alpha, s, M, T, rc, rs, partner, first, red);
   if (tid() == 0) c->kd_jacobi += 1;
-  return c->eta * kd * c->sqrt_eps > 1.0;
+  return h.eta * kd * h.sqrt_eps > 1.0;
 }
 
 __device__ __forceinline__ void store_coeff(double* d64, float* d32, const double* src, int s) {
@@ -1244,19 +1270,19 @@ hipError_t launch_cg_init(CgCtl* ctl, const double* G_R0, const double* G_rho, h
 // Runs only while the solve is live and not suspended (the caller checks).
 // rho_l, sigma_l: copies of c->rho and c->sigma (LDS, loaded by the caller).
 template <int SM>
-__device__ __forceinline__ void cg_alpha_body(CgCtl* c, const double* G, const double* rho_l,
+__device__ __forceinline__ void cg_alpha_body(CgCtl* c, const CgHead& h, const double* G, const double* rho_l,
                                               const double* sigma_l) {
   __shared__ double Al[kSS], Lm[kSS], LS[kSS], W[kSS], T[kSS];
   __shared__ double rc[kMaxS], rs[kMaxS], red[4];
   __shared__ int partner[kMaxS], first[kMaxS];
-  const int s = c->s;
-  const Sub sub{c->kind, s, c->g};
+  const int s = h.s;
+  const Sub sub{h.kind, s, h.g};
   // deferred X update: if the previous iteration's term is still owed, keep
   // its lambda sigma; this iteration's update then adds both, otherwise it
   // defers its own term
   // (the copy is loaded here and stored before the new lambda sigma, so
   // that no wait for it falls on the critical path)
-  const int xin = c->xdef_pend;
+  const int xin = h.xdef_pend;
   SmRegs<SM * SM, double> r_ls;
   SmRegs<SM * SM, float> r_lsf;
   if (xin) {
@@ -1288,7 +1314,7 @@ __device__ __forceinline__ void cg_alpha_body(CgCtl* c, const double* G, const d
     return;
   }
   // lambda = alpha^-1 rho, and L^-1 when the kappa_D test needs its bound
-  if (!rf_cholesky_solve<SM>(Al, rho_l, Lm, reortho_dynamic(c) ? T : nullptr, s)) {
+  if (!rf_cholesky_solve<SM>(Al, rho_l, Lm, reortho_dynamic(h) ? T : nullptr, s)) {
     keep_prev();
     if (tid() == 0) {
       c->status = -2;
@@ -1301,7 +1327,7 @@ __device__ __forceinline__ void cg_alpha_body(CgCtl* c, const double* G, const d
   sm_mm(LS, Lm, sigma_l, s, false);  // lambda sigma
   // the coefficients go to global memory after the kappa_D test: a workgroup
   // barrier after a global store waits for the store
-  const bool fire = reortho_test<SM>(c, Al, W, T, rc, rs, partner, first, red);
+  const bool fire = reortho_test<SM>(c, h, Al, W, T, rc, rs, partner, first, red);
   keep_prev();
   __syncthreads();
   store_coeff(c->lam, c->lam_f, Lm, s);
@@ -1319,13 +1345,13 @@ __device__ __forceinline__ void cg_alpha_body(CgCtl* c, const double* G, const d
 // checks the gate).
 // rho_l, sigma_l, r0n_l: copies of c->rho, c->sigma and c->r0n (LDS).
 template <int SM>
-__device__ __forceinline__ void cg_rho_body(CgCtl* c, const double* G, double* hist, const double* rho_l,
+__device__ __forceinline__ void cg_rho_body(CgCtl* c, const CgHead& h, const double* G, double* hist, const double* rho_l,
                                             const double* sigma_l, const double* r0n_l, const double* Gz) {
   __shared__ double Gm[kSS], T1[kSS], Bt[kSS];
   __shared__ double red[4];
   __shared__ int flag[1];
-  const int s = c->s;
-  const Sub sub{c->kind, s, c->g};
+  const int s = h.s;
+  const Sub sub{h.kind, s, h.g};
   const double* Sg = sigma_l;
   sm_copy(Gm, G, s * s);
   sm_mm(T1, Gm, Sg, s, false);  // G sigma
@@ -1345,29 +1371,30 @@ __device__ __forceinline__ void cg_rho_body(CgCtl* c, const double* G, double* h
   const double m = wmax(rel);
   const bool nan = wany(nanl);
   if (tid() == 0) {
-    const int it = c->iters;
-    if (hist && it < c->hist_cap) hist[it] = nan ? NAN : m;
+    const int it = h.iters;
+    if (hist && it < h.hist_cap) hist[it] = nan ? NAN : m;
     c->iters = it + 1;
-    if (c->fire) c->nreorth += 1;
+    if (h.fire) c->nreorth += 1;
     int state = 0;  // 0 continue, 1 ended
     if (nan) {
       c->status = -3;
       state = 1;
-    } else if (m <= c->tol) {
+    } else if (m <= h.tol) {
       c->converged = 1;
       state = 1;
-    } else if (it + 1 >= c->maxit) {
+    } else if (it + 1 >= h.maxit) {
       state = 1;
     }
     c->done = state;
     // a dynamically decided re-normalisation suspends the iteration; the host
     // launches it at its next read-back
-    c->suspended = (!state && c->fire && c->dynamic) ? 1 : 0;
-    c->gate = state | c->suspended;
+    const int susp = (!state && h.fire && h.dynamic) ? 1 : 0;
+    c->suspended = susp;
+    c->gate = state | susp;
     flag[0] = state;
   }
   __syncthreads();
-  if (flag[0] || c->fire) return;
+  if (flag[0] || h.fire) return;
   // rho' = <Z, R~>_S, beta = rho^-1 rho' (gamma = I); Z = R~ unless a
   // preconditioner's Gram Gz = R~^T M^-1 R~ is given
   if (Gz) {
@@ -1397,14 +1424,14 @@ __device__ __forceinline__ void cg_rho_body(CgCtl* c, const double* G, double* h
 // alpha^k, which decides whether R~^{k+1} is re-normalised.
 // rho_l, sigma_l, r0n_l: copies of c->rho, c->sigma and c->r0n (LDS).
 template <int SM>
-__device__ __forceinline__ void cg1r_body(CgCtl* c, const double* G, double* hist, const double* rho_l,
+__device__ __forceinline__ void cg1r_body(CgCtl* c, const CgHead& h, const double* G, double* hist, const double* rho_l,
                                           const double* sigma_l, const double* r0n_l) {
   __shared__ double Rh[kSS], Dl[kSS], T1[kSS], Bt[kSS], Al[kSS], Lm[kSS], W[kSS], Tt[kSS];
   __shared__ double rc[kMaxS], rs[kMaxS], red[4];
   __shared__ int partner[kMaxS], first[kMaxS], flag[1];
-  const int s = c->s, ss = s * s;
-  const Sub sub{c->kind, s, c->g};
-  const int k = c->lam_iter + 1;
+  const int s = h.s, ss = s * s;
+  const Sub sub{h.kind, s, h.g};
+  const int k = h.lam_iter + 1;
   auto fail = [&](int status) {
     if (tid() == 0) {
       c->status = status;
@@ -1428,16 +1455,16 @@ __device__ __forceinline__ void cg1r_body(CgCtl* c, const double* G, double* his
     const double m = wmax(rel);
     const bool nan = wany(nanl);
     if (tid() == 0) {
-      if (hist && k - 1 < c->hist_cap) hist[k - 1] = nan ? NAN : m;
+      if (hist && k - 1 < h.hist_cap) hist[k - 1] = nan ? NAN : m;
       c->iters = k;
       int state = 0;
       if (nan) {
         c->status = -3;
         state = 1;
-      } else if (m <= c->tol) {
+      } else if (m <= h.tol) {
         c->converged = 1;
         state = 1;
-      } else if (k >= c->maxit) {
+      } else if (k >= h.maxit) {
         state = 1;
       }
       c->done = state;
@@ -1453,7 +1480,7 @@ __device__ __forceinline__ void cg1r_body(CgCtl* c, const double* G, double* his
   sm_project(Dl, sub, red);
   if (!all_finite(Rh, ss, red) || !all_finite(Dl, ss, red)) return fail(-3);
   if (k > 0) {
-    if (c->fire) {  // gamma^T rho'
+    if (h.fire) {  // gamma^T rho'
       sm_copy(W, c->gamma, ss);
       sm_mm(T1, W, Rh, s, true);
     } else {
@@ -1471,10 +1498,10 @@ __device__ __forceinline__ void cg1r_body(CgCtl* c, const double* G, double* his
     }
   }
   if (!all_finite(Al, ss, red)) return fail(-3);
-  if (!rf_cholesky_solve<SM>(Al, Rh, Lm, reortho_dynamic(c) ? Tt : nullptr, s)) return fail(-2);
+  if (!rf_cholesky_solve<SM>(Al, Rh, Lm, reortho_dynamic(h) ? Tt : nullptr, s)) return fail(-2);
   sm_mm(T1, Lm, sigma_l, s, false);  // lambda sigma
   // global stores after the kappa_D test (see cg_alpha_body)
-  const bool fire = reortho_test<SM>(c, Al, W, Tt, rc, rs, partner, first, red);
+  const bool fire = reortho_test<SM>(c, h, Al, W, Tt, rc, rs, partner, first, red);
   __syncthreads();
   sm_fetch<kSS>(c->lamsig_prev, c->lamsig, ss);
   store_coeff(c->lam, c->lam_f, Lm, s);
@@ -1487,8 +1514,9 @@ __device__ __forceinline__ void cg1r_body(CgCtl* c, const double* G, double* his
     c->lam_iter = k;
     // a dynamically decided re-normalisation suspends the iteration after
     // its fused pass; the host launches it at its next read-back
-    c->suspended = (fire && c->dynamic) ? 1 : 0;
-    c->gate = c->suspended;
+    const int susp = (fire && h.dynamic) ? 1 : 0;
+    c->suspended = susp;
+    c->gate = susp;
   }
 }
 
@@ -1572,9 +1600,11 @@ __global__ __launch_bounds__(EPI == EPI_NONE ? kRedPlain : kSB) void reduce_kern
   SmRegs<SM * SM, double> r_rho, r_sig;
   SmRegs<SM, double> r_r0n;
   int32_t cdone = 0, cgate = 0, gv = 0, fv = 1;
+  CgHead h{};
   if constexpr (EPI != EPI_NONE) {
     if constexpr (EPI == EPI_CG_ALPHA) cdone = c->done;
     cgate = c->gate;
+    h = cg_head(c);
     sm_load(r_rho, c->rho, ss);
     sm_load(r_sig, c->sigma, ss);
     if constexpr (NORMS) sm_load(r_r0n, c->r0n, s);
@@ -1623,13 +1653,13 @@ __global__ __launch_bounds__(EPI == EPI_NONE ? kRedPlain : kSB) void reduce_kern
   }
   if constexpr (EPI == EPI_CG_ALPHA) {
     __syncthreads();
-    cg_alpha_body<SM>(c, Gl, pre_rho, pre_sig);
+    cg_alpha_body<SM>(c, h, Gl, pre_rho, pre_sig);
   } else if constexpr (RHO) {
     __syncthreads();
-    cg_rho_body<SM>(c, Gl, hist, pre_rho, pre_sig, pre_r0n, NG == 2 ? Gl + ss : nullptr);
+    cg_rho_body<SM>(c, h, Gl, hist, pre_rho, pre_sig, pre_r0n, NG == 2 ? Gl + ss : nullptr);
   } else if constexpr (EPI == EPI_CG_1R) {
     __syncthreads();
-    cg1r_body<SM>(c, Gl, hist, pre_rho, pre_sig, pre_r0n);
+    cg1r_body<SM>(c, h, Gl, hist, pre_rho, pre_sig, pre_r0n);
   }
 }
 
@@ -1646,6 +1676,7 @@ __global__ __launch_bounds__(kSB) void cg_epi_kernel(int s, const double* G, CgC
   // wait (s = c->s, passed by the host)
   const int ss = s * s;
   const int32_t cdone = EPI == EPI_CG_ALPHA ? c->done : 0, cgate = c->gate;
+  const CgHead h = cg_head(c);
   SmRegs<SM * SM, double> r_rho, r_sig;
   SmRegs<SM, double> r_r0n;
   SmRegs<NG * SM * SM, double> r_g;
@@ -1669,11 +1700,11 @@ __global__ __launch_bounds__(kSB) void cg_epi_kernel(int s, const double* G, CgC
   sm_store(Gl, r_g, NG * ss);
   __syncthreads();
   if constexpr (EPI == EPI_CG_ALPHA) {
-    cg_alpha_body<SM>(c, Gl, pre_rho, pre_sig);
+    cg_alpha_body<SM>(c, h, Gl, pre_rho, pre_sig);
   } else if constexpr (RHO) {
-    cg_rho_body<SM>(c, Gl, hist, pre_rho, pre_sig, pre_r0n, NG == 2 ? Gl + ss : nullptr);
+    cg_rho_body<SM>(c, h, Gl, hist, pre_rho, pre_sig, pre_r0n, NG == 2 ? Gl + ss : nullptr);
   } else {
-    cg1r_body<SM>(c, Gl, hist, pre_rho, pre_sig, pre_r0n);
+    cg1r_body<SM>(c, h, Gl, hist, pre_rho, pre_sig, pre_r0n);
   }
 }
 
@@ -1924,7 +1955,7 @@ __global__ __launch_bounds__(kSB) void bc_lambda_kernel(CgCtl* c, BcAux* x, cons
   __syncthreads();
   bool fire;
   if (rf_cholesky_factor<SM>(Am, Lo, Li, s))
-    fire = reortho_test<SM>(c, Am, W, Li, rc, rs, partner, first, red);
+    fire = reortho_test<SM>(c, cg_head(c), Am, W, Li, rc, rs, partner, first, red);
   else
     fire = c->eta > 0.0;  // not positive definite: kappa_D = infinity
   __syncthreads();
@@ -2404,26 +2435,32 @@ __global__ __launch_bounds__(kSB) void gm_step_kernel(GmCtl* c, int k, double* H
   // The new column, h_jk = H1_j + H2_j for j <= k (blocks j < k are replaced
   // by their rotated values below); with staging, also every previous
   // rotation's factor and block j + 1 of the new column into LDS.  Loads in
-  // chunks of 8 per lane, all issued before the chunk's stores.
+  // chunks of U per lane, all issued before the chunk's stores: the loads
+  // are unconditional (indexes past the end re-read the last entry) and a
+  // scheduling barrier keeps them ahead of the first use, so a chunk costs
+  // one memory round trip.
   {
-    constexpr int U = 32;
+    constexpr int U = 16;
     const int total = (k + 1) * ss;
     for (int base = 0; base < total; base += U * kSB) {
-      double v[U];
+      double a[U], b[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const int t = base + t0 + u * kSB;
-        v[u] = t < total ? H1[t] + H2[t] : 0.0;
+        const int t = min(base + t0 + u * kSB, total - 1);
+        a[u] = H1[t];
+        b[u] = H2[t];
       }
+      __builtin_amdgcn_sched_barrier(0);
       // block j and entry e of t = base + t0 + u kSB, advanced by kSB per
       // u (one division per batch instead of one per entry)
       int j = (base + t0) / ss, e = base + t0 - j * ss;
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int t = base + t0 + u * kSB;
+        const double v = a[u] + b[u];
         if (t < total) {
-          H[((int64_t)j * m + k) * ss + e] = v[u];
-          if (staged && j >= 1) stage[(j - 1) * (NO + SM * SM) + NO + e] = v[u];
+          H[((int64_t)j * m + k) * ss + e] = v;
+          if (staged && j >= 1) stage[(j - 1) * (NO + SM * SM) + NO + e] = v;
         }
         e += kSB;
         while (e >= ss) {
@@ -2437,10 +2474,8 @@ __global__ __launch_bounds__(kSB) void gm_step_kernel(GmCtl* c, int k, double* H
       for (int base = 0; base < tot; base += U * kSB) {
         double v[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const int t = base + t0 + u * kSB;
-          v[u] = t < tot ? Om[t] : 0.0;
-        }
+        for (int u = 0; u < U; ++u) v[u] = Om[min(base + t0 + u * kSB, tot - 1)];
+        __builtin_amdgcn_sched_barrier(0);
         int j = (base + t0) / no, e = base + t0 - j * no;
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -2756,15 +2791,25 @@ __global__ __launch_bounds__(kSB) void gm_backsub8_kernel(GmCtl* c, const double
   const int s = c->s, g = c->g, m = c->m, ss = s * s, kend = c->kend;
   const int q = tid();
   const bool own = q < ss;
+  if (kend <= 0) return;
+  // loads are unconditional (indexes outside the used range re-read a valid
+  // entry, never stored), so that all of a batch are in flight at once
+  const int qq = own ? q : 0;
   double hv[NB];
   auto load_col = [&](int j) {  // H_lj, l <= j, entry q
 #pragma unroll
-    for (int l = 0; l < NB; ++l) hv[l] = (own && l <= j) ? H[((int64_t)l * m + j) * ss + q] : 0.0;
+    for (int l = 0; l < NB; ++l) hv[l] = H[((int64_t)(l <= j ? l : j) * m + j) * ss + qq];
   };
   load_col(kend - 1);
+  {
+    double sv[NB];
 #pragma unroll
-  for (int l = 0; l < NB; ++l)
-    if (own && l < kend) rhs[l * SS + q] = sig[(int64_t)l * ss + q];
+    for (int l = 0; l < NB; ++l) sv[l] = sig[(int64_t)(l < kend ? l : kend - 1) * ss + qq];
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int l = 0; l < NB; ++l)
+      if (own && l < kend) rhs[l * SS + q] = sv[l];
+  }
 #pragma unroll
   for (int l = 0; l < NB; ++l)
     if (own && l < kend) hb[l * SS + q] = hv[l];
