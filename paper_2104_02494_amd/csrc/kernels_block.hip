@@ -740,6 +740,30 @@ __device__ __forceinline__ void load_coeff(T* dst, const T* src, int s) {
   }
 }
 
+// load_coeff in two halves, so that the loads of several coefficient
+// matrices are in flight together: the entries (clamped indexes, always a
+// valid address) into registers, then (zero outside s x s) into LDS.
+template <typename T, int S>
+struct CoeffRegs {
+  T v[(S * S + kBlock - 1) / kBlock];
+};
+template <typename T, int S>
+__device__ __forceinline__ void coeff_load(CoeffRegs<T, S>& r, const T* src, int s) {
+#pragma unroll
+  for (int u = 0; u < (S * S + kBlock - 1) / kBlock; ++u) {
+    const int t = min((int)threadIdx.x + u * kBlock, S * S - 1), a = t / S, b = t % S;
+    r.v[u] = src[min(a, s - 1) * s + min(b, s - 1)];
+  }
+}
+template <typename T, int S>
+__device__ __forceinline__ void coeff_store(T* dst, const CoeffRegs<T, S>& r, int s) {
+#pragma unroll
+  for (int u = 0; u < (S * S + kBlock - 1) / kBlock; ++u) {
+    const int t = (int)threadIdx.x + u * kBlock, a = t / S, b = t % S;
+    if (t < S * S) dst[t] = (a < s && b < s) ? r.v[u] : T(0);
+  }
+}
+
 // R~ = R - Q lambda (in place in R); Gram partials of R~^T R~, and with
 // PC also of R~^T M^-1 R~ (M^-1 = diag(minv)), stored side by side.
 template <typename T, int S, int VEC, bool PC>
@@ -752,8 +776,12 @@ __global__ __launch_bounds__(kBlock) void cg_update_kernel(int64_t n, int s, T* 
   constexpr int RPB = NW * L::RPW;
   __shared__ T lam[S * S];
   __shared__ T sh[NW * S * S];
-  if (ctl->gate) return;
-  load_coeff<T, S>(lam, ctl_mat<T>(ctl, 0), s);
+  // the gate and the coefficients are requested together
+  const int32_t gate = ctl->gate;
+  CoeffRegs<T, S> rl;
+  coeff_load<T, S>(rl, ctl_mat<T>(ctl, 0), s);
+  if (gate) return;
+  coeff_store<T, S>(lam, rl, s);
   __syncthreads();
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
   const int r = lane / L::LPR, c = lane % L::LPR;
@@ -912,17 +940,24 @@ __global__ __launch_bounds__(kBlock) void cg_pupdate_kernel(int64_t n, int s, T*
   constexpr int NW = kBlock / kWave;
   constexpr int RPB = NW * L::RPW;
   __shared__ T ls[S * S], lp[S * S], bt[S * S];
-  if (ctl->suspended) return;
-  const bool done = ctl->done != 0;
-  const bool xk = ctl->x_pending != 0;  // this iteration's alpha step ran
-  const bool xin = ctl->xdef_in != 0;   // the previous P's term is owed
+  // the control words, then every coefficient matrix, requested before the
+  // first wait for them
+  const int32_t susp = ctl->suspended, dn = ctl->done, xp = ctl->x_pending, xd = ctl->xdef_in;
+  if (susp) return;
+  const bool done = dn != 0;
+  const bool xk = xp != 0;   // this iteration's alpha step ran
+  const bool xin = xd != 0;  // the previous P's term is owed
   if (!xk && !xin) return;
   const bool flush = done || xin;
   const bool addk = xk && flush;
   const bool pdir = xk && !done;
-  if (addk) load_coeff<T, S>(ls, ctl_mat<T>(ctl, 1), s);
-  if (xin) load_coeff<T, S>(lp, ctl_prev<T>(ctl), s);
-  if (pdir) load_coeff<T, S>(bt, ctl_mat<T>(ctl, 2), s);
+  CoeffRegs<T, S> rls, rlp, rbt;
+  if (addk) coeff_load<T, S>(rls, ctl_mat<T>(ctl, 1), s);
+  if (xin) coeff_load<T, S>(rlp, ctl_prev<T>(ctl), s);
+  if (pdir) coeff_load<T, S>(rbt, ctl_mat<T>(ctl, 2), s);
+  if (addk) coeff_store<T, S>(ls, rls, s);
+  if (xin) coeff_store<T, S>(lp, rlp, s);
+  if (pdir) coeff_store<T, S>(bt, rbt, s);
   __syncthreads();
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
   const int r = lane / L::LPR, c = lane % L::LPR;
@@ -1075,17 +1110,22 @@ __global__ __launch_bounds__(kBlock) void gropp_dir_kernel(int64_t n, int s, dou
   constexpr int RPB = NW * L::RPW;
   __shared__ T ls[S * S], lp[S * S], bt[S * S];
   __shared__ T sh[NW * S * S];
-  if (ctl->suspended) return;
-  const bool done = ctl->done != 0;
-  const bool xk = ctl->x_pending != 0;
-  const bool xin = ctl->xdef_in != 0;
+  const int32_t susp = ctl->suspended, dn = ctl->done, xp = ctl->x_pending, xd = ctl->xdef_in;
+  if (susp) return;
+  const bool done = dn != 0;
+  const bool xk = xp != 0;
+  const bool xin = xd != 0;
   if (!xk && !xin) return;
   const bool flush = done || xin;
   const bool addk = xk && flush;
   const bool pdir = xk && !done;
-  if (addk) load_coeff<T, S>(ls, ctl->lamsig, s);
-  if (xin) load_coeff<T, S>(lp, ctl->lamsig_prev, s);
-  if (pdir) load_coeff<T, S>(bt, ctl->beta, s);
+  CoeffRegs<T, S> rls, rlp, rbt;
+  if (addk) coeff_load<T, S>(rls, ctl->lamsig, s);
+  if (xin) coeff_load<T, S>(rlp, ctl->lamsig_prev, s);
+  if (pdir) coeff_load<T, S>(rbt, ctl->beta, s);
+  if (addk) coeff_store<T, S>(ls, rls, s);
+  if (xin) coeff_store<T, S>(lp, rlp, s);
+  if (pdir) coeff_store<T, S>(bt, rbt, s);
   __syncthreads();
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
   const int r = lane / L::LPR, c = lane % L::LPR;

@@ -33,6 +33,30 @@ __device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+// Entries (4 kk + lr, 16 tj + lc) of the s x s matrix C (zero outside s x s)
+// for every k-step kk and tile tj, scaled by sign.  The loads read clamped
+// indexes, are all issued before a scheduling barrier and are consumed
+// through an empty asm, so the compiler can neither put a load under the
+// bounds test nor wait for one before the next is issued: the operands cost
+// one memory round trip.
+template <int NK, int NT>
+__device__ __forceinline__ void coeff_operand(const double* C, int s, double sign, int lr, int lc,
+                                              double (&cb)[NK][NT]) {
+#pragma unroll
+  for (int kk = 0; kk < NK; ++kk)
+#pragma unroll
+    for (int tj = 0; tj < NT; ++tj) cb[kk][tj] = C[min(4 * kk + lr, s - 1) * s + min(16 * tj + lc, s - 1)];
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int kk = 0; kk < NK; ++kk)
+#pragma unroll
+    for (int tj = 0; tj < NT; ++tj) {
+      double v = cb[kk][tj];
+      asm volatile("" : "+v"(v));
+      cb[kk][tj] = (4 * kk + lr < s && 16 * tj + lc < s) ? sign * v : 0.0;
+    }
+}
+
 // Sum the wavefronts' S x S tiles (acc[ti][tj], lane layout above) into the
 // workgroup's partial.  sh: kMW * S * S doubles of LDS.
 // pstride: distance of consecutive workgroups' partials (0: s * s).  Safe to
@@ -149,13 +173,7 @@ __global__ __launch_bounds__(kBlock) void rowmul_mfma_kernel(int64_t n, int s, d
   const int lr = lane / 16, lc = lane % 16;
   // B operands: C[4 kk + lr][16 tj + lc], zero outside s x s
   double cb[NK][NT];
-#pragma unroll
-  for (int kk = 0; kk < NK; ++kk)
-#pragma unroll
-    for (int tj = 0; tj < NT; ++tj) {
-      const int a = 4 * kk + lr, b = 16 * tj + lc;
-      cb[kk][tj] = (a < s && b < s) ? C[a * s + b] : 0.0;
-    }
+  coeff_operand<NK, NT>(C, s, 1.0, lr, lc, cb);
   d4 g[GRAM ? NT : 1][GRAM ? NT : 1];
   if constexpr (GRAM) {
 #pragma unroll
@@ -259,19 +277,6 @@ __device__ __forceinline__ void tile_acc_store(double* __restrict__ Y, int64_t n
       const int64_t row = tb + 4 * v + lr;
       const int col = 16 * tj + lc;
       if (row < n && col < s) __builtin_nontemporal_store(y[tj][v], Y + row * s + col);
-    }
-}
-// B operands of an s x s coefficient matrix C scaled by sign: element
-// (4 kk + lr, 16 tj + lc), zero outside s x s.
-template <int NK, int NT>
-__device__ __forceinline__ void coeff_operand(const double* C, int s, double sign, int lr, int lc,
-                                              double (&cb)[NK][NT]) {
-#pragma unroll
-  for (int kk = 0; kk < NK; ++kk)
-#pragma unroll
-    for (int tj = 0; tj < NT; ++tj) {
-      const int a = 4 * kk + lr, b = 16 * tj + lc;
-      cb[kk][tj] = (a < s && b < s) ? sign * C[a * s + b] : 0.0;
     }
 }
 template <int NK, int NT>
