@@ -94,7 +94,7 @@ def spmm_bytes(A, s, elem=8):
     return (A.n + 1) * 4 + A.nnz * 4 + A.nnz * elem + 2 * A.n * s * elem
 
 
-def cpu_baseline(A, B, iters_a=2, iters_b=16):
+def cpu_baseline(A, B, iters_a=2, iters_b=36):
     """Oracle block CG on the same workload; the per-iteration time is the
     difference of two bounded runs, so set-up is excluded."""
     import oracle
