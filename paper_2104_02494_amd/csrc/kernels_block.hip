@@ -32,6 +32,9 @@ namespace bkry {
 constexpr int kUnroll = 8;
 // Workgroups per gang of the ELL SpMM (see gang_rows).
 constexpr int kGang = 8;
+// Chunks of a row whose matrix entries the ELL SpMM requests ahead (rows of
+// more than one chunk).
+constexpr int kPfChunks = 3;
 
 
 // Store of a streaming output.
@@ -397,7 +400,7 @@ __global__ __launch_bounds__(kBlock) void spmm_csr_kernel(int64_t n, int64_t nnz
 // rows; gangs of kGang workgroups sweep one row range together (gang_rows),
 // so an XCD runs few concurrent row fronts and the X rows that neighbouring
 // rows share (a banded or stencil pattern) are still in its L2 when reused.
-template <typename T, int S, int VEC, int MODE>
+template <typename T, int S, int VEC, int MODE, bool PF = false>
 __global__ __launch_bounds__(kBlock) void spmm_ell_kernel(int64_t n, int W, const int32_t* __restrict__ ecol,
                                                            const T* __restrict__ eval, int s,
                                                            const T* __restrict__ X, T* __restrict__ Y,
@@ -503,12 +506,33 @@ __global__ __launch_bounds__(kBlock) void spmm_ell_kernel(int64_t n, int W, cons
     if (MODE == 1 && rv) own = load_vec<T, VEC>(X + row * s + col0);
     if (MODE == 2 && rv) own = load_vec<T, VEC>(B + row * s + col0);
     vec_t<T, VEC> acc = zero_vec<T, VEC>();
-    chunk(cj, ca, rv, acc);
-    for (int j = 1; j < nch; ++j) {
-      vec_t<int32_t, E> kj;
-      vec_t<T, E> ka;
-      ld(row, j, kj, ka);
-      chunk(kj, ka, rv, acc);
+    if constexpr (PF) {
+      // rows of several chunks (wide stencils): the entries of chunks 1 ..
+      // kPfChunks are requested before the first chunk's gathers, so a row
+      // waits for its matrix entries once instead of once per chunk
+      vec_t<int32_t, E> pj[kPfChunks];
+      vec_t<T, E> pa[kPfChunks];
+#pragma unroll
+      for (int q = 0; q < kPfChunks; ++q)
+        if (1 + q < nch) ld(row, 1 + q, pj[q], pa[q]);
+      chunk(cj, ca, rv, acc);
+#pragma unroll
+      for (int q = 0; q < kPfChunks; ++q)
+        if (1 + q < nch) chunk(pj[q], pa[q], rv, acc);
+      for (int j = 1 + kPfChunks; j < nch; ++j) {
+        vec_t<int32_t, E> kj;
+        vec_t<T, E> ka;
+        ld(row, j, kj, ka);
+        chunk(kj, ka, rv, acc);
+      }
+    } else {
+      chunk(cj, ca, rv, acc);
+      for (int j = 1; j < nch; ++j) {
+        vec_t<int32_t, E> kj;
+        vec_t<T, E> ka;
+        ld(row, j, kj, ka);
+        chunk(kj, ka, rv, acc);
+      }
     }
     if (MODE == 2) {
 #pragma unroll
@@ -552,6 +576,14 @@ static int fit_grid(int nblk) {
   return (cap >= 8 && nblk > cap) ? cap : nblk;
 }
 
+// Whether the ELL rows of width W span several chunks (the prefetching
+// form of the ELL SpMM).
+template <int S, int V>
+static bool ell_prefetch(int W) {
+  constexpr int LPR = S / V;
+  return W / (LPR * ell_entries_per_lane(LPR)) > 1;
+}
+
 template <typename T>
 hipError_t launch_spmm(const CsrView& A, int s, const T* X, T* Y, const T* B, int mode, T* partial, int nblk,
                        Red red, int32_t* bad, const int32_t* done, hipStream_t st, Epi epi, hipEvent_t ev_after,
@@ -575,19 +607,26 @@ hipError_t launch_spmm(const CsrView& A, int s, const T* X, T* Y, const T* B, in
     const T* val = static_cast<const T*>(A.val);
     if (A.ell_w > 0) {
       const T* ev = static_cast<const T*>(A.ell_val);
-      if (mode == 0) {
-        nblk = fit_grid<spmm_ell_kernel<T, S, V, 0>>(nblk);
-        hipLaunchKernelGGL((spmm_ell_kernel<T, S, V, 0>), dim3(nblk), dim3(kBlock), 0, st, A.n, A.ell_w, A.ell_col,
-                           ev, s, X, Y, B, partial, done, pstride);
-      } else if (mode == 1) {
-        nblk = fit_grid<spmm_ell_kernel<T, S, V, 1>>(nblk);
-        hipLaunchKernelGGL((spmm_ell_kernel<T, S, V, 1>), dim3(nblk), dim3(kBlock), 0, st, A.n, A.ell_w, A.ell_col,
-                           ev, s, X, Y, B, partial, done, pstride);
-      } else {
-        nblk = fit_grid<spmm_ell_kernel<T, S, V, 2>>(nblk);
-        hipLaunchKernelGGL((spmm_ell_kernel<T, S, V, 2>), dim3(nblk), dim3(kBlock), 0, st, A.n, A.ell_w, A.ell_col,
-                           ev, s, X, Y, B, partial, done, pstride);
-      }
+      auto go = [&](auto PF_) {
+        constexpr bool PF = decltype(PF_)::value;
+        if (mode == 0) {
+          nblk = fit_grid<spmm_ell_kernel<T, S, V, 0, PF>>(nblk);
+          hipLaunchKernelGGL((spmm_ell_kernel<T, S, V, 0, PF>), dim3(nblk), dim3(kBlock), 0, st, A.n, A.ell_w,
+                             A.ell_col, ev, s, X, Y, B, partial, done, pstride);
+        } else if (mode == 1) {
+          nblk = fit_grid<spmm_ell_kernel<T, S, V, 1, PF>>(nblk);
+          hipLaunchKernelGGL((spmm_ell_kernel<T, S, V, 1, PF>), dim3(nblk), dim3(kBlock), 0, st, A.n, A.ell_w,
+                             A.ell_col, ev, s, X, Y, B, partial, done, pstride);
+        } else {
+          nblk = fit_grid<spmm_ell_kernel<T, S, V, 2, PF>>(nblk);
+          hipLaunchKernelGGL((spmm_ell_kernel<T, S, V, 2, PF>), dim3(nblk), dim3(kBlock), 0, st, A.n, A.ell_w,
+                             A.ell_col, ev, s, X, Y, B, partial, done, pstride);
+        }
+      };
+      if (ell_prefetch<S, V>(A.ell_w))
+        go(std::true_type{});
+      else
+        go(std::false_type{});
       return hipGetLastError();
     }
     if (mode == 0)
@@ -618,7 +657,11 @@ int spmm_grid(const CsrView& A, int s, int mode, int nblk) {
   int out = nblk;
   (void)dispatch_s<T>(s, [&](auto S_, auto V_) -> hipError_t {
     constexpr int S = decltype(S_)::value, V = decltype(V_)::value;
-    if (A.ell_w > 0)
+    if (A.ell_w > 0 && ell_prefetch<S, V>(A.ell_w))
+      out = mode == 0 ? fit_grid<spmm_ell_kernel<T, S, V, 0, true>>(nblk)
+                      : (mode == 1 ? fit_grid<spmm_ell_kernel<T, S, V, 1, true>>(nblk)
+                                   : fit_grid<spmm_ell_kernel<T, S, V, 2, true>>(nblk));
+    else if (A.ell_w > 0)
       out = mode == 0 ? fit_grid<spmm_ell_kernel<T, S, V, 0>>(nblk)
                       : (mode == 1 ? fit_grid<spmm_ell_kernel<T, S, V, 1>>(nblk)
                                    : fit_grid<spmm_ell_kernel<T, S, V, 2>>(nblk));
