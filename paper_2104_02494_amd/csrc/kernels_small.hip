@@ -1772,19 +1772,29 @@ static hipError_t launch_reduce_t(int s, const T* partial, int nblk, int batch, 
       (epi.kind != EPI_CG_ALPHA && epi.kind != EPI_CG_RHO && epi.kind != EPI_CG_RHO_M && epi.kind != EPI_CG_1R))
     return hipErrorInvalidValue;
   if ((epi.kind == EPI_CG_RHO_M || epi.kind == EPI_CG_1R) && sizeof(T) != 8) return hipErrorInvalidValue;
-  if (s > 16) {
-    // wide Grams: plain reduction (gated like the epilogue), then the
-    // coefficient step in its own single-wavefront launch
+  if (s >= 16) {
+    // wide Grams (256 entries and more): plain reduction (gated like the
+    // epilogue), then the coefficient step in its own single-wavefront
+    // launch; the fused form's single wavefront would sum the partials in
+    // s^2 / 64 dependent batches
     const int ng = (epi.kind == EPI_CG_RHO_M || epi.kind == EPI_CG_1R) ? 2 : 1;
     launch_reduce_plain<T>(ng * s * s, partial, nblk, 1, red, &epi.ctl->gate, nullptr, s, ng, st);
-    if (epi.kind == EPI_CG_ALPHA)
-      hipLaunchKernelGGL((cg_epi_kernel<EPI_CG_ALPHA, 32>), dim3(1), dim3(kSB), 0, st, s, red.G, epi.ctl, epi.hist);
-    else if (epi.kind == EPI_CG_RHO)
-      hipLaunchKernelGGL((cg_epi_kernel<EPI_CG_RHO, 32>), dim3(1), dim3(kSB), 0, st, s, red.G, epi.ctl, epi.hist);
-    else if (epi.kind == EPI_CG_RHO_M)
-      hipLaunchKernelGGL((cg_epi_kernel<EPI_CG_RHO_M, 32>), dim3(1), dim3(kSB), 0, st, s, red.G, epi.ctl, epi.hist);
+    auto go = [&](auto SM_) {
+      constexpr int SM = decltype(SM_)::value;
+      if (epi.kind == EPI_CG_ALPHA)
+        hipLaunchKernelGGL((cg_epi_kernel<EPI_CG_ALPHA, SM>), dim3(1), dim3(kSB), 0, st, s, red.G, epi.ctl, epi.hist);
+      else if (epi.kind == EPI_CG_RHO)
+        hipLaunchKernelGGL((cg_epi_kernel<EPI_CG_RHO, SM>), dim3(1), dim3(kSB), 0, st, s, red.G, epi.ctl, epi.hist);
+      else if (epi.kind == EPI_CG_RHO_M)
+        hipLaunchKernelGGL((cg_epi_kernel<EPI_CG_RHO_M, SM>), dim3(1), dim3(kSB), 0, st, s, red.G, epi.ctl,
+                           epi.hist);
+      else
+        hipLaunchKernelGGL((cg_epi_kernel<EPI_CG_1R, SM>), dim3(1), dim3(kSB), 0, st, s, red.G, epi.ctl, epi.hist);
+    };
+    if (s > 16)
+      go(std::integral_constant<int, 32>{});
     else
-      hipLaunchKernelGGL((cg_epi_kernel<EPI_CG_1R, 32>), dim3(1), dim3(kSB), 0, st, s, red.G, epi.ctl, epi.hist);
+      go(std::integral_constant<int, 16>{});
     return hipGetLastError();
   }
   return dispatch_sm(s, [&](auto SM_) -> hipError_t {
