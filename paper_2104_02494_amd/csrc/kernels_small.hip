@@ -96,8 +96,26 @@ __device__ __forceinline__ double wmax(double v) {
 }
 __device__ __forceinline__ bool wany(bool b) { return __any(b ? 1 : 0) != 0; }
 
+// dst[0 .. count) = src[0 .. count) (LDS or global, not overlapping), in
+// batches of 8 entries per lane whose loads (clamped indexes) are all issued
+// before the batch's stores: from global memory a batch costs one round trip,
+// where the plain loop waited for every entry.
 __device__ __forceinline__ void sm_copy(double* dst, const double* src, int count) {
-  for (int t = tid(); t < count; t += kSB) dst[t] = src[t];
+  constexpr int U = 8;
+  for (int base = 0; base < count; base += U * kSB) {
+    double v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int t = base + tid() + u * kSB;
+      v[u] = src[t < count ? t : count - 1];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int t = base + tid() + u * kSB;
+      if (t < count) dst[t] = v[u];
+    }
+  }
 }
 
 // dst = src (count <= N entries, typically global memory into LDS) with every
@@ -2094,11 +2112,13 @@ template <int SM>
 __global__ __launch_bounds__(kSB) void cholqr_kernel(int stage, const double* G, Sub sub, double* R1, double* Rinv,
                                                       double* N, int32_t* plan, double ratio_min, const int32_t* gd,
                                                       const int32_t* gf) {
-  __shared__ double Gm[kSS], L[kSS], Li[kSS];
+  __shared__ double Gm[kSS], L[kSS], Li[kSS], R1l[kSS];
   __shared__ double red[4];
   const int s = sub.s, t = tid();
+  // the gates and the plan flag are read in one batch
+  const int32_t gdv = gd ? *gd : 0, gfv = gf ? *gf : 1, p0 = plan[0];
   if (stage == 1) {
-    if ((gd && *gd) || (gf && !*gf)) {
+    if (gdv || !gfv) {
       if (t == 0) {
         plan[0] = 0;
         plan[1] = 0;
@@ -2106,7 +2126,7 @@ __global__ __launch_bounds__(kSB) void cholqr_kernel(int stage, const double* G,
       }
       return;
     }
-  } else if (!plan[0]) {
+  } else if (!p0) {
     return;
   }
   sm_copy(Gm, G, s * s);
@@ -2168,11 +2188,13 @@ __global__ __launch_bounds__(kSB) void cholqr_kernel(int stage, const double* G,
     }
   } else {
     if (ok) {
+      sm_copy(R1l, R1, s * s);
+      __syncthreads();
       for (int e = t; e < s * s; e += kSB) {
         const int i = e / s, j = e % s;
         Rinv[e] = Li[j * s + i];
         double acc = 0.0;  // (L^T R1)_ij
-        for (int k = 0; k < s; ++k) acc = fma(L[k * s + i], R1[k * s + j], acc);
+        for (int k = 0; k < s; ++k) acc = fma(L[k * s + i], R1l[k * s + j], acc);
         N[e] = acc;
       }
     }
