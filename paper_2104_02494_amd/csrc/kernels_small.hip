@@ -1950,9 +1950,11 @@ __global__ __launch_bounds__(kSB) void bc_lambda_kernel(CgCtl* c, BcAux* x, cons
   __shared__ double Am[kSS], Bm[kSS], Lm[kSS], Sg[kSS], T1[kSS], Lo[kSS], Li[kSS], W[kSS];
   __shared__ double rc[kMaxS], rs[kMaxS], red[4];
   __shared__ int partner[kMaxS], first[kMaxS], piv[1];
-  if (c->done) return;
-  const int s = c->s, ss = s * s;
-  const Sub sub{c->kind, s, c->g};
+  const int32_t cdone = c->done;
+  const CgHead h = cg_head(c);  // before any write to the control block
+  if (cdone) return;
+  const int s = h.s, ss = s * s;
+  const Sub sub{h.kind, s, h.g};
   // a = <R~0, Q>_S = proj((Q^T R~0)^T), <R~0, R>_S likewise
   for (int t = tid(); t < ss; t += kSB) {
     const int i = t / s, j = t % s;
@@ -1983,9 +1985,9 @@ __global__ __launch_bounds__(kSB) void bc_lambda_kernel(CgCtl* c, BcAux* x, cons
   __syncthreads();
   bool fire;
   if (rf_cholesky_factor<SM>(Am, Lo, Li, s))
-    fire = reortho_test<SM>(c, cg_head(c), Am, W, Li, rc, rs, partner, first, red);
+    fire = reortho_test<SM>(c, h, Am, W, Li, rc, rs, partner, first, red);
   else
-    fire = c->eta > 0.0;  // not positive definite: kappa_D = infinity
+    fire = h.eta > 0.0;  // not positive definite: kappa_D = infinity
   __syncthreads();
   if (tid() == 0) {
     c->fire = fire ? 1 : 0;
@@ -2046,8 +2048,11 @@ __global__ __launch_bounds__(kSB) void bc_omega_kernel(CgCtl* c, BcAux* x, const
 
 __global__ __launch_bounds__(kSB) void bc_stop_kernel(CgCtl* c, const double* Grr, double* hist) {
   __shared__ double Gm[kSS], Sg[kSS], T1[kSS];
-  if (c->done) return;
-  const int s = c->s;
+  const int32_t cdone = c->done;
+  const CgHead h = cg_head(c);  // before any write to the control block
+  if (cdone) return;
+  const int s = h.s;
+  const double r0i = tid() < s ? c->r0n[tid()] : 0.0;
   sm_copy(Gm, Grr, s * s);
   sm_copy(Sg, c->sigma, s * s);
   sm_mm(T1, Gm, Sg, s, false);  // G sigma
@@ -2057,7 +2062,7 @@ __global__ __launch_bounds__(kSB) void bc_stop_kernel(CgCtl* c, const double* Gr
     double acc = 0.0;
 #pragma unroll 8
     for (int a = 0; a < s; ++a) acc += Sg[a * s + i] * T1[a * s + i];
-    const double r = c->r0n[i] > 0.0 ? sqrt(fmax(acc, 0.0)) / c->r0n[i] : 0.0;
+    const double r = r0i > 0.0 ? sqrt(fmax(acc, 0.0)) / r0i : 0.0;
     nanl |= !isfinite(acc);
     c->relres[i] = r;
     rel = fmax(rel, r);
@@ -2065,16 +2070,16 @@ __global__ __launch_bounds__(kSB) void bc_stop_kernel(CgCtl* c, const double* Gr
   const double m = wmax(rel);
   const bool nan = wany(nanl);
   if (tid() == 0) {
-    const int it = c->iters;
-    if (hist && it < c->hist_cap) hist[it] = nan ? NAN : m;
+    const int it = h.iters;
+    if (hist && it < h.hist_cap) hist[it] = nan ? NAN : m;
     c->iters = it + 1;
     if (nan) {
       c->status = -3;
       c->done = 1;
-    } else if (m <= c->tol) {
+    } else if (m <= h.tol) {
       c->converged = 1;
       c->done = 1;
-    } else if (it + 1 >= c->maxit) {
+    } else if (it + 1 >= h.maxit) {
       c->done = 1;
     }
   }
