@@ -1287,7 +1287,13 @@ hipError_t launch_cg_init(CgCtl* ctl, const double* G_R0, const double* G_rho, h
 // alpha = <P, Q>_S; lambda = alpha^-1 rho; lambda sigma; the kappa_D test.
 // Runs only while the solve is live and not suspended (the caller checks).
 // rho_l, sigma_l: copies of c->rho and c->sigma (LDS, loaded by the caller).
-template <int SM>
+// PART: kAlphaAll does everything; a launch of two workgroups splits the
+// step into kAlphaCoef (lambda, lambda sigma, the deferred X bookkeeping;
+// every failure is reported there) and kAlphaKappa (the kappa_D test on its
+// own factorisation of the same alpha, writing only the fire flag), which
+// run side by side: neither output depends on the other.
+constexpr int kAlphaAll = 0, kAlphaCoef = 1, kAlphaKappa = 2;
+template <int SM, int PART = kAlphaAll>
 __device__ __forceinline__ void cg_alpha_body(CgCtl* c, const CgHead& h, const double* G, const double* rho_l,
                                               const double* sigma_l) {
   __shared__ double Al[kSS], Lm[kSS], LS[kSS], W[kSS], T[kSS];
@@ -1295,6 +1301,17 @@ __device__ __forceinline__ void cg_alpha_body(CgCtl* c, const CgHead& h, const d
   __shared__ int partner[kMaxS], first[kMaxS];
   const int s = h.s;
   const Sub sub{h.kind, s, h.g};
+  if constexpr (PART == kAlphaKappa) {
+    sm_copy(Al, G, s * s);
+    sm_project(Al, sub, red);
+    if (!all_finite(Al, s * s, red)) return;  // reported by the other part
+    // L^-1 for the bounds (W serves as scratch for L); a failed
+    // factorisation is reported by the other part
+    if (reortho_dynamic(h) && !rf_cholesky_factor<SM>(Al, W, T, s)) return;
+    const bool fire = reortho_test<SM>(c, h, Al, W, T, rc, rs, partner, first, red);
+    if (tid() == 0) c->fire = fire ? 1 : 0;
+    return;
+  }
   // deferred X update: if the previous iteration's term is still owed, keep
   // its lambda sigma; this iteration's update then adds both, otherwise it
   // defers its own term
@@ -1332,7 +1349,7 @@ __device__ __forceinline__ void cg_alpha_body(CgCtl* c, const CgHead& h, const d
     return;
   }
   // lambda = alpha^-1 rho, and L^-1 when the kappa_D test needs its bound
-  if (!rf_cholesky_solve<SM>(Al, rho_l, Lm, reortho_dynamic(h) ? T : nullptr, s)) {
+  if (!rf_cholesky_solve<SM>(Al, rho_l, Lm, (PART == kAlphaAll && reortho_dynamic(h)) ? T : nullptr, s)) {
     keep_prev();
     if (tid() == 0) {
       c->status = -2;
@@ -1345,14 +1362,15 @@ __device__ __forceinline__ void cg_alpha_body(CgCtl* c, const CgHead& h, const d
   sm_mm(LS, Lm, sigma_l, s, false);  // lambda sigma
   // the coefficients go to global memory after the kappa_D test: a workgroup
   // barrier after a global store waits for the store
-  const bool fire = reortho_test<SM>(c, h, Al, W, T, rc, rs, partner, first, red);
+  bool fire = false;
+  if constexpr (PART == kAlphaAll) fire = reortho_test<SM>(c, h, Al, W, T, rc, rs, partner, first, red);
   keep_prev();
   __syncthreads();
   store_coeff(c->lam, c->lam_f, Lm, s);
   store_coeff(c->lamsig, c->lamsig_f, LS, s);
   sm_copy(c->alpha, Al, s * s);
   if (tid() == 0) {
-    c->fire = fire ? 1 : 0;
+    if constexpr (PART == kAlphaAll) c->fire = fire ? 1 : 0;
     c->x_pending = 1;
   }
 }
@@ -1704,7 +1722,7 @@ __global__ __launch_bounds__(kSB) void cg_epi_kernel(int s, const double* G, CgC
   sm_load(r_g, G, NG * ss);
   if constexpr (EPI == EPI_CG_ALPHA) {
     if (cdone) {
-      if (tid() == 0) {
+      if (blockIdx.x == 0 && tid() == 0) {
         c->x_pending = 0;
         c->xdef_in = 0;
       }
@@ -1718,7 +1736,12 @@ __global__ __launch_bounds__(kSB) void cg_epi_kernel(int s, const double* G, CgC
   sm_store(Gl, r_g, NG * ss);
   __syncthreads();
   if constexpr (EPI == EPI_CG_ALPHA) {
-    cg_alpha_body<SM>(c, h, Gl, pre_rho, pre_sig);
+    // launched with two workgroups: the coefficients and the kappa_D test
+    // side by side
+    if (blockIdx.x == 0)
+      cg_alpha_body<SM, kAlphaCoef>(c, h, Gl, pre_rho, pre_sig);
+    else
+      cg_alpha_body<SM, kAlphaKappa>(c, h, Gl, pre_rho, pre_sig);
   } else if constexpr (RHO) {
     cg_rho_body<SM>(c, h, Gl, hist, pre_rho, pre_sig, pre_r0n, NG == 2 ? Gl + ss : nullptr);
   } else {
@@ -1800,7 +1823,7 @@ static hipError_t launch_reduce_t(int s, const T* partial, int nblk, int batch, 
     auto go = [&](auto SM_) {
       constexpr int SM = decltype(SM_)::value;
       if (epi.kind == EPI_CG_ALPHA)
-        hipLaunchKernelGGL((cg_epi_kernel<EPI_CG_ALPHA, SM>), dim3(1), dim3(kSB), 0, st, s, red.G, epi.ctl, epi.hist);
+        hipLaunchKernelGGL((cg_epi_kernel<EPI_CG_ALPHA, SM>), dim3(2), dim3(kSB), 0, st, s, red.G, epi.ctl, epi.hist);
       else if (epi.kind == EPI_CG_RHO)
         hipLaunchKernelGGL((cg_epi_kernel<EPI_CG_RHO, SM>), dim3(1), dim3(kSB), 0, st, s, red.G, epi.ctl, epi.hist);
       else if (epi.kind == EPI_CG_RHO_M)
