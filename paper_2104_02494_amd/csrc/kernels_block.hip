@@ -1083,8 +1083,11 @@ __global__ __launch_bounds__(kBlock) void gropp_update_kernel(int64_t n, int s, 
   constexpr int RPB = NW * L::RPW;
   __shared__ T lam[S * S];
   __shared__ T sh[NW * S * S];
-  if (ctl->gate) return;
-  load_coeff<T, S>(lam, ctl->lam, s);
+  const int32_t gate = ctl->gate;
+  CoeffRegs<T, S> rl;
+  coeff_load<T, S>(rl, ctl->lam, s);
+  if (gate) return;
+  coeff_store<T, S>(lam, rl, s);
   __syncthreads();
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
   const int r = lane / L::LPR, c = lane % L::LPR;
@@ -1256,12 +1259,20 @@ __global__ __launch_bounds__(kBlock) void bc_tail_rs_kernel(int64_t n, int s, do
   constexpr int NW = kBlock / kWave;
   constexpr int RPB = NW * L::RPW;
   __shared__ T cl[S * S], co[S * S], cu[S * S], cp[S * S], cq[S * S];
-  if (done && *done) return;
-  load_coeff<T, S>(cl, lamsig, s);
-  load_coeff<T, S>(co, omsig, s);
-  load_coeff<T, S>(cu, negomI, s);
-  load_coeff<T, S>(cp, pbeta, s);
-  load_coeff<T, S>(cq, qbeta, s);
+  // the gate and the five coefficient matrices are requested together
+  const int32_t dn = done ? *done : 0;
+  CoeffRegs<T, S> rl, ro, ru, rp, rq;
+  coeff_load<T, S>(rl, lamsig, s);
+  coeff_load<T, S>(ro, omsig, s);
+  coeff_load<T, S>(ru, negomI, s);
+  coeff_load<T, S>(rp, pbeta, s);
+  coeff_load<T, S>(rq, qbeta, s);
+  if (dn) return;
+  coeff_store<T, S>(cl, rl, s);
+  coeff_store<T, S>(co, ro, s);
+  coeff_store<T, S>(cu, ru, s);
+  coeff_store<T, S>(cp, rp, s);
+  coeff_store<T, S>(cq, rq, s);
   __syncthreads();
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
   const int r = lane / L::LPR, c = lane % L::LPR;
@@ -1327,17 +1338,27 @@ __global__ __launch_bounds__(kBlock) void cg1r_pass_kernel(int64_t n, int s, dou
   __shared__ T sh[MODE != 2 ? NW * S * S : 1];
   // MODE 2 runs after the end; MODE 1 with k < 0 (the initial residual)
   // does not depend on a re-normalisation decision
-  if (MODE != 2 && ctl->done) return;
-  if (MODE == 0 && ctl->lam_iter != k) return;
-  if (MODE == 1 && k >= 0 && !ctl->fire) return;
+  // the control words, then the coefficient matrices, requested before the
+  // first wait for them
+  const int32_t cdone = ctl->done, liter = ctl->lam_iter, cfire = ctl->fire;
+  if (MODE != 2 && cdone) return;
+  if (MODE == 0 && liter != k) return;
+  if (MODE == 1 && k >= 0 && !cfire) return;
   const bool first = k == 0, xodd = (k & 1) != 0;
-  const bool gram = MODE == 1 || (MODE == 0 && !ctl->fire);
+  const bool gram = MODE == 1 || (MODE == 0 && !cfire);
   if constexpr (MODE == 0) {
-    load_coeff<T, S>(lam, ctl->lam, s);
-    if (!first) load_coeff<T, S>(bt, ctl->beta, s);
+    CoeffRegs<T, S> rl, rb, rs, rp;
+    coeff_load<T, S>(rl, ctl->lam, s);
+    if (!first) coeff_load<T, S>(rb, ctl->beta, s);
     if (xodd) {
-      load_coeff<T, S>(cs, ctl->lamsig, s);
-      load_coeff<T, S>(cp, ctl->lamsig_prev, s);
+      coeff_load<T, S>(rs, ctl->lamsig, s);
+      coeff_load<T, S>(rp, ctl->lamsig_prev, s);
+    }
+    coeff_store<T, S>(lam, rl, s);
+    if (!first) coeff_store<T, S>(bt, rb, s);
+    if (xodd) {
+      coeff_store<T, S>(cs, rs, s);
+      coeff_store<T, S>(cp, rp, s);
     }
   } else if constexpr (MODE == 2) {
     load_coeff<T, S>(cs, ctl->lamsig, s);
