@@ -97,11 +97,11 @@ __device__ __forceinline__ double wmax(double v) {
 __device__ __forceinline__ bool wany(bool b) { return __any(b ? 1 : 0) != 0; }
 
 // dst[0 .. count) = src[0 .. count) (LDS or global, not overlapping), in
-// batches of 8 entries per lane whose loads (clamped indexes) are all issued
+// batches of U entries per lane whose loads (clamped indexes) are all issued
 // before the batch's stores: from global memory a batch costs one round trip,
 // where the plain loop waited for every entry.
-__device__ __forceinline__ void sm_copy(double* dst, const double* src, int count) {
-  constexpr int U = 8;
+template <int U>
+__device__ __forceinline__ void sm_copy_batched(double* dst, const double* src, int count) {
   for (int base = 0; base < count; base += U * kSB) {
     double v[U];
 #pragma unroll
@@ -115,6 +115,15 @@ __device__ __forceinline__ void sm_copy(double* dst, const double* src, int coun
       const int t = base + tid() + u * kSB;
       if (t < count) dst[t] = v[u];
     }
+  }
+}
+__device__ __forceinline__ void sm_copy(double* dst, const double* src, int count) {
+  if (count <= kSB) {  // one entry per lane (s <= 8)
+    if (tid() < count) dst[tid()] = src[tid()];
+  } else if (count <= 4 * kSB) {
+    sm_copy_batched<4>(dst, src, count);
+  } else {
+    sm_copy_batched<8>(dst, src, count);
   }
 }
 
