@@ -33,6 +33,28 @@ namespace bkry {
 constexpr int kTileRows = 256;  // rows per tile = threads per workgroup
 constexpr int kTW = kTileRows / kWave;
 
+// Row loads of the tile kernels in two halves: row_issue loads the G
+// entries of row p (of the valid fallback row q when !ok; columns past g
+// clamped), so that several rows' loads are in flight together; row_mask
+// then zeroes what lies outside (consuming each value through an empty asm,
+// so that the compiler cannot move a load under the bounds test and wait
+// for it there).
+template <typename U, int G>
+__device__ __forceinline__ void row_issue(U (&v)[G], const U* p, const U* q, bool ok, int g) {
+  const U* r = ok ? p : q;
+#pragma unroll
+  for (int c = 0; c < G; ++c) v[c] = r[c < g ? c : g - 1];
+}
+template <typename T, typename U, int G>
+__device__ __forceinline__ void row_mask(T (&x)[G], U (&v)[G], bool ok, int g) {
+#pragma unroll
+  for (int c = 0; c < G; ++c) {
+    U w = v[c];
+    asm volatile("" : "+v"(w));
+    x[c] = (ok && c < g) ? (T)w : T(0);
+  }
+}
+
 template <int V>
 using ICt = std::integral_constant<int, V>;
 
@@ -151,9 +173,10 @@ __global__ __launch_bounds__(kTileRows) void tsqr_leaf_kernel(int64_t n, int s, 
   const int t = threadIdx.x, tile = blockIdx.x, grp = blockIdx.y;
   const int64_t row = (int64_t)tile * kTileRows + t;
   T* base = X + row * s + grp * g;
-  T x[G];
-#pragma unroll
-  for (int c = 0; c < G; ++c) x[c] = (row < n && c < g) ? base[c] : T(0);
+  T x[G], xr[G];
+  row_issue<T, G>(xr, base, X + grp * g, row < n, g);
+  __builtin_amdgcn_sched_barrier(0);
+  row_mask<T, T, G>(x, xr, row < n, g);
   tile_factor<T, G>(x, g, lds, beta);
   if (row < n) {
 #pragma unroll
@@ -184,9 +207,10 @@ __global__ __launch_bounds__(kTileRows) void tsqr_tree_kernel(int g, int cnt_in,
   const int ridx = tile * nr + t / g, rrow = t % g;
   const bool valid = t < nr * g && ridx < cnt_in;
   double* src = Rin + ((int64_t)grp * cnt_in + ridx) * g * g + rrow * g;
-  double x[G];
-#pragma unroll
-  for (int c = 0; c < G; ++c) x[c] = (valid && c < g) ? src[c] : 0.0;
+  double x[G], xr[G];
+  row_issue<double, G>(xr, src, Rin, valid, g);
+  __builtin_amdgcn_sched_barrier(0);
+  row_mask<double, double, G>(x, xr, valid, g);
   tile_factor<double, G>(x, g, lds, beta);
   if (valid) {
 #pragma unroll
@@ -234,14 +258,14 @@ __global__ __launch_bounds__(kTileRows) void tsqr_down_kernel(int g, int cnt_in,
   const int ridx = tile * nr + t / g, rrow = t % g;
   const bool valid = t < nr * g && ridx < cnt_in;
   const int64_t id = (int64_t)grp * cnt_k + tile;
-  if (t < g) beta[t] = betas[id * g + t];
   const double* src = Rin + ((int64_t)grp * cnt_in + ridx) * g * g + rrow * g;
-  double v[G], z[G];
-#pragma unroll
-  for (int c = 0; c < G; ++c) {
-    v[c] = (valid && c < g) ? src[c] : 0.0;
-    z[c] = (t < g && c < g) ? Mk[id * g * g + t * g + c] : 0.0;
-  }
+  double v[G], z[G], vr[G], zr[G];
+  row_issue<double, G>(vr, src, Rin, valid, g);
+  row_issue<double, G>(zr, Mk + id * g * g + t * g, Mk + id * g * g, t < g, g);
+  if (t < g) beta[t] = betas[id * g + t];
+  __builtin_amdgcn_sched_barrier(0);
+  row_mask<double, double, G>(v, vr, valid, g);
+  row_mask<double, double, G>(z, zr, t < g, g);
   __syncthreads();
   tile_apply<double, G>(z, v, g, beta, lds);
   if (valid) {
@@ -264,14 +288,15 @@ __global__ __launch_bounds__(kTileRows) void tsqr_apply_kernel(int64_t n, int s,
   const int t = threadIdx.x, tile = blockIdx.x, grp = blockIdx.y;
   const int64_t row = (int64_t)tile * kTileRows + t;
   const int64_t id = (int64_t)grp * ntile + tile;
-  if (t < g) beta[t] = betas[id * g + t];
   T* base = X + row * s + grp * g;
-  T v[G], z[G];
-#pragma unroll
-  for (int c = 0; c < G; ++c) {
-    v[c] = (row < n && c < g) ? base[c] : T(0);
-    z[c] = (t < g && c < g) ? (T)M0[id * g * g + t * g + c] : T(0);
-  }
+  T v[G], z[G], vr[G];
+  double zr[G];
+  row_issue<T, G>(vr, base, X + grp * g, row < n, g);
+  row_issue<double, G>(zr, M0 + id * g * g + t * g, M0 + id * g * g, t < g, g);
+  if (t < g) beta[t] = betas[id * g + t];
+  __builtin_amdgcn_sched_barrier(0);
+  row_mask<T, T, G>(v, vr, row < n, g);
+  row_mask<T, double, G>(z, zr, t < g, g);
   __syncthreads();
   tile_apply<T, G>(z, v, g, beta, lds);
   if (row < n) {
