@@ -72,13 +72,16 @@ ETAS = [1e2, 1e3, 1e4, 1e5, 1e6, 1e7]
 
 
 @pytest.mark.parametrize("name,s,kind,q", [("poisson32", 4, "block", 1), ("laplace41", 8, "block", 1),
-                                           ("laplace41", 16, "block", 1), ("laplace41", 16, "hybrid", 2)])
+                                           ("laplace41", 16, "block", 1), ("laplace41", 16, "hybrid", 2),
+                                           ("laplace41", 32, "block", 1)])
 def test_cg_reortho_decisions_match_oracle(orc, h, name, s, kind, q):
     """Intermediate eta: the kappa_D test fires at the same iterations as
     the oracle's (same iteration and re-orthonormalisation counts, same
     residual history).  Each eta is used only where every kappa_D of the
     oracle's run is at least 1e-6 (relative) away from the threshold
-    1 / (eta sqrt(eps)), so that rounding cannot decide."""
+    1 / (eta sqrt(eps)), so that rounding cannot decide.  Histories agree
+    to 1e-6 relative or 1e-13 absolute: perturbing B by one ulp moves the
+    oracle's own s = 32 history by up to 2e-14 in its last steps."""
     if name == "poisson32":
         A, B, _ = W.build_workload("poisson2d_32x32_s4")
     else:
@@ -96,7 +99,7 @@ def test_cg_reortho_decisions_match_oracle(orc, h, name, s, kind, q):
         X, info = gpu_cg(h, A, B, kind=kind, q=q, tol=1e-10, maxit=3000, eta=eta, hist_cap=3000)
         assert info["converged"] and ro["converged"]
         assert (info["iters"], info["reorth"]) == (ro["iters"], ro["reorth"])
-        assert np.allclose(info["hist"], ro["hist"], rtol=1e-6, atol=1e-15)
+        assert np.allclose(info["hist"], ro["hist"], rtol=1e-6, atol=1e-13)
     assert used >= 4
 
 
@@ -135,6 +138,39 @@ def test_cg_edge_cases(orc, h):
     with pytest.raises(P.BkryError) as e:
         gpu_cg(h, A, Bn, eta=0.0, tol=1e-10)
     assert e.value.code == P.E_NONFINITE
+
+
+@pytest.mark.parametrize("s", [16, 32])
+def test_cg_edge_cases_wide(h, s):
+    """The wide blocks' coefficient steps run in launches of their own (the
+    alpha step as two workgroups side by side): their failures must be
+    reported as in the fused form."""
+    A = W.laplace_2d(32)
+    B = W.uniform_block(A.n, s, 7)
+    say("cg wide edges: zero column, eta 0 -> breakdown", s)
+    Bz = B.copy()
+    Bz[:, 3] = 0.0
+    with pytest.raises(P.BkryError) as e:
+        gpu_cg(h, A, Bz, eta=0.0, tol=1e-10)
+    assert e.value.code == P.E_BREAKDOWN
+    say("cg wide edges: zero column, eta inf", s)
+    X, info = gpu_cg(h, A, Bz, eta=np.inf, tol=1e-10, maxit=2000)
+    assert info["converged"] and np.abs(X[:, 3]).max() < 1e-12
+    say("cg wide edges: non-SPD", s)
+    negA = W.Csr(A.n, A.rowptr, A.colind, -A.val)
+    with pytest.raises(P.BkryError) as e:
+        gpu_cg(h, negA, B, eta=0.0)
+    assert e.value.code == P.E_BREAKDOWN
+    say("cg wide edges: nan rhs", s)
+    Bn = B.copy()
+    Bn[5, 1] = np.nan
+    with pytest.raises(P.BkryError) as e:
+        gpu_cg(h, A, Bn, eta=0.0, tol=1e-10)
+    assert e.value.code == P.E_NONFINITE
+    say("cg wide edges: eta 1e4 full solve", s)
+    X, info = gpu_cg(h, A, B, eta=1e4, tol=1e-10, maxit=2000)
+    assert info["converged"] and max(info["true_relres"]) <= 1.5e-10
+    assert rel(X, np.linalg.solve(A.to_dense(), B)) < 1e-8
 
 
 def test_cg_deterministic(h):
