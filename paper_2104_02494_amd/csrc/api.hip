@@ -27,6 +27,7 @@ struct bkry_handle_s {
   int32_t* hflags = nullptr;  // pinned host, kHostFlagsInts
   int32_t* dflags = nullptr;  // device: [0] bad CSR index seen by an asynchronous kernel,
                               // [1] longest CSR row, [2] bad index seen while building an ELL copy,
+                              // [3] row without a diagonal entry seen while building a solver's ELL copy,
                               // [4] bad diagonal seen by bkry_jacobi_minv
   uint32_t* cnt = nullptr;    // device: zeroed grid-reduction counters (left zero by every kernel)
   Prof* prof = nullptr;       // kernel timing, when enabled
@@ -137,18 +138,25 @@ int ell_width_for(bkry_handle h, const bkry_csr* A, int p, int elem_bytes, bool 
 }
 
 // Fill the ELL copy (width W) of A with values val and attach it to v;
-// synchronous, so that a bad column index is reported here.
+// synchronous, so that a bad column index is reported here.  The solvers'
+// copies (diag_first) hold each row's diagonal entry in slot 0 when every row
+// has one (v.ell_diag0), else CSR order.
 template <typename Tin, typename T>
-int ell_build(bkry_handle h, const bkry_csr* A, const Tin* val, int W, int32_t* ecol, T* eval, CsrView& v) {
+int ell_build(bkry_handle h, const bkry_csr* A, const Tin* val, int W, int32_t* ecol, T* eval, CsrView& v,
+              bool diag_first) {
   if (W <= 0) return BKRY_OK;
-  API_HIP(hipMemsetAsync(h->dflags + 2, 0, sizeof(int32_t), h->stream), "ell fill");
-  API_HIP((launch_ell_fill<Tin, T>(view(A), val, W, ecol, eval, h->dflags + 2, h->stream)), "ell fill");
-  API_HIP(hipMemcpyAsync(h->hflags, h->dflags + 2, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream), "ell fill");
+  API_HIP(hipMemsetAsync(h->dflags + 2, 0, 2 * sizeof(int32_t), h->stream), "ell fill");
+  API_HIP((launch_ell_fill<Tin, T>(view(A), val, W, ecol, eval, h->dflags + 2, diag_first ? h->dflags + 3 : nullptr,
+                                   h->stream)),
+          "ell fill");
+  API_HIP(hipMemcpyAsync(h->hflags, h->dflags + 2, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, h->stream),
+          "ell fill");
   API_HIP(hipStreamSynchronize(h->stream), "ell fill");
   if (h->hflags[0]) return fail(h, BKRY_E_INVALID, "a CSR column index was outside [0, n)");
   v.ell_w = W;
   v.ell_col = ecol;
   v.ell_val = eval;
+  v.ell_diag0 = diag_first && h->hflags[1] == 0;
   return BKRY_OK;
 }
 
@@ -360,7 +368,7 @@ int bkry_spmm(bkry_handle h, const bkry_csr* A, int32_t p, const double* X, doub
     Carver w{h->ws};
     int32_t* ecol = w.take<int32_t>((size_t)A->n * W);
     double* eval = w.take<double>((size_t)A->n * W);
-    rc = ell_build<double, double>(h, A, A->val, W, ecol, eval, v);
+    rc = ell_build<double, double>(h, A, A->val, W, ecol, eval, v, false);
     if (rc) return rc;
   }
   const int nblk = stream_grid(A->n, p, sizeof(double));
@@ -390,7 +398,7 @@ int bkry_spmm_f32(bkry_handle h, int64_t n, int64_t nnz, const int32_t* rowptr, 
     Carver w{h->ws};
     int32_t* ecol = w.take<int32_t>((size_t)n * W);
     float* eval = w.take<float>((size_t)n * W);
-    rc = ell_build<float, float>(h, &A, val, W, ecol, eval, v);
+    rc = ell_build<float, float>(h, &A, val, W, ecol, eval, v, false);
     if (rc) return rc;
   }
   const int nblk = stream_grid(n, p, sizeof(float));
@@ -518,7 +526,7 @@ int cg_solve_impl(bkry_handle h, const bkry_csr* A, int32_t p, bkry_subalg S, co
     double* gU = gropp ? w.take<double>((size_t)n * p) : nullptr;
     double* gZ = (gropp && minv) ? w.take<double>((size_t)n * p) : nullptr;
     CsrView v = view(A);
-    rc = ell_build<double, double>(h, A, A->val, W, ecol, eval, v);
+    rc = ell_build<double, double>(h, A, A->val, W, ecol, eval, v, true);
     if (rc) return rc;
     SsorPlan plan;
     if (ssor_colors) {
@@ -567,11 +575,12 @@ int cg_solve_impl(bkry_handle h, const bkry_csr* A, int32_t p, bkry_subalg S, co
     int32_t* ecol = w.take<int32_t>(ne);
     float* eval = w.take<float>(ne);
     CsrView v32 = view(A);
-    rc = ell_build<double, float>(h, A, A->val, W, ecol, eval, v32);
+    rc = ell_build<double, float>(h, A, A->val, W, ecol, eval, v32, true);
     if (rc) return rc;
     ib.ell_w = v32.ell_w;
     ib.ell_col = v32.ell_col;
     ib.ell_val = static_cast<const float*>(v32.ell_val);
+    ib.ell_diag0 = v32.ell_diag0;
     const double itol = (info && info->inner_tol > 0.0) ? info->inner_tol : 1e-5;
     const int mo = (info && info->max_outer > 0) ? info->max_outer : 30;
     IrResult r;
@@ -759,7 +768,7 @@ int gmres_impl(bkry_handle h, const bkry_csr* A, int32_t p, bkry_subalg S, const
   int32_t* ecol = w.take<int32_t>(ne);
   double* eval = w.take<double>(ne);
   CsrView v = view(A);
-  rc = ell_build<double, double>(h, A, A->val, W, ecol, eval, v);
+  rc = ell_build<double, double>(h, A, A->val, W, ecol, eval, v, true);
   if (rc) return rc;
   GmResult r;
   if (maxit > 0) {
@@ -857,7 +866,7 @@ int bkry_bicgstab_solve(bkry_handle h, const bkry_csr* A, int32_t p, bkry_subalg
   double* eval = w.take<double>(ne);
   double* r0save = w.take<double>(kMaxS);
   CsrView v = view(A);
-  rc = ell_build<double, double>(h, A, A->val, W, ecol, eval, v);
+  rc = ell_build<double, double>(h, A, A->val, W, ecol, eval, v, true);
   if (rc) return rc;
   // The recursion's residual can drift from the true one (BiCGStab's residual
   // gap).  When the recursion meets tol but the FP64 true residual does not,

@@ -51,6 +51,7 @@ struct CsrView {
   int ell_w = 0;                    // 0: no ELL copy
   const int32_t* ell_col = nullptr; // [n * ell_w], padding -1
   const void* ell_val = nullptr;    // [n * ell_w], element type of val
+  bool ell_diag0 = false;           // slot 0 of every ELL row holds its diagonal entry
 };
 
 // Device control block of a block CG solve.  The integer header is read back
@@ -363,10 +364,13 @@ int ell_chunk(int s, int elem_bytes);
 // *wmax = longest row of A (enqueued on st; the caller reads it back).
 hipError_t launch_ell_width(const CsrView& A, int32_t* wmax, hipStream_t st);
 // Fill the ELL copy (row width W >= longest row) from A's CSR arrays with
-// values `val` converted to T; bad column indices set *bad = 1.
+// values `val` converted to T; bad column indices set *bad = 1.  nodiag not
+// null: every row's first diagonal entry goes to slot 0 (the entries before
+// it move up by one); a row without one keeps CSR order and sets
+// *nodiag = 1 (the copy then does not qualify as diagonal first).
 template <typename Tin, typename T>
 hipError_t launch_ell_fill(const CsrView& A, const Tin* val, int W, int32_t* ecol, T* eval, int32_t* bad,
-                           hipStream_t st);
+                           int32_t* nodiag, hipStream_t st);
 
 // minv[i] = 1 / A_ii (FP64 values); a missing, non-positive or non-finite
 // diagonal sets *bad = 1.

@@ -393,7 +393,10 @@ __global__ __launch_bounds__(kBlock) void spmm_csr_kernel(int64_t n, int64_t nnz
 // the entries are passed around the row group with lane permutations before
 // the gathers.  The first chunk of the next tile is loaded while the current
 // tile gathers.  Entries are summed in storage order, padding contributing
-// nothing, so the result equals the CSR kernel's bit for bit.
+// nothing: on a copy in CSR order the result equals the CSR kernel's bit for
+// bit.  The solvers' copies hold each row's diagonal entry in slot 0 (diag0):
+// the Gram X^T (A X) of MODE 1 then takes the row's own X values from that
+// entry's gather instead of loading them a second time.
 //
 // Cache use: every matrix line is consumed by one load, so the matrix stream
 // is read with the non-temporal hint and leaves the L2 to the gathered X
@@ -405,7 +408,7 @@ __global__ __launch_bounds__(kBlock) void spmm_ell_kernel(int64_t n, int W, cons
                                                            const T* __restrict__ eval, int s,
                                                            const T* __restrict__ X, T* __restrict__ Y,
                                                            const T* __restrict__ B, T* __restrict__ partial,
-                                                           const int32_t* done, int64_t pstride) {
+                                                           const int32_t* done, int64_t pstride, int diag0) {
   using L = Layout<T, S, VEC>;
   constexpr int LPR = L::LPR;
   constexpr int E = ell_entries_per_lane(LPR);
@@ -449,8 +452,9 @@ __global__ __launch_bounds__(kBlock) void spmm_ell_kernel(int64_t n, int W, cons
   };
   // acc += sum over the chunk's C entries, in storage order
   // (slots of 8 or more lanes share the chunk's entries through LDS, as
-  // lds_row does for rows)
-  auto chunk = [&](const vec_t<int32_t, E>& cj, const vec_t<T, E>& ca, bool rv, vec_t<T, VEC>& acc) {
+  // lds_row does for rows); with take, first = the X values of entry 0
+  auto chunk = [&](const vec_t<int32_t, E>& cj, const vec_t<T, E>& ca, bool rv, vec_t<T, VEC>& acc, bool take,
+                   vec_t<T, VEC>& first) {
     int jj[C];
     T aa[C];
     if constexpr (LPR >= 8) {
@@ -489,11 +493,17 @@ __global__ __launch_bounds__(kBlock) void spmm_ell_kernel(int64_t n, int W, cons
       xx[u] = ok ? load_vec<T, VEC>(X + (int64_t)jj[u] * s + col0) : zero_vec<T, VEC>();
       if (!ok) aa[u] = T(0);
     }
+    if (take) {
+#pragma unroll
+      for (int w = 0; w < VEC; ++w) first.v[w] = xx[0].v[w];
+    }
 #pragma unroll
     for (int u = 0; u < C; ++u)
 #pragma unroll
       for (int w = 0; w < VEC; ++w) acc.v[w] = fma(aa[u], xx[u].v[w], acc.v[w]);
   };
+  // MODE 1 on a diagonal-first copy: the own rows come from the first gather
+  const bool own_first = MODE == 1 && diag0;
 
   vec_t<int32_t, E> cj, nj;
   vec_t<T, E> ca, na;
@@ -503,7 +513,7 @@ __global__ __launch_bounds__(kBlock) void spmm_ell_kernel(int64_t n, int W, cons
     const bool rv = row < r1 && active;
     ld(row + step, 0, nj, na);
     vec_t<T, VEC> own = zero_vec<T, VEC>();
-    if (MODE == 1 && rv) own = load_vec<T, VEC>(X + row * s + col0);
+    if (MODE == 1 && rv && !own_first) own = load_vec<T, VEC>(X + row * s + col0);
     if (MODE == 2 && rv) own = load_vec<T, VEC>(B + row * s + col0);
     vec_t<T, VEC> acc = zero_vec<T, VEC>();
     if constexpr (PF) {
@@ -515,23 +525,23 @@ __global__ __launch_bounds__(kBlock) void spmm_ell_kernel(int64_t n, int W, cons
 #pragma unroll
       for (int q = 0; q < kPfChunks; ++q)
         if (1 + q < nch) ld(row, 1 + q, pj[q], pa[q]);
-      chunk(cj, ca, rv, acc);
+      chunk(cj, ca, rv, acc, own_first, own);
 #pragma unroll
       for (int q = 0; q < kPfChunks; ++q)
-        if (1 + q < nch) chunk(pj[q], pa[q], rv, acc);
+        if (1 + q < nch) chunk(pj[q], pa[q], rv, acc, false, own);
       for (int j = 1 + kPfChunks; j < nch; ++j) {
         vec_t<int32_t, E> kj;
         vec_t<T, E> ka;
         ld(row, j, kj, ka);
-        chunk(kj, ka, rv, acc);
+        chunk(kj, ka, rv, acc, false, own);
       }
     } else {
-      chunk(cj, ca, rv, acc);
+      chunk(cj, ca, rv, acc, own_first, own);
       for (int j = 1; j < nch; ++j) {
         vec_t<int32_t, E> kj;
         vec_t<T, E> ka;
         ld(row, j, kj, ka);
-        chunk(kj, ka, rv, acc);
+        chunk(kj, ka, rv, acc, false, own);
       }
     }
     if (MODE == 2) {
@@ -612,15 +622,15 @@ hipError_t launch_spmm(const CsrView& A, int s, const T* X, T* Y, const T* B, in
         if (mode == 0) {
           nblk = fit_grid<spmm_ell_kernel<T, S, V, 0, PF>>(nblk);
           hipLaunchKernelGGL((spmm_ell_kernel<T, S, V, 0, PF>), dim3(nblk), dim3(kBlock), 0, st, A.n, A.ell_w,
-                             A.ell_col, ev, s, X, Y, B, partial, done, pstride);
+                             A.ell_col, ev, s, X, Y, B, partial, done, pstride, 0);
         } else if (mode == 1) {
           nblk = fit_grid<spmm_ell_kernel<T, S, V, 1, PF>>(nblk);
           hipLaunchKernelGGL((spmm_ell_kernel<T, S, V, 1, PF>), dim3(nblk), dim3(kBlock), 0, st, A.n, A.ell_w,
-                             A.ell_col, ev, s, X, Y, B, partial, done, pstride);
+                             A.ell_col, ev, s, X, Y, B, partial, done, pstride, A.ell_diag0 ? 1 : 0);
         } else {
           nblk = fit_grid<spmm_ell_kernel<T, S, V, 2, PF>>(nblk);
           hipLaunchKernelGGL((spmm_ell_kernel<T, S, V, 2, PF>), dim3(nblk), dim3(kBlock), 0, st, A.n, A.ell_w,
-                             A.ell_col, ev, s, X, Y, B, partial, done, pstride);
+                             A.ell_col, ev, s, X, Y, B, partial, done, pstride, 0);
         }
       };
       if (ell_prefetch<S, V>(A.ell_w))

@@ -1,7 +1,10 @@
 // kernels_ell.hip -- padded row-major (ELL) copy of a CSR matrix for the
 // SpMM of the solvers.  Row i's entries go to [i*W, i*W + W) in storage
-// order; the tail of a shorter row is padding (column -1, value 0).  A column
-// index outside [0, n) is reported through `bad` and stored as padding.
+// order, or with its first diagonal entry moved to the front (the solvers'
+// copies: the fused SpMM and Gram then reads a row's own X values from the
+// diagonal's gather); the tail of a shorter row is padding (column -1, value
+// 0).  A column index outside [0, n) is reported through `bad` and stored as
+// padding.
 #include "common.hpp"
 #include "internal.hpp"
 
@@ -23,13 +26,32 @@ __global__ __launch_bounds__(kBlock) void ell_width_kernel(int64_t n, int64_t nn
   if ((threadIdx.x & (kWave - 1)) == 0 && m > 0) atomicMax(wmax, m);
 }
 
+// Offset of row i's first diagonal entry in [k0, k1) (-1: none).  The
+// column indices are read eight at a time, from clamped indexes, so that a
+// row waits for one round trip per eight entries.
+__device__ __forceinline__ int ell_diag_pos(int64_t i, int64_t k0, int64_t k1, const int32_t* __restrict__ colind) {
+  constexpr int kB = 8;
+  for (int64_t kb = k0; kb < k1; kb += kB) {
+    int32_t cc[kB];
+#pragma unroll
+    for (int e = 0; e < kB; ++e) cc[e] = colind[kb + e < k1 ? kb + e : k1 - 1];
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int e = 0; e < kB; ++e)
+      if (kb + e < k1 && cc[e] == i) return (int)(kb + e - k0);
+  }
+  return -1;
+}
+
 // One thread per padded entry (row-major), so the writes are coalesced.
+// nodiag not null: slot 0 takes the row's first diagonal entry (at offset d),
+// slots 1 .. d the entries before it, the others stay where they are.
 template <typename Tin, typename T>
 __global__ __launch_bounds__(kBlock) void ell_fill_kernel(int64_t n, int64_t nnz, const int32_t* __restrict__ rowptr,
                                                            const int32_t* __restrict__ colind,
                                                            const Tin* __restrict__ val, int W,
                                                            int32_t* __restrict__ ecol, T* __restrict__ eval,
-                                                           int32_t* bad) {
+                                                           int32_t* bad, int32_t* nodiag) {
   const int64_t total = n * (int64_t)W;
   for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < total; t += (int64_t)gridDim.x * kBlock) {
     const int64_t i = t / W;
@@ -37,13 +59,19 @@ __global__ __launch_bounds__(kBlock) void ell_fill_kernel(int64_t n, int64_t nnz
     int64_t k0 = rowptr[i], k1 = rowptr[i + 1];
     k0 = k0 < 0 ? 0 : (k0 > nnz ? nnz : k0);
     k1 = k1 < 0 ? 0 : (k1 > nnz ? nnz : k1);
+    int src = u;  // offset in the CSR row of the entry stored at slot u
+    if (nodiag) {
+      const int d = ell_diag_pos(i, k0, k1, colind);
+      if (d < 0 && u == 0) *nodiag = 1;
+      if (d > 0) src = u == 0 ? d : (u <= d ? u - 1 : u);
+    }
     int32_t j = -1;
     T a = T(0);
-    if (k0 + u < k1) {
-      const int32_t cj = colind[k0 + u];
+    if (k0 + src < k1) {
+      const int32_t cj = colind[k0 + src];
       if ((uint32_t)cj < (uint64_t)n) {
         j = cj;
-        a = (T)val[k0 + u];
+        a = (T)val[k0 + src];
       } else if (bad) {
         *bad = 1;
       }
@@ -104,21 +132,21 @@ hipError_t launch_ell_width(const CsrView& A, int32_t* wmax, hipStream_t st) {
 
 template <typename Tin, typename T>
 hipError_t launch_ell_fill(const CsrView& A, const Tin* val, int W, int32_t* ecol, T* eval, int32_t* bad,
-                           hipStream_t st) {
+                           int32_t* nodiag, hipStream_t st) {
   const int64_t total = A.n * (int64_t)W;
   if (total <= 0) return hipSuccess;
   int64_t blocks = (total + kBlock - 1) / kBlock;
   if (blocks > 8192) blocks = 8192;
   hipLaunchKernelGGL((ell_fill_kernel<Tin, T>), dim3((unsigned)blocks), dim3(kBlock), 0, st, A.n, A.nnz, A.rowptr,
-                     A.colind, val, W, ecol, eval, bad);
+                     A.colind, val, W, ecol, eval, bad, nodiag);
   return hipGetLastError();
 }
 
 template hipError_t launch_ell_fill<double, double>(const CsrView&, const double*, int, int32_t*, double*,
-                                                    int32_t*, hipStream_t);
+                                                    int32_t*, int32_t*, hipStream_t);
 template hipError_t launch_ell_fill<double, float>(const CsrView&, const double*, int, int32_t*, float*, int32_t*,
-                                                   hipStream_t);
+                                                   int32_t*, hipStream_t);
 template hipError_t launch_ell_fill<float, float>(const CsrView&, const float*, int, int32_t*, float*, int32_t*,
-                                                  hipStream_t);
+                                                  int32_t*, hipStream_t);
 
 }  // namespace bkry

@@ -808,6 +808,7 @@ hipError_t ir_run(const CsrView& A, Sub sub, const double* B, double* X, double 
   A32.ell_w = b.ell_w;
   A32.ell_col = b.ell_col;
   A32.ell_val = b.ell_val;
+  A32.ell_diag0 = b.ell_diag0;
   int32_t* dflag = b.flag;
   BK_TRY(hipMemsetAsync(dflag, 0, 4 * sizeof(int32_t), st));
   for (int outer = 0;; ++outer) {

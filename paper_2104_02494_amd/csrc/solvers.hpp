@@ -120,6 +120,7 @@ struct IrBufs {
   int ell_w = 0;
   const int32_t* ell_col = nullptr;
   const float* ell_val = nullptr;
+  bool ell_diag0 = false;  // slot 0 of every ELL row holds its diagonal entry
 };
 IrBufs carve_ir(Carver& c, int64_t n, int64_t nnz, Sub sub, uint32_t* cnt);
 
