@@ -452,15 +452,20 @@ def extras(P, W, h, dev, A, Ad, Bd, args):
         vals = A5d.val.clone().requires_grad_(True)
         B5d = torch.as_tensor(B5).to(dev).requires_grad_(True)
         T5 = torch.as_tensor(e5["target"]).to(dev)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        X5 = P.block_solve(vals, B5d, A5d, h, tol=1e-10, eta=1e4)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        loss = 0.5 * ((X5 - T5) ** 2).sum()
-        loss.backward()
-        torch.cuda.synchronize()
-        t2 = time.perf_counter()
+        # two rounds, the second timed: the first backward pass of a process
+        # also starts autograd and loads torch's elementwise kernels
+        for _ in range(2):
+            vals.grad = None
+            B5d.grad = None
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            X5 = P.block_solve(vals, B5d, A5d, h, tol=1e-10, eta=1e4)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            loss = 0.5 * ((X5 - T5) ** 2).sum()
+            loss.backward()
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
         ex["adjoint_diffusion7var_64_s32"] = dict(forward_s=round(t1 - t0, 4), backward_s=round(t2 - t1, 4))
         log("adjoint", ex["adjoint_diffusion7var_64_s32"])
     except Exception as e:
