@@ -137,8 +137,12 @@ int bkry_profile_read(bkry_handle h, int32_t kernel, double* total_ms, int64_t* 
  * more bytes per product than CSR, and streams CSR otherwise and in
  * bkry_spmm; BKRY_FMT_CSR always streams CSR; BKRY_FMT_ELL always streams
  * the ELL copy (bkry_spmm and bkry_spmm_f32 then build it on every call and
- * return when it is built).  Entries are summed in storage order either way,
- * so results are bit-identical across formats. */
+ * return when it is built).  bkry_spmm and bkry_spmm_f32 sum each row's
+ * entries in CSR order in either format, so their results are bit-identical
+ * across formats.  The solvers' ELL copy holds each row's first diagonal
+ * entry in slot 0 (the fused product and Gram reads a row's own values from
+ * that entry's gather) and the other entries in CSR order, so a solve through
+ * it agrees with a CSR solve to rounding, not bit for bit. */
 #define BKRY_FMT_AUTO 0
 #define BKRY_FMT_CSR 1
 #define BKRY_FMT_ELL 2
