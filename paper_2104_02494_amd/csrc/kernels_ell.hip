@@ -10,7 +10,10 @@
 
 namespace bkry {
 
-// Longest row (entries after clamping the row pointers to [0, nnz]).
+// Longest row (entries after clamping the row pointers to [0, nnz]).  A
+// wavefront posts its maximum only if it exceeds the value already there: on
+// rows of similar length almost no wavefront then issues the atomic, which
+// the L2 would otherwise serialise (one per wavefront on one address).
 __global__ __launch_bounds__(kBlock) void ell_width_kernel(int64_t n, int64_t nnz, const int32_t* __restrict__ rowptr,
                                                             int32_t* wmax) {
   int m = 0;
@@ -23,7 +26,8 @@ __global__ __launch_bounds__(kBlock) void ell_width_kernel(int64_t n, int64_t nn
   }
 #pragma unroll
   for (int d = 1; d < kWave; d <<= 1) m = max(m, __shfl_xor(m, d));
-  if ((threadIdx.x & (kWave - 1)) == 0 && m > 0) atomicMax(wmax, m);
+  if ((threadIdx.x & (kWave - 1)) == 0 && m > 0 && m > __hip_atomic_load(wmax, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+    atomicMax(wmax, m);
 }
 
 // Offset of row i's first diagonal entry in [k0, k1) (-1: none).  The
