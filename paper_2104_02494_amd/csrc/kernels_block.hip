@@ -504,10 +504,21 @@ __global__ __launch_bounds__(kBlock) void spmm_ell_kernel(int64_t n, int W, cons
   };
   // MODE 1 on a diagonal-first copy: the own rows come from the first gather
   const bool own_first = MODE == 1 && diag0;
+  // FP32 entries up to 16 columns: chunks 1 .. kPfChunks of the next tile are
+  // requested with its chunk 0, during this tile's gathers (for FP64 entries
+  // the extra registers would cost a wavefront per SIMD)
+  constexpr bool NEXT = PF && sizeof(T) == 4 && S <= 16;
 
   vec_t<int32_t, E> cj, nj;
   vec_t<T, E> ca, na;
+  vec_t<int32_t, E> pj[kPfChunks], qj[kPfChunks];
+  vec_t<T, E> pa[kPfChunks], qa[kPfChunks];
   ld(r0 + roff, 0, cj, ca);
+  if constexpr (NEXT) {
+#pragma unroll
+    for (int q = 0; q < kPfChunks; ++q)
+      if (1 + q < nch) ld(r0 + roff, 1 + q, pj[q], pa[q]);
+  }
   for (int64_t base = r0; base < r1; base += step) {
     const int64_t row = base + roff;
     const bool rv = row < r1 && active;
@@ -516,19 +527,40 @@ __global__ __launch_bounds__(kBlock) void spmm_ell_kernel(int64_t n, int W, cons
     if (MODE == 1 && rv && !own_first) own = load_vec<T, VEC>(X + row * s + col0);
     if (MODE == 2 && rv) own = load_vec<T, VEC>(B + row * s + col0);
     vec_t<T, VEC> acc = zero_vec<T, VEC>();
-    if constexpr (PF) {
-      // rows of several chunks (wide stencils): the entries of chunks 1 ..
-      // kPfChunks are requested before the first chunk's gathers, so a row
-      // waits for its matrix entries once instead of once per chunk
-      vec_t<int32_t, E> pj[kPfChunks];
-      vec_t<T, E> pa[kPfChunks];
+    if constexpr (NEXT) {
+      // this tile's chunks 1 .. kPfChunks arrived during the previous tile;
+      // the next tile's are requested now
 #pragma unroll
       for (int q = 0; q < kPfChunks; ++q)
-        if (1 + q < nch) ld(row, 1 + q, pj[q], pa[q]);
+        if (1 + q < nch) ld(row + step, 1 + q, qj[q], qa[q]);
       chunk(cj, ca, rv, acc, own_first, own);
 #pragma unroll
       for (int q = 0; q < kPfChunks; ++q)
         if (1 + q < nch) chunk(pj[q], pa[q], rv, acc, false, own);
+      for (int j = 1 + kPfChunks; j < nch; ++j) {
+        vec_t<int32_t, E> kj;
+        vec_t<T, E> ka;
+        ld(row, j, kj, ka);
+        chunk(kj, ka, rv, acc, false, own);
+      }
+#pragma unroll
+      for (int q = 0; q < kPfChunks; ++q) {
+        pj[q] = qj[q];
+        pa[q] = qa[q];
+      }
+    } else if constexpr (PF) {
+      // rows of several chunks (wide stencils): the entries of chunks 1 ..
+      // kPfChunks are requested before the first chunk's gathers, so a row
+      // waits for its matrix entries once instead of once per chunk
+      vec_t<int32_t, E> rj[kPfChunks];
+      vec_t<T, E> ra[kPfChunks];
+#pragma unroll
+      for (int q = 0; q < kPfChunks; ++q)
+        if (1 + q < nch) ld(row, 1 + q, rj[q], ra[q]);
+      chunk(cj, ca, rv, acc, own_first, own);
+#pragma unroll
+      for (int q = 0; q < kPfChunks; ++q)
+        if (1 + q < nch) chunk(rj[q], ra[q], rv, acc, false, own);
       for (int j = 1 + kPfChunks; j < nch; ++j) {
         vec_t<int32_t, E> kj;
         vec_t<T, E> ka;
